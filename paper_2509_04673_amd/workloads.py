@@ -1,0 +1,167 @@
+"""Seeded synthetic workloads: mesh, physics, parameters and initial data.
+
+This module holds no arithmetic of the method.  It draws the seeded
+parameters of each workload with splitmix64 and evaluates the initial data
+u_0 at the Bernstein nodal points, u_j(0) = u_0(x_j) (nodal initialisation
+of the numerical study, [KHV §5]).  Both the HIP path and the oracle consume
+the arrays it returns.
+
+Workloads (shapes of the paper's test problems):
+  adv1d      1D linear advection, P2, periodic [0,1]: sin(2 pi x) plus a
+             square pulse on [0.3, 0.5] of seeded amplitude in [0.5, 1]
+  kpp2d      2D KPP flux (sin u, cos u) on [-2,2]x[-2.5,1.5], Q2:
+             u = 7 pi / 2 in a radius-1 disc (seeded centre +-0.05),
+             pi / 4 outside
+  euler2d    2D Euler, gamma = 1.4, unit square, Q3: four quadrants with
+             seeded rho, p in [0.1, 2] and velocities in [-1, 1]
+  euler3d    3D Euler, unit cube, Q2: rho = 1, v = 0, p = 1e-2, p = 10
+             inside a radius-0.1 ball at a seeded centre
+"""
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+_MASK = (1 << 64) - 1
+
+
+class SplitMix64:
+    """splitmix64 (Steele, Lea & Flood 2014); uniforms (x >> 11) * 2^-53."""
+
+    def __init__(self, seed):
+        self.state = int(seed) & _MASK
+
+    def next_u64(self):
+        self.state = (self.state + 0x9E3779B97F4A7C15) & _MASK
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+        return z ^ (z >> 31)
+
+    def uniform(self):
+        return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+
+
+@dataclass
+class Workload:
+    name: str
+    d: int
+    p: int
+    n: tuple
+    lo: tuple
+    hi: tuple
+    kind: str                       # "advection" | "kpp" | "euler"
+    u0: np.ndarray                  # (m, N) float64, component-major, x fastest
+    velocity: tuple = (1.0, 0.0, 0.0)
+    gamma_gas: float = 1.4
+    w_lin: float = 1e-3
+    q: float = 1.0
+    dt: float = 0.0                 # > 0: fixed step; 0: adaptive
+    cfl: float = 0.5
+    nsteps: int = 1
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self):
+        return self.u0.shape[0]
+
+    @property
+    def N(self):
+        return self.u0.shape[1]
+
+    @property
+    def dofs(self):
+        return self.u0.size
+
+
+def node_coords(d, p, n, lo, hi):
+    """(N, d) nodal points x_j = lo + h i / p on the periodic node lattice,
+    x fastest (node index sum_k i_k prod_{j<k} L_j)."""
+    L = [p * nk for nk in n]
+    h = [(hi[k] - lo[k]) / n[k] for k in range(d)]
+    axes = [lo[k] + h[k] * np.arange(L[k]) / p for k in range(d)]
+    grids = np.meshgrid(*reversed(axes), indexing="ij")    # slowest first
+    return np.stack([g.ravel() for g in reversed(grids)], axis=1)
+
+
+def _conserved(rho, vel, pres, gamma):
+    """(rho, rho v, rho E) from primitive variables of an ideal gas
+    (equation of state of [KHV §5.2])."""
+    d = len(vel)
+    kin = 0.5 * rho * sum(v * v for v in vel)
+    return np.stack([rho] + [rho * v for v in vel] + [pres / (gamma - 1.0) + kin])
+
+
+def adv1d(seed=0, n=64, p=2):
+    rng = SplitMix64(seed)
+    amp = 0.5 + 0.5 * rng.uniform()
+    x = node_coords(1, p, (n,), (0.0,), (1.0,))[:, 0]
+    u = np.sin(2.0 * math.pi * x) + amp * ((x >= 0.3) & (x <= 0.5))
+    return Workload("adv1d", 1, p, (n,), (0.0,), (1.0,), "advection", u[None, :],
+                    velocity=(1.0, 0.0, 0.0), w_lin=1e-3, dt=0.2 * (1.0 / n) / 2.0,
+                    cfl=0.2, nsteps=200, meta=dict(amplitude=amp, seed=seed))
+
+
+def kpp2d(seed=0, n=256, p=2):
+    rng = SplitMix64(seed)
+    cx = -0.05 + 0.1 * rng.uniform()
+    cy = -0.05 + 0.1 * rng.uniform()
+    lo, hi = (-2.0, -2.5), (2.0, 1.5)
+    xy = node_coords(2, p, (n, n), lo, hi)
+    r2 = (xy[:, 0] - cx) ** 2 + (xy[:, 1] - cy) ** 2
+    u = np.where(r2 <= 1.0, 3.5 * math.pi, 0.25 * math.pi)
+    return Workload("kpp2d", 2, p, (n, n), lo, hi, "kpp", u[None, :], w_lin=0.2,
+                    dt=5e-4, nsteps=2000, meta=dict(centre=(cx, cy), seed=seed))
+
+
+def _quadrant_states(rng):
+    """(rho, vx, vy, p) per quadrant, drawn in the order NE, NW, SW, SE."""
+    out = []
+    for _ in range(4):
+        rho = 0.1 + 1.9 * rng.uniform()
+        vx = -1.0 + 2.0 * rng.uniform()
+        vy = -1.0 + 2.0 * rng.uniform()
+        pr = 0.1 + 1.9 * rng.uniform()
+        out.append((rho, vx, vy, pr))
+    return out
+
+
+def euler2d(seed=0, n=512, p=3, gamma=1.4):
+    rng = SplitMix64(seed)
+    st = _quadrant_states(rng)
+    xy = node_coords(2, p, (n, n), (0.0, 0.0), (1.0, 1.0))
+    east = xy[:, 0] >= 0.5
+    north = xy[:, 1] >= 0.5
+    q = np.where(north, np.where(east, 0, 1), np.where(east, 3, 2))
+    prim = np.array(st)[q]                      # (N, 4)
+    u = _conserved(prim[:, 0], [prim[:, 1], prim[:, 2]], prim[:, 3], gamma)
+    return Workload("euler2d", 2, p, (n, n), (0.0, 0.0), (1.0, 1.0), "euler", u,
+                    gamma_gas=gamma, w_lin=1e-3, dt=0.0, cfl=0.5, nsteps=100,
+                    meta=dict(quadrants=st, seed=seed))
+
+
+def euler3d(seed=0, n=128, p=2, gamma=1.4):
+    rng = SplitMix64(seed)
+    c = [0.2 + 0.6 * rng.uniform() for _ in range(3)]
+    xyz = node_coords(3, p, (n, n, n), (0.0,) * 3, (1.0,) * 3)
+    r2 = sum((xyz[:, k] - c[k]) ** 2 for k in range(3))
+    pres = np.where(r2 <= 0.01, 10.0, 1e-2)
+    rho = np.ones_like(pres)
+    z = np.zeros_like(pres)
+    u = _conserved(rho, [z, z, z], pres, gamma)
+    return Workload("euler3d", 3, p, (n, n, n), (0.0,) * 3, (1.0,) * 3, "euler", u,
+                    gamma_gas=gamma, w_lin=1e-3, dt=0.0, cfl=0.5, nsteps=500,
+                    meta=dict(centre=c, seed=seed))
+
+
+def euler_batch_sizes(seed=0, count=512):
+    """Mesh sizes n_k = 32 + floor(225 U) of the batched Euler workload."""
+    rng = SplitMix64(seed)
+    return [32 + int(225 * rng.uniform()) for _ in range(count)]
+
+
+MAKERS = dict(adv1d=adv1d, kpp2d=kpp2d, euler2d=euler2d, euler3d=euler3d)
+
+
+def make(name, seed=0, **kw):
+    return MAKERS[name](seed=seed, **kw)
