@@ -16,13 +16,15 @@ Readings of points the paper leaves open (each listed in the design doc):
     neighbour's polynomial extended into K_e (its cell average is
     irrelevant: the semi-norm (8) has no zero-order term); r = 2,
     eps = 1e-12; gamma_e of a system is the minimum over components;
-    0/0 in (7): deviation 0 -> gamma = 1, else zero norm -> gamma = 0.
+    the ratio in (7) is 0/0 on constant elements and is regularised as
+    ||u - u*||_e / (||u||_e^2 + eps)^(1/2) with the weights' epsilon.
   * The element integral of grad(phi_i) . f(u_h) uses (p+1)^d Gauss points.
   * The flux limiter is on with pseudo time steps (40); Euler facet pairs use
     Appendix A with the increments the states u_ee', u_e'e actually receive.
-  * Strict positivity margin eps_pos in the Appendix A limiters; a scalar
-    stage result that leaves [u_min, u_max] by no more than a few ulps of
-    rounding is clamped back and counted.
+  * Strict positivity margin eps_pos in the Appendix A limiters; slope
+    limiter ratios of (55) are clipped to [0, 1]; a scalar stage result that
+    leaves [u_min, u_max] by no more than a few ulps of rounding is clamped
+    back and counted, larger excursions are left and counted as violations.
 """
 from dataclasses import dataclass, field
 from functools import cached_property
@@ -232,9 +234,9 @@ class Oracle:
                 dev2 = dev2 + np.sum(W * diff ** 2, axis=axes_q)
             dev = np.sqrt(np.maximum(dev2, 0.0))
             nrm = np.sqrt(np.maximum(beta[0], 0.0))
-            safe = np.where(nrm == 0.0, 1.0, nrm)
-            ratio = np.where(dev == 0.0, 0.0,
-                             np.where(nrm == 0.0, 1.0, np.minimum(1.0, dev / safe)))
+            # the ratio of (7) is 0/0 on constant elements; it is regularised
+            # with the epsilon of the weights, ||u||_e^2 -> ||u||_e^2 + eps
+            ratio = np.minimum(1.0, dev / np.sqrt(np.maximum(beta[0], 0.0) + prm.eps))
             for key, val in (("beta", beta), ("omega", om), ("dev", dev), ("nrm", nrm),
                              ("gamma", 1.0 - ratio ** prm.q)):
                 out[key].append(val)
@@ -389,8 +391,10 @@ class Oracle:
             ub = ubar[0][:, None]
             f0 = fe[0]
             with np.errstate(divide="ignore", invalid="ignore"):
-                bpos = np.minimum(1.0, mloc * (prob.u_max - ub) / np.where(f0 > 0, f0, 1.0))
-                bneg = np.minimum(1.0, mloc * (prob.u_min - ub) / np.where(f0 < 0, f0, 1.0))
+                # ubar lies in [u_min, u_max] up to rounding; a ratio made
+                # negative by a rounding excess is taken as 0
+                bpos = np.clip(mloc * (prob.u_max - ub) / np.where(f0 > 0, f0, 1.0), 0.0, 1.0)
+                bneg = np.clip(mloc * (prob.u_min - ub) / np.where(f0 < 0, f0, 1.0), 0.0, 1.0)
             bi = np.where(f0 > 0, bpos, np.where(f0 < 0, bneg, 1.0))
             beta = np.min(bi, axis=-1)
 
@@ -420,12 +424,11 @@ class Oracle:
             bad = int(np.sum(u[0] <= 0) + np.sum(prob.phys.pressure(u) <= 0))
             return u, 0, bad
         tol = prob.params.clamp_ulps * np.finfo(float).eps * max(abs(prob.u_min), abs(prob.u_max))
-        over = u > prob.u_max
-        under = u < prob.u_min
+        hi = (u > prob.u_max) & (u <= prob.u_max + tol)
+        lo = (u < prob.u_min) & (u >= prob.u_min - tol)
         bad = int(np.sum(u > prob.u_max + tol) + np.sum(u < prob.u_min - tol))
-        n = int(np.sum(over) + np.sum(under))
-        u = np.clip(u, prob.u_min, prob.u_max)
-        return u, n - bad, bad
+        u = np.where(hi, prob.u_max, np.where(lo, prob.u_min, u))
+        return u, int(np.sum(hi) + np.sum(lo)), bad
 
     def max_dt(self, u):
         """min_e dt_e(u) of [KHV eq. (40)] without running a stage."""

@@ -116,11 +116,19 @@ def test_gamma_affine_invariance():
 
 
 def test_constant_element_next_to_varying_neighbour():
-    # 0/0 reading: a constant element with a non-constant neighbour has zero
-    # own norm and nonzero deviation -> gamma = 0
+    # regularised 0/0 reading: a constant element has zero own semi-norm and
+    # the sensor ratio is taken against (||u||^2 + eps)^(1/2); it is smooth
+    # (gamma ~ 1), continuous in the data, and the varying element is not
     orc = _oracle(1, 2, (4,))
     U = np.zeros((1, 4, 3))
     U[0, 1] = [0.0, 0.3, 1.0]
     gam = orc.weno_parts(U)["gamma"][0]
-    assert gam[0] == 0.0 and gam[2] == 0.0
+    assert gam[0] > 1 - 1e-6 and gam[2] > 1 - 1e-6
     assert gam[3] == 1.0        # itself and both neighbours constant
+    assert gam[1] < 0.5
+    # continuity: a 1-ulp perturbation of a constant element moves gamma by
+    # at most |u| ulp / sqrt(eps)
+    V = U.copy()
+    V[0, 3] = [0.0, 2.0 ** -1074, 0.0]
+    g2 = orc.weno_parts(V)["gamma"][0]
+    assert np.max(np.abs(g2 - gam)) < 1e-9
