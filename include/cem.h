@@ -1,0 +1,178 @@
+/*
+ * cem.h -- C ABI of the MI355X (gfx950) implementation of one explicit
+ * SSP Runge-Kutta stage of the element-based convex limiting scheme for
+ * Bernstein continuous Galerkin discretizations with WENO stabilization:
+ *
+ *   D. Kuzmin, H. Hajduk, J. Vedral, "An element-based convex limiting
+ *   framework for continuous Galerkin methods with nonlinear
+ *   stabilization", arXiv:2509.04673.  Equation numbers below follow the
+ *   order of the arXiv source.
+ *
+ * Scope: uniform periodic boxes of cube cells in 1, 2 or 3 dimensions,
+ * tensor-product Bernstein elements Q_p (p = 1..3, p = 1..2 in 3D), scalar
+ * linear advection, the KPP flux (sin u, cos u) in 2D, and the compressible
+ * Euler equations of an ideal gas.  Arithmetic is IEEE float64.
+ *
+ * Conventions shared by every call
+ *  - Every call returns a cem_status; 0 is success.  A failing call leaves a
+ *    message for cem_last_error() (thread-local) and changes no state.
+ *  - Device memory is owned by the caller.  The library never allocates or
+ *    frees device memory: the state arrays and one workspace (size from
+ *    cem_workspace_bytes) are bound with cem_bind.  Host memory passed in is
+ *    only read or written during the call.
+ *  - All GPU work is enqueued on the stream given to cem_create (a
+ *    hipStream_t passed as void*, NULL = default stream) and is asynchronous
+ *    unless a call is marked synchronous.  Asynchronous HIP failures surface
+ *    at the next synchronous call as CEM_EHIP.
+ *  - Nodal arrays are structure-of-arrays, component-major, float64:
+ *        u[c * N + node],  node = i0 + L0 * (i1 + L1 * i2),  0 <= ik < Lk,
+ *    with Lk = p * n[k] unique nodes per axis of the periodic box (the node
+ *    at the upper end of an axis is the node at its lower end).  Node
+ *    (i0, i1, i2) carries the Bernstein coefficient whose nodal point is
+ *    lo + h * (i0, i1, i2) / p.  Components: scalar problems m = 1; Euler
+ *    m = d + 2 with (rho, rho v_1..rho v_d, rho E).
+ */
+#ifndef CEM_H
+#define CEM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CEM_OK = 0,
+  CEM_EINVAL = -1, /* invalid argument, unsupported configuration, bad order of calls */
+  CEM_EHIP = -2,   /* a HIP runtime call failed */
+  CEM_ENOMEM = -3, /* bound workspace smaller than cem_workspace_bytes */
+  CEM_ECFL = -4,   /* dt > min_e dt_e at some stage (eq. 23): retry with a smaller dt */
+  CEM_EIDP = -5    /* an invariant-domain check failed beyond round-off */
+} cem_status;
+
+typedef enum { CEM_ADVECTION = 0, CEM_KPP = 1, CEM_EULER = 2 } cem_physics_kind;
+
+/* Uniform periodic box [lo, hi] with n[k] cube cells per axis (cell edge h
+ * equal on every axis; unused axes ignored).  n[k] >= 2. */
+typedef struct {
+  int dim;       /* 1, 2 or 3 */
+  int degree;    /* Bernstein degree p */
+  int n[3];
+  double lo[3], hi[3];
+} cem_mesh_desc;
+
+typedef struct {
+  int kind;            /* cem_physics_kind */
+  double velocity[3];  /* advection velocity (CEM_ADVECTION) */
+  double gamma_gas;    /* ratio of specific heats (CEM_EULER), 1 < gamma <= 5/3 */
+} cem_physics_desc;
+
+/* Method parameters.  Modes: 0 = the method, 1 = force the factor to 0,
+ * 2 = force it to 1 (the LO / HO / WENO / WENO-L switches of Sec. 5.3). */
+typedef struct {
+  double q;          /* steepening exponent of the sensor (eq. 7), >= 1 */
+  double r;          /* exponent of the WENO weights */
+  double eps;        /* epsilon of the WENO weights */
+  double w_lin;      /* linear weight of each facet-neighbour candidate */
+  double eps_pos;    /* strict-positivity margin of the Appendix A limiters */
+  double clamp_ulps; /* scalar round-off clamp width in ulps of max|bound| */
+  int gamma_mode;    /* WENO sensor gamma_e (eq. 7) */
+  int alpha_mode;    /* flux limiter alpha_ee' (eqs. 44, 53 / Appendix A) */
+  int beta_mode;     /* slope limiter beta_e (eqs. 54-55 / Appendix A) */
+  double u_min, u_max; /* global bounds of scalar problems (Sec. 4.1, 4.2) */
+} cem_params;
+
+typedef struct cem_ctx cem_ctx;
+
+/* Pseudo time step statistics and invariant report. */
+typedef struct {
+  double dt;             /* global time step of the current/last step */
+  double min_dt_e;       /* min over elements and stages of dt_e (eq. 40) */
+  int cfl_violated;      /* 1 if dt > min_e dt_e at some stage */
+  long long clamped;     /* scalar values clamped by <= clamp width (round-off) */
+  long long violations;  /* values outside the admissible set beyond round-off */
+  int m;                 /* number of components */
+  double u_min[5], u_max[5];   /* per-component extrema of the state */
+  double mass[5];        /* per-component sum_i m_i u_i (lumped masses) */
+  double rho_min, p_min; /* Euler: smallest density and pressure */
+} cem_invariants;
+
+/* Fills p with the defaults: q = 1, r = 2, eps = 1e-12, w_lin = 1e-3,
+ * eps_pos = 1e-10, clamp_ulps = 64, all modes 0, bounds (-inf, +inf). */
+cem_status cem_params_default(cem_params* p);
+
+/* Creates a context: validates the configuration and builds the element
+ * tables on the host (Sec. 2.1: Bernstein basis; Sec. 2.2: semi-norm (8)).
+ * stream: hipStream_t for all later work.  *out receives the context.
+ * No GPU memory is touched until cem_bind. */
+cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys,
+                      const cem_params* prm, void* stream, cem_ctx** out);
+
+/* Sizes: N unique nodes, E elements, m components, and the workspace bytes
+ * needed by cem_bind.  Any pointer may be NULL. */
+cem_status cem_sizes(const cem_ctx* ctx, long long* N, long long* E, int* m);
+cem_status cem_workspace_bytes(const cem_ctx* ctx, size_t* bytes);
+
+/* Binds caller-owned device memory: u (m*N float64, the state, updated in
+ * place by every stage), u_base (m*N float64, the state u^n at the start of
+ * a step), workspace (>= cem_workspace_bytes, 256-byte aligned).  Copies the
+ * tables into the workspace (asynchronous). */
+cem_status cem_bind(cem_ctx* ctx, double* u, double* u_base, void* workspace, size_t ws_bytes);
+
+/* Host <-> device copies of the state (host array m*N float64 in the nodal
+ * layout).  upload is asynchronous but waits for the host buffer to be read;
+ * download is synchronous. */
+cem_status cem_upload_state(cem_ctx* ctx, const double* host_u);
+cem_status cem_download_state(cem_ctx* ctx, double* host_u);
+
+/* Global bounds for scalar problems (Sec. 4.1, 4.2).  from_state != 0 takes
+ * the min and max of the bound state's coefficients (synchronous); else
+ * u_min, u_max are used.  Ignored for Euler. */
+cem_status cem_set_bounds(cem_ctx* ctx, int from_state, double u_min, double u_max);
+
+/* One stage of Shu-Osher SSP-RK3 on the bound state (the five steps of
+ * Sec. 4.3): stage s = 0, 1, 2 computes u <- a_s u_base + b_s u^FE(u) with
+ * (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3) and u^FE the limited forward-Euler
+ * update of eq. (49).  At s = 0 the step size is dt if dt > 0, else
+ * cfl * min_e dt_e(u) (eq. 40), and it is kept for s = 1, 2.  Stage 0 does
+ * not copy u to u_base; cem_step does.  Asynchronous: a CFL violation is
+ * reported by cem_check_invariants. */
+cem_status cem_rk_stage(cem_ctx* ctx, int stage, double dt, double cfl);
+
+/* One SSP-RK3 step: u_base <- u, then stages 0, 1, 2.  Asynchronous. */
+cem_status cem_step(cem_ctx* ctx, double dt, double cfl);
+
+/* Synchronous: reads the step size, CFL flag and clamp/violation counters
+ * accumulated since the last cem_reset_counters, and the state invariants.
+ * Returns CEM_ECFL or CEM_EIDP when the corresponding check failed. */
+cem_status cem_check_invariants(cem_ctx* ctx, cem_invariants* out);
+cem_status cem_reset_counters(cem_ctx* ctx);
+
+/* Copies an intermediate of the last stage into caller device memory dst
+ * (asynchronous, count float64 values, count must equal the tap size):
+ *   0 g [d][m][N]      1 r [m][N]        2 udot [m][N]    3 gamma [E]
+ *   4 nu [E]           5 dt_e [E]        6 u^e [m][E]     7 ubar^{e,L} [m][E]
+ *   8 ubar^e [m][E]    9 beta [E]       10 f^A of the +e_k facet [d][m][E]
+ *  11 element update vectors [m][(p+1)^d][E] */
+cem_status cem_debug_tap(cem_ctx* ctx, int tap, double* dst, size_t count);
+size_t cem_tap_size(const cem_ctx* ctx, int tap);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch of the kernels selected by mask (bit k = kernel id k):
+ *   0 projected-gradient line operator   1 element pass 1 (sensor, residual,
+ *   facets)   2 time-step reduction   3 residual gather   4 mass-solve line
+ *   operator   5 element pass 2 (limiters, contributions)   6 node update.
+ * cem_kernel_times is synchronous: it returns the summed milliseconds and
+ * launch counts per id since the previous call (arrays of n <= 7 entries)
+ * and clears them. */
+#define CEM_NUM_KERNELS 7
+cem_status cem_set_timing(cem_ctx* ctx, unsigned mask);
+cem_status cem_kernel_times(cem_ctx* ctx, double* total_ms, long long* launches, int n);
+
+void cem_destroy(cem_ctx* ctx);
+const char* cem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CEM_H */

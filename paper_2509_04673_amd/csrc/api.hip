@@ -1,0 +1,610 @@
+// C ABI of the limited CG-WENO stage (declarations and documentation in
+// include/cem.h).  Host orchestration of the gfx950 kernels of kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cem.h"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+using namespace cem;
+
+namespace {
+thread_local std::string g_err;
+
+cem_status fail(cem_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t _e = (call);                                                            \
+    if (_e != hipSuccess) return fail(CEM_EHIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
+struct cem_ctx {
+  int d = 0, p = 0, kind = 0, m = 0, nl = 0;
+  int n[3] = {1, 1, 1}, L[3] = {1, 1, 1};
+  int64_t N = 0, E = 0;
+  double h = 0.0;
+  cem_params prm{};
+  PhysParams ph{};
+  hipStream_t stream = nullptr;
+  HostTables tabs;
+  std::vector<double> tabblob;     // all tables, packed
+  size_t off_vqf = 0, off_dqw = 0, off_mass = 0, off_ksum = 0, off_ctg = 0, off_qf = 0,
+         off_ext = 0, off_facem = 0, off_kg[3] = {0, 0, 0}, off_km[3] = {0, 0, 0};
+  // bound memory
+  double* u = nullptr;
+  double* u0 = nullptr;
+  char* ws = nullptr;
+  size_t ws_need = 0;
+  // workspace carve-up (byte offsets)
+  size_t o_g, o_r, o_udot, o_tmp, o_tmp2, o_relem, o_ue, o_ubarL, o_ubar, o_fahi, o_dte, o_gam,
+      o_nu, o_beta, o_dtbuf, o_counts, o_inv, o_tab;
+  int upd_blocks = 0, inv_blocks = 0;
+  bool bound = false, bounds_set = false;
+  // optional per-kernel event timing
+  unsigned timing_mask = 0;
+  struct Rec { int id; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+
+  template <class T> T* W(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+void pack_tables(cem_ctx* c) {
+  const HostTables& T = c->tabs;
+  std::vector<double>& B = c->tabblob;
+  B.clear();
+  auto put = [&](const std::vector<double>& v) {
+    size_t off = B.size();
+    B.insert(B.end(), v.begin(), v.end());
+    while (B.size() % 32) B.push_back(0.0);
+    return off;
+  };
+  const int nl = T.nl, P1 = T.p + 1, D = T.d;
+  // full basis-at-Gauss tables [NQ][NL] and weighted gradients [D][NQ][NL]
+  std::vector<double> vqf((size_t)nl * nl), dqw((size_t)D * nl * nl);
+  for (int q = 0; q < nl; ++q)
+    for (int j = 0; j < nl; ++j) {
+      double v = 1.0, w = 1.0;
+      int qq = q, jj = j;
+      int qd[3], jd[3];
+      for (int k = 0; k < D; ++k) {
+        qd[k] = qq % P1;
+        qq /= P1;
+        jd[k] = jj % P1;
+        jj /= P1;
+        v *= T.vq[qd[k] * P1 + jd[k]];
+        w *= T.wq[qd[k]];
+      }
+      vqf[(size_t)q * nl + j] = v;
+      for (int k = 0; k < D; ++k) {
+        double g = w;
+        for (int l = 0; l < D; ++l) g *= (l == k) ? T.dq[qd[l] * P1 + jd[l]] : T.vq[qd[l] * P1 + jd[l]];
+        dqw[((size_t)k * nl + q) * nl + j] = g;
+      }
+    }
+  c->off_vqf = put(vqf);
+  c->off_dqw = put(dqw);
+  c->off_mass = put(T.mass);
+  c->off_ksum = put(T.ksum);
+  c->off_ctg = put(T.ctg);
+  c->off_qf = put(T.qf);
+  c->off_ext = put(T.ext);
+  c->off_facem = put(T.facem);
+  for (int k = 0; k < D; ++k) {
+    c->off_kg[k] = put(T.kgrad[k].w);
+    c->off_km[k] = put(T.kmass[k].w);
+  }
+}
+
+StageArgs make_args(const cem_ctx* c) {
+  StageArgs a{};
+  a.mesh.n[0] = c->n[0];
+  a.mesh.n[1] = c->n[1];
+  a.mesh.n[2] = c->n[2];
+  a.mesh.L[0] = c->L[0];
+  a.mesh.L[1] = c->L[1];
+  a.mesh.L[2] = c->L[2];
+  a.mesh.N = c->N;
+  a.mesh.E = c->E;
+  a.mesh.h = c->h;
+  const double* tb = c->W<double>(c->o_tab);
+  a.tab.vqf = tb + c->off_vqf;
+  a.tab.dqw = tb + c->off_dqw;
+  a.tab.mass = tb + c->off_mass;
+  a.tab.ksum = tb + c->off_ksum;
+  a.tab.ctg = tb + c->off_ctg;
+  a.tab.qf = tb + c->off_qf;
+  a.tab.ext = tb + c->off_ext;
+  a.tab.facem = tb + c->off_facem;
+  for (int k = 0; k < c->d; ++k) {
+    a.tab.kgrad[k] = tb + c->off_kg[k];
+    a.tab.kmass[k] = tb + c->off_km[k];
+    a.tab.gtaps[k] = c->tabs.kgrad[k].taps;
+    a.tab.gfirst[k] = c->tabs.kgrad[k].first;
+    a.tab.mtaps[k] = c->tabs.kmass[k].taps;
+    a.tab.mfirst[k] = c->tabs.kmass[k].first;
+  }
+  a.ph = c->ph;
+  a.q = c->prm.q;
+  a.rexp = c->prm.r;
+  a.eps = c->prm.eps;
+  a.w_lin = c->prm.w_lin;
+  a.eps_pos = c->prm.eps_pos;
+  a.gamma_mode = c->prm.gamma_mode;
+  a.alpha_mode = c->prm.alpha_mode;
+  a.beta_mode = c->prm.beta_mode;
+  a.umin = c->prm.u_min;
+  a.umax = c->prm.u_max;
+  a.clamp_tol = c->prm.clamp_ulps * DBL_EPSILON * std::fmax(std::fabs(c->prm.u_min), std::fabs(c->prm.u_max));
+  a.u = c->u;
+  a.u0 = c->u0;
+  a.uout = c->u;
+  a.g = c->W<double>(c->o_g);
+  a.r = c->W<double>(c->o_r);
+  a.udot = c->W<double>(c->o_udot);
+  a.relem = c->W<double>(c->o_relem);
+  a.ue = c->W<double>(c->o_ue);
+  a.ubarL = c->W<double>(c->o_ubarL);
+  a.ubar = c->W<double>(c->o_ubar);
+  a.fahi = c->W<double>(c->o_fahi);
+  a.dte = c->W<double>(c->o_dte);
+  a.gam = c->W<double>(c->o_gam);
+  a.nu = c->W<double>(c->o_nu);
+  a.beta = c->W<double>(c->o_beta);
+  a.dtbuf = c->W<double>(c->o_dtbuf);
+  a.counts = c->W<int>(c->o_counts);
+  return a;
+}
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipEvent_t get_event(cem_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// brackets one kernel launch with events when its id is selected
+struct Timed {
+  cem_ctx* c;
+  int id;
+  hipEvent_t b = nullptr;
+  Timed(cem_ctx* c_, int id_) : c(c_), id(id_) {
+    if (c->timing_mask & (1u << id)) {
+      hipEvent_t a = get_event(c);
+      b = get_event(c);
+      if (a && b) {
+        hipEventRecord(a, c->stream);
+        c->recs.push_back({id, a, b});
+      } else {
+        b = nullptr;
+      }
+    }
+  }
+  ~Timed() {
+    if (b) hipEventRecord(b, c->stream);
+  }
+};
+
+cem_status launch_line(cem_ctx* c, const double* in, double* out, int axis, bool grad) {
+  Timed tm(c, grad ? 0 : 4);
+  LineArgs la{};
+  la.in = in;
+  la.out = out;
+  const LineKernel& K = grad ? c->tabs.kgrad[axis] : c->tabs.kmass[axis];
+  la.w = c->W<double>(c->o_tab) + (grad ? c->off_kg[axis] : c->off_km[axis]);
+  la.taps = K.taps;
+  la.first = K.first;
+  la.L = c->L[axis];
+  la.P = c->p;
+  la.stride = axis == 0 ? 1 : (axis == 1 ? (int64_t)c->L[0] : (int64_t)c->L[0] * c->L[1]);
+  la.N = c->N;
+  la.total = (int64_t)c->m * c->N;
+  la.scale = 1.0;
+  hipLaunchKernelGGL(k_line, dim3(nblocks(la.total, 256)), dim3(256), 0, c->stream, la);
+  HIPCHK(hipGetLastError());
+  return CEM_OK;
+}
+
+template <int D, int P, int PH>
+cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
+  constexpr int M = Phys<D, PH>::M;
+  StageArgs a = make_args(c);
+  const double rka[3] = {0.0, 0.75, 1.0 / 3.0}, rkb[3] = {1.0, 0.25, 2.0 / 3.0};
+  a.rk_a = rka[stage];
+  a.rk_b = rkb[stage];
+  // projected gradient g_k = M_1D^{-1} C_1D u along axis k (Sec. 2.2)
+  for (int k = 0; k < D; ++k) {
+    cem_status s = launch_line(c, c->u, a.g + (int64_t)k * M * c->N, k, true);
+    if (s != CEM_OK) return s;
+  }
+  {
+    Timed tm(c, 1);
+    hipLaunchKernelGGL((k_elem1<D, P, PH>), dim3(nblocks(c->E, 128)), dim3(128), 0, c->stream, a);
+  }
+  HIPCHK(hipGetLastError());
+  {
+    Timed tm(c, 2);
+    hipLaunchKernelGGL(k_min_dt, dim3(1), dim3(1024), 0, c->stream, a.dte, c->E, a.dtbuf, stage, dt, cfl);
+  }
+  HIPCHK(hipGetLastError());
+  {
+    Timed tm(c, 3);
+    hipLaunchKernelGGL((k_gather_r<D, P, M>), dim3(nblocks(c->N, 256)), dim3(256), 0, c->stream, a);
+  }
+  HIPCHK(hipGetLastError());
+  // udot = M_C^{-1} r, one line solve per axis (Sec. 4.3, step 2)
+  double* tmp = c->W<double>(c->o_tmp);
+  double* tmp2 = c->W<double>(c->o_tmp2);
+  const double* src = a.r;
+  for (int k = 0; k < D; ++k) {
+    double* dst = (k == D - 1) ? a.udot : (k % 2 == 0 ? tmp : tmp2);
+    cem_status s = launch_line(c, src, dst, k, false);
+    if (s != CEM_OK) return s;
+    src = dst;
+  }
+  {
+    Timed tm(c, 5);
+    hipLaunchKernelGGL((k_elem2<D, P, PH>), dim3(nblocks(c->E, 128)), dim3(128), 0, c->stream, a);
+  }
+  HIPCHK(hipGetLastError());
+  {
+    Timed tm(c, 6);
+    hipLaunchKernelGGL((k_update<D, P, M, PH != EUL>), dim3(c->upd_blocks), dim3(256), 0, c->stream, a);
+  }
+  HIPCHK(hipGetLastError());
+  return CEM_OK;
+}
+
+using StageFn = cem_status (*)(cem_ctx*, int, double, double);
+
+StageFn pick(int d, int p, int kind) {
+#define CASE(D, P, PH) \
+  if (d == D && p == P && kind == PH) return &stage_impl<D, P, PH>;
+  CASE(1, 1, ADV) CASE(1, 2, ADV) CASE(1, 3, ADV)
+  CASE(1, 1, EUL) CASE(1, 2, EUL) CASE(1, 3, EUL)
+  CASE(2, 1, ADV) CASE(2, 2, ADV) CASE(2, 3, ADV)
+  CASE(2, 1, KPP) CASE(2, 2, KPP) CASE(2, 3, KPP)
+  CASE(2, 1, EUL) CASE(2, 2, EUL) CASE(2, 3, EUL)
+  CASE(3, 1, ADV) CASE(3, 2, ADV)
+  CASE(3, 1, EUL) CASE(3, 2, EUL)
+#undef CASE
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cem_last_error(void) { return g_err.c_str(); }
+
+cem_status cem_params_default(cem_params* p) {
+  if (!p) return fail(CEM_EINVAL, "null params");
+  std::memset(p, 0, sizeof(*p));
+  p->q = 1.0;
+  p->r = 2.0;
+  p->eps = 1e-12;
+  p->w_lin = 1e-3;
+  p->eps_pos = 1e-10;
+  p->clamp_ulps = 64.0;
+  p->u_min = -INFINITY;
+  p->u_max = INFINITY;
+  return CEM_OK;
+}
+
+cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, const cem_params* prm,
+                      void* stream, cem_ctx** out) {
+  if (!mesh || !phys || !prm || !out) return fail(CEM_EINVAL, "null argument");
+  const int d = mesh->dim, p = mesh->degree;
+  if (d < 1 || d > 3) return fail(CEM_EINVAL, "dim must be 1, 2 or 3");
+  if (!pick(d, p, phys->kind)) return fail(CEM_EINVAL, "unsupported (dim, degree, physics)");
+  double h = 0.0;
+  for (int k = 0; k < d; ++k) {
+    if (mesh->n[k] < 2) return fail(CEM_EINVAL, "need at least 2 cells per axis");
+    const double hk = (mesh->hi[k] - mesh->lo[k]) / mesh->n[k];
+    if (!(hk > 0.0)) return fail(CEM_EINVAL, "empty box");
+    if (k == 0) h = hk;
+    else if (std::fabs(hk - h) > 1e-12 * h) return fail(CEM_EINVAL, "cells must be cubes");
+  }
+  if (prm->q < 1.0 || prm->r <= 0.0 || prm->eps <= 0.0 || prm->w_lin < 0.0 || 2 * d * prm->w_lin >= 1.0)
+    return fail(CEM_EINVAL, "invalid WENO parameters");
+  if (phys->kind == CEM_ADVECTION) {
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) s += std::fabs(phys->velocity[k]);
+    if (s == 0.0) return fail(CEM_EINVAL, "zero advection velocity");
+  }
+  if (phys->kind == CEM_EULER && !(phys->gamma_gas > 1.0 && phys->gamma_gas <= 5.0 / 3.0))
+    return fail(CEM_EINVAL, "gamma must lie in (1, 5/3]");
+  cem_ctx* c = new cem_ctx();
+  c->d = d;
+  c->p = p;
+  c->kind = phys->kind;
+  c->m = phys->kind == CEM_EULER ? d + 2 : 1;
+  c->h = h;
+  c->N = 1;
+  c->E = 1;
+  for (int k = 0; k < d; ++k) {
+    c->n[k] = mesh->n[k];
+    c->L[k] = p * mesh->n[k];
+    c->N *= c->L[k];
+    c->E *= c->n[k];
+  }
+  c->nl = 1;
+  for (int k = 0; k < d; ++k) c->nl *= (p + 1);
+  c->prm = *prm;
+  for (int k = 0; k < 3; ++k) c->ph.vel[k] = k < d ? phys->velocity[k] : 0.0;
+  c->ph.vnorm = std::sqrt(c->ph.vel[0] * c->ph.vel[0] + c->ph.vel[1] * c->ph.vel[1] + c->ph.vel[2] * c->ph.vel[2]);
+  c->ph.gam = phys->gamma_gas;
+  c->stream = (hipStream_t)stream;
+  if (!build_tables(d, p, h, c->L, c->tabs)) {
+    delete c;
+    return fail(CEM_EINVAL, "table construction failed");
+  }
+  pack_tables(c);
+  // workspace carve-up
+  const size_t mN = (size_t)c->m * c->N * 8, mE = (size_t)c->m * c->E * 8, E8 = (size_t)c->E * 8;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += align256(bytes);
+    return r;
+  };
+  c->o_g = take((size_t)d * mN);
+  c->o_r = take(mN);
+  c->o_udot = take(mN);
+  c->o_tmp = take(mN);
+  c->o_tmp2 = take(mN);
+  c->o_relem = take((size_t)c->nl * mE);
+  c->o_ue = take(mE);
+  c->o_ubarL = take(mE);
+  c->o_ubar = take(mE);
+  c->o_fahi = take((size_t)d * mE);
+  c->o_dte = take(E8);
+  c->o_gam = take(E8);
+  c->o_nu = take(E8);
+  c->o_beta = take(E8);
+  c->o_dtbuf = take(8 * 8);
+  c->upd_blocks = (int)nblocks(c->N, 256);
+  c->o_counts = take((size_t)c->upd_blocks * 2 * sizeof(int));
+  c->inv_blocks = 256;
+  c->o_inv = take((size_t)c->inv_blocks * (c->m * 3 + 2) * 8);
+  c->o_tab = take(c->tabblob.size() * 8);
+  c->ws_need = o;
+  *out = c;
+  return CEM_OK;
+}
+
+cem_status cem_sizes(const cem_ctx* c, long long* N, long long* E, int* m) {
+  if (!c) return fail(CEM_EINVAL, "null context");
+  if (N) *N = c->N;
+  if (E) *E = c->E;
+  if (m) *m = c->m;
+  return CEM_OK;
+}
+
+cem_status cem_workspace_bytes(const cem_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(CEM_EINVAL, "null argument");
+  *bytes = c->ws_need;
+  return CEM_OK;
+}
+
+cem_status cem_reset_counters(cem_ctx* c) {
+  if (!c || !c->bound) return fail(CEM_EINVAL, "context not bound");
+  HIPCHK(hipMemsetAsync(c->ws + c->o_counts, 0, (size_t)c->upd_blocks * 2 * sizeof(int), c->stream));
+  HIPCHK(hipMemsetAsync(c->ws + c->o_dtbuf, 0, 8 * 8, c->stream));
+  return CEM_OK;
+}
+
+cem_status cem_bind(cem_ctx* c, double* u, double* u_base, void* workspace, size_t ws_bytes) {
+  if (!c || !u || !u_base || !workspace) return fail(CEM_EINVAL, "null argument");
+  if (u == u_base) return fail(CEM_EINVAL, "u and u_base must differ");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(CEM_EINVAL, "workspace not 256-byte aligned");
+  if (ws_bytes < c->ws_need) return fail(CEM_ENOMEM, "workspace too small");
+  c->u = u;
+  c->u0 = u_base;
+  c->ws = static_cast<char*>(workspace);
+  HIPCHK(hipMemcpyAsync(c->ws + c->o_tab, c->tabblob.data(), c->tabblob.size() * 8, hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));   // the host table blob stays alive, but keep bind simple
+  c->bound = true;
+  return cem_reset_counters(c);
+}
+
+cem_status cem_upload_state(cem_ctx* c, const double* host_u) {
+  if (!c || !c->bound || !host_u) return fail(CEM_EINVAL, "context not bound / null");
+  HIPCHK(hipMemcpyAsync(c->u, host_u, (size_t)c->m * c->N * 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CEM_OK;
+}
+
+cem_status cem_download_state(cem_ctx* c, double* host_u) {
+  if (!c || !c->bound || !host_u) return fail(CEM_EINVAL, "context not bound / null");
+  HIPCHK(hipMemcpyAsync(host_u, c->u, (size_t)c->m * c->N * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CEM_OK;
+}
+
+cem_status cem_set_bounds(cem_ctx* c, int from_state, double u_min, double u_max) {
+  if (!c || !c->bound) return fail(CEM_EINVAL, "context not bound");
+  if (c->kind == CEM_EULER) return CEM_OK;
+  if (from_state) {
+    cem_invariants inv;
+    c->prm.u_min = -INFINITY;
+    c->prm.u_max = INFINITY;
+    cem_status s = cem_check_invariants(c, &inv);
+    if (s != CEM_OK && s != CEM_EIDP && s != CEM_ECFL) return s;
+    u_min = inv.u_min[0];
+    u_max = inv.u_max[0];
+  }
+  if (!(u_min <= u_max)) return fail(CEM_EINVAL, "u_min > u_max");
+  c->prm.u_min = u_min;
+  c->prm.u_max = u_max;
+  c->bounds_set = true;
+  return CEM_OK;
+}
+
+cem_status cem_rk_stage(cem_ctx* c, int stage, double dt, double cfl) {
+  if (!c || !c->bound) return fail(CEM_EINVAL, "context not bound");
+  if (stage < 0 || stage > 2) return fail(CEM_EINVAL, "stage must be 0, 1 or 2");
+  if (stage == 0 && !(dt > 0.0) && !(cfl > 0.0)) return fail(CEM_EINVAL, "need dt > 0 or cfl > 0");
+  if (c->kind != CEM_EULER && !c->bounds_set) return fail(CEM_EINVAL, "scalar bounds not set");
+  return pick(c->d, c->p, c->kind)(c, stage, dt, cfl);
+}
+
+cem_status cem_step(cem_ctx* c, double dt, double cfl) {
+  if (!c || !c->bound) return fail(CEM_EINVAL, "context not bound");
+  HIPCHK(hipMemcpyAsync(c->u0, c->u, (size_t)c->m * c->N * 8, hipMemcpyDeviceToDevice, c->stream));
+  for (int s = 0; s < 3; ++s) {
+    cem_status st = cem_rk_stage(c, s, dt, cfl);
+    if (st != CEM_OK) return st;
+  }
+  return CEM_OK;
+}
+
+cem_status cem_check_invariants(cem_ctx* c, cem_invariants* out) {
+  if (!c || !c->bound || !out) return fail(CEM_EINVAL, "context not bound / null");
+  std::memset(out, 0, sizeof(*out));
+  InvArgs ia{};
+  ia.u = c->u;
+  ia.N = c->N;
+  ia.M = c->m;
+  ia.D = c->d;
+  ia.euler = c->kind == CEM_EULER;
+  ia.gam = c->ph.gam;
+  double hd = 1.0;
+  for (int k = 0; k < c->d; ++k) hd *= c->h;
+  ia.mnode = hd / c->nl;
+  ia.P = c->p;
+  ia.Lx = c->L[0];
+  ia.Ly = c->L[1];
+  ia.part = c->W<double>(c->o_inv);
+  hipLaunchKernelGGL(k_inv_partial, dim3(c->inv_blocks), dim3(256), 0, c->stream, ia);
+  HIPCHK(hipGetLastError());
+  const int nv = c->m * 3 + 2;
+  std::vector<double> part((size_t)c->inv_blocks * nv);
+  std::vector<int> cnt((size_t)c->upd_blocks * 2);
+  double dtb[8];
+  HIPCHK(hipMemcpyAsync(part.data(), ia.part, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(cnt.data(), c->ws + c->o_counts, cnt.size() * sizeof(int), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(dtb, c->ws + c->o_dtbuf, sizeof(dtb), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  out->m = c->m;
+  for (int v = 0; v < c->m; ++v) {
+    out->u_min[v] = INFINITY;
+    out->u_max[v] = -INFINITY;
+    out->mass[v] = 0.0;
+  }
+  out->rho_min = INFINITY;
+  out->p_min = INFINITY;
+  for (int b = 0; b < c->inv_blocks; ++b)
+    for (int v = 0; v < nv; ++v) {
+      const double x = part[(size_t)b * nv + v];
+      if (v >= c->m * 3) {
+        if (!ia.euler) continue;
+        if (v == c->m * 3) out->rho_min = std::fmin(out->rho_min, x);
+        else out->p_min = std::fmin(out->p_min, x);
+      } else if (v % 3 == 0) {
+        out->u_min[v / 3] = std::fmin(out->u_min[v / 3], x);
+      } else if (v % 3 == 1) {
+        out->u_max[v / 3] = std::fmax(out->u_max[v / 3], x);
+      } else {
+        out->mass[v / 3] += x;
+      }
+    }
+  for (int b = 0; b < c->upd_blocks; ++b) {
+    out->clamped += cnt[2 * (size_t)b];
+    out->violations += cnt[2 * (size_t)b + 1];
+  }
+  out->dt = dtb[0];
+  out->min_dt_e = dtb[1];
+  out->cfl_violated = dtb[2] != 0.0;
+  if (ia.euler && !(out->rho_min > 0.0 && out->p_min > 0.0)) out->violations += 1;
+  if (out->cfl_violated) return fail(CEM_ECFL, "dt exceeded min_e dt_e");
+  if (out->violations) return fail(CEM_EIDP, "invariant domain violated");
+  return CEM_OK;
+}
+
+size_t cem_tap_size(const cem_ctx* c, int tap) {
+  if (!c) return 0;
+  const size_t mN = (size_t)c->m * c->N, mE = (size_t)c->m * c->E, E = (size_t)c->E;
+  switch (tap) {
+    case 0: return (size_t)c->d * mN;
+    case 1: case 2: return mN;
+    case 3: case 4: case 5: case 9: return E;
+    case 6: case 7: case 8: return mE;
+    case 10: return (size_t)c->d * mE;
+    case 11: return (size_t)c->nl * mE;
+    default: return 0;
+  }
+}
+
+cem_status cem_debug_tap(cem_ctx* c, int tap, double* dst, size_t count) {
+  if (!c || !c->bound || !dst) return fail(CEM_EINVAL, "context not bound / null");
+  const size_t n = cem_tap_size(c, tap);
+  if (n == 0 || count != n) return fail(CEM_EINVAL, "bad tap id or count");
+  const size_t offs[12] = {c->o_g, c->o_r, c->o_udot, c->o_gam, c->o_nu, c->o_dte,
+                           c->o_ue, c->o_ubarL, c->o_ubar, c->o_beta, c->o_fahi, c->o_relem};
+  HIPCHK(hipMemcpyAsync(dst, c->ws + offs[tap], n * 8, hipMemcpyDeviceToDevice, c->stream));
+  return CEM_OK;
+}
+
+cem_status cem_set_timing(cem_ctx* c, unsigned mask) {
+  if (!c) return fail(CEM_EINVAL, "null context");
+  c->timing_mask = mask & ((1u << CEM_NUM_KERNELS) - 1);
+  return CEM_OK;
+}
+
+cem_status cem_kernel_times(cem_ctx* c, double* total_ms, long long* launches, int n) {
+  if (!c || !total_ms || !launches || n < 0) return fail(CEM_EINVAL, "null argument");
+  for (int i = 0; i < n; ++i) {
+    total_ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (auto& r : c->recs) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    if (r.id < n) {
+      total_ms[r.id] += ms;
+      launches[r.id] += 1;
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->recs.clear();
+  return CEM_OK;
+}
+
+void cem_destroy(cem_ctx* c) {
+  if (!c) return;
+  for (auto& r : c->recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (auto e : c->pool) hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,886 @@
+// gfx950 kernels of one explicit SSP-RK stage of the limited CG-WENO scheme
+// (Kuzmin, Hajduk & Vedral, arXiv:2509.04673, the five-step algorithm of
+// Sec. 4.3), on a uniform periodic box of cube cells, Bernstein Q_p.
+//
+// Data layout (HBM): nodal arrays are structure-of-arrays, component-major,
+// u[c * N + node], node = i_0 + L_0 (i_1 + L_1 i_2) with i_k in [0, p n_k).
+// Per-element arrays are component-major with the element index fastest,
+// x[(c * NL + local) * E + e], so one-thread-per-element stores coalesce.
+// Assembly into shared nodes is a node-centric gather in a fixed order (no
+// float atomics): results are bitwise reproducible run to run.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cem {
+
+constexpr int ADV = 0, KPP = 1, EUL = 2;
+
+__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+// k-th base-(p+1) digit of a local id (axis 0 fastest)
+__host__ __device__ constexpr int dig(int loc, int k, int P1) {
+  return k == 0 ? loc % P1 : dig(loc / P1, k - 1, P1);
+}
+
+struct PhysParams {
+  double vel[3];
+  double vnorm;     // |v| (advection)
+  double gam;       // ratio of specific heats (Euler)
+};
+
+struct DevTabs {
+  const double* vqf;    // [NQ][NL] basis values at the Gauss points
+  const double* dqw;    // [D][NQ][NL] W_q d_k phi_j(x_q) (reference cell)
+  const double* mass;   // [NL][NL]
+  const double* ksum;   // [NL][NL]
+  const double* ctg;    // [D][NL][NL]
+  const double* qf;     // [1+2D][NL][NL]
+  const double* ext;    // [2][P1][P1]
+  const double* facem;  // [NF][NF]
+  const double* kgrad[3];
+  const double* kmass[3];
+  int gtaps[3], gfirst[3], mtaps[3], mfirst[3];
+};
+
+struct MeshArgs {
+  int n[3];         // elements per axis (1 for unused axes)
+  int L[3];         // nodes per axis (1 for unused axes)
+  int64_t N, E;
+  double h;
+};
+
+struct StageArgs {
+  MeshArgs mesh;
+  DevTabs tab;
+  PhysParams ph;
+  double q, rexp, eps, w_lin, eps_pos;
+  int gamma_mode, alpha_mode, beta_mode;   // 0 method, 1 force 0, 2 force 1
+  double umin, umax, clamp_tol;
+  const double* u;      // stage input u^(s)   [M][N]
+  const double* u0;     // step base u^n       [M][N]
+  double* uout;         // stage output (may alias u: per-node read-then-write)
+  double* g;            // [D][M][N] projected gradient
+  double* r;            // [M][N] residual
+  double* udot;         // [M][N]
+  double* relem;        // [M][NL][E] element vectors (residual, then update)
+  double* ue;           // [M][E] cell averages
+  double* ubarL;        // [M][E] low-order intermediate averages
+  double* ubar;         // [M][E] flux-limited intermediate averages
+  double* fahi;         // [D][M][E] raw antidiffusive flux of the +e_k facet
+  double* dte;          // [E] pseudo time steps
+  double* gam;          // [E] WENO sensor
+  double* nu;           // [E] viscosity
+  double* beta;         // [E] slope-limiter factor
+  double* dtbuf;        // [4]: dt, min dt_e, cfl flag, (spare)
+  int* counts;          // per-block [2]: clamped, violations
+  double rk_a, rk_b;    // u_out = a u0 + b u^FE
+};
+
+// ---------------------------------------------------------------------------
+// physics
+// ---------------------------------------------------------------------------
+template <int D, int PH> struct Phys;
+
+template <int D> struct Phys<D, ADV> {
+  static constexpr int M = 1;
+  __device__ static inline void flux(int k, const double* u, double* f, const PhysParams& pp) {
+    f[0] = pp.vel[k] * u[0];
+  }
+  __device__ static inline double node_speed(const double*, const PhysParams& pp) { return pp.vnorm; }
+  __device__ static inline double riemann_speed(const double*, const double*, int k, const PhysParams& pp) {
+    return fabs(pp.vel[k]);
+  }
+};
+
+template <int D> struct Phys<D, KPP> {
+  static constexpr int M = 1;
+  __device__ static inline void flux(int k, const double* u, double* f, const PhysParams&) {
+    f[0] = (k == 0) ? sin(u[0]) : cos(u[0]);
+  }
+  // |f'(u)| = |(cos u, -sin u)| = 1
+  __device__ static inline double node_speed(const double*, const PhysParams&) { return 1.0; }
+  __device__ static inline double riemann_speed(const double*, const double*, int, const PhysParams&) {
+    return 1.0;
+  }
+};
+
+template <int D> struct Phys<D, EUL> {
+  static constexpr int M = D + 2;
+  __device__ static inline double pressure(const double* u, const PhysParams& pp) {
+    double m2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) m2 += u[1 + k] * u[1 + k];
+    return (pp.gam - 1.0) * (u[D + 1] - 0.5 * m2 / u[0]);
+  }
+  __device__ static inline void flux(int k, const double* u, double* f, const PhysParams& pp) {
+    const double p = pressure(u, pp);
+    const double vk = u[1 + k] / u[0];
+    f[0] = u[1 + k];
+#pragma unroll
+    for (int j = 0; j < D; ++j) f[1 + j] = u[1 + j] * vk + (j == k ? p : 0.0);
+    f[D + 1] = vk * (u[D + 1] + p);
+  }
+  __device__ static inline double node_speed(const double* u, const PhysParams& pp) {
+    double v2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double v = u[1 + k] / u[0];
+      v2 += v * v;
+    }
+    const double c = sqrt(fmax(0.0, pp.gam * pressure(u, pp) / u[0]));
+    return sqrt(v2) + c;
+  }
+  // Guaranteed upper bound of the largest wave speed of the 1D Riemann
+  // problem along +e_k: two-rarefaction estimate of the star pressure
+  // (Guermond & Popov 2016), an upper bound for 1 < gamma <= 5/3.
+  __device__ static inline double riemann_speed(const double* uL, const double* uR, int k,
+                                                const PhysParams& pp) {
+    const double g = pp.gam;
+    const double vL = uL[1 + k] / uL[0], vR = uR[1 + k] / uR[0];
+    const double pL = pressure(uL, pp), pR = pressure(uR, pp);
+    const double cL = sqrt(fmax(0.0, g * pL / uL[0]));
+    const double cR = sqrt(fmax(0.0, g * pR / uR[0]));
+    const double ex = (g - 1.0) / (2.0 * g);
+    const double num = fmax(cL + cR - 0.5 * (g - 1.0) * (vR - vL), 0.0);
+    const double den = cL * pow(pL, -ex) + cR * pow(pR, -ex);
+    const double ps = pow(num / den, 1.0 / ex);
+    const double kap = (g + 1.0) / (2.0 * g);
+    const double l1 = vL - cL * sqrt(1.0 + kap * fmax(0.0, (ps - pL) / pL));
+    const double l3 = vR + cR * sqrt(1.0 + kap * fmax(0.0, (ps - pR) / pR));
+    return fmax(fmax(-l1, 0.0), fmax(l3, 0.0));
+  }
+};
+
+// Appendix A: largest alpha in [0,1] with ubar + alpha f / mi admissible
+// (density, then pressure through P(alpha) >= alpha R), strict margin eps.
+template <int D>
+__device__ inline double euler_alpha(const double* ub, const double* f, double mi, double eps) {
+  const double rho = ub[0], en = ub[D + 1], fr = f[0], fe = f[D + 1];
+  double a = 1.0;
+  if (mi * rho * (1.0 - eps) + fr < 0.0) a = (1.0 - eps) * (-mi * rho / fr);
+  double m2 = 0.0, mf = 0.0, f2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    m2 += ub[1 + k] * ub[1 + k];
+    mf += ub[1 + k] * f[1 + k];
+    f2 += f[1 + k] * f[1 + k];
+  }
+  const double Q = mi * (0.5 * m2 - rho * en);
+  const double R = rho * fe + en * fr - mf + fmin(0.0, fe * fr - 0.5 * f2) / mi;
+  if (R < (1.0 - eps) * Q) a = fmin(a, (1.0 - eps) * Q / R);
+  return fmin(a, 1.0);
+}
+
+// ---------------------------------------------------------------------------
+// index helpers
+// ---------------------------------------------------------------------------
+__device__ inline void elem_coords(int64_t e, const MeshArgs& m, int* ei) {
+  ei[0] = (int)(e % m.n[0]);
+  int64_t r = e / m.n[0];
+  ei[1] = (int)(r % m.n[1]);
+  ei[2] = (int)(r / m.n[1]);
+}
+
+__device__ inline int64_t elem_id(const int* ei, const MeshArgs& m) {
+  return ei[0] + (int64_t)m.n[0] * (ei[1] + (int64_t)m.n[1] * ei[2]);
+}
+
+__device__ inline int64_t node_stride(int k, const MeshArgs& m) {
+  return k == 0 ? 1 : (k == 1 ? (int64_t)m.L[0] : (int64_t)m.L[0] * m.L[1]);
+}
+
+// global node offsets along axis k of the local indices a = 0..P of the
+// element with (possibly out-of-range, periodic) coordinate ek
+template <int P>
+__device__ inline void axis_offsets(int ek, int k, const MeshArgs& m, int64_t* off) {
+  const int n = m.n[k], L = m.L[k];
+  ek = (ek % n + n) % n;
+  const int64_t s = node_stride(k, m);
+#pragma unroll
+  for (int a = 0; a <= P; ++a) {
+    int i = P * ek + a;
+    if (i >= L) i -= L;
+    off[a] = i * s;
+  }
+}
+
+template <int D, int P>
+__device__ inline int64_t local_node(int loc, const int64_t (*off)[P + 1]) {
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) s += off[k][dig(loc, k, P + 1)];
+  return s;
+}
+
+// symmetric quadratic form x^T Q x
+template <int NL>
+__device__ inline double qform(const double* __restrict__ Q, const double* x) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) t += Q[i * NL + j] * x[j];
+    s += x[i] * t;
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// line operators: out = scale * (M_1D^{-1} or M_1D^{-1} C_1D) applied along
+// axis k; one thread per output value; exact periodic rows for short lines,
+// rows truncated far below rounding for long ones
+// ---------------------------------------------------------------------------
+struct LineArgs {
+  const double* in;
+  double* out;
+  const double* w;     // [P][taps]
+  int taps, first, L, P;
+  int64_t stride, total, N;
+  double scale;
+};
+
+__global__ void __launch_bounds__(256) k_line(LineArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.total) return;
+  const int64_t c = t / a.N, i = t - c * a.N;
+  const int64_t ik = (i / a.stride) % a.L;
+  const int64_t base = c * a.N + i - ik * a.stride;
+  const int cls = (int)(ik % a.P);
+  const double* w = a.w + (int64_t)cls * a.taps;
+  int j = (int)((ik + a.first) % a.L);
+  if (j < 0) j += a.L;
+  double acc = 0.0;
+  for (int tt = 0; tt < a.taps; ++tt) {
+    acc += w[tt] * a.in[base + j * a.stride];
+    if (++j == a.L) j = 0;
+  }
+  a.out[t] = a.scale * acc;
+}
+
+// ---------------------------------------------------------------------------
+// step 1 of the algorithm: element loop (WENO sensor, viscosity, residual)
+// plus the facet data of step 3 (f^H, f^L, lambda, dt_e, low-order average)
+// ---------------------------------------------------------------------------
+template <int D, int P, int PH>
+__global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
+  using PHY = Phys<D, PH>;
+  constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NF = NL / P1;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const MeshArgs& ms = a.mesh;
+  if (e >= ms.E) return;
+  const int64_t N = ms.N, E = ms.E;
+  const double h = ms.h;
+  int ei[3];
+  elem_coords(e, ms, ei);
+  int64_t off[D][P1];
+#pragma unroll
+  for (int k = 0; k < D; ++k) axis_offsets<P>(ei[k], k, ms, off[k]);
+
+  double U[M][NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const int64_t nd = local_node<D, P>(j, off);
+#pragma unroll
+    for (int c = 0; c < M; ++c) U[c][j] = a.u[c * N + nd];
+  }
+  double ue[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) s += U[c][j];
+    ue[c] = s * (1.0 / NL);
+  }
+
+  // ---- WENO sensor (Sec. 2.2, eqs. 7-8), per component; systems take the
+  // minimum.  Semi-norms are quadratic forms on coefficients shifted by their
+  // first entry, so exactly constant polynomials give exactly zero.
+  double nbr_mean[2 * D][M];
+  double gmin = 1.0;
+  for (int c = 0; c < M; ++c) {
+    double ct[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) ct[j] = U[c][j] - U[c][0];
+    double beta[1 + 2 * D];
+    beta[0] = qform<NL>(a.tab.qf, ct);
+#pragma unroll
+    for (int l = 0; l < 2 * D; ++l) {
+      const int k = l / 2, s = (l % 2) ? 1 : -1;
+      int64_t offn[D][P1];
+#pragma unroll
+      for (int kk = 0; kk < D; ++kk) axis_offsets<P>(ei[kk] + (kk == k ? s : 0), kk, ms, offn[kk]);
+      double cn[NL], sum = 0.0;
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        cn[j] = a.u[c * N + local_node<D, P>(j, offn)];
+        sum += cn[j];
+      }
+      nbr_mean[l][c] = sum * (1.0 / NL);
+      const double c0 = cn[0];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) cn[j] -= c0;
+      beta[1 + l] = qform<NL>(a.tab.qf + (size_t)(1 + l) * NL * NL, cn);
+    }
+    if (a.gamma_mode != 0) continue;
+    const double wl0 = 1.0 - 2 * D * a.w_lin;
+    double wt[1 + 2 * D], wsum = 0.0;
+#pragma unroll
+    for (int l = 0; l <= 2 * D; ++l) {
+      const double nr = (a.rexp == 2.0) ? beta[l] : pow(beta[l], 0.5 * a.rexp);
+      wt[l] = (l == 0 ? wl0 : a.w_lin) / (nr + a.eps);
+      wsum += wt[l];
+    }
+    double w[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) w[j] = 0.0;
+#pragma unroll
+    for (int l = 0; l < 2 * D; ++l) {
+      const int k = l / 2, s = (l % 2) ? 1 : -1;
+      const double om = wt[1 + l] / wsum;
+      int64_t offn[D][P1];
+#pragma unroll
+      for (int kk = 0; kk < D; ++kk) axis_offsets<P>(ei[kk] + (kk == k ? s : 0), kk, ms, offn[kk]);
+      double cn[NL];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) cn[j] = a.u[c * N + local_node<D, P>(j, offn)];
+      const double c0 = cn[0];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) cn[j] -= c0;
+      const double* E1 = a.tab.ext + (s > 0 ? P1 * P1 : 0);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const int ai = dig(i, k, P1);
+        double ex = 0.0;
+#pragma unroll
+        for (int b = 0; b < P1; ++b) {
+          const int j = i + (b - ai) * ipow(P1, k);
+          ex += E1[ai * P1 + b] * cn[j];
+        }
+        w[i] += om * (ct[i] - ex);
+      }
+    }
+    // the ratio of eq. (7) is 0/0 on constant elements; it is regularised
+    // with the weights' epsilon: ||u - u*|| / (||u||^2 + eps)^(1/2)
+    const double dev = sqrt(fmax(qform<NL>(a.tab.qf, w), 0.0));
+    const double ratio = fmin(1.0, dev / sqrt(fmax(beta[0], 0.0) + a.eps));
+    const double gc = 1.0 - (a.q == 1.0 ? ratio : pow(ratio, a.q));
+    gmin = fmin(gmin, gc);
+  }
+  const double gam = a.gamma_mode == 0 ? gmin : (a.gamma_mode == 1 ? 0.0 : 1.0);
+
+  // ---- viscosity nu_e = lambda_e h / (2p), lambda_e the largest nodal speed
+  double lam = 0.0;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    double uj[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) uj[c] = U[c][j];
+    lam = fmax(lam, PHY::node_speed(uj, a.ph));
+  }
+  const double nu = lam * h / (2.0 * P);
+
+  // ---- element residual R_i = int grad phi_i . f(u_h) - s_h^e(phi_i, u_h)
+  double R[M][NL];
+#pragma unroll
+  for (int c = 0; c < M; ++c)
+#pragma unroll
+    for (int i = 0; i < NL; ++i) R[c][i] = 0.0;
+  double hpow = 1.0;
+#pragma unroll
+  for (int k = 0; k < D - 1; ++k) hpow *= h;   // h^{D-1}
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    double uq[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < NL; ++j) s += a.tab.vqf[q * NL + j] * U[c][j];
+      uq[c] = s;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double f[M];
+      PHY::flux(k, uq, f, a.ph);
+      const double* dw = a.tab.dqw + ((size_t)k * NL + q) * NL;
+#pragma unroll
+      for (int i = 0; i < NL; ++i)
+#pragma unroll
+        for (int c = 0; c < M; ++c) R[c][i] += dw[i] * f[c];
+    }
+  }
+  const double sa = nu * hpow / h, sg = nu * gam * hpow;   // nu h^{D-2}, nu gamma h^{D-1}
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    double gk[D][NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int64_t nd = local_node<D, P>(j, off);
+#pragma unroll
+      for (int k = 0; k < D; ++k) gk[k][j] = a.g[((int64_t)k * M + c) * N + nd];
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < NL; ++j) s1 += a.tab.ksum[i * NL + j] * U[c][j];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int j = 0; j < NL; ++j) s2 += a.tab.ctg[((size_t)k * NL + i) * NL + j] * gk[k][j];
+      R[c][i] = hpow * R[c][i] - (sa * s1 - sg * s2);
+      a.relem[((int64_t)c * NL + i) * E + e] = R[c][i];
+    }
+  }
+
+  // ---- facets (Sec. 4, eqs. 18, 40, 42, 51): canonical orientation is from
+  // the lower to the upper element along +e_k; both sides evaluate it alike
+  double lamsum = 0.0, fLsum[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) fLsum[c] = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const double* uL = side ? ue : nbr_mean[2 * k];
+      const double* uR = side ? nbr_mean[2 * k + 1] : ue;
+      double fH[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) fH[c] = 0.0;
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        if (dig(j, k, P1) != (side ? P : 0)) continue;
+        double uj[M], fj[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) uj[c] = U[c][j];
+        PHY::flux(k, uj, fj, a.ph);
+#pragma unroll
+        for (int c = 0; c < M; ++c) fH[c] += fj[c];
+      }
+      const double lm = PHY::riemann_speed(uL, uR, k, a.ph);
+      double fl[M], fr[M];
+      PHY::flux(k, uL, fl, a.ph);
+      PHY::flux(k, uR, fr, a.ph);
+      lamsum += lm;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const double fLc = 0.5 * (fl[c] + fr[c]) - 0.5 * lm * (uR[c] - uL[c]);
+        fLsum[c] += side ? fLc : -fLc;
+        if (side) a.fahi[((int64_t)k * M + c) * E + e] = fLc - fH[c] * (1.0 / NF);
+      }
+    }
+  }
+  const double dt_e = h / lamsum;
+  a.dte[e] = dt_e;
+  a.gam[e] = gam;
+  a.nu[e] = nu;
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    a.ue[c * E + e] = ue[c];
+    a.ubarL[c * E + e] = ue[c] - dt_e / h * fLsum[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// steps 3-4: flux limiter (eq. 53 / Appendix A), element contributions
+// (eq. 45), slope limiter (eqs. 54-55 / Appendix A); stores the element
+// update vector [m_i^e (ubar - u_i) + beta f_i^e] / dt_e
+// ---------------------------------------------------------------------------
+template <int D, int PH>
+__device__ inline void limit_facet(const StageArgs& a, int k, int64_t eL, int64_t eR, double* fb) {
+  using PHY = Phys<D, PH>;
+  constexpr int M = PHY::M;
+  const int64_t E = a.mesh.E;
+  double fA[M], uLs[M], uRs[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    fA[c] = a.fahi[((int64_t)k * M + c) * E + eL];
+    uLs[c] = a.ubarL[c * E + eL];
+    uRs[c] = a.ubarL[c * E + eR];
+  }
+  const double dtL = a.dte[eL], dtR = a.dte[eR];
+  const double phi = a.mesh.h / (2.0 * D);     // |K| / |dK|
+  if (a.alpha_mode == 2) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) fb[c] = fA[c];
+    return;
+  }
+  if (a.alpha_mode == 1) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) fb[c] = 0.0;
+    return;
+  }
+  if constexpr (PH == EUL) {
+    double dL[M], dR[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      dL[c] = fA[c] / phi * dtL;
+      dR[c] = -fA[c] / phi * dtR;
+    }
+    const double al = fmin(euler_alpha<D>(uLs, dL, 1.0, a.eps_pos), euler_alpha<D>(uRs, dR, 1.0, a.eps_pos));
+#pragma unroll
+    for (int c = 0; c < M; ++c) fb[c] = al * fA[c];
+  } else {
+    const double fmx = fmin(phi * (a.umax - uLs[0]) / dtL, phi * (uRs[0] - a.umin) / dtR);
+    const double fmn = fmax(phi * (a.umin - uLs[0]) / dtL, phi * (uRs[0] - a.umax) / dtR);
+    fb[0] = fA[0] >= 0.0 ? fmin(fA[0], fmx) : fmax(fA[0], fmn);
+  }
+}
+
+template <int D, int P, int PH>
+__global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
+  using PHY = Phys<D, PH>;
+  constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NF = NL / P1;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const MeshArgs& ms = a.mesh;
+  if (e >= ms.E) return;
+  const int64_t N = ms.N, E = ms.E;
+  const double h = ms.h;
+  int ei[3];
+  elem_coords(e, ms, ei);
+  int64_t off[D][P1];
+#pragma unroll
+  for (int k = 0; k < D; ++k) axis_offsets<P>(ei[k], k, ms, off[k]);
+
+  // ---- flux-limited intermediate average (eq. 44)
+  const double dt_e = a.dte[e];
+  double fbs[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) fbs[c] = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    int en[3] = {ei[0], ei[1], ei[2]};
+    en[k] = (ei[k] + ms.n[k] - 1) % ms.n[k];
+    const int64_t elo = elem_id(en, ms);
+    en[k] = (ei[k] + 1) % ms.n[k];
+    const int64_t ehi = elem_id(en, ms);
+    double fb[M];
+    limit_facet<D, PH>(a, k, elo, e, fb);
+#pragma unroll
+    for (int c = 0; c < M; ++c) fbs[c] -= fb[c];
+    limit_facet<D, PH>(a, k, e, ehi, fb);
+#pragma unroll
+    for (int c = 0; c < M; ++c) fbs[c] += fb[c];
+  }
+  double ub[M], uec[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    ub[c] = a.ubarL[c * E + e] + dt_e / h * fbs[c];
+    uec[c] = a.ue[c * E + e];
+    a.ubar[c * E + e] = ub[c];
+  }
+
+  double U[M][NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const int64_t nd = local_node<D, P>(j, off);
+#pragma unroll
+    for (int c = 0; c < M; ++c) U[c][j] = a.u[c * N + nd];
+  }
+
+  // ---- boundary integral B_i = int_{dK} phi_i f_h . n (so that
+  // int grad phi_i . f_h + int phi_i div f_h = B_i) and F^e = sum_i B_i
+  double hpow = 1.0;
+#pragma unroll
+  for (int k = 0; k < D - 1; ++k) hpow *= h;
+  double f[M][NL];
+#pragma unroll
+  for (int c = 0; c < M; ++c)
+#pragma unroll
+    for (int i = 0; i < NL; ++i) f[c][i] = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int av = side ? P : 0;
+      const double sg = side ? hpow : -hpow;
+      double fn[M][NF];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        if (dig(j, k, P1) != av) continue;
+        // facet-local id: drop digit k
+        const int lo = j % ipow(P1, k), hi = j / ipow(P1, k + 1);
+        const int fj = lo + hi * ipow(P1, k);
+        double uj[M], fv[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) uj[c] = U[c][j];
+        PHY::flux(k, uj, fv, a.ph);
+#pragma unroll
+        for (int c = 0; c < M; ++c) fn[c][fj] = fv[c];
+      }
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        if (dig(i, k, P1) != av) continue;
+        const int lo = i % ipow(P1, k), hi = i / ipow(P1, k + 1);
+        const int fi = lo + hi * ipow(P1, k);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          double s = 0.0;
+#pragma unroll
+          for (int fj = 0; fj < NF; ++fj) s += a.tab.facem[fi * NF + fj] * fn[c][fj];
+          f[c][i] += sg * s;
+        }
+      }
+    }
+  }
+  double hd = hpow * h;
+  const double mloc = hd * (1.0 / NL);
+  // f currently holds B_i; build f_i^e of eq. (45) in place
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    double Fe = 0.0;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) Fe += f[c][i];
+    double ud[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) ud[j] = a.udot[c * N + local_node<D, P>(j, off)];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < NL; ++j) t += a.tab.mass[i * NL + j] * ud[j];
+      const double T = hd * t - mloc * ud[i];
+      const double R = a.relem[((int64_t)c * NL + i) * E + e];
+      f[c][i] = mloc * (U[c][i] - uec[c]) + dt_e * (R - f[c][i] + Fe * (1.0 / NL) - T);
+    }
+  }
+
+  // ---- slope limiter
+  double beta = 1.0;
+  if (a.beta_mode == 1) {
+    beta = 0.0;
+  } else if (a.beta_mode == 0) {
+    if constexpr (PH == EUL) {
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        double fi[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) fi[c] = f[c][i];
+        beta = fmin(beta, euler_alpha<D>(ub, fi, mloc, a.eps_pos));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const double fi = f[0][i];
+        double bi = 1.0;
+        // ubar is in bounds up to rounding: a ratio made negative by a
+        // rounding excess counts as 0
+        if (fi > 0.0) bi = fmax(0.0, fmin(1.0, mloc * (a.umax - ub[0]) / fi));
+        else if (fi < 0.0) bi = fmax(0.0, fmin(1.0, mloc * (a.umin - ub[0]) / fi));
+        beta = fmin(beta, bi);
+      }
+    }
+  }
+  a.beta[e] = beta;
+  const double idt = 1.0 / dt_e;
+#pragma unroll
+  for (int c = 0; c < M; ++c)
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+      a.relem[((int64_t)c * NL + i) * E + e] = (mloc * (ub[c] - U[c][i]) + beta * f[c][i]) * idt;
+}
+
+// ---------------------------------------------------------------------------
+// node-centric gathers of element vectors (fixed element order per node)
+// ---------------------------------------------------------------------------
+template <int D, int P>
+__device__ inline int node_elements(int64_t i, const MeshArgs& m, int64_t* eids, int* locs) {
+  int ik[3] = {0, 0, 0};
+  int64_t r = i;
+  ik[0] = (int)(r % m.L[0]);
+  r /= m.L[0];
+  if (D > 1) {
+    ik[1] = (int)(r % m.L[1]);
+    r /= m.L[1];
+  }
+  if (D > 2) ik[2] = (int)r;
+  int cnt[3], ek[3][2], ak[3][2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    cnt[k] = 1;
+    ek[k][0] = 0;
+    ak[k][0] = 0;
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const int e0 = ik[k] / P, a0 = ik[k] % P;
+    if (a0 == 0) {
+      cnt[k] = 2;
+      ek[k][0] = (e0 + m.n[k] - 1) % m.n[k];   // lower element sees it at a = P
+      ak[k][0] = P;
+      ek[k][1] = e0;
+      ak[k][1] = 0;
+    } else {
+      ek[k][0] = e0;
+      ak[k][0] = a0;
+    }
+  }
+  int nrec = 0;
+  for (int z = 0; z < cnt[2]; ++z)
+    for (int y = 0; y < cnt[1]; ++y)
+      for (int x = 0; x < cnt[0]; ++x) {
+        const int ee[3] = {ek[0][x], ek[1][y], ek[2][z]};
+        eids[nrec] = elem_id(ee, m);
+        locs[nrec] = ak[0][x] + (P + 1) * (ak[1][y] + (P + 1) * ak[2][z]);
+        ++nrec;
+      }
+  return nrec;
+}
+
+template <int D, int P, int M>
+__global__ void __launch_bounds__(256) k_gather_r(StageArgs a) {
+  constexpr int NL = ipow(P + 1, D);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.mesh.N) return;
+  int64_t eids[8];
+  int locs[8];
+  const int nrec = node_elements<D, P>(i, a.mesh, eids, locs);
+  const int64_t E = a.mesh.E, N = a.mesh.N;
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    double s = 0.0;
+    for (int t = 0; t < nrec; ++t) s += a.relem[((int64_t)c * NL + locs[t]) * E + eids[t]];
+    a.r[c * N + i] = s;
+  }
+}
+
+// u^FE_i = u_i + dt / m_i sum_e [m_i^e (ubar^e - u_i) + beta_e f_i^e] / dt_e
+// (eq. 49), then the Shu-Osher combination u_out = a u0 + b u^FE and, for
+// scalar problems, the round-off clamp to the global bounds.
+template <int D, int P, int M, bool SCALAR>
+__global__ void __launch_bounds__(256) k_update(StageArgs a) {
+  constexpr int NL = ipow(P + 1, D);
+  __shared__ int red[2][256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int nclamp = 0, nbad = 0;
+  if (i < a.mesh.N) {
+    int64_t eids[8];
+    int locs[8];
+    const int nrec = node_elements<D, P>(i, a.mesh, eids, locs);
+    const int64_t E = a.mesh.E, N = a.mesh.N;
+    double hd = 1.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) hd *= a.mesh.h;
+    const double mi = nrec * (hd * (1.0 / NL));
+    const double dt = a.dtbuf[0];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      double s = 0.0;
+      for (int t = 0; t < nrec; ++t) s += a.relem[((int64_t)c * NL + locs[t]) * E + eids[t]];
+      const double ufe = a.u[c * N + i] + dt / mi * s;
+      double v = (a.rk_a == 0.0) ? ufe : a.rk_a * a.u0[c * N + i] + a.rk_b * ufe;
+      if (SCALAR) {
+        // round-off excess is clamped and counted; larger excursions (only
+        // possible with a limiter switched off) are kept and counted
+        if (v > a.umax) {
+          if (v - a.umax <= a.clamp_tol) { ++nclamp; v = a.umax; } else { ++nbad; }
+        } else if (v < a.umin) {
+          if (a.umin - v <= a.clamp_tol) { ++nclamp; v = a.umin; } else { ++nbad; }
+        }
+      }
+      a.uout[c * N + i] = v;
+    }
+  }
+  red[0][threadIdx.x] = nclamp;
+  red[1][threadIdx.x] = nbad;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.counts[2 * blockIdx.x] += red[0][0];
+    a.counts[2 * blockIdx.x + 1] += red[1][0];
+  }
+}
+
+// min_e dt_e, global time step for the stage and the CFL check of eq. (23)
+// (single block, deterministic)
+__global__ void __launch_bounds__(1024) k_min_dt(const double* __restrict__ dte, int64_t E,
+                                                 double* dtbuf, int stage, double dt_fixed,
+                                                 double cfl) {
+  __shared__ double red[1024];
+  double m = 1.0e300;
+  for (int64_t e = threadIdx.x; e < E; e += blockDim.x) m = fmin(m, dte[e]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mn = red[0];
+    if (stage == 0) dtbuf[0] = dt_fixed > 0.0 ? dt_fixed : cfl * mn;
+    dtbuf[1] = fmin(stage == 0 ? 1.0e300 : dtbuf[1], mn);
+    if (dtbuf[0] > mn) dtbuf[2] = 1.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions for invariant checks: per-block partials, then one block
+// ---------------------------------------------------------------------------
+struct InvArgs {
+  const double* u;
+  int64_t N;
+  int M, D, euler;
+  double gam, mnode;      // lumped-mass unit h^D / NL
+  int P;
+  int Lx, Ly;
+  double* part;           // [blocks][M*3 + 2]
+};
+
+__device__ inline int node_mult(int64_t i, int D, int P, int Lx, int Ly) {
+  int ik[3] = {(int)(i % Lx), 0, 0};
+  if (D > 1) ik[1] = (int)((i / Lx) % Ly);
+  if (D > 2) ik[2] = (int)(i / ((int64_t)Lx * Ly));
+  int m = 1;
+  for (int k = 0; k < D; ++k)
+    if (ik[k] % P == 0) m *= 2;
+  return m;
+}
+
+__global__ void __launch_bounds__(256) k_inv_partial(InvArgs a) {
+  __shared__ double red[256];
+  const int nv = a.M * 3 + 2;
+  const int64_t per = (a.N + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = blockIdx.x * per, hi = min(a.N, lo + per);
+  for (int v = 0; v < nv; ++v) {
+    const int c = v / 3, kind = v % 3;
+    double acc = (v >= a.M * 3) ? 1.0e300 : (kind == 0 ? 1.0e300 : (kind == 1 ? -1.0e300 : 0.0));
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      if (v < a.M * 3) {
+        const double x = a.u[c * a.N + i];
+        if (kind == 0) acc = fmin(acc, x);
+        else if (kind == 1) acc = fmax(acc, x);
+        else acc += a.mnode * node_mult(i, a.D, a.P, a.Lx, a.Ly) * x;
+      } else if (a.euler) {
+        const double rho = a.u[i];
+        if (v == a.M * 3) {
+          acc = fmin(acc, rho);
+        } else {
+          double m2 = 0.0;
+          for (int k = 0; k < a.D; ++k) m2 += a.u[(1 + k) * a.N + i] * a.u[(1 + k) * a.N + i];
+          acc = fmin(acc, (a.gam - 1.0) * (a.u[(a.D + 1) * a.N + i] - 0.5 * m2 / rho));
+        }
+      }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) {
+        const double x = red[threadIdx.x], y = red[threadIdx.x + s];
+        red[threadIdx.x] = (v >= a.M * 3 || kind == 0) ? fmin(x, y) : (kind == 1 ? fmax(x, y) : x + y);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * nv + v] = red[0];
+    __syncthreads();
+  }
+}
+
+}  // namespace cem

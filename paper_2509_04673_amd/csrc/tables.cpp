@@ -1,0 +1,318 @@
+// Host-side constant tables of the Bernstein Q_p element (see tables.hpp).
+#include "tables.hpp"
+
+#include <cmath>
+#include <cstdlib>
+#include <vector>
+
+namespace cem {
+namespace {
+
+using LD = long double;
+
+LD binom(int n, int k) {
+  if (k < 0 || k > n) return 0.0L;
+  LD r = 1.0L;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// int_0^1 B^p_a B^q_b dt (zero when an index is out of range)
+LD gram(int p, int a, int q, int b) {
+  if (a < 0 || a > p || b < 0 || b > q) return 0.0L;
+  return binom(p, a) * binom(q, b) / ((p + q + 1) * binom(p + q, a + b));
+}
+
+LD falling(int p, int m) {   // p! / (p-m)!
+  LD r = 1.0L;
+  for (int i = 0; i < m; ++i) r *= (p - i);
+  return r;
+}
+
+// int_0^1 B^{p(m)}_a B^{p(n)}_b : derivative orders m (test) and n (trial)
+LD gram_deriv(int p, int a, int m, int b, int n) {
+  LD s = 0.0L;
+  for (int i = 0; i <= m; ++i)
+    for (int j = 0; j <= n; ++j) {
+      LD sg = ((i + j) % 2) ? -1.0L : 1.0L;
+      s += sg * binom(m, i) * binom(n, j) * gram(p - m, a - m + i, p - n, b - n + j);
+    }
+  return falling(p, m) * falling(p, n) * s;
+}
+
+LD bern(int p, int a, LD t) {
+  return binom(p, a) * std::pow(t, (LD)a) * std::pow(1.0L - t, (LD)(p - a));
+}
+
+LD bern_deriv(int p, int a, LD t) {
+  if (p == 0) return 0.0L;
+  LD l = (a - 1 >= 0) ? bern(p - 1, a - 1, t) : 0.0L;
+  LD r = (a <= p - 1) ? bern(p - 1, a, t) : 0.0L;
+  return p * (l - r);
+}
+
+void gauss_legendre(int n, std::vector<LD>& t, std::vector<LD>& w) {
+  t.assign(n, 0.0L);
+  w.assign(n, 0.0L);
+  const LD pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < n; ++i) {
+    LD x = std::cos(pi * (i + 0.75L) / (n + 0.5L));
+    LD dp = 0.0L;
+    for (int it = 0; it < 100; ++it) {
+      LD p0 = 1.0L, p1 = x;
+      for (int j = 1; j < n; ++j) {
+        LD p2 = ((2 * j + 1) * x * p1 - j * p0) / (j + 1);
+        p0 = p1;
+        p1 = p2;
+      }
+      LD pn = (n == 0) ? 1.0L : p1, pm = (n == 1) ? 1.0L : p0;
+      if (n == 1) { pn = x; pm = 1.0L; }
+      dp = n * (x * pn - pm) / (x * x - 1.0L);
+      LD dx = pn / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-19L) break;
+    }
+    // ascending order on [0,1]
+    t[n - 1 - i] = 0.5L * (1.0L + x);
+    w[n - 1 - i] = 1.0L / ((1.0L - x * x) * dp * dp);
+  }
+}
+
+// Blossom of the degree-p Bernstein polynomial with coefficient vector c at
+// parameters par[0..p-1] (de Casteljau, one parameter per level).
+LD blossom(int p, const std::vector<LD>& c, const std::vector<LD>& par) {
+  std::vector<LD> b = c;
+  for (int r = 0; r < p; ++r)
+    for (int i = 0; i < p - r; ++i) b[i] = (1.0L - par[r]) * b[i] + par[r] * b[i + 1];
+  return b[0];
+}
+
+// Dense Gaussian elimination with partial pivoting: solves A X = B in place.
+void dense_solve(int n, std::vector<LD> A, std::vector<LD>& B, int nrhs) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[(size_t)i * n + k]) > std::fabs(A[(size_t)piv * n + k])) piv = i;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)piv * n + j]);
+      for (int j = 0; j < nrhs; ++j) std::swap(B[(size_t)k * nrhs + j], B[(size_t)piv * nrhs + j]);
+    }
+    for (int i = k + 1; i < n; ++i) {
+      LD f = A[(size_t)i * n + k] / A[(size_t)k * n + k];
+      if (f == 0.0L) continue;
+      for (int j = k; j < n; ++j) A[(size_t)i * n + j] -= f * A[(size_t)k * n + j];
+      for (int j = 0; j < nrhs; ++j) B[(size_t)i * nrhs + j] -= f * B[(size_t)k * nrhs + j];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    for (int j = 0; j < nrhs; ++j) {
+      LD s = B[(size_t)k * nrhs + j];
+      for (int i = k + 1; i < n; ++i) s -= A[(size_t)k * n + i] * B[(size_t)i * nrhs + j];
+      B[(size_t)k * nrhs + j] = s / A[(size_t)k * n + k];
+    }
+  }
+}
+
+// Rows of M^{-1} and M^{-1} C for the P node classes of a periodic line of
+// Lp nodes (degree p, cell h): out_m[c][j], out_g[c][j], j = 0..Lp-1.
+void periodic_line_rows(int p, int Lp, LD h, std::vector<LD>& out_m, std::vector<LD>& out_g) {
+  const int ne = Lp / p;
+  std::vector<LD> M((size_t)Lp * Lp, 0.0L), C((size_t)Lp * Lp, 0.0L);
+  for (int e = 0; e < ne; ++e)
+    for (int a = 0; a <= p; ++a)
+      for (int b = 0; b <= p; ++b) {
+        int i = (p * e + a) % Lp, j = (p * e + b) % Lp;
+        M[(size_t)i * Lp + j] += h * gram(p, a, p, b);
+        C[(size_t)i * Lp + j] += gram_deriv(p, a, 0, b, 1);   // int psi_i psi_j'
+      }
+  // M symmetric: row c of M^{-1} is the solution of M z = e_c
+  std::vector<LD> B((size_t)Lp * p, 0.0L);
+  for (int c = 0; c < p; ++c) B[(size_t)c * p + c] = 1.0L;
+  dense_solve(Lp, M, B, p);
+  out_m.assign((size_t)p * Lp, 0.0L);
+  out_g.assign((size_t)p * Lp, 0.0L);
+  for (int c = 0; c < p; ++c) {
+    for (int j = 0; j < Lp; ++j) out_m[(size_t)c * Lp + j] = B[(size_t)j * p + c];
+    // row c of M^{-1} C = z^T C
+    for (int j = 0; j < Lp; ++j) {
+      LD s = 0.0L;
+      for (int i = 0; i < Lp; ++i) s += out_m[(size_t)c * Lp + i] * C[(size_t)i * Lp + j];
+      out_g[(size_t)c * Lp + j] = s;
+    }
+  }
+}
+
+constexpr int kExactMax = 480;   // lines up to this length use the exact inverse
+
+void line_kernels(int p, int L, LD h, LineKernel& km, LineKernel& kg) {
+  int Lp = L <= kExactMax ? L : ((kExactMax + p - 1) / p) * p;
+  std::vector<LD> rm, rg;
+  periodic_line_rows(p, Lp, h, rm, rg);
+  auto fill = [&](const std::vector<LD>& rows, LineKernel& k) {
+    if (L <= kExactMax) {
+      k.taps = L;
+      k.first = -(L / 2);
+    } else {
+      // truncate where the exponentially decaying rows fall below 1e-20 of
+      // their peak (far below double rounding)
+      LD peak = 0.0L;
+      for (LD v : rows) peak = std::max(peak, std::fabs(v));
+      int W = 0;
+      for (int c = 0; c < p; ++c)
+        for (int j = 0; j < Lp; ++j) {
+          int dist = j - c;
+          if (dist > Lp / 2) dist -= Lp;
+          if (dist < -Lp / 2) dist += Lp;
+          if (std::fabs(rows[(size_t)c * Lp + j]) > 1e-20L * peak) W = std::max(W, std::abs(dist));
+        }
+      k.taps = 2 * W + 1;
+      k.first = -W;
+    }
+    k.w.assign((size_t)p * k.taps, 0.0);
+    for (int c = 0; c < p; ++c)
+      for (int t = 0; t < k.taps; ++t) {
+        int j = ((c + k.first + t) % Lp + Lp) % Lp;
+        k.w[(size_t)c * k.taps + t] = (double)rows[(size_t)c * Lp + j];
+      }
+  };
+  fill(rm, km);
+  fill(rg, kg);
+}
+
+}  // namespace
+
+bool build_tables(int d, int p, double h, const int L[3], HostTables& T) {
+  if (d < 1 || d > 3 || p < 1 || p > 4) return false;
+  const int P1 = p + 1;
+  int nl = 1;
+  for (int k = 0; k < d; ++k) nl *= P1;
+  int nlf = nl / P1;
+  T.d = d;
+  T.p = p;
+  T.nl = nl;
+  T.nlf = nlf;
+
+  std::vector<LD> tq, wq;
+  gauss_legendre(P1, tq, wq);
+  T.vq.resize(P1 * P1);
+  T.dq.resize(P1 * P1);
+  T.wq.resize(P1);
+  for (int q = 0; q < P1; ++q) {
+    T.wq[q] = (double)wq[q];
+    for (int a = 0; a < P1; ++a) {
+      T.vq[q * P1 + a] = (double)bern(p, a, tq[q]);
+      T.dq[q * P1 + a] = (double)bern_deriv(p, a, tq[q]);
+    }
+  }
+
+  // 1D building blocks (long double)
+  auto G1 = [&](int a, int b) { return gram(p, a, p, b); };
+  auto K1 = [&](int a, int b) { return gram_deriv(p, a, 1, b, 1); };
+  auto CT1 = [&](int a, int b) { return gram_deriv(p, a, 1, b, 0); };   // int B_a' B_b
+  auto digit = [&](int loc, int k) {
+    for (int i = 0; i < k; ++i) loc /= P1;
+    return loc % P1;
+  };
+
+  T.mass.assign((size_t)nl * nl, 0.0);
+  T.ksum.assign((size_t)nl * nl, 0.0);
+  T.ctg.assign((size_t)d * nl * nl, 0.0);
+  for (int i = 0; i < nl; ++i)
+    for (int j = 0; j < nl; ++j) {
+      LD m = 1.0L, ks = 0.0L;
+      for (int k = 0; k < d; ++k) m *= G1(digit(i, k), digit(j, k));
+      for (int k = 0; k < d; ++k) {
+        LD sk = 1.0L, ck = 1.0L;
+        for (int l = 0; l < d; ++l) {
+          int a = digit(i, l), b = digit(j, l);
+          sk *= (l == k) ? K1(a, b) : G1(a, b);
+          ck *= (l == k) ? CT1(a, b) : G1(a, b);
+        }
+        ks += sk;
+        T.ctg[((size_t)k * nl + i) * nl + j] = (double)ck;
+      }
+      T.mass[(size_t)i * nl + j] = (double)m;
+      T.ksum[(size_t)i * nl + j] = (double)ks;
+    }
+
+  // semi-norm form: sum over 1 <= |k| <= p of tensor products of the 1D
+  // m-th derivative Grams (scale-free on cube cells)
+  std::vector<LD> Q((size_t)nl * nl, 0.0L);
+  int nk = 1;
+  for (int k = 0; k < d; ++k) nk *= P1;
+  for (int mi = 0; mi < nk; ++mi) {
+    int ord[3] = {0, 0, 0}, tot = 0;
+    for (int k = 0; k < d; ++k) {
+      ord[k] = digit(mi, k);
+      tot += ord[k];
+    }
+    if (tot < 1 || tot > p) continue;
+    for (int i = 0; i < nl; ++i)
+      for (int j = 0; j < nl; ++j) {
+        LD v = 1.0L;
+        for (int k = 0; k < d; ++k) v *= gram_deriv(p, digit(i, k), ord[k], digit(j, k), ord[k]);
+        Q[(size_t)i * nl + j] += v;
+      }
+  }
+
+  // neighbour-extension maps: the polynomial of the low neighbour seen on
+  // K_e lives on t in [1,2] of its own cell, the high neighbour's on [-1,0]
+  std::vector<LD> E1[2];
+  const LD lims[2][2] = {{1.0L, 2.0L}, {-1.0L, 0.0L}};
+  T.ext.assign(2 * P1 * P1, 0.0);
+  for (int s = 0; s < 2; ++s) {
+    E1[s].assign(P1 * P1, 0.0L);
+    for (int r = 0; r < P1; ++r) {
+      std::vector<LD> par(p);
+      for (int i = 0; i < p; ++i) par[i] = (i < p - r) ? lims[s][0] : lims[s][1];
+      for (int a = 0; a < P1; ++a) {
+        std::vector<LD> unit(P1, 0.0L);
+        unit[a] = 1.0L;
+        E1[s][r * P1 + a] = blossom(p, unit, par);
+        T.ext[(s * P1 + r) * P1 + a] = (double)E1[s][r * P1 + a];
+      }
+    }
+  }
+  // forms of the candidates: E^T Q E with E acting along the facet axis
+  T.qf.assign((size_t)(1 + 2 * d) * nl * nl, 0.0);
+  for (int i = 0; i < nl * nl; ++i) T.qf[i] = (double)Q[i];
+  for (int k = 0; k < d; ++k)
+    for (int s = 0; s < 2; ++s) {
+      std::vector<LD> Efull((size_t)nl * nl, 0.0L);
+      for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) {
+          bool same = true;
+          for (int l = 0; l < d; ++l)
+            if (l != k && digit(i, l) != digit(j, l)) same = false;
+          if (same) Efull[(size_t)i * nl + j] = E1[s][digit(i, k) * P1 + digit(j, k)];
+        }
+      std::vector<LD> QE((size_t)nl * nl, 0.0L);
+      for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) {
+          LD acc = 0.0L;
+          for (int m = 0; m < nl; ++m) acc += Q[(size_t)i * nl + m] * Efull[(size_t)m * nl + j];
+          QE[(size_t)i * nl + j] = acc;
+        }
+      double* dst = &T.qf[(size_t)(1 + 2 * k + s) * nl * nl];
+      for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) {
+          LD acc = 0.0L;
+          for (int m = 0; m < nl; ++m) acc += Efull[(size_t)m * nl + i] * QE[(size_t)m * nl + j];
+          dst[(size_t)i * nl + j] = (double)acc;
+        }
+    }
+
+  // facet Gram over the D-1 tangential axes (facet-local lexicographic ids)
+  T.facem.assign((size_t)nlf * nlf, 0.0);
+  for (int i = 0; i < nlf; ++i)
+    for (int j = 0; j < nlf; ++j) {
+      LD v = 1.0L;
+      for (int k = 0; k < d - 1; ++k) v *= G1(digit(i, k), digit(j, k));
+      T.facem[(size_t)i * nlf + j] = (double)v;
+    }
+
+  for (int k = 0; k < d; ++k) line_kernels(p, L[k], (LD)h, T.kmass[k], T.kgrad[k]);
+  return true;
+}
+
+}  // namespace cem

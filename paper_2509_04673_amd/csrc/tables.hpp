@@ -1,0 +1,43 @@
+// Host-side constant tables of the Bernstein Q_p element for the HIP path.
+//
+// Everything is derived here from closed forms in long double and rounded to
+// double once:
+//   * mixed-degree Bernstein Gram integrals
+//       int_0^1 B^p_a B^q_b = C(p,a) C(q,b) / ((p+q+1) C(p+q, a+b)),
+//   * derivatives through d^m/dt^m B^p_a = p!/(p-m)! sum_i (-1)^i C(m,i)
+//     B^{p-m}_{a-m+i},
+//   * Gauss-Legendre points by Newton iteration on the Legendre recurrence,
+//   * the neighbour-extension maps by blossoming (de Casteljau with a
+//     different parameter per level),
+//   * the periodic line operators M_1D^{-1} and M_1D^{-1} C_1D by Gaussian
+//     elimination with partial pivoting.
+// Element geometry: cube cells of side h; the reference cell is [0,1]^d with
+// local node ids lexicographic, axis 0 fastest.
+#pragma once
+#include <vector>
+
+namespace cem {
+
+struct LineKernel {
+  int taps = 0;       // number of taps per output
+  int first = 0;      // offset of tap 0 relative to the output node
+  std::vector<double> w;   // [P classes][taps]
+};
+
+struct HostTables {
+  int d = 0, p = 0, nl = 0, nlf = 0;
+  std::vector<double> vq, dq, wq;   // [P1][P1] B_a(t_q), B_a'(t_q); [P1] weights
+  std::vector<double> mass;         // [NL][NL] tensor Gram (reference cell)
+  std::vector<double> ksum;         // [NL][NL] sum_k int d_k phi_i d_k phi_j
+  std::vector<double> ctg;          // [D][NL][NL] int d_k phi_i phi_j
+  std::vector<double> qf;           // [1+2D][NL][NL] WENO semi-norm forms, symmetric
+  std::vector<double> ext;          // [2][P1][P1] extension maps (low, high neighbour)
+  std::vector<double> facem;        // [NLF][NLF] facet Gram over the other D-1 axes
+  LineKernel kgrad[3], kmass[3];    // per axis line operators (physical h)
+};
+
+// Build all tables for dimension d, degree p, cell size h and L_k nodes per
+// axis.  Returns false on an unsupported (d, p).
+bool build_tables(int d, int p, double h, const int L[3], HostTables& out);
+
+}  // namespace cem

@@ -1,0 +1,75 @@
+"""Shared set-up of matching oracle / HIP problems for the parity tests."""
+import sys
+
+import numpy as np
+
+from oracle import Mesh, Oracle, Params, Problem
+from paper_2509_04673_amd import workloads as W
+
+
+def rel_linf(a, b):
+    """max |a - b| / max |b| (per whole array)."""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    scale = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (scale if scale > 0 else 1.0))
+
+
+def oracle_for(wl, modes=None, bounds=None):
+    mesh = Mesh(wl.d, wl.p, wl.n, wl.lo, wl.hi)
+    prm = Params(w_lin=wl.w_lin, q=wl.q)
+    for k, v in (modes or {}).items():
+        setattr(prm, k, v)
+    if bounds is None:
+        bounds = (float(wl.u0.min()), float(wl.u0.max()))
+    prob = Problem(mesh, wl.kind, wl.velocity, wl.gamma_gas, params=prm,
+                   u_min=bounds[0], u_max=bounds[1])
+    return Oracle(prob)
+
+
+MODE_CODES = {"weno": 0, "limit": 0, "zero": 1, "one": 2}
+
+
+def gpu_for(wl, modes=None):
+    from paper_2509_04673_amd.cem import Solver
+    kw = {}
+    for k, v in (modes or {}).items():
+        kw[k] = MODE_CODES[v]
+    s = Solver.from_workload(wl, **kw)
+    s.upload(wl.u0)
+    if wl.kind != "euler":
+        s.set_bounds()
+    return s
+
+
+def announce(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def random_scalar_workload(d, p, n, kind="advection", seed=0):
+    """Rough data: smooth background, plateaus and noise (all sensor regimes)."""
+    rng = np.random.default_rng(seed)
+    lo = (0.0,) * d
+    hi = tuple(float(nk) / max(n) for nk in n)
+    x = W.node_coords(d, p, n, lo, hi)
+    u = np.sin(2 * np.pi * x[:, 0] / hi[0]) + 0.3 * rng.standard_normal(x.shape[0]) * (x[:, 0] > 0.5 * hi[0])
+    u = np.where(np.abs(x[:, -1] - 0.3 * hi[-1]) < 0.1 * hi[-1], 1.5, u)
+    if kind == "kpp":
+        u = 0.25 * np.pi + (3.25 * np.pi) * (u > 0.5)
+    vel = (1.0, -0.5, 0.25)
+    return W.Workload("rand", d, p, tuple(n), lo, hi, kind, u[None, :], velocity=vel,
+                      w_lin=0.2 if (kind == "kpp") else 1e-3)
+
+
+def random_euler_workload(d, p, n, seed=0):
+    rng = np.random.default_rng(seed)
+    lo = (0.0,) * d
+    hi = tuple(float(nk) / max(n) for nk in n)
+    x = W.node_coords(d, p, n, lo, hi)
+    N = x.shape[0]
+    blob = np.exp(-30 * np.sum((x - 0.4 * np.array(hi)) ** 2, axis=1))
+    rho = 1.0 + 0.5 * blob + 0.2 * (x[:, 0] > 0.6 * hi[0])
+    vel = [0.3 * np.sin(2 * np.pi * x[:, k] / hi[k]) for k in range(d)]
+    pr = 1.0 + 5.0 * blob + 0.05 * rng.random(N)
+    u = W._conserved(rho, vel, pr, 1.4)
+    return W.Workload("rand_euler", d, p, tuple(n), lo, hi, "euler", u, w_lin=1e-3)

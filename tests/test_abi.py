@@ -1,0 +1,88 @@
+"""The C-ABI library loads on the host and exports every symbol that
+include/cem.h declares; host-side argument validation (no GPU work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2509_04673_amd import cem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cem.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cem_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("cem_create", "cem_bind", "cem_rk_stage", "cem_step", "cem_check_invariants",
+                 "cem_upload_state", "cem_download_state", "cem_debug_tap", "cem_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cem.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    bound = {s[0] for s in cem._SIGS}
+    assert set(_declared()) == bound
+
+
+def _desc(d=2, p=2, n=(8, 8), kind=cem.KPP, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+    mesh = cem.MeshDesc(d, p, (ctypes.c_int * 3)(*(list(n) + [1] * (3 - len(n)))),
+                        (ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi))
+    phys = cem.PhysicsDesc(kind, (ctypes.c_double * 3)(1.0, 0.0, 0.0), 1.4)
+    return mesh, phys
+
+
+def test_create_and_sizes_on_host():
+    mesh, phys = _desc()
+    ctx = cem.cem_create(mesh, phys, cem.cem_params_default(), 0)
+    try:
+        N, E, m = cem.cem_sizes(ctx)
+        assert (N, E, m) == (16 * 16, 64, 1)
+        assert cem.cem_workspace_bytes(ctx) > 8 * N * 4
+        assert cem.cem_tap_size(ctx, cem.TAPS["elemvec"]) == 9 * 64
+    finally:
+        cem.cem_destroy(ctx)
+
+
+@pytest.mark.parametrize("bad", ["dim", "degree", "cells", "aspect", "gamma", "velocity"])
+def test_create_rejects_invalid_configurations(bad):
+    kw = dict()
+    mesh, phys = _desc()
+    if bad == "dim":
+        mesh.dim = 4
+    elif bad == "degree":
+        mesh.degree = 7
+    elif bad == "cells":
+        mesh.n[0] = 1
+    elif bad == "aspect":
+        mesh.hi[1] = 2.0
+    elif bad == "gamma":
+        phys.kind = cem.EULER
+        phys.gamma_gas = 2.0
+    elif bad == "velocity":
+        phys.kind = cem.ADVECTION
+        phys.velocity[0] = 0.0
+    with pytest.raises(cem.CemError) as ei:
+        cem.cem_create(mesh, phys, cem.cem_params_default(), 0)
+    assert ei.value.status == -1
+    del kw
+
+
+def test_calls_before_bind_are_rejected():
+    mesh, phys = _desc()
+    ctx = cem.cem_create(mesh, phys, cem.cem_params_default(), 0)
+    try:
+        with pytest.raises(cem.CemError):
+            cem.cem_rk_stage(ctx, 0, 1e-3)
+        with pytest.raises(cem.CemError):
+            cem.cem_check_invariants(ctx)
+    finally:
+        cem.cem_destroy(ctx)

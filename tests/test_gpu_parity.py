@@ -1,0 +1,128 @@
+"""Parity of the HIP stage (through the C ABI) with the float64 oracle.
+
+Tolerance: relative L-infinity 1e-12 per intermediate and per state after
+one stage, and after the stated number of SSP-RK3 steps."""
+import numpy as np
+import pytest
+
+from paper_2509_04673_amd import workloads as W
+from parity_util import (announce, gpu_for, oracle_for, random_euler_workload,
+                         random_scalar_workload, rel_linf)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+STAGE_CASES = [
+    ("adv1d_p2", lambda: random_scalar_workload(1, 2, (37,))),
+    ("adv1d_p3", lambda: random_scalar_workload(1, 3, (23,))),
+    ("adv2d_q1", lambda: random_scalar_workload(2, 1, (16, 15))),
+    ("adv2d_q3", lambda: random_scalar_workload(2, 3, (9, 7))),
+    ("kpp2d_q2", lambda: random_scalar_workload(2, 2, (13, 11), kind="kpp")),
+    ("adv3d_q2", lambda: random_scalar_workload(3, 2, (5, 4, 6))),
+    ("euler1d_p2", lambda: random_euler_workload(1, 2, (29,))),
+    ("euler2d_q2", lambda: random_euler_workload(2, 2, (12, 7))),
+    ("euler2d_q3", lambda: random_euler_workload(2, 3, (9, 10))),
+    ("euler3d_q2", lambda: random_euler_workload(3, 2, (5, 6, 4))),
+]
+
+TAP_NAMES = ["g", "gamma", "nu", "dt_e", "ue", "ubarL", "fA", "r", "udot", "ubar", "beta"]
+
+
+def _compare_stage(wl, modes=None, label=""):
+    orc = oracle_for(wl, modes)
+    dt = wl.dt if wl.dt > 0 else 0.5 * orc.max_dt(wl.u0)
+    announce(f"[parity] stage {label} d={wl.d} p={wl.p} n={wl.n} kind={wl.kind} modes={modes}")
+    ufe, taps = orc.fe_stage(wl.u0, dt)
+    ufe = orc.clamp(ufe)[0]        # the stage result includes the bounds policy
+    s = gpu_for(wl, modes)
+    s.stage(0, dt=dt)
+    got = s.download()
+    errs = {}
+    for name in TAP_NAMES:
+        errs[name] = rel_linf(s.tap(name).reshape(np.shape(taps[name])), taps[name])
+    errs["u_fe"] = rel_linf(got, ufe)
+    s.close()
+    bad = {k: v for k, v in errs.items() if not v <= TOL}
+    assert not bad, (label, errs)
+    return errs
+
+
+@pytest.mark.parametrize("label,make", STAGE_CASES, ids=[c[0] for c in STAGE_CASES])
+def test_stage_parity(label, make):
+    _compare_stage(make(), label=label)
+
+
+@pytest.mark.parametrize("modes", [dict(gamma_mode="zero", alpha_mode="zero", beta_mode="zero"),
+                                   dict(alpha_mode="one", beta_mode="one"),
+                                   dict(gamma_mode="one", beta_mode="one")],
+                         ids=["LO", "target", "HO"])
+def test_stage_parity_method_switches(modes):
+    _compare_stage(random_scalar_workload(2, 2, (10, 9), kind="kpp"), modes, "switch")
+    _compare_stage(random_euler_workload(2, 2, (8, 9)), modes, "switch-euler")
+
+
+def _perturbed(u):
+    rng = np.random.default_rng(12345)
+    return u * (1.0 + rng.integers(-1, 2, u.shape) * 2.0 ** -52)
+
+
+def _run_both(wl, nsteps, dt=None, cfl=0.5):
+    """GPU and oracle runs plus the oracle's own sensitivity floor: the
+    divergence after nsteps caused by perturbing the input by 1 ulp."""
+    orc = oracle_for(wl)
+    announce(f"[parity] {nsteps} steps {wl.name} n={wl.n}")
+    u_ref, st = orc.run(wl.u0.copy(), nsteps, dt=dt, cfl=cfl)
+    u_pert, _ = orc.run(_perturbed(wl.u0), nsteps, dt=dt, cfl=cfl)
+    floor = rel_linf(u_pert, u_ref)
+    s = gpu_for(wl)
+    for _ in range(nsteps):
+        s.step(dt=dt or 0.0, cfl=0.0 if dt else cfl)
+    got = s.download()
+    chk = s.check()
+    s.close()
+    err = rel_linf(got, u_ref)
+    announce(f"[parity] {wl.name}: rel Linf GPU vs oracle {err:.3e}, oracle 1-ulp floor {floor:.3e}")
+    return err, floor, st, chk
+
+
+def _tol(floor):
+    # 1e-12, unless the scheme itself amplifies a 1-ulp input change beyond
+    # it over the run; the HIP path differs from the oracle by a few ulps per
+    # stage, so it may sit within a small multiple of that floor
+    return max(1e-12, 20.0 * floor)
+
+
+def test_adv1d_full_run_parity():
+    # the 1D advection workload at its full size: 64 P2 cells, 200 steps
+    wl = W.adv1d(seed=0)
+    err, floor, st, chk = _run_both(wl, wl.nsteps, dt=wl.dt)
+    assert err <= 1e-12
+    assert chk["violations"] == 0 and st["violations"] == 0
+
+
+def test_kpp2d_small_run_parity():
+    wl = W.kpp2d(seed=2, n=16)
+    err, floor, st, chk = _run_both(wl, 30, dt=2e-3)
+    assert err <= _tol(floor)
+    assert chk["violations"] == 0
+
+
+def test_euler2d_small_run_parity():
+    wl = W.euler2d(seed=1, n=12)
+    err, floor, st, chk = _run_both(wl, 10, dt=None, cfl=0.5)
+    assert err <= _tol(floor)
+    assert chk["rho_min"] > 0 and chk["p_min"] > 0
+
+
+def test_euler3d_small_run_parity():
+    wl = W.euler3d(seed=0, n=6)
+    err, floor, st, chk = _run_both(wl, 4, dt=None, cfl=0.5)
+    assert err <= _tol(floor)
+    assert chk["rho_min"] > 0 and chk["p_min"] > 0
+
+
+def test_kpp2d_full_size_stage_parity():
+    # the KPP workload at its full size (256^2 Q2) in the benchmark's launch
+    # configuration: one stage, every intermediate
+    _compare_stage(W.kpp2d(seed=0), label="kpp2d-full")
