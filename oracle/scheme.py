@@ -179,10 +179,13 @@ class Oracle:
         axis (the neighbour's own coordinates of a point of K_e)."""
         p, d = self.mesh.p, self.mesh.d
         X = T
+        # every difference first (exact on nearly equal coefficients), then
+        # the evaluation: differencing evaluated values would cancel digits
+        for j in range(d):
+            if k[j] > 0:
+                X = np.diff(X, n=k[j], axis=X.ndim - 1 - j) * float(bz.derivative_factor(p, k[j]))
         for j in range(d):
             ax = X.ndim - 1 - j
-            if k[j] > 0:
-                X = np.diff(X, n=k[j], axis=ax) * float(bz.derivative_factor(p, k[j]))
             t = self.el.tq + (shift if j == shift_axis else 0.0)
             V = bz.basis_values(p - k[j], t)          # (q, a)
             X = np.moveaxis(np.tensordot(X, V, axes=([ax], [1])), -1, ax)
