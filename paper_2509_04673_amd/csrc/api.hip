@@ -30,6 +30,7 @@ cem_status fail(cem_status s, const std::string& msg) {
   } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 }  // namespace
 
 struct cem_ctx {
@@ -43,7 +44,8 @@ struct cem_ctx {
   HostTables tabs;
   std::vector<double> tabblob;     // all tables, packed
   size_t off_vqf = 0, off_dqw = 0, off_mass = 0, off_ksum = 0, off_ctg = 0, off_qf = 0,
-         off_ext = 0, off_facem = 0, off_kg[3] = {0, 0, 0}, off_km[3] = {0, 0, 0};
+         off_ext = 0, off_facem = 0, off_kg[3] = {0, 0, 0}, off_km[3] = {0, 0, 0},
+         off_kgf[3] = {0, 0, 0}, off_kmf[3] = {0, 0, 0};
   // bound memory
   double* u = nullptr;
   double* u0 = nullptr;
@@ -51,7 +53,7 @@ struct cem_ctx {
   size_t ws_need = 0;
   // workspace carve-up (byte offsets)
   size_t o_g, o_r, o_udot, o_tmp, o_tmp2, o_relem, o_ue, o_ubarL, o_ubar, o_fahi, o_dte, o_gam,
-      o_nu, o_beta, o_dtbuf, o_counts, o_inv, o_tab;
+      o_nu, o_beta, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart;
   int upd_blocks = 0, inv_blocks = 0;
   bool bound = false, bounds_set = false;
   // optional per-kernel event timing
@@ -109,6 +111,30 @@ void pack_tables(cem_ctx* c) {
   for (int k = 0; k < D; ++k) {
     c->off_kg[k] = put(T.kgrad[k].w);
     c->off_km[k] = put(T.kmass[k].w);
+    c->off_kgf[k] = put(T.kgrad[k].wf);
+    c->off_kmf[k] = put(T.kmass[k].wf);
+  }
+}
+
+// fixed widths of the register-blocked line kernel per degree (device
+// templates LineTaps<P>)
+const int kWfast[5] = {0, LineTaps<1>::W, LineTaps<2>::W, LineTaps<3>::W, 0};
+const int kRfast[5] = {0, 1, 2, 3, 0};   // shortest run: RE = 1
+const int kSfast[5] = {0, LineTaps<1>::S, LineTaps<2>::S, LineTaps<3>::S, 0};
+
+template <int P>
+void launch_line_fast(const LineFastArgs& la, hipStream_t st) {
+  // longest run that still gives >= 2^17 threads (2 waves per SIMD)
+  int re = kLineMaxRE;
+  while (re > 1 && (la.L < P * re + 2 * LineTaps<P>::W ||
+                    la.ntrans * ((la.L + P * re - 1) / (P * re)) < (int64_t(1) << 17)))
+    re /= 2;
+  const int R = P * re;
+  dim3 grid(nblocks(la.ntrans, 256), (unsigned)((la.L + R - 1) / R));
+  switch (re) {
+    case 4: hipLaunchKernelGGL((k_line_fast<P, 4>), grid, dim3(256), 0, st, la); break;
+    case 2: hipLaunchKernelGGL((k_line_fast<P, 2>), grid, dim3(256), 0, st, la); break;
+    default: hipLaunchKernelGGL((k_line_fast<P, 1>), grid, dim3(256), 0, st, la); break;
   }
 }
 
@@ -169,10 +195,10 @@ StageArgs make_args(const cem_ctx* c) {
   a.beta = c->W<double>(c->o_beta);
   a.dtbuf = c->W<double>(c->o_dtbuf);
   a.counts = c->W<int>(c->o_counts);
+  a.dtpart = c->W<double>(c->o_dtpart);
   return a;
 }
 
-inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 hipEvent_t get_event(cem_ctx* c) {
   if (!c->pool.empty()) {
@@ -209,11 +235,33 @@ struct Timed {
 
 cem_status launch_line(cem_ctx* c, const double* in, double* out, int axis, bool grad) {
   Timed tm(c, grad ? 0 : 4);
+  const LineKernel& K = grad ? c->tabs.kgrad[axis] : c->tabs.kmass[axis];
+  const double* tb = c->W<double>(c->o_tab);
+  if (K.wfast > 0) {
+    LineFastArgs la{};
+    la.in = in;
+    la.out = out;
+    la.w = tb + (grad ? c->off_kgf[axis] : c->off_kmf[axis]);
+    la.L = c->L[axis];
+    la.axis = axis;
+    la.L0 = c->L[0];
+    la.L1 = c->L[1];
+    la.N = c->N;
+    la.NT = c->N / c->L[axis];
+    la.ntrans = (int64_t)c->m * la.NT;
+    switch (c->p) {
+      case 1: launch_line_fast<1>(la, c->stream); break;
+      case 2: launch_line_fast<2>(la, c->stream); break;
+      case 3: launch_line_fast<3>(la, c->stream); break;
+      default: return fail(CEM_EINVAL, "no fast line kernel for this degree");
+    }
+    HIPCHK(hipGetLastError());
+    return CEM_OK;
+  }
   LineArgs la{};
   la.in = in;
   la.out = out;
-  const LineKernel& K = grad ? c->tabs.kgrad[axis] : c->tabs.kmass[axis];
-  la.w = c->W<double>(c->o_tab) + (grad ? c->off_kg[axis] : c->off_km[axis]);
+  la.w = tb + (grad ? c->off_kg[axis] : c->off_km[axis]);
   la.taps = K.taps;
   la.first = K.first;
   la.L = c->L[axis];
@@ -227,8 +275,23 @@ cem_status launch_line(cem_ctx* c, const double* in, double* out, int axis, bool
   return CEM_OK;
 }
 
+template <int D, int P>
+constexpr size_t lds_bytes() {
+  return TabLayout<D, P>::lds ? sizeof(double) * TabLayout<D, P>::total : 0;
+}
+
+template <int D, int P>
+bool layout_matches(const cem_ctx* c) {
+  using TL = TabLayout<D, P>;
+  return c->off_dqw - c->off_vqf == (size_t)TL::dqw && c->off_mass - c->off_vqf == (size_t)TL::mass &&
+         c->off_ksum - c->off_vqf == (size_t)TL::ksum && c->off_ctg - c->off_vqf == (size_t)TL::ctg &&
+         c->off_qf - c->off_vqf == (size_t)TL::qf && c->off_ext - c->off_vqf == (size_t)TL::ext &&
+         c->off_facem - c->off_vqf == (size_t)TL::facem;
+}
+
 template <int D, int P, int PH>
 cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
+  if (!layout_matches<D, P>(c)) return fail(CEM_EINVAL, "internal: table layout mismatch");
   constexpr int M = Phys<D, PH>::M;
   StageArgs a = make_args(c);
   const double rka[3] = {0.0, 0.75, 1.0 / 3.0}, rkb[3] = {1.0, 0.25, 2.0 / 3.0};
@@ -241,12 +304,13 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   }
   {
     Timed tm(c, 1);
-    hipLaunchKernelGGL((k_elem1<D, P, PH>), dim3(nblocks(c->E, 128)), dim3(128), 0, c->stream, a);
+    hipLaunchKernelGGL((k_elem1<D, P, PH>), dim3(nblocks(c->E, 128)), dim3(128), (lds_bytes<D, P>()), c->stream, a);
   }
   HIPCHK(hipGetLastError());
   {
     Timed tm(c, 2);
-    hipLaunchKernelGGL(k_min_dt, dim3(1), dim3(1024), 0, c->stream, a.dte, c->E, a.dtbuf, stage, dt, cfl);
+    hipLaunchKernelGGL(k_min_dt, dim3(1), dim3(1024), 0, c->stream, a.dtpart, (int64_t)nblocks(c->E, 128),
+                       a.dtbuf, stage, dt, cfl);
   }
   HIPCHK(hipGetLastError());
   {
@@ -266,7 +330,7 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   }
   {
     Timed tm(c, 5);
-    hipLaunchKernelGGL((k_elem2<D, P, PH>), dim3(nblocks(c->E, 128)), dim3(128), 0, c->stream, a);
+    hipLaunchKernelGGL((k_elem2<D, P, PH>), dim3(nblocks(c->E, 128)), dim3(128), (lds_bytes<D, P>()), c->stream, a);
   }
   HIPCHK(hipGetLastError());
   {
@@ -357,7 +421,7 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->ph.vnorm = std::sqrt(c->ph.vel[0] * c->ph.vel[0] + c->ph.vel[1] * c->ph.vel[1] + c->ph.vel[2] * c->ph.vel[2]);
   c->ph.gam = phys->gamma_gas;
   c->stream = (hipStream_t)stream;
-  if (!build_tables(d, p, h, c->L, c->tabs)) {
+  if (!build_tables(d, p, h, c->L, kWfast, kRfast, kSfast, c->tabs)) {
     delete c;
     return fail(CEM_EINVAL, "table construction failed");
   }
@@ -385,6 +449,7 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->o_nu = take(E8);
   c->o_beta = take(E8);
   c->o_dtbuf = take(8 * 8);
+  c->o_dtpart = take((size_t)nblocks(c->E, 128) * 8);
   c->upd_blocks = (int)nblocks(c->N, 256);
   c->o_counts = take((size_t)c->upd_blocks * 2 * sizeof(int));
   c->inv_blocks = 256;

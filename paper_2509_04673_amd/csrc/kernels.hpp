@@ -43,6 +43,47 @@ struct DevTabs {
   int gtaps[3], gfirst[3], mtaps[3], mfirst[3];
 };
 
+// Compile-time layout of the element tables (the host packs them in this
+// order, each padded to a multiple of 32 doubles): vqf, dqw, mass, ksum, ctg,
+// qf, ext, facem.  When they fit in 32 KB the element kernels stage them in
+// LDS and read them with immediate offsets.
+template <int D, int P> struct TabLayout {
+  static constexpr int P1 = P + 1, NL = ipow(P1, D), NF = NL / P1;
+  static constexpr int pad(int n) { return (n + 31) / 32 * 32; }
+  static constexpr int vqf = 0;
+  static constexpr int dqw = vqf + pad(NL * NL);
+  static constexpr int mass = dqw + pad(D * NL * NL);
+  static constexpr int ksum = mass + pad(NL * NL);
+  static constexpr int ctg = ksum + pad(NL * NL);
+  static constexpr int qf = ctg + pad(D * NL * NL);
+  static constexpr int ext = qf + pad((1 + 2 * D) * NL * NL);
+  static constexpr int facem = ext + pad(2 * P1 * P1);
+  static constexpr int total = facem + pad(NF * NF);
+  // staging in LDS makes the scheduler hoist every table read into VGPRs in
+  // the fully unrolled element code (measured: more spills than the scalar
+  // path), so the element kernels read the tables through the scalar cache
+  static constexpr bool lds = false;
+};
+
+extern __shared__ double cem_smem[];
+
+template <bool LDS> struct TabRef {
+  const double* g;
+  __device__ __forceinline__ double operator()(int i) const { return LDS ? cem_smem[i] : g[i]; }
+};
+
+// stage the element tables of (D, P) in LDS (no-op when they do not fit);
+// every thread of the block must call it
+template <int D, int P>
+__device__ __forceinline__ TabRef<TabLayout<D, P>::lds> stage_tables(const double* gtab) {
+  using TL = TabLayout<D, P>;
+  if constexpr (TL::lds) {
+    for (int i = threadIdx.x; i < TL::total; i += blockDim.x) cem_smem[i] = gtab[i];
+    __syncthreads();
+  }
+  return TabRef<TL::lds>{gtab};
+}
+
 struct MeshArgs {
   int n[3];         // elements per axis (1 for unused axes)
   int L[3];         // nodes per axis (1 for unused axes)
@@ -73,6 +114,7 @@ struct StageArgs {
   double* nu;           // [E] viscosity
   double* beta;         // [E] slope-limiter factor
   double* dtbuf;        // [4]: dt, min dt_e, cfl flag, (spare)
+  double* dtpart;       // per-block minima of dt_e from the element pass
   int* counts;          // per-block [2]: clamped, violations
   double rk_a, rk_b;    // u_out = a u0 + b u^FE
 };
@@ -213,15 +255,15 @@ __device__ inline int64_t local_node(int loc, const int64_t (*off)[P + 1]) {
   return s;
 }
 
-// symmetric quadratic form x^T Q x
-template <int NL>
-__device__ inline double qform(const double* __restrict__ Q, const double* x) {
+// quadratic form x^T Q x of a symmetric table at offset off
+template <int NL, class TR>
+__device__ inline double qform(const TR& T, int off, const double* x) {
   double s = 0.0;
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
     double t = 0.0;
 #pragma unroll
-    for (int j = 0; j < NL; ++j) t += Q[i * NL + j] * x[j];
+    for (int j = 0; j < NL; ++j) t += T(off + i * NL + j) * x[j];
     s += x[i] * t;
   }
   return s;
@@ -259,17 +301,117 @@ __global__ void __launch_bounds__(256) k_line(LineArgs a) {
   a.out[t] = a.scale * acc;
 }
 
+// Register-blocked line operator for long lines (L >= R + TAPS): the rows of
+// the periodic inverse decay exponentially, so 2W+1 taps of the infinite-line
+// rows reproduce them below 1e-20 relative.  Lanes of a wave take different
+// transverse lines at the same run of R consecutive outputs along the axis,
+// so every output of a lane shares its node class with the other lanes and
+// the weights are wave-uniform (scalar loads); each thread keeps R
+// accumulators and streams R + TAPS - 1 inputs once.
+// W: half-width; runs of R = P * RE outputs, RE in {1, 2, 4} chosen per
+// launch so that small meshes still fill the chip
+template <int P> struct LineTaps;
+constexpr int kLineMaxRE = 4;
+// S: per-class weight stride, 2W+1 taps zero padded to a multiple of every
+// run length P * RE
+template <int P_, int W_> struct LineTapsBase {
+  static constexpr int W = W_;
+  static constexpr int S = (2 * W_ + 1 + kLineMaxRE * P_ - 1) / (kLineMaxRE * P_) * (kLineMaxRE * P_);
+};
+template <> struct LineTaps<1> : LineTapsBase<1, 36> {};
+template <> struct LineTaps<2> : LineTapsBase<2, 54> {};
+template <> struct LineTaps<3> : LineTapsBase<3, 68> {};
+
+struct LineFastArgs {
+  const double* in;
+  double* out;
+  const double* w;     // [P][S] (taps zero padded), tap t at offset t - W
+  int L, axis;
+  int L0, L1;
+  int64_t N, NT, ntrans;   // NT = N / L lines per component
+};
+
+template <int P, int RE>
+__global__ void __launch_bounds__(256) k_line_fast(LineFastArgs a) {
+  constexpr int W = LineTaps<P>::W, R = P * RE, S = LineTaps<P>::S;
+  constexpr int NB = S / R;                       // tap blocks of R (zero padded)
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.ntrans) return;
+  const int64_t comp = t / a.NT, rr = t - comp * a.NT;
+  int64_t base, sl;
+  if (a.axis == 0) {
+    base = comp * a.N + rr * a.L0;
+    sl = 1;
+  } else if (a.axis == 1) {
+    const int64_t x = rr % a.L0, z = rr / a.L0;
+    base = comp * a.N + x + z * (int64_t)a.L0 * a.L1;
+    sl = a.L0;
+  } else {
+    base = comp * a.N + rr;
+    sl = (int64_t)a.L0 * a.L1;
+  }
+  const int s = blockIdx.y * R;            // first output of the run (uniform)
+  int pos = s - W;                         // input feeding tap 0 of output 0
+  if (pos < 0) pos += a.L;
+  // acc[r] = sum_t w[r % P][t] in[s + r + t - W]; taps are walked in blocks
+  // of R with a window of 2R inputs held in registers
+  double acc[R], win[2 * R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    win[r] = a.in[base + (int64_t)pos * sl];
+    if (++pos == a.L) pos = 0;
+  }
+  // unrolled so that the loads of several tap blocks are in flight at once
+#pragma unroll 8
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      win[R + r] = a.in[base + (int64_t)pos * sl];
+      if (++pos == a.L) pos = 0;
+    }
+    const double* wb = a.w + b * R;          // weights of taps b*R .. b*R+R-1
+#pragma unroll
+    for (int tt = 0; tt < R; ++tt) {
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const double wv = wb[c * S + tt];
+#pragma unroll
+        for (int r = c; r < R; r += P) acc[r] += wv * win[r + tt];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) win[r] = win[R + r];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (s + r < a.L) a.out[base + (int64_t)(s + r) * sl] = acc[r];
+}
+
 // ---------------------------------------------------------------------------
 // step 1 of the algorithm: element loop (WENO sensor, viscosity, residual)
 // plus the facet data of step 3 (f^H, f^L, lambda, dt_e, low-order average)
 // ---------------------------------------------------------------------------
-template <int D, int P, int PH>
-__global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
+// minimum of dt_e over the 128 threads of a block (threads past the last
+// element contribute +inf) written to part[blockIdx.x]
+__device__ inline void block_min_dt(double* part, double v) {
+  __shared__ double red[128];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 64; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+template <int D, int P, int PH, class TR>
+__device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, int64_t e) {
   using PHY = Phys<D, PH>;
+  using TL = TabLayout<D, P>;
   constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NF = NL / P1;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const MeshArgs& ms = a.mesh;
-  if (e >= ms.E) return;
   const int64_t N = ms.N, E = ms.E;
   const double h = ms.h;
   int ei[3];
@@ -304,7 +446,7 @@ __global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
 #pragma unroll
     for (int j = 0; j < NL; ++j) ct[j] = U[c][j] - U[c][0];
     double beta[1 + 2 * D];
-    beta[0] = qform<NL>(a.tab.qf, ct);
+    beta[0] = qform<NL>(T, TL::qf, ct);
 #pragma unroll
     for (int l = 0; l < 2 * D; ++l) {
       const int k = l / 2, s = (l % 2) ? 1 : -1;
@@ -321,7 +463,7 @@ __global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
       const double c0 = cn[0];
 #pragma unroll
       for (int j = 0; j < NL; ++j) cn[j] -= c0;
-      beta[1 + l] = qform<NL>(a.tab.qf + (size_t)(1 + l) * NL * NL, cn);
+      beta[1 + l] = qform<NL>(T, TL::qf + (1 + l) * NL * NL, cn);
     }
     if (a.gamma_mode != 0) continue;
     const double wl0 = 1.0 - 2 * D * a.w_lin;
@@ -348,7 +490,7 @@ __global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
       const double c0 = cn[0];
 #pragma unroll
       for (int j = 0; j < NL; ++j) cn[j] -= c0;
-      const double* E1 = a.tab.ext + (s > 0 ? P1 * P1 : 0);
+      const int E1 = TL::ext + (s > 0 ? P1 * P1 : 0);
 #pragma unroll
       for (int i = 0; i < NL; ++i) {
         const int ai = dig(i, k, P1);
@@ -356,14 +498,14 @@ __global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
 #pragma unroll
         for (int b = 0; b < P1; ++b) {
           const int j = i + (b - ai) * ipow(P1, k);
-          ex += E1[ai * P1 + b] * cn[j];
+          ex += T(E1 + ai * P1 + b) * cn[j];
         }
         w[i] += om * (ct[i] - ex);
       }
     }
     // the ratio of eq. (7) is 0/0 on constant elements; it is regularised
     // with the weights' epsilon: ||u - u*|| / (||u||^2 + eps)^(1/2)
-    const double dev = sqrt(fmax(qform<NL>(a.tab.qf, w), 0.0));
+    const double dev = sqrt(fmax(qform<NL>(T, TL::qf, w), 0.0));
     const double ratio = fmin(1.0, dev / sqrt(fmax(beta[0], 0.0) + a.eps));
     const double gc = 1.0 - (a.q == 1.0 ? ratio : pow(ratio, a.q));
     gmin = fmin(gmin, gc);
@@ -397,18 +539,20 @@ __global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
     for (int c = 0; c < M; ++c) {
       double s = 0.0;
 #pragma unroll
-      for (int j = 0; j < NL; ++j) s += a.tab.vqf[q * NL + j] * U[c][j];
+      for (int j = 0; j < NL; ++j) s += T(TL::vqf + q * NL + j) * U[c][j];
       uq[c] = s;
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       double f[M];
       PHY::flux(k, uq, f, a.ph);
-      const double* dw = a.tab.dqw + ((size_t)k * NL + q) * NL;
+      const int dw = TL::dqw + (k * NL + q) * NL;
 #pragma unroll
-      for (int i = 0; i < NL; ++i)
+      for (int i = 0; i < NL; ++i) {
+        const double wv = T(dw + i);
 #pragma unroll
-        for (int c = 0; c < M; ++c) R[c][i] += dw[i] * f[c];
+        for (int c = 0; c < M; ++c) R[c][i] += wv * f[c];
+      }
     }
   }
   const double sa = nu * hpow / h, sg = nu * gam * hpow;   // nu h^{D-2}, nu gamma h^{D-1}
@@ -425,11 +569,11 @@ __global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
     for (int i = 0; i < NL; ++i) {
       double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-      for (int j = 0; j < NL; ++j) s1 += a.tab.ksum[i * NL + j] * U[c][j];
+      for (int j = 0; j < NL; ++j) s1 += T(TL::ksum + i * NL + j) * U[c][j];
 #pragma unroll
       for (int k = 0; k < D; ++k)
 #pragma unroll
-        for (int j = 0; j < NL; ++j) s2 += a.tab.ctg[((size_t)k * NL + i) * NL + j] * gk[k][j];
+        for (int j = 0; j < NL; ++j) s2 += T(TL::ctg + (k * NL + i) * NL + j) * gk[k][j];
       R[c][i] = hpow * R[c][i] - (sa * s1 - sg * s2);
       a.relem[((int64_t)c * NL + i) * E + e] = R[c][i];
     }
@@ -481,6 +625,16 @@ __global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
     a.ue[c * E + e] = ue[c];
     a.ubarL[c * E + e] = ue[c] - dt_e / h * fLsum[c];
   }
+  return dt_e;
+}
+
+template <int D, int P, int PH>
+__global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
+  const auto T = stage_tables<D, P>(a.tab.vqf);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double dt_e = 1.0e300;
+  if (e < a.mesh.E) dt_e = elem1_body<D, P, PH>(a, T, e);
+  block_min_dt(a.dtpart, dt_e);     // every thread of the block reaches this
 }
 
 // ---------------------------------------------------------------------------
@@ -532,10 +686,12 @@ __device__ inline void limit_facet(const StageArgs& a, int k, int64_t eL, int64_
 template <int D, int P, int PH>
 __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
   using PHY = Phys<D, PH>;
+  using TL = TabLayout<D, P>;
   constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NF = NL / P1;
+  const auto T = stage_tables<D, P>(a.tab.vqf);
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const MeshArgs& ms = a.mesh;
-  if (e >= ms.E) return;
+  if (e >= ms.E) return;       // no barrier below this point
   const int64_t N = ms.N, E = ms.E;
   const double h = ms.h;
   int ei[3];
@@ -619,7 +775,7 @@ __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
         for (int c = 0; c < M; ++c) {
           double s = 0.0;
 #pragma unroll
-          for (int fj = 0; fj < NF; ++fj) s += a.tab.facem[fi * NF + fj] * fn[c][fj];
+          for (int fj = 0; fj < NF; ++fj) s += T(TL::facem + fi * NF + fj) * fn[c][fj];
           f[c][i] += sg * s;
         }
       }
@@ -640,7 +796,7 @@ __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
     for (int i = 0; i < NL; ++i) {
       double t = 0.0;
 #pragma unroll
-      for (int j = 0; j < NL; ++j) t += a.tab.mass[i * NL + j] * ud[j];
+      for (int j = 0; j < NL; ++j) t += T(TL::mass + i * NL + j) * ud[j];
       const double T = hd * t - mloc * ud[i];
       const double R = a.relem[((int64_t)c * NL + i) * E + e];
       f[c][i] = mloc * (U[c][i] - uec[c]) + dt_e * (R - f[c][i] + Fe * (1.0 / NL) - T);
@@ -799,8 +955,8 @@ __global__ void __launch_bounds__(256) k_update(StageArgs a) {
   }
 }
 
-// min_e dt_e, global time step for the stage and the CFL check of eq. (23)
-// (single block, deterministic)
+// min_e dt_e from the per-block minima, global time step for the stage and
+// the CFL check of eq. (23) (single block, deterministic)
 __global__ void __launch_bounds__(1024) k_min_dt(const double* __restrict__ dte, int64_t E,
                                                  double* dtbuf, int stage, double dt_fixed,
                                                  double cfl) {

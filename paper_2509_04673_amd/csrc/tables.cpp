@@ -65,8 +65,7 @@ void gauss_legendre(int n, std::vector<LD>& t, std::vector<LD>& w) {
         p0 = p1;
         p1 = p2;
       }
-      LD pn = (n == 0) ? 1.0L : p1, pm = (n == 1) ? 1.0L : p0;
-      if (n == 1) { pn = x; pm = 1.0L; }
+      const LD pn = p1, pm = p0;   // P_n(x), P_{n-1}(x)
       dp = n * (x * pn - pm) / (x * x - 1.0L);
       LD dx = pn / dp;
       x -= dx;
@@ -144,44 +143,77 @@ void periodic_line_rows(int p, int Lp, LD h, std::vector<LD>& out_m, std::vector
 
 constexpr int kExactMax = 480;   // lines up to this length use the exact inverse
 
-void line_kernels(int p, int L, LD h, LineKernel& km, LineKernel& kg) {
-  int Lp = L <= kExactMax ? L : ((kExactMax + p - 1) / p) * p;
-  std::vector<LD> rm, rg;
-  periodic_line_rows(p, Lp, h, rm, rg);
-  auto fill = [&](const std::vector<LD>& rows, LineKernel& k) {
-    if (L <= kExactMax) {
-      k.taps = L;
-      k.first = -(L / 2);
-    } else {
-      // truncate where the exponentially decaying rows fall below 1e-20 of
-      // their peak (far below double rounding)
-      LD peak = 0.0L;
-      for (LD v : rows) peak = std::max(peak, std::fabs(v));
-      int W = 0;
-      for (int c = 0; c < p; ++c)
-        for (int j = 0; j < Lp; ++j) {
-          int dist = j - c;
-          if (dist > Lp / 2) dist -= Lp;
-          if (dist < -Lp / 2) dist += Lp;
-          if (std::fabs(rows[(size_t)c * Lp + j]) > 1e-20L * peak) W = std::max(W, std::abs(dist));
-        }
-      k.taps = 2 * W + 1;
-      k.first = -W;
+// rows of the periodic operators on a line of Lp nodes, cut to taps
+void fill_kernel(int p, int Lp, const std::vector<LD>& rows, int taps, int first, std::vector<double>& w) {
+  w.assign((size_t)p * taps, 0.0);
+  for (int c = 0; c < p; ++c)
+    for (int t = 0; t < taps; ++t) {
+      int j = ((c + first + t) % Lp + Lp) % Lp;
+      w[(size_t)c * taps + t] = (double)rows[(size_t)c * Lp + j];
     }
-    k.w.assign((size_t)p * k.taps, 0.0);
-    for (int c = 0; c < p; ++c)
-      for (int t = 0; t < k.taps; ++t) {
-        int j = ((c + k.first + t) % Lp + Lp) % Lp;
-        k.w[(size_t)c * k.taps + t] = (double)rows[(size_t)c * Lp + j];
-      }
-  };
-  fill(rm, km);
-  fill(rg, kg);
+}
+
+// half-width beyond which the rows fall below 1e-20 of their peak
+int decay_width(int p, int Lp, const std::vector<LD>& rows) {
+  LD peak = 0.0L;
+  for (LD v : rows) peak = std::max(peak, std::fabs(v));
+  int W = 0;
+  for (int c = 0; c < p; ++c)
+    for (int j = 0; j < Lp; ++j) {
+      int dist = j - c;
+      if (dist > Lp / 2) dist -= Lp;
+      if (dist < -Lp / 2) dist += Lp;
+      if (std::fabs(rows[(size_t)c * Lp + j]) > 1e-20L * peak) W = std::max(W, std::abs(dist));
+    }
+  return W;
+}
+
+void line_kernels(int p, int L, LD h, int wfast, int rfast, int sfast, LineKernel& km, LineKernel& kg) {
+  // infinite-line rows from a periodic auxiliary line long enough for the
+  // periodic images to vanish below 1e-20
+  const int Laux = ((4 * wfast + 64 + p - 1) / p) * p;
+  std::vector<LD> am, ag;
+  periodic_line_rows(p, Laux, h, am, ag);
+  const bool fast = L >= rfast + 2 * wfast && decay_width(p, Laux, am) <= wfast &&
+                    decay_width(p, Laux, ag) <= wfast;
+  for (LineKernel* k : {&km, &kg}) {
+    const std::vector<LD>& rows = (k == &km) ? am : ag;
+    k->wfast = 0;
+    k->wf.clear();
+    if (fast) {
+      // taps 0..2W at offsets -W..W, each class row zero padded to the
+      // stride sfast of the device kernel
+      k->wfast = wfast;
+      std::vector<double> tmp;
+      fill_kernel(p, Laux, rows, 2 * wfast + 1, -wfast, tmp);
+      k->wf.assign((size_t)p * sfast, 0.0);
+      for (int cc = 0; cc < p; ++cc)
+        for (int t = 0; t < 2 * wfast + 1; ++t) k->wf[(size_t)cc * sfast + t] = tmp[(size_t)cc * (2 * wfast + 1) + t];
+    }
+  }
+  // generic kernel: the exact periodic rows of this line
+  std::vector<LD> rm, rg;
+  if (L <= kExactMax) {
+    periodic_line_rows(p, L, h, rm, rg);
+    km.taps = kg.taps = L;
+    km.first = kg.first = -(L / 2);
+    fill_kernel(p, L, rm, L, -(L / 2), km.w);
+    fill_kernel(p, L, rg, L, -(L / 2), kg.w);
+  } else {
+    const int Wm = decay_width(p, Laux, am), Wg = decay_width(p, Laux, ag);
+    km.taps = 2 * Wm + 1;
+    km.first = -Wm;
+    kg.taps = 2 * Wg + 1;
+    kg.first = -Wg;
+    fill_kernel(p, Laux, am, km.taps, km.first, km.w);
+    fill_kernel(p, Laux, ag, kg.taps, kg.first, kg.w);
+  }
 }
 
 }  // namespace
 
-bool build_tables(int d, int p, double h, const int L[3], HostTables& T) {
+bool build_tables(int d, int p, double h, const int L[3], const int wfast[5], const int rfast[5],
+                  const int sfast[5], HostTables& T) {
   if (d < 1 || d > 3 || p < 1 || p > 4) return false;
   const int P1 = p + 1;
   int nl = 1;
@@ -311,7 +343,8 @@ bool build_tables(int d, int p, double h, const int L[3], HostTables& T) {
       T.facem[(size_t)i * nlf + j] = (double)v;
     }
 
-  for (int k = 0; k < d; ++k) line_kernels(p, L[k], (LD)h, T.kmass[k], T.kgrad[k]);
+  for (int k = 0; k < d; ++k)
+    line_kernels(p, L[k], (LD)h, wfast[p], rfast[p], sfast[p], T.kmass[k], T.kgrad[k]);
   return true;
 }
 

@@ -22,6 +22,10 @@ struct LineKernel {
   int taps = 0;       // number of taps per output
   int first = 0;      // offset of tap 0 relative to the output node
   std::vector<double> w;   // [P classes][taps]
+  // infinite-line rows padded to the fixed width 2*wfast+1 of the
+  // register-blocked kernel (empty when the line is too short for it)
+  int wfast = 0;
+  std::vector<double> wf;  // [P][sfast]: 2*wfast+1 taps, zero padded
 };
 
 struct HostTables {
@@ -38,6 +42,10 @@ struct HostTables {
 
 // Build all tables for dimension d, degree p, cell size h and L_k nodes per
 // axis.  Returns false on an unsupported (d, p).
-bool build_tables(int d, int p, double h, const int L[3], HostTables& out);
+// wfast[p]: half-width of the register-blocked line kernel, rfast[p]: its
+// shortest run of outputs, sfast[p]: its per-class weight stride (all must
+// match the device templates)
+bool build_tables(int d, int p, double h, const int L[3], const int wfast[5], const int rfast[5],
+                  const int sfast[5], HostTables& out);
 
 }  // namespace cem

@@ -24,6 +24,11 @@ STAGE_CASES = [
     ("euler2d_q2", lambda: random_euler_workload(2, 2, (12, 7))),
     ("euler2d_q3", lambda: random_euler_workload(2, 3, (9, 10))),
     ("euler3d_q2", lambda: random_euler_workload(3, 2, (5, 6, 4))),
+    # lines long enough for the register-blocked line kernel (p = 1, 2, 3)
+    ("adv2d_q1_long", lambda: random_scalar_workload(2, 1, (81, 80))),
+    ("kpp2d_q2_long", lambda: random_scalar_workload(2, 2, (64, 63), kind="kpp")),
+    ("euler2d_q3_long", lambda: random_euler_workload(2, 3, (55, 54))),
+    ("euler3d_q2_mixed", lambda: random_euler_workload(3, 2, (63, 5, 4))),
 ]
 
 TAP_NAMES = ["g", "gamma", "nu", "dt_e", "ue", "ubarL", "fA", "r", "udot", "ubar", "beta"]
@@ -43,6 +48,7 @@ def _compare_stage(wl, modes=None, label=""):
         errs[name] = rel_linf(s.tap(name).reshape(np.shape(taps[name])), taps[name])
     errs["u_fe"] = rel_linf(got, ufe)
     s.close()
+    announce(f"[parity] {label}: " + ", ".join(f"{k}={v:.1e}" for k, v in errs.items()))
     bad = {k: v for k, v in errs.items() if not v <= TOL}
     assert not bad, (label, errs)
     return errs
