@@ -139,8 +139,15 @@ cem_status cem_set_bounds(cem_ctx* ctx, int from_state, double u_min, double u_m
  * reported by cem_check_invariants. */
 cem_status cem_rk_stage(cem_ctx* ctx, int stage, double dt, double cfl);
 
-/* One SSP-RK3 step: u_base <- u, then stages 0, 1, 2.  Asynchronous. */
+/* One SSP-RK3 step: u_base <- u, then stages 0, 1, 2.  Asynchronous.  By
+ * default the three stages are captured once into a HIP graph (on a private
+ * stream) and replayed on the context's stream; a new capture happens when
+ * dt or cfl change, and after cem_bind / cem_set_bounds.  With kernel timing
+ * enabled the stages are launched directly. */
 cem_status cem_step(cem_ctx* ctx, double dt, double cfl);
+
+/* Enables (default) or disables graph replay in cem_step. */
+cem_status cem_set_graphs(cem_ctx* ctx, int enable);
 
 /* Synchronous: reads the step size, CFL flag and clamp/violation counters
  * accumulated since the last cem_reset_counters, and the state invariants.
@@ -160,8 +167,9 @@ size_t cem_tap_size(const cem_ctx* ctx, int tap);
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch of the kernels selected by mask (bit k = kernel id k):
  *   0 projected-gradient line operator   1 element pass 1 (sensor, residual,
- *   facets)   2 time-step reduction   3 residual gather   4 mass-solve line
- *   operator   5 element pass 2 (limiters, contributions)   6 node update.
+ *   facets)   2 (unused)   3 residual gather (fused with the first mass-solve
+ *   pass on long x-lines)   4 mass-solve line operator   5 element pass 2
+ *   (limiters, contributions)   6 node update (with the time-step reduction).
  * cem_kernel_times is synchronous: it returns the summed milliseconds and
  * launch counts per id since the previous call (arrays of n <= 7 entries)
  * and clears them. */

@@ -73,6 +73,7 @@ _SIGS = [
     ("cem_reset_counters", ctypes.c_int, [_P]),
     ("cem_debug_tap", ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_size_t]),
     ("cem_tap_size", ctypes.c_size_t, [_P, ctypes.c_int]),
+    ("cem_set_graphs", ctypes.c_int, [_P, ctypes.c_int]),
     ("cem_set_timing", ctypes.c_int, [_P, ctypes.c_uint]),
     ("cem_kernel_times", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
@@ -178,7 +179,11 @@ def cem_debug_tap(ctx, tap, dst_ptr, count):
     _check(lib().cem_debug_tap(ctx, int(tap), _P(dst_ptr), int(count)))
 
 
-KERNELS = ["grad_line", "elem1", "min_dt", "gather_r", "mass_line", "elem2", "update"]
+KERNELS = ["grad_line", "elem1", "unused", "gather_r", "mass_line", "elem2", "update"]
+
+
+def cem_set_graphs(ctx, enable):
+    _check(lib().cem_set_graphs(ctx, int(bool(enable))))
 
 
 def cem_set_timing(ctx, mask):

@@ -2,6 +2,7 @@
 // include/cem.h).  Host orchestration of the gfx950 kernels of kernels.hpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <cstdio>
@@ -56,6 +57,12 @@ struct cem_ctx {
       o_nu, o_beta, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart;
   int upd_blocks = 0, inv_blocks = 0;
   bool bound = false, bounds_set = false;
+  // whole-step HIP graph (captured on a private stream, launched on stream)
+  bool use_graphs = true;
+  bool copy_base_next = false;   // the next stage 0 also writes u_base = u
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  double graph_dt = -1.0, graph_cfl = -1.0;
   // optional per-kernel event timing
   unsigned timing_mask = 0;
   struct Rec { int id; hipEvent_t a, b; };
@@ -123,7 +130,26 @@ const int kRfast[5] = {0, 1, 2, 3, 0};   // shortest run: RE = 1
 const int kSfast[5] = {0, LineTaps<1>::S, LineTaps<2>::S, LineTaps<3>::S, 0};
 
 template <int P>
-void launch_line_fast(const LineFastArgs& la, hipStream_t st) {
+void launch_line_fast(LineFastArgs la, hipStream_t st) {
+  constexpr int W = LineTaps<P>::W;
+  if (la.axis == 0 && la.L <= 4096) {
+    // whole lines in LDS; one line per block unless lines are short
+    la.nlb = std::max(1, std::min(2048 / la.L, (int)((la.ntrans + 511) / 512)));
+    const size_t lds = (size_t)la.nlb * la.L * sizeof(double);
+    const unsigned grid = (unsigned)((la.ntrans + la.nlb - 1) / la.nlb);
+    if (la.L >= 2 * P + 2 * W)
+      hipLaunchKernelGGL((k_line_x<P, 2>), dim3(grid), dim3(256), lds, st, la);
+    else
+      hipLaunchKernelGGL((k_line_x<P, 1>), dim3(grid), dim3(256), lds, st, la);
+    return;
+  }
+  if (la.axis > 0) {
+    const int RE = 1, R = P * RE, TY = 8 * R;
+    const size_t lds = (size_t)(TY + LineTaps<P>::S) * kTileX * sizeof(double);
+    dim3 grid(nblocks(la.ntrans, kTileX), (unsigned)((la.L + TY - 1) / TY));
+    hipLaunchKernelGGL((k_line_y<P, 1>), grid, dim3(256), lds, st, la);
+    return;
+  }
   // longest run that still gives >= 2^17 threads (2 waves per SIMD)
   int re = kLineMaxRE;
   while (re > 1 && (la.L < P * re + 2 * LineTaps<P>::W ||
@@ -233,22 +259,27 @@ struct Timed {
   }
 };
 
+LineFastArgs line_args(const cem_ctx* c, const double* in, double* out, int axis, bool grad) {
+  LineFastArgs la{};
+  la.in = in;
+  la.out = out;
+  la.w = c->W<double>(c->o_tab) + (grad ? c->off_kgf[axis] : c->off_kmf[axis]);
+  la.L = c->L[axis];
+  la.axis = axis;
+  la.L0 = c->L[0];
+  la.L1 = c->L[1];
+  la.N = c->N;
+  la.NT = c->N / c->L[axis];
+  la.ntrans = (int64_t)c->m * la.NT;
+  return la;
+}
+
 cem_status launch_line(cem_ctx* c, const double* in, double* out, int axis, bool grad) {
   Timed tm(c, grad ? 0 : 4);
   const LineKernel& K = grad ? c->tabs.kgrad[axis] : c->tabs.kmass[axis];
   const double* tb = c->W<double>(c->o_tab);
   if (K.wfast > 0) {
-    LineFastArgs la{};
-    la.in = in;
-    la.out = out;
-    la.w = tb + (grad ? c->off_kgf[axis] : c->off_kmf[axis]);
-    la.L = c->L[axis];
-    la.axis = axis;
-    la.L0 = c->L[0];
-    la.L1 = c->L[1];
-    la.N = c->N;
-    la.NT = c->N / c->L[axis];
-    la.ntrans = (int64_t)c->m * la.NT;
+    LineFastArgs la = line_args(c, in, out, axis, grad);
     switch (c->p) {
       case 1: launch_line_fast<1>(la, c->stream); break;
       case 2: launch_line_fast<2>(la, c->stream); break;
@@ -297,6 +328,11 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   const double rka[3] = {0.0, 0.75, 1.0 / 3.0}, rkb[3] = {1.0, 0.25, 2.0 / 3.0};
   a.rk_a = rka[stage];
   a.rk_b = rkb[stage];
+  a.stage = stage;
+  a.copy_base = (stage == 0 && c->copy_base_next) ? 1 : 0;
+  a.ndtpart = (int)nblocks(c->E, 128);
+  a.dt_fixed = dt;
+  a.cfl = cfl;
   // projected gradient g_k = M_1D^{-1} C_1D u along axis k (Sec. 2.2)
   for (int k = 0; k < D; ++k) {
     cem_status s = launch_line(c, c->u, a.g + (int64_t)k * M * c->N, k, true);
@@ -307,22 +343,28 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     hipLaunchKernelGGL((k_elem1<D, P, PH>), dim3(nblocks(c->E, 128)), dim3(128), (lds_bytes<D, P>()), c->stream, a);
   }
   HIPCHK(hipGetLastError());
-  {
-    Timed tm(c, 2);
-    hipLaunchKernelGGL(k_min_dt, dim3(1), dim3(1024), 0, c->stream, a.dtpart, (int64_t)nblocks(c->E, 128),
-                       a.dtbuf, stage, dt, cfl);
-  }
-  HIPCHK(hipGetLastError());
-  {
-    Timed tm(c, 3);
-    hipLaunchKernelGGL((k_gather_r<D, P, M>), dim3(nblocks(c->N, 256)), dim3(256), 0, c->stream, a);
-  }
-  HIPCHK(hipGetLastError());
-  // udot = M_C^{-1} r, one line solve per axis (Sec. 4.3, step 2)
+  // udot = M_C^{-1} r, one line pass per axis (Sec. 4.3, step 2); the
+  // assembly of r is fused into the first pass when it runs on whole x-lines
   double* tmp = c->W<double>(c->o_tmp);
   double* tmp2 = c->W<double>(c->o_tmp2);
   const double* src = a.r;
-  for (int k = 0; k < D; ++k) {
+  int k0 = 0;
+  if (c->tabs.kmass[0].wfast > 0 && c->L[0] <= 4096) {
+    Timed tm(c, 3);
+    LineFastArgs la = line_args(c, a.r, D == 1 ? a.udot : tmp, 0, false);
+    la.nlb = std::max(1, std::min(2048 / la.L, (int)((la.ntrans + 511) / 512)));
+    const size_t lds = (size_t)la.nlb * la.L * sizeof(double);
+    const unsigned grid = (unsigned)((la.ntrans + la.nlb - 1) / la.nlb);
+    hipLaunchKernelGGL((k_gather_line_x<D, P, M, 1>), dim3(grid), dim3(256), lds, c->stream, a, la);
+    HIPCHK(hipGetLastError());
+    src = D == 1 ? a.udot : tmp;
+    k0 = 1;
+  } else {
+    Timed tm(c, 3);
+    hipLaunchKernelGGL((k_gather_r<D, P, M>), dim3(nblocks(c->N, 256)), dim3(256), 0, c->stream, a);
+    HIPCHK(hipGetLastError());
+  }
+  for (int k = k0; k < D; ++k) {
     double* dst = (k == D - 1) ? a.udot : (k % 2 == 0 ? tmp : tmp2);
     cem_status s = launch_line(c, src, dst, k, false);
     if (s != CEM_OK) return s;
@@ -342,6 +384,11 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
 }
 
 using StageFn = cem_status (*)(cem_ctx*, int, double, double);
+
+void drop_graph(cem_ctx* c) {
+  if (c->graph) hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+}
 
 StageFn pick(int d, int p, int kind) {
 #define CASE(D, P, PH) \
@@ -486,6 +533,7 @@ cem_status cem_bind(cem_ctx* c, double* u, double* u_base, void* workspace, size
   if (u == u_base) return fail(CEM_EINVAL, "u and u_base must differ");
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(CEM_EINVAL, "workspace not 256-byte aligned");
   if (ws_bytes < c->ws_need) return fail(CEM_ENOMEM, "workspace too small");
+  drop_graph(c);
   c->u = u;
   c->u0 = u_base;
   c->ws = static_cast<char*>(workspace);
@@ -526,6 +574,7 @@ cem_status cem_set_bounds(cem_ctx* c, int from_state, double u_min, double u_max
   c->prm.u_min = u_min;
   c->prm.u_max = u_max;
   c->bounds_set = true;
+  drop_graph(c);            // the bounds are baked into captured launches
   return CEM_OK;
 }
 
@@ -537,13 +586,53 @@ cem_status cem_rk_stage(cem_ctx* c, int stage, double dt, double cfl) {
   return pick(c->d, c->p, c->kind)(c, stage, dt, cfl);
 }
 
+static cem_status step_direct(cem_ctx* c, double dt, double cfl) {
+  c->copy_base_next = true;     // stage 0 writes u_base = u (no separate copy)
+  cem_status st = CEM_OK;
+  for (int s = 0; s < 3 && st == CEM_OK; ++s) st = pick(c->d, c->p, c->kind)(c, s, dt, cfl);
+  c->copy_base_next = false;
+  return st;
+}
+
 cem_status cem_step(cem_ctx* c, double dt, double cfl) {
   if (!c || !c->bound) return fail(CEM_EINVAL, "context not bound");
-  HIPCHK(hipMemcpyAsync(c->u0, c->u, (size_t)c->m * c->N * 8, hipMemcpyDeviceToDevice, c->stream));
-  for (int s = 0; s < 3; ++s) {
-    cem_status st = cem_rk_stage(c, s, dt, cfl);
-    if (st != CEM_OK) return st;
+  if (!(dt > 0.0) && !(cfl > 0.0)) return fail(CEM_EINVAL, "need dt > 0 or cfl > 0");
+  if (c->kind != CEM_EULER && !c->bounds_set) return fail(CEM_EINVAL, "scalar bounds not set");
+  if (!c->use_graphs || c->timing_mask) return step_direct(c, dt, cfl);
+  if (!c->graph || c->graph_dt != dt || c->graph_cfl != cfl) {
+    // capture the three stages on the private stream, then replay the graph
+    // on the caller's stream
+    drop_graph(c);
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    cem_status st = step_direct(c, dt, cfl);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->stream = user;
+    if (st != CEM_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(CEM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->graph = nullptr;
+      return fail(CEM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    c->graph_dt = dt;
+    c->graph_cfl = cfl;
   }
+  HIPCHK(hipGraphLaunch(c->graph, c->stream));
+  return CEM_OK;
+}
+
+cem_status cem_set_graphs(cem_ctx* c, int enable) {
+  if (!c) return fail(CEM_EINVAL, "null context");
+  c->use_graphs = enable != 0;
+  if (!c->use_graphs) drop_graph(c);
   return CEM_OK;
 }
 
@@ -664,6 +753,8 @@ cem_status cem_kernel_times(cem_ctx* c, double* total_ms, long long* launches, i
 
 void cem_destroy(cem_ctx* c) {
   if (!c) return;
+  drop_graph(c);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   for (auto& r : c->recs) {
     hipEventDestroy(r.a);
     hipEventDestroy(r.b);

@@ -99,7 +99,7 @@ struct StageArgs {
   int gamma_mode, alpha_mode, beta_mode;   // 0 method, 1 force 0, 2 force 1
   double umin, umax, clamp_tol;
   const double* u;      // stage input u^(s)   [M][N]
-  const double* u0;     // step base u^n       [M][N]
+  double* u0;           // step base u^n       [M][N]
   double* uout;         // stage output (may alias u: per-node read-then-write)
   double* g;            // [D][M][N] projected gradient
   double* r;            // [M][N] residual
@@ -117,6 +117,10 @@ struct StageArgs {
   double* dtpart;       // per-block minima of dt_e from the element pass
   int* counts;          // per-block [2]: clamped, violations
   double rk_a, rk_b;    // u_out = a u0 + b u^FE
+  int stage;            // 0, 1, 2
+  int copy_base;        // stage 0 of a step: write u_base = u before updating
+  int ndtpart;          // number of per-block dt_e minima
+  double dt_fixed, cfl; // stage 0: dt = dt_fixed > 0 ? dt_fixed : cfl min_e dt_e
 };
 
 // ---------------------------------------------------------------------------
@@ -329,6 +333,7 @@ struct LineFastArgs {
   int L, axis;
   int L0, L1;
   int64_t N, NT, ntrans;   // NT = N / L lines per component
+  int nlb;                 // lines per block (axis 0 LDS kernel)
 };
 
 template <int P, int RE>
@@ -387,6 +392,115 @@ __global__ void __launch_bounds__(256) k_line_fast(LineFastArgs a) {
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (s + r < a.L) a.out[base + (int64_t)(s + r) * sl] = acc[r];
+}
+
+// One run of R = P * RE outputs of a line operator: acc[r] = sum_t
+// w[r % P][t] x(s + r + t - W), with x read through ld(j) for the inputs
+// j = 0, 1, ... of the run's window (x(s - W + j)).  Taps are walked in blocks
+// of R with a 2R-input register window; weights are wave-uniform.
+template <int P, int RE, class LD>
+__device__ __forceinline__ void line_run(const double* __restrict__ w, const LD& ld, double* acc) {
+  constexpr int R = P * RE, S = LineTaps<P>::S, NB = S / R;
+  double win[2 * R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) win[r] = ld(r);
+#pragma unroll 4
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) win[R + r] = ld((b + 1) * R + r);
+    const double* wb = w + b * R;
+#pragma unroll
+    for (int tt = 0; tt < R; ++tt) {
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const double wv = wb[c * S + tt];
+#pragma unroll
+        for (int r = c; r < R; r += P) acc[r] += wv * win[r + tt];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) win[r] = win[R + r];
+  }
+}
+
+// Axis 0 (contiguous lines): a block stages nlb whole lines in LDS (one
+// coalesced copy, periodic wrap inside LDS) and each thread computes runs of
+// R outputs.  Consecutive lanes take consecutive runs.
+template <int P, int RE>
+__global__ void __launch_bounds__(256) k_line_x(LineFastArgs a) {
+  constexpr int W = LineTaps<P>::W, R = P * RE;
+  const int L = a.L;
+  const int64_t t0 = (int64_t)blockIdx.x * a.nlb;
+  const int nl = (int)min((int64_t)a.nlb, a.ntrans - t0);
+  const double* src = a.in + t0 * L;          // lines of axis 0 are contiguous
+  for (int i = threadIdx.x; i < nl * L; i += blockDim.x) cem_smem[i] = src[i];
+  __syncthreads();
+  const int runs = (L + R - 1) / R;
+  for (int g = threadIdx.x; g < nl * runs; g += blockDim.x) {
+    const int line = g / runs, s = (g - line * runs) * R;
+    const double* row = cem_smem + line * L;
+    int p0 = s - W;
+    if (p0 < 0) p0 += L;
+    auto ld = [&](int j) {
+      int q = p0 + j;
+      if (q >= L) q -= L;
+      if (q >= L) q -= L;
+      return row[q];
+    };
+    double acc[R];
+    line_run<P, RE>(a.w, ld, acc);
+    double* dst = a.out + (t0 + line) * L;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (s + r < L) dst[s + r] = acc[r];
+  }
+}
+
+// Axes 1 and 2 (strided lines): a block stages a tile of 32 consecutive
+// transverse lines x (TY + S) line positions in LDS (coalesced rows) and
+// computes TY = 8R outputs per line; a wave is 32 lines x 2 runs.
+constexpr int kTileX = 32;
+template <int P, int RE>
+__global__ void __launch_bounds__(256) k_line_y(LineFastArgs a) {
+  // rows: the window of the last run reads up to TY + S - 1 (zero-weight tail)
+  constexpr int W = LineTaps<P>::W, R = P * RE, TY = 8 * R, ROWS = TY + LineTaps<P>::S;
+  const int L = a.L;
+  const int64_t t0 = (int64_t)blockIdx.x * kTileX;
+  const int s0 = blockIdx.y * TY;
+  const int tx = threadIdx.x % kTileX, rg = threadIdx.x / kTileX;   // rg = 0..7
+  // base of transverse line t and the stride along the line
+  auto base_of = [&](int64_t t) -> int64_t {
+    const int64_t comp = t / a.NT, rr = t - comp * a.NT;
+    if (a.axis == 1) {
+      const int64_t x = rr % a.L0, z = rr / a.L0;
+      return comp * a.N + x + z * (int64_t)a.L0 * a.L1;
+    }
+    return comp * a.N + rr;
+  };
+  const int64_t sl = (a.axis == 1) ? (int64_t)a.L0 : (int64_t)a.L0 * a.L1;
+  const bool have = t0 + tx < a.ntrans;
+  const int64_t b = have ? base_of(t0 + tx) : 0;
+  int p = s0 - W;
+  if (p < 0) p += L;
+  p += rg;
+  if (p >= L) p -= L;
+  for (int row = rg; row < ROWS; row += 8) {
+    cem_smem[row * kTileX + tx] = have ? a.in[b + (int64_t)p * sl] : 0.0;
+    p += 8;
+    if (p >= L) p -= L;
+    if (p >= L) p -= L;
+  }
+  __syncthreads();
+  const int s = s0 + rg * R;
+  if (!have || s >= L) return;
+  auto ld = [&](int j) { return cem_smem[(rg * R + j) * kTileX + tx]; };
+  double acc[R];
+  line_run<P, RE>(a.w, ld, acc);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (s + r < L) a.out[b + (int64_t)(s + r) * sl] = acc[r];
 }
 
 // ---------------------------------------------------------------------------
@@ -905,10 +1019,34 @@ __global__ void __launch_bounds__(256) k_gather_r(StageArgs a) {
 // u^FE_i = u_i + dt / m_i sum_e [m_i^e (ubar^e - u_i) + beta_e f_i^e] / dt_e
 // (eq. 49), then the Shu-Osher combination u_out = a u0 + b u^FE and, for
 // scalar problems, the round-off clamp to the global bounds.
+// global time step of the stage from the per-block minima of dt_e (every
+// block reduces them itself; block 0 records dt, the running minimum and the
+// CFL flag of eq. (23))
+__device__ inline double stage_dt(const StageArgs& a) {
+  __shared__ double red[256];
+  double m = 1.0e300;
+  for (int j = threadIdx.x; j < a.ndtpart; j += blockDim.x) m = fmin(m, a.dtpart[j]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double mn = red[0];
+  const double dt = a.stage == 0 ? (a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl * mn) : a.dtbuf[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (a.stage == 0) a.dtbuf[0] = dt;
+    a.dtbuf[1] = a.stage == 0 ? mn : fmin(a.dtbuf[1], mn);
+    if (dt > mn) a.dtbuf[2] = 1.0;
+  }
+  return dt;
+}
+
 template <int D, int P, int M, bool SCALAR>
 __global__ void __launch_bounds__(256) k_update(StageArgs a) {
   constexpr int NL = ipow(P + 1, D);
   __shared__ int red[2][256];
+  const double dt = stage_dt(a);          // every thread of the block
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int nclamp = 0, nbad = 0;
   if (i < a.mesh.N) {
@@ -920,12 +1058,13 @@ __global__ void __launch_bounds__(256) k_update(StageArgs a) {
 #pragma unroll
     for (int k = 0; k < D; ++k) hd *= a.mesh.h;
     const double mi = nrec * (hd * (1.0 / NL));
-    const double dt = a.dtbuf[0];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
       double s = 0.0;
       for (int t = 0; t < nrec; ++t) s += a.relem[((int64_t)c * NL + locs[t]) * E + eids[t]];
-      const double ufe = a.u[c * N + i] + dt / mi * s;
+      const double ui = a.u[c * N + i];
+      if (a.copy_base) a.u0[c * N + i] = ui;
+      const double ufe = ui + dt / mi * s;
       double v = (a.rk_a == 0.0) ? ufe : a.rk_a * a.u0[c * N + i] + a.rk_b * ufe;
       if (SCALAR) {
         // round-off excess is clamped and counted; larger excursions (only
@@ -974,6 +1113,50 @@ __global__ void __launch_bounds__(1024) k_min_dt(const double* __restrict__ dte,
     if (stage == 0) dtbuf[0] = dt_fixed > 0.0 ? dt_fixed : cfl * mn;
     dtbuf[1] = fmin(stage == 0 ? 1.0e300 : dtbuf[1], mn);
     if (dtbuf[0] > mn) dtbuf[2] = 1.0;
+  }
+}
+
+// Residual assembly fused with the first mass-solve pass (axis 0): a block
+// gathers r = sum_e (element residual vectors) for nlb whole x-lines into LDS
+// (fixed element order per node, as k_gather_r), stores r, then applies the
+// axis-0 line operator.
+template <int D, int P, int M, int RE>
+__global__ void __launch_bounds__(256) k_gather_line_x(StageArgs sa, LineFastArgs a) {
+  constexpr int W = LineTaps<P>::W, R = P * RE, NL = ipow(P + 1, D);
+  const int L = a.L;
+  const int64_t t0 = (int64_t)blockIdx.x * a.nlb;
+  const int nl = (int)min((int64_t)a.nlb, a.ntrans - t0);
+  const int64_t E = sa.mesh.E, N = sa.mesh.N;
+  for (int q = threadIdx.x; q < nl * L; q += blockDim.x) {
+    const int64_t g = (t0 + q / L) * L + q % L;   // component-major flat index
+    const int64_t c = g / N, i = g - c * N;
+    int64_t eids[8];
+    int locs[8];
+    const int nrec = node_elements<D, P>(i, sa.mesh, eids, locs);
+    double s = 0.0;
+    for (int t = 0; t < nrec; ++t) s += sa.relem[(c * NL + locs[t]) * E + eids[t]];
+    cem_smem[q] = s;
+    sa.r[g] = s;
+  }
+  __syncthreads();
+  const int runs = (L + R - 1) / R;
+  for (int g = threadIdx.x; g < nl * runs; g += blockDim.x) {
+    const int line = g / runs, s = (g - line * runs) * R;
+    const double* row = cem_smem + line * L;
+    int p0 = s - W;
+    if (p0 < 0) p0 += L;
+    auto ld = [&](int j) {
+      int q = p0 + j;
+      if (q >= L) q -= L;
+      if (q >= L) q -= L;
+      return row[q];
+    };
+    double acc[R];
+    line_run<P, RE>(a.w, ld, acc);
+    double* dst = a.out + (t0 + line) * L;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (s + r < L) dst[s + r] = acc[r];
   }
 }
 

@@ -29,6 +29,8 @@ STAGE_CASES = [
     ("kpp2d_q2_long", lambda: random_scalar_workload(2, 2, (64, 63), kind="kpp")),
     ("euler2d_q3_long", lambda: random_euler_workload(2, 3, (55, 54))),
     ("euler3d_q2_mixed", lambda: random_euler_workload(3, 2, (63, 5, 4))),
+    ("adv3d_q2_ylong", lambda: random_scalar_workload(3, 2, (4, 63, 5))),
+    ("adv3d_q2_zlong", lambda: random_scalar_workload(3, 2, (5, 4, 63))),
 ]
 
 TAP_NAMES = ["g", "gamma", "nu", "dt_e", "ue", "ubarL", "fA", "r", "udot", "ubar", "beta"]
@@ -132,3 +134,39 @@ def test_kpp2d_full_size_stage_parity():
     # the KPP workload at its full size (256^2 Q2) in the benchmark's launch
     # configuration: one stage, every intermediate
     _compare_stage(W.kpp2d(seed=0), label="kpp2d-full")
+
+
+def test_graph_replay_matches_direct_launches():
+    # cem_step replays a captured HIP graph; every replay, with downloads and
+    # other eager work in between, must equal the directly launched stages
+    from paper_2509_04673_amd import cem
+    wl = W.kpp2d(seed=4, n=64)
+    a = gpu_for(wl)
+    b = gpu_for(wl)
+    cem.cem_set_graphs(b.ctx, 0)
+    for step in range(5):
+        a.step(dt=2e-3)
+        b.step(dt=2e-3)
+        ua, ub = a.download(), b.download()
+        assert np.array_equal(ua, ub), step
+    ca, cb = a.check(), b.check()
+    assert ca["dt"] == cb["dt"] == 2e-3 and ca["violations"] == 0
+    a.close()
+    b.close()
+
+
+def test_adaptive_dt_and_cfl_flag():
+    # stage 0 picks dt = cfl * min_e dt_e; a fixed dt above min_e dt_e raises
+    # the CFL flag (CEM_ECFL) through the invariant check
+    wl = W.euler2d(seed=3, n=16)
+    orc = oracle_for(wl)
+    s = gpu_for(wl)
+    s.step(cfl=0.5)
+    chk = s.check()
+    assert abs(chk["dt"] - 0.5 * orc.max_dt(wl.u0)) <= 1e-14 * chk["dt"]
+    assert chk["cfl_violated"] == 0
+    s.upload(wl.u0)
+    s.step(dt=4.0 * orc.max_dt(wl.u0))
+    chk = s.check()
+    assert chk["cfl_violated"] == 1 and chk["status"] == -4
+    s.close()
