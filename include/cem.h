@@ -149,6 +149,11 @@ cem_status cem_step(cem_ctx* ctx, double dt, double cfl);
 /* Enables (default) or disables graph replay in cem_step. */
 cem_status cem_set_graphs(cem_ctx* ctx, int enable);
 
+/* Call after writing the bound state u by other means than
+ * cem_upload_state or the stage calls (e.g. a device copy): derived per-node
+ * data kept between stages (nodal fluxes of the KPP flux) is rebuilt. */
+cem_status cem_state_modified(cem_ctx* ctx);
+
 /* Synchronous: reads the step size, CFL flag and clamp/violation counters
  * accumulated since the last cem_reset_counters, and the state invariants.
  * Returns CEM_ECFL or CEM_EIDP when the corresponding check failed. */
@@ -166,10 +171,11 @@ size_t cem_tap_size(const cem_ctx* ctx, int tap);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch of the kernels selected by mask (bit k = kernel id k):
- *   0 projected-gradient line operator   1 element pass 1 (sensor, residual,
- *   facets)   2 (unused)   3 residual gather (fused with the first mass-solve
- *   pass on long x-lines)   4 mass-solve line operator   5 element pass 2
- *   (limiters, contributions)   6 node update (with the time-step reduction).
+ *   0 projected-gradient line operator   1 element pass 1 (sensor,
+ *   residual, facets)   2 (unused)   3 residual
+ *   gather (fused with the first mass-solve pass on long x-lines)   4 mass-
+ *   solve line operator   5 element pass 2 (limiters, contributions)   6 node
+ *   update (with the time-step reduction).
  * cem_kernel_times is synchronous: it returns the summed milliseconds and
  * launch counts per id since the previous call (arrays of n <= 7 entries)
  * and clears them. */

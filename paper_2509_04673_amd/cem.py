@@ -74,6 +74,7 @@ _SIGS = [
     ("cem_debug_tap", ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_size_t]),
     ("cem_tap_size", ctypes.c_size_t, [_P, ctypes.c_int]),
     ("cem_set_graphs", ctypes.c_int, [_P, ctypes.c_int]),
+    ("cem_state_modified", ctypes.c_int, [_P]),
     ("cem_set_timing", ctypes.c_int, [_P, ctypes.c_uint]),
     ("cem_kernel_times", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
@@ -184,6 +185,10 @@ KERNELS = ["grad_line", "elem1", "unused", "gather_r", "mass_line", "elem2", "up
 
 def cem_set_graphs(ctx, enable):
     _check(lib().cem_set_graphs(ctx, int(bool(enable))))
+
+
+def cem_state_modified(ctx):
+    _check(lib().cem_state_modified(ctx))
 
 
 def cem_set_timing(ctx, mask):

@@ -46,7 +46,7 @@ struct cem_ctx {
   std::vector<double> tabblob;     // all tables, packed
   size_t off_vqf = 0, off_dqw = 0, off_mass = 0, off_ksum = 0, off_ctg = 0, off_qf = 0,
          off_ext = 0, off_facem = 0, off_kg[3] = {0, 0, 0}, off_km[3] = {0, 0, 0},
-         off_kgf[3] = {0, 0, 0}, off_kmf[3] = {0, 0, 0};
+         off_kgf[3] = {0, 0, 0}, off_kmf[3] = {0, 0, 0}, off_sf = 0;
   // bound memory
   double* u = nullptr;
   double* u0 = nullptr;
@@ -54,7 +54,8 @@ struct cem_ctx {
   size_t ws_need = 0;
   // workspace carve-up (byte offsets)
   size_t o_g, o_r, o_udot, o_tmp, o_tmp2, o_relem, o_ue, o_ubarL, o_ubar, o_fahi, o_dte, o_gam,
-      o_nu, o_beta, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart;
+      o_nu, o_beta, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart, o_fnode;
+  bool fnode_valid = false;   // nodal fluxes match the bound state
   int upd_blocks = 0, inv_blocks = 0;
   bool bound = false, bounds_set = false;
   // whole-step HIP graph (captured on a private stream, launched on stream)
@@ -115,6 +116,23 @@ void pack_tables(cem_ctx* c) {
   c->off_qf = put(T.qf);
   c->off_ext = put(T.ext);
   c->off_facem = put(T.facem);
+  {
+    // compact tables of the sum-factorised element kernels (SFLayout order)
+    std::vector<double> sf;
+    const int PP = P1 * P1;
+    auto app = [&](const std::vector<double>& v, int n) {
+      for (int i = 0; i < n; ++i) sf.push_back(i < (int)v.size() ? v[i] : 0.0);
+    };
+    app(T.vq, PP);
+    app(T.dq, PP);
+    app(T.wq, PP);
+    app(T.g1, PP);
+    app(T.k1, PP);
+    app(T.ct1, PP);
+    app(T.ext, 2 * PP);
+    app(T.qp, (int)T.qp.size());
+    c->off_sf = put(sf);
+  }
   for (int k = 0; k < D; ++k) {
     c->off_kg[k] = put(T.kgrad[k].w);
     c->off_km[k] = put(T.kmass[k].w);
@@ -184,6 +202,7 @@ StageArgs make_args(const cem_ctx* c) {
   a.tab.qf = tb + c->off_qf;
   a.tab.ext = tb + c->off_ext;
   a.tab.facem = tb + c->off_facem;
+  a.tab.sf = tb + c->off_sf;
   for (int k = 0; k < c->d; ++k) {
     a.tab.kgrad[k] = tb + c->off_kg[k];
     a.tab.kmass[k] = tb + c->off_km[k];
@@ -208,6 +227,7 @@ StageArgs make_args(const cem_ctx* c) {
   a.u0 = c->u0;
   a.uout = c->u;
   a.g = c->W<double>(c->o_g);
+  a.fnode = c->W<double>(c->o_fnode);
   a.r = c->W<double>(c->o_r);
   a.udot = c->W<double>(c->o_udot);
   a.relem = c->W<double>(c->o_relem);
@@ -241,13 +261,14 @@ hipEvent_t get_event(cem_ctx* c) {
 struct Timed {
   cem_ctx* c;
   int id;
+  hipStream_t st;
   hipEvent_t b = nullptr;
-  Timed(cem_ctx* c_, int id_) : c(c_), id(id_) {
+  Timed(cem_ctx* c_, int id_, hipStream_t st_ = nullptr) : c(c_), id(id_), st(st_ ? st_ : c_->stream) {
     if (c->timing_mask & (1u << id)) {
       hipEvent_t a = get_event(c);
       b = get_event(c);
       if (a && b) {
-        hipEventRecord(a, c->stream);
+        hipEventRecord(a, st);
         c->recs.push_back({id, a, b});
       } else {
         b = nullptr;
@@ -255,7 +276,7 @@ struct Timed {
     }
   }
   ~Timed() {
-    if (b) hipEventRecord(b, c->stream);
+    if (b) hipEventRecord(b, st);
   }
 };
 
@@ -325,6 +346,13 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   if (!layout_matches<D, P>(c)) return fail(CEM_EINVAL, "internal: table layout mismatch");
   constexpr int M = Phys<D, PH>::M;
   StageArgs a = make_args(c);
+  if constexpr (Phys<D, PH>::kNodal) {
+    if (!c->fnode_valid) {
+      hipLaunchKernelGGL((k_nodal_flux<D, PH>), dim3(nblocks(c->N, 256)), dim3(256), 0, c->stream, a);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  c->fnode_valid = true;    // the update at the end of the stage refreshes them
   const double rka[3] = {0.0, 0.75, 1.0 / 3.0}, rkb[3] = {1.0, 0.25, 2.0 / 3.0};
   a.rk_a = rka[stage];
   a.rk_b = rkb[stage];
@@ -338,9 +366,20 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     cem_status s = launch_line(c, c->u, a.g + (int64_t)k * M * c->N, k, true);
     if (s != CEM_OK) return s;
   }
+  // element pass: sensor, residual (with the stabilisation), facet data.
+  // (Running the g-independent part concurrently with the gradient passes on
+  // a second stream was measured slower on the 256^2 KPP mesh.)
   {
     Timed tm(c, 1);
-    hipLaunchKernelGGL((k_elem1<D, P, PH>), dim3(nblocks(c->E, 128)), dim3(128), (lds_bytes<D, P>()), c->stream, a);
+    if constexpr (D == 2) {
+      using TT = Tile2<P, M>;
+      const int nb = ((c->n[0] + TT::TEX - 1) / TT::TEX) * ((c->n[1] + TT::TEY - 1) / TT::TEY);
+      a.ndtpart = nb;
+      hipLaunchKernelGGL((k_elem1_tile<P, PH, true>), dim3(nb), dim3(128), TT::words * sizeof(double),
+                         c->stream, a);
+    } else {
+      hipLaunchKernelGGL((k_elem1<D, P, PH, true>), dim3(nblocks(c->E, 128)), dim3(128), 0, c->stream, a);
+    }
   }
   HIPCHK(hipGetLastError());
   // udot = M_C^{-1} r, one line pass per axis (Sec. 4.3, step 2); the
@@ -377,7 +416,7 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   HIPCHK(hipGetLastError());
   {
     Timed tm(c, 6);
-    hipLaunchKernelGGL((k_update<D, P, M, PH != EUL>), dim3(c->upd_blocks), dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL((k_update<D, P, PH>), dim3(c->upd_blocks), dim3(256), 0, c->stream, a);
   }
   HIPCHK(hipGetLastError());
   return CEM_OK;
@@ -482,6 +521,7 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
     return r;
   };
   c->o_g = take((size_t)d * mN);
+  c->o_fnode = take((size_t)d * mN);
   c->o_r = take(mN);
   c->o_udot = take(mN);
   c->o_tmp = take(mN);
@@ -496,7 +536,10 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->o_nu = take(E8);
   c->o_beta = take(E8);
   c->o_dtbuf = take(8 * 8);
-  c->o_dtpart = take((size_t)nblocks(c->E, 128) * 8);
+  // per-block dt_e minima: one-thread-per-element blocks or 2D element tiles
+  size_t ndtp = nblocks(c->E, 128);
+  if (d == 2) ndtp = std::max(ndtp, (size_t)((c->n[0] + 15) / 16) * (size_t)((c->n[1] + 7) / 8));
+  c->o_dtpart = take(ndtp * 8);
   c->upd_blocks = (int)nblocks(c->N, 256);
   c->o_counts = take((size_t)c->upd_blocks * 2 * sizeof(int));
   c->inv_blocks = 256;
@@ -534,6 +577,7 @@ cem_status cem_bind(cem_ctx* c, double* u, double* u_base, void* workspace, size
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(CEM_EINVAL, "workspace not 256-byte aligned");
   if (ws_bytes < c->ws_need) return fail(CEM_ENOMEM, "workspace too small");
   drop_graph(c);
+  c->fnode_valid = false;
   c->u = u;
   c->u0 = u_base;
   c->ws = static_cast<char*>(workspace);
@@ -546,6 +590,7 @@ cem_status cem_bind(cem_ctx* c, double* u, double* u_base, void* workspace, size
 
 cem_status cem_upload_state(cem_ctx* c, const double* host_u) {
   if (!c || !c->bound || !host_u) return fail(CEM_EINVAL, "context not bound / null");
+  c->fnode_valid = false;
   HIPCHK(hipMemcpyAsync(c->u, host_u, (size_t)c->m * c->N * 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return CEM_OK;
@@ -598,7 +643,9 @@ cem_status cem_step(cem_ctx* c, double dt, double cfl) {
   if (!c || !c->bound) return fail(CEM_EINVAL, "context not bound");
   if (!(dt > 0.0) && !(cfl > 0.0)) return fail(CEM_EINVAL, "need dt > 0 or cfl > 0");
   if (c->kind != CEM_EULER && !c->bounds_set) return fail(CEM_EINVAL, "scalar bounds not set");
-  if (!c->use_graphs || c->timing_mask) return step_direct(c, dt, cfl);
+  // direct launches with timing, without graphs, and whenever derived state
+  // (nodal fluxes) must be rebuilt first so that captures stay replayable
+  if (!c->use_graphs || c->timing_mask || !c->fnode_valid) return step_direct(c, dt, cfl);
   if (!c->graph || c->graph_dt != dt || c->graph_cfl != cfl) {
     // capture the three stages on the private stream, then replay the graph
     // on the caller's stream
@@ -626,6 +673,12 @@ cem_status cem_step(cem_ctx* c, double dt, double cfl) {
     c->graph_cfl = cfl;
   }
   HIPCHK(hipGraphLaunch(c->graph, c->stream));
+  return CEM_OK;
+}
+
+cem_status cem_state_modified(cem_ctx* c) {
+  if (!c) return fail(CEM_EINVAL, "null context");
+  c->fnode_valid = false;
   return CEM_OK;
 }
 

@@ -38,6 +38,7 @@ struct DevTabs {
   const double* qf;     // [1+2D][NL][NL]
   const double* ext;    // [2][P1][P1]
   const double* facem;  // [NF][NF]
+  const double* sf;     // compact tables of the sum-factorised kernels (SFLayout)
   const double* kgrad[3];
   const double* kmass[3];
   int gtaps[3], gfirst[3], mtaps[3], mfirst[3];
@@ -63,6 +64,16 @@ template <int D, int P> struct TabLayout {
   // the fully unrolled element code (measured: more spills than the scalar
   // path), so the element kernels read the tables through the scalar cache
   static constexpr bool lds = false;
+};
+
+// Compact tables of the sum-factorised element operators: 1D P1 x P1
+// matrices (Gauss values, derivatives, weights, mass, stiffness,
+// int B_a' B_b, the two extension maps) and the packed semi-norm form.
+template <int D, int P> struct SFLayout {
+  static constexpr int P1 = P + 1, PP = P1 * P1, NL = ipow(P1, D);
+  static constexpr int vq = 0, dq = PP, wq = 2 * PP, g = 3 * PP, k1 = 4 * PP, ct = 5 * PP;
+  static constexpr int ext = 6 * PP, qp = 8 * PP;
+  static constexpr int total = qp + NL * (NL + 1) / 2;
 };
 
 extern __shared__ double cem_smem[];
@@ -102,6 +113,7 @@ struct StageArgs {
   double* u0;           // step base u^n       [M][N]
   double* uout;         // stage output (may alias u: per-node read-then-write)
   double* g;            // [D][M][N] projected gradient
+  double* fnode;        // [D][M][N] nodal fluxes f_k(u_j) of the stage input (kNodal physics)
   double* r;            // [M][N] residual
   double* udot;         // [M][N]
   double* relem;        // [M][NL][E] element vectors (residual, then update)
@@ -128,8 +140,16 @@ struct StageArgs {
 // ---------------------------------------------------------------------------
 template <int D, int PH> struct Phys;
 
+// flux_all(u, f): all d directional fluxes f[k * M + c] at one state.
+// kNodal: the flux is expensive enough (transcendental) that its nodal
+// values f(u_j) are computed once per node and stage and stored.
 template <int D> struct Phys<D, ADV> {
   static constexpr int M = 1;
+  static constexpr bool kNodal = false;
+  __device__ static inline void flux_all(const double* u, double* f, const PhysParams& pp) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) f[k] = pp.vel[k] * u[0];
+  }
   __device__ static inline void flux(int k, const double* u, double* f, const PhysParams& pp) {
     f[0] = pp.vel[k] * u[0];
   }
@@ -141,6 +161,13 @@ template <int D> struct Phys<D, ADV> {
 
 template <int D> struct Phys<D, KPP> {
   static constexpr int M = 1;
+  static constexpr bool kNodal = true;
+  __device__ static inline void flux_all(const double* u, double* f, const PhysParams&) {
+    double s, c;
+    sincos(u[0], &s, &c);
+    f[0] = s;
+    f[1] = c;
+  }
   __device__ static inline void flux(int k, const double* u, double* f, const PhysParams&) {
     f[0] = (k == 0) ? sin(u[0]) : cos(u[0]);
   }
@@ -153,6 +180,7 @@ template <int D> struct Phys<D, KPP> {
 
 template <int D> struct Phys<D, EUL> {
   static constexpr int M = D + 2;
+  static constexpr bool kNodal = false;
   __device__ static inline double pressure(const double* u, const PhysParams& pp) {
     double m2 = 0.0;
 #pragma unroll
@@ -166,6 +194,10 @@ template <int D> struct Phys<D, EUL> {
 #pragma unroll
     for (int j = 0; j < D; ++j) f[1 + j] = u[1 + j] * vk + (j == k ? p : 0.0);
     f[D + 1] = vk * (u[D + 1] + p);
+  }
+  __device__ static inline void flux_all(const double* u, double* f, const PhysParams& pp) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) flux(k, u, f + k * M, pp);
   }
   __device__ static inline double node_speed(const double* u, const PhysParams& pp) {
     double v2 = 0.0;
@@ -520,27 +552,167 @@ __device__ inline void block_min_dt(double* part, double v) {
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-template <int D, int P, int PH, class TR>
-__device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, int64_t e) {
+
+// ---------------------------------------------------------------------------
+// sum-factorised element operators
+// ---------------------------------------------------------------------------
+// y = (A along axis K) x with the P1 x P1 table A at offset ao:
+// y[i] = sum_b A[i_K][b] x[i | i_K = b]  (TRN: A[b][i_K])
+template <int D, int P, int K, class TB>
+__device__ __forceinline__ void ax1(const TB& T, int ao, bool trn, const double* x, double* y) {
+  constexpr int P1 = P + 1, NL = ipow(P1, D), ST = ipow(P1, K);
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int ai = (i / ST) % P1, i0 = i - ai * ST;
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < P1; ++b) s += T(ao + (trn ? b * P1 + ai : ai * P1 + b)) * x[i0 + b * ST];
+    y[i] = s;
+  }
+}
+
+template <int D, int P, class TB>
+__device__ __forceinline__ void ax(int k, const TB& T, int ao, bool trn, const double* x, double* y) {
+  if (k == 0) ax1<D, P, 0>(T, ao, trn, x, y);
+  else if constexpr (D > 1) {
+    if (k == 1) ax1<D, P, 1>(T, ao, trn, x, y);
+    else if constexpr (D > 2) ax1<D, P, 2>(T, ao, trn, x, y);
+  }
+}
+
+// y = (A_{D-1} (x) ... (x) A_0) x with table offsets mo[j] along axis j
+template <int D, int P, class TB>
+__device__ __forceinline__ void tensor_apply(const TB& T, const int* mo, bool trn, const double* x, double* y) {
+  constexpr int NL = ipow(P + 1, D);
+  if constexpr (D == 0) {
+    y[0] = x[0];
+  } else {
+    double t[NL];
+    ax<D, P>(0, T, mo[0], trn, x, D == 1 ? y : t);
+    if constexpr (D == 2) ax<D, P>(1, T, mo[1], trn, t, y);
+    if constexpr (D == 3) {
+      double t2[NL];
+      ax<D, P>(1, T, mo[1], trn, t, t2);
+      ax<D, P>(2, T, mo[2], trn, t2, y);
+    }
+  }
+}
+
+// x^T Q x with Q packed as upper-triangle rows (off-diagonals doubled)
+template <int NL, class TB>
+__device__ __forceinline__ double qsym(const TB& T, int off, const double* x) {
+  double s = 0.0;
+  int p = off;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    double t = T(p++) * x[i];
+#pragma unroll
+    for (int j = i + 1; j < NL; ++j) t += T(p++) * x[j];
+    s += x[i] * t;
+  }
+  return s;
+}
+
+// Node access of the element passes.  GlobalNodes gathers straight from the
+// nodal arrays; TileNodes2 reads a block's LDS tile (2D): u with a
+// one-element halo (the WENO candidates and facet neighbours) and, when it
+// fits, g on the block's own nodes.
+template <int D, int P, int M> struct GlobalNodes {
+  const StageArgs* a;
+  int ei[3];
+  int64_t off[D][P + 1];
+  __device__ __forceinline__ GlobalNodes(const StageArgs& a_, int64_t e) : a(&a_) {
+    elem_coords(e, a_.mesh, ei);
+#pragma unroll
+    for (int k = 0; k < D; ++k) axis_offsets<P>(ei[k], k, a_.mesh, off[k]);
+  }
+  __device__ __forceinline__ void load_own(double (*U)[ipow(P + 1, D)]) const {
+    constexpr int NL = ipow(P + 1, D);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int64_t nd = local_node<D, P>(j, off);
+#pragma unroll
+      for (int c = 0; c < M; ++c) U[c][j] = a->u[c * a->mesh.N + nd];
+    }
+  }
+  // neighbour l = 2k + (s > 0) across the facet normal to axis k
+  __device__ __forceinline__ void load_nbr(int c, int l, double* cn) const {
+    constexpr int NL = ipow(P + 1, D);
+    const int k = l / 2, s = (l % 2) ? 1 : -1;
+    int64_t offn[D][P + 1];
+#pragma unroll
+    for (int kk = 0; kk < D; ++kk) axis_offsets<P>(ei[kk] + (kk == k ? s : 0), kk, a->mesh, offn[kk]);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) cn[j] = a->u[c * a->mesh.N + local_node<D, P>(j, offn)];
+  }
+  __device__ __forceinline__ int64_t own_node(int j) const { return local_node<D, P>(j, off); }
+  __device__ __forceinline__ void load_grad(int c, double (*gk)[ipow(P + 1, D)]) const {
+    constexpr int NL = ipow(P + 1, D);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int64_t nd = local_node<D, P>(j, off);
+#pragma unroll
+      for (int k = 0; k < D; ++k) gk[k][j] = a->g[((int64_t)k * M + c) * a->mesh.N + nd];
+    }
+  }
+};
+
+template <int P, int M> struct Tile2 {
+  static constexpr int TEX = 16, TEY = 8;                       // elements per block
+  static constexpr int NX = P * (TEX + 2) + 1, NY = P * (TEY + 2) + 1, NXY = NX * NY;
+  static constexpr int GX = P * TEX + 1, GY = P * TEY + 1, GXY = GX * GY;
+  static constexpr bool stage_g = M * NXY + 2 * M * GXY <= 4096;
+  static constexpr int words = M * NXY + (stage_g ? 2 * M * GXY : 0);
+};
+
+template <int P, int M> struct TileNodes2 {
+  using TT = Tile2<P, M>;
+  static constexpr int NL = (P + 1) * (P + 1);
+  const StageArgs* a;
+  int base, gbase;          // tile offsets of local node (0, 0)
+  GlobalNodes<2, P, M> gl;  // fallback for g when it is not staged
+  __device__ __forceinline__ TileNodes2(const StageArgs& a_, int64_t e, int tx, int ty)
+      : a(&a_), gl(a_, e) {
+    base = P * (ty + 1) * TT::NX + P * (tx + 1);
+    gbase = P * ty * TT::GX + P * tx;
+  }
+  __device__ __forceinline__ int64_t own_node(int j) const { return gl.own_node(j); }
+  __device__ __forceinline__ void load_own(double (*U)[NL]) const {
+#pragma unroll
+    for (int j = 0; j < NL; ++j)
+#pragma unroll
+      for (int c = 0; c < M; ++c) U[c][j] = cem_smem[c * TT::NXY + base + (j / (P + 1)) * TT::NX + j % (P + 1)];
+  }
+  __device__ __forceinline__ void load_nbr(int c, int l, double* cn) const {
+    const int k = l / 2, s = (l % 2) ? 1 : -1;
+    const int b = base + s * P * (k == 0 ? 1 : TT::NX);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) cn[j] = cem_smem[c * TT::NXY + b + (j / (P + 1)) * TT::NX + j % (P + 1)];
+  }
+  __device__ __forceinline__ void load_grad(int c, double (*gk)[NL]) const {
+    if constexpr (TT::stage_g) {
+      const double* gs = cem_smem + M * TT::NXY;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int j = 0; j < NL; ++j)
+          gk[k][j] = gs[(k * M + c) * TT::GXY + gbase + (j / (P + 1)) * TT::GX + j % (P + 1)];
+    } else {
+      gl.load_grad(c, gk);
+    }
+  }
+};
+
+template <int D, int P, int PH, bool WS, class TR, class NS>
+__device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, int64_t e, const NS& ns) {
   using PHY = Phys<D, PH>;
-  using TL = TabLayout<D, P>;
+  using SF = SFLayout<D, P>;
   constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NF = NL / P1;
   const MeshArgs& ms = a.mesh;
-  const int64_t N = ms.N, E = ms.E;
+  const int64_t E = ms.E;
   const double h = ms.h;
-  int ei[3];
-  elem_coords(e, ms, ei);
-  int64_t off[D][P1];
-#pragma unroll
-  for (int k = 0; k < D; ++k) axis_offsets<P>(ei[k], k, ms, off[k]);
-
   double U[M][NL];
-#pragma unroll
-  for (int j = 0; j < NL; ++j) {
-    const int64_t nd = local_node<D, P>(j, off);
-#pragma unroll
-    for (int c = 0; c < M; ++c) U[c][j] = a.u[c * N + nd];
-  }
+  ns.load_own(U);
   double ue[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) {
@@ -551,8 +723,10 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
   }
 
   // ---- WENO sensor (Sec. 2.2, eqs. 7-8), per component; systems take the
-  // minimum.  Semi-norms are quadratic forms on coefficients shifted by their
-  // first entry, so exactly constant polynomials give exactly zero.
+  // minimum.  Candidates are extended into K_e by the blossom maps; every
+  // semi-norm is the same packed quadratic form on coefficients shifted by
+  // their first entry (exactly zero for constant polynomials).
+  constexpr bool keepx = 2 * D * NL <= 64;
   double nbr_mean[2 * D][M];
   double gmin = 1.0;
   for (int c = 0; c < M; ++c) {
@@ -560,24 +734,24 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
 #pragma unroll
     for (int j = 0; j < NL; ++j) ct[j] = U[c][j] - U[c][0];
     double beta[1 + 2 * D];
-    beta[0] = qform<NL>(T, TL::qf, ct);
+    beta[0] = qsym<NL>(T, SF::qp, ct);
+    double X[keepx ? 2 * D : 1][NL];
 #pragma unroll
     for (int l = 0; l < 2 * D; ++l) {
-      const int k = l / 2, s = (l % 2) ? 1 : -1;
-      int64_t offn[D][P1];
+      double cn[NL], sum = 0.0, xe[NL];
+      ns.load_nbr(c, l, cn);
 #pragma unroll
-      for (int kk = 0; kk < D; ++kk) axis_offsets<P>(ei[kk] + (kk == k ? s : 0), kk, ms, offn[kk]);
-      double cn[NL], sum = 0.0;
-#pragma unroll
-      for (int j = 0; j < NL; ++j) {
-        cn[j] = a.u[c * N + local_node<D, P>(j, offn)];
-        sum += cn[j];
-      }
+      for (int j = 0; j < NL; ++j) sum += cn[j];
       nbr_mean[l][c] = sum * (1.0 / NL);
       const double c0 = cn[0];
 #pragma unroll
       for (int j = 0; j < NL; ++j) cn[j] -= c0;
-      beta[1 + l] = qform<NL>(T, TL::qf + (1 + l) * NL * NL, cn);
+      ax<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cn, xe);
+      beta[1 + l] = qsym<NL>(T, SF::qp, xe);
+      if constexpr (keepx) {
+#pragma unroll
+        for (int j = 0; j < NL; ++j) X[l][j] = xe[j];
+      }
     }
     if (a.gamma_mode != 0) continue;
     const double wl0 = 1.0 - 2 * D * a.w_lin;
@@ -588,38 +762,31 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
       wt[l] = (l == 0 ? wl0 : a.w_lin) / (nr + a.eps);
       wsum += wt[l];
     }
+    const double iws = 1.0 / wsum;
     double w[NL];
 #pragma unroll
     for (int j = 0; j < NL; ++j) w[j] = 0.0;
 #pragma unroll
     for (int l = 0; l < 2 * D; ++l) {
-      const int k = l / 2, s = (l % 2) ? 1 : -1;
-      const double om = wt[1 + l] / wsum;
-      int64_t offn[D][P1];
+      const double om = wt[1 + l] * iws;
+      double xe[NL];
+      if constexpr (keepx) {
 #pragma unroll
-      for (int kk = 0; kk < D; ++kk) axis_offsets<P>(ei[kk] + (kk == k ? s : 0), kk, ms, offn[kk]);
-      double cn[NL];
+        for (int j = 0; j < NL; ++j) xe[j] = X[l][j];
+      } else {
+        double cn[NL];
+        ns.load_nbr(c, l, cn);
+        const double c0 = cn[0];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) cn[j] = a.u[c * N + local_node<D, P>(j, offn)];
-      const double c0 = cn[0];
-#pragma unroll
-      for (int j = 0; j < NL; ++j) cn[j] -= c0;
-      const int E1 = TL::ext + (s > 0 ? P1 * P1 : 0);
-#pragma unroll
-      for (int i = 0; i < NL; ++i) {
-        const int ai = dig(i, k, P1);
-        double ex = 0.0;
-#pragma unroll
-        for (int b = 0; b < P1; ++b) {
-          const int j = i + (b - ai) * ipow(P1, k);
-          ex += T(E1 + ai * P1 + b) * cn[j];
-        }
-        w[i] += om * (ct[i] - ex);
+        for (int j = 0; j < NL; ++j) cn[j] -= c0;
+        ax<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cn, xe);
       }
+#pragma unroll
+      for (int i = 0; i < NL; ++i) w[i] += om * (ct[i] - xe[i]);
     }
     // the ratio of eq. (7) is 0/0 on constant elements; it is regularised
     // with the weights' epsilon: ||u - u*|| / (||u||^2 + eps)^(1/2)
-    const double dev = sqrt(fmax(qform<NL>(T, TL::qf, w), 0.0));
+    const double dev = sqrt(fmax(qsym<NL>(T, SF::qp, w), 0.0));
     const double ratio = fmin(1.0, dev / sqrt(fmax(beta[0], 0.0) + a.eps));
     const double gc = 1.0 - (a.q == 1.0 ? ratio : pow(ratio, a.q));
     gmin = fmin(gmin, gc);
@@ -637,58 +804,101 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
   }
   const double nu = lam * h / (2.0 * P);
 
-  // ---- element residual R_i = int grad phi_i . f(u_h) - s_h^e(phi_i, u_h)
-  double R[M][NL];
-#pragma unroll
-  for (int c = 0; c < M; ++c)
-#pragma unroll
-    for (int i = 0; i < NL; ++i) R[c][i] = 0.0;
+  // ---- element residual R_i = int grad phi_i . f(u_h) - s_h^e(phi_i, u_h),
+  // sum-factorised: interpolate to the Gauss points, evaluate the flux, test
+  // with the gradients (transposed 1D tables)
   double hpow = 1.0;
 #pragma unroll
   for (int k = 0; k < D - 1; ++k) hpow *= h;   // h^{D-1}
+  double R[M][NL];
+  {
+    double uq[M][NL];
+    int mv[3] = {SF::vq, SF::vq, SF::vq};
 #pragma unroll
-  for (int q = 0; q < NL; ++q) {
-    double uq[M];
+    for (int c = 0; c < M; ++c) tensor_apply<D, P>(T, mv, false, U[c], uq[c]);
+    double wq[NL];
 #pragma unroll
-    for (int c = 0; c < M; ++c) {
-      double s = 0.0;
+    for (int q = 0; q < NL; ++q) {
+      double wv = 1.0;
 #pragma unroll
-      for (int j = 0; j < NL; ++j) s += T(TL::vqf + q * NL + j) * U[c][j];
-      uq[c] = s;
+      for (int j = 0; j < D; ++j) wv *= T(SF::wq + dig(q, j, P1));
+      wq[q] = wv;
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+      for (int i = 0; i < NL; ++i) R[c][i] = 0.0;
+    // all directional fluxes at once when they are cheap to keep (scalar
+    // problems; one sincos per point for KPP), else one direction at a time
+    constexpr bool allk = (M == 1);
+    double FA[allk ? D : 1][NL];
+    if constexpr (allk) {
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        double fv[D];
+        PHY::flux_all(&uq[0][q], fv, a.ph);
+#pragma unroll
+        for (int kk = 0; kk < D; ++kk) FA[kk][q] = wq[q] * fv[kk];
+      }
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      double f[M];
-      PHY::flux(k, uq, f, a.ph);
-      const int dw = TL::dqw + (k * NL + q) * NL;
+      double F[M][NL];
 #pragma unroll
-      for (int i = 0; i < NL; ++i) {
-        const double wv = T(dw + i);
+      for (int q = 0; q < NL; ++q) {
+        if constexpr (allk) {
+          F[0][q] = FA[k][q];
+        } else {
+          double uv[M], fv[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c) R[c][i] += wv * f[c];
+          for (int c = 0; c < M; ++c) uv[c] = uq[c][q];
+          PHY::flux(k, uv, fv, a.ph);
+#pragma unroll
+          for (int c = 0; c < M; ++c) F[c][q] = wq[q] * fv[c];
+        }
+      }
+      int mt[3] = {SF::vq, SF::vq, SF::vq};
+      mt[k] = SF::dq;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        double t[NL];
+        tensor_apply<D, P>(T, mt, true, F[c], t);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) R[c][i] += t[i];
       }
     }
   }
+  if constexpr (!WS) {
+    // residual without the stabilisation term
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+      for (int i = 0; i < NL; ++i) a.relem[((int64_t)c * NL + i) * E + e] = hpow * R[c][i];
+  }
   const double sa = nu * hpow / h, sg = nu * gam * hpow;   // nu h^{D-2}, nu gamma h^{D-1}
 #pragma unroll
-  for (int c = 0; c < M; ++c) {
+  for (int c = 0; c < (WS ? M : 0); ++c) {
     double gk[D][NL];
+    ns.load_grad(c, gk);
+    double s1[NL], s2[NL];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) {
-      const int64_t nd = local_node<D, P>(j, off);
+    for (int i = 0; i < NL; ++i) s1[i] = s2[i] = 0.0;
 #pragma unroll
-      for (int k = 0; k < D; ++k) gk[k][j] = a.g[((int64_t)k * M + c) * N + nd];
+    for (int k = 0; k < D; ++k) {
+      int ms1[3] = {SF::g, SF::g, SF::g}, ms2[3] = {SF::g, SF::g, SF::g};
+      ms1[k] = SF::k1;
+      ms2[k] = SF::ct;
+      double t[NL];
+      tensor_apply<D, P>(T, ms1, false, U[c], t);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) s1[i] += t[i];
+      tensor_apply<D, P>(T, ms2, false, gk[k], t);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) s2[i] += t[i];
     }
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int j = 0; j < NL; ++j) s1 += T(TL::ksum + i * NL + j) * U[c][j];
-#pragma unroll
-      for (int k = 0; k < D; ++k)
-#pragma unroll
-        for (int j = 0; j < NL; ++j) s2 += T(TL::ctg + (k * NL + i) * NL + j) * gk[k][j];
-      R[c][i] = hpow * R[c][i] - (sa * s1 - sg * s2);
+      R[c][i] = hpow * R[c][i] - (sa * s1[i] - sg * s2[i]);
       a.relem[((int64_t)c * NL + i) * E + e] = R[c][i];
     }
   }
@@ -698,29 +908,41 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
   double lamsum = 0.0, fLsum[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) fLsum[c] = 0.0;
+  double foa[D * M];
+  PHY::flux_all(ue, foa, a.ph);          // fluxes of the own average
 #pragma unroll
   for (int k = 0; k < D; ++k) {
+    const double* fo = foa + k * M;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const double* uL = side ? ue : nbr_mean[2 * k];
-      const double* uR = side ? nbr_mean[2 * k + 1] : ue;
+      const double* un = nbr_mean[2 * k + side];
+      double fn[M];
+      PHY::flux(k, un, fn, a.ph);
+      const double* uL = side ? ue : un;
+      const double* uR = side ? un : ue;
+      const double* fl = side ? fo : fn;
+      const double* fr = side ? fn : fo;
       double fH[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) fH[c] = 0.0;
 #pragma unroll
       for (int j = 0; j < NL; ++j) {
         if (dig(j, k, P1) != (side ? P : 0)) continue;
-        double uj[M], fj[M];
+        double fj[M];
+        if constexpr (PHY::kNodal) {
+          const int64_t nd = ns.own_node(j);
 #pragma unroll
-        for (int c = 0; c < M; ++c) uj[c] = U[c][j];
-        PHY::flux(k, uj, fj, a.ph);
+          for (int c = 0; c < M; ++c) fj[c] = a.fnode[((int64_t)k * M + c) * ms.N + nd];
+        } else {
+          double uj[M];
+#pragma unroll
+          for (int c = 0; c < M; ++c) uj[c] = U[c][j];
+          PHY::flux(k, uj, fj, a.ph);
+        }
 #pragma unroll
         for (int c = 0; c < M; ++c) fH[c] += fj[c];
       }
       const double lm = PHY::riemann_speed(uL, uR, k, a.ph);
-      double fl[M], fr[M];
-      PHY::flux(k, uL, fl, a.ph);
-      PHY::flux(k, uR, fr, a.ph);
       lamsum += lm;
 #pragma unroll
       for (int c = 0; c < M; ++c) {
@@ -742,12 +964,50 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
   return dt_e;
 }
 
-template <int D, int P, int PH>
+template <int D, int P, int PH, bool WS>
 __global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
-  const auto T = stage_tables<D, P>(a.tab.vqf);
+  const TabRef<false> T{a.tab.sf};
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double dt_e = 1.0e300;
-  if (e < a.mesh.E) dt_e = elem1_body<D, P, PH>(a, T, e);
+  if (e < a.mesh.E) dt_e = elem1_body<D, P, PH, WS>(a, T, e, GlobalNodes<D, P, Phys<D, PH>::M>(a, e));
+  block_min_dt(a.dtpart, dt_e);     // every thread of the block reaches this
+}
+
+// 2D element pass on a 16 x 8 element tile: the block first stages the
+// tile's nodes (one-element halo) and, when it fits, g in LDS.
+template <int P, int PH, bool WS>
+__global__ void __launch_bounds__(128) k_elem1_tile(StageArgs a) {
+  constexpr int M = Phys<2, PH>::M;
+  using TT = Tile2<P, M>;
+  const TabRef<false> T{a.tab.sf};
+  const MeshArgs& ms = a.mesh;
+  const int nbx = (ms.n[0] + TT::TEX - 1) / TT::TEX;
+  const int ex0 = (blockIdx.x % nbx) * TT::TEX, ey0 = (blockIdx.x / nbx) * TT::TEY;
+  const int L0 = ms.L[0], L1 = ms.L[1];
+  int X0 = P * (ex0 - 1), Y0 = P * (ey0 - 1);
+  if (X0 < 0) X0 += L0;
+  if (Y0 < 0) Y0 += L1;
+  for (int q = threadIdx.x; q < M * TT::NXY; q += blockDim.x) {
+    const int c = q / TT::NXY, r = q - c * TT::NXY, iy = r / TT::NX, ix = r - iy * TT::NX;
+    const int gx = (X0 + ix) % L0, gy = (Y0 + iy) % L1;
+    cem_smem[q] = a.u[c * ms.N + gx + (int64_t)L0 * gy];
+  }
+  if constexpr (TT::stage_g) {
+    double* gs = cem_smem + M * TT::NXY;
+    for (int q = threadIdx.x; q < 2 * M * TT::GXY; q += blockDim.x) {
+      const int kc = q / TT::GXY, r = q - kc * TT::GXY, iy = r / TT::GX, ix = r - iy * TT::GX;
+      const int gx = (P * ex0 + ix) % L0, gy = (P * ey0 + iy) % L1;
+      gs[q] = a.g[(int64_t)kc * ms.N + gx + (int64_t)L0 * gy];
+    }
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % TT::TEX, ty = threadIdx.x / TT::TEX;
+  const int ex = ex0 + tx, ey = ey0 + ty;
+  double dt_e = 1.0e300;
+  if (ex < ms.n[0] && ey < ms.n[1]) {
+    const int64_t e = ex + (int64_t)ms.n[0] * ey;
+    dt_e = elem1_body<2, P, PH, WS>(a, T, e, TileNodes2<P, M>(a, e, tx, ty));
+  }
   block_min_dt(a.dtpart, dt_e);     // every thread of the block reaches this
 }
 
@@ -802,10 +1062,10 @@ __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
   using PHY = Phys<D, PH>;
   using TL = TabLayout<D, P>;
   constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NF = NL / P1;
-  const auto T = stage_tables<D, P>(a.tab.vqf);
+  const TabRef<false> T{a.tab.sf};
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const MeshArgs& ms = a.mesh;
-  if (e >= ms.E) return;       // no barrier below this point
+  if (e >= ms.E) return;
   const int64_t N = ms.N, E = ms.E;
   const double h = ms.h;
   int ei[3];
@@ -851,7 +1111,9 @@ __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
   }
 
   // ---- boundary integral B_i = int_{dK} phi_i f_h . n (so that
-  // int grad phi_i . f_h + int phi_i div f_h = B_i) and F^e = sum_i B_i
+  // int grad phi_i . f_h + int phi_i div f_h = B_i) and F^e = sum_i B_i:
+  // on each facet the (D-1)-dimensional Gram of the facet nodes
+  using SF = SFLayout<D, P>;
   double hpow = 1.0;
 #pragma unroll
   for (int k = 0; k < D - 1; ++k) hpow *= h;
@@ -866,31 +1128,35 @@ __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
     for (int side = 0; side < 2; ++side) {
       const int av = side ? P : 0;
       const double sg = side ? hpow : -hpow;
-      double fn[M][NF];
+      double fn[M][NF > 0 ? NF : 1];
 #pragma unroll
       for (int j = 0; j < NL; ++j) {
         if (dig(j, k, P1) != av) continue;
-        // facet-local id: drop digit k
-        const int lo = j % ipow(P1, k), hi = j / ipow(P1, k + 1);
-        const int fj = lo + hi * ipow(P1, k);
-        double uj[M], fv[M];
+        const int fj = j % ipow(P1, k) + (j / ipow(P1, k + 1)) * ipow(P1, k);   // drop digit k
+        double fv[M];
+        if constexpr (PHY::kNodal) {
+          const int64_t nd = local_node<D, P>(j, off);
 #pragma unroll
-        for (int c = 0; c < M; ++c) uj[c] = U[c][j];
-        PHY::flux(k, uj, fv, a.ph);
+          for (int c = 0; c < M; ++c) fv[c] = a.fnode[((int64_t)k * M + c) * N + nd];
+        } else {
+          double uj[M];
+#pragma unroll
+          for (int c = 0; c < M; ++c) uj[c] = U[c][j];
+          PHY::flux(k, uj, fv, a.ph);
+        }
 #pragma unroll
         for (int c = 0; c < M; ++c) fn[c][fj] = fv[c];
       }
+      const int mg[3] = {SF::g, SF::g, SF::g};
 #pragma unroll
-      for (int i = 0; i < NL; ++i) {
-        if (dig(i, k, P1) != av) continue;
-        const int lo = i % ipow(P1, k), hi = i / ipow(P1, k + 1);
-        const int fi = lo + hi * ipow(P1, k);
+      for (int c = 0; c < M; ++c) {
+        double t[NF > 0 ? NF : 1];
+        tensor_apply<D - 1, P>(T, mg, false, fn[c], t);
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-          double s = 0.0;
-#pragma unroll
-          for (int fj = 0; fj < NF; ++fj) s += T(TL::facem + fi * NF + fj) * fn[c][fj];
-          f[c][i] += sg * s;
+        for (int i = 0; i < NL; ++i) {
+          if (dig(i, k, P1) != av) continue;
+          const int fi = i % ipow(P1, k) + (i / ipow(P1, k + 1)) * ipow(P1, k);
+          f[c][i] += sg * t[fi];
         }
       }
     }
@@ -903,17 +1169,16 @@ __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
     double Fe = 0.0;
 #pragma unroll
     for (int i = 0; i < NL; ++i) Fe += f[c][i];
-    double ud[NL];
+    double ud[NL], mu[NL];
 #pragma unroll
     for (int j = 0; j < NL; ++j) ud[j] = a.udot[c * N + local_node<D, P>(j, off)];
+    const int mg[3] = {SF::g, SF::g, SF::g};
+    tensor_apply<D, P>(T, mg, false, ud, mu);
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      double t = 0.0;
-#pragma unroll
-      for (int j = 0; j < NL; ++j) t += T(TL::mass + i * NL + j) * ud[j];
-      const double T = hd * t - mloc * ud[i];
+      const double Tc = hd * mu[i] - mloc * ud[i];
       const double R = a.relem[((int64_t)c * NL + i) * E + e];
-      f[c][i] = mloc * (U[c][i] - uec[c]) + dt_e * (R - f[c][i] + Fe * (1.0 / NL) - T);
+      f[c][i] = mloc * (U[c][i] - uec[c]) + dt_e * (R - f[c][i] + Fe * (1.0 / NL) - Tc);
     }
   }
 
@@ -1042,8 +1307,10 @@ __device__ inline double stage_dt(const StageArgs& a) {
   return dt;
 }
 
-template <int D, int P, int M, bool SCALAR>
+template <int D, int P, int PH>
 __global__ void __launch_bounds__(256) k_update(StageArgs a) {
+  constexpr int M = Phys<D, PH>::M;
+  constexpr bool SCALAR = PH != EUL;
   constexpr int NL = ipow(P + 1, D);
   __shared__ int red[2][256];
   const double dt = stage_dt(a);          // every thread of the block
@@ -1058,6 +1325,7 @@ __global__ void __launch_bounds__(256) k_update(StageArgs a) {
 #pragma unroll
     for (int k = 0; k < D; ++k) hd *= a.mesh.h;
     const double mi = nrec * (hd * (1.0 / NL));
+    double vout[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
       double s = 0.0;
@@ -1076,6 +1344,14 @@ __global__ void __launch_bounds__(256) k_update(StageArgs a) {
         }
       }
       a.uout[c * N + i] = v;
+      vout[c] = v;
+    }
+    if constexpr (Phys<D, PH>::kNodal) {
+      // nodal fluxes of the new state, read by the next stage's element passes
+      double f[D * M];
+      Phys<D, PH>::flux_all(vout, f, a.ph);
+#pragma unroll
+      for (int q = 0; q < D * M; ++q) a.fnode[q * N + i] = f[q];
     }
   }
   red[0][threadIdx.x] = nclamp;
@@ -1092,6 +1368,21 @@ __global__ void __launch_bounds__(256) k_update(StageArgs a) {
     a.counts[2 * blockIdx.x] += red[0][0];
     a.counts[2 * blockIdx.x + 1] += red[1][0];
   }
+}
+
+// nodal fluxes f_k(u_j) of the bound state (kNodal physics), used when the
+// state did not come from a stage update (upload, bind, direct stage calls)
+template <int D, int PH>
+__global__ void __launch_bounds__(256) k_nodal_flux(StageArgs a) {
+  constexpr int M = Phys<D, PH>::M;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.mesh.N) return;
+  double v[M], f[D * M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) v[c] = a.u[c * a.mesh.N + i];
+  Phys<D, PH>::flux_all(v, f, a.ph);
+#pragma unroll
+  for (int q = 0; q < D * M; ++q) a.fnode[q * a.mesh.N + i] = f[q];
 }
 
 // min_e dt_e from the per-block minima, global time step for the stage and

@@ -334,6 +334,20 @@ bool build_tables(int d, int p, double h, const int L[3], const int wfast[5], co
         }
     }
 
+  // 1D tables of the sum-factorised element operators
+  T.g1.assign(P1 * P1, 0.0);
+  T.k1.assign(P1 * P1, 0.0);
+  T.ct1.assign(P1 * P1, 0.0);
+  for (int a = 0; a < P1; ++a)
+    for (int b = 0; b < P1; ++b) {
+      T.g1[a * P1 + b] = (double)G1(a, b);
+      T.k1[a * P1 + b] = (double)K1(a, b);
+      T.ct1[a * P1 + b] = (double)CT1(a, b);
+    }
+  T.qp.clear();
+  for (int i = 0; i < nl; ++i)
+    for (int j = i; j < nl; ++j) T.qp.push_back((double)((j == i ? 1.0L : 2.0L) * Q[(size_t)i * nl + j]));
+
   // facet Gram over the D-1 tangential axes (facet-local lexicographic ids)
   T.facem.assign((size_t)nlf * nlf, 0.0);
   for (int i = 0; i < nlf; ++i)

@@ -37,6 +37,9 @@ struct HostTables {
   std::vector<double> qf;           // [1+2D][NL][NL] WENO semi-norm forms, symmetric
   std::vector<double> ext;          // [2][P1][P1] extension maps (low, high neighbour)
   std::vector<double> facem;        // [NLF][NLF] facet Gram over the other D-1 axes
+  std::vector<double> g1, k1, ct1;  // [P1][P1] 1D mass, stiffness, int B_a' B_b
+  std::vector<double> qp;           // packed upper triangle of the semi-norm form,
+                                    // row i: Q_ii, 2 Q_i,i+1, ..., 2 Q_i,NL-1
   LineKernel kgrad[3], kmass[3];    // per axis line operators (physical h)
 };
 
