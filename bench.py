@@ -9,10 +9,20 @@ sensor and residual, consistent-mass solve, facet fluxes with the flux
 limiter, element contributions with the slope limiter, assembly and the RK
 combination).  Inputs are resident in HBM when the timed region starts.
 
-Prints one JSON line with the throughput, a roofline record of the dominant
-kernel (HIP events on the library's stream around the dominant kernel in a pass of
-directly launched steps right after the graph-replayed timed region) and the
-float64 oracle timed on the host on a bounded sample of the same workload.
+Prints one JSON line with the throughput (HIP events around the
+graph-replayed timed region), a roofline record of the dominant kernel and
+the float64 oracle timed on the host on a bounded sample of the same
+workload.  The dominant kernel is the single-launch-per-stage kernel with the
+largest warm-up time; its average duration is measured in a pass of directly
+launched steps right after the timed region, each launch carrying HIP events
+that take the dispatch's own timestamps.  Its achieved rate is its
+algorithmic bytes (or flops, whichever bound is higher) per launch over that
+duration; `traffic` is the HBM bytes per launch from the committed rocprofv3
+counter summary of this workload, null when the kernel sources changed since.
+
+Profiling helpers: --copy-probe BYTES runs a plain device copy (calibration
+of the byte counters) and --summarize-profile DIR writes that summary from
+rocprofv3 CSV output.
 """
 import argparse
 import json
@@ -26,31 +36,183 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector peak
+COPY_PROBE_BYTES = 1 << 28     # plain copy used to calibrate the byte counters
 
 
-def kernel_model(name, wl, N, E, m):
-    """(bound, algorithmic units per launch, unit) of each kernel.
+FLUX_FLOPS = {"advection": 1, "kpp": 40, "euler": 30}   # per state and direction
 
-    Line operators read and write one nodal array: 16 m N bytes.  The gather
-    reads the element vectors and writes r; the update reads the element
-    vectors, u and u_base and writes u.  The element passes are priced by
-    the nodal and per-element arrays they must read and write."""
+
+def elem1_flops(d, p, m, kind):
+    """Float64 operations of the element pass per element (FMA = 2), by the
+    sum-factorised algorithm: cell average, WENO sensor (2d candidate
+    extensions and 2d + 2 packed quadratic forms), interpolation to the
+    (p+1)^d Gauss points, fluxes, gradient test, stabilisation (2 d^2
+    one-axis passes), facet fluxes; transcendental fluxes at a nominal 40."""
+    nl, p1 = (p + 1) ** d, p + 1
+    ax = 2 * nl * p1                       # one sum-factorised axis pass
+    qs = nl * (nl + 1)                     # one packed quadratic form
+    weno = m * (nl + qs + 2 * d * (2 * nl + p1 * 2 * nl + qs) + 4 * d * nl + qs + 6 * (2 * d + 1))
+    resid = m * (d * ax + d * d * ax) + nl * (d * FLUX_FLOPS[kind] + 2 * d) + m * (2 * d * d * ax + 4 * nl)
+    facets = 2 * d * (m * (nl // p1) + 10 * m + FLUX_FLOPS[kind])
+    return weno + resid + facets + m * nl
+
+
+def elem2_flops(d, p, m, kind):
+    """Float64 operations of the limiter / contribution pass per element:
+    flux limiter on 2d facets, boundary integral (2d facet Gram passes),
+    consistent-mass term (d axis passes), contributions, slope limiter."""
+    nl, p1 = (p + 1) ** d, p + 1
+    nf = nl // p1
+    return (2 * d * m * 12 + 2 * d * m * 2 * nf * p1 * max(d - 1, 1) + m * (d * 2 * nl * p1 + 10 * nl)
+            + nl * (8 if m == 1 else 40) + 4 * m * nl)
+
+
+def kernel_work(name, wl, N, E, m):
+    """Algorithmic (bytes, flops) of one launch of a stage kernel.
+
+    Bytes are the arrays the method must read and write in that pass, each
+    once: the line operators read and write one nodal array (16 m N); the
+    gather reads the element vectors and writes r and the first line pass;
+    the update reads the element vectors, u and u_base and writes u (and the
+    nodal fluxes of KPP).  The element passes read the nodal arrays they
+    need (u, g, nodal fluxes, udot) and write the element data of the next
+    pass.  Flops of the line operators are those of a banded solve (about
+    8p per node, not the wider truncated-inverse apply that runs); those of
+    the element passes come from elem1_flops / elem2_flops."""
     d, p = wl.d, wl.p
     nl = (p + 1) ** d
+    kn = d * m * N if wl.kind == "kpp" else 0        # nodal fluxes of KPP
     f8 = 8.0
     if name in ("grad_line", "mass_line"):
-        return "hbm", 2 * m * N * f8
+        return 2 * m * N * f8, 8 * p * m * N
     if name == "gather_r":
-        return "hbm", (m * nl * E + m * N) * f8
+        return (m * nl * E + 2 * m * N) * f8, m * nl * E
     if name == "update":
-        return "hbm", (m * nl * E + 3 * m * N) * f8
+        return (m * nl * E + 3 * m * N + kn) * f8, (nl + 4) * m * N
     if name == "elem1":
-        # reads u, g; writes element residual vectors and per-element data
-        return "hbm", ((1 + d) * m * N + m * nl * E + (2 * m + d * m + 3) * E) * f8
+        return (((1 + d) * m * N + kn) + (m * nl + d * m + 3 + 2 * m) * E) * f8, E * elem1_flops(d, p, m, wl.kind)
     if name == "elem2":
-        # reads u, udot, element vectors, per-element data; writes vectors
-        return "hbm", (2 * m * N + 2 * m * nl * E + (3 * m + d * m + 1) * E) * f8
-    return "hbm", 0.0
+        rd = 2 * m * N + kn + (m * nl + d * m + 2 * m + 1) * E
+        return (rd + (m * nl + m + 1) * E) * f8, E * elem2_flops(d, p, m, wl.kind)
+    return 0.0, 0.0
+
+
+def source_digest():
+    """sha256 of the kernel sources and build flags: counter figures taken on
+    another digest no longer describe the kernels that run."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("csrc/kernels.hpp", "csrc/api.hip", "csrc/tables.cpp", "csrc/tables.hpp", "build.py"):
+        with open(os.path.join(ROOT, "paper_2509_04673_amd", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def profile_name(wl):
+    return f"{wl.name}_{'x'.join(str(k) for k in wl.n)}_q{wl.p}_stage_kernels.md"
+
+
+def _read_csv(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _one(folder, suffix):
+    import glob
+    hits = sorted(glob.glob(os.path.join(folder, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {folder}")
+    return hits[0]
+
+
+def _counter_means(folder):
+    """Mean counter value (KiB) per kernel name over its dispatches."""
+    agg = {}
+    for r in _read_csv(_one(folder, "counter_collection.csv")):
+        agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def summarize_profile(out_dir, dest, command, copy_bytes):
+    """Write the rocprofv3 summary of one bench workload: kernel-trace stats
+    and FETCH_SIZE / WRITE_SIZE per dispatch, the counters scaled by the
+    factor that makes a plain copy of copy_bytes read what it moved."""
+    stats = _read_csv(_one(os.path.join(out_dir, "stats"), "kernel_stats.csv"))
+    fetch = _counter_means(os.path.join(out_dir, "fetch"))
+    write = _counter_means(os.path.join(out_dir, "write"))
+    cf = _counter_means(os.path.join(out_dir, "copy_fetch"))
+    cw = _counter_means(os.path.join(out_dir, "copy_write"))
+    ck = max(cf, key=cf.get)
+    kib = copy_bytes / 1024.0
+    ffac, wfac = kib / cf[ck], kib / cw[ck]
+    rows, data = [], {}
+    for r in stats:
+        name = r["Name"]
+        if "cem::" not in name:
+            continue
+        avg_us = float(r["AverageNs"]) / 1e3
+        f = fetch.get(name)
+        w = write.get(name)
+        tr = None if f is None or w is None else (f * ffac + w * wfac) * 1024.0
+        data[name] = dict(calls=int(r["Calls"]), avg_us=avg_us, fetch_kib=f, write_kib=w, traffic_bytes=tr)
+        rows.append(f"| `{name}` | {r['Calls']} | {avg_us:.2f} | {float(r['Percentage']):.1f} | "
+                    + (f"{f:.0f} | {w:.0f} | {tr / 1e6:.2f} |" if tr is not None else "- | - | - |"))
+    blob = dict(digest=source_digest(), fetch_factor=ffac, write_factor=wfac, copy_kernel=ck,
+                copy_bytes=copy_bytes, kernels=data)
+    text = ["# Stage kernels: rocprofv3 kernel trace and HBM counters", "",
+            "Command (from the repository root, R = its absolute path):", "", "```", command.strip(), "```", "",
+            f"Counter calibration: a plain device copy of {copy_bytes} bytes (`{ck}`) reads "
+            f"FETCH_SIZE {cf[ck]:.0f} KiB and WRITE_SIZE {cw[ck]:.0f} KiB per dispatch, so traffic = "
+            f"{ffac:.3f} x FETCH_SIZE + {wfac:.3f} x WRITE_SIZE.", "",
+            "| kernel | calls | avg us | % time | FETCH_SIZE KiB | WRITE_SIZE KiB | traffic MB |",
+            "|---|---|---|---|---|---|---|", *rows, "",
+            "Machine-readable copy (read by bench.py for the roofline traffic):", "",
+            "```json", json.dumps(blob), "```", ""]
+    with open(dest, "w") as fh:
+        fh.write("\n".join(text))
+    print(f"wrote {dest}", flush=True)
+
+
+def profiled_traffic(wl, kernel_names):
+    """Bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is missing or was taken on other sources."""
+    path = os.path.join(PROFILE_DIR, profile_name(wl))
+    if not os.path.exists(path):
+        return None, None
+    text = open(path).read()
+    try:
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (IndexError, ValueError):
+        return None, None
+    if blob.get("digest") != source_digest():
+        return None, blob
+    for name, rec in blob["kernels"].items():
+        if any(k in name for k in kernel_names):
+            return rec["traffic_bytes"], blob
+    return None, blob
+
+
+# device kernel names behind each timing id
+DEVICE_KERNELS = {"grad_line": ["k_line_x", "k_line_y", "k_line_fast", "k_line("],
+                  "elem1": ["k_elem1"], "gather_r": ["k_gather"], "mass_line": ["k_line_y", "k_line_fast"],
+                  "elem2": ["k_elem2"], "update": ["k_update"]}
+
+
+def copy_probe(nbytes):
+    """Plain device copy of a known size (calibrates the FETCH_SIZE and
+    WRITE_SIZE counters of a profiling run against bytes actually moved)."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_probe_bytes=n * 8, copies=3)), flush=True)
 
 
 def cpu_baseline(wl, seconds):
@@ -87,7 +249,22 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="cells per axis (default: workload size)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="write the rocprofv3 summary of DIR/{stats,fetch,write,copy_fetch,copy_write}")
+    ap.add_argument("--profile-command", default="", help="command text recorded in the summary")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    if args.summarize_profile:
+        from paper_2509_04673_amd import workloads
+        kw = {} if args.n is None else dict(n=args.n)
+        wl = workloads.make(args.workload, seed=0, **kw)
+        summarize_profile(args.summarize_profile, os.path.join(PROFILE_DIR, profile_name(wl)),
+                          args.profile_command, COPY_PROBE_BYTES)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -112,7 +289,10 @@ def main():
     for _ in range(args.warmup):
         s.step(dt, cfl)
     warm = cem.cem_kernel_times(s.ctx)
-    dominant = max(warm, key=lambda k: warm[k][0])
+    # the dominant kernel among the ids that are one device launch per stage
+    # (the line-operator ids cover one launch per axis)
+    single = {k: v for k, v in warm.items() if v[1] == 3 * args.warmup}
+    dominant = max(single, key=lambda k: single[k][0])
     print("[bench] warm-up kernel ms: " + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in warm.items()
                                                    if v[1]), flush=True)
 
@@ -145,18 +325,21 @@ def main():
 
     stages = 3 * args.steps
     value = wl.dofs * stages / (ms * 1e-3)
-    bound, units = kernel_model(dominant, wl, s.N, s.E, s.m)
+    nbytes, nflops = kernel_work(dominant, wl, s.N, s.E, s.m)
     kms, kcnt = kt[dominant]
     avg_s = (kms / kcnt) * 1e-3 if kcnt else float("nan")
-    if bound == "hbm":
-        achieved = units / avg_s / 1e9
-        peak, unit = HBM_PEAK_GBS, "GB/s"
+    # the bound is the larger of the two algorithmic lower bounds
+    if nbytes / (HBM_PEAK_GBS * 1e9) >= nflops / (FP64_VECTOR_TFLOPS * 1e12):
+        bound, achieved, peak, unit = "hbm", nbytes / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
     else:
-        achieved = units / avg_s / 1e12
-        peak, unit = FP64_VECTOR_TFLOPS, "TFLOP/s"
+        bound, achieved, peak, unit = "alu", nflops / avg_s / 1e12, FP64_VECTOR_TFLOPS, "TFLOP/s"
+    traffic, prof = profiled_traffic(wl, DEVICE_KERNELS[dominant])
     roof = dict(bound=bound, kernel=dominant, achieved=achieved, peak=peak, unit=unit,
-                frac=achieved / peak, traffic=None, avg_launch_us=avg_s * 1e6,
-                launches=kcnt)
+                frac=achieved / peak, traffic=traffic, algorithmic_bytes=nbytes, algorithmic_flops=nflops,
+                avg_launch_us=avg_s * 1e6, launches=kcnt,
+                profiled_avg_us=None if prof is None or traffic is None else
+                next(r["avg_us"] for n, r in prof["kernels"].items()
+                     if any(k in n for k in DEVICE_KERNELS[dominant])))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -169,8 +169,11 @@ cem_status cem_reset_counters(cem_ctx* ctx);
 cem_status cem_debug_tap(cem_ctx* ctx, int tap, double* dst, size_t count);
 size_t cem_tap_size(const cem_ctx* ctx, int tap);
 
-/* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch of the kernels selected by mask (bit k = kernel id k):
+/* Per-kernel timing: every launch of a kernel selected by mask (bit k =
+ * kernel id k) is issued with a start and a stop HIP event that take the
+ * dispatch's own begin and end timestamps (hipExtLaunchKernelGGL), so the
+ * times are kernel execution times without launch latency.  While a mask is
+ * set, cem_step launches directly instead of replaying a graph.  Ids:
  *   0 projected-gradient line operator   1 element pass 1 (sensor,
  *   residual, facets)   2 (unused)   3 residual
  *   gather (fused with the first mass-solve pass on long x-lines)   4 mass-

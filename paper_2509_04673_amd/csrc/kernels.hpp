@@ -30,40 +30,7 @@ struct PhysParams {
 };
 
 struct DevTabs {
-  const double* vqf;    // [NQ][NL] basis values at the Gauss points
-  const double* dqw;    // [D][NQ][NL] W_q d_k phi_j(x_q) (reference cell)
-  const double* mass;   // [NL][NL]
-  const double* ksum;   // [NL][NL]
-  const double* ctg;    // [D][NL][NL]
-  const double* qf;     // [1+2D][NL][NL]
-  const double* ext;    // [2][P1][P1]
-  const double* facem;  // [NF][NF]
   const double* sf;     // compact tables of the sum-factorised kernels (SFLayout)
-  const double* kgrad[3];
-  const double* kmass[3];
-  int gtaps[3], gfirst[3], mtaps[3], mfirst[3];
-};
-
-// Compile-time layout of the element tables (the host packs them in this
-// order, each padded to a multiple of 32 doubles): vqf, dqw, mass, ksum, ctg,
-// qf, ext, facem.  When they fit in 32 KB the element kernels stage them in
-// LDS and read them with immediate offsets.
-template <int D, int P> struct TabLayout {
-  static constexpr int P1 = P + 1, NL = ipow(P1, D), NF = NL / P1;
-  static constexpr int pad(int n) { return (n + 31) / 32 * 32; }
-  static constexpr int vqf = 0;
-  static constexpr int dqw = vqf + pad(NL * NL);
-  static constexpr int mass = dqw + pad(D * NL * NL);
-  static constexpr int ksum = mass + pad(NL * NL);
-  static constexpr int ctg = ksum + pad(NL * NL);
-  static constexpr int qf = ctg + pad(D * NL * NL);
-  static constexpr int ext = qf + pad((1 + 2 * D) * NL * NL);
-  static constexpr int facem = ext + pad(2 * P1 * P1);
-  static constexpr int total = facem + pad(NF * NF);
-  // staging in LDS makes the scheduler hoist every table read into VGPRs in
-  // the fully unrolled element code (measured: more spills than the scalar
-  // path), so the element kernels read the tables through the scalar cache
-  static constexpr bool lds = false;
 };
 
 // Compact tables of the sum-factorised element operators: 1D P1 x P1
@@ -78,22 +45,11 @@ template <int D, int P> struct SFLayout {
 
 extern __shared__ double cem_smem[];
 
+// read-only element tables (scalar loads: every lane reads the same entry)
 template <bool LDS> struct TabRef {
   const double* g;
-  __device__ __forceinline__ double operator()(int i) const { return LDS ? cem_smem[i] : g[i]; }
+  __device__ __forceinline__ double operator()(int i) const { return g[i]; }
 };
-
-// stage the element tables of (D, P) in LDS (no-op when they do not fit);
-// every thread of the block must call it
-template <int D, int P>
-__device__ __forceinline__ TabRef<TabLayout<D, P>::lds> stage_tables(const double* gtab) {
-  using TL = TabLayout<D, P>;
-  if constexpr (TL::lds) {
-    for (int i = threadIdx.x; i < TL::total; i += blockDim.x) cem_smem[i] = gtab[i];
-    __syncthreads();
-  }
-  return TabRef<TL::lds>{gtab};
-}
 
 struct MeshArgs {
   int n[3];         // elements per axis (1 for unused axes)
@@ -291,19 +247,6 @@ __device__ inline int64_t local_node(int loc, const int64_t (*off)[P + 1]) {
   return s;
 }
 
-// quadratic form x^T Q x of a symmetric table at offset off
-template <int NL, class TR>
-__device__ inline double qform(const TR& T, int off, const double* x) {
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < NL; ++i) {
-    double t = 0.0;
-#pragma unroll
-    for (int j = 0; j < NL; ++j) t += T(off + i * NL + j) * x[j];
-    s += x[i] * t;
-  }
-  return s;
-}
 
 // ---------------------------------------------------------------------------
 // line operators: out = scale * (M_1D^{-1} or M_1D^{-1} C_1D) applied along
@@ -1060,7 +1003,6 @@ __device__ inline void limit_facet(const StageArgs& a, int k, int64_t eL, int64_
 template <int D, int P, int PH>
 __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
   using PHY = Phys<D, PH>;
-  using TL = TabLayout<D, P>;
   constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NF = NL / P1;
   const TabRef<false> T{a.tab.sf};
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

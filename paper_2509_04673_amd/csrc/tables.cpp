@@ -246,27 +246,6 @@ bool build_tables(int d, int p, double h, const int L[3], const int wfast[5], co
     return loc % P1;
   };
 
-  T.mass.assign((size_t)nl * nl, 0.0);
-  T.ksum.assign((size_t)nl * nl, 0.0);
-  T.ctg.assign((size_t)d * nl * nl, 0.0);
-  for (int i = 0; i < nl; ++i)
-    for (int j = 0; j < nl; ++j) {
-      LD m = 1.0L, ks = 0.0L;
-      for (int k = 0; k < d; ++k) m *= G1(digit(i, k), digit(j, k));
-      for (int k = 0; k < d; ++k) {
-        LD sk = 1.0L, ck = 1.0L;
-        for (int l = 0; l < d; ++l) {
-          int a = digit(i, l), b = digit(j, l);
-          sk *= (l == k) ? K1(a, b) : G1(a, b);
-          ck *= (l == k) ? CT1(a, b) : G1(a, b);
-        }
-        ks += sk;
-        T.ctg[((size_t)k * nl + i) * nl + j] = (double)ck;
-      }
-      T.mass[(size_t)i * nl + j] = (double)m;
-      T.ksum[(size_t)i * nl + j] = (double)ks;
-    }
-
   // semi-norm form: sum over 1 <= |k| <= p of tensor products of the 1D
   // m-th derivative Grams (scale-free on cube cells)
   std::vector<LD> Q((size_t)nl * nl, 0.0L);
@@ -305,35 +284,6 @@ bool build_tables(int d, int p, double h, const int L[3], const int wfast[5], co
       }
     }
   }
-  // forms of the candidates: E^T Q E with E acting along the facet axis
-  T.qf.assign((size_t)(1 + 2 * d) * nl * nl, 0.0);
-  for (int i = 0; i < nl * nl; ++i) T.qf[i] = (double)Q[i];
-  for (int k = 0; k < d; ++k)
-    for (int s = 0; s < 2; ++s) {
-      std::vector<LD> Efull((size_t)nl * nl, 0.0L);
-      for (int i = 0; i < nl; ++i)
-        for (int j = 0; j < nl; ++j) {
-          bool same = true;
-          for (int l = 0; l < d; ++l)
-            if (l != k && digit(i, l) != digit(j, l)) same = false;
-          if (same) Efull[(size_t)i * nl + j] = E1[s][digit(i, k) * P1 + digit(j, k)];
-        }
-      std::vector<LD> QE((size_t)nl * nl, 0.0L);
-      for (int i = 0; i < nl; ++i)
-        for (int j = 0; j < nl; ++j) {
-          LD acc = 0.0L;
-          for (int m = 0; m < nl; ++m) acc += Q[(size_t)i * nl + m] * Efull[(size_t)m * nl + j];
-          QE[(size_t)i * nl + j] = acc;
-        }
-      double* dst = &T.qf[(size_t)(1 + 2 * k + s) * nl * nl];
-      for (int i = 0; i < nl; ++i)
-        for (int j = 0; j < nl; ++j) {
-          LD acc = 0.0L;
-          for (int m = 0; m < nl; ++m) acc += Efull[(size_t)m * nl + i] * QE[(size_t)m * nl + j];
-          dst[(size_t)i * nl + j] = (double)acc;
-        }
-    }
-
   // 1D tables of the sum-factorised element operators
   T.g1.assign(P1 * P1, 0.0);
   T.k1.assign(P1 * P1, 0.0);
@@ -347,15 +297,6 @@ bool build_tables(int d, int p, double h, const int L[3], const int wfast[5], co
   T.qp.clear();
   for (int i = 0; i < nl; ++i)
     for (int j = i; j < nl; ++j) T.qp.push_back((double)((j == i ? 1.0L : 2.0L) * Q[(size_t)i * nl + j]));
-
-  // facet Gram over the D-1 tangential axes (facet-local lexicographic ids)
-  T.facem.assign((size_t)nlf * nlf, 0.0);
-  for (int i = 0; i < nlf; ++i)
-    for (int j = 0; j < nlf; ++j) {
-      LD v = 1.0L;
-      for (int k = 0; k < d - 1; ++k) v *= G1(digit(i, k), digit(j, k));
-      T.facem[(size_t)i * nlf + j] = (double)v;
-    }
 
   for (int k = 0; k < d; ++k)
     line_kernels(p, L[k], (LD)h, wfast[p], rfast[p], sfast[p], T.kmass[k], T.kgrad[k]);

@@ -31,12 +31,7 @@ struct LineKernel {
 struct HostTables {
   int d = 0, p = 0, nl = 0, nlf = 0;
   std::vector<double> vq, dq, wq;   // [P1][P1] B_a(t_q), B_a'(t_q); [P1] weights
-  std::vector<double> mass;         // [NL][NL] tensor Gram (reference cell)
-  std::vector<double> ksum;         // [NL][NL] sum_k int d_k phi_i d_k phi_j
-  std::vector<double> ctg;          // [D][NL][NL] int d_k phi_i phi_j
-  std::vector<double> qf;           // [1+2D][NL][NL] WENO semi-norm forms, symmetric
   std::vector<double> ext;          // [2][P1][P1] extension maps (low, high neighbour)
-  std::vector<double> facem;        // [NLF][NLF] facet Gram over the other D-1 axes
   std::vector<double> g1, k1, ct1;  // [P1][P1] 1D mass, stiffness, int B_a' B_b
   std::vector<double> qp;           // packed upper triangle of the semi-norm form,
                                     // row i: Q_ii, 2 Q_i,i+1, ..., 2 Q_i,NL-1
