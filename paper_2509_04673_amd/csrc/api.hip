@@ -13,6 +13,7 @@
 
 #include "../../include/cem.h"
 #include "kernels.hpp"
+#include "kernels_sys.hpp"
 #include "tables.hpp"
 
 using namespace cem;
@@ -56,6 +57,7 @@ struct cem_ctx {
   size_t o_g, o_r, o_udot, o_tmp, o_tmp2, o_relem, o_ue, o_ubarL, o_ubar, o_fahi, o_dte, o_gam,
       o_nu, o_beta, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart, o_fnode;
   bool fnode_valid = false;   // nodal fluxes match the bound state
+  int lds_max = 65536;        // LDS bytes one block may use on the bound device
   int upd_blocks = 0, inv_blocks = 0;
   bool bound = false, bounds_set = false;
   // whole-step HIP graph (captured on a private stream, launched on stream)
@@ -286,6 +288,24 @@ cem_status launch_line(cem_ctx* c, const double* in, double* out, int axis, bool
   return CEM_OK;
 }
 
+// element passes of systems (one thread per element and component)
+template <int D, int P, int PH>
+cem_status launch_sys(cem_ctx* c, StageArgs& a, bool first) {
+  using TL = SysTile<D, P, PH>;
+  constexpr int M = Phys<D, PH>::M, EB = TL::EB;
+  const size_t lds = TL::LY::bytes;
+  if (lds > (size_t)c->lds_max) return fail(CEM_EINVAL, "element tile does not fit the LDS of a block");
+  const unsigned nb = (unsigned)nblocks(c->E, EB);
+  if (first) {
+    a.ndtpart = (int)nb;
+    CEM_LAUNCH(c, 1, (k_elem1_sys<D, P, PH>), nb, M * EB, lds, c->stream, a);
+  } else {
+    CEM_LAUNCH(c, 5, (k_elem2_sys<D, P, PH>), nb, M * EB, lds, c->stream, a);
+  }
+  HIPCHK(hipGetLastError());
+  return CEM_OK;
+}
+
 template <int D, int P, int PH>
 cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   constexpr int M = Phys<D, PH>::M;
@@ -314,7 +334,12 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   // (Running the g-independent part concurrently with the gradient passes on
   // a second stream was measured slower on the 256^2 KPP mesh.)
   {
-    if constexpr (D == 2) {
+    // 3D systems: one thread per (element, component); 2D: the LDS element
+    // tile with one thread per element measured faster for both physics
+    if constexpr (PH == EUL && D == 3) {
+      cem_status st = launch_sys<D, P, PH>(c, a, true);
+      if (st != CEM_OK) return st;
+    } else if constexpr (D == 2) {
       using TT = Tile2<P, M>;
       const int nb = ((c->n[0] + TT::TEX - 1) / TT::TEX) * ((c->n[1] + TT::TEY - 1) / TT::TEY);
       a.ndtpart = nb;
@@ -349,7 +374,12 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     if (s != CEM_OK) return s;
     src = dst;
   }
-  CEM_LAUNCH(c, 5, (k_elem2<D, P, PH>), nblocks(c->E, 128), 128, 0, c->stream, a);
+  if constexpr (PH == EUL && D >= 2) {
+    cem_status st = launch_sys<D, P, PH>(c, a, false);
+    if (st != CEM_OK) return st;
+  } else {
+    CEM_LAUNCH(c, 5, (k_elem2<D, P, PH>), nblocks(c->E, 128), 128, 0, c->stream, a);
+  }
   HIPCHK(hipGetLastError());
   CEM_LAUNCH(c, 6, (k_update<D, P, PH>), c->upd_blocks, 256, 0, c->stream, a);
   HIPCHK(hipGetLastError());
@@ -470,8 +500,9 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->o_nu = take(E8);
   c->o_beta = take(E8);
   c->o_dtbuf = take(8 * 8);
-  // per-block dt_e minima: one-thread-per-element blocks or 2D element tiles
-  size_t ndtp = nblocks(c->E, 128);
+  // per-block dt_e minima: one-thread-per-element blocks, 2D element tiles
+  // or the 32- / 64-element blocks of the system passes
+  size_t ndtp = nblocks(c->E, 32);
   if (d == 2) ndtp = std::max(ndtp, (size_t)((c->n[0] + 15) / 16) * (size_t)((c->n[1] + 7) / 8));
   c->o_dtpart = take(ndtp * 8);
   c->upd_blocks = (int)nblocks(c->N, 256);
@@ -518,6 +549,12 @@ cem_status cem_bind(cem_ctx* c, double* u, double* u_base, void* workspace, size
   HIPCHK(hipMemcpyAsync(c->ws + c->o_tab, c->tabblob.data(), c->tabblob.size() * 8, hipMemcpyHostToDevice,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));   // the host table blob stays alive, but keep bind simple
+  {
+    int dev = 0, v = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    c->lds_max = v;
+  }
   c->bound = true;
   return cem_reset_counters(c);
 }

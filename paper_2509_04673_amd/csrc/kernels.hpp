@@ -46,9 +46,13 @@ template <int D, int P> struct SFLayout {
 extern __shared__ double cem_smem[];
 
 // read-only element tables (scalar loads: every lane reads the same entry)
+// The tables are read through the constant address space: they are not
+// written while a kernel runs, so uniform reads become scalar loads into
+// SGPRs instead of vector loads that occupy VGPRs.
+typedef const double __attribute__((address_space(4))) const_f64;
 template <bool LDS> struct TabRef {
   const double* g;
-  __device__ __forceinline__ double operator()(int i) const { return g[i]; }
+  __device__ __forceinline__ double operator()(int i) const { return ((const const_f64*)g)[i]; }
 };
 
 struct MeshArgs {

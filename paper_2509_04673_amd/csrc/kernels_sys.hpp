@@ -1,0 +1,549 @@
+// Element passes of systems (the Euler equations, m = d + 2 components) on
+// gfx950: one thread per (element, component).  A block holds EB elements
+// and m groups of EB threads, group c working on component c.  Everything
+// that acts on one component at a time (the WENO sensor of eqs. (7)-(8), the
+// interpolation to the Gauss points, the test-function contractions, the
+// stabilisation, the consistent-mass term) runs in the component's thread;
+// what couples the components (fluxes at Gauss points and facet nodes, node
+// and facet wave speeds, the positivity factors of Appendix A) reads the full
+// states from one LDS buffer S[point][component][element].
+//
+// Register budget: a thread holds at most three arrays of (p+1)^d doubles.
+// The element's own coefficients are read from S (LDS addresses are a base
+// register plus an immediate), not re-gathered from HBM: held 64-bit gather
+// addresses were what exhausted the registers of the 3D Q2 pass.
+#pragma once
+#include "kernels.hpp"
+
+namespace cem {
+
+template <int D, int P, int PH, int EB_> struct SysLayout {
+  static constexpr int EB = EB_;
+  static constexpr int M = Phys<D, PH>::M, P1 = P + 1, NL = ipow(P1, D);
+  static constexpr int NS = NL * M * EB;         // nodal states, later Gauss-point states
+  static constexpr int oUe = NS;                 // [M][EB] cell averages (pass 1)
+  static constexpr int oNm = oUe + M * EB;       // [2D][M][EB] neighbour averages (pass 1)
+  static constexpr int oPart = oNm + 2 * D * M * EB;   // [M][EB] per-group maxima / minima
+  static constexpr int oGam = oPart + M * EB;    // [M][EB] per-component sensor values
+  static constexpr int oFac = oGam + M * EB;     // [2D][EB] facet wave speeds or facet alphas
+  static constexpr int oUb = oFac + 2 * D * EB;  // [M][EB] flux-limited averages (pass 2)
+  static constexpr int oRed = oUb + M * EB;      // [EB] dt_e of the block
+  static constexpr int words = oRed + EB;
+  static constexpr size_t bytes = (size_t)words * sizeof(double);
+};
+
+// elements per block: 64 when the block's LDS stays within 64 KiB, else 32
+template <int D, int P, int PH> struct SysTile {
+  static constexpr int EB = SysLayout<D, P, PH, 64>::bytes <= 65536 ? 64 : 32;
+  using LY = SysLayout<D, P, PH, EB>;
+};
+
+// component c of a value array computed for all components (a select chain:
+// no dynamically indexed register array)
+template <int M>
+__device__ __forceinline__ double pick_c(const double* v, int c) {
+  double r = v[0];
+#pragma unroll
+  for (int k = 1; k < M; ++k)
+    if (c == k) r = v[k];
+  return r;
+}
+
+// v[i] for a runtime i < K, and v[i] = x, without a dynamically indexed
+// register array (which would live in scratch)
+template <int K>
+__device__ __forceinline__ double get_sel(const double* v, int i) {
+  double r = v[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k)
+    if (i == k) r = v[k];
+  return r;
+}
+template <int K>
+__device__ __forceinline__ void set_sel(double* v, int i, double x) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (i == k) v[k] = x;
+}
+
+// x <- (A along axis K) x in place, one line of P+1 values at a time (the
+// same sums as ax1 with a (P+1)-value temporary instead of a second array)
+template <int D, int P, int K, class TB>
+__device__ __forceinline__ void ax_ip1(const TB& T, int ao, bool trn, double* x) {
+  constexpr int P1 = P + 1, NL = ipow(P1, D), ST = ipow(P1, K);
+#pragma unroll
+  for (int i0 = 0; i0 < NL; ++i0) {
+    if ((i0 / ST) % P1 != 0) continue;   // i0 starts a line along axis K
+    double v[P1];
+#pragma unroll
+    for (int b = 0; b < P1; ++b) v[b] = x[i0 + b * ST];
+#pragma unroll
+    for (int ai = 0; ai < P1; ++ai) {
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < P1; ++b) s += T(ao + (trn ? b * P1 + ai : ai * P1 + b)) * v[b];
+      x[i0 + ai * ST] = s;
+    }
+  }
+}
+
+template <int D, int P, class TB>
+__device__ __forceinline__ void ax_ip(int k, const TB& T, int ao, bool trn, double* x) {
+  if (k == 0) ax_ip1<D, P, 0>(T, ao, trn, x);
+  else if constexpr (D > 1) {
+    if (k == 1) ax_ip1<D, P, 1>(T, ao, trn, x);
+    else if constexpr (D > 2) ax_ip1<D, P, 2>(T, ao, trn, x);
+  }
+}
+
+// x <- (A_{D-1} (x) ... (x) A_0) x in place, axis 0 first (as tensor_apply)
+template <int D, int P, class TB>
+__device__ __forceinline__ void tensor_ip(const TB& T, const int* mo, bool trn, double* x) {
+  if constexpr (D >= 1) ax_ip1<D, P, 0>(T, mo[0], trn, x);
+  if constexpr (D >= 2) ax_ip1<D, P, 1>(T, mo[1], trn, x);
+  if constexpr (D >= 3) ax_ip1<D, P, 2>(T, mo[2], trn, x);
+}
+
+// component c of the Euler flux along axis k (both may be runtime values):
+// the same operations as Phys<D, EUL>::flux, written with selects so that
+// no register array is indexed dynamically
+template <int D>
+__device__ __forceinline__ double euler_flux_comp(int k, int c, const double* u, double gam) {
+  double mk = u[1];
+  if (D > 1 && k == 1) mk = u[2];
+  if (D > 2 && k == 2) mk = u[3];
+  double m2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) m2 += u[1 + j] * u[1 + j];
+  const double p = (gam - 1.0) * (u[D + 1] - 0.5 * m2 / u[0]);
+  const double vk = mk / u[0];
+  double r = pick_c<D + 2>(u, c) * vk + (c - 1 == k ? p : 0.0);
+  if (c == 0) r = mk;
+  if (c == D + 1) r = vk * (u[D + 1] + p);
+  return r;
+}
+
+// full state of point q from S (component-major inside a point)
+template <int M, int EB>
+__device__ __forceinline__ void state_at(const double* S, int q, int le, double* u) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) u[k] = S[(q * M + k) * EB + le];
+}
+
+// minimum of dt_e over the block's elements (group 0 holds them)
+template <int EB>
+__device__ __forceinline__ void block_min_dt_sys(double* red, double* part, int c, int le, double v) {
+  if (c == 0) red[le] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int i = 1; i < EB; ++i) m = fmin(m, red[i]);
+    part[blockIdx.x] = m;
+  }
+}
+
+template <int D, int P, int PH>
+__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_elem1_sys(StageArgs a) {
+  static_assert(PH == EUL, "system element pass 1 is written for the Euler equations");
+  using PHY = Phys<D, PH>;
+  using SF = SFLayout<D, P>;
+  using LY = typename SysTile<D, P, PH>::LY;
+  constexpr int EB = LY::EB, P1 = P + 1, NL = LY::NL, M = LY::M, NF = NL / P1, CS = M * EB;
+  const TabRef<false> T{a.tab.sf};
+  const MeshArgs& ms = a.mesh;
+  const int64_t E = ms.E, N = ms.N;
+  const double h = ms.h;
+  const int c = threadIdx.x / EB, le = threadIdx.x - c * EB;
+  const int64_t e0 = (int64_t)blockIdx.x * EB;
+  const bool live = e0 + le < E;
+  const int64_t e = live ? e0 + le : E - 1;   // idle lanes redo the last element, store nothing
+  double* S = cem_smem;
+  double* Us = S + c * EB + le;               // own coefficients / Gauss values: Us[j * CS]
+  const GlobalNodes<D, P, M> ns(a, e);
+
+  // ---- own coefficients into S, cell average
+  double ue_c = 0.0;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const double v = a.u[c * N + ns.own_node(j)];
+    ue_c += v;
+    Us[j * CS] = v;
+  }
+  ue_c *= (1.0 / NL);
+
+  // ---- WENO sensor of component c (Sec. 2.2, eqs. 7-8): candidates are
+  // the facet neighbours extended into K_e by the blossom maps; semi-norms
+  // are the packed quadratic form on coefficients shifted by their first
+  // entry.  The neighbour averages go to S for the facet fluxes.  The
+  // neighbour loops are not unrolled: unrolled, the compiler issues all 2d
+  // candidates' loads together and runs out of registers.
+  double gc = 1.0;
+  {
+    double beta0, betan[2 * D];
+    {
+      double x[NL];
+      const double u0 = Us[0];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) x[j] = Us[j * CS] - u0;
+      beta0 = qsym<NL>(T, SF::qp, x);
+    }
+#pragma unroll 1
+    for (int l = 0; l < 2 * D; ++l) {
+      double cn[NL], sum = 0.0;
+      ns.load_nbr(c, l, cn);
+#pragma unroll
+      for (int j = 0; j < NL; ++j) sum += cn[j];
+      S[LY::oNm + (l * M + c) * EB + le] = sum * (1.0 / NL);
+      const double c0 = cn[0];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) cn[j] -= c0;
+      ax_ip<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cn);
+      set_sel<2 * D>(betan, l, qsym<NL>(T, SF::qp, cn));
+    }
+    if (a.gamma_mode == 0) {
+      auto nrm = [&](double b) { return (a.rexp == 2.0) ? b : pow(b, 0.5 * a.rexp); };
+      double wt[2 * D];
+      double wsum = (1.0 - 2 * D * a.w_lin) / (nrm(beta0) + a.eps);
+#pragma unroll
+      for (int l = 0; l < 2 * D; ++l) {
+        wt[l] = a.w_lin / (nrm(betan[l]) + a.eps);
+        wsum += wt[l];
+      }
+      const double iws = 1.0 / wsum;
+      double w[NL];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) w[j] = 0.0;
+      const double u0 = Us[0];
+#pragma unroll 1
+      for (int l = 0; l < 2 * D; ++l) {
+        const double om = get_sel<2 * D>(wt, l) * iws;
+        double cn[NL];
+        ns.load_nbr(c, l, cn);
+        const double c0 = cn[0];
+#pragma unroll
+        for (int j = 0; j < NL; ++j) cn[j] -= c0;
+        ax_ip<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cn);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) w[i] += om * ((Us[i * CS] - u0) - cn[i]);
+      }
+      // 0/0 on constant elements, regularised with the weights' epsilon
+      const double dev = sqrt(fmax(qsym<NL>(T, SF::qp, w), 0.0));
+      const double ratio = fmin(1.0, dev / sqrt(fmax(beta0, 0.0) + a.eps));
+      gc = 1.0 - (a.q == 1.0 ? ratio : pow(ratio, a.q));
+    }
+  }
+  S[LY::oUe + c * EB + le] = ue_c;
+  S[LY::oGam + c * EB + le] = gc;
+  __syncthreads();
+
+  // ---- facet wave speeds (eq. 18), facet l handled by group l mod m;
+  // node speeds (viscosity), nodes j = c, c + m, ...
+  double uo[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) uo[k] = S[LY::oUe + k * EB + le];
+#pragma unroll
+  for (int l = 0; l < 2 * D; ++l) {
+    if (l % M != c) continue;
+    double un[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) un[k] = S[LY::oNm + (l * M + k) * EB + le];
+    const int k = l / 2;
+    const double lm = (l % 2) ? PHY::riemann_speed(uo, un, k, a.ph) : PHY::riemann_speed(un, uo, k, a.ph);
+    S[LY::oFac + l * EB + le] = lm;
+  }
+  {
+    double lam = 0.0;
+    for (int j = c; j < NL; j += M) {
+      double uj[M];
+      state_at<M, EB>(S, j, le, uj);
+      lam = fmax(lam, PHY::node_speed(uj, a.ph));
+    }
+    S[LY::oPart + c * EB + le] = lam;
+  }
+  __syncthreads();
+  double gmin = 1.0, lam = 0.0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    gmin = fmin(gmin, S[LY::oGam + k * EB + le]);
+    lam = fmax(lam, S[LY::oPart + k * EB + le]);
+  }
+  const double gam = a.gamma_mode == 0 ? gmin : (a.gamma_mode == 1 ? 0.0 : 1.0);
+  const double nu = lam * h / (2.0 * P);
+
+  // ---- facet fluxes of component c (eqs. 18, 40, 42, 51): f^L against the
+  // neighbour averages, f^H = mean of f(u_j) n over the + facet's nodes
+  double lamsum = 0.0, fLsum = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    double fo[M];
+    PHY::flux(k, uo, fo, a.ph);
+    const double foc = pick_c<M>(fo, c);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int l = 2 * k + side;
+      double un[M], fn[M];
+#pragma unroll
+      for (int kk = 0; kk < M; ++kk) un[kk] = S[LY::oNm + (l * M + kk) * EB + le];
+      PHY::flux(k, un, fn, a.ph);
+      const double fnc = pick_c<M>(fn, c), unc = pick_c<M>(un, c);
+      const double lm = S[LY::oFac + l * EB + le];
+      lamsum += lm;
+      const double fl = side ? foc : fnc, fr = side ? fnc : foc;
+      const double uL = side ? ue_c : unc, uR = side ? unc : ue_c;
+      const double fLc = 0.5 * (fl + fr) - 0.5 * lm * (uR - uL);
+      fLsum += side ? fLc : -fLc;
+      if (side) {
+        double fH = 0.0;
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+          if (dig(j, k, P1) != P) continue;
+          double uj[M], fj[M];
+          state_at<M, EB>(S, j, le, uj);
+          PHY::flux(k, uj, fj, a.ph);
+          fH += pick_c<M>(fj, c);
+        }
+        if (live) a.fahi[((int64_t)k * M + c) * E + e] = fLc - fH * (1.0 / NF);
+      }
+    }
+  }
+  const double dt_e = h / lamsum;
+  if (live) {
+    a.ue[c * E + e] = ue_c;
+    a.ubarL[c * E + e] = ue_c - dt_e / h * fLsum;
+    if (c == 0) {
+      a.dte[e] = dt_e;
+      a.gam[e] = gam;
+      a.nu[e] = nu;
+    }
+  }
+
+  // ---- element residual R_i = int grad phi_i . f(u_h) - s_h^e(phi_i, u_h):
+  // the stabilisation first (from the nodal coefficients), then the Gauss-
+  // point states replace the nodal ones in S for the flux term
+  double hpow = 1.0;
+#pragma unroll
+  for (int k = 0; k < D - 1; ++k) hpow *= h;   // h^{D-1}
+  double R[NL];
+  {
+    const double sa = nu * hpow / h, sg = nu * gam * hpow;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) R[i] = 0.0;
+    // not unrolled: unrolled, all D (p+1)^d gradient loads are issued up
+    // front and spilled
+#pragma unroll 1
+    for (int k = 0; k < D; ++k) {
+      const int ms1[3] = {k == 0 ? SF::k1 : SF::g, k == 1 ? SF::k1 : SF::g, k == 2 ? SF::k1 : SF::g};
+      const int ms2[3] = {k == 0 ? SF::ct : SF::g, k == 1 ? SF::ct : SF::g, k == 2 ? SF::ct : SF::g};
+      double t[NL];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) t[j] = Us[j * CS];
+      tensor_ip<D, P>(T, ms1, false, t);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) R[i] -= sa * t[i];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) t[j] = a.g[((int64_t)k * M + c) * N + ns.own_node(j)];
+      tensor_ip<D, P>(T, ms2, false, t);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) R[i] += sg * t[i];
+    }
+  }
+  {
+    double uq[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) uq[j] = Us[j * CS];
+    const int mv[3] = {SF::vq, SF::vq, SF::vq};
+    tensor_ip<D, P>(T, mv, false, uq);
+    __syncthreads();    // every thread is done with the nodal states
+#pragma unroll
+    for (int q = 0; q < NL; ++q) Us[q * CS] = uq[q];
+  }
+  __syncthreads();
+  // flux term, one axis at a time (a rolled loop: unrolled, the axes'
+  // Gauss-point work is interleaved and runs out of registers)
+#pragma unroll 1
+  for (int k = 0; k < D; ++k) {
+    double F[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      double wv = 1.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) wv *= T(SF::wq + dig(q, j, P1));
+      double uv[M];
+      state_at<M, EB>(S, q, le, uv);
+      F[q] = wv * euler_flux_comp<D>(k, c, uv, a.ph.gam);
+    }
+    const int mt[3] = {k == 0 ? SF::dq : SF::vq, k == 1 ? SF::dq : SF::vq, k == 2 ? SF::dq : SF::vq};
+    tensor_ip<D, P>(T, mt, true, F);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) R[i] += hpow * F[i];
+  }
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) a.relem[((int64_t)c * NL + i) * E + e] = R[i];
+  }
+  block_min_dt_sys<EB>(S + LY::oRed, a.dtpart, c, le, live ? dt_e : 1.0e300);
+}
+
+// flux-pair factor of Appendix A for the facet between eL and eR normal to
+// axis k (states ubar^{e,L} of both sides, increments of the raw f^A)
+template <int D>
+__device__ inline double euler_facet_alpha(const StageArgs& a, int k, int64_t eL, int64_t eR) {
+  constexpr int M = D + 2;
+  if (a.alpha_mode == 2) return 1.0;
+  if (a.alpha_mode == 1) return 0.0;
+  const int64_t E = a.mesh.E;
+  const double dtL = a.dte[eL], dtR = a.dte[eR];
+  const double phi = a.mesh.h / (2.0 * D);
+  double uLs[M], uRs[M], dL[M], dR[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    const double fA = a.fahi[((int64_t)k * M + q) * E + eL];
+    uLs[q] = a.ubarL[q * E + eL];
+    uRs[q] = a.ubarL[q * E + eR];
+    dL[q] = fA / phi * dtL;
+    dR[q] = -fA / phi * dtR;
+  }
+  return fmin(euler_alpha<D>(uLs, dL, 1.0, a.eps_pos), euler_alpha<D>(uRs, dR, 1.0, a.eps_pos));
+}
+
+template <int D, int P, int PH>
+__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_elem2_sys(StageArgs a) {
+  static_assert(PH == EUL, "system element pass 2 is written for the Euler equations");
+  using PHY = Phys<D, PH>;
+  using SF = SFLayout<D, P>;
+  using LY = typename SysTile<D, P, PH>::LY;
+  constexpr int EB = LY::EB, P1 = P + 1, NL = LY::NL, M = LY::M, NF = NL / P1, CS = M * EB;
+  const TabRef<false> T{a.tab.sf};
+  const MeshArgs& ms = a.mesh;
+  const int64_t E = ms.E, N = ms.N;
+  const double h = ms.h;
+  const int c = threadIdx.x / EB, le = threadIdx.x - c * EB;
+  const int64_t e0 = (int64_t)blockIdx.x * EB;
+  const bool live = e0 + le < E;
+  const int64_t e = live ? e0 + le : E - 1;
+  double* S = cem_smem;
+  double* Us = S + c * EB + le;
+  const GlobalNodes<D, P, M> ns(a, e);
+  int64_t enb[2 * D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    int en[3] = {ns.ei[0], ns.ei[1], ns.ei[2]};
+    en[k] = (ns.ei[k] + ms.n[k] - 1) % ms.n[k];
+    enb[2 * k] = elem_id(en, ms);
+    en[k] = (ns.ei[k] + 1) % ms.n[k];
+    enb[2 * k + 1] = elem_id(en, ms);
+  }
+
+  // ---- facet factors (Appendix A), facet l handled by group l mod m;
+  // own coefficients into S
+#pragma unroll
+  for (int l = 0; l < 2 * D; ++l) {
+    if (l % M != c) continue;
+    const int k = l / 2;
+    S[LY::oFac + l * EB + le] =
+        (l % 2) ? euler_facet_alpha<D>(a, k, e, enb[l]) : euler_facet_alpha<D>(a, k, enb[l], e);
+  }
+#pragma unroll
+  for (int j = 0; j < NL; ++j) Us[j * CS] = a.u[c * N + ns.own_node(j)];
+  __syncthreads();
+
+  // ---- flux-limited average (eq. 44)
+  const double dt_e = a.dte[e];
+  double fbs = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    fbs -= S[LY::oFac + (2 * k) * EB + le] * a.fahi[((int64_t)k * M + c) * E + enb[2 * k]];
+    fbs += S[LY::oFac + (2 * k + 1) * EB + le] * a.fahi[((int64_t)k * M + c) * E + e];
+  }
+  const double ub_c = a.ubarL[c * E + e] + dt_e / h * fbs;
+  const double ue_c = a.ue[c * E + e];
+  S[LY::oUb + c * EB + le] = ub_c;
+  if (live) a.ubar[c * E + e] = ub_c;
+
+  // ---- boundary integral B_i = int_{dK} phi_i f_h . n of component c
+  double hpow = 1.0;
+#pragma unroll
+  for (int k = 0; k < D - 1; ++k) hpow *= h;
+  double f[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) f[i] = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int av = side ? P : 0;
+      const double sg = side ? hpow : -hpow;
+      double fn[NF];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        if (dig(j, k, P1) != av) continue;
+        const int fj = j % ipow(P1, k) + (j / ipow(P1, k + 1)) * ipow(P1, k);
+        double uj[M], fv[M];
+        state_at<M, EB>(S, j, le, uj);
+        PHY::flux(k, uj, fv, a.ph);
+        fn[fj] = pick_c<M>(fv, c);
+      }
+      const int mg[3] = {SF::g, SF::g, SF::g};
+      tensor_ip<D - 1, P>(T, mg, false, fn);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        if (dig(i, k, P1) != av) continue;
+        const int fi = i % ipow(P1, k) + (i / ipow(P1, k + 1)) * ipow(P1, k);
+        f[i] += sg * fn[fi];
+      }
+    }
+  }
+  // ---- element contributions f_i^e of eq. (45); dU_i = m_i^e (ubar - u_i)
+  const double hd = hpow * h, mloc = hd * (1.0 / NL);
+  double dU[NL];
+  {
+    double Fe = 0.0;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) Fe += f[i];
+    double mu[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) mu[j] = a.udot[c * N + ns.own_node(j)];
+    const int mg[3] = {SF::g, SF::g, SF::g};
+    tensor_ip<D, P>(T, mg, false, mu);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const double Tc = hd * mu[i] - mloc * a.udot[c * N + ns.own_node(i)];
+      const double R = a.relem[((int64_t)c * NL + i) * E + e];
+      const double Ui = Us[i * CS];
+      f[i] = mloc * (Ui - ue_c) + dt_e * (R - f[i] + Fe * (1.0 / NL) - Tc);
+      dU[i] = mloc * (ub_c - Ui);
+    }
+  }
+  __syncthreads();    // all reads of the nodal states are done
+
+  // ---- slope limiter (Appendix A on every node, ubar_i = ubar^e)
+#pragma unroll
+  for (int i = 0; i < NL; ++i) Us[i * CS] = f[i];
+  __syncthreads();
+  {
+    double ub[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) ub[k] = S[LY::oUb + k * EB + le];
+    double bp = 1.0;
+    for (int i = c; i < NL; i += M) {
+      double fi[M];
+      state_at<M, EB>(S, i, le, fi);
+      bp = fmin(bp, euler_alpha<D>(ub, fi, mloc, a.eps_pos));
+    }
+    S[LY::oPart + c * EB + le] = bp;
+  }
+  __syncthreads();
+  double beta = 1.0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) beta = fmin(beta, S[LY::oPart + k * EB + le]);
+  if (a.beta_mode == 1) beta = 0.0;
+  else if (a.beta_mode == 2) beta = 1.0;
+  if (live) {
+    if (c == 0) a.beta[e] = beta;
+    const double idt = 1.0 / dt_e;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) a.relem[((int64_t)c * NL + i) * E + e] = (dU[i] + beta * f[i]) * idt;
+  }
+}
+
+}  // namespace cem

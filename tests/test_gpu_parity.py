@@ -24,6 +24,7 @@ STAGE_CASES = [
     ("euler2d_q2", lambda: random_euler_workload(2, 2, (12, 7))),
     ("euler2d_q3", lambda: random_euler_workload(2, 3, (9, 10))),
     ("euler3d_q2", lambda: random_euler_workload(3, 2, (5, 6, 4))),
+    ("euler3d_q1", lambda: random_euler_workload(3, 1, (7, 5, 6))),
     # lines long enough for the register-blocked line kernel (p = 1, 2, 3)
     ("adv2d_q1_long", lambda: random_scalar_workload(2, 1, (81, 80))),
     ("kpp2d_q2_long", lambda: random_scalar_workload(2, 2, (64, 63), kind="kpp")),
@@ -68,6 +69,7 @@ def test_stage_parity(label, make):
 def test_stage_parity_method_switches(modes):
     _compare_stage(random_scalar_workload(2, 2, (10, 9), kind="kpp"), modes, "switch")
     _compare_stage(random_euler_workload(2, 2, (8, 9)), modes, "switch-euler")
+    _compare_stage(random_euler_workload(3, 2, (4, 5, 3)), modes, "switch-euler3d")
 
 
 def _perturbed(u):
