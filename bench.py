@@ -36,6 +36,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector peak
+FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak (the element passes of the mixed form)
 COPY_PROBE_BYTES = 1 << 28     # plain copy used to calibrate the byte counters
 
 
@@ -67,7 +68,7 @@ def elem2_flops(d, p, m, kind):
             + nl * (8 if m == 1 else 40) + 4 * m * nl)
 
 
-def kernel_work(name, wl, N, E, m):
+def kernel_work(name, wl, N, E, m, mixed=False):
     """Algorithmic (bytes, flops) of one launch of a stage kernel.
 
     Bytes are the arrays the method must read and write in that pass, each
@@ -76,24 +77,29 @@ def kernel_work(name, wl, N, E, m):
     the update reads the element vectors, u and u_base and writes u (and the
     nodal fluxes of KPP).  The element passes read the nodal arrays they
     need (u, g, nodal fluxes, udot) and write the element data of the next
-    pass.  Flops of the line operators are those of a banded solve (about
-    8p per node, not the wider truncated-inverse apply that runs); those of
-    the element passes come from elem1_flops / elem2_flops."""
+    pass.  In the mixed form g, r, udot and the residual vectors are float
+    (4 bytes).  Flops of the line operators are those of a banded solve
+    (about 8p per node, not the wider truncated-inverse apply that runs);
+    those of the element passes come from elem1_flops / elem2_flops."""
     d, p = wl.d, wl.p
     nl = (p + 1) ** d
     kn = d * m * N if wl.kind == "kpp" else 0        # nodal fluxes of KPP
-    f8 = 8.0
-    if name in ("grad_line", "mass_line"):
-        return 2 * m * N * f8, 8 * p * m * N
+    f8, fr = 8.0, (4.0 if mixed else 8.0)             # state / intermediates
+    if name == "grad_line":
+        return m * N * (f8 + fr), 8 * p * m * N
+    if name == "mass_line":
+        return 2 * m * N * fr, 8 * p * m * N
     if name == "gather_r":
-        return (m * nl * E + 2 * m * N) * f8, m * nl * E
+        return (m * nl * E + 2 * m * N) * fr, m * nl * E
     if name == "update":
         return (m * nl * E + 3 * m * N + kn) * f8, (nl + 4) * m * N
     if name == "elem1":
-        return (((1 + d) * m * N + kn) + (m * nl + d * m + 3 + 2 * m) * E) * f8, E * elem1_flops(d, p, m, wl.kind)
+        rd = (m * N + kn) * f8 + d * m * N * fr
+        wr = m * nl * E * fr + (d * m + 3 + 2 * m) * E * f8
+        return rd + wr, E * elem1_flops(d, p, m, wl.kind)
     if name == "elem2":
-        rd = 2 * m * N + kn + (m * nl + d * m + 2 * m + 1) * E
-        return (rd + (m * nl + m + 1) * E) * f8, E * elem2_flops(d, p, m, wl.kind)
+        rd = (m * N + kn + (d * m + 2 * m + 1) * E) * f8 + (m * N + m * nl * E) * fr
+        return rd + (m * nl + m + 1) * E * f8, E * elem2_flops(d, p, m, wl.kind)
     return 0.0, 0.0
 
 
@@ -111,8 +117,9 @@ def source_digest():
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
-def profile_name(wl):
-    return f"{wl.name}_{'x'.join(str(k) for k in wl.n)}_q{wl.p}_stage_kernels.md"
+def profile_name(wl, precision="fp64"):
+    tag = "" if precision == "fp64" else "_mixed"
+    return f"{wl.name}_{'x'.join(str(k) for k in wl.n)}_q{wl.p}{tag}_stage_kernels.md"
 
 
 def _read_csv(path):
@@ -177,10 +184,10 @@ def summarize_profile(out_dir, dest, command, copy_bytes):
     print(f"wrote {dest}", flush=True)
 
 
-def profiled_traffic(wl, kernel_names):
+def profiled_traffic(wl, kernel_names, precision="fp64"):
     """Bytes per launch of the dominant kernel from the committed counter
     summary, or None when it is missing or was taken on other sources."""
-    path = os.path.join(PROFILE_DIR, profile_name(wl))
+    path = os.path.join(PROFILE_DIR, profile_name(wl, precision))
     if not os.path.exists(path):
         return None, None
     text = open(path).read()
@@ -247,6 +254,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="kpp2d", choices=["kpp2d", "adv1d", "euler2d", "euler3d"])
     ap.add_argument("--n", type=int, default=None, help="cells per axis (default: workload size)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="fp64, or mixed: float contractions with float64 state, limiters and dt")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -262,7 +271,7 @@ def main():
         from paper_2509_04673_amd import workloads
         kw = {} if args.n is None else dict(n=args.n)
         wl = workloads.make(args.workload, seed=0, **kw)
-        summarize_profile(args.summarize_profile, os.path.join(PROFILE_DIR, profile_name(wl)),
+        summarize_profile(args.summarize_profile, os.path.join(PROFILE_DIR, profile_name(wl, args.precision)),
                           args.profile_command, COPY_PROBE_BYTES)
         return
 
@@ -276,9 +285,10 @@ def main():
 
     kw = {} if args.n is None else dict(n=args.n)
     wl = workloads.make(args.workload, seed=0, **kw)
-    print(f"[bench] workload {wl.name} d={wl.d} p={wl.p} n={wl.n} dofs={wl.dofs}", flush=True)
+    print(f"[bench] workload {wl.name} d={wl.d} p={wl.p} n={wl.n} dofs={wl.dofs} "
+          f"precision={args.precision}", flush=True)
     dev = torch.device("cuda:0")
-    s = cem.Solver.from_workload(wl, device="cuda:0")
+    s = cem.Solver.from_workload(wl, device="cuda:0", precision=args.precision)
     s.upload(wl.u0)
     if wl.kind != "euler":
         s.set_bounds()
@@ -325,15 +335,17 @@ def main():
 
     stages = 3 * args.steps
     value = wl.dofs * stages / (ms * 1e-3)
-    nbytes, nflops = kernel_work(dominant, wl, s.N, s.E, s.m)
+    mixed = args.precision == "mixed"
+    nbytes, nflops = kernel_work(dominant, wl, s.N, s.E, s.m, mixed)
     kms, kcnt = kt[dominant]
     avg_s = (kms / kcnt) * 1e-3 if kcnt else float("nan")
     # the bound is the larger of the two algorithmic lower bounds
-    if nbytes / (HBM_PEAK_GBS * 1e9) >= nflops / (FP64_VECTOR_TFLOPS * 1e12):
+    fpeak = FP32_VECTOR_TFLOPS if mixed else FP64_VECTOR_TFLOPS
+    if nbytes / (HBM_PEAK_GBS * 1e9) >= nflops / (fpeak * 1e12):
         bound, achieved, peak, unit = "hbm", nbytes / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
     else:
-        bound, achieved, peak, unit = "alu", nflops / avg_s / 1e12, FP64_VECTOR_TFLOPS, "TFLOP/s"
-    traffic, prof = profiled_traffic(wl, DEVICE_KERNELS[dominant])
+        bound, achieved, peak, unit = "alu", nflops / avg_s / 1e12, fpeak, "TFLOP/s"
+    traffic, prof = profiled_traffic(wl, DEVICE_KERNELS[dominant], args.precision)
     roof = dict(bound=bound, kernel=dominant, achieved=achieved, peak=peak, unit=unit,
                 frac=achieved / peak, traffic=traffic, algorithmic_bytes=nbytes, algorithmic_flops=nflops,
                 avg_launch_us=avg_s * 1e6, launches=kcnt,
@@ -348,7 +360,8 @@ def main():
 
     out = dict(metric="DOF*RK-stage updates/s", value=value, unit="DOF*stage/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps,
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64" if args.precision == "fp64" else "f32+f64",
                data="synthetic",
                config=dict(workload=wl.name, dim=wl.d, degree=wl.p, cells=list(wl.n),
                            dofs=wl.dofs, physics=wl.kind, dt=wl.dt if wl.dt > 0 else None,

@@ -52,6 +52,15 @@ typedef enum {
 
 typedef enum { CEM_ADVECTION = 0, CEM_KPP = 1, CEM_EULER = 2 } cem_physics_kind;
 
+/* Arithmetic of a stage.  CEM_FP32_MIXED (d = 2, 3): the projected
+ * gradient and mass-solve line operators, the WENO sensor (eqs. 7-8) and the
+ * residual and element-contribution contractions (eq. 45) run in float with
+ * float accumulation, on float copies of g, r, udot and the residual
+ * vectors; the state, cell averages, facet fluxes and dt_e (eqs. 18, 40,
+ * 42, 51), both limiters (eqs. 44, 53-55, Appendix A) and the update
+ * (eq. 49) stay float64, so the invariant domain is kept exactly. */
+typedef enum { CEM_FP64 = 0, CEM_FP32_MIXED = 1 } cem_precision;
+
 /* Uniform periodic box [lo, hi] with n[k] cube cells per axis (cell edge h
  * equal on every axis; unused axes ignored).  n[k] >= 2. */
 typedef struct {
@@ -80,6 +89,7 @@ typedef struct {
   int alpha_mode;    /* flux limiter alpha_ee' (eqs. 44, 53 / Appendix A) */
   int beta_mode;     /* slope limiter beta_e (eqs. 54-55 / Appendix A) */
   double u_min, u_max; /* global bounds of scalar problems (Sec. 4.1, 4.2) */
+  int precision;       /* cem_precision */
 } cem_params;
 
 typedef struct cem_ctx cem_ctx;
@@ -98,7 +108,8 @@ typedef struct {
 } cem_invariants;
 
 /* Fills p with the defaults: q = 1, r = 2, eps = 1e-12, w_lin = 1e-3,
- * eps_pos = 1e-10, clamp_ulps = 64, all modes 0, bounds (-inf, +inf). */
+ * eps_pos = 1e-10, clamp_ulps = 64, all modes 0, bounds (-inf, +inf),
+ * precision CEM_FP64. */
 cem_status cem_params_default(cem_params* p);
 
 /* Creates a context: validates the configuration and builds the element

@@ -15,6 +15,8 @@ LIBPATH = os.path.join(HERE, "libcem.so")
 
 ADVECTION, KPP, EULER = 0, 1, 2
 KINDS = {"advection": ADVECTION, "kpp": KPP, "euler": EULER}
+FP64, FP32_MIXED = 0, 1
+PRECISIONS = {"fp64": FP64, "mixed": FP32_MIXED}
 STATUS = {0: "CEM_OK", -1: "CEM_EINVAL", -2: "CEM_EHIP", -3: "CEM_ENOMEM",
           -4: "CEM_ECFL", -5: "CEM_EIDP"}
 TAPS = dict(g=0, r=1, udot=2, gamma=3, nu=4, dt_e=5, ue=6, ubarL=7, ubar=8, beta=9,
@@ -42,7 +44,8 @@ class Params(ctypes.Structure):
                 ("w_lin", ctypes.c_double), ("eps_pos", ctypes.c_double),
                 ("clamp_ulps", ctypes.c_double), ("gamma_mode", ctypes.c_int),
                 ("alpha_mode", ctypes.c_int), ("beta_mode", ctypes.c_int),
-                ("u_min", ctypes.c_double), ("u_max", ctypes.c_double)]
+                ("u_min", ctypes.c_double), ("u_max", ctypes.c_double),
+                ("precision", ctypes.c_int)]
 
 
 class Invariants(ctypes.Structure):
@@ -225,6 +228,8 @@ class Solver:
                            gamma_gas)
         prm = cem_params_default()
         for k, v in params.items():
+            if k == "precision" and isinstance(v, str):
+                v = PRECISIONS[v]
             setattr(prm, k, v)
         self.stream = torch.cuda.current_stream(self.device)
         self.ctx = cem_create(mesh, phys, prm, self.stream.cuda_stream)

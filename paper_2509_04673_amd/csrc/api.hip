@@ -48,6 +48,10 @@ struct cem_ctx {
   std::vector<double> tabblob;     // all tables, packed
   size_t off_kg[3] = {0, 0, 0}, off_km[3] = {0, 0, 0}, off_kgf[3] = {0, 0, 0},
          off_kmf[3] = {0, 0, 0}, off_sf = 0;
+  // float copies (mixed precision), byte offsets into the table region
+  size_t boff_kg32[3] = {0, 0, 0}, boff_km32[3] = {0, 0, 0}, boff_kgf32[3] = {0, 0, 0},
+         boff_kmf32[3] = {0, 0, 0}, boff_sf32 = 0;
+  bool mixed = false;
   // bound memory
   double* u = nullptr;
   double* u0 = nullptr;
@@ -56,6 +60,7 @@ struct cem_ctx {
   // workspace carve-up (byte offsets)
   size_t o_g, o_r, o_udot, o_tmp, o_tmp2, o_relem, o_ue, o_ubarL, o_ubar, o_fahi, o_dte, o_gam,
       o_nu, o_beta, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart, o_fnode;
+  size_t o_g32 = 0, o_r32 = 0, o_udot32 = 0, o_tmp32 = 0, o_tmp2_32 = 0;
   bool fnode_valid = false;   // nodal fluxes match the bound state
   int lds_max = 65536;        // LDS bytes one block may use on the bound device
   int upd_blocks = 0, inv_blocks = 0;
@@ -111,6 +116,26 @@ void pack_tables(cem_ctx* c) {
     c->off_kgf[k] = put(T.kgrad[k].wf);
     c->off_kmf[k] = put(T.kmass[k].wf);
   }
+  // float copies of every table (the mixed-precision contractions), stored
+  // two per double word; offsets in bytes from the start of the blob
+  auto put32 = [&](size_t off, size_t n) {
+    std::vector<float> f(n);
+    for (size_t i = 0; i < n; ++i) f[i] = (float)B[off + i];
+    std::vector<double> packed((n + 1) / 2, 0.0);
+    std::memcpy(packed.data(), f.data(), n * sizeof(float));
+    return put(packed) * sizeof(double);
+  };
+  {
+    const int PP = P1 * P1;
+    const size_t nsf = 8 * (size_t)PP + T.qp.size();
+    c->boff_sf32 = put32(c->off_sf, nsf);
+  }
+  for (int k = 0; k < D; ++k) {
+    c->boff_kg32[k] = put32(c->off_kg[k], T.kgrad[k].w.size());
+    c->boff_km32[k] = put32(c->off_km[k], T.kmass[k].w.size());
+    c->boff_kgf32[k] = put32(c->off_kgf[k], T.kgrad[k].wf.size());
+    c->boff_kmf32[k] = put32(c->off_kmf[k], T.kmass[k].wf.size());
+  }
 }
 
 hipEvent_t get_event(cem_ctx* c) {
@@ -158,25 +183,25 @@ const int kWfast[5] = {0, LineTaps<1>::W, LineTaps<2>::W, LineTaps<3>::W, 0};
 const int kRfast[5] = {0, 1, 2, 3, 0};   // shortest run: RE = 1
 const int kSfast[5] = {0, LineTaps<1>::S, LineTaps<2>::S, LineTaps<3>::S, 0};
 
-template <int P>
+template <int P, class TI, class TO>
 void launch_line_fast(cem_ctx* c, int id, LineFastArgs la, hipStream_t st) {
   constexpr int W = LineTaps<P>::W;
   if (la.axis == 0 && la.L <= 4096) {
     // whole lines in LDS; one line per block unless lines are short
     la.nlb = std::max(1, std::min(2048 / la.L, (int)((la.ntrans + 511) / 512)));
-    const size_t lds = (size_t)la.nlb * la.L * sizeof(double);
+    const size_t lds = (size_t)la.nlb * la.L * sizeof(TO);
     const unsigned grid = (unsigned)((la.ntrans + la.nlb - 1) / la.nlb);
     if (la.L >= 2 * P + 2 * W)
-      CEM_LAUNCH(c, id, (k_line_x<P, 2>), grid, 256, lds, st, la);
+      CEM_LAUNCH(c, id, (k_line_x<P, 2, TI, TO>), grid, 256, lds, st, la);
     else
-      CEM_LAUNCH(c, id, (k_line_x<P, 1>), grid, 256, lds, st, la);
+      CEM_LAUNCH(c, id, (k_line_x<P, 1, TI, TO>), grid, 256, lds, st, la);
     return;
   }
   if (la.axis > 0) {
     const int RE = 1, R = P * RE, TY = 8 * R;
-    const size_t lds = (size_t)(TY + LineTaps<P>::S) * kTileX * sizeof(double);
+    const size_t lds = (size_t)(TY + LineTaps<P>::S) * kTileX * sizeof(TO);
     dim3 grid(nblocks(la.ntrans, kTileX), (unsigned)((la.L + TY - 1) / TY));
-    CEM_LAUNCH(c, id, (k_line_y<P, 1>), grid, 256, lds, st, la);
+    CEM_LAUNCH(c, id, (k_line_y<P, 1, TI, TO>), grid, 256, lds, st, la);
     return;
   }
   // longest run that still gives >= 2^17 threads (2 waves per SIMD)
@@ -187,9 +212,9 @@ void launch_line_fast(cem_ctx* c, int id, LineFastArgs la, hipStream_t st) {
   const int R = P * re;
   dim3 grid(nblocks(la.ntrans, 256), (unsigned)((la.L + R - 1) / R));
   switch (re) {
-    case 4: CEM_LAUNCH(c, id, (k_line_fast<P, 4>), grid, 256, 0, st, la); break;
-    case 2: CEM_LAUNCH(c, id, (k_line_fast<P, 2>), grid, 256, 0, st, la); break;
-    default: CEM_LAUNCH(c, id, (k_line_fast<P, 1>), grid, 256, 0, st, la); break;
+    case 4: CEM_LAUNCH(c, id, (k_line_fast<P, 4, TI, TO>), grid, 256, 0, st, la); break;
+    case 2: CEM_LAUNCH(c, id, (k_line_fast<P, 2, TI, TO>), grid, 256, 0, st, la); break;
+    default: CEM_LAUNCH(c, id, (k_line_fast<P, 1, TI, TO>), grid, 256, 0, st, la); break;
   }
 }
 
@@ -206,6 +231,12 @@ StageArgs make_args(const cem_ctx* c) {
   a.mesh.h = c->h;
   const double* tb = c->W<double>(c->o_tab);
   a.tab.sf = tb + c->off_sf;
+  a.tab.sf32 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(tb) + c->boff_sf32);
+  if (c->mixed) {
+    a.g32 = c->W<float>(c->o_g32);
+    a.r32 = c->W<float>(c->o_r32);
+    a.udot32 = c->W<float>(c->o_udot32);
+  }
   a.ph = c->ph;
   a.q = c->prm.q;
   a.rexp = c->prm.r;
@@ -241,11 +272,18 @@ StageArgs make_args(const cem_ctx* c) {
 }
 
 
-LineFastArgs line_args(const cem_ctx* c, const double* in, double* out, int axis, bool grad) {
+// line operator arguments; weights of the output type (float copies in the
+// mixed-precision form)
+template <class TO>
+LineFastArgs line_args(const cem_ctx* c, const void* in, void* out, int axis, bool grad) {
   LineFastArgs la{};
   la.in = in;
   la.out = out;
-  la.w = c->W<double>(c->o_tab) + (grad ? c->off_kgf[axis] : c->off_kmf[axis]);
+  const char* tb = c->ws + c->o_tab;
+  if (sizeof(TO) == 4)
+    la.w = tb + (grad ? c->boff_kgf32[axis] : c->boff_kmf32[axis]);
+  else
+    la.w = tb + 8 * (grad ? c->off_kgf[axis] : c->off_kmf[axis]);
   la.L = c->L[axis];
   la.axis = axis;
   la.L0 = c->L[0];
@@ -256,16 +294,17 @@ LineFastArgs line_args(const cem_ctx* c, const double* in, double* out, int axis
   return la;
 }
 
-cem_status launch_line(cem_ctx* c, const double* in, double* out, int axis, bool grad) {
+template <class TI, class TO>
+cem_status launch_line(cem_ctx* c, const TI* in, TO* out, int axis, bool grad) {
   const int id = grad ? 0 : 4;
   const LineKernel& K = grad ? c->tabs.kgrad[axis] : c->tabs.kmass[axis];
-  const double* tb = c->W<double>(c->o_tab);
+  const char* tb = c->ws + c->o_tab;
   if (K.wfast > 0) {
-    LineFastArgs la = line_args(c, in, out, axis, grad);
+    LineFastArgs la = line_args<TO>(c, in, out, axis, grad);
     switch (c->p) {
-      case 1: launch_line_fast<1>(c, id, la, c->stream); break;
-      case 2: launch_line_fast<2>(c, id, la, c->stream); break;
-      case 3: launch_line_fast<3>(c, id, la, c->stream); break;
+      case 1: launch_line_fast<1, TI, TO>(c, id, la, c->stream); break;
+      case 2: launch_line_fast<2, TI, TO>(c, id, la, c->stream); break;
+      case 3: launch_line_fast<3, TI, TO>(c, id, la, c->stream); break;
       default: return fail(CEM_EINVAL, "no fast line kernel for this degree");
     }
     HIPCHK(hipGetLastError());
@@ -274,7 +313,10 @@ cem_status launch_line(cem_ctx* c, const double* in, double* out, int axis, bool
   LineArgs la{};
   la.in = in;
   la.out = out;
-  la.w = tb + (grad ? c->off_kg[axis] : c->off_km[axis]);
+  if (sizeof(TO) == 4)
+    la.w = tb + (grad ? c->boff_kg32[axis] : c->boff_km32[axis]);
+  else
+    la.w = tb + 8 * (grad ? c->off_kg[axis] : c->off_km[axis]);
   la.taps = K.taps;
   la.first = K.first;
   la.L = c->L[axis];
@@ -283,13 +325,13 @@ cem_status launch_line(cem_ctx* c, const double* in, double* out, int axis, bool
   la.N = c->N;
   la.total = (int64_t)c->m * c->N;
   la.scale = 1.0;
-  CEM_LAUNCH(c, id, k_line, nblocks(la.total, 256), 256, 0, c->stream, la);
+  CEM_LAUNCH(c, id, (k_line<TI, TO>), nblocks(la.total, 256), 256, 0, c->stream, la);
   HIPCHK(hipGetLastError());
   return CEM_OK;
 }
 
 // element passes of systems (one thread per element and component)
-template <int D, int P, int PH>
+template <int D, int P, int PH, class RT>
 cem_status launch_sys(cem_ctx* c, StageArgs& a, bool first) {
   using TL = SysTile<D, P, PH>;
   constexpr int M = Phys<D, PH>::M, EB = TL::EB;
@@ -298,17 +340,20 @@ cem_status launch_sys(cem_ctx* c, StageArgs& a, bool first) {
   const unsigned nb = (unsigned)nblocks(c->E, EB);
   if (first) {
     a.ndtpart = (int)nb;
-    CEM_LAUNCH(c, 1, (k_elem1_sys<D, P, PH>), nb, M * EB, lds, c->stream, a);
+    CEM_LAUNCH(c, 1, (k_elem1_sys<D, P, PH, RT>), nb, M * EB, lds, c->stream, a);
   } else {
-    CEM_LAUNCH(c, 5, (k_elem2_sys<D, P, PH>), nb, M * EB, lds, c->stream, a);
+    CEM_LAUNCH(c, 5, (k_elem2_sys<D, P, PH, RT>), nb, M * EB, lds, c->stream, a);
   }
   HIPCHK(hipGetLastError());
   return CEM_OK;
 }
 
-template <int D, int P, int PH>
+// RT: value type of the contractions (double; float in the mixed form,
+// where g, r, udot and the residual vectors are float arrays)
+template <int D, int P, int PH, class RT>
 cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   constexpr int M = Phys<D, PH>::M;
+  constexpr bool MIX = sizeof(RT) == 4;
   StageArgs a = make_args(c);
   if constexpr (Phys<D, PH>::kNodal) {
     if (!c->fnode_valid) {
@@ -325,9 +370,14 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   a.ndtpart = (int)nblocks(c->E, 128);
   a.dt_fixed = dt;
   a.cfl = cfl;
+  RT* g = MIX ? (RT*)a.g32 : (RT*)a.g;
+  RT* r = MIX ? (RT*)a.r32 : (RT*)a.r;
+  RT* udot = MIX ? (RT*)a.udot32 : (RT*)a.udot;
+  RT* tmp = c->W<RT>(MIX ? c->o_tmp32 : c->o_tmp);
+  RT* tmp2 = c->W<RT>(MIX ? c->o_tmp2_32 : c->o_tmp2);
   // projected gradient g_k = M_1D^{-1} C_1D u along axis k (Sec. 2.2)
   for (int k = 0; k < D; ++k) {
-    cem_status s = launch_line(c, c->u, a.g + (int64_t)k * M * c->N, k, true);
+    cem_status s = launch_line(c, (const double*)c->u, g + (int64_t)k * M * c->N, k, true);
     if (s != CEM_OK) return s;
   }
   // element pass: sensor, residual (with the stabilisation), facet data.
@@ -337,48 +387,46 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     // 3D systems: one thread per (element, component); 2D: the LDS element
     // tile with one thread per element measured faster for both physics
     if constexpr (PH == EUL && D == 3) {
-      cem_status st = launch_sys<D, P, PH>(c, a, true);
+      cem_status st = launch_sys<D, P, PH, RT>(c, a, true);
       if (st != CEM_OK) return st;
     } else if constexpr (D == 2) {
       using TT = Tile2<P, M>;
       const int nb = ((c->n[0] + TT::TEX - 1) / TT::TEX) * ((c->n[1] + TT::TEY - 1) / TT::TEY);
       a.ndtpart = nb;
-      CEM_LAUNCH(c, 1, (k_elem1_tile<P, PH, true>), nb, 128, TT::words * sizeof(double), c->stream, a);
+      CEM_LAUNCH(c, 1, (k_elem1_tile<P, PH, true, RT>), nb, 128, TT::words * sizeof(double), c->stream, a);
     } else {
-      CEM_LAUNCH(c, 1, (k_elem1<D, P, PH, true>), nblocks(c->E, 128), 128, 0, c->stream, a);
+      CEM_LAUNCH(c, 1, (k_elem1<D, P, PH, true, RT>), nblocks(c->E, 128), 128, 0, c->stream, a);
     }
   }
   HIPCHK(hipGetLastError());
   // udot = M_C^{-1} r, one line pass per axis (Sec. 4.3, step 2); the
   // assembly of r is fused into the first pass when it runs on whole x-lines
-  double* tmp = c->W<double>(c->o_tmp);
-  double* tmp2 = c->W<double>(c->o_tmp2);
-  const double* src = a.r;
+  const RT* src = r;
   int k0 = 0;
   if (c->tabs.kmass[0].wfast > 0 && c->L[0] <= 4096) {
-    LineFastArgs la = line_args(c, a.r, D == 1 ? a.udot : tmp, 0, false);
+    LineFastArgs la = line_args<RT>(c, r, D == 1 ? udot : tmp, 0, false);
     la.nlb = std::max(1, std::min(2048 / la.L, (int)((la.ntrans + 511) / 512)));
-    const size_t lds = (size_t)la.nlb * la.L * sizeof(double);
+    const size_t lds = (size_t)la.nlb * la.L * sizeof(RT);
     const unsigned grid = (unsigned)((la.ntrans + la.nlb - 1) / la.nlb);
-    CEM_LAUNCH(c, 3, (k_gather_line_x<D, P, M, 1>), grid, 256, lds, c->stream, a, la);
+    CEM_LAUNCH(c, 3, (k_gather_line_x<D, P, M, 1, RT>), grid, 256, lds, c->stream, a, la);
     HIPCHK(hipGetLastError());
-    src = D == 1 ? a.udot : tmp;
+    src = D == 1 ? udot : tmp;
     k0 = 1;
   } else {
-    CEM_LAUNCH(c, 3, (k_gather_r<D, P, M>), nblocks(c->N, 256), 256, 0, c->stream, a);
+    CEM_LAUNCH(c, 3, (k_gather_r<D, P, M, RT>), nblocks(c->N, 256), 256, 0, c->stream, a);
     HIPCHK(hipGetLastError());
   }
   for (int k = k0; k < D; ++k) {
-    double* dst = (k == D - 1) ? a.udot : (k % 2 == 0 ? tmp : tmp2);
+    RT* dst = (k == D - 1) ? udot : (k % 2 == 0 ? tmp : tmp2);
     cem_status s = launch_line(c, src, dst, k, false);
     if (s != CEM_OK) return s;
     src = dst;
   }
   if constexpr (PH == EUL && D >= 2) {
-    cem_status st = launch_sys<D, P, PH>(c, a, false);
+    cem_status st = launch_sys<D, P, PH, RT>(c, a, false);
     if (st != CEM_OK) return st;
   } else {
-    CEM_LAUNCH(c, 5, (k_elem2<D, P, PH>), nblocks(c->E, 128), 128, 0, c->stream, a);
+    CEM_LAUNCH(c, 5, (k_elem2<D, P, PH, RT>), nblocks(c->E, 128), 128, 0, c->stream, a);
   }
   HIPCHK(hipGetLastError());
   CEM_LAUNCH(c, 6, (k_update<D, P, PH>), c->upd_blocks, 256, 0, c->stream, a);
@@ -393,17 +441,22 @@ void drop_graph(cem_ctx* c) {
   c->graph = nullptr;
 }
 
-StageFn pick(int d, int p, int kind) {
+// float64 stages for every supported (d, p, physics); the mixed-precision
+// form is built for d = 2, 3
+StageFn pick(int d, int p, int kind, bool mixed = false) {
 #define CASE(D, P, PH) \
-  if (d == D && p == P && kind == PH) return &stage_impl<D, P, PH>;
+  if (d == D && p == P && kind == PH && !mixed) return &stage_impl<D, P, PH, double>;
+#define CASEM(D, P, PH) \
+  if (d == D && p == P && kind == PH) return mixed ? &stage_impl<D, P, PH, float> : &stage_impl<D, P, PH, double>;
   CASE(1, 1, ADV) CASE(1, 2, ADV) CASE(1, 3, ADV)
   CASE(1, 1, EUL) CASE(1, 2, EUL) CASE(1, 3, EUL)
-  CASE(2, 1, ADV) CASE(2, 2, ADV) CASE(2, 3, ADV)
-  CASE(2, 1, KPP) CASE(2, 2, KPP) CASE(2, 3, KPP)
-  CASE(2, 1, EUL) CASE(2, 2, EUL) CASE(2, 3, EUL)
-  CASE(3, 1, ADV) CASE(3, 2, ADV)
-  CASE(3, 1, EUL) CASE(3, 2, EUL)
+  CASEM(2, 1, ADV) CASEM(2, 2, ADV) CASEM(2, 3, ADV)
+  CASEM(2, 1, KPP) CASEM(2, 2, KPP) CASEM(2, 3, KPP)
+  CASEM(2, 1, EUL) CASEM(2, 2, EUL) CASEM(2, 3, EUL)
+  CASEM(3, 1, ADV) CASEM(3, 2, ADV)
+  CASEM(3, 1, EUL) CASEM(3, 2, EUL)
 #undef CASE
+#undef CASEM
   return nullptr;
 }
 
@@ -432,7 +485,10 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   if (!mesh || !phys || !prm || !out) return fail(CEM_EINVAL, "null argument");
   const int d = mesh->dim, p = mesh->degree;
   if (d < 1 || d > 3) return fail(CEM_EINVAL, "dim must be 1, 2 or 3");
-  if (!pick(d, p, phys->kind)) return fail(CEM_EINVAL, "unsupported (dim, degree, physics)");
+  if (prm->precision != CEM_FP64 && prm->precision != CEM_FP32_MIXED)
+    return fail(CEM_EINVAL, "precision must be CEM_FP64 or CEM_FP32_MIXED");
+  if (!pick(d, p, phys->kind, prm->precision == CEM_FP32_MIXED))
+    return fail(CEM_EINVAL, "unsupported (dim, degree, physics, precision)");
   double h = 0.0;
   for (int k = 0; k < d; ++k) {
     if (mesh->n[k] < 2) return fail(CEM_EINVAL, "need at least 2 cells per axis");
@@ -467,6 +523,7 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->nl = 1;
   for (int k = 0; k < d; ++k) c->nl *= (p + 1);
   c->prm = *prm;
+  c->mixed = prm->precision == CEM_FP32_MIXED;
   for (int k = 0; k < 3; ++k) c->ph.vel[k] = k < d ? phys->velocity[k] : 0.0;
   c->ph.vnorm = std::sqrt(c->ph.vel[0] * c->ph.vel[0] + c->ph.vel[1] * c->ph.vel[1] + c->ph.vel[2] * c->ph.vel[2]);
   c->ph.gam = phys->gamma_gas;
@@ -509,6 +566,14 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->o_counts = take((size_t)c->upd_blocks * 2 * sizeof(int));
   c->inv_blocks = 256;
   c->o_inv = take((size_t)c->inv_blocks * (c->m * 3 + 2) * 8);
+  if (c->mixed) {
+    const size_t mN4 = (size_t)c->m * c->N * 4;
+    c->o_g32 = take((size_t)d * mN4);
+    c->o_r32 = take(mN4);
+    c->o_udot32 = take(mN4);
+    c->o_tmp32 = take(mN4);
+    c->o_tmp2_32 = take(mN4);
+  }
   c->o_tab = take(c->tabblob.size() * 8);
   c->ws_need = o;
   *out = c;
@@ -599,13 +664,13 @@ cem_status cem_rk_stage(cem_ctx* c, int stage, double dt, double cfl) {
   if (stage < 0 || stage > 2) return fail(CEM_EINVAL, "stage must be 0, 1 or 2");
   if (stage == 0 && !(dt > 0.0) && !(cfl > 0.0)) return fail(CEM_EINVAL, "need dt > 0 or cfl > 0");
   if (c->kind != CEM_EULER && !c->bounds_set) return fail(CEM_EINVAL, "scalar bounds not set");
-  return pick(c->d, c->p, c->kind)(c, stage, dt, cfl);
+  return pick(c->d, c->p, c->kind, c->mixed)(c, stage, dt, cfl);
 }
 
 static cem_status step_direct(cem_ctx* c, double dt, double cfl) {
   c->copy_base_next = true;     // stage 0 writes u_base = u (no separate copy)
   cem_status st = CEM_OK;
-  for (int s = 0; s < 3 && st == CEM_OK; ++s) st = pick(c->d, c->p, c->kind)(c, s, dt, cfl);
+  for (int s = 0; s < 3 && st == CEM_OK; ++s) st = pick(c->d, c->p, c->kind, c->mixed)(c, s, dt, cfl);
   c->copy_base_next = false;
   return st;
 }
@@ -744,6 +809,14 @@ cem_status cem_debug_tap(cem_ctx* c, int tap, double* dst, size_t count) {
   if (n == 0 || count != n) return fail(CEM_EINVAL, "bad tap id or count");
   const size_t offs[12] = {c->o_g, c->o_r, c->o_udot, c->o_gam, c->o_nu, c->o_dte,
                            c->o_ue, c->o_ubarL, c->o_ubar, c->o_beta, c->o_fahi, c->o_relem};
+  if (c->mixed && tap <= 2) {
+    // g, r and udot are float arrays in the mixed form
+    const size_t o32[3] = {c->o_g32, c->o_r32, c->o_udot32};
+    hipLaunchKernelGGL(k_widen, dim3(nblocks(n, 256)), dim3(256), 0, c->stream,
+                       c->W<const float>(o32[tap]), dst, (int64_t)n);
+    HIPCHK(hipGetLastError());
+    return CEM_OK;
+  }
   HIPCHK(hipMemcpyAsync(dst, c->ws + offs[tap], n * 8, hipMemcpyDeviceToDevice, c->stream));
   return CEM_OK;
 }

@@ -31,6 +31,7 @@ struct PhysParams {
 
 struct DevTabs {
   const double* sf;     // compact tables of the sum-factorised kernels (SFLayout)
+  const float* sf32;    // the same tables rounded to float (mixed precision)
 };
 
 // Compact tables of the sum-factorised element operators: 1D P1 x P1
@@ -48,11 +49,20 @@ extern __shared__ double cem_smem[];
 // read-only element tables (scalar loads: every lane reads the same entry)
 // The tables are read through the constant address space: they are not
 // written while a kernel runs, so uniform reads become scalar loads into
-// SGPRs instead of vector loads that occupy VGPRs.
-typedef const double __attribute__((address_space(4))) const_f64;
-template <bool LDS> struct TabRef {
-  const double* g;
-  __device__ __forceinline__ double operator()(int i) const { return ((const const_f64*)g)[i]; }
+// SGPRs instead of vector loads that occupy VGPRs.  V: double, or float for
+// the contractions of the mixed-precision form.
+template <class V> struct TabRef {
+  typedef const V __attribute__((address_space(4))) cv;
+  const V* g;
+  __device__ __forceinline__ V operator()(int i) const { return ((const cv*)g)[i]; }
+};
+
+template <class V> struct TabSel;
+template <> struct TabSel<double> {
+  __device__ static const double* of(const DevTabs& t) { return t.sf; }
+};
+template <> struct TabSel<float> {
+  __device__ static const float* of(const DevTabs& t) { return t.sf32; }
 };
 
 struct MeshArgs {
@@ -85,6 +95,10 @@ struct StageArgs {
   double* gam;          // [E] WENO sensor
   double* nu;           // [E] viscosity
   double* beta;         // [E] slope-limiter factor
+  // float intermediates of the mixed-precision form (null in float64 runs)
+  float* g32;           // [D][M][N]
+  float* r32;           // [M][N]
+  float* udot32;        // [M][N]
   double* dtbuf;        // [4]: dt, min dt_e, cfl flag, (spare)
   double* dtpart;       // per-block minima of dt_e from the element pass
   int* counts;          // per-block [2]: clamped, violations
@@ -103,15 +117,20 @@ template <int D, int PH> struct Phys;
 // flux_all(u, f): all d directional fluxes f[k * M + c] at one state.
 // kNodal: the flux is expensive enough (transcendental) that its nodal
 // values f(u_j) are computed once per node and stage and stored.
+__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+
 template <int D> struct Phys<D, ADV> {
   static constexpr int M = 1;
   static constexpr bool kNodal = false;
-  __device__ static inline void flux_all(const double* u, double* f, const PhysParams& pp) {
+  template <class T>
+  __device__ static inline void flux_all(const T* u, T* f, const PhysParams& pp) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) f[k] = pp.vel[k] * u[0];
+    for (int k = 0; k < D; ++k) f[k] = (T)pp.vel[k] * u[0];
   }
-  __device__ static inline void flux(int k, const double* u, double* f, const PhysParams& pp) {
-    f[0] = pp.vel[k] * u[0];
+  template <class T>
+  __device__ static inline void flux(int k, const T* u, T* f, const PhysParams& pp) {
+    f[0] = (T)pp.vel[k] * u[0];
   }
   __device__ static inline double node_speed(const double*, const PhysParams& pp) { return pp.vnorm; }
   __device__ static inline double riemann_speed(const double*, const double*, int k, const PhysParams& pp) {
@@ -122,14 +141,18 @@ template <int D> struct Phys<D, ADV> {
 template <int D> struct Phys<D, KPP> {
   static constexpr int M = 1;
   static constexpr bool kNodal = true;
-  __device__ static inline void flux_all(const double* u, double* f, const PhysParams&) {
-    double s, c;
-    sincos(u[0], &s, &c);
+  template <class T>
+  __device__ static inline void flux_all(const T* u, T* f, const PhysParams&) {
+    T s, c;
+    sin_cos(u[0], &s, &c);
     f[0] = s;
     f[1] = c;
   }
-  __device__ static inline void flux(int k, const double* u, double* f, const PhysParams&) {
-    f[0] = (k == 0) ? sin(u[0]) : cos(u[0]);
+  template <class T>
+  __device__ static inline void flux(int k, const T* u, T* f, const PhysParams&) {
+    T s, c;
+    sin_cos(u[0], &s, &c);
+    f[0] = (k == 0) ? s : c;
   }
   // |f'(u)| = |(cos u, -sin u)| = 1
   __device__ static inline double node_speed(const double*, const PhysParams&) { return 1.0; }
@@ -141,21 +164,24 @@ template <int D> struct Phys<D, KPP> {
 template <int D> struct Phys<D, EUL> {
   static constexpr int M = D + 2;
   static constexpr bool kNodal = false;
-  __device__ static inline double pressure(const double* u, const PhysParams& pp) {
-    double m2 = 0.0;
+  template <class T>
+  __device__ static inline T pressure(const T* u, const PhysParams& pp) {
+    T m2 = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) m2 += u[1 + k] * u[1 + k];
-    return (pp.gam - 1.0) * (u[D + 1] - 0.5 * m2 / u[0]);
+    return ((T)pp.gam - (T)1) * (u[D + 1] - (T)0.5 * m2 / u[0]);
   }
-  __device__ static inline void flux(int k, const double* u, double* f, const PhysParams& pp) {
-    const double p = pressure(u, pp);
-    const double vk = u[1 + k] / u[0];
+  template <class T>
+  __device__ static inline void flux(int k, const T* u, T* f, const PhysParams& pp) {
+    const T p = pressure(u, pp);
+    const T vk = u[1 + k] / u[0];
     f[0] = u[1 + k];
 #pragma unroll
-    for (int j = 0; j < D; ++j) f[1 + j] = u[1 + j] * vk + (j == k ? p : 0.0);
+    for (int j = 0; j < D; ++j) f[1 + j] = u[1 + j] * vk + (j == k ? p : (T)0);
     f[D + 1] = vk * (u[D + 1] + p);
   }
-  __device__ static inline void flux_all(const double* u, double* f, const PhysParams& pp) {
+  template <class T>
+  __device__ static inline void flux_all(const T* u, T* f, const PhysParams& pp) {
 #pragma unroll
     for (int k = 0; k < D; ++k) flux(k, u, f + k * M, pp);
   }
@@ -257,31 +283,36 @@ __device__ inline int64_t local_node(int loc, const int64_t (*off)[P + 1]) {
 // axis k; one thread per output value; exact periodic rows for short lines,
 // rows truncated far below rounding for long ones
 // ---------------------------------------------------------------------------
+// TI / TO: value types of the input and output arrays; the operator is
+// applied in TO (double, or float in the mixed-precision form) with weights
+// of that type
 struct LineArgs {
-  const double* in;
-  double* out;
-  const double* w;     // [P][taps]
+  const void* in;
+  void* out;
+  const void* w;       // [P][taps]
   int taps, first, L, P;
   int64_t stride, total, N;
   double scale;
 };
 
+template <class TI, class TO>
 __global__ void __launch_bounds__(256) k_line(LineArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.total) return;
+  const TI* in = static_cast<const TI*>(a.in);
   const int64_t c = t / a.N, i = t - c * a.N;
   const int64_t ik = (i / a.stride) % a.L;
   const int64_t base = c * a.N + i - ik * a.stride;
   const int cls = (int)(ik % a.P);
-  const double* w = a.w + (int64_t)cls * a.taps;
+  const TO* w = static_cast<const TO*>(a.w) + (int64_t)cls * a.taps;
   int j = (int)((ik + a.first) % a.L);
   if (j < 0) j += a.L;
-  double acc = 0.0;
+  TO acc = 0;
   for (int tt = 0; tt < a.taps; ++tt) {
-    acc += w[tt] * a.in[base + j * a.stride];
+    acc += w[tt] * (TO)in[base + j * a.stride];
     if (++j == a.L) j = 0;
   }
-  a.out[t] = a.scale * acc;
+  static_cast<TO*>(a.out)[t] = (TO)a.scale * acc;
 }
 
 // Register-blocked line operator for long lines (L >= R + TAPS): the rows of
@@ -306,18 +337,21 @@ template <> struct LineTaps<2> : LineTapsBase<2, 54> {};
 template <> struct LineTaps<3> : LineTapsBase<3, 68> {};
 
 struct LineFastArgs {
-  const double* in;
-  double* out;
-  const double* w;     // [P][S] (taps zero padded), tap t at offset t - W
+  const void* in;      // TI
+  void* out;           // TO
+  const void* w;       // TO [P][S] (taps zero padded), tap t at offset t - W
   int L, axis;
   int L0, L1;
   int64_t N, NT, ntrans;   // NT = N / L lines per component
   int nlb;                 // lines per block (axis 0 LDS kernel)
 };
 
-template <int P, int RE>
+template <int P, int RE, class TI, class TO>
 __global__ void __launch_bounds__(256) k_line_fast(LineFastArgs a) {
   constexpr int W = LineTaps<P>::W, R = P * RE, S = LineTaps<P>::S;
+  const TI* in = static_cast<const TI*>(a.in);
+  TO* out = static_cast<TO*>(a.out);
+  const TO* w = static_cast<const TO*>(a.w);
   constexpr int NB = S / R;                       // tap blocks of R (zero padded)
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ntrans) return;
@@ -339,12 +373,12 @@ __global__ void __launch_bounds__(256) k_line_fast(LineFastArgs a) {
   if (pos < 0) pos += a.L;
   // acc[r] = sum_t w[r % P][t] in[s + r + t - W]; taps are walked in blocks
   // of R with a window of 2R inputs held in registers
-  double acc[R], win[2 * R];
+  TO acc[R], win[2 * R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int r = 0; r < R; ++r) acc[r] = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    win[r] = a.in[base + (int64_t)pos * sl];
+    win[r] = (TO)in[base + (int64_t)pos * sl];
     if (++pos == a.L) pos = 0;
   }
   // unrolled so that the loads of several tap blocks are in flight at once
@@ -352,15 +386,15 @@ __global__ void __launch_bounds__(256) k_line_fast(LineFastArgs a) {
   for (int b = 0; b < NB; ++b) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      win[R + r] = a.in[base + (int64_t)pos * sl];
+      win[R + r] = (TO)in[base + (int64_t)pos * sl];
       if (++pos == a.L) pos = 0;
     }
-    const double* wb = a.w + b * R;          // weights of taps b*R .. b*R+R-1
+    const TO* wb = w + b * R;          // weights of taps b*R .. b*R+R-1
 #pragma unroll
     for (int tt = 0; tt < R; ++tt) {
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const double wv = wb[c * S + tt];
+        const TO wv = wb[c * S + tt];
 #pragma unroll
         for (int r = c; r < R; r += P) acc[r] += wv * win[r + tt];
       }
@@ -370,31 +404,31 @@ __global__ void __launch_bounds__(256) k_line_fast(LineFastArgs a) {
   }
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    if (s + r < a.L) a.out[base + (int64_t)(s + r) * sl] = acc[r];
+    if (s + r < a.L) out[base + (int64_t)(s + r) * sl] = acc[r];
 }
 
 // One run of R = P * RE outputs of a line operator: acc[r] = sum_t
 // w[r % P][t] x(s + r + t - W), with x read through ld(j) for the inputs
 // j = 0, 1, ... of the run's window (x(s - W + j)).  Taps are walked in blocks
 // of R with a 2R-input register window; weights are wave-uniform.
-template <int P, int RE, class LD>
-__device__ __forceinline__ void line_run(const double* __restrict__ w, const LD& ld, double* acc) {
+template <int P, int RE, class LD, class V>
+__device__ __forceinline__ void line_run(const V* __restrict__ w, const LD& ld, V* acc) {
   constexpr int R = P * RE, S = LineTaps<P>::S, NB = S / R;
-  double win[2 * R];
+  V win[2 * R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int r = 0; r < R; ++r) acc[r] = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) win[r] = ld(r);
 #pragma unroll 4
   for (int b = 0; b < NB; ++b) {
 #pragma unroll
     for (int r = 0; r < R; ++r) win[R + r] = ld((b + 1) * R + r);
-    const double* wb = w + b * R;
+    const V* wb = w + b * R;
 #pragma unroll
     for (int tt = 0; tt < R; ++tt) {
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const double wv = wb[c * S + tt];
+        const V wv = wb[c * S + tt];
 #pragma unroll
         for (int r = c; r < R; r += P) acc[r] += wv * win[r + tt];
       }
@@ -407,19 +441,20 @@ __device__ __forceinline__ void line_run(const double* __restrict__ w, const LD&
 // Axis 0 (contiguous lines): a block stages nlb whole lines in LDS (one
 // coalesced copy, periodic wrap inside LDS) and each thread computes runs of
 // R outputs.  Consecutive lanes take consecutive runs.
-template <int P, int RE>
+template <int P, int RE, class TI, class TO>
 __global__ void __launch_bounds__(256) k_line_x(LineFastArgs a) {
   constexpr int W = LineTaps<P>::W, R = P * RE;
   const int L = a.L;
+  TO* sm = reinterpret_cast<TO*>(cem_smem);
   const int64_t t0 = (int64_t)blockIdx.x * a.nlb;
   const int nl = (int)min((int64_t)a.nlb, a.ntrans - t0);
-  const double* src = a.in + t0 * L;          // lines of axis 0 are contiguous
-  for (int i = threadIdx.x; i < nl * L; i += blockDim.x) cem_smem[i] = src[i];
+  const TI* src = static_cast<const TI*>(a.in) + t0 * L;   // lines of axis 0 are contiguous
+  for (int i = threadIdx.x; i < nl * L; i += blockDim.x) sm[i] = (TO)src[i];
   __syncthreads();
   const int runs = (L + R - 1) / R;
   for (int g = threadIdx.x; g < nl * runs; g += blockDim.x) {
     const int line = g / runs, s = (g - line * runs) * R;
-    const double* row = cem_smem + line * L;
+    const TO* row = sm + line * L;
     int p0 = s - W;
     if (p0 < 0) p0 += L;
     auto ld = [&](int j) {
@@ -428,9 +463,9 @@ __global__ void __launch_bounds__(256) k_line_x(LineFastArgs a) {
       if (q >= L) q -= L;
       return row[q];
     };
-    double acc[R];
-    line_run<P, RE>(a.w, ld, acc);
-    double* dst = a.out + (t0 + line) * L;
+    TO acc[R];
+    line_run<P, RE>(static_cast<const TO*>(a.w), ld, acc);
+    TO* dst = static_cast<TO*>(a.out) + (t0 + line) * L;
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (s + r < L) dst[s + r] = acc[r];
@@ -441,11 +476,13 @@ __global__ void __launch_bounds__(256) k_line_x(LineFastArgs a) {
 // transverse lines x (TY + S) line positions in LDS (coalesced rows) and
 // computes TY = 8R outputs per line; a wave is 32 lines x 2 runs.
 constexpr int kTileX = 32;
-template <int P, int RE>
+template <int P, int RE, class TI, class TO>
 __global__ void __launch_bounds__(256) k_line_y(LineFastArgs a) {
   // rows: the window of the last run reads up to TY + S - 1 (zero-weight tail)
   constexpr int W = LineTaps<P>::W, R = P * RE, TY = 8 * R, ROWS = TY + LineTaps<P>::S;
   const int L = a.L;
+  TO* sm = reinterpret_cast<TO*>(cem_smem);
+  const TI* in = static_cast<const TI*>(a.in);
   const int64_t t0 = (int64_t)blockIdx.x * kTileX;
   const int s0 = blockIdx.y * TY;
   const int tx = threadIdx.x % kTileX, rg = threadIdx.x / kTileX;   // rg = 0..7
@@ -466,7 +503,7 @@ __global__ void __launch_bounds__(256) k_line_y(LineFastArgs a) {
   p += rg;
   if (p >= L) p -= L;
   for (int row = rg; row < ROWS; row += 8) {
-    cem_smem[row * kTileX + tx] = have ? a.in[b + (int64_t)p * sl] : 0.0;
+    sm[row * kTileX + tx] = have ? (TO)in[b + (int64_t)p * sl] : (TO)0;
     p += 8;
     if (p >= L) p -= L;
     if (p >= L) p -= L;
@@ -474,12 +511,13 @@ __global__ void __launch_bounds__(256) k_line_y(LineFastArgs a) {
   __syncthreads();
   const int s = s0 + rg * R;
   if (!have || s >= L) return;
-  auto ld = [&](int j) { return cem_smem[(rg * R + j) * kTileX + tx]; };
-  double acc[R];
-  line_run<P, RE>(a.w, ld, acc);
+  auto ld = [&](int j) { return sm[(rg * R + j) * kTileX + tx]; };
+  TO acc[R];
+  line_run<P, RE>(static_cast<const TO*>(a.w), ld, acc);
+  TO* out = static_cast<TO*>(a.out);
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    if (s + r < L) a.out[b + (int64_t)(s + r) * sl] = acc[r];
+    if (s + r < L) out[b + (int64_t)(s + r) * sl] = acc[r];
 }
 
 // ---------------------------------------------------------------------------
@@ -505,21 +543,21 @@ __device__ inline void block_min_dt(double* part, double v) {
 // ---------------------------------------------------------------------------
 // y = (A along axis K) x with the P1 x P1 table A at offset ao:
 // y[i] = sum_b A[i_K][b] x[i | i_K = b]  (TRN: A[b][i_K])
-template <int D, int P, int K, class TB>
-__device__ __forceinline__ void ax1(const TB& T, int ao, bool trn, const double* x, double* y) {
+template <int D, int P, int K, class TB, class V>
+__device__ __forceinline__ void ax1(const TB& T, int ao, bool trn, const V* x, V* y) {
   constexpr int P1 = P + 1, NL = ipow(P1, D), ST = ipow(P1, K);
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
     const int ai = (i / ST) % P1, i0 = i - ai * ST;
-    double s = 0.0;
+    V s = 0;
 #pragma unroll
     for (int b = 0; b < P1; ++b) s += T(ao + (trn ? b * P1 + ai : ai * P1 + b)) * x[i0 + b * ST];
     y[i] = s;
   }
 }
 
-template <int D, int P, class TB>
-__device__ __forceinline__ void ax(int k, const TB& T, int ao, bool trn, const double* x, double* y) {
+template <int D, int P, class TB, class V>
+__device__ __forceinline__ void ax(int k, const TB& T, int ao, bool trn, const V* x, V* y) {
   if (k == 0) ax1<D, P, 0>(T, ao, trn, x, y);
   else if constexpr (D > 1) {
     if (k == 1) ax1<D, P, 1>(T, ao, trn, x, y);
@@ -528,17 +566,17 @@ __device__ __forceinline__ void ax(int k, const TB& T, int ao, bool trn, const d
 }
 
 // y = (A_{D-1} (x) ... (x) A_0) x with table offsets mo[j] along axis j
-template <int D, int P, class TB>
-__device__ __forceinline__ void tensor_apply(const TB& T, const int* mo, bool trn, const double* x, double* y) {
+template <int D, int P, class TB, class V>
+__device__ __forceinline__ void tensor_apply(const TB& T, const int* mo, bool trn, const V* x, V* y) {
   constexpr int NL = ipow(P + 1, D);
   if constexpr (D == 0) {
     y[0] = x[0];
   } else {
-    double t[NL];
+    V t[NL];
     ax<D, P>(0, T, mo[0], trn, x, D == 1 ? y : t);
     if constexpr (D == 2) ax<D, P>(1, T, mo[1], trn, t, y);
     if constexpr (D == 3) {
-      double t2[NL];
+      V t2[NL];
       ax<D, P>(1, T, mo[1], trn, t, t2);
       ax<D, P>(2, T, mo[2], trn, t2, y);
     }
@@ -546,18 +584,28 @@ __device__ __forceinline__ void tensor_apply(const TB& T, const int* mo, bool tr
 }
 
 // x^T Q x with Q packed as upper-triangle rows (off-diagonals doubled)
-template <int NL, class TB>
-__device__ __forceinline__ double qsym(const TB& T, int off, const double* x) {
-  double s = 0.0;
+template <int NL, class TB, class V>
+__device__ __forceinline__ V qsym(const TB& T, int off, const V* x) {
+  V s = 0;
   int p = off;
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
-    double t = T(p++) * x[i];
+    V t = T(p++) * x[i];
 #pragma unroll
     for (int j = i + 1; j < NL; ++j) t += T(p++) * x[j];
     s += x[i] * t;
   }
   return s;
+}
+
+// int over the reference cell of d/dt_k B_i: +-1/(p+1)^(d-1) on the two
+// facets normal to axis k, 0 elsewhere (exact, used by the mixed form to
+// move the flux of the cell average between element and assembled terms)
+template <int D, int P>
+__device__ __forceinline__ double ref_grad_int(int i, int k) {
+  constexpr double w = 1.0 / ipow(P + 1, D - 1);
+  const int ik = dig(i, k, P + 1);
+  return ik == P ? w : (ik == 0 ? -w : 0.0);
 }
 
 // Node access of the element passes.  GlobalNodes gathers straight from the
@@ -593,13 +641,19 @@ template <int D, int P, int M> struct GlobalNodes {
     for (int j = 0; j < NL; ++j) cn[j] = a->u[c * a->mesh.N + local_node<D, P>(j, offn)];
   }
   __device__ __forceinline__ int64_t own_node(int j) const { return local_node<D, P>(j, off); }
-  __device__ __forceinline__ void load_grad(int c, double (*gk)[ipow(P + 1, D)]) const {
+  // projected gradient: g (float64) or g32 (mixed precision)
+  template <class V>
+  __device__ __forceinline__ void load_grad(int c, V (*gk)[ipow(P + 1, D)]) const {
     constexpr int NL = ipow(P + 1, D);
 #pragma unroll
     for (int j = 0; j < NL; ++j) {
       const int64_t nd = local_node<D, P>(j, off);
 #pragma unroll
-      for (int k = 0; k < D; ++k) gk[k][j] = a->g[((int64_t)k * M + c) * a->mesh.N + nd];
+      for (int k = 0; k < D; ++k) {
+        const int64_t q = ((int64_t)k * M + c) * a->mesh.N + nd;
+        if constexpr (sizeof(V) == 4) gk[k][j] = a->g32[q];
+        else gk[k][j] = a->g[q];
+      }
     }
   }
 };
@@ -636,25 +690,31 @@ template <int P, int M> struct TileNodes2 {
 #pragma unroll
     for (int j = 0; j < NL; ++j) cn[j] = cem_smem[c * TT::NXY + b + (j / (P + 1)) * TT::NX + j % (P + 1)];
   }
-  __device__ __forceinline__ void load_grad(int c, double (*gk)[NL]) const {
+  template <class V>
+  __device__ __forceinline__ void load_grad(int c, V (*gk)[NL]) const {
     if constexpr (TT::stage_g) {
       const double* gs = cem_smem + M * TT::NXY;
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
         for (int j = 0; j < NL; ++j)
-          gk[k][j] = gs[(k * M + c) * TT::GXY + gbase + (j / (P + 1)) * TT::GX + j % (P + 1)];
+          gk[k][j] = (V)gs[(k * M + c) * TT::GXY + gbase + (j / (P + 1)) * TT::GX + j % (P + 1)];
     } else {
       gl.load_grad(c, gk);
     }
   }
 };
 
-template <int D, int P, int PH, bool WS, class TR, class NS>
-__device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, int64_t e, const NS& ns) {
+// RT: value type of the sensor and residual contractions (double, or float
+// in the mixed-precision form); cell averages, facet data and dt_e are
+// always float64
+template <int D, int P, int PH, bool WS, class RT, class NS>
+__device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, const NS& ns) {
   using PHY = Phys<D, PH>;
   using SF = SFLayout<D, P>;
   constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NF = NL / P1;
+  constexpr bool MIX = sizeof(RT) == 4;
+  const TabRef<RT> T{TabSel<RT>::of(a.tab)};
   const MeshArgs& ms = a.mesh;
   const int64_t E = ms.E;
   const double h = ms.h;
@@ -677,23 +737,23 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
   double nbr_mean[2 * D][M];
   double gmin = 1.0;
   for (int c = 0; c < M; ++c) {
-    double ct[NL];
+    RT ct[NL];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) ct[j] = U[c][j] - U[c][0];
-    double beta[1 + 2 * D];
+    for (int j = 0; j < NL; ++j) ct[j] = (RT)(U[c][j] - U[c][0]);
+    RT beta[1 + 2 * D];
     beta[0] = qsym<NL>(T, SF::qp, ct);
-    double X[keepx ? 2 * D : 1][NL];
+    RT X[keepx ? 2 * D : 1][NL];
 #pragma unroll
     for (int l = 0; l < 2 * D; ++l) {
-      double cn[NL], sum = 0.0, xe[NL];
+      double cn[NL], sum = 0.0;
+      RT cr[NL], xe[NL];
       ns.load_nbr(c, l, cn);
 #pragma unroll
       for (int j = 0; j < NL; ++j) sum += cn[j];
       nbr_mean[l][c] = sum * (1.0 / NL);
-      const double c0 = cn[0];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) cn[j] -= c0;
-      ax<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cn, xe);
+      for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
+      ax<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cr, xe);
       beta[1 + l] = qsym<NL>(T, SF::qp, xe);
       if constexpr (keepx) {
 #pragma unroll
@@ -701,41 +761,44 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
       }
     }
     if (a.gamma_mode != 0) continue;
-    const double wl0 = 1.0 - 2 * D * a.w_lin;
-    double wt[1 + 2 * D], wsum = 0.0;
+    const RT wl0 = (RT)(1.0 - 2 * D * a.w_lin), wlin = (RT)a.w_lin, eps = (RT)a.eps;
+    RT wt[1 + 2 * D], wsum = 0;
 #pragma unroll
     for (int l = 0; l <= 2 * D; ++l) {
-      const double nr = (a.rexp == 2.0) ? beta[l] : pow(beta[l], 0.5 * a.rexp);
-      wt[l] = (l == 0 ? wl0 : a.w_lin) / (nr + a.eps);
+      const RT nr = (a.rexp == 2.0) ? beta[l] : (RT)pow((double)beta[l], 0.5 * a.rexp);
+      wt[l] = (l == 0 ? wl0 : wlin) / (nr + eps);
       wsum += wt[l];
     }
-    const double iws = 1.0 / wsum;
-    double w[NL];
+    const RT iws = (RT)1 / wsum;
+    RT w[NL];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) w[j] = 0.0;
+    for (int j = 0; j < NL; ++j) w[j] = 0;
 #pragma unroll
     for (int l = 0; l < 2 * D; ++l) {
-      const double om = wt[1 + l] * iws;
-      double xe[NL];
+      const RT om = wt[1 + l] * iws;
+      RT xe[NL];
       if constexpr (keepx) {
 #pragma unroll
         for (int j = 0; j < NL; ++j) xe[j] = X[l][j];
       } else {
         double cn[NL];
+        RT cr[NL];
         ns.load_nbr(c, l, cn);
-        const double c0 = cn[0];
 #pragma unroll
-        for (int j = 0; j < NL; ++j) cn[j] -= c0;
-        ax<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cn, xe);
+        for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
+        ax<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cr, xe);
       }
 #pragma unroll
       for (int i = 0; i < NL; ++i) w[i] += om * (ct[i] - xe[i]);
     }
     // the ratio of eq. (7) is 0/0 on constant elements; it is regularised
     // with the weights' epsilon: ||u - u*|| / (||u||^2 + eps)^(1/2)
-    const double dev = sqrt(fmax(qsym<NL>(T, SF::qp, w), 0.0));
-    const double ratio = fmin(1.0, dev / sqrt(fmax(beta[0], 0.0) + a.eps));
-    const double gc = 1.0 - (a.q == 1.0 ? ratio : pow(ratio, a.q));
+    const RT q2 = qsym<NL>(T, SF::qp, w);
+    const RT dev = sqrt(q2 > (RT)0 ? q2 : (RT)0);
+    const RT b0 = beta[0] > (RT)0 ? beta[0] : (RT)0;
+    RT ratio = dev / sqrt(b0 + eps);
+    ratio = ratio < (RT)1 ? ratio : (RT)1;
+    const double gc = 1.0 - (a.q == 1.0 ? (double)ratio : pow((double)ratio, a.q));
     gmin = fmin(gmin, gc);
   }
   const double gam = a.gamma_mode == 0 ? gmin : (a.gamma_mode == 1 ? 0.0 : 1.0);
@@ -757,16 +820,28 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
   double hpow = 1.0;
 #pragma unroll
   for (int k = 0; k < D - 1; ++k) hpow *= h;   // h^{D-1}
-  double R[M][NL];
+  // Mixed form (deviation form): the float contractions act on U - ubar and
+  // on f(u_h) - f(ubar) (fluxes evaluated in float64); a constant flux
+  // contributes exactly zero to the element residual minus the boundary
+  // integral, so float rounding scales with the variation inside the
+  // element, not with the size of u or f.
+  double foa[D * M];
+  PHY::flux_all(ue, foa, a.ph);          // fluxes of the own average
+  RT R[M][NL];
   {
-    double uq[M][NL];
+    RT uq[M][NL];
     int mv[3] = {SF::vq, SF::vq, SF::vq};
 #pragma unroll
-    for (int c = 0; c < M; ++c) tensor_apply<D, P>(T, mv, false, U[c], uq[c]);
-    double wq[NL];
+    for (int c = 0; c < M; ++c) {
+      RT uc[NL];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) uc[j] = MIX ? (RT)(U[c][j] - ue[c]) : (RT)U[c][j];
+      tensor_apply<D, P>(T, mv, false, uc, uq[c]);
+    }
+    RT wq[NL];
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
-      double wv = 1.0;
+      RT wv = 1;
 #pragma unroll
       for (int j = 0; j < D; ++j) wv *= T(SF::wq + dig(q, j, P1));
       wq[q] = wv;
@@ -774,29 +849,43 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
 #pragma unroll
     for (int c = 0; c < M; ++c)
 #pragma unroll
-      for (int i = 0; i < NL; ++i) R[c][i] = 0.0;
+      for (int i = 0; i < NL; ++i) R[c][i] = 0;
     // all directional fluxes at once when they are cheap to keep (scalar
     // problems; one sincos per point for KPP), else one direction at a time
     constexpr bool allk = (M == 1);
-    double FA[allk ? D : 1][NL];
+    RT FA[allk ? D : 1][NL];
     if constexpr (allk) {
 #pragma unroll
       for (int q = 0; q < NL; ++q) {
-        double fv[D];
-        PHY::flux_all(&uq[0][q], fv, a.ph);
+        if constexpr (MIX) {
+          double uv = ue[0] + (double)uq[0][q], fv[D];
+          PHY::flux_all(&uv, fv, a.ph);
 #pragma unroll
-        for (int kk = 0; kk < D; ++kk) FA[kk][q] = wq[q] * fv[kk];
+          for (int kk = 0; kk < D; ++kk) FA[kk][q] = wq[q] * (RT)(fv[kk] - foa[kk]);
+        } else {
+          RT fv[D];
+          PHY::flux_all(&uq[0][q], fv, a.ph);
+#pragma unroll
+          for (int kk = 0; kk < D; ++kk) FA[kk][q] = wq[q] * fv[kk];
+        }
       }
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      double F[M][NL];
+      RT F[M][NL];
 #pragma unroll
       for (int q = 0; q < NL; ++q) {
         if constexpr (allk) {
           F[0][q] = FA[k][q];
-        } else {
+        } else if constexpr (MIX) {
           double uv[M], fv[M];
+#pragma unroll
+          for (int c = 0; c < M; ++c) uv[c] = ue[c] + (double)uq[c][q];
+          PHY::flux(k, uv, fv, a.ph);
+#pragma unroll
+          for (int c = 0; c < M; ++c) F[c][q] = wq[q] * (RT)(fv[c] - foa[k * M + c]);
+        } else {
+          RT uv[M], fv[M];
 #pragma unroll
           for (int c = 0; c < M; ++c) uv[c] = uq[c][q];
           PHY::flux(k, uv, fv, a.ph);
@@ -808,35 +897,51 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
       mt[k] = SF::dq;
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        double t[NL];
+        RT t[NL];
         tensor_apply<D, P>(T, mt, true, F[c], t);
 #pragma unroll
         for (int i = 0; i < NL; ++i) R[c][i] += t[i];
       }
     }
   }
+  // element vectors are float64; in the mixed form the flux of the cell
+  // average (removed from the float contraction) is added back exactly
+  auto store_r = [&](int c, int i, RT v) {
+    const int64_t q = ((int64_t)c * NL + i) * E + e;
+    if constexpr (MIX) {
+      double fb = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) fb += foa[k * M + c] * ref_grad_int<D, P>(i, k);
+      a.relem[q] = (double)v + hpow * fb;
+    } else {
+      a.relem[q] = v;
+    }
+  };
   if constexpr (!WS) {
     // residual without the stabilisation term
 #pragma unroll
     for (int c = 0; c < M; ++c)
 #pragma unroll
-      for (int i = 0; i < NL; ++i) a.relem[((int64_t)c * NL + i) * E + e] = hpow * R[c][i];
+      for (int i = 0; i < NL; ++i) store_r(c, i, (RT)hpow * R[c][i]);
   }
-  const double sa = nu * hpow / h, sg = nu * gam * hpow;   // nu h^{D-2}, nu gamma h^{D-1}
+  const RT sa = (RT)(nu * hpow / h), sg = (RT)(nu * gam * hpow);   // nu h^{D-2}, nu gamma h^{D-1}
 #pragma unroll
   for (int c = 0; c < (WS ? M : 0); ++c) {
-    double gk[D][NL];
+    RT gk[D][NL];
     ns.load_grad(c, gk);
-    double s1[NL], s2[NL];
+    RT s1[NL], s2[NL], uc[NL];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) s1[i] = s2[i] = 0.0;
+    for (int i = 0; i < NL; ++i) {
+      s1[i] = s2[i] = 0;
+      uc[i] = MIX ? (RT)(U[c][i] - ue[c]) : (RT)U[c][i];   // the stiffness annihilates constants
+    }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       int ms1[3] = {SF::g, SF::g, SF::g}, ms2[3] = {SF::g, SF::g, SF::g};
       ms1[k] = SF::k1;
       ms2[k] = SF::ct;
-      double t[NL];
-      tensor_apply<D, P>(T, ms1, false, U[c], t);
+      RT t[NL];
+      tensor_apply<D, P>(T, ms1, false, uc, t);
 #pragma unroll
       for (int i = 0; i < NL; ++i) s1[i] += t[i];
       tensor_apply<D, P>(T, ms2, false, gk[k], t);
@@ -844,10 +949,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
       for (int i = 0; i < NL; ++i) s2[i] += t[i];
     }
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      R[c][i] = hpow * R[c][i] - (sa * s1[i] - sg * s2[i]);
-      a.relem[((int64_t)c * NL + i) * E + e] = R[c][i];
-    }
+    for (int i = 0; i < NL; ++i) store_r(c, i, (RT)hpow * R[c][i] - (sa * s1[i] - sg * s2[i]));
   }
 
   // ---- facets (Sec. 4, eqs. 18, 40, 42, 51): canonical orientation is from
@@ -855,8 +957,6 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
   double lamsum = 0.0, fLsum[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) fLsum[c] = 0.0;
-  double foa[D * M];
-  PHY::flux_all(ue, foa, a.ph);          // fluxes of the own average
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     const double* fo = foa + k * M;
@@ -911,22 +1011,20 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, const TR& T, in
   return dt_e;
 }
 
-template <int D, int P, int PH, bool WS>
+template <int D, int P, int PH, bool WS, class RT>
 __global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
-  const TabRef<false> T{a.tab.sf};
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double dt_e = 1.0e300;
-  if (e < a.mesh.E) dt_e = elem1_body<D, P, PH, WS>(a, T, e, GlobalNodes<D, P, Phys<D, PH>::M>(a, e));
+  if (e < a.mesh.E) dt_e = elem1_body<D, P, PH, WS, RT>(a, e, GlobalNodes<D, P, Phys<D, PH>::M>(a, e));
   block_min_dt(a.dtpart, dt_e);     // every thread of the block reaches this
 }
 
 // 2D element pass on a 16 x 8 element tile: the block first stages the
 // tile's nodes (one-element halo) and, when it fits, g in LDS.
-template <int P, int PH, bool WS>
+template <int P, int PH, bool WS, class RT>
 __global__ void __launch_bounds__(128) k_elem1_tile(StageArgs a) {
   constexpr int M = Phys<2, PH>::M;
   using TT = Tile2<P, M>;
-  const TabRef<false> T{a.tab.sf};
   const MeshArgs& ms = a.mesh;
   const int nbx = (ms.n[0] + TT::TEX - 1) / TT::TEX;
   const int ex0 = (blockIdx.x % nbx) * TT::TEX, ey0 = (blockIdx.x / nbx) * TT::TEY;
@@ -944,7 +1042,9 @@ __global__ void __launch_bounds__(128) k_elem1_tile(StageArgs a) {
     for (int q = threadIdx.x; q < 2 * M * TT::GXY; q += blockDim.x) {
       const int kc = q / TT::GXY, r = q - kc * TT::GXY, iy = r / TT::GX, ix = r - iy * TT::GX;
       const int gx = (P * ex0 + ix) % L0, gy = (P * ey0 + iy) % L1;
-      gs[q] = a.g[(int64_t)kc * ms.N + gx + (int64_t)L0 * gy];
+      const int64_t gi = (int64_t)kc * ms.N + gx + (int64_t)L0 * gy;
+      if constexpr (sizeof(RT) == 4) gs[q] = a.g32[gi];
+      else gs[q] = a.g[gi];
     }
   }
   __syncthreads();
@@ -953,7 +1053,7 @@ __global__ void __launch_bounds__(128) k_elem1_tile(StageArgs a) {
   double dt_e = 1.0e300;
   if (ex < ms.n[0] && ey < ms.n[1]) {
     const int64_t e = ex + (int64_t)ms.n[0] * ey;
-    dt_e = elem1_body<2, P, PH, WS>(a, T, e, TileNodes2<P, M>(a, e, tx, ty));
+    dt_e = elem1_body<2, P, PH, WS, RT>(a, e, TileNodes2<P, M>(a, e, tx, ty));
   }
   block_min_dt(a.dtpart, dt_e);     // every thread of the block reaches this
 }
@@ -1004,11 +1104,12 @@ __device__ inline void limit_facet(const StageArgs& a, int k, int64_t eL, int64_
   }
 }
 
-template <int D, int P, int PH>
+template <int D, int P, int PH, class RT>
 __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
   using PHY = Phys<D, PH>;
   constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NF = NL / P1;
-  const TabRef<false> T{a.tab.sf};
+  constexpr bool MIX = sizeof(RT) == 4;
+  const TabRef<RT> T{TabSel<RT>::of(a.tab)};
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const MeshArgs& ms = a.mesh;
   if (e >= ms.E) return;
@@ -1063,18 +1164,20 @@ __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
   double hpow = 1.0;
 #pragma unroll
   for (int k = 0; k < D - 1; ++k) hpow *= h;
-  double f[M][NL];
+  RT fb[M][NL];
 #pragma unroll
   for (int c = 0; c < M; ++c)
 #pragma unroll
-    for (int i = 0; i < NL; ++i) f[c][i] = 0.0;
+    for (int i = 0; i < NL; ++i) fb[c][i] = 0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int av = side ? P : 0;
-      const double sg = side ? hpow : -hpow;
-      double fn[M][NF > 0 ? NF : 1];
+      const RT sg = (RT)(side ? hpow : -hpow);
+      double fbar[M];                  // mixed form: flux of the cell average
+      if constexpr (MIX) PHY::flux(k, uec, fbar, a.ph);
+      RT fn[M][NF > 0 ? NF : 1];
 #pragma unroll
       for (int j = 0; j < NL; ++j) {
         if (dig(j, k, P1) != av) continue;
@@ -1091,41 +1194,73 @@ __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
           PHY::flux(k, uj, fv, a.ph);
         }
 #pragma unroll
-        for (int c = 0; c < M; ++c) fn[c][fj] = fv[c];
+        for (int c = 0; c < M; ++c) fn[c][fj] = MIX ? (RT)(fv[c] - fbar[c]) : (RT)fv[c];
       }
       const int mg[3] = {SF::g, SF::g, SF::g};
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        double t[NF > 0 ? NF : 1];
+        RT t[NF > 0 ? NF : 1];
         tensor_apply<D - 1, P>(T, mg, false, fn[c], t);
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
           if (dig(i, k, P1) != av) continue;
           const int fi = i % ipow(P1, k) + (i / ipow(P1, k + 1)) * ipow(P1, k);
-          f[c][i] += sg * t[fi];
+          fb[c][i] += sg * t[fi];
         }
       }
     }
   }
   double hd = hpow * h;
   const double mloc = hd * (1.0 / NL);
-  // f currently holds B_i; build f_i^e of eq. (45) in place
+  // f_i^e of eq. (45): the contraction terms in RT, their sum promoted.  In
+  // the mixed form the terms' element sum (zero in exact arithmetic, eq. 47)
+  // is removed in float64 so that the update stays conservative to float64
+  // round-off.
+  double f[M][NL];
 #pragma unroll
   for (int c = 0; c < M; ++c) {
-    double Fe = 0.0;
+    RT Fe = 0;
 #pragma unroll
-    for (int i = 0; i < NL; ++i) Fe += f[c][i];
-    double ud[NL], mu[NL];
+    for (int i = 0; i < NL; ++i) Fe += fb[c][i];
+    RT ud[NL], mu[NL];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) ud[j] = a.udot[c * N + local_node<D, P>(j, off)];
+    for (int j = 0; j < NL; ++j) {
+      const int64_t q = c * N + local_node<D, P>(j, off);
+      if constexpr (MIX) ud[j] = a.udot32[q];
+      else ud[j] = a.udot[q];
+    }
     const int mg[3] = {SF::g, SF::g, SF::g};
     tensor_apply<D, P>(T, mg, false, ud, mu);
+    double fbar[D];                 // mixed form: fluxes of the cell average
+    if constexpr (MIX) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double fk[M];
+        PHY::flux(k, uec, fk, a.ph);
+        fbar[k] = fk[c];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      const double Tc = hd * mu[i] - mloc * ud[i];
+      const RT Tc = (RT)hd * mu[i] - (RT)mloc * ud[i];
       const double R = a.relem[((int64_t)c * NL + i) * E + e];
-      f[c][i] = mloc * (U[c][i] - uec[c]) + dt_e * (R - f[c][i] + Fe * (1.0 / NL) - Tc);
+      if constexpr (MIX) {
+        double rb = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) rb += fbar[k] * ref_grad_int<D, P>(i, k);
+        f[c][i] = (R - hpow * rb) + (double)(-fb[c][i] + Fe * (RT)(1.0 / NL) - Tc);
+      } else {
+        f[c][i] = (double)(R - fb[c][i] + Fe * (RT)(1.0 / NL) - Tc);
+      }
     }
+    double zs = 0.0;
+    if constexpr (MIX) {
+#pragma unroll
+      for (int i = 0; i < NL; ++i) zs += f[c][i];
+      zs *= 1.0 / NL;
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) f[c][i] = mloc * (U[c][i] - uec[c]) + dt_e * (f[c][i] - zs);
   }
 
   // ---- slope limiter
@@ -1210,7 +1345,17 @@ __device__ inline int node_elements(int64_t i, const MeshArgs& m, int64_t* eids,
   return nrec;
 }
 
-template <int D, int P, int M>
+// RT: value type of the assembled residual r (float in the mixed form); the
+// element vectors are float64 and summed in float64
+template <class RT> struct ResPtr;
+template <> struct ResPtr<double> {
+  __device__ static double* r(const StageArgs& a) { return a.r; }
+};
+template <> struct ResPtr<float> {
+  __device__ static float* r(const StageArgs& a) { return a.r32; }
+};
+
+template <int D, int P, int M, class RT>
 __global__ void __launch_bounds__(256) k_gather_r(StageArgs a) {
   constexpr int NL = ipow(P + 1, D);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1219,11 +1364,12 @@ __global__ void __launch_bounds__(256) k_gather_r(StageArgs a) {
   int locs[8];
   const int nrec = node_elements<D, P>(i, a.mesh, eids, locs);
   const int64_t E = a.mesh.E, N = a.mesh.N;
+  RT* r = ResPtr<RT>::r(a);
 #pragma unroll
   for (int c = 0; c < M; ++c) {
     double s = 0.0;
     for (int t = 0; t < nrec; ++t) s += a.relem[((int64_t)c * NL + locs[t]) * E + eids[t]];
-    a.r[c * N + i] = s;
+    r[c * N + i] = (RT)s;
   }
 }
 
@@ -1357,10 +1503,12 @@ __global__ void __launch_bounds__(1024) k_min_dt(const double* __restrict__ dte,
 // gathers r = sum_e (element residual vectors) for nlb whole x-lines into LDS
 // (fixed element order per node, as k_gather_r), stores r, then applies the
 // axis-0 line operator.
-template <int D, int P, int M, int RE>
+template <int D, int P, int M, int RE, class RT>
 __global__ void __launch_bounds__(256) k_gather_line_x(StageArgs sa, LineFastArgs a) {
   constexpr int W = LineTaps<P>::W, R = P * RE, NL = ipow(P + 1, D);
   const int L = a.L;
+  RT* sm = reinterpret_cast<RT*>(cem_smem);
+  RT* rr = ResPtr<RT>::r(sa);
   const int64_t t0 = (int64_t)blockIdx.x * a.nlb;
   const int nl = (int)min((int64_t)a.nlb, a.ntrans - t0);
   const int64_t E = sa.mesh.E, N = sa.mesh.N;
@@ -1372,14 +1520,14 @@ __global__ void __launch_bounds__(256) k_gather_line_x(StageArgs sa, LineFastArg
     const int nrec = node_elements<D, P>(i, sa.mesh, eids, locs);
     double s = 0.0;
     for (int t = 0; t < nrec; ++t) s += sa.relem[(c * NL + locs[t]) * E + eids[t]];
-    cem_smem[q] = s;
-    sa.r[g] = s;
+    sm[q] = (RT)s;
+    rr[g] = (RT)s;
   }
   __syncthreads();
   const int runs = (L + R - 1) / R;
   for (int g = threadIdx.x; g < nl * runs; g += blockDim.x) {
     const int line = g / runs, s = (g - line * runs) * R;
-    const double* row = cem_smem + line * L;
+    const RT* row = sm + line * L;
     int p0 = s - W;
     if (p0 < 0) p0 += L;
     auto ld = [&](int j) {
@@ -1388,13 +1536,19 @@ __global__ void __launch_bounds__(256) k_gather_line_x(StageArgs sa, LineFastArg
       if (q >= L) q -= L;
       return row[q];
     };
-    double acc[R];
-    line_run<P, RE>(a.w, ld, acc);
-    double* dst = a.out + (t0 + line) * L;
+    RT acc[R];
+    line_run<P, RE>(static_cast<const RT*>(a.w), ld, acc);
+    RT* dst = static_cast<RT*>(a.out) + (t0 + line) * L;
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (s + r < L) dst[s + r] = acc[r];
   }
+}
+
+// float -> double copy (debug taps of the mixed-precision intermediates)
+__global__ void __launch_bounds__(256) k_widen(const float* in, double* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
 }
 
 // ---------------------------------------------------------------------------

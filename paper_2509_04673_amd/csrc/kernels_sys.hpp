@@ -40,9 +40,9 @@ template <int D, int P, int PH> struct SysTile {
 
 // component c of a value array computed for all components (a select chain:
 // no dynamically indexed register array)
-template <int M>
-__device__ __forceinline__ double pick_c(const double* v, int c) {
-  double r = v[0];
+template <int M, class V>
+__device__ __forceinline__ V pick_c(const V* v, int c) {
+  V r = v[0];
 #pragma unroll
   for (int k = 1; k < M; ++k)
     if (c == k) r = v[k];
@@ -51,16 +51,16 @@ __device__ __forceinline__ double pick_c(const double* v, int c) {
 
 // v[i] for a runtime i < K, and v[i] = x, without a dynamically indexed
 // register array (which would live in scratch)
-template <int K>
-__device__ __forceinline__ double get_sel(const double* v, int i) {
-  double r = v[0];
+template <int K, class V>
+__device__ __forceinline__ V get_sel(const V* v, int i) {
+  V r = v[0];
 #pragma unroll
   for (int k = 1; k < K; ++k)
     if (i == k) r = v[k];
   return r;
 }
-template <int K>
-__device__ __forceinline__ void set_sel(double* v, int i, double x) {
+template <int K, class V>
+__device__ __forceinline__ void set_sel(V* v, int i, V x) {
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (i == k) v[k] = x;
@@ -68,18 +68,18 @@ __device__ __forceinline__ void set_sel(double* v, int i, double x) {
 
 // x <- (A along axis K) x in place, one line of P+1 values at a time (the
 // same sums as ax1 with a (P+1)-value temporary instead of a second array)
-template <int D, int P, int K, class TB>
-__device__ __forceinline__ void ax_ip1(const TB& T, int ao, bool trn, double* x) {
+template <int D, int P, int K, class TB, class V>
+__device__ __forceinline__ void ax_ip1(const TB& T, int ao, bool trn, V* x) {
   constexpr int P1 = P + 1, NL = ipow(P1, D), ST = ipow(P1, K);
 #pragma unroll
   for (int i0 = 0; i0 < NL; ++i0) {
     if ((i0 / ST) % P1 != 0) continue;   // i0 starts a line along axis K
-    double v[P1];
+    V v[P1];
 #pragma unroll
     for (int b = 0; b < P1; ++b) v[b] = x[i0 + b * ST];
 #pragma unroll
     for (int ai = 0; ai < P1; ++ai) {
-      double s = 0.0;
+      V s = 0;
 #pragma unroll
       for (int b = 0; b < P1; ++b) s += T(ao + (trn ? b * P1 + ai : ai * P1 + b)) * v[b];
       x[i0 + ai * ST] = s;
@@ -87,8 +87,8 @@ __device__ __forceinline__ void ax_ip1(const TB& T, int ao, bool trn, double* x)
   }
 }
 
-template <int D, int P, class TB>
-__device__ __forceinline__ void ax_ip(int k, const TB& T, int ao, bool trn, double* x) {
+template <int D, int P, class TB, class V>
+__device__ __forceinline__ void ax_ip(int k, const TB& T, int ao, bool trn, V* x) {
   if (k == 0) ax_ip1<D, P, 0>(T, ao, trn, x);
   else if constexpr (D > 1) {
     if (k == 1) ax_ip1<D, P, 1>(T, ao, trn, x);
@@ -97,8 +97,8 @@ __device__ __forceinline__ void ax_ip(int k, const TB& T, int ao, bool trn, doub
 }
 
 // x <- (A_{D-1} (x) ... (x) A_0) x in place, axis 0 first (as tensor_apply)
-template <int D, int P, class TB>
-__device__ __forceinline__ void tensor_ip(const TB& T, const int* mo, bool trn, double* x) {
+template <int D, int P, class TB, class V>
+__device__ __forceinline__ void tensor_ip(const TB& T, const int* mo, bool trn, V* x) {
   if constexpr (D >= 1) ax_ip1<D, P, 0>(T, mo[0], trn, x);
   if constexpr (D >= 2) ax_ip1<D, P, 1>(T, mo[1], trn, x);
   if constexpr (D >= 3) ax_ip1<D, P, 2>(T, mo[2], trn, x);
@@ -107,17 +107,17 @@ __device__ __forceinline__ void tensor_ip(const TB& T, const int* mo, bool trn, 
 // component c of the Euler flux along axis k (both may be runtime values):
 // the same operations as Phys<D, EUL>::flux, written with selects so that
 // no register array is indexed dynamically
-template <int D>
-__device__ __forceinline__ double euler_flux_comp(int k, int c, const double* u, double gam) {
-  double mk = u[1];
+template <int D, class V>
+__device__ __forceinline__ V euler_flux_comp(int k, int c, const V* u, double gam) {
+  V mk = u[1];
   if (D > 1 && k == 1) mk = u[2];
   if (D > 2 && k == 2) mk = u[3];
-  double m2 = 0.0;
+  V m2 = 0;
 #pragma unroll
   for (int j = 0; j < D; ++j) m2 += u[1 + j] * u[1 + j];
-  const double p = (gam - 1.0) * (u[D + 1] - 0.5 * m2 / u[0]);
-  const double vk = mk / u[0];
-  double r = pick_c<D + 2>(u, c) * vk + (c - 1 == k ? p : 0.0);
+  const V p = ((V)gam - (V)1) * (u[D + 1] - (V)0.5 * m2 / u[0]);
+  const V vk = mk / u[0];
+  V r = pick_c<D + 2>(u, c) * vk + (c - 1 == k ? p : (V)0);
   if (c == 0) r = mk;
   if (c == D + 1) r = vk * (u[D + 1] + p);
   return r;
@@ -142,14 +142,15 @@ __device__ __forceinline__ void block_min_dt_sys(double* red, double* part, int 
   }
 }
 
-template <int D, int P, int PH>
+template <int D, int P, int PH, class RT>
 __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_elem1_sys(StageArgs a) {
   static_assert(PH == EUL, "system element pass 1 is written for the Euler equations");
   using PHY = Phys<D, PH>;
   using SF = SFLayout<D, P>;
   using LY = typename SysTile<D, P, PH>::LY;
   constexpr int EB = LY::EB, P1 = P + 1, NL = LY::NL, M = LY::M, NF = NL / P1, CS = M * EB;
-  const TabRef<false> T{a.tab.sf};
+  constexpr bool MIX = sizeof(RT) == 4;
+  const TabRef<RT> T{TabSel<RT>::of(a.tab)};
   const MeshArgs& ms = a.mesh;
   const int64_t E = ms.E, N = ms.N;
   const double h = ms.h;
@@ -179,12 +180,12 @@ __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_el
   // candidates' loads together and runs out of registers.
   double gc = 1.0;
   {
-    double beta0, betan[2 * D];
+    RT beta0, betan[2 * D];
     {
-      double x[NL];
+      RT x[NL];
       const double u0 = Us[0];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) x[j] = Us[j * CS] - u0;
+      for (int j = 0; j < NL; ++j) x[j] = (RT)(Us[j * CS] - u0);
       beta0 = qsym<NL>(T, SF::qp, x);
     }
 #pragma unroll 1
@@ -194,42 +195,45 @@ __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_el
 #pragma unroll
       for (int j = 0; j < NL; ++j) sum += cn[j];
       S[LY::oNm + (l * M + c) * EB + le] = sum * (1.0 / NL);
-      const double c0 = cn[0];
+      RT cr[NL];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) cn[j] -= c0;
-      ax_ip<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cn);
-      set_sel<2 * D>(betan, l, qsym<NL>(T, SF::qp, cn));
+      for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
+      ax_ip<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cr);
+      set_sel<2 * D>(betan, l, qsym<NL>(T, SF::qp, cr));
     }
     if (a.gamma_mode == 0) {
-      auto nrm = [&](double b) { return (a.rexp == 2.0) ? b : pow(b, 0.5 * a.rexp); };
-      double wt[2 * D];
-      double wsum = (1.0 - 2 * D * a.w_lin) / (nrm(beta0) + a.eps);
+      auto nrm = [&](RT b) { return (a.rexp == 2.0) ? b : (RT)pow((double)b, 0.5 * a.rexp); };
+      const RT eps = (RT)a.eps, wlin = (RT)a.w_lin;
+      RT wt[2 * D];
+      RT wsum = (RT)(1.0 - 2 * D * a.w_lin) / (nrm(beta0) + eps);
 #pragma unroll
       for (int l = 0; l < 2 * D; ++l) {
-        wt[l] = a.w_lin / (nrm(betan[l]) + a.eps);
+        wt[l] = wlin / (nrm(betan[l]) + eps);
         wsum += wt[l];
       }
-      const double iws = 1.0 / wsum;
-      double w[NL];
+      const RT iws = (RT)1 / wsum;
+      RT w[NL];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) w[j] = 0.0;
+      for (int j = 0; j < NL; ++j) w[j] = 0;
       const double u0 = Us[0];
 #pragma unroll 1
       for (int l = 0; l < 2 * D; ++l) {
-        const double om = get_sel<2 * D>(wt, l) * iws;
+        const RT om = get_sel<2 * D>(wt, l) * iws;
         double cn[NL];
         ns.load_nbr(c, l, cn);
-        const double c0 = cn[0];
+        RT cr[NL];
 #pragma unroll
-        for (int j = 0; j < NL; ++j) cn[j] -= c0;
-        ax_ip<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cn);
+        for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
+        ax_ip<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cr);
 #pragma unroll
-        for (int i = 0; i < NL; ++i) w[i] += om * ((Us[i * CS] - u0) - cn[i]);
+        for (int i = 0; i < NL; ++i) w[i] += om * ((RT)(Us[i * CS] - u0) - cr[i]);
       }
       // 0/0 on constant elements, regularised with the weights' epsilon
-      const double dev = sqrt(fmax(qsym<NL>(T, SF::qp, w), 0.0));
-      const double ratio = fmin(1.0, dev / sqrt(fmax(beta0, 0.0) + a.eps));
-      gc = 1.0 - (a.q == 1.0 ? ratio : pow(ratio, a.q));
+      const RT q2 = qsym<NL>(T, SF::qp, w);
+      const RT dev = sqrt(q2 > (RT)0 ? q2 : (RT)0);
+      RT ratio = dev / sqrt((beta0 > (RT)0 ? beta0 : (RT)0) + eps);
+      ratio = ratio < (RT)1 ? ratio : (RT)1;
+      gc = 1.0 - (a.q == 1.0 ? (double)ratio : pow((double)ratio, a.q));
     }
   }
   S[LY::oUe + c * EB + le] = ue_c;
@@ -323,63 +327,91 @@ __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_el
   double hpow = 1.0;
 #pragma unroll
   for (int k = 0; k < D - 1; ++k) hpow *= h;   // h^{D-1}
-  double R[NL];
+  RT R[NL];
   {
-    const double sa = nu * hpow / h, sg = nu * gam * hpow;
+    const RT sa = (RT)(nu * hpow / h), sg = (RT)(nu * gam * hpow);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) R[i] = 0.0;
+    for (int i = 0; i < NL; ++i) R[i] = 0;
     // not unrolled: unrolled, all D (p+1)^d gradient loads are issued up
     // front and spilled
 #pragma unroll 1
     for (int k = 0; k < D; ++k) {
       const int ms1[3] = {k == 0 ? SF::k1 : SF::g, k == 1 ? SF::k1 : SF::g, k == 2 ? SF::k1 : SF::g};
       const int ms2[3] = {k == 0 ? SF::ct : SF::g, k == 1 ? SF::ct : SF::g, k == 2 ? SF::ct : SF::g};
-      double t[NL];
+      RT t[NL];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) t[j] = Us[j * CS];
+      for (int j = 0; j < NL; ++j) t[j] = MIX ? (RT)(Us[j * CS] - ue_c) : (RT)Us[j * CS];
       tensor_ip<D, P>(T, ms1, false, t);
 #pragma unroll
       for (int i = 0; i < NL; ++i) R[i] -= sa * t[i];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) t[j] = a.g[((int64_t)k * M + c) * N + ns.own_node(j)];
+      for (int j = 0; j < NL; ++j) {
+        const int64_t q = ((int64_t)k * M + c) * N + ns.own_node(j);
+        if constexpr (MIX) t[j] = a.g32[q];
+        else t[j] = a.g[q];
+      }
       tensor_ip<D, P>(T, ms2, false, t);
 #pragma unroll
       for (int i = 0; i < NL; ++i) R[i] += sg * t[i];
     }
   }
   {
-    double uq[NL];
+    // mixed form: interpolate U - ubar in float, keep the states in float64
+    RT uq[NL];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) uq[j] = Us[j * CS];
+    for (int j = 0; j < NL; ++j) uq[j] = MIX ? (RT)(Us[j * CS] - ue_c) : (RT)Us[j * CS];
     const int mv[3] = {SF::vq, SF::vq, SF::vq};
     tensor_ip<D, P>(T, mv, false, uq);
     __syncthreads();    // every thread is done with the nodal states
 #pragma unroll
-    for (int q = 0; q < NL; ++q) Us[q * CS] = uq[q];
+    for (int q = 0; q < NL; ++q) Us[q * CS] = MIX ? ue_c + (double)uq[q] : (double)uq[q];
   }
   __syncthreads();
   // flux term, one axis at a time (a rolled loop: unrolled, the axes'
   // Gauss-point work is interleaved and runs out of registers)
 #pragma unroll 1
   for (int k = 0; k < D; ++k) {
-    double F[NL];
+    RT F[NL];
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
-      double wv = 1.0;
+      RT wv = 1;
 #pragma unroll
       for (int j = 0; j < D; ++j) wv *= T(SF::wq + dig(q, j, P1));
-      double uv[M];
-      state_at<M, EB>(S, q, le, uv);
-      F[q] = wv * euler_flux_comp<D>(k, c, uv, a.ph.gam);
+      if constexpr (MIX) {
+        // flux deviation from the cell average's flux, evaluated in float64
+        double uv[M];
+#pragma unroll
+        for (int kk = 0; kk < M; ++kk) uv[kk] = S[(q * M + kk) * EB + le];
+        F[q] = wv * (RT)(euler_flux_comp<D>(k, c, uv, a.ph.gam) - euler_flux_comp<D>(k, c, uo, a.ph.gam));
+      } else {
+        RT uv[M];
+#pragma unroll
+        for (int kk = 0; kk < M; ++kk) uv[kk] = (RT)S[(q * M + kk) * EB + le];
+        F[q] = wv * euler_flux_comp<D>(k, c, uv, a.ph.gam);
+      }
     }
     const int mt[3] = {k == 0 ? SF::dq : SF::vq, k == 1 ? SF::dq : SF::vq, k == 2 ? SF::dq : SF::vq};
     tensor_ip<D, P>(T, mt, true, F);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) R[i] += hpow * F[i];
+    for (int i = 0; i < NL; ++i) R[i] += (RT)hpow * F[i];
   }
   if (live) {
+    // element vectors are float64; the mixed form adds back the flux of the
+    // cell average removed from the float contraction
+    double fbk[D];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) a.relem[((int64_t)c * NL + i) * E + e] = R[i];
+    for (int k = 0; k < D; ++k) fbk[k] = MIX ? euler_flux_comp<D>(k, c, uo, a.ph.gam) : 0.0;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      double v = (double)R[i];
+      if constexpr (MIX) {
+        double fb = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) fb += fbk[k] * ref_grad_int<D, P>(i, k);
+        v += hpow * fb;
+      }
+      a.relem[((int64_t)c * NL + i) * E + e] = v;
+    }
   }
   block_min_dt_sys<EB>(S + LY::oRed, a.dtpart, c, le, live ? dt_e : 1.0e300);
 }
@@ -406,14 +438,15 @@ __device__ inline double euler_facet_alpha(const StageArgs& a, int k, int64_t eL
   return fmin(euler_alpha<D>(uLs, dL, 1.0, a.eps_pos), euler_alpha<D>(uRs, dR, 1.0, a.eps_pos));
 }
 
-template <int D, int P, int PH>
+template <int D, int P, int PH, class RT>
 __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_elem2_sys(StageArgs a) {
   static_assert(PH == EUL, "system element pass 2 is written for the Euler equations");
   using PHY = Phys<D, PH>;
   using SF = SFLayout<D, P>;
   using LY = typename SysTile<D, P, PH>::LY;
   constexpr int EB = LY::EB, P1 = P + 1, NL = LY::NL, M = LY::M, NF = NL / P1, CS = M * EB;
-  const TabRef<false> T{a.tab.sf};
+  constexpr bool MIX = sizeof(RT) == 4;
+  const TabRef<RT> T{TabSel<RT>::of(a.tab)};
   const MeshArgs& ms = a.mesh;
   const int64_t E = ms.E, N = ms.N;
   const double h = ms.h;
@@ -460,20 +493,25 @@ __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_el
   S[LY::oUb + c * EB + le] = ub_c;
   if (live) a.ubar[c * E + e] = ub_c;
 
-  // ---- boundary integral B_i = int_{dK} phi_i f_h . n of component c
+  // ---- boundary integral B_i = int_{dK} phi_i f_h . n of component c (the
+  // mixed form integrates f_h - f(ubar), its contraction partner)
+  double ueall[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) ueall[k] = a.ue[k * E + e];
   double hpow = 1.0;
 #pragma unroll
   for (int k = 0; k < D - 1; ++k) hpow *= h;
-  double f[NL];
+  RT fb[NL];
 #pragma unroll
-  for (int i = 0; i < NL; ++i) f[i] = 0.0;
+  for (int i = 0; i < NL; ++i) fb[i] = 0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int av = side ? P : 0;
-      const double sg = side ? hpow : -hpow;
-      double fn[NF];
+      const RT sg = (RT)(side ? hpow : -hpow);
+      const double fbar = MIX ? euler_flux_comp<D>(k, c, ueall, a.ph.gam) : 0.0;
+      RT fn[NF];
 #pragma unroll
       for (int j = 0; j < NL; ++j) {
         if (dig(j, k, P1) != av) continue;
@@ -481,7 +519,7 @@ __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_el
         double uj[M], fv[M];
         state_at<M, EB>(S, j, le, uj);
         PHY::flux(k, uj, fv, a.ph);
-        fn[fj] = pick_c<M>(fv, c);
+        fn[fj] = (RT)(pick_c<M>(fv, c) - fbar);
       }
       const int mg[3] = {SF::g, SF::g, SF::g};
       tensor_ip<D - 1, P>(T, mg, false, fn);
@@ -489,28 +527,52 @@ __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_el
       for (int i = 0; i < NL; ++i) {
         if (dig(i, k, P1) != av) continue;
         const int fi = i % ipow(P1, k) + (i / ipow(P1, k + 1)) * ipow(P1, k);
-        f[i] += sg * fn[fi];
+        fb[i] += sg * fn[fi];
       }
     }
   }
   // ---- element contributions f_i^e of eq. (45); dU_i = m_i^e (ubar - u_i)
   const double hd = hpow * h, mloc = hd * (1.0 / NL);
-  double dU[NL];
+  double dU[NL], f[NL];
   {
-    double Fe = 0.0;
+    RT Fe = 0;
 #pragma unroll
-    for (int i = 0; i < NL; ++i) Fe += f[i];
-    double mu[NL];
+    for (int i = 0; i < NL; ++i) Fe += fb[i];
+    auto udot_at = [&](int j) -> RT {
+      const int64_t q = c * N + ns.own_node(j);
+      if constexpr (MIX) return a.udot32[q];
+      else return a.udot[q];
+    };
+    RT mu[NL];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) mu[j] = a.udot[c * N + ns.own_node(j)];
+    for (int j = 0; j < NL; ++j) mu[j] = udot_at(j);
     const int mg[3] = {SF::g, SF::g, SF::g};
     tensor_ip<D, P>(T, mg, false, mu);
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      const double Tc = hd * mu[i] - mloc * a.udot[c * N + ns.own_node(i)];
+      const RT Tc = (RT)hd * mu[i] - (RT)mloc * udot_at(i);
       const double R = a.relem[((int64_t)c * NL + i) * E + e];
+      if constexpr (MIX) {
+        double rb = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) rb += euler_flux_comp<D>(k, c, ueall, a.ph.gam) * ref_grad_int<D, P>(i, k);
+        f[i] = (R - hpow * rb) + (double)(-fb[i] + Fe * (RT)(1.0 / NL) - Tc);
+      } else {
+        f[i] = (double)(R - fb[i] + Fe * (RT)(1.0 / NL) - Tc);
+      }
+    }
+    // mixed form: remove the float rounding of the element sum of the
+    // contraction terms (zero in exact arithmetic, eq. 47)
+    double zs = 0.0;
+    if constexpr (MIX) {
+#pragma unroll
+      for (int i = 0; i < NL; ++i) zs += f[i];
+      zs *= 1.0 / NL;
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
       const double Ui = Us[i * CS];
-      f[i] = mloc * (Ui - ue_c) + dt_e * (R - f[i] + Fe * (1.0 / NL) - Tc);
+      f[i] = mloc * (Ui - ue_c) + dt_e * (f[i] - zs);
       dU[i] = mloc * (ub_c - Ui);
     }
   }

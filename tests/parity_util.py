@@ -14,6 +14,22 @@ def rel_linf(a, b):
     return float(np.max(np.abs(a - b)) / (scale if scale > 0 else 1.0))
 
 
+def rel_l1(a, b, mass):
+    """max over components of sum_i m_i |a - b| / sum_i m_i |b| (lumped
+    nodal masses m_i)."""
+    a = np.asarray(a, dtype=np.float64).reshape(-1, mass.size)
+    b = np.asarray(b, dtype=np.float64).reshape(-1, mass.size)
+    num = np.sum(mass * np.abs(a - b), axis=1)
+    den = np.sum(mass * np.abs(b), axis=1)
+    return float(np.max(num / np.where(den > 0, den, 1.0)))
+
+
+def lumped_mass(orc):
+    """m_i = |E_i| |K| / (p+1)^d on the oracle's mesh."""
+    mesh = orc.mesh
+    return mesh.multiplicity() * mesh.h ** mesh.d / mesh.nloc
+
+
 def oracle_for(wl, modes=None, bounds=None):
     mesh = Mesh(wl.d, wl.p, wl.n, wl.lo, wl.hi)
     prm = Params(w_lin=wl.w_lin, q=wl.q)
@@ -29,12 +45,12 @@ def oracle_for(wl, modes=None, bounds=None):
 MODE_CODES = {"weno": 0, "limit": 0, "zero": 1, "one": 2}
 
 
-def gpu_for(wl, modes=None):
+def gpu_for(wl, modes=None, precision="fp64"):
     from paper_2509_04673_amd.cem import Solver
     kw = {}
     for k, v in (modes or {}).items():
         kw[k] = MODE_CODES[v]
-    s = Solver.from_workload(wl, **kw)
+    s = Solver.from_workload(wl, precision=precision, **kw)
     s.upload(wl.u0)
     if wl.kind != "euler":
         s.set_bounds()

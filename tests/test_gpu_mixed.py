@@ -1,0 +1,186 @@
+"""The mixed-precision form (float contractions, float64 state, limiters
+and time step) against the float64 oracle: error within 1e-5 relative L1 or
+within the problem's own response to float-sized input perturbations,
+invariant domain kept exactly, conservation to float64 round-off."""
+import numpy as np
+import pytest
+
+from parity_util import (announce, gpu_for, lumped_mass, oracle_for, random_euler_workload,
+                         random_scalar_workload, rel_l1, rel_linf)
+from paper_2509_04673_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# Float contractions carry ~1e-7 relative rounding per term; the float mass
+# solve loses up to log10 kappa(M_C) digits more (kappa ~ 2600 for 2D Q3).
+STAGE_L1 = 1e-5
+STAGE_LINF = 5e-5
+# Over a run the target is 1e-5 relative L1, unless the scheme itself moves
+# further when its input changes by float rounding (limiter switching at
+# discontinuities): then within a small multiple of that float floor.
+RUN_L1 = 1e-5
+FLOAT_EPS = 2.0 ** -24
+
+
+def _float_perturbed(u, seed=7):
+    rng = np.random.default_rng(seed)
+    return u * (1.0 + rng.uniform(-1.0, 1.0, u.shape) * FLOAT_EPS)
+
+
+def _run_tol(floor):
+    return max(RUN_L1, 4.0 * floor)
+
+STAGE_CASES = [
+    ("kpp2d_q2", lambda: random_scalar_workload(2, 2, (13, 11), kind="kpp")),
+    ("adv2d_q3", lambda: random_scalar_workload(2, 3, (9, 7))),
+    ("adv3d_q2", lambda: random_scalar_workload(3, 2, (5, 4, 6))),
+    ("euler2d_q2", lambda: random_euler_workload(2, 2, (12, 7))),
+    ("euler2d_q3", lambda: random_euler_workload(2, 3, (9, 10))),
+    ("euler3d_q1", lambda: random_euler_workload(3, 1, (7, 5, 6))),
+    ("euler3d_q2", lambda: random_euler_workload(3, 2, (5, 6, 4))),
+    ("kpp2d_q2_long", lambda: random_scalar_workload(2, 2, (64, 63), kind="kpp")),
+    ("euler2d_q3_long", lambda: random_euler_workload(2, 3, (55, 54))),
+]
+
+
+@pytest.mark.parametrize("label,make", STAGE_CASES, ids=[c[0] for c in STAGE_CASES])
+def test_mixed_stage(label, make):
+    wl = make()
+    orc = oracle_for(wl)
+    dt = wl.dt if wl.dt > 0 else 0.5 * orc.max_dt(wl.u0)
+    announce(f"[mixed] stage {label} d={wl.d} p={wl.p} n={wl.n} kind={wl.kind}")
+    ufe, taps = orc.fe_stage(wl.u0, dt)
+    ufe = orc.clamp(ufe)[0]
+    s = gpu_for(wl, precision="mixed")
+    s.stage(0, dt=dt)
+    got = s.download()
+    gam = s.tap("gamma")
+    chk = s.check()
+    s.close()
+    mass = lumped_mass(orc)
+    e1, einf = rel_l1(got, ufe, mass), rel_linf(got, ufe)
+    egam = float(np.max(np.abs(gam - taps["gamma"])))
+    announce(f"[mixed] {label}: rel L1 {e1:.2e}, rel Linf {einf:.2e}, max |dgamma| {egam:.2e}")
+    assert e1 <= STAGE_L1 and einf <= STAGE_LINF, (label, e1, einf)
+    assert chk["violations"] == 0
+    if wl.kind == "euler":
+        assert chk["rho_min"] > 0 and chk["p_min"] > 0
+    else:
+        assert np.all(got >= s_bounds(wl)[0]) and np.all(got <= s_bounds(wl)[1])
+    # conservation: sum_i m_i u_i changes by float64 round-off only
+    m0 = np.sum(mass * wl.u0.reshape(-1, mass.size), axis=1)
+    m1 = np.sum(mass * got.reshape(-1, mass.size), axis=1)
+    scale = np.sum(mass * np.abs(wl.u0.reshape(-1, mass.size)), axis=1)
+    assert np.all(np.abs(m1 - m0) <= 1e-13 * scale + chk["clamped"] * 1e-12 * scale), (m0, m1)
+
+
+def s_bounds(wl):
+    return float(wl.u0.min()), float(wl.u0.max())
+
+
+def _run_mixed(wl, nsteps, dt=None, cfl=0.5):
+    """Mixed GPU run vs the oracle, and the oracle's float floor: how far it
+    moves over the run when its input is perturbed by float rounding."""
+    orc = oracle_for(wl)
+    announce(f"[mixed] {nsteps} steps {wl.name} n={wl.n}")
+    u_ref, _ = orc.run(wl.u0.copy(), nsteps, dt=dt, cfl=cfl)
+    u_pert, _ = orc.run(_float_perturbed(wl.u0), nsteps, dt=dt, cfl=cfl)
+    mass = lumped_mass(orc)
+    floor = rel_l1(u_pert, u_ref, mass)
+    s = gpu_for(wl, precision="mixed")
+    for _ in range(nsteps):
+        s.step(dt=dt or 0.0, cfl=0.0 if dt else cfl)
+    got = s.download()
+    chk = s.check()
+    s.close()
+    e1 = rel_l1(got, u_ref, mass)
+    announce(f"[mixed] {wl.name}: rel L1 after {nsteps} steps {e1:.2e} (oracle float floor "
+             f"{floor:.2e}), violations {chk['violations']}, clamped {chk['clamped']}")
+    return e1, floor, chk, got
+
+
+def test_mixed_kpp2d_run():
+    wl = W.kpp2d(seed=2, n=16)
+    e1, floor, chk, got = _run_mixed(wl, 30, dt=2e-3)
+    assert e1 <= _run_tol(floor)
+    assert chk["violations"] == 0
+    lo, hi = s_bounds(wl)
+    assert np.all(got >= lo) and np.all(got <= hi)
+
+
+def test_mixed_euler2d_run():
+    wl = W.euler2d(seed=1, n=12)
+    e1, floor, chk, _ = _run_mixed(wl, 10)
+    assert e1 <= _run_tol(floor)
+    assert chk["rho_min"] > 0 and chk["p_min"] > 0 and chk["violations"] == 0
+
+
+def test_mixed_euler3d_run():
+    wl = W.euler3d(seed=0, n=6)
+    e1, floor, chk, _ = _run_mixed(wl, 4)
+    assert e1 <= _run_tol(floor)
+    assert chk["rho_min"] > 0 and chk["p_min"] > 0 and chk["violations"] == 0
+
+
+# Full benchmark sizes: the mixed form against the float64 HIP path (itself
+# parity-checked against the oracle), with the float64 path's own response
+# to float-rounded input as the floor.
+FULL_CASES = [
+    ("kpp2d", lambda: W.kpp2d(seed=0), 50),
+    ("euler2d", lambda: W.euler2d(seed=0), 5),
+    ("euler3d", lambda: W.euler3d(seed=0), 2),
+]
+
+
+@pytest.mark.parametrize("name,make,nsteps", FULL_CASES, ids=[c[0] for c in FULL_CASES])
+def test_mixed_full_size_vs_fp64(name, make, nsteps):
+    wl = make()
+    announce(f"[mixed] full size {name} n={wl.n} {nsteps} steps")
+    dt, cfl = (wl.dt, 0.0) if wl.dt > 0 else (0.0, wl.cfl)
+
+    def run(precision, u0):
+        s = gpu_for(wl, precision=precision)
+        s.upload(u0)
+        for _ in range(nsteps):
+            s.step(dt=dt, cfl=cfl)
+        out, chk = s.download(), s.check()
+        s.close()
+        return out, chk
+
+    ref, _ = run("fp64", wl.u0)
+    pert, _ = run("fp64", _float_perturbed(wl.u0))
+    got, chk = run("mixed", wl.u0)
+    # lumped masses of a uniform mesh are proportional to node multiplicities
+    mass = _multiplicity(wl)
+    floor, e1 = rel_l1(pert, ref, mass), rel_l1(got, ref, mass)
+    for c in range(ref.reshape(-1, mass.size).shape[0]):
+        rc = ref.reshape(-1, mass.size)[c]
+        announce(f"[mixed]   comp {c}: mixed {rel_l1(got.reshape(-1, mass.size)[c], rc, mass):.2e} "
+                 f"floor {rel_l1(pert.reshape(-1, mass.size)[c], rc, mass):.2e} "
+                 f"ref L1 {np.sum(mass * np.abs(rc)):.3e} max|ref| {np.max(np.abs(rc)):.3e} "
+                 f"max|diff| {np.max(np.abs(got.reshape(-1, mass.size)[c] - rc)):.2e}")
+    announce(f"[mixed] {name}: rel L1 mixed vs fp64 {e1:.2e}, fp64 float floor {floor:.2e}, "
+             f"violations {chk['violations']}")
+    assert e1 <= _run_tol(floor)
+    assert chk["violations"] == 0
+    if wl.kind == "euler":
+        assert chk["rho_min"] > 0 and chk["p_min"] > 0
+
+
+def _multiplicity(wl):
+    # nodes with i_k % p == 0 on axis k are shared by 2 elements along it
+    counts = []
+    for k in range(wl.d):
+        ik = np.arange(wl.p * wl.n[k])
+        counts.append(np.where(ik % wl.p == 0, 2.0, 1.0))
+    m = counts[0]
+    for c in counts[1:]:
+        m = np.multiply.outer(c, m)
+    return m.ravel()
+
+
+def test_mixed_precision_rejected_in_1d():
+    from paper_2509_04673_amd.cem import CemError
+    wl = random_scalar_workload(1, 2, (16,))
+    with pytest.raises(CemError):
+        gpu_for(wl, precision="mixed")
