@@ -247,12 +247,57 @@ def cpu_baseline(wl, seconds):
                        f"({wl.dofs} DOFs), numpy float64, 1 thread, {el:.1f} s")
 
 
+def bench_batch(args):
+    """The batched workload: count independent four-quadrant Euler problems
+    (Q2, n_k^2 meshes, n_k = 32 + floor(225 U)) advanced together, one launch
+    per kernel and stage, each step one HIP graph; adaptive dt per problem."""
+    import torch
+    from paper_2509_04673_amd import cem, workloads
+    prec = args.precision if args.precision != "fp64" or "--precision" in sys.argv else "mixed"
+    wls = workloads.euler_batch(seed=0, count=args.count)
+    dofs = sum(w.dofs for w in wls)
+    print(f"[bench] batched Euler: {len(wls)} problems, n in [{min(w.n[0] for w in wls)}, "
+          f"{max(w.n[0] for w in wls)}], {dofs} DOFs, precision={prec}", flush=True)
+    dev = torch.device("cuda:0")
+    b = cem.BatchSolver([(w.d, w.p, w.n, w.lo, w.hi) for w in wls], "euler", gamma_gas=wls[0].gamma_gas,
+                        w_lin=wls[0].w_lin, precision=prec)
+    b.upload([w.u0 for w in wls])
+    del wls
+    cfl = 0.5
+    b.step(cfl=cfl, nsteps=args.warmup)
+    cem.cem_batch_reset_counters(b.b)
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    b.step(cfl=cfl, nsteps=args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    chk = b.check()
+    b.close()
+    value = dofs * 3 * args.steps / (ms * 1e-3)
+    out = dict(metric="DOF*RK-stage updates/s", value=value, unit="DOF*stage/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps,
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64" if prec == "fp64" else "f32+f64", data="synthetic",
+               config=dict(workload="euler_batch", problems=args.count, degree=2, dofs=dofs, physics="euler",
+                           cfl=cfl, seed=0, wall_s=wall,
+                           violations=int(sum(c["violations"] for c in chk)),
+                           rho_min=min(c["rho_min"] for c in chk), p_min=min(c["p_min"] for c in chk)),
+               roofline=None, cpu_baseline=None)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="kpp2d", choices=["kpp2d", "adv1d", "euler2d", "euler3d"])
+    ap.add_argument("--workload", default="kpp2d", choices=["kpp2d", "adv1d", "euler2d", "euler3d", "euler_batch"])
+    ap.add_argument("--count", type=int, default=512, help="problems of the batched workload")
     ap.add_argument("--n", type=int, default=None, help="cells per axis (default: workload size)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="fp64, or mixed: float contractions with float64 state, limiters and dt")
@@ -282,6 +327,9 @@ def main():
 
     import torch
     from paper_2509_04673_amd import cem, workloads
+
+    if args.workload == "euler_batch":
+        return bench_batch(args)
 
     kw = {} if args.n is None else dict(n=args.n)
     wl = workloads.make(args.workload, seed=0, **kw)

@@ -200,6 +200,42 @@ cem_status cem_kernel_times(cem_ctx* ctx, double* total_ms, long long* launches,
 void cem_destroy(cem_ctx* ctx);
 const char* cem_last_error(void);
 
+/* ---- Batched form --------------------------------------------------------
+ * count independent problems (uneven mesh sizes; the same dimension, degree,
+ * physics, parameters and precision) advance together: every kernel of a
+ * stage runs as ONE launch over all problems (blocks mapped to problems by a
+ * prefix table), and a whole SSP-RK3 step is captured as one HIP graph and
+ * replayed.  Each problem keeps its own time step (fixed dt, or cfl times
+ * its own min_e dt_e, eq. 40) and its own counters.  Supported: d = 2 (all
+ * physics), 3D Euler; both precisions.
+ *
+ * State layout: problem k occupies [offsets[k], offsets[k+1]) of the
+ * concatenated state arrays (its own component-major SoA block).
+ * Ownership as for single problems: u, u_base and the workspace are device
+ * memory owned by the caller; the batch allocates none. */
+typedef struct cem_batch cem_batch;
+
+/* Validates every problem (as cem_create) and sizes the workspace. */
+cem_status cem_batch_create(int count, const cem_mesh_desc* meshes, const cem_physics_desc* phys,
+                            const cem_params* prm, void* stream, cem_batch** out);
+/* offsets: count + 1 entries (doubles from the start of u). */
+cem_status cem_batch_offsets(const cem_batch* b, long long* offsets, int n);
+cem_status cem_batch_workspace_bytes(const cem_batch* b, size_t* bytes);
+/* u, u_base: device arrays of offsets[count] doubles; workspace 256-aligned. */
+cem_status cem_batch_bind(cem_batch* b, double* u, double* u_base, void* workspace, size_t ws_bytes);
+/* host arrays of offsets[count] doubles; synchronous. */
+cem_status cem_batch_upload_state(cem_batch* b, const double* host_u);
+cem_status cem_batch_download_state(cem_batch* b, double* host_u);
+/* as cem_set_bounds, for every problem (scalar physics). */
+cem_status cem_batch_set_bounds(cem_batch* b, int from_state, double u_min, double u_max);
+/* nsteps SSP-RK3 steps of every problem; dt > 0 fixed, else cfl > 0. */
+cem_status cem_batch_step(cem_batch* b, double dt, double cfl, int nsteps);
+cem_status cem_batch_set_graphs(cem_batch* b, int enable);
+cem_status cem_batch_reset_counters(cem_batch* b);
+/* one record per problem (n == count); returns the worst status. */
+cem_status cem_batch_check_invariants(cem_batch* b, cem_invariants* out, int n);
+void cem_batch_destroy(cem_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

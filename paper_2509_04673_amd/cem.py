@@ -83,6 +83,19 @@ _SIGS = [
                                         ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
     ("cem_destroy", None, [_P]),
     ("cem_last_error", ctypes.c_char_p, []),
+    ("cem_batch_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(MeshDesc), ctypes.POINTER(PhysicsDesc),
+                                        ctypes.POINTER(Params), _P, ctypes.POINTER(_P)]),
+    ("cem_batch_offsets", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
+    ("cem_batch_workspace_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    ("cem_batch_bind", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t]),
+    ("cem_batch_upload_state", ctypes.c_int, [_P, _P]),
+    ("cem_batch_download_state", ctypes.c_int, [_P, _P]),
+    ("cem_batch_set_bounds", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
+    ("cem_batch_step", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
+    ("cem_batch_set_graphs", ctypes.c_int, [_P, ctypes.c_int]),
+    ("cem_batch_reset_counters", ctypes.c_int, [_P]),
+    ("cem_batch_check_invariants", ctypes.c_int, [_P, ctypes.POINTER(Invariants), ctypes.c_int]),
+    ("cem_batch_destroy", None, [_P]),
 ]
 
 _lib = None
@@ -289,6 +302,141 @@ class Solver:
         if self.ctx:
             cem_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# -- batched form --------------------------------------------------------------
+def cem_batch_create(meshes, phys, prm, stream):
+    arr = (MeshDesc * len(meshes))(*meshes)
+    b = _P()
+    _check(lib().cem_batch_create(len(meshes), arr, ctypes.byref(phys), ctypes.byref(prm), _P(stream),
+                                  ctypes.byref(b)))
+    return b
+
+
+def cem_batch_offsets(b, count):
+    off = (ctypes.c_longlong * (count + 1))()
+    _check(lib().cem_batch_offsets(b, off, count + 1))
+    return np.array(off[:], dtype=np.int64)
+
+
+def cem_batch_workspace_bytes(b):
+    n = ctypes.c_size_t()
+    _check(lib().cem_batch_workspace_bytes(b, ctypes.byref(n)))
+    return n.value
+
+
+def cem_batch_bind(b, u_ptr, u0_ptr, ws_ptr, nbytes):
+    _check(lib().cem_batch_bind(b, _P(u_ptr), _P(u0_ptr), _P(ws_ptr), nbytes))
+
+
+def cem_batch_upload_state(b, host):
+    host = np.ascontiguousarray(host, dtype=np.float64)
+    _check(lib().cem_batch_upload_state(b, host.ctypes.data_as(_P)))
+
+
+def cem_batch_download_state(b, n):
+    out = np.empty(n, dtype=np.float64)
+    _check(lib().cem_batch_download_state(b, out.ctypes.data_as(_P)))
+    return out
+
+
+def cem_batch_set_bounds(b, from_state, u_min=0.0, u_max=0.0):
+    _check(lib().cem_batch_set_bounds(b, int(from_state), float(u_min), float(u_max)))
+
+
+def cem_batch_step(b, dt, cfl, nsteps):
+    _check(lib().cem_batch_step(b, float(dt), float(cfl), int(nsteps)))
+
+
+def cem_batch_set_graphs(b, enable):
+    _check(lib().cem_batch_set_graphs(b, int(bool(enable))))
+
+
+def cem_batch_reset_counters(b):
+    _check(lib().cem_batch_reset_counters(b))
+
+
+def cem_batch_check_invariants(b, count):
+    inv = (Invariants * count)()
+    st = lib().cem_batch_check_invariants(b, inv, count)
+    return list(inv), st
+
+
+def cem_batch_destroy(b):
+    lib().cem_batch_destroy(b)
+
+
+class BatchSolver:
+    """Independent problems advanced by the batched kernels: the states are
+    one concatenated torch tensor (problem k at offsets[k]:offsets[k+1])."""
+
+    def __init__(self, problems, kind, velocity=(1.0, 0.0, 0.0), gamma_gas=1.4, device="cuda:0", **params):
+        """problems: list of (d, p, n, lo, hi)."""
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        meshes = []
+        for d, p, n, lo, hi in problems:
+            meshes.append(MeshDesc(d, p, (ctypes.c_int * 3)(*(list(n) + [1] * (3 - d))),
+                                   (ctypes.c_double * 3)(*(list(lo) + [0.0] * (3 - d))),
+                                   (ctypes.c_double * 3)(*(list(hi) + [1.0] * (3 - d)))))
+        phys = PhysicsDesc(KINDS[kind], (ctypes.c_double * 3)(*(list(velocity) + [0.0] * 3)[:3]), gamma_gas)
+        prm = cem_params_default()
+        for k, v in params.items():
+            if k == "precision" and isinstance(v, str):
+                v = PRECISIONS[v]
+            setattr(prm, k, v)
+        self.count = len(problems)
+        self.kind = kind
+        self.stream = torch.cuda.current_stream(self.device)
+        self.b = cem_batch_create(meshes, phys, prm, self.stream.cuda_stream)
+        self.offsets = cem_batch_offsets(self.b, self.count)
+        nbytes = cem_batch_workspace_bytes(self.b)
+        total = int(self.offsets[-1])
+        self.u = torch.zeros(total, dtype=torch.float64, device=self.device)
+        self.u_base = torch.zeros_like(self.u)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.ws.data_ptr() + 255) & ~255
+        cem_batch_bind(self.b, self.u.data_ptr(), self.u_base.data_ptr(), aligned, nbytes)
+
+    def upload(self, states):
+        """states: list of per-problem arrays (m, N) or one concatenated array."""
+        if isinstance(states, (list, tuple)):
+            states = np.concatenate([np.asarray(s, dtype=np.float64).ravel() for s in states])
+        cem_batch_upload_state(self.b, states)
+
+    def download(self, split=True):
+        flat = cem_batch_download_state(self.b, int(self.offsets[-1]))
+        if not split:
+            return flat
+        return [flat[self.offsets[k]:self.offsets[k + 1]] for k in range(self.count)]
+
+    def set_bounds(self, u_min=None, u_max=None):
+        if u_min is None:
+            cem_batch_set_bounds(self.b, 1)
+        else:
+            cem_batch_set_bounds(self.b, 0, u_min, u_max)
+
+    def step(self, dt=0.0, cfl=0.0, nsteps=1):
+        cem_batch_step(self.b, dt, cfl, nsteps)
+
+    def check(self):
+        inv, st = cem_batch_check_invariants(self.b, self.count)
+        return [dict(status=st, dt=r.dt, min_dt_e=r.min_dt_e, cfl_violated=r.cfl_violated,
+                     clamped=r.clamped, violations=r.violations, rho_min=r.rho_min, p_min=r.p_min,
+                     mass=list(r.mass)[:r.m]) for r in inv]
+
+    def close(self):
+        if self.b:
+            cem_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

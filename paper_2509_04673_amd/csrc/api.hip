@@ -14,6 +14,7 @@
 #include "../../include/cem.h"
 #include "kernels.hpp"
 #include "kernels_sys.hpp"
+#include "kernels_batch.hpp"
 #include "tables.hpp"
 
 using namespace cem;
@@ -78,6 +79,38 @@ struct cem_ctx {
   std::vector<hipEvent_t> pool;
 
   template <class T> T* W(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+// batched form: launches of one stage over all problems (see kernels_batch.hpp)
+enum BKind { B_LINE, B_LINE_X, B_LINE_Y, B_ELEM1_TILE, B_ELEM1_SYS, B_GATHER_LX, B_GATHER_R, B_ELEM2,
+             B_ELEM2_SYS, B_UPDATE };
+
+struct BLaunch {
+  int kind = 0;
+  bool grad = false;       // line kernels: float64 input (u) rather than RT
+  int nprob = 0, blocks = 0;
+  size_t lds = 0;
+  size_t o_first = 0, o_args = 0, o_args2 = 0;   // byte offsets in the plan region
+};
+
+struct cem_batch {
+  int count = 0, d = 0, p = 0, kind = 0, m = 0;
+  bool mixed = false;
+  hipStream_t stream = nullptr;
+  std::vector<cem_ctx*> pr;
+  std::vector<long long> uoff;     // [count + 1] start of each problem in the state arrays
+  std::vector<size_t> wsoff;       // start of each problem's workspace (bytes)
+  size_t ws_need = 0, o_plan = 0, plan_cap = 0;
+  char* ws = nullptr;
+  double* u = nullptr;
+  double* u0 = nullptr;
+  bool bound = false;
+  std::vector<BLaunch> launches[3];
+  double plan_dt = -1.0, plan_cfl = -1.0;
+  bool use_graphs = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int xlines_cap = 2048;           // axis-0 line kernels: cap on values staged per block
 };
 
 namespace {
@@ -432,6 +465,305 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   CEM_LAUNCH(c, 6, (k_update<D, P, PH>), c->upd_blocks, 256, 0, c->stream, a);
   HIPCHK(hipGetLastError());
   return CEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched form: plan (per-stage launch list with per-problem arguments in
+// device memory) and dispatch
+// ---------------------------------------------------------------------------
+template <int D, int P, int PH, class RT>
+StageArgs batch_stage_args(cem_ctx* c, int stage, double dt, double cfl) {
+  StageArgs a = make_args(c);
+  const double rka[3] = {0.0, 0.75, 1.0 / 3.0}, rkb[3] = {1.0, 0.25, 2.0 / 3.0};
+  a.rk_a = rka[stage];
+  a.rk_b = rkb[stage];
+  a.stage = stage;
+  a.copy_base = stage == 0 ? 1 : 0;
+  a.dt_fixed = dt;
+  a.cfl = cfl;
+  constexpr int M = Phys<D, PH>::M;
+  if constexpr (D == 2) {
+    using TT = Tile2<P, M>;
+    a.ndtpart = ((c->n[0] + TT::TEX - 1) / TT::TEX) * ((c->n[1] + TT::TEY - 1) / TT::TEY);
+  } else if constexpr (PH == EUL && D == 3) {
+    a.ndtpart = (int)nblocks(c->E, SysTile<D, P, PH>::EB);
+  } else {
+    a.ndtpart = (int)nblocks(c->E, 128);
+  }
+  return a;
+}
+
+template <int D, int P, int PH, class RT>
+cem_status batch_plan(cem_batch* b, double dt, double cfl) {
+  constexpr int M = Phys<D, PH>::M;
+  constexpr bool MIX = sizeof(RT) == 4;
+  constexpr int W = LineTaps<P>::W, S = LineTaps<P>::S;
+  std::vector<char> blob;
+  auto put = [&](const void* p, size_t n) {
+    const size_t off = blob.size();
+    blob.insert(blob.end(), static_cast<const char*>(p), static_cast<const char*>(p) + n);
+    while (blob.size() % 256) blob.push_back(0);
+    return off;
+  };
+  struct Group {
+    BLaunch l;
+    std::vector<int> first{0};
+    std::vector<StageArgs> sa;
+    std::vector<LineFastArgs> lf;
+    std::vector<LineArgs> la;
+  };
+  auto close = [&](Group& g, std::vector<BLaunch>& out) {
+    if (g.first.size() <= 1) return;
+    g.l.nprob = (int)g.first.size() - 1;
+    g.l.blocks = g.first.back();
+    g.l.o_first = put(g.first.data(), g.first.size() * sizeof(int));
+    if (!g.sa.empty()) g.l.o_args = put(g.sa.data(), g.sa.size() * sizeof(StageArgs));
+    if (!g.lf.empty()) (g.sa.empty() ? g.l.o_args : g.l.o_args2) = put(g.lf.data(), g.lf.size() * sizeof(LineFastArgs));
+    if (!g.la.empty()) g.l.o_args = put(g.la.data(), g.la.size() * sizeof(LineArgs));
+    out.push_back(g.l);
+  };
+  // one line pass of every problem (axis k), grouped by kernel variant
+  auto lines = [&](std::vector<BLaunch>& out, bool grad, int k, auto src_of, auto dst_of) -> cem_status {
+    Group gx, gy, gg;
+    gx.l.kind = B_LINE_X;
+    gy.l.kind = B_LINE_Y;
+    gg.l.kind = B_LINE;
+    gx.l.grad = gy.l.grad = gg.l.grad = grad;
+    for (int q = 0; q < b->count; ++q) {
+      cem_ctx* c = b->pr[q];
+      const LineKernel& K = grad ? c->tabs.kgrad[k] : c->tabs.kmass[k];
+      const void* in = src_of(c);
+      void* out_p = dst_of(c);
+      if (K.wfast > 0) {
+        LineFastArgs a = line_args<RT>(c, in, out_p, k, grad);
+        if (k == 0) {
+          if (a.L > 4096) return fail(CEM_EINVAL, "batched form: x-lines longer than 4096 nodes");
+          a.nlb = std::max(1, std::min(b->xlines_cap / a.L, (int)((a.ntrans + 511) / 512)));
+          gx.lf.push_back(a);
+          gx.first.push_back(gx.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
+          gx.l.lds = std::max(gx.l.lds, (size_t)a.nlb * a.L * sizeof(RT));
+        } else {
+          const int TY = 8 * P;
+          a.gx = (int)nblocks(a.ntrans, kTileX);
+          gy.lf.push_back(a);
+          gy.first.push_back(gy.first.back() + a.gx * ((a.L + TY - 1) / TY));
+          gy.l.lds = (size_t)(TY + S) * kTileX * sizeof(RT);
+        }
+      } else {
+        LineArgs a{};
+        const char* tb = c->ws + c->o_tab;
+        a.in = in;
+        a.out = out_p;
+        a.w = MIX ? (const void*)(tb + (grad ? c->boff_kg32[k] : c->boff_km32[k]))
+                  : (const void*)(tb + 8 * (grad ? c->off_kg[k] : c->off_km[k]));
+        a.taps = K.taps;
+        a.first = K.first;
+        a.L = c->L[k];
+        a.P = c->p;
+        a.stride = k == 0 ? 1 : (k == 1 ? (int64_t)c->L[0] : (int64_t)c->L[0] * c->L[1]);
+        a.N = c->N;
+        a.total = (int64_t)c->m * c->N;
+        a.scale = 1.0;
+        gg.la.push_back(a);
+        gg.first.push_back(gg.first.back() + (int)nblocks(a.total, 256));
+      }
+    }
+    (void)W;
+    close(gx, out);
+    close(gy, out);
+    close(gg, out);
+    return CEM_OK;
+  };
+  auto gbuf = [&](cem_ctx* c) -> RT* { return c->W<RT>(MIX ? c->o_g32 : c->o_g); };
+  auto rbuf = [&](cem_ctx* c) -> RT* { return c->W<RT>(MIX ? c->o_r32 : c->o_r); };
+  auto ubuf = [&](cem_ctx* c) -> RT* { return c->W<RT>(MIX ? c->o_udot32 : c->o_udot); };
+  auto tbuf = [&](cem_ctx* c, int i) -> RT* {
+    return c->W<RT>(i == 0 ? (MIX ? c->o_tmp32 : c->o_tmp) : (MIX ? c->o_tmp2_32 : c->o_tmp2));
+  };
+  // mass pass k of problem c: (source, destination) as in the single-problem stage
+  auto fused = [&](cem_ctx* c) { return c->tabs.kmass[0].wfast > 0 && c->L[0] <= 4096; };
+  auto mass_dst = [&](cem_ctx* c, int k) -> RT* { return k == D - 1 ? ubuf(c) : tbuf(c, k % 2); };
+  auto mass_src = [&](cem_ctx* c, int k) -> const RT* { return k == 0 ? rbuf(c) : mass_dst(c, k - 1); };
+  for (int st = 0; st < 3; ++st) {
+    std::vector<BLaunch>& L = b->launches[st];
+    L.clear();
+    std::vector<StageArgs> sa(b->count);
+    for (int q = 0; q < b->count; ++q) sa[q] = batch_stage_args<D, P, PH, RT>(b->pr[q], st, dt, cfl);
+    // projected gradient, one pass per axis
+    for (int k = 0; k < D; ++k) {
+      cem_status s = lines(L, true, k, [&](cem_ctx* c) -> const void* { return c->u; },
+                           [&](cem_ctx* c) -> void* { return gbuf(c) + (int64_t)k * M * c->N; });
+      if (s != CEM_OK) return s;
+    }
+    // element pass 1
+    {
+      Group g;
+      if constexpr (D == 2) {
+        using TT = Tile2<P, M>;
+        g.l.kind = B_ELEM1_TILE;
+        g.l.lds = TT::words * sizeof(double);
+      } else if constexpr (PH == EUL && D == 3) {
+        g.l.kind = B_ELEM1_SYS;
+        g.l.lds = SysTile<D, P, PH>::LY::bytes;
+      } else {
+        return fail(CEM_EINVAL, "batched form: 2D problems or 3D Euler only");
+      }
+      for (int q = 0; q < b->count; ++q) {
+        g.sa.push_back(sa[q]);
+        g.first.push_back(g.first.back() + sa[q].ndtpart);
+      }
+      close(g, L);
+    }
+    // assembly of r fused with the first mass pass where the x-lines allow it
+    {
+      Group gf, gr;
+      gf.l.kind = B_GATHER_LX;
+      gr.l.kind = B_GATHER_R;
+      for (int q = 0; q < b->count; ++q) {
+        cem_ctx* c = b->pr[q];
+        if (fused(c)) {
+          LineFastArgs a = line_args<RT>(c, rbuf(c), mass_dst(c, 0), 0, false);
+          a.nlb = std::max(1, std::min(b->xlines_cap / a.L, (int)((a.ntrans + 511) / 512)));
+          gf.sa.push_back(sa[q]);
+          gf.lf.push_back(a);
+          gf.first.push_back(gf.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
+          gf.l.lds = std::max(gf.l.lds, (size_t)a.nlb * a.L * sizeof(RT));
+        } else {
+          gr.sa.push_back(sa[q]);
+          gr.first.push_back(gr.first.back() + (int)nblocks(c->N, 256));
+        }
+      }
+      close(gf, L);
+      close(gr, L);
+    }
+    // remaining mass passes (axis 0 of the unfused problems, then axes >= 1)
+    for (int k = 0; k < D; ++k) {
+      std::vector<cem_ctx*> keep;
+      std::vector<cem_ctx*> all = b->pr;
+      if (k == 0) {
+        // only the problems whose first pass was not fused
+        std::vector<cem_ctx*> sel;
+        for (cem_ctx* c : all)
+          if (!fused(c)) sel.push_back(c);
+        if (sel.empty()) continue;
+        std::swap(b->pr, sel);
+        const int cnt = b->count;
+        b->count = (int)b->pr.size();
+        cem_status s = lines(L, false, 0, [&](cem_ctx* c) -> const void* { return mass_src(c, 0); },
+                             [&](cem_ctx* c) -> void* { return mass_dst(c, 0); });
+        std::swap(b->pr, sel);
+        b->count = cnt;
+        if (s != CEM_OK) return s;
+        continue;
+      }
+      cem_status s = lines(L, false, k, [&](cem_ctx* c) -> const void* { return mass_src(c, k); },
+                           [&](cem_ctx* c) -> void* { return mass_dst(c, k); });
+      if (s != CEM_OK) return s;
+    }
+    // element pass 2 and the update
+    {
+      Group g2, gu;
+      if constexpr (PH == EUL && D >= 2) {
+        g2.l.kind = B_ELEM2_SYS;
+        g2.l.lds = SysTile<D, P, PH>::LY::bytes;
+      } else {
+        g2.l.kind = B_ELEM2;
+      }
+      gu.l.kind = B_UPDATE;
+      for (int q = 0; q < b->count; ++q) {
+        cem_ctx* c = b->pr[q];
+        g2.sa.push_back(sa[q]);
+        if constexpr (PH == EUL && D >= 2)
+          g2.first.push_back(g2.first.back() + (int)nblocks(c->E, SysTile<D, P, PH>::EB));
+        else
+          g2.first.push_back(g2.first.back() + (int)nblocks(c->E, 128));
+        gu.sa.push_back(sa[q]);
+        gu.first.push_back(gu.first.back() + c->upd_blocks);
+      }
+      close(g2, L);
+      close(gu, L);
+    }
+  }
+  if (blob.size() > b->plan_cap) return fail(CEM_EINVAL, "batched form: plan region too small");
+  HIPCHK(hipMemcpyAsync(b->ws + b->o_plan, blob.data(), blob.size(), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  b->plan_dt = dt;
+  b->plan_cfl = cfl;
+  return CEM_OK;
+}
+
+template <int D, int P, int PH, class RT>
+cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
+  constexpr int M = Phys<D, PH>::M;
+  const char* base = b->ws + b->o_plan;
+  for (const BLaunch& l : b->launches[st]) {
+    const BatchMap mp{reinterpret_cast<const int*>(base + l.o_first), l.nprob};
+    const StageArgs* sa = reinterpret_cast<const StageArgs*>(base + l.o_args);
+    const LineFastArgs* lf = reinterpret_cast<const LineFastArgs*>(base + l.o_args);
+    const LineArgs* la = reinterpret_cast<const LineArgs*>(base + l.o_args);
+    const dim3 g(l.blocks);
+    switch (l.kind) {
+      case B_LINE:
+        if (l.grad) hipLaunchKernelGGL((kb_line<double, RT>), g, dim3(256), 0, stream, la, mp);
+        else hipLaunchKernelGGL((kb_line<RT, RT>), g, dim3(256), 0, stream, la, mp);
+        break;
+      case B_LINE_X:
+        if (l.grad) hipLaunchKernelGGL((kb_line_x<P, 1, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        else hipLaunchKernelGGL((kb_line_x<P, 1, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        break;
+      case B_LINE_Y:
+        if (l.grad) hipLaunchKernelGGL((kb_line_y<P, 1, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        else hipLaunchKernelGGL((kb_line_y<P, 1, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        break;
+      case B_ELEM1_TILE:
+        if constexpr (D == 2) hipLaunchKernelGGL((kb_elem1_tile<P, PH, true, RT>), g, dim3(128), l.lds, stream, sa, mp);
+        break;
+      case B_ELEM1_SYS:
+        if constexpr (PH == EUL && D == 3)
+          hipLaunchKernelGGL((kb_elem1_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
+        break;
+      case B_GATHER_LX:
+        hipLaunchKernelGGL((kb_gather_line_x<D, P, M, 1, RT>), g, dim3(256), l.lds, stream, sa,
+                           reinterpret_cast<const LineFastArgs*>(base + l.o_args2), mp);
+        break;
+      case B_GATHER_R:
+        hipLaunchKernelGGL((kb_gather_r<D, P, M, RT>), g, dim3(256), 0, stream, sa, mp);
+        break;
+      case B_ELEM2:
+        hipLaunchKernelGGL((kb_elem2<D, P, PH, RT>), g, dim3(128), 0, stream, sa, mp);
+        break;
+      case B_ELEM2_SYS:
+        if constexpr (PH == EUL && D >= 2)
+          hipLaunchKernelGGL((kb_elem2_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
+        break;
+      case B_UPDATE:
+        hipLaunchKernelGGL((kb_update<D, P, PH>), g, dim3(256), 0, stream, sa, mp);
+        break;
+      default:
+        return fail(CEM_EINVAL, "batched form: unknown launch");
+    }
+    HIPCHK(hipGetLastError());
+  }
+  return CEM_OK;
+}
+
+struct BatchFns {
+  cem_status (*plan)(cem_batch*, double, double);
+  cem_status (*stage)(cem_batch*, int, hipStream_t);
+};
+
+// the batched form covers 2D problems (every physics) and 3D Euler
+BatchFns pick_batch(int d, int p, int kind, bool mixed) {
+#define BCASE(D, P, PH)                                                                 \
+  if (d == D && p == P && kind == PH)                                                   \
+    return mixed ? BatchFns{&batch_plan<D, P, PH, float>, &batch_stage<D, P, PH, float>} \
+                 : BatchFns{&batch_plan<D, P, PH, double>, &batch_stage<D, P, PH, double>};
+  BCASE(2, 1, ADV) BCASE(2, 2, ADV) BCASE(2, 3, ADV)
+  BCASE(2, 1, KPP) BCASE(2, 2, KPP) BCASE(2, 3, KPP)
+  BCASE(2, 1, EUL) BCASE(2, 2, EUL) BCASE(2, 3, EUL)
+  BCASE(3, 1, EUL) BCASE(3, 2, EUL)
+#undef BCASE
+  return BatchFns{nullptr, nullptr};
 }
 
 using StageFn = cem_status (*)(cem_ctx*, int, double, double);
@@ -858,6 +1190,204 @@ void cem_destroy(cem_ctx* c) {
   }
   for (auto e : c->pool) hipEventDestroy(e);
   delete c;
+}
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+static void batch_drop_graph(cem_batch* b) {
+  if (b->graph) hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+}
+
+void cem_batch_destroy(cem_batch* b) {
+  if (!b) return;
+  batch_drop_graph(b);
+  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  for (cem_ctx* c : b->pr) cem_destroy(c);
+  delete b;
+}
+
+cem_status cem_batch_create(int count, const cem_mesh_desc* meshes, const cem_physics_desc* phys,
+                            const cem_params* prm, void* stream, cem_batch** out) {
+  if (count < 1 || !meshes || !phys || !prm || !out) return fail(CEM_EINVAL, "null argument or count < 1");
+  const int d = meshes[0].dim, p = meshes[0].degree;
+  const bool mixed = prm->precision == CEM_FP32_MIXED;
+  if (!pick_batch(d, p, phys->kind, mixed).plan)
+    return fail(CEM_EINVAL, "batched form: 2D problems or 3D Euler only");
+  cem_batch* b = new cem_batch();
+  b->count = count;
+  b->d = d;
+  b->p = p;
+  b->kind = phys->kind;
+  b->mixed = mixed;
+  b->stream = (hipStream_t)stream;
+  b->uoff.assign(1, 0);
+  size_t ws = 0;
+  for (int k = 0; k < count; ++k) {
+    if (meshes[k].dim != d || meshes[k].degree != p) {
+      cem_batch_destroy(b);
+      return fail(CEM_EINVAL, "batched form: every problem needs the same dimension and degree");
+    }
+    cem_ctx* c = nullptr;
+    cem_status st = cem_create(&meshes[k], phys, prm, stream, &c);
+    if (st != CEM_OK) {
+      cem_batch_destroy(b);
+      return st;
+    }
+    b->pr.push_back(c);
+    b->m = c->m;
+    b->uoff.push_back(b->uoff.back() + (long long)c->m * c->N);
+    b->wsoff.push_back(ws);
+    ws += align256(c->ws_need);
+  }
+  // plan region: per stage at most 4 StageArgs arrays, 2d + 1 LineFastArgs
+  // arrays, 2d LineArgs arrays and 6d + 4 block prefixes, each padded
+  const size_t per_stage = 4 * (size_t)count * sizeof(StageArgs) +
+                           (2 * d + 1) * (size_t)count * sizeof(LineFastArgs) +
+                           2 * d * (size_t)count * sizeof(LineArgs) + (6 * d + 4) * (size_t)(count + 1) * sizeof(int) +
+                           (12 * d + 8) * 256;
+  b->o_plan = ws;
+  b->plan_cap = 3 * per_stage;
+  b->ws_need = ws + align256(b->plan_cap);
+  *out = b;
+  return CEM_OK;
+}
+
+cem_status cem_batch_offsets(const cem_batch* b, long long* offsets, int n) {
+  if (!b || !offsets || n != b->count + 1) return fail(CEM_EINVAL, "need count + 1 offsets");
+  for (int k = 0; k <= b->count; ++k) offsets[k] = b->uoff[k];
+  return CEM_OK;
+}
+
+cem_status cem_batch_workspace_bytes(const cem_batch* b, size_t* bytes) {
+  if (!b || !bytes) return fail(CEM_EINVAL, "null argument");
+  *bytes = b->ws_need;
+  return CEM_OK;
+}
+
+cem_status cem_batch_bind(cem_batch* b, double* u, double* u_base, void* workspace, size_t ws_bytes) {
+  if (!b || !u || !u_base || !workspace) return fail(CEM_EINVAL, "null argument");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(CEM_EINVAL, "workspace not 256-byte aligned");
+  if (ws_bytes < b->ws_need) return fail(CEM_ENOMEM, "workspace too small");
+  batch_drop_graph(b);
+  char* ws = static_cast<char*>(workspace);
+  for (int k = 0; k < b->count; ++k) {
+    cem_status st = cem_bind(b->pr[k], u + b->uoff[k], u_base + b->uoff[k], ws + b->wsoff[k], b->pr[k]->ws_need);
+    if (st != CEM_OK) return st;
+  }
+  b->ws = ws;
+  b->u = u;
+  b->u0 = u_base;
+  b->plan_dt = b->plan_cfl = -1.0;
+  b->bound = true;
+  return CEM_OK;
+}
+
+cem_status cem_batch_upload_state(cem_batch* b, const double* host_u) {
+  if (!b || !b->bound || !host_u) return fail(CEM_EINVAL, "batch not bound / null");
+  for (int k = 0; k < b->count; ++k) {
+    cem_status st = cem_upload_state(b->pr[k], host_u + b->uoff[k]);
+    if (st != CEM_OK) return st;
+  }
+  return CEM_OK;
+}
+
+cem_status cem_batch_download_state(cem_batch* b, double* host_u) {
+  if (!b || !b->bound || !host_u) return fail(CEM_EINVAL, "batch not bound / null");
+  for (int k = 0; k < b->count; ++k) {
+    cem_status st = cem_download_state(b->pr[k], host_u + b->uoff[k]);
+    if (st != CEM_OK) return st;
+  }
+  return CEM_OK;
+}
+
+cem_status cem_batch_set_bounds(cem_batch* b, int from_state, double u_min, double u_max) {
+  if (!b || !b->bound) return fail(CEM_EINVAL, "batch not bound");
+  for (int k = 0; k < b->count; ++k) {
+    cem_status st = cem_set_bounds(b->pr[k], from_state, u_min, u_max);
+    if (st != CEM_OK) return st;
+  }
+  batch_drop_graph(b);
+  b->plan_dt = b->plan_cfl = -1.0;   // the stage arguments carry the bounds
+  return CEM_OK;
+}
+
+cem_status cem_batch_set_graphs(cem_batch* b, int enable) {
+  if (!b) return fail(CEM_EINVAL, "null batch");
+  b->use_graphs = enable != 0;
+  return CEM_OK;
+}
+
+cem_status cem_batch_step(cem_batch* b, double dt, double cfl, int nsteps) {
+  if (!b || !b->bound) return fail(CEM_EINVAL, "batch not bound");
+  if (!(dt > 0.0) && !(cfl > 0.0)) return fail(CEM_EINVAL, "need dt > 0 or cfl > 0");
+  if (nsteps < 0) return fail(CEM_EINVAL, "nsteps < 0");
+  for (cem_ctx* c : b->pr) {
+    if (c->kind != CEM_EULER && !c->bounds_set) return fail(CEM_EINVAL, "scalar bounds not set");
+    if (c->kind == CEM_KPP && !c->fnode_valid) {
+      // nodal fluxes of the uploaded state (refreshed by every update after)
+      StageArgs a = make_args(c);
+      hipLaunchKernelGGL((k_nodal_flux<2, KPP>), dim3(nblocks(c->N, 256)), dim3(256), 0, c->stream, a);
+      HIPCHK(hipGetLastError());
+      c->fnode_valid = true;
+    }
+  }
+  const BatchFns fn = pick_batch(b->d, b->p, b->kind, b->mixed);
+  if (b->plan_dt != dt || b->plan_cfl != cfl) {
+    batch_drop_graph(b);
+    cem_status st = fn.plan(b, dt, cfl);
+    if (st != CEM_OK) return st;
+  }
+  if (!b->use_graphs) {
+    for (int n = 0; n < nsteps; ++n)
+      for (int s = 0; s < 3; ++s) {
+        cem_status st = fn.stage(b, s, b->stream);
+        if (st != CEM_OK) return st;
+      }
+    return CEM_OK;
+  }
+  if (!b->graph) {
+    if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    cem_status st = CEM_OK;
+    for (int s = 0; s < 3 && st == CEM_OK; ++s) st = fn.stage(b, s, b->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (st != CEM_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(CEM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b->graph = nullptr;
+      return fail(CEM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+  }
+  for (int n = 0; n < nsteps; ++n) HIPCHK(hipGraphLaunch(b->graph, b->stream));
+  return CEM_OK;
+}
+
+cem_status cem_batch_reset_counters(cem_batch* b) {
+  if (!b || !b->bound) return fail(CEM_EINVAL, "batch not bound");
+  for (cem_ctx* c : b->pr) {
+    cem_status st = cem_reset_counters(c);
+    if (st != CEM_OK) return st;
+  }
+  return CEM_OK;
+}
+
+cem_status cem_batch_check_invariants(cem_batch* b, cem_invariants* out, int n) {
+  if (!b || !b->bound || !out || n != b->count) return fail(CEM_EINVAL, "need one record per problem");
+  cem_status worst = CEM_OK;
+  for (int k = 0; k < b->count; ++k) {
+    cem_status st = cem_check_invariants(b->pr[k], &out[k]);
+    if (st == CEM_EHIP || st == CEM_EINVAL) return st;
+    if (st == CEM_EIDP || (st == CEM_ECFL && worst == CEM_OK)) worst = st;
+  }
+  return worst;
 }
 
 }  // extern "C"

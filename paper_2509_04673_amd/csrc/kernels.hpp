@@ -296,8 +296,8 @@ struct LineArgs {
 };
 
 template <class TI, class TO>
-__global__ void __launch_bounds__(256) k_line(LineArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_line_body(const LineArgs& a, int bx) {
+  const int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   if (t >= a.total) return;
   const TI* in = static_cast<const TI*>(a.in);
   const int64_t c = t / a.N, i = t - c * a.N;
@@ -313,6 +313,11 @@ __global__ void __launch_bounds__(256) k_line(LineArgs a) {
     if (++j == a.L) j = 0;
   }
   static_cast<TO*>(a.out)[t] = (TO)a.scale * acc;
+}
+
+template <class TI, class TO>
+__global__ void __launch_bounds__(256) k_line(LineArgs a) {
+  k_line_body<TI, TO>(a, blockIdx.x);
 }
 
 // Register-blocked line operator for long lines (L >= R + TAPS): the rows of
@@ -344,6 +349,7 @@ struct LineFastArgs {
   int L0, L1;
   int64_t N, NT, ntrans;   // NT = N / L lines per component
   int nlb;                 // lines per block (axis 0 LDS kernel)
+  int gx;                  // blocks across lines of a 2D grid (batched launches)
 };
 
 template <int P, int RE, class TI, class TO>
@@ -442,11 +448,11 @@ __device__ __forceinline__ void line_run(const V* __restrict__ w, const LD& ld, 
 // coalesced copy, periodic wrap inside LDS) and each thread computes runs of
 // R outputs.  Consecutive lanes take consecutive runs.
 template <int P, int RE, class TI, class TO>
-__global__ void __launch_bounds__(256) k_line_x(LineFastArgs a) {
+__device__ __forceinline__ void k_line_x_body(const LineFastArgs& a, int bx) {
   constexpr int W = LineTaps<P>::W, R = P * RE;
   const int L = a.L;
   TO* sm = reinterpret_cast<TO*>(cem_smem);
-  const int64_t t0 = (int64_t)blockIdx.x * a.nlb;
+  const int64_t t0 = (int64_t)bx * a.nlb;
   const int nl = (int)min((int64_t)a.nlb, a.ntrans - t0);
   const TI* src = static_cast<const TI*>(a.in) + t0 * L;   // lines of axis 0 are contiguous
   for (int i = threadIdx.x; i < nl * L; i += blockDim.x) sm[i] = (TO)src[i];
@@ -472,19 +478,24 @@ __global__ void __launch_bounds__(256) k_line_x(LineFastArgs a) {
   }
 }
 
+template <int P, int RE, class TI, class TO>
+__global__ void __launch_bounds__(256) k_line_x(LineFastArgs a) {
+  k_line_x_body<P, RE, TI, TO>(a, blockIdx.x);
+}
+
 // Axes 1 and 2 (strided lines): a block stages a tile of 32 consecutive
 // transverse lines x (TY + S) line positions in LDS (coalesced rows) and
 // computes TY = 8R outputs per line; a wave is 32 lines x 2 runs.
 constexpr int kTileX = 32;
 template <int P, int RE, class TI, class TO>
-__global__ void __launch_bounds__(256) k_line_y(LineFastArgs a) {
+__device__ __forceinline__ void k_line_y_body(const LineFastArgs& a, int bx, int by) {
   // rows: the window of the last run reads up to TY + S - 1 (zero-weight tail)
   constexpr int W = LineTaps<P>::W, R = P * RE, TY = 8 * R, ROWS = TY + LineTaps<P>::S;
   const int L = a.L;
   TO* sm = reinterpret_cast<TO*>(cem_smem);
   const TI* in = static_cast<const TI*>(a.in);
-  const int64_t t0 = (int64_t)blockIdx.x * kTileX;
-  const int s0 = blockIdx.y * TY;
+  const int64_t t0 = (int64_t)bx * kTileX;
+  const int s0 = by * TY;
   const int tx = threadIdx.x % kTileX, rg = threadIdx.x / kTileX;   // rg = 0..7
   // base of transverse line t and the stride along the line
   auto base_of = [&](int64_t t) -> int64_t {
@@ -520,13 +531,18 @@ __global__ void __launch_bounds__(256) k_line_y(LineFastArgs a) {
     if (s + r < L) out[b + (int64_t)(s + r) * sl] = acc[r];
 }
 
+template <int P, int RE, class TI, class TO>
+__global__ void __launch_bounds__(256) k_line_y(LineFastArgs a) {
+  k_line_y_body<P, RE, TI, TO>(a, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // step 1 of the algorithm: element loop (WENO sensor, viscosity, residual)
 // plus the facet data of step 3 (f^H, f^L, lambda, dt_e, low-order average)
 // ---------------------------------------------------------------------------
 // minimum of dt_e over the 128 threads of a block (threads past the last
-// element contribute +inf) written to part[blockIdx.x]
-__device__ inline void block_min_dt(double* part, double v) {
+// element contribute +inf) written to part[bx] (bx: the block's index)
+__device__ inline void block_min_dt(double* part, double v, int bx) {
   __shared__ double red[128];
   red[threadIdx.x] = v;
   __syncthreads();
@@ -534,7 +550,7 @@ __device__ inline void block_min_dt(double* part, double v) {
     if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) part[bx] = red[0];
 }
 
 
@@ -1016,18 +1032,18 @@ __global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double dt_e = 1.0e300;
   if (e < a.mesh.E) dt_e = elem1_body<D, P, PH, WS, RT>(a, e, GlobalNodes<D, P, Phys<D, PH>::M>(a, e));
-  block_min_dt(a.dtpart, dt_e);     // every thread of the block reaches this
+  block_min_dt(a.dtpart, dt_e, blockIdx.x);     // every thread of the block reaches this
 }
 
 // 2D element pass on a 16 x 8 element tile: the block first stages the
 // tile's nodes (one-element halo) and, when it fits, g in LDS.
 template <int P, int PH, bool WS, class RT>
-__global__ void __launch_bounds__(128) k_elem1_tile(StageArgs a) {
+__device__ __forceinline__ void k_elem1_tile_body(const StageArgs& a, int bx) {
   constexpr int M = Phys<2, PH>::M;
   using TT = Tile2<P, M>;
   const MeshArgs& ms = a.mesh;
   const int nbx = (ms.n[0] + TT::TEX - 1) / TT::TEX;
-  const int ex0 = (blockIdx.x % nbx) * TT::TEX, ey0 = (blockIdx.x / nbx) * TT::TEY;
+  const int ex0 = (bx % nbx) * TT::TEX, ey0 = (bx / nbx) * TT::TEY;
   const int L0 = ms.L[0], L1 = ms.L[1];
   int X0 = P * (ex0 - 1), Y0 = P * (ey0 - 1);
   if (X0 < 0) X0 += L0;
@@ -1055,7 +1071,12 @@ __global__ void __launch_bounds__(128) k_elem1_tile(StageArgs a) {
     const int64_t e = ex + (int64_t)ms.n[0] * ey;
     dt_e = elem1_body<2, P, PH, WS, RT>(a, e, TileNodes2<P, M>(a, e, tx, ty));
   }
-  block_min_dt(a.dtpart, dt_e);     // every thread of the block reaches this
+  block_min_dt(a.dtpart, dt_e, bx);     // every thread of the block reaches this
+}
+
+template <int P, int PH, bool WS, class RT>
+__global__ void __launch_bounds__(128) k_elem1_tile(StageArgs a) {
+  k_elem1_tile_body<P, PH, WS, RT>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1105,12 +1126,12 @@ __device__ inline void limit_facet(const StageArgs& a, int k, int64_t eL, int64_
 }
 
 template <int D, int P, int PH, class RT>
-__global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
+__device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
   using PHY = Phys<D, PH>;
   constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NF = NL / P1;
   constexpr bool MIX = sizeof(RT) == 4;
   const TabRef<RT> T{TabSel<RT>::of(a.tab)};
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
   const MeshArgs& ms = a.mesh;
   if (e >= ms.E) return;
   const int64_t N = ms.N, E = ms.E;
@@ -1298,6 +1319,11 @@ __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
       a.relem[((int64_t)c * NL + i) * E + e] = (mloc * (ub[c] - U[c][i]) + beta * f[c][i]) * idt;
 }
 
+template <int D, int P, int PH, class RT>
+__global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
+  k_elem2_body<D, P, PH, RT>(a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // node-centric gathers of element vectors (fixed element order per node)
 // ---------------------------------------------------------------------------
@@ -1356,9 +1382,9 @@ template <> struct ResPtr<float> {
 };
 
 template <int D, int P, int M, class RT>
-__global__ void __launch_bounds__(256) k_gather_r(StageArgs a) {
+__device__ __forceinline__ void k_gather_r_body(const StageArgs& a, int bx) {
   constexpr int NL = ipow(P + 1, D);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
   if (i >= a.mesh.N) return;
   int64_t eids[8];
   int locs[8];
@@ -1373,13 +1399,18 @@ __global__ void __launch_bounds__(256) k_gather_r(StageArgs a) {
   }
 }
 
+template <int D, int P, int M, class RT>
+__global__ void __launch_bounds__(256) k_gather_r(StageArgs a) {
+  k_gather_r_body<D, P, M, RT>(a, blockIdx.x);
+}
+
 // u^FE_i = u_i + dt / m_i sum_e [m_i^e (ubar^e - u_i) + beta_e f_i^e] / dt_e
 // (eq. 49), then the Shu-Osher combination u_out = a u0 + b u^FE and, for
 // scalar problems, the round-off clamp to the global bounds.
 // global time step of the stage from the per-block minima of dt_e (every
 // block reduces them itself; block 0 records dt, the running minimum and the
 // CFL flag of eq. (23))
-__device__ inline double stage_dt(const StageArgs& a) {
+__device__ inline double stage_dt(const StageArgs& a, int bx) {
   __shared__ double red[256];
   double m = 1.0e300;
   for (int j = threadIdx.x; j < a.ndtpart; j += blockDim.x) m = fmin(m, a.dtpart[j]);
@@ -1391,7 +1422,7 @@ __device__ inline double stage_dt(const StageArgs& a) {
   }
   const double mn = red[0];
   const double dt = a.stage == 0 ? (a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl * mn) : a.dtbuf[0];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bx == 0 && threadIdx.x == 0) {
     if (a.stage == 0) a.dtbuf[0] = dt;
     a.dtbuf[1] = a.stage == 0 ? mn : fmin(a.dtbuf[1], mn);
     if (dt > mn) a.dtbuf[2] = 1.0;
@@ -1400,13 +1431,13 @@ __device__ inline double stage_dt(const StageArgs& a) {
 }
 
 template <int D, int P, int PH>
-__global__ void __launch_bounds__(256) k_update(StageArgs a) {
+__device__ __forceinline__ void k_update_body(const StageArgs& a, int bx) {
   constexpr int M = Phys<D, PH>::M;
   constexpr bool SCALAR = PH != EUL;
   constexpr int NL = ipow(P + 1, D);
   __shared__ int red[2][256];
-  const double dt = stage_dt(a);          // every thread of the block
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double dt = stage_dt(a, bx);      // every thread of the block
+  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
   int nclamp = 0, nbad = 0;
   if (i < a.mesh.N) {
     int64_t eids[8];
@@ -1457,9 +1488,14 @@ __global__ void __launch_bounds__(256) k_update(StageArgs a) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    a.counts[2 * blockIdx.x] += red[0][0];
-    a.counts[2 * blockIdx.x + 1] += red[1][0];
+    a.counts[2 * bx] += red[0][0];
+    a.counts[2 * bx + 1] += red[1][0];
   }
+}
+
+template <int D, int P, int PH>
+__global__ void __launch_bounds__(256) k_update(StageArgs a) {
+  k_update_body<D, P, PH>(a, blockIdx.x);
 }
 
 // nodal fluxes f_k(u_j) of the bound state (kNodal physics), used when the
@@ -1504,12 +1540,12 @@ __global__ void __launch_bounds__(1024) k_min_dt(const double* __restrict__ dte,
 // (fixed element order per node, as k_gather_r), stores r, then applies the
 // axis-0 line operator.
 template <int D, int P, int M, int RE, class RT>
-__global__ void __launch_bounds__(256) k_gather_line_x(StageArgs sa, LineFastArgs a) {
+__device__ __forceinline__ void k_gather_line_x_body(const StageArgs& sa, const LineFastArgs& a, int bx) {
   constexpr int W = LineTaps<P>::W, R = P * RE, NL = ipow(P + 1, D);
   const int L = a.L;
   RT* sm = reinterpret_cast<RT*>(cem_smem);
   RT* rr = ResPtr<RT>::r(sa);
-  const int64_t t0 = (int64_t)blockIdx.x * a.nlb;
+  const int64_t t0 = (int64_t)bx * a.nlb;
   const int nl = (int)min((int64_t)a.nlb, a.ntrans - t0);
   const int64_t E = sa.mesh.E, N = sa.mesh.N;
   for (int q = threadIdx.x; q < nl * L; q += blockDim.x) {
@@ -1543,6 +1579,11 @@ __global__ void __launch_bounds__(256) k_gather_line_x(StageArgs sa, LineFastArg
     for (int r = 0; r < R; ++r)
       if (s + r < L) dst[s + r] = acc[r];
   }
+}
+
+template <int D, int P, int M, int RE, class RT>
+__global__ void __launch_bounds__(256) k_gather_line_x(StageArgs sa, LineFastArgs a) {
+  k_gather_line_x_body<D, P, M, RE, RT>(sa, a, blockIdx.x);
 }
 
 // float -> double copy (debug taps of the mixed-precision intermediates)

@@ -1,0 +1,109 @@
+// Batched launches: one grid advances many independent problems (uneven
+// mesh sizes, same dimension, degree, physics and precision).  Block b of a
+// batched grid belongs to the problem pid with first[pid] <= b <
+// first[pid + 1]; it runs the same kernel body as the single-problem launch
+// with that problem's arguments and its local block index b - first[pid].
+// The argument arrays and block prefixes live in device memory, written once
+// when the batch is bound, so a whole step can be captured as a HIP graph.
+#pragma once
+#include "kernels.hpp"
+#include "kernels_sys.hpp"
+
+namespace cem {
+
+struct BatchMap {
+  const int* first;    // [nprob + 1] prefix sums of the problems' block counts
+  int nprob;
+};
+
+// problem of block b (uniform per block: a scalar binary search)
+__device__ __forceinline__ int batch_find(const BatchMap& m, int b, int* local) {
+  typedef const int __attribute__((address_space(4))) ci;
+  const ci* f = (const ci*)m.first;
+  int lo = 0, hi = m.nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (f[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  *local = b - f[lo];
+  return lo;
+}
+
+template <class TI, class TO>
+__global__ void __launch_bounds__(256) kb_line(const LineArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_line_body<TI, TO>(args[pid], lb);
+}
+
+template <int P, int RE, class TI, class TO>
+__global__ void __launch_bounds__(256) kb_line_x(const LineFastArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_line_x_body<P, RE, TI, TO>(args[pid], lb);
+}
+
+// the problem's 2D grid (gx tiles across lines, runs along the line) is
+// flattened: local block lb -> (lb % gx, lb / gx)
+template <int P, int RE, class TI, class TO>
+__global__ void __launch_bounds__(256) kb_line_y(const LineFastArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  const int gx = args[pid].gx;
+  k_line_y_body<P, RE, TI, TO>(args[pid], lb % gx, lb / gx);
+}
+
+template <int P, int PH, bool WS, class RT>
+__global__ void __launch_bounds__(128) kb_elem1_tile(const StageArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_elem1_tile_body<P, PH, WS, RT>(args[pid], lb);
+}
+
+template <int D, int P, int PH, class RT>
+__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB))
+    kb_elem1_sys(const StageArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_elem1_sys_body<D, P, PH, RT>(args[pid], lb);
+}
+
+template <int D, int P, int M, int RE, class RT>
+__global__ void __launch_bounds__(256) kb_gather_line_x(const StageArgs* __restrict__ sargs,
+                                                        const LineFastArgs* __restrict__ largs, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_gather_line_x_body<D, P, M, RE, RT>(sargs[pid], largs[pid], lb);
+}
+
+template <int D, int P, int M, class RT>
+__global__ void __launch_bounds__(256) kb_gather_r(const StageArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_gather_r_body<D, P, M, RT>(args[pid], lb);
+}
+
+template <int D, int P, int PH, class RT>
+__global__ void __launch_bounds__(128) kb_elem2(const StageArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_elem2_body<D, P, PH, RT>(args[pid], lb);
+}
+
+template <int D, int P, int PH, class RT>
+__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB))
+    kb_elem2_sys(const StageArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_elem2_sys_body<D, P, PH, RT>(args[pid], lb);
+}
+
+template <int D, int P, int PH>
+__global__ void __launch_bounds__(256) kb_update(const StageArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_update_body<D, P, PH>(args[pid], lb);
+}
+
+}  // namespace cem

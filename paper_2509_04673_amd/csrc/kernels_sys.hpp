@@ -132,18 +132,18 @@ __device__ __forceinline__ void state_at(const double* S, int q, int le, double*
 
 // minimum of dt_e over the block's elements (group 0 holds them)
 template <int EB>
-__device__ __forceinline__ void block_min_dt_sys(double* red, double* part, int c, int le, double v) {
+__device__ __forceinline__ void block_min_dt_sys(double* red, double* part, int c, int le, double v, int bx) {
   if (c == 0) red[le] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = red[0];
     for (int i = 1; i < EB; ++i) m = fmin(m, red[i]);
-    part[blockIdx.x] = m;
+    part[bx] = m;
   }
 }
 
 template <int D, int P, int PH, class RT>
-__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_elem1_sys(StageArgs a) {
+__device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
   static_assert(PH == EUL, "system element pass 1 is written for the Euler equations");
   using PHY = Phys<D, PH>;
   using SF = SFLayout<D, P>;
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_el
   const int64_t E = ms.E, N = ms.N;
   const double h = ms.h;
   const int c = threadIdx.x / EB, le = threadIdx.x - c * EB;
-  const int64_t e0 = (int64_t)blockIdx.x * EB;
+  const int64_t e0 = (int64_t)bx * EB;
   const bool live = e0 + le < E;
   const int64_t e = live ? e0 + le : E - 1;   // idle lanes redo the last element, store nothing
   double* S = cem_smem;
@@ -413,7 +413,12 @@ __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_el
       a.relem[((int64_t)c * NL + i) * E + e] = v;
     }
   }
-  block_min_dt_sys<EB>(S + LY::oRed, a.dtpart, c, le, live ? dt_e : 1.0e300);
+  block_min_dt_sys<EB>(S + LY::oRed, a.dtpart, c, le, live ? dt_e : 1.0e300, bx);
+}
+
+template <int D, int P, int PH, class RT>
+__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_elem1_sys(StageArgs a) {
+  k_elem1_sys_body<D, P, PH, RT>(a, blockIdx.x);
 }
 
 // flux-pair factor of Appendix A for the facet between eL and eR normal to
@@ -439,7 +444,7 @@ __device__ inline double euler_facet_alpha(const StageArgs& a, int k, int64_t eL
 }
 
 template <int D, int P, int PH, class RT>
-__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_elem2_sys(StageArgs a) {
+__device__ __forceinline__ void k_elem2_sys_body(const StageArgs& a, int bx) {
   static_assert(PH == EUL, "system element pass 2 is written for the Euler equations");
   using PHY = Phys<D, PH>;
   using SF = SFLayout<D, P>;
@@ -451,7 +456,7 @@ __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_el
   const int64_t E = ms.E, N = ms.N;
   const double h = ms.h;
   const int c = threadIdx.x / EB, le = threadIdx.x - c * EB;
-  const int64_t e0 = (int64_t)blockIdx.x * EB;
+  const int64_t e0 = (int64_t)bx * EB;
   const bool live = e0 + le < E;
   const int64_t e = live ? e0 + le : E - 1;
   double* S = cem_smem;
@@ -606,6 +611,11 @@ __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_el
 #pragma unroll
     for (int i = 0; i < NL; ++i) a.relem[((int64_t)c * NL + i) * E + e] = (dU[i] + beta * f[i]) * idt;
   }
+}
+
+template <int D, int P, int PH, class RT>
+__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_elem2_sys(StageArgs a) {
+  k_elem2_sys_body<D, P, PH, RT>(a, blockIdx.x);
 }
 
 }  // namespace cem

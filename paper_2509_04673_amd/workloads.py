@@ -160,6 +160,29 @@ def euler_batch_sizes(seed=0, count=512):
     return [32 + int(225 * rng.uniform()) for _ in range(count)]
 
 
+def euler_batch(seed=0, count=512, p=2, gamma=1.4, sizes=None):
+    """The batched Euler workload: count independent four-quadrant problems
+    on the unit square, Q2, square n_k^2 meshes with n_k = 32 + floor(225 U)
+    (drawn first), then each problem's quadrant states (NE, NW, SW, SE; rho,
+    vx, vy, p per quadrant) from the same generator."""
+    rng = SplitMix64(seed)
+    if sizes is None:
+        sizes = [32 + int(225 * rng.uniform()) for _ in range(count)]
+    out = []
+    for k, n in enumerate(sizes):
+        st = _quadrant_states(rng)
+        xy = node_coords(2, p, (n, n), (0.0, 0.0), (1.0, 1.0))
+        east = xy[:, 0] >= 0.5
+        north = xy[:, 1] >= 0.5
+        q = np.where(north, np.where(east, 0, 1), np.where(east, 3, 2))
+        prim = np.array(st)[q]
+        u = _conserved(prim[:, 0], [prim[:, 1], prim[:, 2]], prim[:, 3], gamma)
+        out.append(Workload(f"euler_batch[{k}]", 2, p, (n, n), (0.0, 0.0), (1.0, 1.0), "euler", u,
+                            gamma_gas=gamma, w_lin=1e-3, dt=0.0, cfl=0.5, nsteps=50,
+                            meta=dict(quadrants=st, seed=seed, index=k)))
+    return out
+
+
 MAKERS = dict(adv1d=adv1d, kpp2d=kpp2d, euler2d=euler2d, euler3d=euler3d)
 
 

@@ -1,0 +1,108 @@
+"""Batched form: independent problems of uneven sizes advanced by one launch
+per kernel and stage (HIP graph per step) give the same states as the
+single-problem path, problem by problem (to rounding), and match the
+oracle."""
+import numpy as np
+import pytest
+
+from parity_util import announce, gpu_for, oracle_for, random_scalar_workload, rel_l1, rel_linf
+from paper_2509_04673_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch_for(wls, precision="fp64"):
+    from paper_2509_04673_amd.cem import BatchSolver
+    w0 = wls[0]
+    probs = [(w.d, w.p, w.n, w.lo, w.hi) for w in wls]
+    b = BatchSolver(probs, w0.kind, w0.velocity, w0.gamma_gas, w_lin=w0.w_lin, q=w0.q, precision=precision)
+    b.upload([w.u0 for w in wls])
+    if w0.kind != "euler":
+        b.set_bounds()
+    return b
+
+
+def _singles(wls, nsteps, dt, cfl, precision="fp64"):
+    outs = []
+    for w in wls:
+        s = gpu_for(w, precision=precision)
+        for _ in range(nsteps):
+            s.step(dt=dt, cfl=cfl)
+        outs.append(s.download().ravel())
+        s.close()
+    return outs
+
+
+def _multiplicity(n, p):
+    c = np.where(np.arange(p * n) % p == 0, 2.0, 1.0)
+    return np.multiply.outer(c, c).ravel()
+
+
+# sizes straddle the switch between exact periodic line rows (n < 55 for
+# Q2) and the LDS / register-blocked line kernels
+SIZES = [32, 40, 54, 55, 64, 97, 128]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_matches_single_problems_euler(precision):
+    wls = W.euler_batch(seed=3, sizes=SIZES)
+    announce(f"[batch] euler {len(wls)} problems {SIZES} {precision}")
+    b = _batch_for(wls, precision)
+    b.step(cfl=0.5, nsteps=3)
+    got = b.download()
+    chk = b.check()
+    b.close()
+    ref = _singles(wls, 3, 0.0, 0.5, precision)
+    for k, (g, r) in enumerate(zip(got, ref)):
+        err = rel_linf(g, r)
+        mass = _multiplicity(SIZES[k], wls[k].p)
+        e1 = rel_l1(g, r, mass)
+        announce(f"[batch] problem {k} n={SIZES[k]}: batch vs single rel Linf {err:.1e}, rel L1 {e1:.1e}")
+        # the same kernel bodies, compiled into the batched wrappers: agreement
+        # to rounding (an ulp here and there from different FMA contraction);
+        # in the mixed form float-sized differences grow through the limiters
+        # at the quadrant discontinuities within three steps
+        if precision == "fp64":
+            assert err <= 1e-10, (k, err)
+        else:
+            assert e1 <= 1e-6 and err <= 1e-4, (k, e1, err)
+        assert chk[k]["violations"] == 0 and chk[k]["rho_min"] > 0 and chk[k]["p_min"] > 0
+
+
+def test_batch_matches_single_problems_kpp():
+    wls = [random_scalar_workload(2, 2, (n, n + 3), kind="kpp", seed=n) for n in (20, 57, 70)]
+    b = _batch_for(wls)
+    b.step(dt=1e-3, nsteps=4)
+    got = b.download()
+    b.close()
+    ref = _singles(wls, 4, 1e-3, 0.0)
+    for k, (g, r) in enumerate(zip(got, ref)):
+        assert rel_linf(g, r) <= 1e-12, k
+
+
+def test_batch_small_problems_match_oracle():
+    wls = W.euler_batch(seed=5, sizes=[8, 11, 6])
+    b = _batch_for(wls)
+    b.step(cfl=0.5, nsteps=2)
+    got = b.download()
+    b.close()
+    for k, w in enumerate(wls):
+        orc = oracle_for(w)
+        ref, _ = orc.run(w.u0.copy(), 2, cfl=0.5)
+        err = rel_linf(got[k], np.asarray(ref).ravel())
+        announce(f"[batch] oracle problem {k} n={w.n}: rel Linf {err:.1e}")
+        assert err <= 1e-11, (k, err)
+
+
+def test_batch_graph_replay_matches_direct():
+    from paper_2509_04673_amd import cem
+    wls = W.euler_batch(seed=4, sizes=[33, 60, 41])
+    outs = []
+    for graphs in (True, False):
+        b = _batch_for(wls)
+        cem.cem_batch_set_graphs(b.b, graphs)
+        b.step(cfl=0.5, nsteps=2)
+        b.step(cfl=0.5, nsteps=1)
+        outs.append(b.download(split=False))
+        b.close()
+    assert np.array_equal(outs[0], outs[1])
