@@ -264,6 +264,8 @@ def bench_batch(args):
     b.upload([w.u0 for w in wls])
     del wls
     cfl = 0.5
+    tune = b.autotune(cfl=cfl, steps=1)
+    print(f"[bench] autotuned plan: {tune['best']}", flush=True)
     b.step(cfl=cfl, nsteps=args.warmup)
     cem.cem_batch_reset_counters(b.b)
     stream = torch.cuda.current_stream(dev)
@@ -286,7 +288,8 @@ def bench_batch(args):
                config=dict(workload="euler_batch", problems=args.count, degree=2, dofs=dofs, physics="euler",
                            cfl=cfl, seed=0, wall_s=wall,
                            violations=int(sum(c["violations"] for c in chk)),
-                           rho_min=min(c["rho_min"] for c in chk), p_min=min(c["p_min"] for c in chk)),
+                           rho_min=min(c["rho_min"] for c in chk), p_min=min(c["p_min"] for c in chk),
+                           autotune=tune["best"]),
                roofline=None, cpu_baseline=None)
     print(json.dumps(out), flush=True)
 

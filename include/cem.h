@@ -234,6 +234,15 @@ cem_status cem_batch_set_graphs(cem_batch* b, int enable);
 cem_status cem_batch_reset_counters(cem_batch* b);
 /* one record per problem (n == count); returns the worst status. */
 cem_status cem_batch_check_invariants(cem_batch* b, cem_invariants* out, int n);
+/* Autotuner of the batched launches: times `steps` steps of every candidate
+ * plan (lines per block of the x-line kernels: 512 .. 4096 staged values;
+ * problem order: input or largest first) from the current state, keeps the
+ * fastest, and restores the state.  scratch: caller-owned device memory of
+ * at least offsets[count] doubles (the saved state).  report (optional):
+ * a JSON record of the trials and the choice, NUL-terminated, truncated to
+ * report_cap bytes.  Synchronous; resets the counters. */
+cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, void* scratch,
+                              size_t scratch_bytes, char* report, size_t report_cap);
 void cem_batch_destroy(cem_batch* b);
 
 #ifdef __cplusplus

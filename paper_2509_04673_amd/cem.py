@@ -95,6 +95,8 @@ _SIGS = [
     ("cem_batch_set_graphs", ctypes.c_int, [_P, ctypes.c_int]),
     ("cem_batch_reset_counters", ctypes.c_int, [_P]),
     ("cem_batch_check_invariants", ctypes.c_int, [_P, ctypes.POINTER(Invariants), ctypes.c_int]),
+    ("cem_batch_autotune", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _P,
+                                          ctypes.c_size_t, ctypes.c_char_p, ctypes.c_size_t]),
     ("cem_batch_destroy", None, [_P]),
 ]
 
@@ -368,6 +370,13 @@ def cem_batch_check_invariants(b, count):
     return list(inv), st
 
 
+def cem_batch_autotune(b, dt, cfl, steps, scratch_ptr, scratch_bytes):
+    buf = ctypes.create_string_buffer(8192)
+    _check(lib().cem_batch_autotune(b, float(dt), float(cfl), int(steps), _P(scratch_ptr), int(scratch_bytes),
+                                    buf, len(buf)))
+    return buf.value.decode()
+
+
 def cem_batch_destroy(b):
     lib().cem_batch_destroy(b)
 
@@ -426,6 +435,14 @@ class BatchSolver:
 
     def step(self, dt=0.0, cfl=0.0, nsteps=1):
         cem_batch_step(self.b, dt, cfl, nsteps)
+
+    def autotune(self, dt=0.0, cfl=0.0, steps=2):
+        """Pick the fastest plan (see cem_batch_autotune); returns its JSON report."""
+        import json
+        scratch = self.torch.empty_like(self.u)
+        rep = cem_batch_autotune(self.b, dt, cfl, steps, scratch.data_ptr(), scratch.numel() * 8)
+        del scratch
+        return json.loads(rep)
 
     def check(self):
         inv, st = cem_batch_check_invariants(self.b, self.count)

@@ -110,7 +110,9 @@ struct cem_batch {
   bool use_graphs = true;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph = nullptr;
+  // tuning knobs of the plan (cem_batch_autotune)
   int xlines_cap = 2048;           // axis-0 line kernels: cap on values staged per block
+  int order = 0;                   // 0: problems in input order, 1: largest first
 };
 
 namespace {
@@ -496,6 +498,11 @@ StageArgs batch_stage_args(cem_ctx* c, int stage, double dt, double cfl) {
 template <int D, int P, int PH, class RT>
 cem_status batch_plan(cem_batch* b, double dt, double cfl) {
   constexpr int M = Phys<D, PH>::M;
+  // problems in launch order (largest first puts the long-running blocks at
+  // the front of every grid)
+  std::vector<cem_ctx*> all = b->pr;
+  if (b->order == 1)
+    std::stable_sort(all.begin(), all.end(), [](const cem_ctx* x, const cem_ctx* y) { return x->N > y->N; });
   constexpr bool MIX = sizeof(RT) == 4;
   constexpr int W = LineTaps<P>::W, S = LineTaps<P>::S;
   std::vector<char> blob;
@@ -523,14 +530,14 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     out.push_back(g.l);
   };
   // one line pass of every problem (axis k), grouped by kernel variant
-  auto lines = [&](std::vector<BLaunch>& out, bool grad, int k, auto src_of, auto dst_of) -> cem_status {
+  auto lines = [&](std::vector<BLaunch>& out, const std::vector<cem_ctx*>& probs, bool grad, int k, auto src_of,
+                   auto dst_of) -> cem_status {
     Group gx, gy, gg;
     gx.l.kind = B_LINE_X;
     gy.l.kind = B_LINE_Y;
     gg.l.kind = B_LINE;
     gx.l.grad = gy.l.grad = gg.l.grad = grad;
-    for (int q = 0; q < b->count; ++q) {
-      cem_ctx* c = b->pr[q];
+    for (cem_ctx* c : probs) {
       const LineKernel& K = grad ? c->tabs.kgrad[k] : c->tabs.kmass[k];
       const void* in = src_of(c);
       void* out_p = dst_of(c);
@@ -588,10 +595,10 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     std::vector<BLaunch>& L = b->launches[st];
     L.clear();
     std::vector<StageArgs> sa(b->count);
-    for (int q = 0; q < b->count; ++q) sa[q] = batch_stage_args<D, P, PH, RT>(b->pr[q], st, dt, cfl);
+    for (int q = 0; q < b->count; ++q) sa[q] = batch_stage_args<D, P, PH, RT>(all[q], st, dt, cfl);
     // projected gradient, one pass per axis
     for (int k = 0; k < D; ++k) {
-      cem_status s = lines(L, true, k, [&](cem_ctx* c) -> const void* { return c->u; },
+      cem_status s = lines(L, all, true, k, [&](cem_ctx* c) -> const void* { return c->u; },
                            [&](cem_ctx* c) -> void* { return gbuf(c) + (int64_t)k * M * c->N; });
       if (s != CEM_OK) return s;
     }
@@ -620,7 +627,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
       gf.l.kind = B_GATHER_LX;
       gr.l.kind = B_GATHER_R;
       for (int q = 0; q < b->count; ++q) {
-        cem_ctx* c = b->pr[q];
+        cem_ctx* c = all[q];
         if (fused(c)) {
           LineFastArgs a = line_args<RT>(c, rbuf(c), mass_dst(c, 0), 0, false);
           a.nlb = std::max(1, std::min(b->xlines_cap / a.L, (int)((a.ntrans + 511) / 512)));
@@ -638,25 +645,11 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     }
     // remaining mass passes (axis 0 of the unfused problems, then axes >= 1)
     for (int k = 0; k < D; ++k) {
-      std::vector<cem_ctx*> keep;
-      std::vector<cem_ctx*> all = b->pr;
-      if (k == 0) {
-        // only the problems whose first pass was not fused
-        std::vector<cem_ctx*> sel;
-        for (cem_ctx* c : all)
-          if (!fused(c)) sel.push_back(c);
-        if (sel.empty()) continue;
-        std::swap(b->pr, sel);
-        const int cnt = b->count;
-        b->count = (int)b->pr.size();
-        cem_status s = lines(L, false, 0, [&](cem_ctx* c) -> const void* { return mass_src(c, 0); },
-                             [&](cem_ctx* c) -> void* { return mass_dst(c, 0); });
-        std::swap(b->pr, sel);
-        b->count = cnt;
-        if (s != CEM_OK) return s;
-        continue;
-      }
-      cem_status s = lines(L, false, k, [&](cem_ctx* c) -> const void* { return mass_src(c, k); },
+      std::vector<cem_ctx*> sel;        // axis 0: only the problems whose first pass was not fused
+      for (cem_ctx* c : all)
+        if (k > 0 || !fused(c)) sel.push_back(c);
+      if (sel.empty()) continue;
+      cem_status s = lines(L, sel, false, k, [&](cem_ctx* c) -> const void* { return mass_src(c, k); },
                            [&](cem_ctx* c) -> void* { return mass_dst(c, k); });
       if (s != CEM_OK) return s;
     }
@@ -671,7 +664,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
       }
       gu.l.kind = B_UPDATE;
       for (int q = 0; q < b->count; ++q) {
-        cem_ctx* c = b->pr[q];
+        cem_ctx* c = all[q];
         g2.sa.push_back(sa[q]);
         if constexpr (PH == EUL && D >= 2)
           g2.first.push_back(g2.first.back() + (int)nblocks(c->E, SysTile<D, P, PH>::EB));
@@ -1388,6 +1381,84 @@ cem_status cem_batch_check_invariants(cem_batch* b, cem_invariants* out, int n) 
     if (st == CEM_EIDP || (st == CEM_ECFL && worst == CEM_OK)) worst = st;
   }
   return worst;
+}
+
+cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, void* scratch, size_t scratch_bytes,
+                              char* report, size_t report_cap) {
+  if (!b || !b->bound || !scratch) return fail(CEM_EINVAL, "batch not bound / null scratch");
+  if (steps < 1) return fail(CEM_EINVAL, "steps < 1");
+  const size_t bytes = (size_t)b->uoff.back() * sizeof(double);
+  if (scratch_bytes < bytes) return fail(CEM_ENOMEM, "scratch smaller than the batch state");
+  auto restore = [&]() -> cem_status {
+    HIPCHK(hipMemcpyAsync(b->u, scratch, bytes, hipMemcpyDeviceToDevice, b->stream));
+    for (cem_ctx* c : b->pr) c->fnode_valid = false;   // derived nodal fluxes follow the state
+    return CEM_OK;
+  };
+  HIPCHK(hipMemcpyAsync(scratch, b->u, bytes, hipMemcpyDeviceToDevice, b->stream));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int caps[4] = {512, 1024, 2048, 4096};
+  struct Trial { int cap, order; float ms; };
+  std::vector<Trial> trials;
+  cem_status st = CEM_OK;
+  for (int order = 0; order < 2 && st == CEM_OK; ++order)
+    for (int ci = 0; ci < 4 && st == CEM_OK; ++ci) {
+      b->xlines_cap = caps[ci];
+      b->order = order;
+      batch_drop_graph(b);
+      b->plan_dt = b->plan_cfl = -1.0;
+      if ((st = restore()) != CEM_OK) break;
+      if ((st = cem_batch_step(b, dt, cfl, 1)) != CEM_OK) break;      // plan, capture, warm
+      if ((st = restore()) != CEM_OK) break;
+      if ((st = cem_batch_step(b, dt, cfl, 1)) != CEM_OK) break;      // nodal fluxes outside the timing
+      if ((st = restore()) != CEM_OK) break;
+      for (cem_ctx* c : b->pr) c->fnode_valid = c->kind != CEM_KPP;
+      if (b->kind == CEM_KPP) {
+        // KPP: the restored state needs its nodal fluxes before timing
+        for (cem_ctx* c : b->pr) {
+          StageArgs a = make_args(c);
+          hipLaunchKernelGGL((k_nodal_flux<2, KPP>), dim3(nblocks(c->N, 256)), dim3(256), 0, c->stream, a);
+          c->fnode_valid = true;
+        }
+      }
+      HIPCHK(hipEventRecord(e0, b->stream));
+      if ((st = cem_batch_step(b, dt, cfl, steps)) != CEM_OK) break;
+      HIPCHK(hipEventRecord(e1, b->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      trials.push_back({caps[ci], order, ms / steps});
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != CEM_OK) return st;
+  const Trial* best = &trials[0];
+  for (const Trial& t : trials)
+    if (t.ms < best->ms) best = &t;
+  b->xlines_cap = best->cap;
+  b->order = best->order;
+  batch_drop_graph(b);
+  b->plan_dt = b->plan_cfl = -1.0;
+  st = restore();
+  if (st != CEM_OK) return st;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  st = cem_batch_reset_counters(b);
+  if (st != CEM_OK) return st;
+  if (report && report_cap) {
+    std::string r = "{\"trials\": [";
+    char buf[160];
+    for (size_t k = 0; k < trials.size(); ++k) {
+      std::snprintf(buf, sizeof(buf), "%s{\"xlines_cap\": %d, \"order\": \"%s\", \"ms_per_step\": %.4f}",
+                    k ? ", " : "", trials[k].cap, trials[k].order ? "largest_first" : "input", trials[k].ms);
+      r += buf;
+    }
+    std::snprintf(buf, sizeof(buf), "], \"best\": {\"xlines_cap\": %d, \"order\": \"%s\", \"ms_per_step\": %.4f}}",
+                  best->cap, best->order ? "largest_first" : "input", best->ms);
+    r += buf;
+    std::snprintf(report, report_cap, "%s", r.c_str());
+  }
+  return CEM_OK;
 }
 
 }  // extern "C"

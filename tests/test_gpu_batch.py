@@ -106,3 +106,22 @@ def test_batch_graph_replay_matches_direct():
         outs.append(b.download(split=False))
         b.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_batch_autotune_keeps_state_and_results():
+    wls = W.euler_batch(seed=6, sizes=[36, 70, 50, 90])
+    b = _batch_for(wls)
+    before = b.download(split=False)
+    rep = b.autotune(cfl=0.5, steps=1)
+    announce(f"[batch] autotune: {rep['best']}")
+    assert len(rep["trials"]) == 8 and rep["best"]["ms_per_step"] > 0
+    assert np.array_equal(b.download(split=False), before)     # state restored
+    b.step(cfl=0.5, nsteps=2)
+    tuned = b.download(split=False)
+    b.close()
+    ref = _batch_for(wls)
+    ref.step(cfl=0.5, nsteps=2)
+    plain = ref.download(split=False)
+    ref.close()
+    # the plan choices change launch shapes and order, not the arithmetic
+    assert rel_linf(tuned, plain) <= 1e-12
