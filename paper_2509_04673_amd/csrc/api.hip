@@ -410,10 +410,39 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   RT* udot = MIX ? (RT*)a.udot32 : (RT*)a.udot;
   RT* tmp = c->W<RT>(MIX ? c->o_tmp32 : c->o_tmp);
   RT* tmp2 = c->W<RT>(MIX ? c->o_tmp2_32 : c->o_tmp2);
-  // projected gradient g_k = M_1D^{-1} C_1D u along axis k (Sec. 2.2)
-  for (int k = 0; k < D; ++k) {
-    cem_status s = launch_line(c, (const double*)c->u, g + (int64_t)k * M * c->N, k, true);
-    if (s != CEM_OK) return s;
+  // projected gradient g_k = M_1D^{-1} C_1D u along axis k (Sec. 2.2): the
+  // passes are independent, so on fast-kernel lines they share one launch
+  bool multi = D >= 2 && c->L[0] <= 4096;
+  for (int k = 0; k < D; ++k) multi = multi && c->tabs.kgrad[k].wfast > 0;
+  if (multi) {
+    constexpr int W = LineTaps<P>::W, S = LineTaps<P>::S, TY = 8 * P;
+    MultiLineArgs ml{};
+    ml.naxes = D;
+    size_t lds = (size_t)(TY + S) * kTileX * sizeof(RT);
+    for (int k = 0; k < D; ++k) {
+      LineFastArgs la = line_args<RT>(c, c->u, g + (int64_t)k * M * c->N, k, true);
+      if (k == 0) {
+        la.nlb = std::max(1, std::min(2048 / la.L, (int)((la.ntrans + 511) / 512)));
+        ml.nb[0] = (int)((la.ntrans + la.nlb - 1) / la.nlb);
+        lds = std::max(lds, (size_t)la.nlb * la.L * sizeof(RT));
+      } else {
+        la.gx = (int)nblocks(la.ntrans, kTileX);
+        ml.nb[k] = la.gx * ((la.L + TY - 1) / TY);
+      }
+      ml.a[k] = la;
+    }
+    int nb = 0;
+    for (int k = 0; k < D; ++k) nb += ml.nb[k];
+    if (c->L[0] >= 2 * P + 2 * W)
+      CEM_LAUNCH(c, 0, (k_line_multi<P, 2, double, RT>), nb, 256, lds, c->stream, ml);
+    else
+      CEM_LAUNCH(c, 0, (k_line_multi<P, 1, double, RT>), nb, 256, lds, c->stream, ml);
+    HIPCHK(hipGetLastError());
+  } else {
+    for (int k = 0; k < D; ++k) {
+      cem_status s = launch_line(c, (const double*)c->u, g + (int64_t)k * M * c->N, k, true);
+      if (s != CEM_OK) return s;
+    }
   }
   // element pass: sensor, residual (with the stabilisation), facet data.
   // (Running the g-independent part concurrently with the gradient passes on

@@ -536,6 +536,33 @@ __global__ void __launch_bounds__(256) k_line_y(LineFastArgs a) {
   k_line_y_body<P, RE, TI, TO>(a, blockIdx.x, blockIdx.y);
 }
 
+// The independent projected-gradient passes of all axes in one launch:
+// blocks [0, nb[0]) run the axis-0 LDS kernel, the following nb[k] blocks
+// the strided kernel of axis k (its 2D grid flattened with gx blocks across
+// lines).  Each block runs exactly one body.
+struct MultiLineArgs {
+  LineFastArgs a[3];
+  int nb[3];
+  int naxes;
+};
+
+template <int P, int REX, class TI, class TO>
+__global__ void __launch_bounds__(256) k_line_multi(MultiLineArgs m) {
+  int b = blockIdx.x;
+  if (b < m.nb[0]) {
+    k_line_x_body<P, REX, TI, TO>(m.a[0], b);
+    return;
+  }
+  b -= m.nb[0];
+  for (int k = 1; k < m.naxes; ++k) {
+    if (b < m.nb[k]) {
+      k_line_y_body<P, 1, TI, TO>(m.a[k], b % m.a[k].gx, b / m.a[k].gx);
+      return;
+    }
+    b -= m.nb[k];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // step 1 of the algorithm: element loop (WENO sensor, viscosity, residual)
 // plus the facet data of step 3 (f^H, f^L, lambda, dt_e, low-order average)
