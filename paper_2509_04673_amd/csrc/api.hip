@@ -168,8 +168,9 @@ void pack_tables(cem_ctx* c) {
   for (int k = 0; k < D; ++k) {
     c->boff_kg32[k] = put32(c->off_kg[k], T.kgrad[k].w.size());
     c->boff_km32[k] = put32(c->off_km[k], T.kmass[k].w.size());
-    c->boff_kgf32[k] = put32(c->off_kgf[k], T.kgrad[k].wf.size());
-    c->boff_kmf32[k] = put32(c->off_kmf[k], T.kmass[k].wf.size());
+    // the fast float kernels use their own, narrower rows
+    c->boff_kgf32[k] = put32(put(T.kgrad[k].wf32), T.kgrad[k].wf32.size());
+    c->boff_kmf32[k] = put32(put(T.kmass[k].wf32), T.kmass[k].wf32.size());
   }
 }
 
@@ -217,10 +218,12 @@ bool timing_events(cem_ctx* c, int id, hipEvent_t* a, hipEvent_t* b) {
 const int kWfast[5] = {0, LineTaps<1>::W, LineTaps<2>::W, LineTaps<3>::W, 0};
 const int kRfast[5] = {0, 1, 2, 3, 0};   // shortest run: RE = 1
 const int kSfast[5] = {0, LineTaps<1>::S, LineTaps<2>::S, LineTaps<3>::S, 0};
+const int kWfast32[5] = {0, LineTaps32<1>::W, LineTaps32<2>::W, LineTaps32<3>::W, 0};
+const int kSfast32[5] = {0, LineTaps32<1>::S, LineTaps32<2>::S, LineTaps32<3>::S, 0};
 
 template <int P, class TI, class TO>
 void launch_line_fast(cem_ctx* c, int id, LineFastArgs la, hipStream_t st) {
-  constexpr int W = LineTaps<P>::W;
+  constexpr int W = LineTapsV<P, TO>::W;
   if (la.axis == 0 && la.L <= 4096) {
     // whole lines in LDS; one line per block unless lines are short
     la.nlb = std::max(1, std::min(2048 / la.L, (int)((la.ntrans + 511) / 512)));
@@ -234,14 +237,14 @@ void launch_line_fast(cem_ctx* c, int id, LineFastArgs la, hipStream_t st) {
   }
   if (la.axis > 0) {
     const int RE = 1, R = P * RE, TY = 8 * R;
-    const size_t lds = (size_t)(TY + LineTaps<P>::S) * kTileX * sizeof(TO);
+    const size_t lds = (size_t)(TY + LineTapsV<P, TO>::S) * kTileX * sizeof(TO);
     dim3 grid(nblocks(la.ntrans, kTileX), (unsigned)((la.L + TY - 1) / TY));
     CEM_LAUNCH(c, id, (k_line_y<P, 1, TI, TO>), grid, 256, lds, st, la);
     return;
   }
   // longest run that still gives >= 2^17 threads (2 waves per SIMD)
   int re = kLineMaxRE;
-  while (re > 1 && (la.L < P * re + 2 * LineTaps<P>::W ||
+  while (re > 1 && (la.L < P * re + 2 * LineTapsV<P, TO>::W ||
                     la.ntrans * ((la.L + P * re - 1) / (P * re)) < (int64_t(1) << 17)))
     re /= 2;
   const int R = P * re;
@@ -415,7 +418,7 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   bool multi = D >= 2 && c->L[0] <= 4096;
   for (int k = 0; k < D; ++k) multi = multi && c->tabs.kgrad[k].wfast > 0;
   if (multi) {
-    constexpr int W = LineTaps<P>::W, S = LineTaps<P>::S, TY = 8 * P;
+    constexpr int W = LineTapsV<P, RT>::W, S = LineTapsV<P, RT>::S, TY = 8 * P;
     MultiLineArgs ml{};
     ml.naxes = D;
     size_t lds = (size_t)(TY + S) * kTileX * sizeof(RT);
@@ -533,7 +536,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
   if (b->order == 1)
     std::stable_sort(all.begin(), all.end(), [](const cem_ctx* x, const cem_ctx* y) { return x->N > y->N; });
   constexpr bool MIX = sizeof(RT) == 4;
-  constexpr int W = LineTaps<P>::W, S = LineTaps<P>::S;
+  constexpr int W = LineTapsV<P, RT>::W, S = LineTapsV<P, RT>::S;
   std::vector<char> blob;
   auto put = [&](const void* p, size_t n) {
     const size_t off = blob.size();
@@ -882,7 +885,7 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->ph.vnorm = std::sqrt(c->ph.vel[0] * c->ph.vel[0] + c->ph.vel[1] * c->ph.vel[1] + c->ph.vel[2] * c->ph.vel[2]);
   c->ph.gam = phys->gamma_gas;
   c->stream = (hipStream_t)stream;
-  if (!build_tables(d, p, h, c->L, kWfast, kRfast, kSfast, c->tabs)) {
+  if (!build_tables(d, p, h, c->L, kWfast, kRfast, kSfast, kWfast32, kSfast32, c->tabs)) {
     delete c;
     return fail(CEM_EINVAL, "table construction failed");
   }

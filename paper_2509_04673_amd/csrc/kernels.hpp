@@ -340,6 +340,13 @@ template <int P_, int W_> struct LineTapsBase {
 template <> struct LineTaps<1> : LineTapsBase<1, 36> {};
 template <> struct LineTaps<2> : LineTapsBase<2, 54> {};
 template <> struct LineTaps<3> : LineTapsBase<3, 68> {};
+// float operators (mixed precision): rows cut below 1e-9 of their peak
+template <int P> struct LineTaps32;
+template <> struct LineTaps32<1> : LineTapsBase<1, 18> {};
+template <> struct LineTaps32<2> : LineTapsBase<2, 26> {};
+template <> struct LineTaps32<3> : LineTapsBase<3, 32> {};
+template <int P, class V> struct LineTapsV : LineTaps<P> {};
+template <int P> struct LineTapsV<P, float> : LineTaps32<P> {};
 
 struct LineFastArgs {
   const void* in;      // TI
@@ -354,7 +361,7 @@ struct LineFastArgs {
 
 template <int P, int RE, class TI, class TO>
 __global__ void __launch_bounds__(256) k_line_fast(LineFastArgs a) {
-  constexpr int W = LineTaps<P>::W, R = P * RE, S = LineTaps<P>::S;
+  constexpr int W = LineTapsV<P, TO>::W, R = P * RE, S = LineTapsV<P, TO>::S;
   const TI* in = static_cast<const TI*>(a.in);
   TO* out = static_cast<TO*>(a.out);
   const TO* w = static_cast<const TO*>(a.w);
@@ -419,7 +426,7 @@ __global__ void __launch_bounds__(256) k_line_fast(LineFastArgs a) {
 // of R with a 2R-input register window; weights are wave-uniform.
 template <int P, int RE, class LD, class V>
 __device__ __forceinline__ void line_run(const V* __restrict__ w, const LD& ld, V* acc) {
-  constexpr int R = P * RE, S = LineTaps<P>::S, NB = S / R;
+  constexpr int R = P * RE, S = LineTapsV<P, V>::S, NB = S / R;
   V win[2 * R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0;
@@ -449,7 +456,7 @@ __device__ __forceinline__ void line_run(const V* __restrict__ w, const LD& ld, 
 // R outputs.  Consecutive lanes take consecutive runs.
 template <int P, int RE, class TI, class TO>
 __device__ __forceinline__ void k_line_x_body(const LineFastArgs& a, int bx) {
-  constexpr int W = LineTaps<P>::W, R = P * RE;
+  constexpr int W = LineTapsV<P, TO>::W, R = P * RE;
   const int L = a.L;
   TO* sm = reinterpret_cast<TO*>(cem_smem);
   const int64_t t0 = (int64_t)bx * a.nlb;
@@ -490,7 +497,7 @@ constexpr int kTileX = 32;
 template <int P, int RE, class TI, class TO>
 __device__ __forceinline__ void k_line_y_body(const LineFastArgs& a, int bx, int by) {
   // rows: the window of the last run reads up to TY + S - 1 (zero-weight tail)
-  constexpr int W = LineTaps<P>::W, R = P * RE, TY = 8 * R, ROWS = TY + LineTaps<P>::S;
+  constexpr int W = LineTapsV<P, TO>::W, R = P * RE, TY = 8 * R, ROWS = TY + LineTapsV<P, TO>::S;
   const int L = a.L;
   TO* sm = reinterpret_cast<TO*>(cem_smem);
   const TI* in = static_cast<const TI*>(a.in);
@@ -1568,7 +1575,7 @@ __global__ void __launch_bounds__(1024) k_min_dt(const double* __restrict__ dte,
 // axis-0 line operator.
 template <int D, int P, int M, int RE, class RT>
 __device__ __forceinline__ void k_gather_line_x_body(const StageArgs& sa, const LineFastArgs& a, int bx) {
-  constexpr int W = LineTaps<P>::W, R = P * RE, NL = ipow(P + 1, D);
+  constexpr int W = LineTapsV<P, RT>::W, R = P * RE, NL = ipow(P + 1, D);
   const int L = a.L;
   RT* sm = reinterpret_cast<RT*>(cem_smem);
   RT* rr = ResPtr<RT>::r(sa);

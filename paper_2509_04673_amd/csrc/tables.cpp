@@ -153,8 +153,8 @@ void fill_kernel(int p, int Lp, const std::vector<LD>& rows, int taps, int first
     }
 }
 
-// half-width beyond which the rows fall below 1e-20 of their peak
-int decay_width(int p, int Lp, const std::vector<LD>& rows) {
+// half-width beyond which the rows fall below thresh (1e-20) of their peak
+int decay_width(int p, int Lp, const std::vector<LD>& rows, LD thresh = 1e-20L) {
   LD peak = 0.0L;
   for (LD v : rows) peak = std::max(peak, std::fabs(v));
   int W = 0;
@@ -163,23 +163,27 @@ int decay_width(int p, int Lp, const std::vector<LD>& rows) {
       int dist = j - c;
       if (dist > Lp / 2) dist -= Lp;
       if (dist < -Lp / 2) dist += Lp;
-      if (std::fabs(rows[(size_t)c * Lp + j]) > 1e-20L * peak) W = std::max(W, std::abs(dist));
+      if (std::fabs(rows[(size_t)c * Lp + j]) > thresh * peak) W = std::max(W, std::abs(dist));
     }
   return W;
 }
 
-void line_kernels(int p, int L, LD h, int wfast, int rfast, int sfast, LineKernel& km, LineKernel& kg) {
+void line_kernels(int p, int L, LD h, int wfast, int rfast, int sfast, int wfast32, int sfast32, LineKernel& km,
+                  LineKernel& kg) {
   // infinite-line rows from a periodic auxiliary line long enough for the
   // periodic images to vanish below 1e-20
   const int Laux = ((4 * wfast + 64 + p - 1) / p) * p;
   std::vector<LD> am, ag;
   periodic_line_rows(p, Laux, h, am, ag);
   const bool fast = L >= rfast + 2 * wfast && decay_width(p, Laux, am) <= wfast &&
-                    decay_width(p, Laux, ag) <= wfast;
+                    decay_width(p, Laux, ag) <= wfast && decay_width(p, Laux, am, 1e-9L) <= wfast32 &&
+                    decay_width(p, Laux, ag, 1e-9L) <= wfast32;
   for (LineKernel* k : {&km, &kg}) {
     const std::vector<LD>& rows = (k == &km) ? am : ag;
     k->wfast = 0;
     k->wf.clear();
+    k->wfast32 = 0;
+    k->wf32.clear();
     if (fast) {
       // taps 0..2W at offsets -W..W, each class row zero padded to the
       // stride sfast of the device kernel
@@ -189,6 +193,12 @@ void line_kernels(int p, int L, LD h, int wfast, int rfast, int sfast, LineKerne
       k->wf.assign((size_t)p * sfast, 0.0);
       for (int cc = 0; cc < p; ++cc)
         for (int t = 0; t < 2 * wfast + 1; ++t) k->wf[(size_t)cc * sfast + t] = tmp[(size_t)cc * (2 * wfast + 1) + t];
+      k->wfast32 = wfast32;
+      fill_kernel(p, Laux, rows, 2 * wfast32 + 1, -wfast32, tmp);
+      k->wf32.assign((size_t)p * sfast32, 0.0);
+      for (int cc = 0; cc < p; ++cc)
+        for (int t = 0; t < 2 * wfast32 + 1; ++t)
+          k->wf32[(size_t)cc * sfast32 + t] = tmp[(size_t)cc * (2 * wfast32 + 1) + t];
     }
   }
   // generic kernel: the exact periodic rows of this line
@@ -213,7 +223,7 @@ void line_kernels(int p, int L, LD h, int wfast, int rfast, int sfast, LineKerne
 }  // namespace
 
 bool build_tables(int d, int p, double h, const int L[3], const int wfast[5], const int rfast[5],
-                  const int sfast[5], HostTables& T) {
+                  const int sfast[5], const int wfast32[5], const int sfast32[5], HostTables& T) {
   if (d < 1 || d > 3 || p < 1 || p > 4) return false;
   const int P1 = p + 1;
   int nl = 1;
@@ -299,7 +309,7 @@ bool build_tables(int d, int p, double h, const int L[3], const int wfast[5], co
     for (int j = i; j < nl; ++j) T.qp.push_back((double)((j == i ? 1.0L : 2.0L) * Q[(size_t)i * nl + j]));
 
   for (int k = 0; k < d; ++k)
-    line_kernels(p, L[k], (LD)h, wfast[p], rfast[p], sfast[p], T.kmass[k], T.kgrad[k]);
+    line_kernels(p, L[k], (LD)h, wfast[p], rfast[p], sfast[p], wfast32[p], sfast32[p], T.kmass[k], T.kgrad[k]);
   return true;
 }
 

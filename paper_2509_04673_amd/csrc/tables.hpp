@@ -26,6 +26,9 @@ struct LineKernel {
   // register-blocked kernel (empty when the line is too short for it)
   int wfast = 0;
   std::vector<double> wf;  // [P][sfast]: 2*wfast+1 taps, zero padded
+  // the same rows cut below 1e-9 of their peak (float kernels), width wfast32
+  int wfast32 = 0;
+  std::vector<double> wf32;  // [P][sfast32]
 };
 
 struct HostTables {
@@ -43,7 +46,9 @@ struct HostTables {
 // wfast[p]: half-width of the register-blocked line kernel, rfast[p]: its
 // shortest run of outputs, sfast[p]: its per-class weight stride (all must
 // match the device templates)
+// wfast32[p], sfast32[p]: width and stride of the float kernels (rows cut
+// below 1e-9 of their peak)
 bool build_tables(int d, int p, double h, const int L[3], const int wfast[5], const int rfast[5],
-                  const int sfast[5], HostTables& out);
+                  const int sfast[5], const int wfast32[5], const int sfast32[5], HostTables& out);
 
 }  // namespace cem
