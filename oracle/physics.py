@@ -31,6 +31,10 @@ class Advection:
         [KHV eq. (18)]: |v . n|."""
         return np.full(uL.shape[1:], abs(self.v[axis]))
 
+    def riemann_speed_n(self, uL, uR, n):
+        """Along a unit normal n (the subcell bound of [KHV eq. (37)])."""
+        return np.full(uL.shape[1:], abs(float(np.dot(self.v, n))))
+
 
 class KPP:
     def __init__(self, d):
@@ -47,6 +51,9 @@ class KPP:
 
     def riemann_speed(self, uL, uR, axis):
         # |f'(u) . n| <= 1 for every state between u_L and u_R
+        return np.ones(uL.shape[1:])
+
+    def riemann_speed_n(self, uL, uR, n):
         return np.ones(uL.shape[1:])
 
 
@@ -92,6 +99,25 @@ class Euler:
         g = self.g
         rhoL, rhoR = uL[0], uR[0]
         vL, vR = uL[1 + axis] / rhoL, uR[1 + axis] / rhoR
+        pL, pR = self.pressure(uL), self.pressure(uR)
+        cL = np.sqrt(np.maximum(0.0, g * pL / rhoL))
+        cR = np.sqrt(np.maximum(0.0, g * pR / rhoR))
+        e = (g - 1.0) / (2.0 * g)
+        num = np.maximum(cL + cR - 0.5 * (g - 1.0) * (vR - vL), 0.0)
+        den = cL * pL ** (-e) + cR * pR ** (-e)
+        pstar = (num / den) ** (1.0 / e)
+        kappa = (g + 1.0) / (2.0 * g)
+        lam1 = vL - cL * np.sqrt(1.0 + kappa * np.maximum(0.0, (pstar - pL) / pL))
+        lam3 = vR + cR * np.sqrt(1.0 + kappa * np.maximum(0.0, (pstar - pR) / pR))
+        return np.maximum(np.maximum(-lam1, 0.0), np.maximum(lam3, 0.0))
+
+    def riemann_speed_n(self, uL, uR, n):
+        """The same bound along a unit normal n (rotational invariance: the
+        1D problem sees the normal velocity v . n)."""
+        g = self.g
+        rhoL, rhoR = uL[0], uR[0]
+        vL = sum(n[k] * uL[1 + k] for k in range(self.d)) / rhoL
+        vR = sum(n[k] * uR[1 + k] for k in range(self.d)) / rhoR
         pL, pR = self.pressure(uL), self.pressure(uR)
         cL = np.sqrt(np.maximum(0.0, g * pL / rhoL))
         cR = np.sqrt(np.maximum(0.0, g * pR / rhoR))

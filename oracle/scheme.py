@@ -48,6 +48,11 @@ class Params:
     beta_mode: str = "limit"    # "limit" | "one" | "zero"  slope limiter
     eps_pos: float = 1e-10      # strict-positivity margin (Euler)
     clamp_ulps: float = 64.0    # round-off clamp width, in ulps of max|bound|
+    # intermediate cell averages [KHV Sec. 4.3, step 3]: "limit" = flux
+    # limiter with dt_e of eq. (40); "subcell" = no flux limiter (f = f^H)
+    # with dt_e of eq. (37); "shrink" = no flux limiter, dt_e of eq. (40)
+    # reduced until ubar^e is admissible (the Remark after eq. (40))
+    flux_mode: str = "limit"
 
 
 @dataclass
@@ -257,6 +262,53 @@ class Oracle:
         return np.min(self.weno_parts(U)["gamma"], axis=0)
 
     # -- Appendix A ---------------------------------------------------------
+    def subcell_dt(self, U, ue):
+        """Subcell bound dt_e^max of Lemma 1 [KHV eq. (37)]: boundary nodes
+        i with c_i = int_dK phi_i n ds and lambda_0i the Riemann speed of
+        (u_0, u_i) along c_i / |c_i|; u_0 is the mass-weighted mean of the
+        interior nodes (s = 1).  Without interior nodes (p = 1) u_0 = u^e,
+        s = 2 and m_0 = |K_e| (the weight 1/2 of u_0 in the decomposition
+        u^e = (u_0 + sum_i m_i u_i / |K_e|) / 2, with the doubled step)."""
+        mesh, el, F = self.mesh, self.el, self.prob.phys
+        d, p, h = mesh.d, mesh.p, mesh.h
+        vol, area = h ** d, h ** (d - 1)
+        idx = mesh.local_index()
+        lump1 = el.t1["lump"]
+        mloc = vol * el.lump
+        bnd = np.any((idx == 0) | (idx == p), axis=1)
+        cvec = np.zeros((d, mesh.nloc))
+        for k in range(d):
+            w = area * np.prod([lump1[idx[:, j]] for j in range(d) if j != k], axis=0) if d > 1 \
+                else np.ones(mesh.nloc)
+            cvec[k] = np.where(idx[:, k] == p, w, 0.0) - np.where(idx[:, k] == 0, w, 0.0)
+        cabs = np.sqrt(np.sum(cvec ** 2, axis=0))
+        if np.any(~bnd):
+            m0 = mloc[~bnd].sum()
+            u0 = np.einsum("i,cei->ce", mloc[~bnd], U[:, :, ~bnd]) / m0
+            s = 1.0
+        else:
+            m0, u0, s = vol, ue, 2.0
+        bi = np.nonzero(bnd)[0]
+        lam = np.stack([F.riemann_speed_n(u0, U[:, :, i], cvec[:, i] / cabs[i]) for i in bi], axis=-1)
+        with np.errstate(divide="ignore"):
+            t_node = np.min(mloc[bi][None, :] / (cabs[bi][None, :] * lam), axis=-1)
+            t_mean = m0 / np.sum(cabs[bi][None, :] * lam, axis=-1)
+        return np.minimum(t_node, t_mean) / s
+
+    def shrunk_dt(self, ue, fH_sum, dt_cell):
+        """The Remark after [KHV eq. (40)]: start from dt_e of (40) and take
+        the largest dt_e <= it with ubar^e = u^e - dt_e |dK|/|K| sum f^H
+        admissible (global bounds; Euler: Appendix A with its margin)."""
+        h, d = self.mesh.h, self.mesh.d
+        D = h ** (d - 1) / h ** d * fH_sum             # ubar(dt) = ue - dt D
+        if self.prob.kind == "euler":
+            return self._euler_alpha(ue, -dt_cell[None, :] * D, 1.0) * dt_cell
+        u, D0 = ue[0], D[0]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            lim = np.where(D0 > 0, (u - self.prob.u_min) / D0,
+                           np.where(D0 < 0, (self.prob.u_max - u) / -D0, np.inf))
+        return np.minimum(dt_cell, np.maximum(lim, 0.0))
+
     def _euler_alpha(self, ubar, f, mi):
         """Largest alpha_i in [0,1] with ubar + alpha f/m_i admissible
         (density, then pressure via P_i(alpha) >= alpha R_i), strict margin
@@ -333,6 +385,11 @@ class Oracle:
 
         lam_sum = sum(lam_c[k] + lam_c[k][self.nbr[(k, -1)]] for k in range(d))
         dt_e = vol / (area * lam_sum)                          # [KHV eq. (40)]
+        fH_sum = sum(outward(fH_c, k, s) for k in range(d) for s in (-1, 1))
+        if prm.flux_mode == "subcell":
+            dt_e = self.subcell_dt(U, ue)                      # [KHV eq. (37)]
+        elif prm.flux_mode == "shrink":
+            dt_e = self.shrunk_dt(ue, fH_sum, dt_e)            # Remark after (40)
         fL_sum = sum(outward(fL_c, k, s) for k in range(d) for s in (-1, 1))
         ubarL = ue - dt_e / vol * area * fL_sum                # [KHV eq. (51)]
 
@@ -365,7 +422,10 @@ class Oracle:
 
         # ---- step 4: element loop: limited averages, contributions, beta ---
         fAbar_sum = sum(outward(fAbar_c, k, s) for k in range(d) for s in (-1, 1))
-        ubar = ubarL + dt_e / vol * area * fAbar_sum           # [KHV eq. (44)]
+        if prm.flux_mode == "limit":
+            ubar = ubarL + dt_e / vol * area * fAbar_sum       # [KHV eq. (44)]
+        else:
+            ubar = ue - dt_e / vol * area * fH_sum             # f_ee' = f^H, Sec. 4.3 step 4
 
         # antidiffusive element contributions [KHV eq. (45)], g_i^e = 0
         fgrad_h = area * sum(np.einsum("ij,cej->cei", el.cgrad[k], fh_nodes[k])
@@ -434,7 +494,10 @@ class Oracle:
         return u, int(np.sum(hi) + np.sum(lo)), bad
 
     def max_dt(self, u):
-        """min_e dt_e(u) of [KHV eq. (40)] without running a stage."""
+        """min_e dt_e(u) of [KHV eq. (40)] without running a stage (with the
+        flux limiter off: of the stage's own dt_e, eq. (37) or the Remark)."""
+        if self.prob.params.flux_mode != "limit":
+            return float(np.min(self.fe_stage(u, 0.0)[1]["dt_e"]))
         mesh, F = self.mesh, self.prob.phys
         d, h = mesh.d, mesh.h
         U = u[:, self.conn]
