@@ -61,6 +61,25 @@ typedef enum { CEM_ADVECTION = 0, CEM_KPP = 1, CEM_EULER = 2 } cem_physics_kind;
  * (eq. 49) stay float64, so the invariant domain is kept exactly. */
 typedef enum { CEM_FP64 = 0, CEM_FP32_MIXED = 1 } cem_precision;
 
+/* Facet fluxes of the intermediate cell averages (Sec. 4.3, steps 3-4).
+ * CEM_FLUX_LIMIT: the flux limiter of eqs. (44), (53) / Appendix A, with
+ *   dt_e of eq. (40) (the method as presented).
+ * CEM_FLUX_SUBCELL: limiter off, f_ee' = f^H of eq. (42), dt_e the subcell
+ *   bound dt_e^max of Lemma 1 (eq. 37): over the boundary nodes i of K_e,
+ *   min of m_i / (|c_i| lambda_0i) and m_0 / sum_i |c_i| lambda_0i, with
+ *   c_i = int_dK phi_i n, lambda_0i the Riemann speed of (u_0, u_i) along
+ *   c_i / |c_i|, u_0 the mean of the interior nodes (m_0 their lumped mass);
+ *   for p = 1 (no interior node) u_0 = u^e, m_0 = |K_e| and the bound is
+ *   halved.
+ * CEM_FLUX_SHRINK: limiter off, f_ee' = f^H, dt_e of eq. (40) reduced to the
+ *   largest value that keeps u^e - dt_e |dK|/|K| sum f^H . n admissible (the
+ *   Remark after eq. 40; scalar: the global bounds, Euler: Appendix A with
+ *   its margin eps_pos).  dt_e may reach 0, which a fixed dt reports as a
+ *   CFL violation.
+ * The flux-off modes are not available for the 3D Euler equations
+ * (cem_create returns CEM_EINVAL). */
+typedef enum { CEM_FLUX_LIMIT = 0, CEM_FLUX_SUBCELL = 1, CEM_FLUX_SHRINK = 2 } cem_flux_mode;
+
 /* Uniform periodic box [lo, hi] with n[k] cube cells per axis (cell edge h
  * equal on every axis; unused axes ignored).  n[k] >= 2. */
 typedef struct {
@@ -90,6 +109,7 @@ typedef struct {
   int beta_mode;     /* slope limiter beta_e (eqs. 54-55 / Appendix A) */
   double u_min, u_max; /* global bounds of scalar problems (Sec. 4.1, 4.2) */
   int precision;       /* cem_precision */
+  int flux_mode;       /* cem_flux_mode */
 } cem_params;
 
 typedef struct cem_ctx cem_ctx;
@@ -109,7 +129,7 @@ typedef struct {
 
 /* Fills p with the defaults: q = 1, r = 2, eps = 1e-12, w_lin = 1e-3,
  * eps_pos = 1e-10, clamp_ulps = 64, all modes 0, bounds (-inf, +inf),
- * precision CEM_FP64. */
+ * precision CEM_FP64, flux_mode CEM_FLUX_LIMIT. */
 cem_status cem_params_default(cem_params* p);
 
 /* Creates a context: validates the configuration and builds the element

@@ -17,6 +17,8 @@ ADVECTION, KPP, EULER = 0, 1, 2
 KINDS = {"advection": ADVECTION, "kpp": KPP, "euler": EULER}
 FP64, FP32_MIXED = 0, 1
 PRECISIONS = {"fp64": FP64, "mixed": FP32_MIXED}
+FLUX_LIMIT, FLUX_SUBCELL, FLUX_SHRINK = 0, 1, 2
+FLUX_MODES = {"limit": FLUX_LIMIT, "subcell": FLUX_SUBCELL, "shrink": FLUX_SHRINK}
 STATUS = {0: "CEM_OK", -1: "CEM_EINVAL", -2: "CEM_EHIP", -3: "CEM_ENOMEM",
           -4: "CEM_ECFL", -5: "CEM_EIDP"}
 TAPS = dict(g=0, r=1, udot=2, gamma=3, nu=4, dt_e=5, ue=6, ubarL=7, ubar=8, beta=9,
@@ -45,7 +47,7 @@ class Params(ctypes.Structure):
                 ("clamp_ulps", ctypes.c_double), ("gamma_mode", ctypes.c_int),
                 ("alpha_mode", ctypes.c_int), ("beta_mode", ctypes.c_int),
                 ("u_min", ctypes.c_double), ("u_max", ctypes.c_double),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("flux_mode", ctypes.c_int)]
 
 
 class Invariants(ctypes.Structure):
@@ -130,6 +132,20 @@ def cem_params_default():
     p = Params()
     _check(lib().cem_params_default(ctypes.byref(p)))
     return p
+
+
+def make_params(params):
+    """cem_params from the defaults and keyword overrides; precision and
+    flux_mode also take their names ("fp64" / "mixed", "limit" / "subcell" /
+    "shrink")."""
+    prm = cem_params_default()
+    for k, v in params.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if k == "flux_mode" and isinstance(v, str):
+            v = FLUX_MODES[v]
+        setattr(prm, k, v)
+    return prm
 
 
 def cem_create(mesh, phys, prm, stream):
@@ -241,11 +257,7 @@ class Solver:
                         (ctypes.c_double * 3)(*(list(hi) + [1.0] * (3 - d))))
         phys = PhysicsDesc(KINDS[kind], (ctypes.c_double * 3)(*(list(velocity) + [0.0] * 3)[:3]),
                            gamma_gas)
-        prm = cem_params_default()
-        for k, v in params.items():
-            if k == "precision" and isinstance(v, str):
-                v = PRECISIONS[v]
-            setattr(prm, k, v)
+        prm = make_params(params)
         self.stream = torch.cuda.current_stream(self.device)
         self.ctx = cem_create(mesh, phys, prm, self.stream.cuda_stream)
         self.N, self.E, self.m = cem_sizes(self.ctx)
@@ -397,11 +409,7 @@ class BatchSolver:
                                    (ctypes.c_double * 3)(*(list(lo) + [0.0] * (3 - d))),
                                    (ctypes.c_double * 3)(*(list(hi) + [1.0] * (3 - d)))))
         phys = PhysicsDesc(KINDS[kind], (ctypes.c_double * 3)(*(list(velocity) + [0.0] * 3)[:3]), gamma_gas)
-        prm = cem_params_default()
-        for k, v in params.items():
-            if k == "precision" and isinstance(v, str):
-                v = PRECISIONS[v]
-            setattr(prm, k, v)
+        prm = make_params(params)
         self.count = len(problems)
         self.kind = kind
         self.stream = torch.cuda.current_stream(self.device)

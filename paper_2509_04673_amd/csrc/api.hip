@@ -284,6 +284,7 @@ StageArgs make_args(const cem_ctx* c) {
   a.gamma_mode = c->prm.gamma_mode;
   a.alpha_mode = c->prm.alpha_mode;
   a.beta_mode = c->prm.beta_mode;
+  a.flux_mode = c->prm.flux_mode;
   a.umin = c->prm.u_min;
   a.umax = c->prm.u_max;
   a.clamp_tol = c->prm.clamp_ulps * DBL_EPSILON * std::fmax(std::fabs(c->prm.u_min), std::fabs(c->prm.u_max));
@@ -846,6 +847,10 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
     return fail(CEM_EINVAL, "precision must be CEM_FP64 or CEM_FP32_MIXED");
   if (!pick(d, p, phys->kind, prm->precision == CEM_FP32_MIXED))
     return fail(CEM_EINVAL, "unsupported (dim, degree, physics, precision)");
+  if (prm->flux_mode < CEM_FLUX_LIMIT || prm->flux_mode > CEM_FLUX_SHRINK)
+    return fail(CEM_EINVAL, "flux_mode must be CEM_FLUX_LIMIT, CEM_FLUX_SUBCELL or CEM_FLUX_SHRINK");
+  if (prm->flux_mode != CEM_FLUX_LIMIT && d == 3 && phys->kind == CEM_EULER)
+    return fail(CEM_EINVAL, "flux limiter off is not available for the 3D Euler equations");
   double h = 0.0;
   for (int k = 0; k < d; ++k) {
     if (mesh->n[k] < 2) return fail(CEM_EINVAL, "need at least 2 cells per axis");

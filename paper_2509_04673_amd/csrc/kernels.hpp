@@ -78,6 +78,7 @@ struct StageArgs {
   PhysParams ph;
   double q, rexp, eps, w_lin, eps_pos;
   int gamma_mode, alpha_mode, beta_mode;   // 0 method, 1 force 0, 2 force 1
+  int flux_mode;        // 0 flux limiter, dt_e of (40); 1 f = f^H, dt_e of (37); 2 f = f^H, reduced (40)
   double umin, umax, clamp_tol;
   const double* u;      // stage input u^(s)   [M][N]
   double* u0;           // step base u^n       [M][N]
@@ -136,6 +137,13 @@ template <int D> struct Phys<D, ADV> {
   __device__ static inline double riemann_speed(const double*, const double*, int k, const PhysParams& pp) {
     return fabs(pp.vel[k]);
   }
+  __device__ static inline double riemann_speed_n(const double*, const double*, const double* n,
+                                                  const PhysParams& pp) {
+    double vn = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) vn += pp.vel[k] * n[k];
+    return fabs(vn);
+  }
 };
 
 template <int D> struct Phys<D, KPP> {
@@ -157,6 +165,9 @@ template <int D> struct Phys<D, KPP> {
   // |f'(u)| = |(cos u, -sin u)| = 1
   __device__ static inline double node_speed(const double*, const PhysParams&) { return 1.0; }
   __device__ static inline double riemann_speed(const double*, const double*, int, const PhysParams&) {
+    return 1.0;
+  }
+  __device__ static inline double riemann_speed_n(const double*, const double*, const double*, const PhysParams&) {
     return 1.0;
   }
 };
@@ -202,6 +213,29 @@ template <int D> struct Phys<D, EUL> {
                                                 const PhysParams& pp) {
     const double g = pp.gam;
     const double vL = uL[1 + k] / uL[0], vR = uR[1 + k] / uR[0];
+    const double pL = pressure(uL, pp), pR = pressure(uR, pp);
+    const double cL = sqrt(fmax(0.0, g * pL / uL[0]));
+    const double cR = sqrt(fmax(0.0, g * pR / uR[0]));
+    const double ex = (g - 1.0) / (2.0 * g);
+    const double num = fmax(cL + cR - 0.5 * (g - 1.0) * (vR - vL), 0.0);
+    const double den = cL * pow(pL, -ex) + cR * pow(pR, -ex);
+    const double ps = pow(num / den, 1.0 / ex);
+    const double kap = (g + 1.0) / (2.0 * g);
+    const double l1 = vL - cL * sqrt(1.0 + kap * fmax(0.0, (ps - pL) / pL));
+    const double l3 = vR + cR * sqrt(1.0 + kap * fmax(0.0, (ps - pR) / pR));
+    return fmax(fmax(-l1, 0.0), fmax(l3, 0.0));
+  }
+  // the same bound along a unit normal n (the 1D problem sees v . n)
+  __device__ static inline double riemann_speed_n(const double* uL, const double* uR, const double* n,
+                                                  const PhysParams& pp) {
+    const double g = pp.gam;
+    double mL = 0.0, mR = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      mL += n[k] * uL[1 + k];
+      mR += n[k] * uR[1 + k];
+    }
+    const double vL = mL / uL[0], vR = mR / uR[0];
     const double pL = pressure(uL, pp), pR = pressure(uR, pp);
     const double cL = sqrt(fmax(0.0, g * pL / uL[0]));
     const double cR = sqrt(fmax(0.0, g * pR / uR[0]));
@@ -755,6 +789,66 @@ template <int P, int M> struct TileNodes2 {
   }
 };
 
+// Subcell bound dt_e^max of Lemma 1 (eq. 37): over the boundary nodes i,
+// c_i = int_dK phi_i n = h^{d-1}/(p+1)^{d-1} sum over the facets holding i of
+// their outward normals, lambda_0i the Riemann speed of (u_0, u_i) along
+// c_i / |c_i|, m_i = h^d / (p+1)^d; u_0 the mean of the interior nodes and
+// s = 1, or for Q1 u_0 = u^e, m_0 = |K| and s = 2.
+template <int D, int P, class PHY>
+__device__ inline double subcell_dt(const double (*U)[ipow(P + 1, D)], const double* ue, double h,
+                                    const PhysParams& ph) {
+  constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NI = ipow(P - 1, D);
+  double hd = 1.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) hd *= h;
+  const double mi = hd * (1.0 / NL), cf = hd / h * (1.0 / ipow(P1, D - 1));
+  double u0[M];
+  double m0 = hd;
+  if constexpr (NI > 0) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        bool in = true;
+#pragma unroll
+        for (int k = 0; k < D; ++k) in = in && dig(j, k, P1) != 0 && dig(j, k, P1) != P;
+        if (in) s += U[c][j];
+      }
+      u0[c] = s * (1.0 / NI);
+    }
+    m0 = NI * mi;
+  } else {
+#pragma unroll
+    for (int c = 0; c < M; ++c) u0[c] = ue[c];
+  }
+  double tnode = 1.0e300, csum = 0.0;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    double cv[3] = {0.0, 0.0, 0.0};
+    int nf = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int dk = dig(j, k, P1);
+      if (dk == P) { cv[k] = 1.0; ++nf; }
+      else if (dk == 0) { cv[k] = -1.0; ++nf; }
+    }
+    if (nf == 0) continue;                      // interior node
+    const double nrm = sqrt((double)nf), cabs = cf * nrm;
+    double n[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) n[k] = cv[k] / nrm;
+    double uj[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) uj[c] = U[c][j];
+    const double cl = cabs * PHY::riemann_speed_n(u0, uj, n, ph);
+    if (cl > 0.0) tnode = fmin(tnode, mi / cl);
+    csum += cl;
+  }
+  const double t = fmin(tnode, csum > 0.0 ? m0 / csum : 1.0e300);
+  return NI > 0 ? t : 0.5 * t;
+}
+
 // RT: value type of the sensor and residual contractions (double, or float
 // in the mixed-precision form); cell averages, facet data and dt_e are
 // always float64
@@ -1004,9 +1098,9 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
 
   // ---- facets (Sec. 4, eqs. 18, 40, 42, 51): canonical orientation is from
   // the lower to the upper element along +e_k; both sides evaluate it alike
-  double lamsum = 0.0, fLsum[M];
+  double lamsum = 0.0, fLsum[M], fHout[M];
 #pragma unroll
-  for (int c = 0; c < M; ++c) fLsum[c] = 0.0;
+  for (int c = 0; c < M; ++c) fLsum[c] = fHout[c] = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     const double* fo = foa + k * M;
@@ -1045,11 +1139,31 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
       for (int c = 0; c < M; ++c) {
         const double fLc = 0.5 * (fl[c] + fr[c]) - 0.5 * lm * (uR[c] - uL[c]);
         fLsum[c] += side ? fLc : -fLc;
+        fHout[c] += side ? fH[c] * (1.0 / NF) : -(fH[c] * (1.0 / NF));
         if (side) a.fahi[((int64_t)k * M + c) * E + e] = fLc - fH[c] * (1.0 / NF);
       }
     }
   }
-  const double dt_e = h / lamsum;
+  double dt_e = h / lamsum;                                   // eq. (40)
+  if (a.flux_mode != 0) {
+    // flux limiter off (Sec. 4.3, steps 3-4): f_ee' = f^H and ubar^e =
+    // u^e - dt_e / h sum_facets f^H . n, with dt_e of Lemma 1 (eq. 37) or
+    // eq. (40) reduced until ubar^e is admissible
+    if (a.flux_mode == 1) {
+      dt_e = subcell_dt<D, P, PHY>(U, ue, h, a.ph);
+    } else if constexpr (PH == EUL) {
+      double dl[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) dl[c] = -dt_e / h * fHout[c];
+      dt_e *= euler_alpha<D>(ue, dl, 1.0, a.eps_pos);
+    } else {
+      const double Dr = fHout[0] / h;
+      const double lim = Dr > 0.0 ? (ue[0] - a.umin) / Dr : (Dr < 0.0 ? (a.umax - ue[0]) / -Dr : 1.0e300);
+      dt_e = fmin(dt_e, fmax(lim, 0.0));
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) a.ubar[c * E + e] = ue[c] - dt_e / h * fHout[c];
+  }
   a.dte[e] = dt_e;
   a.gam[e] = gam;
   a.nu[e] = nu;
@@ -1183,6 +1297,7 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
   for (int c = 0; c < M; ++c) fbs[c] = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
+    if (a.flux_mode != 0) break;
     int en[3] = {ei[0], ei[1], ei[2]};
     en[k] = (ei[k] + ms.n[k] - 1) % ms.n[k];
     const int64_t elo = elem_id(en, ms);
@@ -1199,9 +1314,13 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
   double ub[M], uec[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) {
-    ub[c] = a.ubarL[c * E + e] + dt_e / h * fbs[c];
     uec[c] = a.ue[c * E + e];
-    a.ubar[c * E + e] = ub[c];
+    if (a.flux_mode != 0) {
+      ub[c] = a.ubar[c * E + e];               // f = f^H, written by element pass 1
+    } else {
+      ub[c] = a.ubarL[c * E + e] + dt_e / h * fbs[c];
+      a.ubar[c * E + e] = ub[c];
+    }
   }
 
   double U[M][NL];

@@ -476,7 +476,7 @@ __device__ __forceinline__ void k_elem2_sys_body(const StageArgs& a, int bx) {
   // own coefficients into S
 #pragma unroll
   for (int l = 0; l < 2 * D; ++l) {
-    if (l % M != c) continue;
+    if (l % M != c || a.flux_mode != 0) continue;
     const int k = l / 2;
     S[LY::oFac + l * EB + le] =
         (l % 2) ? euler_facet_alpha<D>(a, k, e, enb[l]) : euler_facet_alpha<D>(a, k, enb[l], e);
@@ -490,13 +490,15 @@ __device__ __forceinline__ void k_elem2_sys_body(const StageArgs& a, int bx) {
   double fbs = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
+    if (a.flux_mode != 0) break;
     fbs -= S[LY::oFac + (2 * k) * EB + le] * a.fahi[((int64_t)k * M + c) * E + enb[2 * k]];
     fbs += S[LY::oFac + (2 * k + 1) * EB + le] * a.fahi[((int64_t)k * M + c) * E + e];
   }
-  const double ub_c = a.ubarL[c * E + e] + dt_e / h * fbs;
+  const double ub_c = a.flux_mode != 0 ? a.ubar[c * E + e]      // f = f^H, from element pass 1
+                                       : a.ubarL[c * E + e] + dt_e / h * fbs;
   const double ue_c = a.ue[c * E + e];
   S[LY::oUb + c * EB + le] = ub_c;
-  if (live) a.ubar[c * E + e] = ub_c;
+  if (live && a.flux_mode == 0) a.ubar[c * E + e] = ub_c;
 
   // ---- boundary integral B_i = int_{dK} phi_i f_h . n of component c (the
   // mixed form integrates f_h - f(ubar), its contraction partner)

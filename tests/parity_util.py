@@ -49,7 +49,7 @@ def gpu_for(wl, modes=None, precision="fp64"):
     from paper_2509_04673_amd.cem import Solver
     kw = {}
     for k, v in (modes or {}).items():
-        kw[k] = MODE_CODES[v]
+        kw[k] = v if k == "flux_mode" else MODE_CODES[v]
     s = Solver.from_workload(wl, precision=precision, **kw)
     s.upload(wl.u0)
     if wl.kind != "euler":
@@ -60,6 +60,63 @@ def gpu_for(wl, modes=None, precision="fp64"):
 def announce(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+STAGE_TAPS = ["g", "gamma", "nu", "dt_e", "ue", "ubarL", "fA", "r", "udot", "ubar", "beta"]
+
+
+def compare_stage(wl, modes=None, label="", tol=1e-12):
+    """One forward-Euler stage on the GPU and in the oracle from the same
+    state: relative L-infinity error of every intermediate and of the stage
+    result (which includes the bounds policy)."""
+    orc = oracle_for(wl, modes)
+    dt = wl.dt if wl.dt > 0 else 0.5 * orc.max_dt(wl.u0)
+    announce(f"[parity] stage {label} d={wl.d} p={wl.p} n={wl.n} kind={wl.kind} modes={modes}")
+    ufe, taps = orc.fe_stage(wl.u0, dt)
+    ufe = orc.clamp(ufe)[0]
+    s = gpu_for(wl, modes)
+    s.stage(0, dt=dt)
+    got = s.download()
+    errs = {}
+    for name in STAGE_TAPS:
+        errs[name] = rel_linf(s.tap(name).reshape(np.shape(taps[name])), taps[name])
+    errs["u_fe"] = rel_linf(got, ufe)
+    s.close()
+    announce(f"[parity] {label}: " + ", ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, (label, errs)
+    return errs, taps
+
+
+def _perturbed(u):
+    rng = np.random.default_rng(12345)
+    return u * (1.0 + rng.integers(-1, 2, u.shape) * 2.0 ** -52)
+
+
+def run_both(wl, nsteps, dt=None, cfl=0.5, modes=None):
+    """GPU and oracle runs plus the oracle's own sensitivity floor: the
+    divergence after nsteps caused by perturbing the input by 1 ulp."""
+    orc = oracle_for(wl, modes)
+    announce(f"[parity] {nsteps} steps {wl.name} n={wl.n} modes={modes}")
+    u_ref, st = orc.run(wl.u0.copy(), nsteps, dt=dt, cfl=cfl)
+    u_pert, _ = orc.run(_perturbed(wl.u0), nsteps, dt=dt, cfl=cfl)
+    floor = rel_linf(u_pert, u_ref)
+    s = gpu_for(wl, modes)
+    for _ in range(nsteps):
+        s.step(dt=dt or 0.0, cfl=0.0 if dt else cfl)
+    got = s.download()
+    chk = s.check()
+    s.close()
+    err = rel_linf(got, u_ref)
+    announce(f"[parity] {wl.name}: rel Linf GPU vs oracle {err:.3e}, oracle 1-ulp floor {floor:.3e}")
+    return err, floor, st, chk
+
+
+def run_tol(floor):
+    """1e-12, unless the scheme itself amplifies a 1-ulp input change beyond
+    it over the run; the HIP path differs from the oracle by a few ulps per
+    stage, so it may sit within a small multiple of that floor."""
+    return max(1e-12, 20.0 * floor)
 
 
 def random_scalar_workload(d, p, n, kind="advection", seed=0):

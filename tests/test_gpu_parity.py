@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 
 from paper_2509_04673_amd import workloads as W
-from parity_util import (announce, gpu_for, oracle_for, random_euler_workload,
-                         random_scalar_workload, rel_linf)
+from parity_util import (compare_stage, gpu_for, oracle_for, random_euler_workload,
+                         random_scalar_workload, run_both, run_tol)
 
 pytestmark = pytest.mark.gpu
 
@@ -34,27 +34,8 @@ STAGE_CASES = [
     ("adv3d_q2_zlong", lambda: random_scalar_workload(3, 2, (5, 4, 63))),
 ]
 
-TAP_NAMES = ["g", "gamma", "nu", "dt_e", "ue", "ubarL", "fA", "r", "udot", "ubar", "beta"]
-
-
 def _compare_stage(wl, modes=None, label=""):
-    orc = oracle_for(wl, modes)
-    dt = wl.dt if wl.dt > 0 else 0.5 * orc.max_dt(wl.u0)
-    announce(f"[parity] stage {label} d={wl.d} p={wl.p} n={wl.n} kind={wl.kind} modes={modes}")
-    ufe, taps = orc.fe_stage(wl.u0, dt)
-    ufe = orc.clamp(ufe)[0]        # the stage result includes the bounds policy
-    s = gpu_for(wl, modes)
-    s.stage(0, dt=dt)
-    got = s.download()
-    errs = {}
-    for name in TAP_NAMES:
-        errs[name] = rel_linf(s.tap(name).reshape(np.shape(taps[name])), taps[name])
-    errs["u_fe"] = rel_linf(got, ufe)
-    s.close()
-    announce(f"[parity] {label}: " + ", ".join(f"{k}={v:.1e}" for k, v in errs.items()))
-    bad = {k: v for k, v in errs.items() if not v <= TOL}
-    assert not bad, (label, errs)
-    return errs
+    return compare_stage(wl, modes, label, TOL)[0]
 
 
 @pytest.mark.parametrize("label,make", STAGE_CASES, ids=[c[0] for c in STAGE_CASES])
@@ -72,35 +53,8 @@ def test_stage_parity_method_switches(modes):
     _compare_stage(random_euler_workload(3, 2, (4, 5, 3)), modes, "switch-euler3d")
 
 
-def _perturbed(u):
-    rng = np.random.default_rng(12345)
-    return u * (1.0 + rng.integers(-1, 2, u.shape) * 2.0 ** -52)
-
-
-def _run_both(wl, nsteps, dt=None, cfl=0.5):
-    """GPU and oracle runs plus the oracle's own sensitivity floor: the
-    divergence after nsteps caused by perturbing the input by 1 ulp."""
-    orc = oracle_for(wl)
-    announce(f"[parity] {nsteps} steps {wl.name} n={wl.n}")
-    u_ref, st = orc.run(wl.u0.copy(), nsteps, dt=dt, cfl=cfl)
-    u_pert, _ = orc.run(_perturbed(wl.u0), nsteps, dt=dt, cfl=cfl)
-    floor = rel_linf(u_pert, u_ref)
-    s = gpu_for(wl)
-    for _ in range(nsteps):
-        s.step(dt=dt or 0.0, cfl=0.0 if dt else cfl)
-    got = s.download()
-    chk = s.check()
-    s.close()
-    err = rel_linf(got, u_ref)
-    announce(f"[parity] {wl.name}: rel Linf GPU vs oracle {err:.3e}, oracle 1-ulp floor {floor:.3e}")
-    return err, floor, st, chk
-
-
-def _tol(floor):
-    # 1e-12, unless the scheme itself amplifies a 1-ulp input change beyond
-    # it over the run; the HIP path differs from the oracle by a few ulps per
-    # stage, so it may sit within a small multiple of that floor
-    return max(1e-12, 20.0 * floor)
+_run_both = run_both
+_tol = run_tol
 
 
 def test_adv1d_full_run_parity():
