@@ -346,13 +346,15 @@ def main():
     dt, cfl = (wl.dt, 0.0) if wl.dt > 0 else (0.0, wl.cfl)
 
     # warm-up with every kernel timed (direct launches): the dominant kernel
+    # (at least one step, also with --warmup 0, to find that kernel)
+    nwarm = max(1, args.warmup)
     cem.cem_set_timing(s.ctx, (1 << len(cem.KERNELS)) - 1)
-    for _ in range(args.warmup):
+    for _ in range(nwarm):
         s.step(dt, cfl)
     warm = cem.cem_kernel_times(s.ctx)
     # the dominant kernel among the ids that are one device launch per stage
     # (the line-operator ids cover one launch per axis)
-    single = {k: v for k, v in warm.items() if v[1] == 3 * args.warmup}
+    single = {k: v for k, v in warm.items() if v[1] == 3 * nwarm}
     dominant = max(single, key=lambda k: single[k][0])
     print("[bench] warm-up kernel ms: " + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in warm.items()
                                                    if v[1]), flush=True)
@@ -390,7 +392,7 @@ def main():
     nbytes, nflops = kernel_work(dominant, wl, s.N, s.E, s.m, mixed)
     if dominant == "grad_line":
         # one launch may carry the passes of several axes
-        per_stage = warm[dominant][1] / (3 * args.warmup)
+        per_stage = warm[dominant][1] / (3 * nwarm)
         nbytes, nflops = nbytes * wl.d / per_stage, nflops * wl.d / per_stage
     kms, kcnt = kt[dominant]
     avg_s = (kms / kcnt) * 1e-3 if kcnt else float("nan")

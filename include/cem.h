@@ -134,6 +134,7 @@ cem_status cem_params_default(cem_params* p);
 
 /* Creates a context: validates the configuration and builds the element
  * tables on the host (Sec. 2.1: Bernstein basis; Sec. 2.2: semi-norm (8)).
+ * Size limit: m * N < 2^31 (device index arithmetic is 32-bit below it).
  * stream: hipStream_t for all later work.  *out receives the context.
  * No GPU memory is touched until cem_bind. */
 cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys,
@@ -206,10 +207,11 @@ size_t cem_tap_size(const cem_ctx* ctx, int tap);
  * times are kernel execution times without launch latency.  While a mask is
  * set, cem_step launches directly instead of replaying a graph.  Ids:
  *   0 projected-gradient line operator   1 element pass 1 (sensor,
- *   residual, facets)   2 (unused)   3 residual
- *   gather (fused with the first mass-solve pass on long x-lines)   4 mass-
- *   solve line operator   5 element pass 2 (limiters, contributions)   6 node
- *   update (with the time-step reduction).
+ *   residual, facets)   2 global time step from the per-block minima of
+ *   dt_e (a launch of its own only on large meshes; otherwise inside 6)
+ *   3 residual gather (fused with the first mass-solve pass on long
+ *   x-lines)   4 mass-solve line operator   5 element pass 2 (limiters,
+ *   contributions)   6 node update.
  * cem_kernel_times is synchronous: it returns the summed milliseconds and
  * launch counts per id since the previous call (arrays of n <= 7 entries)
  * and clears them. */

@@ -20,6 +20,11 @@
 using namespace cem;
 
 namespace {
+
+// up to this many per-block dt_e minima every node-update block reduces them
+// itself; above it one block does it once (k_stage_dt)
+constexpr int kDtFusedMax = 1024;
+
 thread_local std::string g_err;
 
 cem_status fail(cem_status s, const std::string& msg) {
@@ -226,8 +231,8 @@ void launch_line_fast(cem_ctx* c, int id, LineFastArgs la, hipStream_t st) {
   constexpr int W = LineTapsV<P, TO>::W;
   if (la.axis == 0 && la.L <= 4096) {
     // whole lines in LDS; one line per block unless lines are short
-    la.nlb = std::max(1, std::min(2048 / la.L, (int)((la.ntrans + 511) / 512)));
-    const size_t lds = (size_t)la.nlb * la.L * sizeof(TO);
+    la.nlb = line_rows_per_block<P, TO>(la.L, la.ntrans, 2048);
+    const size_t lds = (size_t)la.nlb * line_row_len<P, TO>(la.L) * sizeof(TO);
     const unsigned grid = (unsigned)((la.ntrans + la.nlb - 1) / la.nlb);
     if (la.L >= 2 * P + 2 * W)
       CEM_LAUNCH(c, id, (k_line_x<P, 2, TI, TO>), grid, 256, lds, st, la);
@@ -426,9 +431,9 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     for (int k = 0; k < D; ++k) {
       LineFastArgs la = line_args<RT>(c, c->u, g + (int64_t)k * M * c->N, k, true);
       if (k == 0) {
-        la.nlb = std::max(1, std::min(2048 / la.L, (int)((la.ntrans + 511) / 512)));
+        la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 2048);
         ml.nb[0] = (int)((la.ntrans + la.nlb - 1) / la.nlb);
-        lds = std::max(lds, (size_t)la.nlb * la.L * sizeof(RT));
+        lds = std::max(lds, (size_t)la.nlb * line_row_len<P, RT>(la.L) * sizeof(RT));
       } else {
         la.gx = (int)nblocks(la.ntrans, kTileX);
         ml.nb[k] = la.gx * ((la.L + TY - 1) / TY);
@@ -473,8 +478,8 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   int k0 = 0;
   if (c->tabs.kmass[0].wfast > 0 && c->L[0] <= 4096) {
     LineFastArgs la = line_args<RT>(c, r, D == 1 ? udot : tmp, 0, false);
-    la.nlb = std::max(1, std::min(2048 / la.L, (int)((la.ntrans + 511) / 512)));
-    const size_t lds = (size_t)la.nlb * la.L * sizeof(RT);
+    la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 2048);
+    const size_t lds = (size_t)la.nlb * line_row_len<P, RT>(la.L) * sizeof(RT);
     const unsigned grid = (unsigned)((la.ntrans + la.nlb - 1) / la.nlb);
     CEM_LAUNCH(c, 3, (k_gather_line_x<D, P, M, 1, RT>), grid, 256, lds, c->stream, a, la);
     HIPCHK(hipGetLastError());
@@ -497,6 +502,12 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     CEM_LAUNCH(c, 5, (k_elem2<D, P, PH, RT>), nblocks(c->E, 128), 128, 0, c->stream, a);
   }
   HIPCHK(hipGetLastError());
+  if (a.ndtpart > kDtFusedMax) {
+    // many per-block minima: one block reduces them once for the update
+    a.dt_ready = 1;
+    CEM_LAUNCH(c, 2, k_stage_dt, 1, 1024, 0, c->stream, a);
+    HIPCHK(hipGetLastError());
+  }
   CEM_LAUNCH(c, 6, (k_update<D, P, PH>), c->upd_blocks, 256, 0, c->stream, a);
   HIPCHK(hipGetLastError());
   return CEM_OK;
@@ -578,10 +589,10 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         LineFastArgs a = line_args<RT>(c, in, out_p, k, grad);
         if (k == 0) {
           if (a.L > 4096) return fail(CEM_EINVAL, "batched form: x-lines longer than 4096 nodes");
-          a.nlb = std::max(1, std::min(b->xlines_cap / a.L, (int)((a.ntrans + 511) / 512)));
+          a.nlb = line_rows_per_block<P, RT>(a.L, a.ntrans, b->xlines_cap);
           gx.lf.push_back(a);
           gx.first.push_back(gx.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
-          gx.l.lds = std::max(gx.l.lds, (size_t)a.nlb * a.L * sizeof(RT));
+          gx.l.lds = std::max(gx.l.lds, (size_t)a.nlb * line_row_len<P, RT>(a.L) * sizeof(RT));
         } else {
           const int TY = 8 * P;
           a.gx = (int)nblocks(a.ntrans, kTileX);
@@ -663,11 +674,11 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         cem_ctx* c = all[q];
         if (fused(c)) {
           LineFastArgs a = line_args<RT>(c, rbuf(c), mass_dst(c, 0), 0, false);
-          a.nlb = std::max(1, std::min(b->xlines_cap / a.L, (int)((a.ntrans + 511) / 512)));
+          a.nlb = line_rows_per_block<P, RT>(a.L, a.ntrans, b->xlines_cap);
           gf.sa.push_back(sa[q]);
           gf.lf.push_back(a);
           gf.first.push_back(gf.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
-          gf.l.lds = std::max(gf.l.lds, (size_t)a.nlb * a.L * sizeof(RT));
+          gf.l.lds = std::max(gf.l.lds, (size_t)a.nlb * line_row_len<P, RT>(a.L) * sizeof(RT));
         } else {
           gr.sa.push_back(sa[q]);
           gr.first.push_back(gr.first.back() + (int)nblocks(c->N, 256));
@@ -881,6 +892,10 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
     c->L[k] = p * mesh->n[k];
     c->N *= c->L[k];
     c->E *= c->n[k];
+  }
+  if ((int64_t)c->m * c->N >= (int64_t(1) << 31)) {
+    delete c;
+    return fail(CEM_EINVAL, "mesh too large: m * N must stay below 2^31");
   }
   c->nl = 1;
   for (int k = 0; k < d; ++k) c->nl *= (p + 1);

@@ -107,6 +107,7 @@ struct StageArgs {
   int stage;            // 0, 1, 2
   int copy_base;        // stage 0 of a step: write u_base = u before updating
   int ndtpart;          // number of per-block dt_e minima
+  int dt_ready;         // 1: k_stage_dt has reduced them into dtbuf
   double dt_fixed, cfl; // stage 0: dt = dt_fixed > 0 ? dt_fixed : cfl min_e dt_e
 };
 
@@ -273,11 +274,14 @@ __device__ inline double euler_alpha(const double* ub, const double* f, double m
 // ---------------------------------------------------------------------------
 // index helpers
 // ---------------------------------------------------------------------------
+// element and node ids are below 2^31 (checked at create): 32-bit division
 __device__ inline void elem_coords(int64_t e, const MeshArgs& m, int* ei) {
-  ei[0] = (int)(e % m.n[0]);
-  int64_t r = e / m.n[0];
-  ei[1] = (int)(r % m.n[1]);
-  ei[2] = (int)(r / m.n[1]);
+  const unsigned n0 = (unsigned)m.n[0], n1 = (unsigned)m.n[1];
+  unsigned r = (unsigned)e;
+  ei[0] = (int)(r % n0);
+  r /= n0;
+  ei[1] = (int)(r % n1);
+  ei[2] = (int)(r / n1);
 }
 
 __device__ inline int64_t elem_id(const int* ei, const MeshArgs& m) {
@@ -459,8 +463,12 @@ __global__ void __launch_bounds__(256) k_line_fast(LineFastArgs a) {
 // j = 0, 1, ... of the run's window (x(s - W + j)).  Taps are walked in blocks
 // of R with a 2R-input register window; weights are wave-uniform.
 template <int P, int RE, class LD, class V>
-__device__ __forceinline__ void line_run(const V* __restrict__ w, const LD& ld, V* acc) {
+__device__ __forceinline__ void line_run(const V* __restrict__ wg, const LD& ld, V* acc) {
   constexpr int R = P * RE, S = LineTapsV<P, V>::S, NB = S / R;
+  // the weights are block-uniform: read through the constant address space
+  // (scalar loads, SGPR operands of the FMAs)
+  typedef const V __attribute__((address_space(4))) CV;
+  const CV* w = (const CV*)wg;
   V win[2 * R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0;
@@ -470,7 +478,7 @@ __device__ __forceinline__ void line_run(const V* __restrict__ w, const LD& ld, 
   for (int b = 0; b < NB; ++b) {
 #pragma unroll
     for (int r = 0; r < R; ++r) win[R + r] = ld((b + 1) * R + r);
-    const V* wb = w + b * R;
+    const CV* wb = w + b * R;
 #pragma unroll
     for (int tt = 0; tt < R; ++tt) {
 #pragma unroll
@@ -485,6 +493,31 @@ __device__ __forceinline__ void line_run(const V* __restrict__ w, const LD& ld, 
   }
 }
 
+// LDS rows of the axis-0 kernels hold a periodic line padded on both sides,
+// row[k] = x((k - W) mod L) for k < line_row_len(L), so that the window of
+// every run is a plain slice: run s reads row[s + j], j < S + R.
+template <int P, class V>
+__host__ __device__ constexpr int line_row_len(int L) {
+  return L + LineTapsV<P, V>::S + kLineMaxRE * P;
+}
+
+// lines per block of the axis-0 kernels: up to cap LDS values per block, and
+// about two lines' worth of runs per thread at most
+template <int P, class V>
+__host__ __device__ inline int line_rows_per_block(int L, int64_t nlines, int cap) {
+  const int per = cap / line_row_len<P, V>(L);
+  const int64_t want = (nlines + 511) / 512;
+  return per < 1 ? 1 : (int)(want < per ? (want < 1 ? 1 : want) : per);
+}
+
+// x((k - W) mod L) of the padded row position k
+__device__ __forceinline__ int line_wrap(int k, int W, int L) {
+  int x = k - W;
+  while (x < 0) x += L;
+  while (x >= L) x -= L;
+  return x;
+}
+
 // Axis 0 (contiguous lines): a block stages nlb whole lines in LDS (one
 // coalesced copy, periodic wrap inside LDS) and each thread computes runs of
 // R outputs.  Consecutive lanes take consecutive runs.
@@ -496,20 +529,17 @@ __device__ __forceinline__ void k_line_x_body(const LineFastArgs& a, int bx) {
   const int64_t t0 = (int64_t)bx * a.nlb;
   const int nl = (int)min((int64_t)a.nlb, a.ntrans - t0);
   const TI* src = static_cast<const TI*>(a.in) + t0 * L;   // lines of axis 0 are contiguous
-  for (int i = threadIdx.x; i < nl * L; i += blockDim.x) sm[i] = (TO)src[i];
+  const int LS = line_row_len<P, TO>(L);
+  for (int i = threadIdx.x; i < nl * LS; i += blockDim.x) {
+    const int line = i / LS;
+    sm[i] = (TO)src[line * L + line_wrap(i - line * LS, W, L)];
+  }
   __syncthreads();
   const int runs = (L + R - 1) / R;
   for (int g = threadIdx.x; g < nl * runs; g += blockDim.x) {
     const int line = g / runs, s = (g - line * runs) * R;
-    const TO* row = sm + line * L;
-    int p0 = s - W;
-    if (p0 < 0) p0 += L;
-    auto ld = [&](int j) {
-      int q = p0 + j;
-      if (q >= L) q -= L;
-      if (q >= L) q -= L;
-      return row[q];
-    };
+    const TO* row = sm + line * LS + s;
+    auto ld = [&](int j) { return row[j]; };
     TO acc[R];
     line_run<P, RE>(static_cast<const TO*>(a.w), ld, acc);
     TO* dst = static_cast<TO*>(a.out) + (t0 + line) * L;
@@ -1483,12 +1513,12 @@ __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
 template <int D, int P>
 __device__ inline int node_elements(int64_t i, const MeshArgs& m, int64_t* eids, int* locs) {
   int ik[3] = {0, 0, 0};
-  int64_t r = i;
-  ik[0] = (int)(r % m.L[0]);
-  r /= m.L[0];
+  unsigned r = (unsigned)i;                 // node ids are below 2^31
+  ik[0] = (int)(r % (unsigned)m.L[0]);
+  r /= (unsigned)m.L[0];
   if (D > 1) {
-    ik[1] = (int)(r % m.L[1]);
-    r /= m.L[1];
+    ik[1] = (int)(r % (unsigned)m.L[1]);
+    r /= (unsigned)m.L[1];
   }
   if (D > 2) ik[2] = (int)r;
   int cnt[3], ek[3][2], ak[3][2];
@@ -1563,7 +1593,15 @@ __global__ void __launch_bounds__(256) k_gather_r(StageArgs a) {
 // global time step of the stage from the per-block minima of dt_e (every
 // block reduces them itself; block 0 records dt, the running minimum and the
 // CFL flag of eq. (23))
+__device__ inline void stage_dt_record(const StageArgs& a, double mn) {
+  const double dt = a.stage == 0 ? (a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl * mn) : a.dtbuf[0];
+  if (a.stage == 0) a.dtbuf[0] = dt;
+  a.dtbuf[1] = a.stage == 0 ? mn : fmin(a.dtbuf[1], mn);
+  if (dt > mn) a.dtbuf[2] = 1.0;
+}
+
 __device__ inline double stage_dt(const StageArgs& a, int bx) {
+  if (a.dt_ready) return a.dtbuf[0];       // reduced by k_stage_dt (uniform branch)
   __shared__ double red[256];
   double m = 1.0e300;
   for (int j = threadIdx.x; j < a.ndtpart; j += blockDim.x) m = fmin(m, a.dtpart[j]);
@@ -1574,13 +1612,8 @@ __device__ inline double stage_dt(const StageArgs& a, int bx) {
     __syncthreads();
   }
   const double mn = red[0];
-  const double dt = a.stage == 0 ? (a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl * mn) : a.dtbuf[0];
-  if (bx == 0 && threadIdx.x == 0) {
-    if (a.stage == 0) a.dtbuf[0] = dt;
-    a.dtbuf[1] = a.stage == 0 ? mn : fmin(a.dtbuf[1], mn);
-    if (dt > mn) a.dtbuf[2] = 1.0;
-  }
-  return dt;
+  if (bx == 0 && threadIdx.x == 0) stage_dt_record(a, mn);
+  return a.stage == 0 ? (a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl * mn) : a.dtbuf[0];
 }
 
 template <int D, int P, int PH>
@@ -1666,26 +1699,20 @@ __global__ void __launch_bounds__(256) k_nodal_flux(StageArgs a) {
   for (int q = 0; q < D * M; ++q) a.fnode[q * a.mesh.N + i] = f[q];
 }
 
-// min_e dt_e from the per-block minima, global time step for the stage and
-// the CFL check of eq. (23) (single block, deterministic)
-__global__ void __launch_bounds__(1024) k_min_dt(const double* __restrict__ dte, int64_t E,
-                                                 double* dtbuf, int stage, double dt_fixed,
-                                                 double cfl) {
+// The same reduction in one block of 1024 threads, ahead of the node update,
+// when there are many per-block minima (k_update then reads dtbuf[0] instead
+// of every block reducing all of them itself)
+__global__ void __launch_bounds__(1024) k_stage_dt(StageArgs a) {
   __shared__ double red[1024];
   double m = 1.0e300;
-  for (int64_t e = threadIdx.x; e < E; e += blockDim.x) m = fmin(m, dte[e]);
+  for (int j = threadIdx.x; j < a.ndtpart; j += blockDim.x) m = fmin(m, a.dtpart[j]);
   red[threadIdx.x] = m;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double mn = red[0];
-    if (stage == 0) dtbuf[0] = dt_fixed > 0.0 ? dt_fixed : cfl * mn;
-    dtbuf[1] = fmin(stage == 0 ? 1.0e300 : dtbuf[1], mn);
-    if (dtbuf[0] > mn) dtbuf[2] = 1.0;
-  }
+  if (threadIdx.x == 0) stage_dt_record(a, red[0]);
 }
 
 // Residual assembly fused with the first mass-solve pass (axis 0): a block
@@ -1701,30 +1728,34 @@ __device__ __forceinline__ void k_gather_line_x_body(const StageArgs& sa, const 
   const int64_t t0 = (int64_t)bx * a.nlb;
   const int nl = (int)min((int64_t)a.nlb, a.ntrans - t0);
   const int64_t E = sa.mesh.E, N = sa.mesh.N;
+  const int lpc = (int)(N / L);                  // lines per component
+  const int LS = line_row_len<P, RT>(L);
   for (int q = threadIdx.x; q < nl * L; q += blockDim.x) {
-    const int64_t g = (t0 + q / L) * L + q % L;   // component-major flat index
-    const int64_t c = g / N, i = g - c * N;
+    const int ql = q / L, x = q - ql * L;
+    const int line = (int)t0 + ql, c = line / lpc;
+    const int64_t i = (int64_t)(line - c * lpc) * L + x;
+    const int64_t g = c * N + i;                   // component-major flat index
     int64_t eids[8];
     int locs[8];
     const int nrec = node_elements<D, P>(i, sa.mesh, eids, locs);
     double s = 0.0;
     for (int t = 0; t < nrec; ++t) s += sa.relem[(c * NL + locs[t]) * E + eids[t]];
-    sm[q] = (RT)s;
+    sm[ql * LS + W + x] = (RT)s;
     rr[g] = (RT)s;
+  }
+  __syncthreads();
+  // periodic padding of the rows from their interiors
+  for (int q = threadIdx.x; q < nl * (LS - L); q += blockDim.x) {
+    const int ql = q / (LS - L), h = q - ql * (LS - L);
+    const int k = h < W ? h : L + h;
+    sm[ql * LS + k] = sm[ql * LS + W + line_wrap(k, W, L)];
   }
   __syncthreads();
   const int runs = (L + R - 1) / R;
   for (int g = threadIdx.x; g < nl * runs; g += blockDim.x) {
     const int line = g / runs, s = (g - line * runs) * R;
-    const RT* row = sm + line * L;
-    int p0 = s - W;
-    if (p0 < 0) p0 += L;
-    auto ld = [&](int j) {
-      int q = p0 + j;
-      if (q >= L) q -= L;
-      if (q >= L) q -= L;
-      return row[q];
-    };
+    const RT* row = sm + line * LS + s;
+    auto ld = [&](int j) { return row[j]; };
     RT acc[R];
     line_run<P, RE>(static_cast<const RT*>(a.w), ld, acc);
     RT* dst = static_cast<RT*>(a.out) + (t0 + line) * L;
