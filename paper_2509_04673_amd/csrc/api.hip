@@ -241,7 +241,7 @@ void launch_line_fast(cem_ctx* c, int id, LineFastArgs la, hipStream_t st) {
     return;
   }
   if (la.axis > 0) {
-    const int RE = 1, R = P * RE, TY = 8 * R;
+    const int RE = 1, R = P * RE, TY = 8 * R * la.ky;
     const size_t lds = (size_t)(TY + LineTapsV<P, TO>::S) * kTileX * sizeof(TO);
     dim3 grid(nblocks(la.ntrans, kTileX), (unsigned)((la.L + TY - 1) / TY));
     CEM_LAUNCH(c, id, (k_line_y<P, 1, TI, TO>), grid, 256, lds, st, la);
@@ -335,6 +335,7 @@ LineFastArgs line_args(const cem_ctx* c, const void* in, void* out, int axis, bo
   la.N = c->N;
   la.NT = c->N / c->L[axis];
   la.ntrans = (int64_t)c->m * la.NT;
+  la.ky = axis > 0 ? line_y_runs(la.ntrans, la.L, c->p) : 1;
   return la;
 }
 
@@ -435,8 +436,10 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
         ml.nb[0] = (int)((la.ntrans + la.nlb - 1) / la.nlb);
         lds = std::max(lds, (size_t)la.nlb * line_row_len<P, RT>(la.L) * sizeof(RT));
       } else {
+        const int TYk = TY * la.ky;
         la.gx = (int)nblocks(la.ntrans, kTileX);
-        ml.nb[k] = la.gx * ((la.L + TY - 1) / TY);
+        ml.nb[k] = la.gx * ((la.L + TYk - 1) / TYk);
+        lds = std::max(lds, (size_t)(TYk + S) * kTileX * sizeof(RT));
       }
       ml.a[k] = la;
     }
@@ -594,11 +597,11 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
           gx.first.push_back(gx.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
           gx.l.lds = std::max(gx.l.lds, (size_t)a.nlb * line_row_len<P, RT>(a.L) * sizeof(RT));
         } else {
-          const int TY = 8 * P;
+          const int TY = 8 * P * a.ky;
           a.gx = (int)nblocks(a.ntrans, kTileX);
           gy.lf.push_back(a);
           gy.first.push_back(gy.first.back() + a.gx * ((a.L + TY - 1) / TY));
-          gy.l.lds = (size_t)(TY + S) * kTileX * sizeof(RT);
+          gy.l.lds = std::max(gy.l.lds, (size_t)(TY + S) * kTileX * sizeof(RT));
         }
       } else {
         LineArgs a{};

@@ -395,6 +395,7 @@ struct LineFastArgs {
   int64_t N, NT, ntrans;   // NT = N / L lines per component
   int nlb;                 // lines per block (axis 0 LDS kernel)
   int gx;                  // blocks across lines of a 2D grid (batched launches)
+  int ky;                  // runs per thread of the strided kernel (tile length 8 R ky)
 };
 
 template <int P, int RE, class TI, class TO>
@@ -558,10 +559,21 @@ __global__ void __launch_bounds__(256) k_line_x(LineFastArgs a) {
 // transverse lines x (TY + S) line positions in LDS (coalesced rows) and
 // computes TY = 8R outputs per line; a wave is 32 lines x 2 runs.
 constexpr int kTileX = 32;
+// Longer tiles re-read less of the 2W halo: a thread computes ky runs
+// (rows rg + 8 q, q < ky), the tile covers TY = 8 R ky outputs per line.
+// ky: the longest tile that still leaves >= 2048 blocks for one problem.
+inline int line_y_runs(int64_t ntrans, int L, int R) {
+  const int64_t gx = (ntrans + kTileX - 1) / kTileX;
+  for (int ky = 4; ky > 1; ky /= 2)
+    if (gx * ((L + 8 * R * ky - 1) / (8 * R * ky)) >= 2048) return ky;
+  return 1;
+}
+
 template <int P, int RE, class TI, class TO>
 __device__ __forceinline__ void k_line_y_body(const LineFastArgs& a, int bx, int by) {
   // rows: the window of the last run reads up to TY + S - 1 (zero-weight tail)
-  constexpr int W = LineTapsV<P, TO>::W, R = P * RE, TY = 8 * R, ROWS = TY + LineTapsV<P, TO>::S;
+  constexpr int W = LineTapsV<P, TO>::W, R = P * RE;
+  const int TY = 8 * R * a.ky, ROWS = TY + LineTapsV<P, TO>::S;
   const int L = a.L;
   TO* sm = reinterpret_cast<TO*>(cem_smem);
   const TI* in = static_cast<const TI*>(a.in);
@@ -591,15 +603,20 @@ __device__ __forceinline__ void k_line_y_body(const LineFastArgs& a, int bx, int
     if (p >= L) p -= L;
   }
   __syncthreads();
-  const int s = s0 + rg * R;
-  if (!have || s >= L) return;
-  auto ld = [&](int j) { return sm[(rg * R + j) * kTileX + tx]; };
-  TO acc[R];
-  line_run<P, RE>(static_cast<const TO*>(a.w), ld, acc);
+  if (!have) return;
   TO* out = static_cast<TO*>(a.out);
+#pragma unroll 1
+  for (int q = 0; q < a.ky; ++q) {
+    const int row0 = (rg + 8 * q) * R, s = s0 + row0;
+    if (s >= L) return;
+    const TO* col = sm + row0 * kTileX + tx;
+    auto ld = [&](int j) { return col[j * kTileX]; };
+    TO acc[R];
+    line_run<P, RE>(static_cast<const TO*>(a.w), ld, acc);
 #pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (s + r < L) out[b + (int64_t)(s + r) * sl] = acc[r];
+    for (int r = 0; r < R; ++r)
+      if (s + r < L) out[b + (int64_t)(s + r) * sl] = acc[r];
+  }
 }
 
 template <int P, int RE, class TI, class TO>
