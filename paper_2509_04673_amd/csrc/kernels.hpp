@@ -295,10 +295,10 @@ __device__ inline int64_t node_stride(int k, const MeshArgs& m) {
 // global node offsets along axis k of the local indices a = 0..P of the
 // element with (possibly out-of-range, periodic) coordinate ek
 template <int P>
-__device__ inline void axis_offsets(int ek, int k, const MeshArgs& m, int64_t* off) {
+__device__ inline void axis_offsets(int ek, int k, const MeshArgs& m, int* off) {
   const int n = m.n[k], L = m.L[k];
   ek = (ek % n + n) % n;
-  const int64_t s = node_stride(k, m);
+  const int s = (int)node_stride(k, m);      // node ids are below 2^31
 #pragma unroll
   for (int a = 0; a <= P; ++a) {
     int i = P * ek + a;
@@ -308,8 +308,8 @@ __device__ inline void axis_offsets(int ek, int k, const MeshArgs& m, int64_t* o
 }
 
 template <int D, int P>
-__device__ inline int64_t local_node(int loc, const int64_t (*off)[P + 1]) {
-  int64_t s = 0;
+__device__ inline int local_node(int loc, const int (*off)[P + 1]) {
+  int s = 0;
 #pragma unroll
   for (int k = 0; k < D; ++k) s += off[k][dig(loc, k, P + 1)];
   return s;
@@ -716,11 +716,17 @@ __device__ __forceinline__ void tensor_apply(const TB& T, const int* mo, bool tr
 
 // x^T Q x with Q packed as upper-triangle rows (off-diagonals doubled)
 template <int NL, class TB, class V>
-__device__ __forceinline__ V qsym(const TB& T, int off, const V* x) {
+__device__ __forceinline__ V qsym(const TB& T0, int off, const V* x) {
+  // The coefficients are block-uniform scalar loads.  Issued all at once
+  // (NL (NL+1)/2 of them) they overflow the SGPRs and get parked in VGPR
+  // lanes, one v_readlane per use; tying the pointer of every third row to
+  // the running sum makes the loads stream row group by row group.
+  TB T = T0;
   V s = 0;
   int p = off;
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
+    if (i % 3 == 0) asm volatile("" : "+s"(T.g) : "v"(s));
     V t = T(p++) * x[i];
 #pragma unroll
     for (int j = i + 1; j < NL; ++j) t += T(p++) * x[j];
@@ -746,7 +752,7 @@ __device__ __forceinline__ double ref_grad_int(int i, int k) {
 template <int D, int P, int M> struct GlobalNodes {
   const StageArgs* a;
   int ei[3];
-  int64_t off[D][P + 1];
+  int off[D][P + 1];
   __device__ __forceinline__ GlobalNodes(const StageArgs& a_, int64_t e) : a(&a_) {
     elem_coords(e, a_.mesh, ei);
 #pragma unroll
@@ -765,13 +771,13 @@ template <int D, int P, int M> struct GlobalNodes {
   __device__ __forceinline__ void load_nbr(int c, int l, double* cn) const {
     constexpr int NL = ipow(P + 1, D);
     const int k = l / 2, s = (l % 2) ? 1 : -1;
-    int64_t offn[D][P + 1];
+    int offn[D][P + 1];
 #pragma unroll
     for (int kk = 0; kk < D; ++kk) axis_offsets<P>(ei[kk] + (kk == k ? s : 0), kk, a->mesh, offn[kk]);
 #pragma unroll
     for (int j = 0; j < NL; ++j) cn[j] = a->u[c * a->mesh.N + local_node<D, P>(j, offn)];
   }
-  __device__ __forceinline__ int64_t own_node(int j) const { return local_node<D, P>(j, off); }
+  __device__ __forceinline__ int own_node(int j) const { return local_node<D, P>(j, off); }
   // projected gradient: g (float64) or g32 (mixed precision)
   template <class V>
   __device__ __forceinline__ void load_grad(int c, V (*gk)[ipow(P + 1, D)]) const {
@@ -1333,7 +1339,7 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
   const double h = ms.h;
   int ei[3];
   elem_coords(e, ms, ei);
-  int64_t off[D][P1];
+  int off[D][P1];
 #pragma unroll
   for (int k = 0; k < D; ++k) axis_offsets<P>(ei[k], k, ms, off[k]);
 

@@ -38,6 +38,19 @@ template <int D, int P, int PH> struct SysTile {
   using LY = SysLayout<D, P, PH, EB>;
 };
 
+// f(integral constant K) for K = 0 .. N-1: a loop whose index is a
+// compile-time constant in the body (an axis as a template argument)
+template <int K> struct IC {
+  static constexpr int value = K;
+};
+template <int N, int K = 0, class F>
+__device__ __forceinline__ void static_for(const F& f) {
+  if constexpr (K < N) {
+    f(IC<K>{});
+    static_for<N, K + 1>(f);
+  }
+}
+
 // component c of a value array computed for all components (a select chain:
 // no dynamically indexed register array)
 template <int M, class V>
@@ -142,7 +155,10 @@ __device__ __forceinline__ void block_min_dt_sys(double* red, double* part, int 
   }
 }
 
-template <int D, int P, int PH, class RT>
+// PART 0: the whole pass; PART 1: sensor, viscosity and facet data only;
+// PART 2: the element residual only, from the cell averages, gamma_e and nu_e
+// that PART 1 stored (two launches with fewer live registers each)
+template <int D, int P, int PH, class RT, int PART = 0>
 __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
   static_assert(PH == EUL, "system element pass 1 is written for the Euler equations");
   using PHY = Phys<D, PH>;
@@ -171,6 +187,15 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
     Us[j * CS] = v;
   }
   ue_c *= (1.0 / NL);
+  double uo[M], gam, nu, dt_keep = 0.0;
+  if constexpr (PART == 2) {
+    // stored by PART 1 (the same sums)
+    ue_c = a.ue[c * E + e];
+#pragma unroll
+    for (int k = 0; k < M; ++k) uo[k] = a.ue[k * E + e];
+    gam = a.gam[e];
+    nu = a.nu[e];
+  } else {
 
   // ---- WENO sensor of component c (Sec. 2.2, eqs. 7-8): candidates are
   // the facet neighbours extended into K_e by the blossom maps; semi-norms
@@ -188,19 +213,25 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
       for (int j = 0; j < NL; ++j) x[j] = (RT)(Us[j * CS] - u0);
       beta0 = qsym<NL>(T, SF::qp, x);
     }
+    // the axis is a compile-time constant in the body, so the candidate
+    // arrays stay in registers; the two sides of an axis form a rolled loop
+    static_for<D>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
 #pragma unroll 1
-    for (int l = 0; l < 2 * D; ++l) {
-      double cn[NL], sum = 0.0;
-      ns.load_nbr(c, l, cn);
+      for (int side = 0; side < 2; ++side) {
+        const int l = 2 * k + side;
+        double cn[NL], sum = 0.0;
+        ns.load_nbr(c, l, cn);
 #pragma unroll
-      for (int j = 0; j < NL; ++j) sum += cn[j];
-      S[LY::oNm + (l * M + c) * EB + le] = sum * (1.0 / NL);
-      RT cr[NL];
+        for (int j = 0; j < NL; ++j) sum += cn[j];
+        S[LY::oNm + (l * M + c) * EB + le] = sum * (1.0 / NL);
+        RT cr[NL];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
-      ax_ip<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cr);
-      set_sel<2 * D>(betan, l, qsym<NL>(T, SF::qp, cr));
-    }
+        for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
+        ax_ip1<D, P, k>(T, SF::ext + side * P1 * P1, false, cr);
+        set_sel<2 * D>(betan, l, qsym<NL>(T, SF::qp, cr));
+      }
+    });
     if (a.gamma_mode == 0) {
       auto nrm = [&](RT b) { return (a.rexp == 2.0) ? b : (RT)pow((double)b, 0.5 * a.rexp); };
       const RT eps = (RT)a.eps, wlin = (RT)a.w_lin;
@@ -216,18 +247,22 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
 #pragma unroll
       for (int j = 0; j < NL; ++j) w[j] = 0;
       const double u0 = Us[0];
+      static_for<D>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
 #pragma unroll 1
-      for (int l = 0; l < 2 * D; ++l) {
-        const RT om = get_sel<2 * D>(wt, l) * iws;
-        double cn[NL];
-        ns.load_nbr(c, l, cn);
-        RT cr[NL];
+        for (int side = 0; side < 2; ++side) {
+          const int l = 2 * k + side;
+          const RT om = get_sel<2 * D>(wt, l) * iws;
+          double cn[NL];
+          ns.load_nbr(c, l, cn);
+          RT cr[NL];
 #pragma unroll
-        for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
-        ax_ip<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cr);
+          for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
+          ax_ip1<D, P, k>(T, SF::ext + side * P1 * P1, false, cr);
 #pragma unroll
-        for (int i = 0; i < NL; ++i) w[i] += om * ((RT)(Us[i * CS] - u0) - cr[i]);
-      }
+          for (int i = 0; i < NL; ++i) w[i] += om * ((RT)(Us[i * CS] - u0) - cr[i]);
+        }
+      });
       // 0/0 on constant elements, regularised with the weights' epsilon
       const RT q2 = qsym<NL>(T, SF::qp, w);
       const RT dev = sqrt(q2 > (RT)0 ? q2 : (RT)0);
@@ -242,7 +277,6 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
 
   // ---- facet wave speeds (eq. 18), facet l handled by group l mod m;
   // node speeds (viscosity), nodes j = c, c + m, ...
-  double uo[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) uo[k] = S[LY::oUe + k * EB + le];
 #pragma unroll
@@ -271,8 +305,8 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
     gmin = fmin(gmin, S[LY::oGam + k * EB + le]);
     lam = fmax(lam, S[LY::oPart + k * EB + le]);
   }
-  const double gam = a.gamma_mode == 0 ? gmin : (a.gamma_mode == 1 ? 0.0 : 1.0);
-  const double nu = lam * h / (2.0 * P);
+  gam = a.gamma_mode == 0 ? gmin : (a.gamma_mode == 1 ? 0.0 : 1.0);
+  nu = lam * h / (2.0 * P);
 
   // ---- facet fluxes of component c (eqs. 18, 40, 42, 51): f^L against the
   // neighbour averages, f^H = mean of f(u_j) n over the + facet's nodes
@@ -320,6 +354,13 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
       a.nu[e] = nu;
     }
   }
+  if constexpr (PART == 1) {
+    block_min_dt_sys<EB>(S + LY::oRed, a.dtpart, c, le, live ? dt_e : 1.0e300, bx);
+    return;
+  } else if constexpr (PART == 0) {
+    dt_keep = dt_e;
+  }
+  }   // PART != 2
 
   // ---- element residual R_i = int grad phi_i . f(u_h) - s_h^e(phi_i, u_h):
   // the stabilisation first (from the nodal coefficients), then the Gauss-
@@ -413,12 +454,12 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
       a.relem[((int64_t)c * NL + i) * E + e] = v;
     }
   }
-  block_min_dt_sys<EB>(S + LY::oRed, a.dtpart, c, le, live ? dt_e : 1.0e300, bx);
+  if constexpr (PART == 0) block_min_dt_sys<EB>(S + LY::oRed, a.dtpart, c, le, live ? dt_keep : 1.0e300, bx);
 }
 
-template <int D, int P, int PH, class RT>
+template <int D, int P, int PH, class RT, int PART = 0>
 __global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_elem1_sys(StageArgs a) {
-  k_elem1_sys_body<D, P, PH, RT>(a, blockIdx.x);
+  k_elem1_sys_body<D, P, PH, RT, PART>(a, blockIdx.x);
 }
 
 // flux-pair factor of Appendix A for the facet between eL and eR normal to
