@@ -43,19 +43,31 @@ COPY_PROBE_BYTES = 1 << 28     # plain copy used to calibrate the byte counters
 FLUX_FLOPS = {"advection": 1, "kpp": 40, "euler": 30}   # per state and direction
 
 
-def elem1_flops(d, p, m, kind):
+def elem1_flops(d, p, m, kind, part=0):
     """Float64 operations of the element pass per element (FMA = 2), by the
     sum-factorised algorithm: cell average, WENO sensor (2d candidate
     extensions and 2d + 2 packed quadratic forms), interpolation to the
     (p+1)^d Gauss points, fluxes, gradient test, stabilisation (2 d^2
-    one-axis passes), facet fluxes; transcendental fluxes at a nominal 40."""
+    one-axis passes), facet fluxes; transcendental fluxes at a nominal 40.
+    part 1: sensor and facets only, part 2: residual only (the two launches
+    of the 3D Euler pass)."""
     nl, p1 = (p + 1) ** d, p + 1
     ax = 2 * nl * p1                       # one sum-factorised axis pass
     qs = nl * (nl + 1)                     # one packed quadratic form
     weno = m * (nl + qs + 2 * d * (2 * nl + p1 * 2 * nl + qs) + 4 * d * nl + qs + 6 * (2 * d + 1))
     resid = m * (d * ax + d * d * ax) + nl * (d * FLUX_FLOPS[kind] + 2 * d) + m * (2 * d * d * ax + 4 * nl)
     facets = 2 * d * (m * (nl // p1) + 10 * m + FLUX_FLOPS[kind])
+    if part == 1:
+        return weno + facets + m * nl
+    if part == 2:
+        return resid
     return weno + resid + facets + m * nl
+
+
+def split_elem1(wl):
+    """The 3D Euler element pass 1 runs as two launches (sensor and facets;
+    residual)."""
+    return wl.kind == "euler" and wl.d == 3
 
 
 def elem2_flops(d, p, m, kind):
@@ -93,6 +105,14 @@ def kernel_work(name, wl, N, E, m, mixed=False):
         return (m * nl * E + 2 * m * N) * fr, m * nl * E
     if name == "update":
         return (m * nl * E + 3 * m * N + kn) * f8, (nl + 4) * m * N
+    if name == "elem1" and split_elem1(wl):
+        # sensor and facets: u in; averages, low-order averages, f^A, dt_e,
+        # gamma_e, nu_e out
+        return m * N * f8 + (d * m + 3 + 2 * m) * E * f8, E * elem1_flops(d, p, m, wl.kind, 1)
+    if name == "elem1r":
+        # residual: u, g, averages, gamma_e, nu_e in; element vectors out
+        rd = m * N * f8 + d * m * N * fr + (m + 2) * E * f8
+        return rd + m * nl * E * fr, E * elem1_flops(d, p, m, wl.kind, 2)
     if name == "elem1":
         rd = (m * N + kn) * f8 + d * m * N * fr
         wr = m * nl * E * fr + (d * m + 3 + 2 * m) * E * f8
@@ -108,7 +128,8 @@ def source_digest():
     another digest no longer describe the kernels that run."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("csrc/kernels.hpp", "csrc/api.hip", "csrc/tables.cpp", "csrc/tables.hpp", "build.py"):
+    for f in ("csrc/kernels.hpp", "csrc/kernels_sys.hpp", "csrc/kernels_batch.hpp", "csrc/api.hip",
+              "csrc/tables.cpp", "csrc/tables.hpp", "build.py"):
         with open(os.path.join(ROOT, "paper_2509_04673_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -206,7 +227,8 @@ def profiled_traffic(wl, kernel_names, precision="fp64"):
 # device kernel names behind each timing id
 DEVICE_KERNELS = {"grad_line": ["k_line_multi", "k_line_x", "k_line_y", "k_line_fast", "k_line("],
                   "elem1": ["k_elem1"], "gather_r": ["k_gather"], "mass_line": ["k_line_y", "k_line_fast"],
-                  "elem2": ["k_elem2"], "update": ["k_update"]}
+                  "elem2": ["k_elem2"], "update": ["k_update"], "elem1r": ["k_resid"],
+                  "stage_dt": ["k_stage_dt"]}
 
 
 def copy_probe(nbytes):

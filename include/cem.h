@@ -211,11 +211,13 @@ size_t cem_tap_size(const cem_ctx* ctx, int tap);
  *   dt_e (a launch of its own only on large meshes; otherwise inside 6)
  *   3 residual gather (fused with the first mass-solve pass on long
  *   x-lines)   4 mass-solve line operator   5 element pass 2 (limiters,
- *   contributions)   6 node update.
+ *   contributions)   6 node update   7 element residual of the 3D Euler
+ *   pass 1, a launch of its own there (id 1 is then its sensor and facet
+ *   half).
  * cem_kernel_times is synchronous: it returns the summed milliseconds and
- * launch counts per id since the previous call (arrays of n <= 7 entries)
+ * launch counts per id since the previous call (arrays of n <= 8 entries)
  * and clears them. */
-#define CEM_NUM_KERNELS 7
+#define CEM_NUM_KERNELS 8
 cem_status cem_set_timing(cem_ctx* ctx, unsigned mask);
 cem_status cem_kernel_times(cem_ctx* ctx, double* total_ms, long long* launches, int n);
 

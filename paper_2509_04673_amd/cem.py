@@ -214,7 +214,7 @@ def cem_debug_tap(ctx, tap, dst_ptr, count):
     _check(lib().cem_debug_tap(ctx, int(tap), _P(dst_ptr), int(count)))
 
 
-KERNELS = ["grad_line", "elem1", "stage_dt", "gather_r", "mass_line", "elem2", "update"]
+KERNELS = ["grad_line", "elem1", "stage_dt", "gather_r", "mass_line", "elem2", "update", "elem1r"]
 
 
 def cem_set_graphs(ctx, enable):

@@ -87,8 +87,8 @@ struct cem_ctx {
 };
 
 // batched form: launches of one stage over all problems (see kernels_batch.hpp)
-enum BKind { B_LINE, B_LINE_X, B_LINE_Y, B_ELEM1_TILE, B_ELEM1_SYS, B_GATHER_LX, B_GATHER_R, B_ELEM2,
-             B_ELEM2_SYS, B_UPDATE };
+enum BKind { B_LINE, B_LINE_X, B_LINE_Y, B_ELEM1_TILE, B_ELEM1_SYS, B_RESID_SYS, B_GATHER_LX, B_GATHER_R,
+             B_ELEM2, B_ELEM2_SYS, B_UPDATE };
 
 struct BLaunch {
   int kind = 0;
@@ -386,6 +386,8 @@ cem_status launch_sys(cem_ctx* c, StageArgs& a, bool first) {
   if (first) {
     a.ndtpart = (int)nb;
     CEM_LAUNCH(c, 1, (k_elem1_sys<D, P, PH, RT>), nb, M * EB, lds, c->stream, a);
+    HIPCHK(hipGetLastError());
+    CEM_LAUNCH(c, 7, (k_resid_sys<D, P, PH, RT>), nb, M * EB, lds, c->stream, a);
   } else {
     CEM_LAUNCH(c, 5, (k_elem2_sys<D, P, PH, RT>), nb, M * EB, lds, c->stream, a);
   }
@@ -460,8 +462,10 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   // (Running the g-independent part concurrently with the gradient passes on
   // a second stream was measured slower on the 256^2 KPP mesh.)
   {
-    // 3D systems: one thread per (element, component); 2D: the LDS element
-    // tile with one thread per element measured faster for both physics
+    // 3D systems: one thread per (element, component), in two launches
+    // (sensor and facets; residual).  2D: the LDS element tile with one
+    // thread per element measured faster for both physics (512^2 Q3 Euler:
+    // 0.46 ms per stage against 0.52 for the two system launches)
     if constexpr (PH == EUL && D == 3) {
       cem_status st = launch_sys<D, P, PH, RT>(c, a, true);
       if (st != CEM_OK) return st;
@@ -531,11 +535,11 @@ StageArgs batch_stage_args(cem_ctx* c, int stage, double dt, double cfl) {
   a.dt_fixed = dt;
   a.cfl = cfl;
   constexpr int M = Phys<D, PH>::M;
-  if constexpr (D == 2) {
+  if constexpr (PH == EUL && D == 3) {
+    a.ndtpart = (int)nblocks(c->E, SysTile<D, P, PH>::EB);
+  } else if constexpr (D == 2) {
     using TT = Tile2<P, M>;
     a.ndtpart = ((c->n[0] + TT::TEX - 1) / TT::TEX) * ((c->n[1] + TT::TEY - 1) / TT::TEY);
-  } else if constexpr (PH == EUL && D == 3) {
-    a.ndtpart = (int)nblocks(c->E, SysTile<D, P, PH>::EB);
   } else {
     a.ndtpart = (int)nblocks(c->E, 128);
   }
@@ -652,13 +656,14 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     // element pass 1
     {
       Group g;
-      if constexpr (D == 2) {
+      constexpr bool sys = PH == EUL && D == 3;
+      if constexpr (sys) {
+        g.l.kind = B_ELEM1_SYS;
+        g.l.lds = SysTile<D, P, PH>::LY::bytes;
+      } else if constexpr (D == 2) {
         using TT = Tile2<P, M>;
         g.l.kind = B_ELEM1_TILE;
         g.l.lds = TT::words * sizeof(double);
-      } else if constexpr (PH == EUL && D == 3) {
-        g.l.kind = B_ELEM1_SYS;
-        g.l.lds = SysTile<D, P, PH>::LY::bytes;
       } else {
         return fail(CEM_EINVAL, "batched form: 2D problems or 3D Euler only");
       }
@@ -666,7 +671,15 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         g.sa.push_back(sa[q]);
         g.first.push_back(g.first.back() + sa[q].ndtpart);
       }
-      close(g, L);
+      if constexpr (sys) {
+        // the residual half of the system pass: the same blocks
+        Group gr = g;
+        gr.l.kind = B_RESID_SYS;
+        close(g, L);
+        close(gr, L);
+      } else {
+        close(g, L);
+      }
     }
     // assembly of r fused with the first mass pass where the x-lines allow it
     {
@@ -761,6 +774,10 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
       case B_ELEM1_SYS:
         if constexpr (PH == EUL && D == 3)
           hipLaunchKernelGGL((kb_elem1_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
+        break;
+      case B_RESID_SYS:
+        if constexpr (PH == EUL && D == 3)
+          hipLaunchKernelGGL((kb_resid_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
         break;
       case B_GATHER_LX:
         hipLaunchKernelGGL((kb_gather_line_x<D, P, M, 1, RT>), g, dim3(256), l.lds, stream, sa,

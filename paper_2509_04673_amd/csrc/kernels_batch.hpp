@@ -62,11 +62,17 @@ __global__ void __launch_bounds__(128) kb_elem1_tile(const StageArgs* __restrict
 }
 
 template <int D, int P, int PH, class RT>
-__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB))
-    kb_elem1_sys(const StageArgs* __restrict__ args, BatchMap m) {
+__global__ void CEM_SYS_BOUNDS kb_elem1_sys(const StageArgs* __restrict__ args, BatchMap m) {
   int lb;
   const int pid = batch_find(m, blockIdx.x, &lb);
-  k_elem1_sys_body<D, P, PH, RT>(args[pid], lb);
+  k_elem1_sys_body<D, P, PH, RT, 1>(args[pid], lb);
+}
+
+template <int D, int P, int PH, class RT>
+__global__ void CEM_SYS_BOUNDS kb_resid_sys(const StageArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_elem1_sys_body<D, P, PH, RT, 2>(args[pid], lb);
 }
 
 template <int D, int P, int M, int RE, class RT>

@@ -155,12 +155,14 @@ __device__ __forceinline__ void block_min_dt_sys(double* red, double* part, int 
   }
 }
 
-// PART 0: the whole pass; PART 1: sensor, viscosity and facet data only;
-// PART 2: the element residual only, from the cell averages, gamma_e and nu_e
-// that PART 1 stored (two launches with fewer live registers each)
-template <int D, int P, int PH, class RT, int PART = 0>
+// Element pass 1 of systems in two launches, each with fewer live registers
+// than the whole (so that two waves per SIMD fit without more spilling):
+// PART 1 the sensor, viscosity and facet data; PART 2 the element residual,
+// from the cell averages, gamma_e and nu_e that PART 1 stored.
+template <int D, int P, int PH, class RT, int PART>
 __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
   static_assert(PH == EUL, "system element pass 1 is written for the Euler equations");
+  static_assert(PART == 1 || PART == 2, "PART 1: sensor and facets, PART 2: residual");
   using PHY = Phys<D, PH>;
   using SF = SFLayout<D, P>;
   using LY = typename SysTile<D, P, PH>::LY;
@@ -187,7 +189,7 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
     Us[j * CS] = v;
   }
   ue_c *= (1.0 / NL);
-  double uo[M], gam, nu, dt_keep = 0.0;
+  double uo[M], gam, nu;
   if constexpr (PART == 2) {
     // stored by PART 1 (the same sums)
     ue_c = a.ue[c * E + e];
@@ -354,13 +356,9 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
       a.nu[e] = nu;
     }
   }
-  if constexpr (PART == 1) {
-    block_min_dt_sys<EB>(S + LY::oRed, a.dtpart, c, le, live ? dt_e : 1.0e300, bx);
-    return;
-  } else if constexpr (PART == 0) {
-    dt_keep = dt_e;
-  }
-  }   // PART != 2
+  block_min_dt_sys<EB>(S + LY::oRed, a.dtpart, c, le, live ? dt_e : 1.0e300, bx);
+  return;
+  }   // PART 1
 
   // ---- element residual R_i = int grad phi_i . f(u_h) - s_h^e(phi_i, u_h):
   // the stabilisation first (from the nodal coefficients), then the Gauss-
@@ -454,12 +452,22 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
       a.relem[((int64_t)c * NL + i) * E + e] = v;
     }
   }
-  if constexpr (PART == 0) block_min_dt_sys<EB>(S + LY::oRed, a.dtpart, c, le, live ? dt_keep : 1.0e300, bx);
 }
 
-template <int D, int P, int PH, class RT, int PART = 0>
-__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_elem1_sys(StageArgs a) {
-  k_elem1_sys_body<D, P, PH, RT, PART>(a, blockIdx.x);
+// both halves are compiled for two waves per SIMD (measured: the whole pass
+// at one wave per SIMD took 22.4 ms on the 128^3 Q2 blast, the halves at two
+// 8.1 + 7.6 ms)
+#define CEM_SYS_BOUNDS __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) \
+  __attribute__((amdgpu_waves_per_eu(2, 2)))
+
+template <int D, int P, int PH, class RT>
+__global__ void CEM_SYS_BOUNDS k_elem1_sys(StageArgs a) {
+  k_elem1_sys_body<D, P, PH, RT, 1>(a, blockIdx.x);
+}
+
+template <int D, int P, int PH, class RT>
+__global__ void CEM_SYS_BOUNDS k_resid_sys(StageArgs a) {
+  k_elem1_sys_body<D, P, PH, RT, 2>(a, blockIdx.x);
 }
 
 // flux-pair factor of Appendix A for the facet between eL and eR normal to
