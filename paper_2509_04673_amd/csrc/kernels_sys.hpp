@@ -62,6 +62,18 @@ __device__ __forceinline__ V pick_c(const V* v, int c) {
   return r;
 }
 
+// the same as a sum of masked terms (exact: one term is v[c], the others are
+// +0).  Where a whole flux array is computed only to pick one entry, the
+// compiler folded the select chain into a dynamically indexed stack array
+// (scratch stores and loads); this form it keeps in registers.
+template <int M, class V>
+__device__ __forceinline__ V pick_m(const V* v, int c) {
+  V r = 0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r += (c == k) ? v[k] : (V)0;
+  return r;
+}
+
 // v[i] for a runtime i < K, and v[i] = x, without a dynamically indexed
 // register array (which would live in scratch)
 template <int K, class V>
@@ -317,7 +329,7 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
   for (int k = 0; k < D; ++k) {
     double fo[M];
     PHY::flux(k, uo, fo, a.ph);
-    const double foc = pick_c<M>(fo, c);
+    const double foc = pick_m<M>(fo, c);
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int l = 2 * k + side;
@@ -325,7 +337,7 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
 #pragma unroll
       for (int kk = 0; kk < M; ++kk) un[kk] = S[LY::oNm + (l * M + kk) * EB + le];
       PHY::flux(k, un, fn, a.ph);
-      const double fnc = pick_c<M>(fn, c), unc = pick_c<M>(un, c);
+      const double fnc = pick_m<M>(fn, c), unc = pick_m<M>(un, c);
       const double lm = S[LY::oFac + l * EB + le];
       lamsum += lm;
       const double fl = side ? foc : fnc, fr = side ? fnc : foc;
@@ -340,7 +352,7 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
           double uj[M], fj[M];
           state_at<M, EB>(S, j, le, uj);
           PHY::flux(k, uj, fj, a.ph);
-          fH += pick_c<M>(fj, c);
+          fH += pick_m<M>(fj, c);
         }
         if (live) a.fahi[((int64_t)k * M + c) * E + e] = fLc - fH * (1.0 / NF);
       }
@@ -575,7 +587,7 @@ __device__ __forceinline__ void k_elem2_sys_body(const StageArgs& a, int bx) {
         double uj[M], fv[M];
         state_at<M, EB>(S, j, le, uj);
         PHY::flux(k, uj, fv, a.ph);
-        fn[fj] = (RT)(pick_c<M>(fv, c) - fbar);
+        fn[fj] = (RT)(pick_m<M>(fv, c) - fbar);
       }
       const int mg[3] = {SF::g, SF::g, SF::g};
       tensor_ip<D - 1, P>(T, mg, false, fn);
