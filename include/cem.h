@@ -75,9 +75,7 @@ typedef enum { CEM_FP64 = 0, CEM_FP32_MIXED = 1 } cem_precision;
  *   largest value that keeps u^e - dt_e |dK|/|K| sum f^H . n admissible (the
  *   Remark after eq. 40; scalar: the global bounds, Euler: Appendix A with
  *   its margin eps_pos).  dt_e may reach 0, which a fixed dt reports as a
- *   CFL violation.
- * The flux-off modes are not available for the 3D Euler equations
- * (cem_create returns CEM_EINVAL). */
+ *   CFL violation. */
 typedef enum { CEM_FLUX_LIMIT = 0, CEM_FLUX_SUBCELL = 1, CEM_FLUX_SHRINK = 2 } cem_flux_mode;
 
 /* Uniform periodic box [lo, hi] with n[k] cube cells per axis (cell edge h

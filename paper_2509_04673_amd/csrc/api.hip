@@ -880,8 +880,6 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
     return fail(CEM_EINVAL, "unsupported (dim, degree, physics, precision)");
   if (prm->flux_mode < CEM_FLUX_LIMIT || prm->flux_mode > CEM_FLUX_SHRINK)
     return fail(CEM_EINVAL, "flux_mode must be CEM_FLUX_LIMIT, CEM_FLUX_SUBCELL or CEM_FLUX_SHRINK");
-  if (prm->flux_mode != CEM_FLUX_LIMIT && d == 3 && phys->kind == CEM_EULER)
-    return fail(CEM_EINVAL, "flux limiter off is not available for the 3D Euler equations");
   double h = 0.0;
   for (int k = 0; k < d; ++k) {
     if (mesh->n[k] < 2) return fail(CEM_EINVAL, "need at least 2 cells per axis");

@@ -847,59 +847,79 @@ template <int P, int M> struct TileNodes2 {
 // their outward normals, lambda_0i the Riemann speed of (u_0, u_i) along
 // c_i / |c_i|, m_i = h^d / (p+1)^d; u_0 the mean of the interior nodes and
 // s = 1, or for Q1 u_0 = u^e, m_0 = |K| and s = 2.
+//
+// |c_j| lambda_0j of local node j (0 for an interior node)
 template <int D, int P, class PHY>
-__device__ inline double subcell_dt(const double (*U)[ipow(P + 1, D)], const double* ue, double h,
-                                    const PhysParams& ph) {
-  constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NI = ipow(P - 1, D);
+__device__ inline double subcell_node(int j, const double* u0, const double* uj, double h, const PhysParams& ph) {
+  constexpr int P1 = P + 1;
+  double cf = 1.0;
+#pragma unroll
+  for (int k = 0; k < D - 1; ++k) cf *= h * (1.0 / P1);
+  double cv[3] = {0.0, 0.0, 0.0};
+  int nf = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const int dk = dig(j, k, P1);
+    if (dk == P) { cv[k] = 1.0; ++nf; }
+    else if (dk == 0) { cv[k] = -1.0; ++nf; }
+  }
+  if (nf == 0) return 0.0;
+  const double nrm = sqrt((double)nf);
+  double n[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n[k] = cv[k] / nrm;
+  return cf * nrm * PHY::riemann_speed_n(u0, uj, n, ph);
+}
+
+// the bound from min_j m_j / (|c_j| lambda_0j) over the boundary nodes and
+// the sum of |c_j| lambda_0j
+template <int D, int P>
+__device__ inline double subcell_combine(double tnode, double csum, double h) {
+  constexpr int NL = ipow(P + 1, D), NI = ipow(P - 1, D);
   double hd = 1.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) hd *= h;
-  const double mi = hd * (1.0 / NL), cf = hd / h * (1.0 / ipow(P1, D - 1));
+  const double m0 = NI > 0 ? NI * hd * (1.0 / NL) : hd;
+  const double t = fmin(tnode, csum > 0.0 ? m0 / csum : 1.0e300);
+  return NI > 0 ? t : 0.5 * t;
+}
+
+template <int D, int P>
+__device__ inline bool interior_node(int j) {
+  bool in = true;
+#pragma unroll
+  for (int k = 0; k < D; ++k) in = in && dig(j, k, P + 1) != 0 && dig(j, k, P + 1) != P;
+  return in;
+}
+
+template <int D, int P, class PHY>
+__device__ inline double subcell_dt(const double (*U)[ipow(P + 1, D)], const double* ue, double h,
+                                    const PhysParams& ph) {
+  constexpr int NL = ipow(P + 1, D), M = PHY::M, NI = ipow(P - 1, D);
+  double hd = 1.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) hd *= h;
+  const double mi = hd * (1.0 / NL);
   double u0[M];
-  double m0 = hd;
-  if constexpr (NI > 0) {
 #pragma unroll
-    for (int c = 0; c < M; ++c) {
-      double s = 0.0;
+  for (int c = 0; c < M; ++c) {
+    double s = 0.0;
 #pragma unroll
-      for (int j = 0; j < NL; ++j) {
-        bool in = true;
-#pragma unroll
-        for (int k = 0; k < D; ++k) in = in && dig(j, k, P1) != 0 && dig(j, k, P1) != P;
-        if (in) s += U[c][j];
-      }
-      u0[c] = s * (1.0 / NI);
-    }
-    m0 = NI * mi;
-  } else {
-#pragma unroll
-    for (int c = 0; c < M; ++c) u0[c] = ue[c];
+    for (int j = 0; j < NL; ++j)
+      if (interior_node<D, P>(j)) s += U[c][j];
+    u0[c] = NI > 0 ? s * (1.0 / (NI > 0 ? NI : 1)) : ue[c];
   }
   double tnode = 1.0e300, csum = 0.0;
 #pragma unroll
   for (int j = 0; j < NL; ++j) {
-    double cv[3] = {0.0, 0.0, 0.0};
-    int nf = 0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const int dk = dig(j, k, P1);
-      if (dk == P) { cv[k] = 1.0; ++nf; }
-      else if (dk == 0) { cv[k] = -1.0; ++nf; }
-    }
-    if (nf == 0) continue;                      // interior node
-    const double nrm = sqrt((double)nf), cabs = cf * nrm;
-    double n[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) n[k] = cv[k] / nrm;
     double uj[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) uj[c] = U[c][j];
-    const double cl = cabs * PHY::riemann_speed_n(u0, uj, n, ph);
+    const double cl = subcell_node<D, P, PHY>(j, u0, uj, h, ph);
     if (cl > 0.0) tnode = fmin(tnode, mi / cl);
     csum += cl;
   }
-  const double t = fmin(tnode, csum > 0.0 ? m0 / csum : 1.0e300);
-  return NI > 0 ? t : 0.5 * t;
+  return subcell_combine<D, P>(tnode, csum, h);
 }
 
 // RT: value type of the sensor and residual contractions (double, or float

@@ -323,8 +323,8 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
   nu = lam * h / (2.0 * P);
 
   // ---- facet fluxes of component c (eqs. 18, 40, 42, 51): f^L against the
-  // neighbour averages, f^H = mean of f(u_j) n over the + facet's nodes
-  double lamsum = 0.0, fLsum = 0.0;
+  // neighbour averages, f^H = mean of f(u_j) n over the facet's nodes
+  double lamsum = 0.0, fLsum = 0.0, fHout = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     double fo[M];
@@ -344,21 +344,76 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
       const double uL = side ? ue_c : unc, uR = side ? unc : ue_c;
       const double fLc = 0.5 * (fl + fr) - 0.5 * lm * (uR - uL);
       fLsum += side ? fLc : -fLc;
-      if (side) {
+      if (side || a.flux_mode != 0) {
         double fH = 0.0;
 #pragma unroll
         for (int j = 0; j < NL; ++j) {
-          if (dig(j, k, P1) != P) continue;
+          if (dig(j, k, P1) != (side ? P : 0)) continue;
           double uj[M], fj[M];
           state_at<M, EB>(S, j, le, uj);
           PHY::flux(k, uj, fj, a.ph);
           fH += pick_m<M>(fj, c);
         }
-        if (live) a.fahi[((int64_t)k * M + c) * E + e] = fLc - fH * (1.0 / NF);
+        fHout += side ? fH * (1.0 / NF) : -(fH * (1.0 / NF));
+        if (side && live) a.fahi[((int64_t)k * M + c) * E + e] = fLc - fH * (1.0 / NF);
       }
     }
   }
-  const double dt_e = h / lamsum;
+  double dt_e = h / lamsum;                                   // eq. (40)
+  if (a.flux_mode != 0) {
+    // flux limiter off (Sec. 4.3, steps 3-4): ubar^e = u^e - dt_e / h sum
+    // f^H . n, dt_e of Lemma 1 (eq. 37) or eq. (40) reduced until ubar^e is
+    // admissible.  The groups share the work through S (oGam, oPart, oUb
+    // are free here once every thread has read gamma and the node speeds).
+    __syncthreads();
+    if (a.flux_mode == 1) {
+      constexpr int NI = ipow(P - 1, D);
+      double u0[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) u0[k] = uo[k];
+      if constexpr (NI > 0) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          double sum = 0.0;
+#pragma unroll
+          for (int j = 0; j < NL; ++j)
+            if (interior_node<D, P>(j)) sum += S[(j * M + k) * EB + le];
+          u0[k] = sum * (1.0 / (NI > 0 ? NI : 1));
+        }
+      }
+      double hd = 1.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) hd *= h;
+      const double mi = hd * (1.0 / NL);
+      double tnode = 1.0e300, csum = 0.0;
+      for (int j = c; j < NL; j += M) {        // boundary nodes split over the groups
+        double uj[M];
+        state_at<M, EB>(S, j, le, uj);
+        const double cl = subcell_node<D, P, PHY>(j, u0, uj, h, a.ph);
+        if (cl > 0.0) tnode = fmin(tnode, mi / cl);
+        csum += cl;
+      }
+      S[LY::oGam + c * EB + le] = tnode;
+      S[LY::oPart + c * EB + le] = csum;
+      __syncthreads();
+      tnode = 1.0e300;
+      csum = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        tnode = fmin(tnode, S[LY::oGam + k * EB + le]);
+        csum += S[LY::oPart + k * EB + le];
+      }
+      dt_e = subcell_combine<D, P>(tnode, csum, h);
+    } else {
+      S[LY::oUb + c * EB + le] = fHout;
+      __syncthreads();
+      double dl[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) dl[k] = -dt_e / h * S[LY::oUb + k * EB + le];
+      dt_e *= euler_alpha<D>(uo, dl, 1.0, a.eps_pos);
+    }
+    if (live) a.ubar[c * E + e] = ue_c - dt_e / h * fHout;
+  }
   if (live) {
     a.ue[c * E + e] = ue_c;
     a.ubarL[c * E + e] = ue_c - dt_e / h * fLsum;

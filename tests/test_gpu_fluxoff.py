@@ -28,6 +28,8 @@ CASES = [
     ("euler2d_q1", lambda: random_euler_workload(2, 1, (12, 11))),
     ("euler2d_q2", lambda: random_euler_workload(2, 2, (12, 7))),
     ("euler2d_q3", lambda: random_euler_workload(2, 3, (9, 10))),
+    ("euler3d_q1", lambda: random_euler_workload(3, 1, (7, 5, 6))),
+    ("euler3d_q2", lambda: random_euler_workload(3, 2, (5, 6, 4))),
 ]
 
 
@@ -59,8 +61,15 @@ def test_euler2d_shrink_run_parity():
     assert chk["rho_min"] > 0 and chk["p_min"] > 0
 
 
-def test_flux_off_rejected_for_3d_euler():
+def test_euler3d_subcell_run_parity():
+    wl = W.euler3d(seed=0, n=6)
+    err, floor, st, chk = run_both(wl, 3, dt=None, cfl=0.5, modes=dict(flux_mode="subcell"))
+    assert err <= run_tol(floor)
+    assert chk["rho_min"] > 0 and chk["p_min"] > 0
+
+
+def test_flux_mode_out_of_range_rejected():
     from paper_2509_04673_amd.cem import CemError
-    wl = random_euler_workload(3, 2, (4, 4, 4))
+    wl = random_euler_workload(2, 2, (4, 4))
     with pytest.raises(CemError):
-        gpu_for(wl, dict(flux_mode="subcell"))
+        gpu_for(wl, dict(flux_mode=3))
