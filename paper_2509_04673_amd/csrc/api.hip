@@ -25,6 +25,12 @@ namespace {
 // itself; above it one block does it once (k_stage_dt)
 constexpr int kDtFusedMax = 1024;
 
+// 2D element pass 1 with two threads (roles) per element: scalar problems.
+// Measured per stage: KPP 256^2 Q2 22.7 -> 17.3 us; for 512^2 Q3 Euler the
+// one-thread tile stays faster (0.46 against 0.47 ms, mixed 0.36 against
+// 0.45 ms).
+template <int PH> constexpr bool tile2_roles() { return Phys<2, PH>::M == 1; }
+
 thread_local std::string g_err;
 
 cem_status fail(cem_status s, const std::string& msg) {
@@ -87,8 +93,8 @@ struct cem_ctx {
 };
 
 // batched form: launches of one stage over all problems (see kernels_batch.hpp)
-enum BKind { B_LINE, B_LINE_X, B_LINE_Y, B_ELEM1_TILE, B_ELEM1_SYS, B_RESID_SYS, B_GATHER_LX, B_GATHER_R,
-             B_ELEM2, B_ELEM2_SYS, B_UPDATE };
+enum BKind { B_LINE, B_LINE_X, B_LINE_Y, B_ELEM1_TILE, B_ELEM1_TILE2, B_ELEM1_SYS, B_RESID_SYS, B_GATHER_LX,
+             B_GATHER_R, B_ELEM2, B_ELEM2_SYS, B_UPDATE };
 
 struct BLaunch {
   int kind = 0;
@@ -473,7 +479,11 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
       using TT = Tile2<P, M>;
       const int nb = ((c->n[0] + TT::TEX - 1) / TT::TEX) * ((c->n[1] + TT::TEY - 1) / TT::TEY);
       a.ndtpart = nb;
-      CEM_LAUNCH(c, 1, (k_elem1_tile<P, PH, true, RT>), nb, 128, TT::words * sizeof(double), c->stream, a);
+      if constexpr (tile2_roles<PH>())
+        CEM_LAUNCH(c, 1, (k_elem1_tile2<P, PH, true, RT>), nb, 256, (TT::words + 256) * sizeof(double),
+                   c->stream, a);
+      else
+        CEM_LAUNCH(c, 1, (k_elem1_tile<P, PH, true, RT>), nb, 128, TT::words * sizeof(double), c->stream, a);
     } else {
       CEM_LAUNCH(c, 1, (k_elem1<D, P, PH, true, RT>), nblocks(c->E, 128), 128, 0, c->stream, a);
     }
@@ -662,8 +672,8 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         g.l.lds = SysTile<D, P, PH>::LY::bytes;
       } else if constexpr (D == 2) {
         using TT = Tile2<P, M>;
-        g.l.kind = B_ELEM1_TILE;
-        g.l.lds = TT::words * sizeof(double);
+        g.l.kind = tile2_roles<PH>() ? B_ELEM1_TILE2 : B_ELEM1_TILE;
+        g.l.lds = (TT::words + (tile2_roles<PH>() ? 256 : 0)) * sizeof(double);
       } else {
         return fail(CEM_EINVAL, "batched form: 2D problems or 3D Euler only");
       }
@@ -770,6 +780,10 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
         break;
       case B_ELEM1_TILE:
         if constexpr (D == 2) hipLaunchKernelGGL((kb_elem1_tile<P, PH, true, RT>), g, dim3(128), l.lds, stream, sa, mp);
+        break;
+      case B_ELEM1_TILE2:
+        if constexpr (D == 2 && tile2_roles<PH>())
+          hipLaunchKernelGGL((kb_elem1_tile2<P, PH, true, RT>), g, dim3(256), l.lds, stream, sa, mp);
         break;
       case B_ELEM1_SYS:
         if constexpr (PH == EUL && D == 3)

@@ -657,6 +657,18 @@ __global__ void __launch_bounds__(256) k_line_multi(MultiLineArgs m) {
 // ---------------------------------------------------------------------------
 // minimum of dt_e over the 128 threads of a block (threads past the last
 // element contribute +inf) written to part[bx] (bx: the block's index)
+template <int NT>
+__device__ inline void block_min_dt_n(double* part, double v, int bx) {
+  __shared__ double red[NT];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[bx] = red[0];
+}
+
 __device__ inline void block_min_dt(double* part, double v, int bx) {
   __shared__ double red[128];
   red[threadIdx.x] = v;
@@ -922,11 +934,34 @@ __device__ inline double subcell_dt(const double (*U)[ipow(P + 1, D)], const dou
   return subcell_combine<D, P>(tnode, csum, h);
 }
 
+// Exchange of gamma_e and nu_e between the two roles of a split element
+// pass: ROLE 1 computes the sensor, the viscosity and the facet data, ROLE 2
+// the element residual of the same element, each in its own thread; ROLE 0
+// does everything.  Each role passes the exchange barrier exactly once.
+struct NoXchg {
+  __device__ void put(double, double) const {}
+  __device__ void sync() const {}
+  __device__ void get(double&, double&) const {}
+};
+struct LdsXchg {
+  double* slot;    // gamma at slot[0], nu at slot[stride] (LDS)
+  int stride;
+  __device__ void put(double gam, double nu) const {
+    slot[0] = gam;
+    slot[stride] = nu;
+  }
+  __device__ void sync() const { __syncthreads(); }
+  __device__ void get(double& gam, double& nu) const {
+    gam = slot[0];
+    nu = slot[stride];
+  }
+};
+
 // RT: value type of the sensor and residual contractions (double, or float
 // in the mixed-precision form); cell averages, facet data and dt_e are
 // always float64
-template <int D, int P, int PH, bool WS, class RT, class NS>
-__device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, const NS& ns) {
+template <int D, int P, int PH, bool WS, class RT, class NS, int ROLE = 0, class XC = NoXchg>
+__device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, const NS& ns, const XC& xc = XC()) {
   using PHY = Phys<D, PH>;
   using SF = SFLayout<D, P>;
   constexpr int P1 = P + 1, NL = ipow(P1, D), M = PHY::M, NF = NL / P1;
@@ -952,6 +987,8 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   // their first entry (exactly zero for constant polynomials).
   constexpr bool keepx = 2 * D * NL <= 64;
   double nbr_mean[2 * D][M];
+  double gam = 0.0, nu = 0.0;
+  if constexpr (ROLE != 2) {
   double gmin = 1.0;
   for (int c = 0; c < M; ++c) {
     RT ct[NL];
@@ -1018,7 +1055,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     const double gc = 1.0 - (a.q == 1.0 ? (double)ratio : pow((double)ratio, a.q));
     gmin = fmin(gmin, gc);
   }
-  const double gam = a.gamma_mode == 0 ? gmin : (a.gamma_mode == 1 ? 0.0 : 1.0);
+  gam = a.gamma_mode == 0 ? gmin : (a.gamma_mode == 1 ? 0.0 : 1.0);
 
   // ---- viscosity nu_e = lambda_e h / (2p), lambda_e the largest nodal speed
   double lam = 0.0;
@@ -1029,7 +1066,12 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     for (int c = 0; c < M; ++c) uj[c] = U[c][j];
     lam = fmax(lam, PHY::node_speed(uj, a.ph));
   }
-  const double nu = lam * h / (2.0 * P);
+  nu = lam * h / (2.0 * P);
+  }   // ROLE != 2
+  if constexpr (ROLE == 1) {
+    xc.put(gam, nu);
+    xc.sync();
+  }
 
   // ---- element residual R_i = int grad phi_i . f(u_h) - s_h^e(phi_i, u_h),
   // sum-factorised: interpolate to the Gauss points, evaluate the flux, test
@@ -1044,6 +1086,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   // element, not with the size of u or f.
   double foa[D * M];
   PHY::flux_all(ue, foa, a.ph);          // fluxes of the own average
+  if constexpr (ROLE != 1) {
   RT R[M][NL];
   {
     RT uq[M][NL];
@@ -1136,14 +1179,48 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   };
   if constexpr (!WS) {
     // residual without the stabilisation term
+    if constexpr (ROLE == 2) xc.sync();
 #pragma unroll
     for (int c = 0; c < M; ++c)
 #pragma unroll
       for (int i = 0; i < NL; ++i) store_r(c, i, (RT)hpow * R[c][i]);
+  } else if constexpr (ROLE == 2) {
+    // the stabilisation sums first; gamma_e and nu_e from the other role
+    RT s1[M][NL], s2[M][NL];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      RT gk[D][NL], uc[NL];
+      ns.load_grad(c, gk);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        s1[c][i] = s2[c][i] = 0;
+        uc[i] = MIX ? (RT)(U[c][i] - ue[c]) : (RT)U[c][i];
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        int ms1[3] = {SF::g, SF::g, SF::g}, ms2[3] = {SF::g, SF::g, SF::g};
+        ms1[k] = SF::k1;
+        ms2[k] = SF::ct;
+        RT t[NL];
+        tensor_apply<D, P>(T, ms1, false, uc, t);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) s1[c][i] += t[i];
+        tensor_apply<D, P>(T, ms2, false, gk[k], t);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) s2[c][i] += t[i];
+      }
+    }
+    xc.sync();
+    xc.get(gam, nu);
+    const RT sa = (RT)(nu * hpow / h), sg = (RT)(nu * gam * hpow);
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+      for (int i = 0; i < NL; ++i) store_r(c, i, (RT)hpow * R[c][i] - (sa * s1[c][i] - sg * s2[c][i]));
   }
   const RT sa = (RT)(nu * hpow / h), sg = (RT)(nu * gam * hpow);   // nu h^{D-2}, nu gamma h^{D-1}
 #pragma unroll
-  for (int c = 0; c < (WS ? M : 0); ++c) {
+  for (int c = 0; c < (WS && ROLE == 0 ? M : 0); ++c) {
     RT gk[D][NL];
     ns.load_grad(c, gk);
     RT s1[NL], s2[NL], uc[NL];
@@ -1168,6 +1245,8 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
 #pragma unroll
     for (int i = 0; i < NL; ++i) store_r(c, i, (RT)hpow * R[c][i] - (sa * s1[i] - sg * s2[i]));
   }
+  }   // ROLE != 1
+  if constexpr (ROLE == 2) return 1.0e300;
 
   // ---- facets (Sec. 4, eqs. 18, 40, 42, 51): canonical orientation is from
   // the lower to the upper element along +e_k; both sides evaluate it alike
@@ -1258,13 +1337,11 @@ __global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
 
 // 2D element pass on a 16 x 8 element tile: the block first stages the
 // tile's nodes (one-element halo) and, when it fits, g in LDS.
-template <int P, int PH, bool WS, class RT>
-__device__ __forceinline__ void k_elem1_tile_body(const StageArgs& a, int bx) {
+template <int P, int PH, class RT>
+__device__ __forceinline__ void tile_stage(const StageArgs& a, int ex0, int ey0) {
   constexpr int M = Phys<2, PH>::M;
   using TT = Tile2<P, M>;
   const MeshArgs& ms = a.mesh;
-  const int nbx = (ms.n[0] + TT::TEX - 1) / TT::TEX;
-  const int ex0 = (bx % nbx) * TT::TEX, ey0 = (bx / nbx) * TT::TEY;
   const int L0 = ms.L[0], L1 = ms.L[1];
   int X0 = P * (ex0 - 1), Y0 = P * (ey0 - 1);
   if (X0 < 0) X0 += L0;
@@ -1285,6 +1362,16 @@ __device__ __forceinline__ void k_elem1_tile_body(const StageArgs& a, int bx) {
     }
   }
   __syncthreads();
+}
+
+template <int P, int PH, bool WS, class RT>
+__device__ __forceinline__ void k_elem1_tile_body(const StageArgs& a, int bx) {
+  constexpr int M = Phys<2, PH>::M;
+  using TT = Tile2<P, M>;
+  const MeshArgs& ms = a.mesh;
+  const int nbx = (ms.n[0] + TT::TEX - 1) / TT::TEX;
+  const int ex0 = (bx % nbx) * TT::TEX, ey0 = (bx / nbx) * TT::TEY;
+  tile_stage<P, PH, RT>(a, ex0, ey0);
   const int tx = threadIdx.x % TT::TEX, ty = threadIdx.x / TT::TEX;
   const int ex = ex0 + tx, ey = ey0 + ty;
   double dt_e = 1.0e300;
@@ -1298,6 +1385,41 @@ __device__ __forceinline__ void k_elem1_tile_body(const StageArgs& a, int bx) {
 template <int P, int PH, bool WS, class RT>
 __global__ void __launch_bounds__(128) k_elem1_tile(StageArgs a) {
   k_elem1_tile_body<P, PH, WS, RT>(a, blockIdx.x);
+}
+
+// The same pass with two threads per element (256 threads): role 1 the
+// sensor, the viscosity and the facet data, role 2 the element residual;
+// they meet once in LDS (gamma_e, nu_e).  Twice the waves of the one-thread
+// form, each with about half the work and fewer live registers.
+template <int P, int PH, bool WS, class RT>
+__device__ __forceinline__ void k_elem1_tile2_body(const StageArgs& a, int bx) {
+  constexpr int M = Phys<2, PH>::M;
+  using TT = Tile2<P, M>;
+  using TN = TileNodes2<P, M>;
+  constexpr int NE = TT::TEX * TT::TEY;
+  const MeshArgs& ms = a.mesh;
+  const int nbx = (ms.n[0] + TT::TEX - 1) / TT::TEX;
+  const int ex0 = (bx % nbx) * TT::TEX, ey0 = (bx / nbx) * TT::TEY;
+  tile_stage<P, PH, RT>(a, ex0, ey0);
+  const int role2 = (int)threadIdx.x >= NE, li = (int)threadIdx.x - (role2 ? NE : 0);
+  const int tx = li % TT::TEX, ty = li / TT::TEX;
+  const int ex = ex0 + tx, ey = ey0 + ty;
+  const LdsXchg xc{cem_smem + TT::words + li, NE};
+  double dt_e = 1.0e300;
+  if (ex < ms.n[0] && ey < ms.n[1]) {
+    const int64_t e = ex + (int64_t)ms.n[0] * ey;
+    const TN ns(a, e, tx, ty);
+    if (role2) elem1_body<2, P, PH, WS, RT, TN, 2>(a, e, ns, xc);
+    else dt_e = elem1_body<2, P, PH, WS, RT, TN, 1>(a, e, ns, xc);
+  } else {
+    xc.sync();                          // the one exchange barrier of the block
+  }
+  block_min_dt_n<2 * NE>(a.dtpart, dt_e, bx);
+}
+
+template <int P, int PH, bool WS, class RT>
+__global__ void __launch_bounds__(256) k_elem1_tile2(StageArgs a) {
+  k_elem1_tile2_body<P, PH, WS, RT>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

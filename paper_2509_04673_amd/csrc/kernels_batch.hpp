@@ -61,6 +61,13 @@ __global__ void __launch_bounds__(128) kb_elem1_tile(const StageArgs* __restrict
   k_elem1_tile_body<P, PH, WS, RT>(args[pid], lb);
 }
 
+template <int P, int PH, bool WS, class RT>
+__global__ void __launch_bounds__(256) kb_elem1_tile2(const StageArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_elem1_tile2_body<P, PH, WS, RT>(args[pid], lb);
+}
+
 template <int D, int P, int PH, class RT>
 __global__ void CEM_SYS_BOUNDS kb_elem1_sys(const StageArgs* __restrict__ args, BatchMap m) {
   int lb;
