@@ -170,13 +170,17 @@ def summarize_profile(out_dir, dest, command, copy_bytes):
     and FETCH_SIZE / WRITE_SIZE per dispatch, the counters scaled by the
     factor that makes a plain copy of copy_bytes read what it moved."""
     stats = _read_csv(_one(os.path.join(out_dir, "stats"), "kernel_stats.csv"))
-    fetch = _counter_means(os.path.join(out_dir, "fetch"))
-    write = _counter_means(os.path.join(out_dir, "write"))
-    cf = _counter_means(os.path.join(out_dir, "copy_fetch"))
-    cw = _counter_means(os.path.join(out_dir, "copy_write"))
-    ck = max(cf, key=cf.get)
-    kib = copy_bytes / 1024.0
-    ffac, wfac = kib / cf[ck], kib / cw[ck]
+    counters = os.path.isdir(os.path.join(out_dir, "fetch"))   # else a kernel trace only
+    fetch = _counter_means(os.path.join(out_dir, "fetch")) if counters else {}
+    write = _counter_means(os.path.join(out_dir, "write")) if counters else {}
+    if counters:
+        cf = _counter_means(os.path.join(out_dir, "copy_fetch"))
+        cw = _counter_means(os.path.join(out_dir, "copy_write"))
+        ck = max(cf, key=cf.get)
+        kib = copy_bytes / 1024.0
+        ffac, wfac = kib / cf[ck], kib / cw[ck]
+    else:
+        ck, ffac, wfac = None, None, None
     rows, data = [], {}
     for r in stats:
         name = r["Name"]
@@ -191,11 +195,13 @@ def summarize_profile(out_dir, dest, command, copy_bytes):
                     + (f"{f:.0f} | {w:.0f} | {tr / 1e6:.2f} |" if tr is not None else "- | - | - |"))
     blob = dict(digest=source_digest(), fetch_factor=ffac, write_factor=wfac, copy_kernel=ck,
                 copy_bytes=copy_bytes, kernels=data)
-    text = ["# Stage kernels: rocprofv3 kernel trace and HBM counters", "",
+    calib = (f"Counter calibration: a plain device copy of {copy_bytes} bytes (`{ck}`) reads "
+             f"FETCH_SIZE {cf[ck]:.0f} KiB and WRITE_SIZE {cw[ck]:.0f} KiB per dispatch, so traffic = "
+             f"{ffac:.3f} x FETCH_SIZE + {wfac:.3f} x WRITE_SIZE." if counters
+             else "Kernel trace only (no counter passes for this workload).")
+    text = ["# Stage kernels: rocprofv3 kernel trace" + (" and HBM counters" if counters else ""), "",
             "Command (from the repository root, R = its absolute path):", "", "```", command.strip(), "```", "",
-            f"Counter calibration: a plain device copy of {copy_bytes} bytes (`{ck}`) reads "
-            f"FETCH_SIZE {cf[ck]:.0f} KiB and WRITE_SIZE {cw[ck]:.0f} KiB per dispatch, so traffic = "
-            f"{ffac:.3f} x FETCH_SIZE + {wfac:.3f} x WRITE_SIZE.", "",
+            calib, "",
             "| kernel | calls | avg us | % time | FETCH_SIZE KiB | WRITE_SIZE KiB | traffic MB |",
             "|---|---|---|---|---|---|---|", *rows, "",
             "Machine-readable copy (read by bench.py for the roofline traffic):", "",
@@ -340,8 +346,11 @@ def main():
     if args.summarize_profile:
         from paper_2509_04673_amd import workloads
         kw = {} if args.n is None else dict(n=args.n)
-        wl = workloads.make(args.workload, seed=0, **kw)
-        summarize_profile(args.summarize_profile, os.path.join(PROFILE_DIR, profile_name(wl, args.precision)),
+        if args.workload == "euler_batch":
+            name = f"euler_batch_{args.count}_q2_{args.precision}_stage_kernels.md"
+        else:
+            name = profile_name(workloads.make(args.workload, seed=0, **kw), args.precision)
+        summarize_profile(args.summarize_profile, os.path.join(PROFILE_DIR, name),
                           args.profile_command, COPY_PROBE_BYTES)
         return
 
