@@ -681,6 +681,33 @@ __device__ inline void block_min_dt(double* part, double v, int bx) {
 }
 
 
+// f(integral constant K) for K = 0 .. N-1: a loop whose index is a
+// compile-time constant in the body (an axis or a component as a template
+// argument)
+template <int K> struct IC {
+  static constexpr int value = K;
+};
+template <int N, int K = 0, class F>
+__device__ __forceinline__ void static_for(const F& f) {
+  if constexpr (K < N) {
+    f(IC<K>{});
+    static_for<N, K + 1>(f);
+  }
+}
+
+// component c of a value array computed for all components, as a sum of
+// masked terms (exact: one term is v[c], the others are +0).  Where a whole
+// flux array is computed only to pick one entry, a select chain was folded
+// by the compiler into a dynamically indexed stack array (scratch stores and
+// loads); this form stays in registers.
+template <int M, class V>
+__device__ __forceinline__ V pick_m(const V* v, int c) {
+  V r = 0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r += (c == k) ? v[k] : (V)0;
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // sum-factorised element operators
 // ---------------------------------------------------------------------------
@@ -790,6 +817,13 @@ template <int D, int P, int M> struct GlobalNodes {
     for (int j = 0; j < NL; ++j) cn[j] = a->u[c * a->mesh.N + local_node<D, P>(j, offn)];
   }
   __device__ __forceinline__ int own_node(int j) const { return local_node<D, P>(j, off); }
+  // coefficient j of component c, re-read (not merged with earlier reads of
+  // the same value: the offset passes through an empty asm)
+  __device__ __forceinline__ double own(int c, int j) const {
+    int nd = local_node<D, P>(j, off);
+    asm volatile("" : "+v"(nd));
+    return a->u[c * a->mesh.N + nd];
+  }
   // projected gradient: g (float64) or g32 (mixed precision)
   template <class V>
   __device__ __forceinline__ void load_grad(int c, V (*gk)[ipow(P + 1, D)]) const {
@@ -832,6 +866,12 @@ template <int P, int M> struct TileNodes2 {
     for (int j = 0; j < NL; ++j)
 #pragma unroll
       for (int c = 0; c < M; ++c) U[c][j] = cem_smem[c * TT::NXY + base + (j / (P + 1)) * TT::NX + j % (P + 1)];
+  }
+  // coefficient j of component c, re-read from the tile (see GlobalNodes)
+  __device__ __forceinline__ double own(int c, int j) const {
+    int o = base;
+    asm volatile("" : "+v"(o));
+    return cem_smem[c * TT::NXY + o + (j / (P + 1)) * TT::NX + j % (P + 1)];
   }
   __device__ __forceinline__ void load_nbr(int c, int l, double* cn) const {
     const int k = l / 2, s = (l % 2) ? 1 : -1;
@@ -904,9 +944,9 @@ __device__ inline bool interior_node(int j) {
   return in;
 }
 
-template <int D, int P, class PHY>
-__device__ inline double subcell_dt(const double (*U)[ipow(P + 1, D)], const double* ue, double h,
-                                    const PhysParams& ph) {
+// U(c, j): coefficient j of component c
+template <int D, int P, class PHY, class UA>
+__device__ inline double subcell_dt(const UA& U, const double* ue, double h, const PhysParams& ph) {
   constexpr int NL = ipow(P + 1, D), M = PHY::M, NI = ipow(P - 1, D);
   double hd = 1.0;
 #pragma unroll
@@ -918,7 +958,7 @@ __device__ inline double subcell_dt(const double (*U)[ipow(P + 1, D)], const dou
     double s = 0.0;
 #pragma unroll
     for (int j = 0; j < NL; ++j)
-      if (interior_node<D, P>(j)) s += U[c][j];
+      if (interior_node<D, P>(j)) s += U(c, j);
     u0[c] = NI > 0 ? s * (1.0 / (NI > 0 ? NI : 1)) : ue[c];
   }
   double tnode = 1.0e300, csum = 0.0;
@@ -926,7 +966,7 @@ __device__ inline double subcell_dt(const double (*U)[ipow(P + 1, D)], const dou
   for (int j = 0; j < NL; ++j) {
     double uj[M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) uj[c] = U[c][j];
+    for (int c = 0; c < M; ++c) uj[c] = U(c, j);
     const double cl = subcell_node<D, P, PHY>(j, u0, uj, h, ph);
     if (cl > 0.0) tnode = fmin(tnode, mi / cl);
     csum += cl;
@@ -1086,7 +1126,101 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   // element, not with the size of u or f.
   double foa[D * M];
   PHY::flux_all(ue, foa, a.ph);          // fluxes of the own average
-  if constexpr (ROLE != 1) {
+  // systems: the residual one component at a time (SEQ): the Gauss-point
+  // states of all components stay in registers, the nodal coefficients are
+  // re-read where needed, and each component's element vector is stored as
+  // soon as it is complete (fewer live registers than all components' R, U
+  // and fluxes at once)
+  constexpr bool SEQ = M > 1 && ROLE == 0 && WS;
+  auto store_rc = [&](int c, int i, RT v) {
+    const int64_t q = ((int64_t)c * NL + i) * E + e;
+    if constexpr (MIX) {
+      double fb = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) fb += foa[k * M + c] * ref_grad_int<D, P>(i, k);
+      a.relem[q] = (double)v + hpow * fb;
+    } else {
+      a.relem[q] = v;
+    }
+  };
+  if constexpr (SEQ) {
+    RT uq[M][NL];
+    {
+      const int mv[3] = {SF::vq, SF::vq, SF::vq};
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        RT uc[NL];
+#pragma unroll
+        for (int j = 0; j < NL; ++j) uc[j] = MIX ? (RT)(U[c][j] - ue[c]) : (RT)U[c][j];
+        tensor_apply<D, P>(T, mv, false, uc, uq[c]);
+      }
+    }
+    RT wq[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      RT wv = 1;
+#pragma unroll
+      for (int j = 0; j < D; ++j) wv *= T(SF::wq + dig(q, j, P1));
+      wq[q] = wv;
+    }
+    const RT sa = (RT)(nu * hpow / h), sg = (RT)(nu * gam * hpow);
+    static_for<M>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      const TabRef<RT>& Tc = T;
+      RT Rc[NL];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) Rc[i] = 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        RT Fc[NL];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+          if constexpr (MIX) {
+            double uv[M], fv[M];
+#pragma unroll
+            for (int c2 = 0; c2 < M; ++c2) uv[c2] = ue[c2] + (double)uq[c2][q];
+            PHY::flux(k, uv, fv, a.ph);
+            Fc[q] = wq[q] * (RT)(pick_m<M>(fv, c) - pick_m<M>(foa + k * M, c));
+          } else {
+            RT uv[M], fv[M];
+#pragma unroll
+            for (int c2 = 0; c2 < M; ++c2) uv[c2] = uq[c2][q];
+            PHY::flux(k, uv, fv, a.ph);
+            Fc[q] = wq[q] * pick_m<M>(fv, c);
+          }
+        }
+        int mt[3] = {SF::vq, SF::vq, SF::vq};
+        mt[k] = SF::dq;
+        RT t[NL];
+        tensor_apply<D, P>(Tc, mt, true, Fc, t);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) Rc[i] += t[i];
+      }
+      RT gk[D][NL], s1[NL], s2[NL], uc[NL];
+      ns.load_grad(c, gk);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        s1[i] = s2[i] = 0;
+        uc[i] = MIX ? (RT)(ns.own(c, i) - ue[c]) : (RT)ns.own(c, i);
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        int ms1[3] = {SF::g, SF::g, SF::g}, ms2[3] = {SF::g, SF::g, SF::g};
+        ms1[k] = SF::k1;
+        ms2[k] = SF::ct;
+        RT t[NL];
+        tensor_apply<D, P>(Tc, ms1, false, uc, t);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) s1[i] += t[i];
+        tensor_apply<D, P>(Tc, ms2, false, gk[k], t);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) s2[i] += t[i];
+      }
+#pragma unroll
+      for (int i = 0; i < NL; ++i) store_rc(c, i, (RT)hpow * Rc[i] - (sa * s1[i] - sg * s2[i]));
+    });
+  }
+  if constexpr (ROLE != 1 && !SEQ) {
   RT R[M][NL];
   {
     RT uq[M][NL];
@@ -1279,7 +1413,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
         } else {
           double uj[M];
 #pragma unroll
-          for (int c = 0; c < M; ++c) uj[c] = U[c][j];
+          for (int c = 0; c < M; ++c) uj[c] = SEQ ? ns.own(c, j) : U[c][j];
           PHY::flux(k, uj, fj, a.ph);
         }
 #pragma unroll
@@ -1302,7 +1436,10 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     // u^e - dt_e / h sum_facets f^H . n, with dt_e of Lemma 1 (eq. 37) or
     // eq. (40) reduced until ubar^e is admissible
     if (a.flux_mode == 1) {
-      dt_e = subcell_dt<D, P, PHY>(U, ue, h, a.ph);
+      if constexpr (SEQ)
+        dt_e = subcell_dt<D, P, PHY>([&](int c, int j) { return ns.own(c, j); }, ue, h, a.ph);
+      else
+        dt_e = subcell_dt<D, P, PHY>([&](int c, int j) { return U[c][j]; }, ue, h, a.ph);
     } else if constexpr (PH == EUL) {
       double dl[M];
 #pragma unroll

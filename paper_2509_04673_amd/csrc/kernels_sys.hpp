@@ -38,19 +38,6 @@ template <int D, int P, int PH> struct SysTile {
   using LY = SysLayout<D, P, PH, EB>;
 };
 
-// f(integral constant K) for K = 0 .. N-1: a loop whose index is a
-// compile-time constant in the body (an axis as a template argument)
-template <int K> struct IC {
-  static constexpr int value = K;
-};
-template <int N, int K = 0, class F>
-__device__ __forceinline__ void static_for(const F& f) {
-  if constexpr (K < N) {
-    f(IC<K>{});
-    static_for<N, K + 1>(f);
-  }
-}
-
 // component c of a value array computed for all components (a select chain:
 // no dynamically indexed register array)
 template <int M, class V>
@@ -62,17 +49,6 @@ __device__ __forceinline__ V pick_c(const V* v, int c) {
   return r;
 }
 
-// the same as a sum of masked terms (exact: one term is v[c], the others are
-// +0).  Where a whole flux array is computed only to pick one entry, the
-// compiler folded the select chain into a dynamically indexed stack array
-// (scratch stores and loads); this form it keeps in registers.
-template <int M, class V>
-__device__ __forceinline__ V pick_m(const V* v, int c) {
-  V r = 0;
-#pragma unroll
-  for (int k = 0; k < M; ++k) r += (c == k) ? v[k] : (V)0;
-  return r;
-}
 
 // v[i] for a runtime i < K, and v[i] = x, without a dynamically indexed
 // register array (which would live in scratch)
