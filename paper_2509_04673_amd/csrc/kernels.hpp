@@ -1879,7 +1879,9 @@ __device__ __forceinline__ void k_gather_r_body(const StageArgs& a, int bx) {
 #pragma unroll
   for (int c = 0; c < M; ++c) {
     double s = 0.0;
-    for (int t = 0; t < nrec; ++t) s += a.relem[((int64_t)c * NL + locs[t]) * E + eids[t]];
+    #pragma unroll
+    for (int t = 0; t < (1 << D); ++t)    // constant indices into eids / locs
+      if (t < nrec) s += a.relem[((int64_t)c * NL + locs[t]) * E + eids[t]];
     r[c * N + i] = (RT)s;
   }
 }
@@ -1940,7 +1942,9 @@ __device__ __forceinline__ void k_update_body(const StageArgs& a, int bx) {
 #pragma unroll
     for (int c = 0; c < M; ++c) {
       double s = 0.0;
-      for (int t = 0; t < nrec; ++t) s += a.relem[((int64_t)c * NL + locs[t]) * E + eids[t]];
+      #pragma unroll
+      for (int t = 0; t < (1 << D); ++t)    // constant indices into eids / locs
+        if (t < nrec) s += a.relem[((int64_t)c * NL + locs[t]) * E + eids[t]];
       const double ui = a.u[c * N + i];
       if (a.copy_base) a.u0[c * N + i] = ui;
       const double ufe = ui + dt / mi * s;
@@ -2041,7 +2045,9 @@ __device__ __forceinline__ void k_gather_line_x_body(const StageArgs& sa, const 
     int locs[8];
     const int nrec = node_elements<D, P>(i, sa.mesh, eids, locs);
     double s = 0.0;
-    for (int t = 0; t < nrec; ++t) s += sa.relem[(c * NL + locs[t]) * E + eids[t]];
+    #pragma unroll
+    for (int t = 0; t < (1 << D); ++t)    // constant indices into eids / locs
+      if (t < nrec) s += sa.relem[(c * NL + locs[t]) * E + eids[t]];
     sm[ql * LS + W + x] = (RT)s;
     rr[g] = (RT)s;
   }

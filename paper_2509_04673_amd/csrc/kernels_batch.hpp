@@ -105,8 +105,7 @@ __global__ void __launch_bounds__(128) kb_elem2(const StageArgs* __restrict__ ar
 }
 
 template <int D, int P, int PH, class RT>
-__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB))
-    kb_elem2_sys(const StageArgs* __restrict__ args, BatchMap m) {
+__global__ void CEM_SYS2_BOUNDS kb_elem2_sys(const StageArgs* __restrict__ args, BatchMap m) {
   int lb;
   const int pid = batch_find(m, blockIdx.x, &lb);
   k_elem2_sys_body<D, P, PH, RT>(args[pid], lb);

@@ -502,6 +502,9 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
 // 8.1 + 7.6 ms)
 #define CEM_SYS_BOUNDS __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) \
   __attribute__((amdgpu_waves_per_eu(2, 2)))
+// pass 2: at least two waves per SIMD (the 2D pass fits three)
+#define CEM_SYS2_BOUNDS __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) \
+  __attribute__((amdgpu_waves_per_eu(2)))
 
 template <int D, int P, int PH, class RT>
 __global__ void CEM_SYS_BOUNDS k_elem1_sys(StageArgs a) {
@@ -603,9 +606,13 @@ __device__ __forceinline__ void k_elem2_sys_body(const StageArgs& a, int bx) {
   RT fb[NL];
 #pragma unroll
   for (int i = 0; i < NL; ++i) fb[i] = 0;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-#pragma unroll
+  // the axis as a compile-time constant: left to "#pragma unroll" the
+  // compiler kept the axis loop rolled, and the facet-node index arithmetic
+  // became runtime divisions and dynamically indexed registers; the two
+  // sides stay a rolled loop (fewer live registers)
+  static_for<D>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+#pragma unroll 1
     for (int side = 0; side < 2; ++side) {
       const int av = side ? P : 0;
       const RT sg = (RT)(side ? hpow : -hpow);
@@ -629,7 +636,7 @@ __device__ __forceinline__ void k_elem2_sys_body(const StageArgs& a, int bx) {
         fb[i] += sg * fn[fi];
       }
     }
-  }
+  });
   // ---- element contributions f_i^e of eq. (45); dU_i = m_i^e (ubar - u_i)
   const double hd = hpow * h, mloc = hd * (1.0 / NL);
   double dU[NL], f[NL];
@@ -708,7 +715,7 @@ __device__ __forceinline__ void k_elem2_sys_body(const StageArgs& a, int bx) {
 }
 
 template <int D, int P, int PH, class RT>
-__global__ void __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) k_elem2_sys(StageArgs a) {
+__global__ void CEM_SYS2_BOUNDS k_elem2_sys(StageArgs a) {
   k_elem2_sys_body<D, P, PH, RT>(a, blockIdx.x);
 }
 
