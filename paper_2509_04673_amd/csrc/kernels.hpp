@@ -360,7 +360,7 @@ __global__ void __launch_bounds__(256) k_line(LineArgs a) {
 
 // Register-blocked line operator for long lines (L >= R + TAPS): the rows of
 // the periodic inverse decay exponentially, so 2W+1 taps of the infinite-line
-// rows reproduce them below 1e-20 relative.  Lanes of a wave take different
+// rows reproduce them to 1e-17 of the row peak.  Lanes of a wave take different
 // transverse lines at the same run of R consecutive outputs along the axis,
 // so every output of a lane shares its node class with the other lanes and
 // the weights are wave-uniform (scalar loads); each thread keeps R
@@ -375,9 +375,9 @@ template <int P_, int W_> struct LineTapsBase {
   static constexpr int W = W_;
   static constexpr int S = (2 * W_ + 1 + kLineMaxRE * P_ - 1) / (kLineMaxRE * P_) * (kLineMaxRE * P_);
 };
-template <> struct LineTaps<1> : LineTapsBase<1, 36> {};
-template <> struct LineTaps<2> : LineTapsBase<2, 54> {};
-template <> struct LineTaps<3> : LineTapsBase<3, 68> {};
+template <> struct LineTaps<1> : LineTapsBase<1, 30> {};
+template <> struct LineTaps<2> : LineTapsBase<2, 44> {};
+template <> struct LineTaps<3> : LineTapsBase<3, 57> {};
 // float operators (mixed precision): rows cut below 1e-9 of their peak
 template <int P> struct LineTaps32;
 template <> struct LineTaps32<1> : LineTapsBase<1, 18> {};

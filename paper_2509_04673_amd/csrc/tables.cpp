@@ -153,8 +153,10 @@ void fill_kernel(int p, int Lp, const std::vector<LD>& rows, int taps, int first
     }
 }
 
-// half-width beyond which the rows fall below thresh (1e-20) of their peak
-int decay_width(int p, int Lp, const std::vector<LD>& rows, LD thresh = 1e-20L) {
+// half-width beyond which the rows fall below thresh of their peak (1e-17:
+// the dropped taps then sum to a few 1e-17 of the peak, below float64
+// rounding of the kept ones)
+int decay_width(int p, int Lp, const std::vector<LD>& rows, LD thresh = 1e-17L) {
   LD peak = 0.0L;
   for (LD v : rows) peak = std::max(peak, std::fabs(v));
   int W = 0;
