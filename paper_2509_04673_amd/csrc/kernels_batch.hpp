@@ -69,14 +69,14 @@ __global__ void __launch_bounds__(256) kb_elem1_tile2(const StageArgs* __restric
 }
 
 template <int D, int P, int PH, class RT>
-__global__ void CEM_SYS_BOUNDS kb_elem1_sys(const StageArgs* __restrict__ args, BatchMap m) {
+__global__ void CEM_SYS1_BOUNDS kb_elem1_sys(const StageArgs* __restrict__ args, BatchMap m) {
   int lb;
   const int pid = batch_find(m, blockIdx.x, &lb);
   k_elem1_sys_body<D, P, PH, RT, 1>(args[pid], lb);
 }
 
 template <int D, int P, int PH, class RT>
-__global__ void CEM_SYS_BOUNDS kb_resid_sys(const StageArgs* __restrict__ args, BatchMap m) {
+__global__ void CEM_SYS1_BOUNDS kb_resid_sys(const StageArgs* __restrict__ args, BatchMap m) {
   int lb;
   const int pid = batch_find(m, blockIdx.x, &lb);
   k_elem1_sys_body<D, P, PH, RT, 2>(args[pid], lb);

@@ -497,22 +497,28 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
   }
 }
 
-// both halves are compiled for two waves per SIMD (measured: the whole pass
-// at one wave per SIMD took 22.4 ms on the 128^3 Q2 blast, the halves at two
-// 8.1 + 7.6 ms)
-#define CEM_SYS_BOUNDS __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) \
-  __attribute__((amdgpu_waves_per_eu(2, 2)))
-// pass 2: at least two waves per SIMD (the 2D pass fits three)
+// pass 2: at least two waves per SIMD in float64 (the 2D pass fits three),
+// three in the mixed form (3D: 23.6 -> 20.9 ms per six launches; float64 at
+// three spills and slows, 22.7 -> 25.4)
 #define CEM_SYS2_BOUNDS __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) \
-  __attribute__((amdgpu_waves_per_eu(2)))
+  __attribute__((amdgpu_waves_per_eu(sizeof(RT) == 4 ? 3 : 2, sizeof(RT) == 4 ? 3 : 8)))
+
+// both halves of pass 1 (the whole pass in one kernel needed 256 VGPRs plus
+// AGPRs, one wave per SIMD, 22.4 ms per launch on the 128^3 Q2 blast; the
+// halves at two waves 6.9 + 7.6 ms): two waves per SIMD in float64, three in
+// the mixed form, whose float contractions need fewer registers (ms per six
+// launches: sensor half 37.4 -> 31.7, residual half 44.7 -> 40.5; float64 at
+// three waves spills and slows, residual 45.4 -> 61.6)
+#define CEM_SYS1_BOUNDS __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) \
+  __attribute__((amdgpu_waves_per_eu(sizeof(RT) == 4 ? 3 : 2, sizeof(RT) == 4 ? 3 : 2)))
 
 template <int D, int P, int PH, class RT>
-__global__ void CEM_SYS_BOUNDS k_elem1_sys(StageArgs a) {
+__global__ void CEM_SYS1_BOUNDS k_elem1_sys(StageArgs a) {
   k_elem1_sys_body<D, P, PH, RT, 1>(a, blockIdx.x);
 }
 
 template <int D, int P, int PH, class RT>
-__global__ void CEM_SYS_BOUNDS k_resid_sys(StageArgs a) {
+__global__ void CEM_SYS1_BOUNDS k_resid_sys(StageArgs a) {
   k_elem1_sys_body<D, P, PH, RT, 2>(a, blockIdx.x);
 }
 
