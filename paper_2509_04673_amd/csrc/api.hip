@@ -25,11 +25,24 @@ namespace {
 // itself; above it one block does it once (k_stage_dt)
 constexpr int kDtFusedMax = 1024;
 
+// 2D Euler element pass 1 on the system kernels instead of the one-thread
+// tile: measured slower (512^2 Q3 float64 3.23 against 3.16 ms per step;
+// 512 Q2 problems 90.7 against 81.9 ms float64, 72.2 against 69.0 mixed)
+constexpr bool kSys2D = false;
+
 // 2D element pass 1 with two threads (roles) per element: scalar problems.
 // Measured per stage: KPP 256^2 Q2 22.7 -> 17.3 us; for 512^2 Q3 Euler the
 // one-thread tile stays faster (0.46 against 0.47 ms, mixed 0.36 against
 // 0.45 ms).
 template <int PH> constexpr bool tile2_roles() { return Phys<2, PH>::M == 1; }
+
+// Euler element pass 1: the system kernels (one thread per element and
+// component, two launches) rather than the one-thread LDS tile
+template <int D, int P, int PH, class RT> constexpr bool sys_pass1() {
+  if constexpr (PH != EUL || D == 1) return false;
+  else if constexpr (D == 3) return true;
+  else return kSys2D;
+}
 
 thread_local std::string g_err;
 
@@ -472,7 +485,7 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     // (sensor and facets; residual).  2D: the LDS element tile with one
     // thread per element measured faster for both physics (512^2 Q3 Euler:
     // 0.46 ms per stage against 0.52 for the two system launches)
-    if constexpr (PH == EUL && D == 3) {
+    if constexpr (sys_pass1<D, P, PH, RT>()) {
       cem_status st = launch_sys<D, P, PH, RT>(c, a, true);
       if (st != CEM_OK) return st;
     } else if constexpr (D == 2) {
@@ -545,7 +558,7 @@ StageArgs batch_stage_args(cem_ctx* c, int stage, double dt, double cfl) {
   a.dt_fixed = dt;
   a.cfl = cfl;
   constexpr int M = Phys<D, PH>::M;
-  if constexpr (PH == EUL && D == 3) {
+  if constexpr (sys_pass1<D, P, PH, RT>()) {
     a.ndtpart = (int)nblocks(c->E, SysTile<D, P, PH>::EB);
   } else if constexpr (D == 2) {
     using TT = Tile2<P, M>;
@@ -666,7 +679,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     // element pass 1
     {
       Group g;
-      constexpr bool sys = PH == EUL && D == 3;
+      constexpr bool sys = sys_pass1<D, P, PH, RT>();
       if constexpr (sys) {
         g.l.kind = B_ELEM1_SYS;
         g.l.lds = SysTile<D, P, PH>::LY::bytes;
@@ -786,11 +799,11 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
           hipLaunchKernelGGL((kb_elem1_tile2<P, PH, true, RT>), g, dim3(256), l.lds, stream, sa, mp);
         break;
       case B_ELEM1_SYS:
-        if constexpr (PH == EUL && D == 3)
+        if constexpr (sys_pass1<D, P, PH, RT>())
           hipLaunchKernelGGL((kb_elem1_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
         break;
       case B_RESID_SYS:
-        if constexpr (PH == EUL && D == 3)
+        if constexpr (sys_pass1<D, P, PH, RT>())
           hipLaunchKernelGGL((kb_resid_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
         break;
       case B_GATHER_LX:
