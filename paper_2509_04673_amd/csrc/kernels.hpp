@@ -1032,8 +1032,11 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   double gmin = 1.0;
   for (int c = 0; c < M; ++c) {
     RT ct[NL];
+    // systems: the component is a runtime value here, so the coefficients
+    // are re-read (U[c][j] would index a register array dynamically)
+    const double u00 = M > 1 ? ns.own(c, 0) : U[0][0];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) ct[j] = (RT)(U[c][j] - U[c][0]);
+    for (int j = 0; j < NL; ++j) ct[j] = (RT)((M > 1 ? ns.own(c, j) : U[0][j]) - u00);
     RT beta[1 + 2 * D];
     beta[0] = qsym<NL>(T, SF::qp, ct);
     RT X[keepx ? 2 * D : 1][NL];
