@@ -814,7 +814,8 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
         hipLaunchKernelGGL((kb_gather_r<D, P, M, RT>), g, dim3(256), 0, stream, sa, mp);
         break;
       case B_ELEM2:
-        hipLaunchKernelGGL((kb_elem2<D, P, PH, RT>), g, dim3(128), 0, stream, sa, mp);
+        if constexpr (!(PH == EUL && D >= 2))
+          hipLaunchKernelGGL((kb_elem2<D, P, PH, RT>), g, dim3(128), 0, stream, sa, mp);
         break;
       case B_ELEM2_SYS:
         if constexpr (PH == EUL && D >= 2)
@@ -853,7 +854,7 @@ BatchFns pick_batch(int d, int p, int kind, bool mixed) {
 using StageFn = cem_status (*)(cem_ctx*, int, double, double);
 
 void drop_graph(cem_ctx* c) {
-  if (c->graph) hipGraphExecDestroy(c->graph);
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
   c->graph = nullptr;
 }
 
@@ -1117,12 +1118,12 @@ cem_status cem_step(cem_ctx* c, double dt, double cfl) {
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     c->stream = user;
     if (st != CEM_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return st;
     }
     if (e != hipSuccess) return fail(CEM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       c->graph = nullptr;
       return fail(CEM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
@@ -1273,12 +1274,12 @@ cem_status cem_kernel_times(cem_ctx* c, double* total_ms, long long* launches, i
 void cem_destroy(cem_ctx* c) {
   if (!c) return;
   drop_graph(c);
-  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto& r : c->recs) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
-  for (auto e : c->pool) hipEventDestroy(e);
+  for (auto e : c->pool) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -1286,14 +1287,14 @@ void cem_destroy(cem_ctx* c) {
 // batched form
 // ---------------------------------------------------------------------------
 static void batch_drop_graph(cem_batch* b) {
-  if (b->graph) hipGraphExecDestroy(b->graph);
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
   b->graph = nullptr;
 }
 
 void cem_batch_destroy(cem_batch* b) {
   if (!b) return;
   batch_drop_graph(b);
-  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   for (cem_ctx* c : b->pr) cem_destroy(c);
   delete b;
 }
@@ -1445,12 +1446,12 @@ cem_status cem_batch_step(cem_batch* b, double dt, double cfl, int nsteps) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (st != CEM_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return st;
     }
     if (e != hipSuccess) return fail(CEM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       b->graph = nullptr;
       return fail(CEM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
@@ -1527,8 +1528,8 @@ cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, vo
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
       trials.push_back({caps[ci], order, ms / steps});
     }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != CEM_OK) return st;
   const Trial* best = &trials[0];
   for (const Trial& t : trials)
