@@ -11,21 +11,22 @@ from paper_2509_04673_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _batch_for(wls, precision="fp64"):
+def _batch_for(wls, precision="fp64", **modes):
     from paper_2509_04673_amd.cem import BatchSolver
     w0 = wls[0]
     probs = [(w.d, w.p, w.n, w.lo, w.hi) for w in wls]
-    b = BatchSolver(probs, w0.kind, w0.velocity, w0.gamma_gas, w_lin=w0.w_lin, q=w0.q, precision=precision)
+    b = BatchSolver(probs, w0.kind, w0.velocity, w0.gamma_gas, w_lin=w0.w_lin, q=w0.q, precision=precision,
+                    **modes)
     b.upload([w.u0 for w in wls])
     if w0.kind != "euler":
         b.set_bounds()
     return b
 
 
-def _singles(wls, nsteps, dt, cfl, precision="fp64"):
+def _singles(wls, nsteps, dt, cfl, precision="fp64", **modes):
     outs = []
     for w in wls:
-        s = gpu_for(w, precision=precision)
+        s = gpu_for(w, modes, precision=precision)
         for _ in range(nsteps):
             s.step(dt=dt, cfl=cfl)
         outs.append(s.download().ravel())
@@ -125,3 +126,34 @@ def test_batch_autotune_keeps_state_and_results():
     ref.close()
     # the plan choices change launch shapes and order, not the arithmetic
     assert rel_linf(tuned, plain) <= 1e-12
+
+
+def test_batch_matches_single_problems_euler3d():
+    # the 3D system passes (sensor and residual halves, pass 2) in batched form
+    wls = [W.euler3d(seed=s, n=n) for s, n in ((0, 6), (1, 9), (2, 5))]
+    b = _batch_for(wls)
+    b.step(cfl=0.5, nsteps=2)
+    got = b.download()
+    chk = b.check()
+    b.close()
+    ref = _singles(wls, 2, 0.0, 0.5)
+    for k, (g, r) in enumerate(zip(got, ref)):
+        err = rel_linf(g, r)
+        announce(f"[batch] euler3d problem {k} n={wls[k].n}: batch vs single rel Linf {err:.1e}")
+        assert err <= 1e-10, (k, err)
+        assert chk[k]["violations"] == 0 and chk[k]["rho_min"] > 0 and chk[k]["p_min"] > 0
+
+
+@pytest.mark.parametrize("mode", ["subcell", "shrink"])
+def test_batch_flux_limiter_off_matches_single(mode):
+    # the flux-limiter-off variant (Sec. 4.3) through the batched launches
+    wls = W.euler_batch(seed=7, sizes=[24, 57, 40])
+    b = _batch_for(wls, flux_mode=mode)
+    b.step(cfl=0.5, nsteps=3)
+    got = b.download()
+    b.close()
+    ref = _singles(wls, 3, 0.0, 0.5, flux_mode=mode)
+    for k, (g, r) in enumerate(zip(got, ref)):
+        err = rel_linf(g, r)
+        announce(f"[batch] {mode} problem {k}: batch vs single rel Linf {err:.1e}")
+        assert err <= 1e-10, (k, err)
