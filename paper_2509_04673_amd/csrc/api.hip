@@ -89,6 +89,7 @@ struct cem_ctx {
   bool fnode_valid = false;   // nodal fluxes match the bound state
   int lds_max = 65536;        // LDS bytes one block may use on the bound device
   int upd_blocks = 0, inv_blocks = 0;
+  size_t ndtp = 0;                 // capacity of the per-block dt_e minima
   bool bound = false, bounds_set = false;
   // whole-step HIP graph (captured on a private stream, launched on stream)
   bool use_graphs = true;
@@ -401,7 +402,8 @@ cem_status launch_sys(cem_ctx* c, StageArgs& a, bool first) {
   constexpr int M = Phys<D, PH>::M, EB = TL::EB;
   const size_t lds = TL::LY::bytes;
   if (lds > (size_t)c->lds_max) return fail(CEM_EINVAL, "element tile does not fit the LDS of a block");
-  const unsigned nb = (unsigned)nblocks(c->E, EB);
+  const unsigned nb = (unsigned)TL::blocks(c->n);
+  if (nb > c->ndtp) return fail(CEM_EINVAL, "internal: more element blocks than dt_e minima slots");
   if (first) {
     a.ndtpart = (int)nb;
     CEM_LAUNCH(c, 1, (k_elem1_sys<D, P, PH, RT>), nb, M * EB, lds, c->stream, a);
@@ -492,6 +494,7 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
       using TT = Tile2<P, M>;
       const int nb = ((c->n[0] + TT::TEX - 1) / TT::TEX) * ((c->n[1] + TT::TEY - 1) / TT::TEY);
       a.ndtpart = nb;
+      if ((size_t)nb > c->ndtp) return fail(CEM_EINVAL, "internal: more element blocks than dt_e minima slots");
       if constexpr (tile2_roles<PH>())
         CEM_LAUNCH(c, 1, (k_elem1_tile2<P, PH, true, RT>), nb, 256, (TT::words + 256) * sizeof(double),
                    c->stream, a);
@@ -559,7 +562,7 @@ StageArgs batch_stage_args(cem_ctx* c, int stage, double dt, double cfl) {
   a.cfl = cfl;
   constexpr int M = Phys<D, PH>::M;
   if constexpr (sys_pass1<D, P, PH, RT>()) {
-    a.ndtpart = (int)nblocks(c->E, SysTile<D, P, PH>::EB);
+    a.ndtpart = (int)SysTile<D, P, PH>::blocks(c->n);
   } else if constexpr (D == 2) {
     using TT = Tile2<P, M>;
     a.ndtpart = ((c->n[0] + TT::TEX - 1) / TT::TEX) * ((c->n[1] + TT::TEY - 1) / TT::TEY);
@@ -750,7 +753,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         cem_ctx* c = all[q];
         g2.sa.push_back(sa[q]);
         if constexpr (PH == EUL && D >= 2)
-          g2.first.push_back(g2.first.back() + (int)nblocks(c->E, SysTile<D, P, PH>::EB));
+          g2.first.push_back(g2.first.back() + (int)SysTile<D, P, PH>::blocks(c->n));
         else
           g2.first.push_back(g2.first.back() + (int)nblocks(c->E, 128));
         gu.sa.push_back(sa[q]);
@@ -984,6 +987,7 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   // or the 32- / 64-element blocks of the system passes
   size_t ndtp = nblocks(c->E, 32);
   if (d == 2) ndtp = std::max(ndtp, (size_t)((c->n[0] + 15) / 16) * (size_t)((c->n[1] + 7) / 8));
+  c->ndtp = ndtp;
   c->o_dtpart = take(ndtp * 8);
   c->upd_blocks = (int)nblocks(c->N, 256);
   c->o_counts = take((size_t)c->upd_blocks * 2 * sizeof(int));

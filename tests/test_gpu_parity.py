@@ -84,6 +84,9 @@ def test_euler3d_small_run_parity():
     err, floor, st, chk = _run_both(wl, 4, dt=None, cfl=0.5)
     assert err <= _tol(floor)
     assert chk["rho_min"] > 0 and chk["p_min"] > 0
+    # the counters share the workspace with the per-block dt_e minima: a
+    # block count past their capacity would show up here
+    assert chk["violations"] == 0 and chk["clamped"] == 0 and chk["cfl_violated"] == 0
 
 
 def test_kpp2d_full_size_stage_parity():
