@@ -681,6 +681,18 @@ __device__ inline void block_min_dt(double* part, double v, int bx) {
 }
 
 
+// XCD-aware block order: the hardware hands workgroup b to XCD b mod 8, and
+// each XCD has its own L2.  Giving XCD x the contiguous range of logical
+// blocks [x q + min(x, r), ... + q + (x < r)), q = nb / 8, r = nb mod 8, puts
+// neighbouring elements (which share nodes) on the same L2.  A bijection of
+// [0, nb).
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / kNumXcd, r = nb - q * kNumXcd;
+  const int x = b % kNumXcd, k = b / kNumXcd;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // f(integral constant K) for K = 0 .. N-1: a loop whose index is a
 // compile-time constant in the body (an axis or a component as a template
 // argument)

@@ -532,12 +532,12 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
 
 template <int D, int P, int PH, class RT>
 __global__ void CEM_SYS1_BOUNDS k_elem1_sys(StageArgs a) {
-  k_elem1_sys_body<D, P, PH, RT, 1>(a, blockIdx.x);
+  k_elem1_sys_body<D, P, PH, RT, 1>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 template <int D, int P, int PH, class RT>
 __global__ void CEM_SYS1_BOUNDS k_resid_sys(StageArgs a) {
-  k_elem1_sys_body<D, P, PH, RT, 2>(a, blockIdx.x);
+  k_elem1_sys_body<D, P, PH, RT, 2>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // flux-pair factor of Appendix A for the facet between eL and eR normal to
@@ -739,7 +739,7 @@ __device__ __forceinline__ void k_elem2_sys_body(const StageArgs& a, int bx) {
 
 template <int D, int P, int PH, class RT>
 __global__ void CEM_SYS2_BOUNDS k_elem2_sys(StageArgs a) {
-  k_elem2_sys_body<D, P, PH, RT>(a, blockIdx.x);
+  k_elem2_sys_body<D, P, PH, RT>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 }  // namespace cem
