@@ -271,6 +271,18 @@ __device__ inline double euler_alpha(const double* ub, const double* f, double m
   return fmin(a, 1.0);
 }
 
+// XCD-aware block order: the hardware hands workgroup b to XCD b mod 8, and
+// each XCD has its own L2.  Giving XCD x the contiguous range of logical
+// blocks [x q + min(x, r), ... + q + (x < r)), q = nb / 8, r = nb mod 8, puts
+// neighbouring elements (which share nodes) on the same L2.  A bijection of
+// [0, nb).
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / kNumXcd, r = nb - q * kNumXcd;
+  const int x = b % kNumXcd, k = b / kNumXcd;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // ---------------------------------------------------------------------------
 // index helpers
 // ---------------------------------------------------------------------------
@@ -552,7 +564,7 @@ __device__ __forceinline__ void k_line_x_body(const LineFastArgs& a, int bx) {
 
 template <int P, int RE, class TI, class TO>
 __global__ void __launch_bounds__(256) k_line_x(LineFastArgs a) {
-  k_line_x_body<P, RE, TI, TO>(a, blockIdx.x);
+  k_line_x_body<P, RE, TI, TO>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // Axes 1 and 2 (strided lines): a block stages a tile of 32 consecutive
@@ -680,18 +692,6 @@ __device__ inline void block_min_dt(double* part, double v, int bx) {
   if (threadIdx.x == 0) part[bx] = red[0];
 }
 
-
-// XCD-aware block order: the hardware hands workgroup b to XCD b mod 8, and
-// each XCD has its own L2.  Giving XCD x the contiguous range of logical
-// blocks [x q + min(x, r), ... + q + (x < r)), q = nb / 8, r = nb mod 8, puts
-// neighbouring elements (which share nodes) on the same L2.  A bijection of
-// [0, nb).
-constexpr int kNumXcd = 8;
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-  const int q = nb / kNumXcd, r = nb - q * kNumXcd;
-  const int x = b % kNumXcd, k = b / kNumXcd;
-  return x * q + (x < r ? x : r) + k;
-}
 
 // f(integral constant K) for K = 0 .. N-1: a loop whose index is a
 // compile-time constant in the body (an axis or a component as a template
@@ -1536,7 +1536,7 @@ __device__ __forceinline__ void k_elem1_tile_body(const StageArgs& a, int bx) {
 
 template <int P, int PH, bool WS, class RT>
 __global__ void __launch_bounds__(128) k_elem1_tile(StageArgs a) {
-  k_elem1_tile_body<P, PH, WS, RT>(a, blockIdx.x);
+  k_elem1_tile_body<P, PH, WS, RT>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // The same pass with two threads per element (256 threads): role 1 the
@@ -1571,7 +1571,7 @@ __device__ __forceinline__ void k_elem1_tile2_body(const StageArgs& a, int bx) {
 
 template <int P, int PH, bool WS, class RT>
 __global__ void __launch_bounds__(256) k_elem1_tile2(StageArgs a) {
-  k_elem1_tile2_body<P, PH, WS, RT>(a, blockIdx.x);
+  k_elem1_tile2_body<P, PH, WS, RT>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1821,7 +1821,7 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
 
 template <int D, int P, int PH, class RT>
 __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
-  k_elem2_body<D, P, PH, RT>(a, blockIdx.x);
+  k_elem2_body<D, P, PH, RT>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1903,7 +1903,7 @@ __device__ __forceinline__ void k_gather_r_body(const StageArgs& a, int bx) {
 
 template <int D, int P, int M, class RT>
 __global__ void __launch_bounds__(256) k_gather_r(StageArgs a) {
-  k_gather_r_body<D, P, M, RT>(a, blockIdx.x);
+  k_gather_r_body<D, P, M, RT>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // u^FE_i = u_i + dt / m_i sum_e [m_i^e (ubar^e - u_i) + beta_e f_i^e] / dt_e
@@ -2002,7 +2002,7 @@ __device__ __forceinline__ void k_update_body(const StageArgs& a, int bx) {
 
 template <int D, int P, int PH>
 __global__ void __launch_bounds__(256) k_update(StageArgs a) {
-  k_update_body<D, P, PH>(a, blockIdx.x);
+  k_update_body<D, P, PH>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // nodal fluxes f_k(u_j) of the bound state (kNodal physics), used when the
@@ -2090,7 +2090,7 @@ __device__ __forceinline__ void k_gather_line_x_body(const StageArgs& sa, const 
 
 template <int D, int P, int M, int RE, class RT>
 __global__ void __launch_bounds__(256) k_gather_line_x(StageArgs sa, LineFastArgs a) {
-  k_gather_line_x_body<D, P, M, RE, RT>(sa, a, blockIdx.x);
+  k_gather_line_x_body<D, P, M, RE, RT>(sa, a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // float -> double copy (debug taps of the mixed-precision intermediates)
