@@ -246,8 +246,15 @@ def copy_probe(nbytes):
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)
+    # the achievable HBM rate of a plain copy (read + write), for context
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        b.copy_(a)
+    ev1.record()
     torch.cuda.synchronize()
-    print(json.dumps(dict(copy_probe_bytes=n * 8, copies=3)), flush=True)
+    gbs = 2 * n * 8 * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    print(json.dumps(dict(copy_probe_bytes=n * 8, copies=13, copy_gb_per_s=gbs)), flush=True)
 
 
 def cpu_baseline(wl, seconds):
