@@ -52,11 +52,25 @@ def test_create_and_sizes_on_host():
         cem.cem_destroy(ctx)
 
 
-@pytest.mark.parametrize("bad", ["dim", "degree", "cells", "aspect", "gamma", "velocity"])
+@pytest.mark.parametrize("bad", ["dim", "degree", "cells", "aspect", "gamma", "velocity", "precision",
+                                 "flux_mode", "too_large"])
 def test_create_rejects_invalid_configurations(bad):
     kw = dict()
     mesh, phys = _desc()
-    if bad == "dim":
+    prm = cem.cem_params_default()
+    if bad == "precision":
+        prm.precision = 5
+    elif bad == "flux_mode":
+        prm.flux_mode = 3
+    elif bad == "too_large":
+        # m N must stay below 2^31 (32-bit device index arithmetic)
+        mesh.dim, mesh.degree = 3, 2
+        for k in range(3):
+            mesh.n[k] = 700
+            mesh.hi[k] = 1.0
+        phys.kind = cem.EULER
+        phys.gamma_gas = 1.4
+    elif bad == "dim":
         mesh.dim = 4
     elif bad == "degree":
         mesh.degree = 7
@@ -71,7 +85,7 @@ def test_create_rejects_invalid_configurations(bad):
         phys.kind = cem.ADVECTION
         phys.velocity[0] = 0.0
     with pytest.raises(cem.CemError) as ei:
-        cem.cem_create(mesh, phys, cem.cem_params_default(), 0)
+        cem.cem_create(mesh, phys, prm, 0)
     assert ei.value.status == -1
     del kw
 
