@@ -197,7 +197,10 @@ def test_idp_euler_blast_positivity():
     v = u.copy()
     for _ in range(10):
         try:
-            v, st = orc_ho.run(v, 1, cfl=0.5)
+            # leaving the admissible set makes the Riemann speeds NaN (negative
+            # pressure to a fractional power): expected here, so not a warning
+            with np.errstate(invalid="ignore"):
+                v, st = orc_ho.run(v, 1, cfl=0.5)
         except Exception:
             bad += 1
             break
