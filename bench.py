@@ -363,7 +363,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+              "decomposition is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -9,7 +9,7 @@ dense LU factorisation per axis.  The stage follows the five-step algorithm
 of [KHV §4.3] in the paper's order and notation on a uniform periodic box
 (so the boundary terms b_i and g_i^e vanish, [KHV §3.1, §4]).
 
-Readings of points the paper leaves open (each listed in the design doc):
+Readings of points the paper leaves open:
   * g_h is the consistent L2 projection of grad u_h, solved exactly.
   * lambda_e is the largest nodal speed of the element, h_e the cell edge.
   * WENO candidates: v_0 = u_h^e; one candidate per facet neighbour, the
