@@ -7,10 +7,11 @@ from oracle import Mesh, Oracle, Params, Problem
 from paper_2509_04673_amd import workloads as W
 
 
-def rel_linf(a, b):
-    """max |a - b| / max |b| (per whole array)."""
+def rel_linf(a, b, floor=0.0):
+    """max |a - b| / max(max |b|, floor) (per whole array); floor is the
+    natural size of the quantity where the reference itself may vanish."""
     a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
-    scale = np.max(np.abs(b))
+    scale = max(float(np.max(np.abs(b))), floor)
     return float(np.max(np.abs(a - b)) / (scale if scale > 0 else 1.0))
 
 
@@ -65,10 +66,11 @@ def announce(msg):
 STAGE_TAPS = ["g", "gamma", "nu", "dt_e", "ue", "ubarL", "fA", "r", "udot", "ubar", "beta"]
 
 
-def compare_stage(wl, modes=None, label="", tol=1e-12):
+def compare_stage(wl, modes=None, label="", tol=1e-12, floors=None):
     """One forward-Euler stage on the GPU and in the oracle from the same
     state: relative L-infinity error of every intermediate and of the stage
-    result (which includes the bounds policy)."""
+    result (which includes the bounds policy).  floors: per-tap lower bounds
+    of the error scale (see rel_linf)."""
     orc = oracle_for(wl, modes)
     dt = wl.dt if wl.dt > 0 else 0.5 * orc.max_dt(wl.u0)
     announce(f"[parity] stage {label} d={wl.d} p={wl.p} n={wl.n} kind={wl.kind} modes={modes}")
@@ -79,7 +81,8 @@ def compare_stage(wl, modes=None, label="", tol=1e-12):
     got = s.download()
     errs = {}
     for name in STAGE_TAPS:
-        errs[name] = rel_linf(s.tap(name).reshape(np.shape(taps[name])), taps[name])
+        errs[name] = rel_linf(s.tap(name).reshape(np.shape(taps[name])), taps[name],
+                              (floors or {}).get(name, 0.0))
     errs["u_fe"] = rel_linf(got, ufe)
     s.close()
     announce(f"[parity] {label}: " + ", ".join(f"{k}={v:.1e}" for k, v in errs.items()))
