@@ -251,8 +251,8 @@ void launch_line_fast(cem_ctx* c, int id, LineFastArgs la, hipStream_t st) {
   constexpr int W = LineTapsV<P, TO>::W;
   if (la.axis == 0 && la.L <= 4096) {
     // whole lines in LDS; one line per block unless lines are short
-    la.nlb = line_rows_per_block<P, TO>(la.L, la.ntrans, 2048);
-    const size_t lds = (size_t)la.nlb * line_row_len<P, TO>(la.L) * sizeof(TO);
+    la.nlb = line_rows_per_block<P, TO>(la.L, la.ntrans, 2048, la.L >= 2 * P + 2 * W ? 2 * P : P);
+    const size_t lds = (size_t)la.nlb * line_row_pitch<P, TO>(la.L) * sizeof(TO);
     const unsigned grid = (unsigned)((la.ntrans + la.nlb - 1) / la.nlb);
     if (la.L >= 2 * P + 2 * W)
       CEM_LAUNCH(c, id, (k_line_x<P, 2, TI, TO>), grid, 256, lds, st, la);
@@ -455,9 +455,9 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     for (int k = 0; k < D; ++k) {
       LineFastArgs la = line_args<RT>(c, c->u, g + (int64_t)k * M * c->N, k, true);
       if (k == 0) {
-        la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 2048);
+        la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 2048, la.L >= 2 * P + 2 * W ? 2 * P : P);
         ml.nb[0] = (int)((la.ntrans + la.nlb - 1) / la.nlb);
-        lds = std::max(lds, (size_t)la.nlb * line_row_len<P, RT>(la.L) * sizeof(RT));
+        lds = std::max(lds, (size_t)la.nlb * line_row_pitch<P, RT>(la.L) * sizeof(RT));
       } else {
         const int TYk = TY * la.ky;
         la.gx = (int)nblocks(la.ntrans, kTileX);
@@ -511,8 +511,8 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   int k0 = 0;
   if (c->tabs.kmass[0].wfast > 0 && c->L[0] <= 4096) {
     LineFastArgs la = line_args<RT>(c, r, D == 1 ? udot : tmp, 0, false);
-    la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 2048);
-    const size_t lds = (size_t)la.nlb * line_row_len<P, RT>(la.L) * sizeof(RT);
+    la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 2048, P);
+    const size_t lds = (size_t)la.nlb * line_row_pitch<P, RT>(la.L) * sizeof(RT);
     const unsigned grid = (unsigned)((la.ntrans + la.nlb - 1) / la.nlb);
     CEM_LAUNCH(c, 3, (k_gather_line_x<D, P, M, 1, RT>), grid, 256, lds, c->stream, a, la);
     HIPCHK(hipGetLastError());
@@ -622,10 +622,10 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         LineFastArgs a = line_args<RT>(c, in, out_p, k, grad);
         if (k == 0) {
           if (a.L > 4096) return fail(CEM_EINVAL, "batched form: x-lines longer than 4096 nodes");
-          a.nlb = line_rows_per_block<P, RT>(a.L, a.ntrans, b->xlines_cap);
+          a.nlb = line_rows_per_block<P, RT>(a.L, a.ntrans, b->xlines_cap, P);
           gx.lf.push_back(a);
           gx.first.push_back(gx.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
-          gx.l.lds = std::max(gx.l.lds, (size_t)a.nlb * line_row_len<P, RT>(a.L) * sizeof(RT));
+          gx.l.lds = std::max(gx.l.lds, (size_t)a.nlb * line_row_pitch<P, RT>(a.L) * sizeof(RT));
         } else {
           const int TY = 8 * P * a.ky;
           a.gx = (int)nblocks(a.ntrans, kTileX);
@@ -716,11 +716,11 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         cem_ctx* c = all[q];
         if (fused(c)) {
           LineFastArgs a = line_args<RT>(c, rbuf(c), mass_dst(c, 0), 0, false);
-          a.nlb = line_rows_per_block<P, RT>(a.L, a.ntrans, b->xlines_cap);
+          a.nlb = line_rows_per_block<P, RT>(a.L, a.ntrans, b->xlines_cap, P);
           gf.sa.push_back(sa[q]);
           gf.lf.push_back(a);
           gf.first.push_back(gf.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
-          gf.l.lds = std::max(gf.l.lds, (size_t)a.nlb * line_row_len<P, RT>(a.L) * sizeof(RT));
+          gf.l.lds = std::max(gf.l.lds, (size_t)a.nlb * line_row_pitch<P, RT>(a.L) * sizeof(RT));
         } else {
           gr.sa.push_back(sa[q]);
           gr.first.push_back(gr.first.back() + (int)nblocks(c->N, 256));

@@ -305,11 +305,13 @@ __device__ inline int64_t node_stride(int k, const MeshArgs& m) {
 }
 
 // global node offsets along axis k of the local indices a = 0..P of the
-// element with (possibly out-of-range, periodic) coordinate ek
+// element with periodic coordinate ek in [-n, 2n) (a neighbour's at most one
+// period out of range)
 template <int P>
 __device__ inline void axis_offsets(int ek, int k, const MeshArgs& m, int* off) {
   const int n = m.n[k], L = m.L[k];
-  ek = (ek % n + n) % n;
+  if (ek < 0) ek += n;
+  else if (ek >= n) ek -= n;
   const int s = (int)node_stride(k, m);      // node ids are below 2^31
 #pragma unroll
   for (int a = 0; a <= P; ++a) {
@@ -479,7 +481,8 @@ template <int P, int RE, class LD, class V>
 __device__ __forceinline__ void line_run(const V* __restrict__ wg, const LD& ld, V* acc) {
   constexpr int R = P * RE, S = LineTapsV<P, V>::S, NB = S / R;
   // the weights are block-uniform: read through the constant address space
-  // (scalar loads, SGPR operands of the FMAs)
+  // (scalar loads, SGPR operands of the FMAs; staging them in LDS instead
+  // measured slower)
   typedef const V __attribute__((address_space(4))) CV;
   const CV* w = (const CV*)wg;
   V win[2 * R];
@@ -514,12 +517,31 @@ __host__ __device__ constexpr int line_row_len(int L) {
   return L + LineTapsV<P, V>::S + kLineMaxRE * P;
 }
 
-// lines per block of the axis-0 kernels: up to cap LDS values per block, and
-// about two lines' worth of runs per thread at most
+// LDS slot of row position k when the row is read in runs of R: one unused
+// slot after every R values when R is even, so that lanes reading runs R
+// apart have an odd stride and fall in different LDS banks.  For s a
+// multiple of R, lds_slot(s + j) = lds_slot(s) + lds_slot(j).
+template <int R>
+__host__ __device__ constexpr int lds_slot(int k) {
+  return (R % 2 == 0) ? k + k / R : k;
+}
+
+// row pitch in LDS slots: enough for every run length the axis-0 kernels use
+// (R = P or 2P)
 template <int P, class V>
-__host__ __device__ inline int line_rows_per_block(int L, int64_t nlines, int cap) {
-  const int per = cap / line_row_len<P, V>(L);
-  const int64_t want = (nlines + 511) / 512;
+__host__ __device__ constexpr int line_row_pitch(int L) {
+  return line_row_len<P, V>(L) + line_row_len<P, V>(L) / (P % 2 == 0 ? P : 2 * P) + 1;
+}
+
+// lines per block of the axis-0 kernels (runs of R outputs): up to cap LDS
+// slots per block; enough lines for a run per thread of a 256-thread block,
+// and more on meshes with many lines (at most 512 blocks)
+template <int P, class V>
+__host__ __device__ inline int line_rows_per_block(int L, int64_t nlines, int cap, int R) {
+  const int per = cap / line_row_pitch<P, V>(L);
+  const int64_t runs = (L + R - 1) / R;
+  int64_t want = (nlines + 511) / 512;
+  if (want * runs < 256) want = (256 + runs - 1) / runs;
   return per < 1 ? 1 : (int)(want < per ? (want < 1 ? 1 : want) : per);
 }
 
@@ -537,22 +559,34 @@ __device__ __forceinline__ int line_wrap(int k, int W, int L) {
 template <int P, int RE, class TI, class TO>
 __device__ __forceinline__ void k_line_x_body(const LineFastArgs& a, int bx) {
   constexpr int W = LineTapsV<P, TO>::W, R = P * RE;
+  static_assert(R % 2 == 1 || R >= (P % 2 == 0 ? P : 2 * P), "row pitch too short for this run length");
   const int L = a.L;
   TO* sm = reinterpret_cast<TO*>(cem_smem);
   const int64_t t0 = (int64_t)bx * a.nlb;
   const int nl = (int)min((int64_t)a.nlb, a.ntrans - t0);
   const TI* src = static_cast<const TI*>(a.in) + t0 * L;   // lines of axis 0 are contiguous
-  const int LS = line_row_len<P, TO>(L);
-  for (int i = threadIdx.x; i < nl * LS; i += blockDim.x) {
-    const int line = i / LS;
-    sm[i] = (TO)src[line * L + line_wrap(i - line * LS, W, L)];
+  const int LS = line_row_len<P, TO>(L), LP = line_row_pitch<P, TO>(L);
+  // four values per thread and pass: the loads are issued before the stores
+  const int nv = nl * LS, nt = (int)blockDim.x;
+  for (int i0 = threadIdx.x; i0 < nv; i0 += 4 * nt) {
+    TO v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k * nt, line = i / LS;
+      v[k] = i < nv ? (TO)src[line * L + line_wrap(i - line * LS, W, L)] : (TO)0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k * nt, line = i / LS;
+      if (i < nv) sm[line * LP + lds_slot<R>(i - line * LS)] = v[k];
+    }
   }
   __syncthreads();
   const int runs = (L + R - 1) / R;
   for (int g = threadIdx.x; g < nl * runs; g += blockDim.x) {
     const int line = g / runs, s = (g - line * runs) * R;
-    const TO* row = sm + line * LS + s;
-    auto ld = [&](int j) { return row[j]; };
+    const TO* row = sm + line * LP + lds_slot<R>(s);
+    auto ld = [&](int j) { return row[lds_slot<R>(j)]; };
     TO acc[R];
     line_run<P, RE>(static_cast<const TO*>(a.w), ld, acc);
     TO* dst = static_cast<TO*>(a.out) + (t0 + line) * L;
@@ -608,7 +642,21 @@ __device__ __forceinline__ void k_line_y_body(const LineFastArgs& a, int bx, int
   if (p < 0) p += L;
   p += rg;
   if (p >= L) p -= L;
-  for (int row = rg; row < ROWS; row += 8) {
+  // eight rows per pass: the loads are issued before the first LDS store
+  int row = rg;
+  for (; row + 56 < ROWS; row += 64) {
+    TO v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      v[k] = have ? (TO)in[b + (int64_t)p * sl] : (TO)0;
+      p += 8;
+      if (p >= L) p -= L;
+      if (p >= L) p -= L;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sm[(row + 8 * k) * kTileX + tx] = v[k];
+  }
+  for (; row < ROWS; row += 8) {
     sm[row * kTileX + tx] = have ? (TO)in[b + (int64_t)p * sl] : (TO)0;
     p += 8;
     if (p >= L) p -= L;
@@ -667,30 +715,50 @@ __global__ void __launch_bounds__(256) k_line_multi(MultiLineArgs m) {
 // step 1 of the algorithm: element loop (WENO sensor, viscosity, residual)
 // plus the facet data of step 3 (f^H, f^L, lambda, dt_e, low-order average)
 // ---------------------------------------------------------------------------
-// minimum of dt_e over the 128 threads of a block (threads past the last
+// Reductions over a wave (64 lanes, every lane gets the result) and over a
+// block (one LDS slot per wave, one barrier); min and integer sums are exact,
+// so the order of the combination does not matter
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// minimum of v over the NT threads of a block, returned to every thread;
+// every thread of the block must call it, once per kernel
+template <int NT>
+__device__ __forceinline__ double block_min(double v) {
+  constexpr int NW = NT / 64;
+  static_assert(NT % 64 == 0 && NW >= 1, "block of whole waves");
+  __shared__ double red[NW];
+  v = wave_min(v);
+  if constexpr (NW == 1) {
+    return v;
+  } else {
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = red[0];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) m = fmin(m, red[k]);
+    return m;
+  }
+}
+
+// minimum of dt_e over the NT threads of a block (threads past the last
 // element contribute +inf) written to part[bx] (bx: the block's index)
 template <int NT>
 __device__ inline void block_min_dt_n(double* part, double v, int bx) {
-  __shared__ double red[NT];
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[bx] = red[0];
+  const double m = block_min<NT>(v);
+  if (threadIdx.x == 0) part[bx] = m;
 }
 
-__device__ inline void block_min_dt(double* part, double v, int bx) {
-  __shared__ double red[128];
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = 64; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[bx] = red[0];
-}
+__device__ inline void block_min_dt(double* part, double v, int bx) { block_min_dt_n<128>(part, v, bx); }
 
 
 // f(integral constant K) for K = 0 .. N-1: a loop whose index is a
@@ -1498,19 +1566,47 @@ __device__ __forceinline__ void tile_stage(const StageArgs& a, int ex0, int ey0)
   int X0 = P * (ex0 - 1), Y0 = P * (ey0 - 1);
   if (X0 < 0) X0 += L0;
   if (Y0 < 0) Y0 += L1;
-  for (int q = threadIdx.x; q < M * TT::NXY; q += blockDim.x) {
-    const int c = q / TT::NXY, r = q - c * TT::NXY, iy = r / TT::NX, ix = r - iy * TT::NX;
-    const int gx = (X0 + ix) % L0, gy = (Y0 + iy) % L1;
-    cem_smem[q] = a.u[c * ms.N + gx + (int64_t)L0 * gy];
+  // four values per thread and pass, loads issued before the LDS stores;
+  // periodic wrap by subtraction (tile offsets are below 2 L on all but the
+  // smallest meshes)
+  const int nt = (int)blockDim.x;
+  auto wrap = [](int x, int L) {
+    while (x >= L) x -= L;
+    return x;
+  };
+  for (int q0 = threadIdx.x; q0 < M * TT::NXY; q0 += 4 * nt) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int q = q0 + k * nt;
+      if (q < M * TT::NXY) {
+        const int c = q / TT::NXY, r = q - c * TT::NXY, iy = r / TT::NX, ix = r - iy * TT::NX;
+        const int gx = wrap(X0 + ix, L0), gy = wrap(Y0 + iy, L1);
+        v[k] = a.u[c * ms.N + gx + (int64_t)L0 * gy];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (q0 + k * nt < M * TT::NXY) cem_smem[q0 + k * nt] = v[k];
   }
   if constexpr (TT::stage_g) {
     double* gs = cem_smem + M * TT::NXY;
-    for (int q = threadIdx.x; q < 2 * M * TT::GXY; q += blockDim.x) {
-      const int kc = q / TT::GXY, r = q - kc * TT::GXY, iy = r / TT::GX, ix = r - iy * TT::GX;
-      const int gx = (P * ex0 + ix) % L0, gy = (P * ey0 + iy) % L1;
-      const int64_t gi = (int64_t)kc * ms.N + gx + (int64_t)L0 * gy;
-      if constexpr (sizeof(RT) == 4) gs[q] = a.g32[gi];
-      else gs[q] = a.g[gi];
+    for (int q0 = threadIdx.x; q0 < 2 * M * TT::GXY; q0 += 4 * nt) {
+      double v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int q = q0 + k * nt;
+        if (q < 2 * M * TT::GXY) {
+          const int kc = q / TT::GXY, r = q - kc * TT::GXY, iy = r / TT::GX, ix = r - iy * TT::GX;
+          const int gx = wrap(P * ex0 + ix, L0), gy = wrap(P * ey0 + iy, L1);
+          const int64_t gi = (int64_t)kc * ms.N + gx + (int64_t)L0 * gy;
+          if constexpr (sizeof(RT) == 4) v[k] = a.g32[gi];
+          else v[k] = a.g[gi];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (q0 + k * nt < 2 * M * TT::GXY) gs[q0 + k * nt] = v[k];
     }
   }
   __syncthreads();
@@ -1646,9 +1742,9 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
   for (int k = 0; k < D; ++k) {
     if (a.flux_mode != 0) break;
     int en[3] = {ei[0], ei[1], ei[2]};
-    en[k] = (ei[k] + ms.n[k] - 1) % ms.n[k];
+    en[k] = ei[k] == 0 ? ms.n[k] - 1 : ei[k] - 1;
     const int64_t elo = elem_id(en, ms);
-    en[k] = (ei[k] + 1) % ms.n[k];
+    en[k] = ei[k] + 1 == ms.n[k] ? 0 : ei[k] + 1;
     const int64_t ehi = elem_id(en, ms);
     double fb[M];
     limit_facet<D, PH>(a, k, elo, e, fb);
@@ -1850,7 +1946,7 @@ __device__ inline int node_elements(int64_t i, const MeshArgs& m, int64_t* eids,
     const int e0 = ik[k] / P, a0 = ik[k] % P;
     if (a0 == 0) {
       cnt[k] = 2;
-      ek[k][0] = (e0 + m.n[k] - 1) % m.n[k];   // lower element sees it at a = P
+      ek[k][0] = e0 == 0 ? m.n[k] - 1 : e0 - 1;   // lower element sees it at a = P
       ak[k][0] = P;
       ek[k][1] = e0;
       ak[k][1] = 0;
@@ -1921,16 +2017,9 @@ __device__ inline void stage_dt_record(const StageArgs& a, double mn) {
 
 __device__ inline double stage_dt(const StageArgs& a, int bx) {
   if (a.dt_ready) return a.dtbuf[0];       // reduced by k_stage_dt (uniform branch)
-  __shared__ double red[256];
   double m = 1.0e300;
-  for (int j = threadIdx.x; j < a.ndtpart; j += blockDim.x) m = fmin(m, a.dtpart[j]);
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  const double mn = red[0];
+  for (int j = threadIdx.x; j < a.ndtpart; j += 256) m = fmin(m, a.dtpart[j]);
+  const double mn = block_min<256>(m);
   if (bx == 0 && threadIdx.x == 0) stage_dt_record(a, mn);
   return a.stage == 0 ? (a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl * mn) : a.dtbuf[0];
 }
@@ -1940,15 +2029,32 @@ __device__ __forceinline__ void k_update_body(const StageArgs& a, int bx) {
   constexpr int M = Phys<D, PH>::M;
   constexpr bool SCALAR = PH != EUL;
   constexpr int NL = ipow(P + 1, D);
-  __shared__ int red[2][256];
-  const double dt = stage_dt(a, bx);      // every thread of the block
+  __shared__ int red[2][4];
   const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
-  int nclamp = 0, nbad = 0;
-  if (i < a.mesh.N) {
+  const bool live = i < a.mesh.N;
+  const int64_t E = a.mesh.E, N = a.mesh.N;
+  // the node's data is read first, so that its loads overlap the reduction
+  // of the time step
+  double ssum[M], uin[M], ubase[M];
+  int nrec = 0;
+  if (live) {
     int64_t eids[8];
     int locs[8];
-    const int nrec = node_elements<D, P>(i, a.mesh, eids, locs);
-    const int64_t E = a.mesh.E, N = a.mesh.N;
+    nrec = node_elements<D, P>(i, a.mesh, eids, locs);
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      double s = 0.0;
+      #pragma unroll
+      for (int t = 0; t < (1 << D); ++t)    // constant indices into eids / locs
+        if (t < nrec) s += a.relem[((int64_t)c * NL + locs[t]) * E + eids[t]];
+      ssum[c] = s;
+      uin[c] = a.u[c * N + i];
+      ubase[c] = (a.rk_a == 0.0) ? 0.0 : a.u0[c * N + i];
+    }
+  }
+  const double dt = stage_dt(a, bx);      // every thread of the block (256)
+  int nclamp = 0, nbad = 0;
+  if (live) {
     double hd = 1.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) hd *= a.mesh.h;
@@ -1956,14 +2062,11 @@ __device__ __forceinline__ void k_update_body(const StageArgs& a, int bx) {
     double vout[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      double s = 0.0;
-      #pragma unroll
-      for (int t = 0; t < (1 << D); ++t)    // constant indices into eids / locs
-        if (t < nrec) s += a.relem[((int64_t)c * NL + locs[t]) * E + eids[t]];
-      const double ui = a.u[c * N + i];
+      const double s = ssum[c];
+      const double ui = uin[c];
       if (a.copy_base) a.u0[c * N + i] = ui;
       const double ufe = ui + dt / mi * s;
-      double v = (a.rk_a == 0.0) ? ufe : a.rk_a * a.u0[c * N + i] + a.rk_b * ufe;
+      double v = (a.rk_a == 0.0) ? ufe : a.rk_a * ubase[c] + a.rk_b * ufe;
       if (SCALAR) {
         // round-off excess is clamped and counted; larger excursions (only
         // possible with a limiter switched off) are kept and counted
@@ -1984,19 +2087,19 @@ __device__ __forceinline__ void k_update_body(const StageArgs& a, int bx) {
       for (int q = 0; q < D * M; ++q) a.fnode[q * N + i] = f[q];
     }
   }
-  red[0][threadIdx.x] = nclamp;
-  red[1][threadIdx.x] = nbad;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + s];
-      red[1][threadIdx.x] += red[1][threadIdx.x + s];
-    }
-    __syncthreads();
+  // per-block counters, touched only when this stage counted something
+  nclamp = wave_sum(nclamp);
+  nbad = wave_sum(nbad);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = nclamp;
+    red[1][threadIdx.x >> 6] = nbad;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    a.counts[2 * bx] += red[0][0];
-    a.counts[2 * bx + 1] += red[1][0];
+    const int c0 = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const int c1 = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    if (c0 != 0) a.counts[2 * bx] += c0;
+    if (c1 != 0) a.counts[2 * bx + 1] += c1;
   }
 }
 
@@ -2024,16 +2127,10 @@ __global__ void __launch_bounds__(256) k_nodal_flux(StageArgs a) {
 // when there are many per-block minima (k_update then reads dtbuf[0] instead
 // of every block reducing all of them itself)
 __global__ void __launch_bounds__(1024) k_stage_dt(StageArgs a) {
-  __shared__ double red[1024];
   double m = 1.0e300;
-  for (int j = threadIdx.x; j < a.ndtpart; j += blockDim.x) m = fmin(m, a.dtpart[j]);
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) stage_dt_record(a, red[0]);
+  for (int j = threadIdx.x; j < a.ndtpart; j += 1024) m = fmin(m, a.dtpart[j]);
+  const double mn = block_min<1024>(m);
+  if (threadIdx.x == 0) stage_dt_record(a, mn);
 }
 
 // Residual assembly fused with the first mass-solve pass (axis 0): a block
@@ -2050,7 +2147,8 @@ __device__ __forceinline__ void k_gather_line_x_body(const StageArgs& sa, const 
   const int nl = (int)min((int64_t)a.nlb, a.ntrans - t0);
   const int64_t E = sa.mesh.E, N = sa.mesh.N;
   const int lpc = (int)(N / L);                  // lines per component
-  const int LS = line_row_len<P, RT>(L);
+  const int LS = line_row_len<P, RT>(L), LP = line_row_pitch<P, RT>(L);
+  static_assert(R % 2 == 1 || R >= (P % 2 == 0 ? P : 2 * P), "row pitch too short for this run length");
   for (int q = threadIdx.x; q < nl * L; q += blockDim.x) {
     const int ql = q / L, x = q - ql * L;
     const int line = (int)t0 + ql, c = line / lpc;
@@ -2063,7 +2161,7 @@ __device__ __forceinline__ void k_gather_line_x_body(const StageArgs& sa, const 
     #pragma unroll
     for (int t = 0; t < (1 << D); ++t)    // constant indices into eids / locs
       if (t < nrec) s += sa.relem[(c * NL + locs[t]) * E + eids[t]];
-    sm[ql * LS + W + x] = (RT)s;
+    sm[ql * LP + lds_slot<R>(W + x)] = (RT)s;
     rr[g] = (RT)s;
   }
   __syncthreads();
@@ -2071,14 +2169,14 @@ __device__ __forceinline__ void k_gather_line_x_body(const StageArgs& sa, const 
   for (int q = threadIdx.x; q < nl * (LS - L); q += blockDim.x) {
     const int ql = q / (LS - L), h = q - ql * (LS - L);
     const int k = h < W ? h : L + h;
-    sm[ql * LS + k] = sm[ql * LS + W + line_wrap(k, W, L)];
+    sm[ql * LP + lds_slot<R>(k)] = sm[ql * LP + lds_slot<R>(W + line_wrap(k, W, L))];
   }
   __syncthreads();
   const int runs = (L + R - 1) / R;
   for (int g = threadIdx.x; g < nl * runs; g += blockDim.x) {
     const int line = g / runs, s = (g - line * runs) * R;
-    const RT* row = sm + line * LS + s;
-    auto ld = [&](int j) { return row[j]; };
+    const RT* row = sm + line * LP + lds_slot<R>(s);
+    auto ld = [&](int j) { return row[lds_slot<R>(j)]; };
     RT acc[R];
     line_run<P, RE>(static_cast<const RT*>(a.w), ld, acc);
     RT* dst = static_cast<RT*>(a.out) + (t0 + line) * L;

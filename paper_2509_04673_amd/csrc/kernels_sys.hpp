@@ -584,9 +584,9 @@ __device__ __forceinline__ void k_elem2_sys_body(const StageArgs& a, int bx) {
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     int en[3] = {ns.ei[0], ns.ei[1], ns.ei[2]};
-    en[k] = (ns.ei[k] + ms.n[k] - 1) % ms.n[k];
+    en[k] = ns.ei[k] == 0 ? ms.n[k] - 1 : ns.ei[k] - 1;
     enb[2 * k] = elem_id(en, ms);
-    en[k] = (ns.ei[k] + 1) % ms.n[k];
+    en[k] = ns.ei[k] + 1 == ms.n[k] ? 0 : ns.ei[k] + 1;
     enb[2 * k + 1] = elem_id(en, ms);
   }
 
