@@ -261,10 +261,13 @@ void launch_line_fast(cem_ctx* c, int id, LineFastArgs la, hipStream_t st) {
     return;
   }
   if (la.axis > 0) {
-    const int RE = 1, R = P * RE, TY = 8 * R * la.ky;
+    const int R = P * la.re, TY = 8 * R * la.ky;
     const size_t lds = (size_t)(TY + LineTapsV<P, TO>::S) * kTileX * sizeof(TO);
     dim3 grid(nblocks(la.ntrans, kTileX), (unsigned)((la.L + TY - 1) / TY));
-    CEM_LAUNCH(c, id, (k_line_y<P, 1, TI, TO>), grid, 256, lds, st, la);
+    if (la.re == 2)
+      CEM_LAUNCH(c, id, (k_line_y<P, 2, TI, TO>), grid, 256, lds, st, la);
+    else
+      CEM_LAUNCH(c, id, (k_line_y<P, 1, TI, TO>), grid, 256, lds, st, la);
     return;
   }
   // longest run that still gives >= 2^17 threads (2 waves per SIMD)
@@ -338,8 +341,9 @@ StageArgs make_args(const cem_ctx* c) {
 
 // line operator arguments; weights of the output type (float copies in the
 // mixed-precision form)
+// wide: the strided kernel may take runs of 2P (single-problem launches)
 template <class TO>
-LineFastArgs line_args(const cem_ctx* c, const void* in, void* out, int axis, bool grad) {
+LineFastArgs line_args(const cem_ctx* c, const void* in, void* out, int axis, bool grad, bool wide = true) {
   LineFastArgs la{};
   la.in = in;
   la.out = out;
@@ -355,7 +359,14 @@ LineFastArgs line_args(const cem_ctx* c, const void* in, void* out, int axis, bo
   la.N = c->N;
   la.NT = c->N / c->L[axis];
   la.ntrans = (int64_t)c->m * la.NT;
-  la.ky = axis > 0 ? line_y_runs(la.ntrans, la.L, c->p) : 1;
+  la.re = 1;
+  la.ky = 1;
+  if (axis > 0) {
+    const int W = sizeof(TO) == 4 ? kWfast32[c->p] : kWfast[c->p];
+    const int S = sizeof(TO) == 4 ? kSfast32[c->p] : kSfast[c->p];
+    if (wide) la.re = line_y_re(la.ntrans, la.L, c->p, W);
+    la.ky = line_y_runs(la.ntrans, la.L, c->p * la.re, S, (int)sizeof(TO));
+  }
   return la;
 }
 
@@ -448,12 +459,16 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   bool multi = D >= 2 && c->L[0] <= 4096;
   for (int k = 0; k < D; ++k) multi = multi && c->tabs.kgrad[k].wfast > 0;
   if (multi) {
-    constexpr int W = LineTapsV<P, RT>::W, S = LineTapsV<P, RT>::S, TY = 8 * P;
+    constexpr int W = LineTapsV<P, RT>::W, S = LineTapsV<P, RT>::S;
     MultiLineArgs ml{};
     ml.naxes = D;
+    // one run length for all strided axes (a template argument of the launch)
+    bool wide = true;
+    for (int k = 1; k < D; ++k) wide = wide && line_args<RT>(c, c->u, g, k, true).re == 2;
+    const int TY = 8 * P * (wide ? 2 : 1);
     size_t lds = (size_t)(TY + S) * kTileX * sizeof(RT);
     for (int k = 0; k < D; ++k) {
-      LineFastArgs la = line_args<RT>(c, c->u, g + (int64_t)k * M * c->N, k, true);
+      LineFastArgs la = line_args<RT>(c, c->u, g + (int64_t)k * M * c->N, k, true, wide);
       if (k == 0) {
         la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 2048, la.L >= 2 * P + 2 * W ? 2 * P : P);
         ml.nb[0] = (int)((la.ntrans + la.nlb - 1) / la.nlb);
@@ -468,10 +483,15 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     }
     int nb = 0;
     for (int k = 0; k < D; ++k) nb += ml.nb[k];
-    if (c->L[0] >= 2 * P + 2 * W)
-      CEM_LAUNCH(c, 0, (k_line_multi<P, 2, double, RT>), nb, 256, lds, c->stream, ml);
+    const bool rex = c->L[0] >= 2 * P + 2 * W;
+    if (rex && wide)
+      CEM_LAUNCH(c, 0, (k_line_multi<P, 2, 2, double, RT>), nb, 256, lds, c->stream, ml);
+    else if (rex)
+      CEM_LAUNCH(c, 0, (k_line_multi<P, 2, 1, double, RT>), nb, 256, lds, c->stream, ml);
+    else if (wide)
+      CEM_LAUNCH(c, 0, (k_line_multi<P, 1, 2, double, RT>), nb, 256, lds, c->stream, ml);
     else
-      CEM_LAUNCH(c, 0, (k_line_multi<P, 1, double, RT>), nb, 256, lds, c->stream, ml);
+      CEM_LAUNCH(c, 0, (k_line_multi<P, 1, 1, double, RT>), nb, 256, lds, c->stream, ml);
     HIPCHK(hipGetLastError());
   } else {
     for (int k = 0; k < D; ++k) {
@@ -619,7 +639,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
       const void* in = src_of(c);
       void* out_p = dst_of(c);
       if (K.wfast > 0) {
-        LineFastArgs a = line_args<RT>(c, in, out_p, k, grad);
+        LineFastArgs a = line_args<RT>(c, in, out_p, k, grad, false);
         if (k == 0) {
           if (a.L > 4096) return fail(CEM_EINVAL, "batched form: x-lines longer than 4096 nodes");
           a.nlb = line_rows_per_block<P, RT>(a.L, a.ntrans, b->xlines_cap, P);

@@ -410,6 +410,7 @@ struct LineFastArgs {
   int nlb;                 // lines per block (axis 0 LDS kernel)
   int gx;                  // blocks across lines of a 2D grid (batched launches)
   int ky;                  // runs per thread of the strided kernel (tile length 8 R ky)
+  int re;                  // run length R = P re of the strided kernel (1 or 2)
 };
 
 template <int P, int RE, class TI, class TO>
@@ -608,11 +609,22 @@ constexpr int kTileX = 32;
 // Longer tiles re-read less of the 2W halo: a thread computes ky runs
 // (rows rg + 8 q, q < ky), the tile covers TY = 8 R ky outputs per line.
 // ky: the longest tile that still leaves >= 2048 blocks for one problem.
-inline int line_y_runs(int64_t ntrans, int L, int R) {
-  const int64_t gx = (ntrans + kTileX - 1) / kTileX;
+inline int64_t line_y_blocks(int64_t ntrans, int L, int R, int ky) {
+  return (ntrans + kTileX - 1) / kTileX * ((L + 8 * R * ky - 1) / (8 * R * ky));
+}
+
+// (and whose tile fits 40 KB of LDS, four blocks per CU)
+inline int line_y_runs(int64_t ntrans, int L, int R, int S, int vbytes) {
   for (int ky = 4; ky > 1; ky /= 2)
-    if (gx * ((L + 8 * R * ky - 1) / (8 * R * ky)) >= 2048) return ky;
+    if (line_y_blocks(ntrans, L, R, ky) >= 2048 && (8 * R * ky + S) * kTileX * vbytes <= 40960) return ky;
   return 1;
+}
+
+// Run length of the strided kernel: runs of 2P outputs halve the LDS reads
+// per output (the window of a run is R + S inputs), at half the threads, so
+// they are taken only where 2048 blocks remain
+inline int line_y_re(int64_t ntrans, int L, int P, int W) {
+  return (L >= 2 * P + 2 * W && line_y_blocks(ntrans, L, 2 * P, 1) >= 2048) ? 2 : 1;
 }
 
 template <int P, int RE, class TI, class TO>
@@ -694,7 +706,7 @@ struct MultiLineArgs {
   int naxes;
 };
 
-template <int P, int REX, class TI, class TO>
+template <int P, int REX, int REY, class TI, class TO>
 __global__ void __launch_bounds__(256) k_line_multi(MultiLineArgs m) {
   int b = blockIdx.x;
   if (b < m.nb[0]) {
@@ -704,7 +716,7 @@ __global__ void __launch_bounds__(256) k_line_multi(MultiLineArgs m) {
   b -= m.nb[0];
   for (int k = 1; k < m.naxes; ++k) {
     if (b < m.nb[k]) {
-      k_line_y_body<P, 1, TI, TO>(m.a[k], b % m.a[k].gx, b / m.a[k].gx);
+      k_line_y_body<P, REY, TI, TO>(m.a[k], b % m.a[k].gx, b / m.a[k].gx);
       return;
     }
     b -= m.nb[k];
