@@ -113,6 +113,7 @@ enum BKind { B_LINE, B_LINE_X, B_LINE_Y, B_ELEM1_TILE, B_ELEM1_TILE2, B_ELEM1_SY
 struct BLaunch {
   int kind = 0;
   bool grad = false;       // line kernels: float64 input (u) rather than RT
+  int re = 1;              // line kernels: runs of re P outputs
   int nprob = 0, blocks = 0;
   size_t lds = 0;
   size_t o_first = 0, o_args = 0, o_args2 = 0;   // byte offsets in the plan region
@@ -251,10 +252,11 @@ void launch_line_fast(cem_ctx* c, int id, LineFastArgs la, hipStream_t st) {
   constexpr int W = LineTapsV<P, TO>::W;
   if (la.axis == 0 && la.L <= 4096) {
     // whole lines in LDS; one line per block unless lines are short
-    la.nlb = line_rows_per_block<P, TO>(la.L, la.ntrans, 2048, la.L >= 2 * P + 2 * W ? 2 * P : P);
+    const int re = la.L >= 2 * P + 2 * W ? 2 : 1;
+    la.nlb = line_rows_per_block<P, TO>(la.L, la.ntrans, 4096, re * P);
     const size_t lds = (size_t)la.nlb * line_row_pitch<P, TO>(la.L) * sizeof(TO);
     const unsigned grid = (unsigned)((la.ntrans + la.nlb - 1) / la.nlb);
-    if (la.L >= 2 * P + 2 * W)
+    if (re == 2)
       CEM_LAUNCH(c, id, (k_line_x<P, 2, TI, TO>), grid, 256, lds, st, la);
     else
       CEM_LAUNCH(c, id, (k_line_x<P, 1, TI, TO>), grid, 256, lds, st, la);
@@ -466,11 +468,13 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     bool wide = true;
     for (int k = 1; k < D; ++k) wide = wide && line_args<RT>(c, c->u, g, k, true).re == 2;
     const int TY = 8 * P * (wide ? 2 : 1);
+    // axis 0: runs of 2P where the lines allow (4P measured slower)
+    const int rex = c->L[0] >= 2 * P + 2 * W ? 2 : 1;
     size_t lds = (size_t)(TY + S) * kTileX * sizeof(RT);
     for (int k = 0; k < D; ++k) {
       LineFastArgs la = line_args<RT>(c, c->u, g + (int64_t)k * M * c->N, k, true, wide);
       if (k == 0) {
-        la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 2048, la.L >= 2 * P + 2 * W ? 2 * P : P);
+        la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 4096, rex * P);
         ml.nb[0] = (int)((la.ntrans + la.nlb - 1) / la.nlb);
         lds = std::max(lds, (size_t)la.nlb * line_row_pitch<P, RT>(la.L) * sizeof(RT));
       } else {
@@ -483,10 +487,9 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     }
     int nb = 0;
     for (int k = 0; k < D; ++k) nb += ml.nb[k];
-    const bool rex = c->L[0] >= 2 * P + 2 * W;
-    if (rex && wide)
+    if (rex == 2 && wide)
       CEM_LAUNCH(c, 0, (k_line_multi<P, 2, 2, double, RT>), nb, 256, lds, c->stream, ml);
-    else if (rex)
+    else if (rex == 2)
       CEM_LAUNCH(c, 0, (k_line_multi<P, 2, 1, double, RT>), nb, 256, lds, c->stream, ml);
     else if (wide)
       CEM_LAUNCH(c, 0, (k_line_multi<P, 1, 2, double, RT>), nb, 256, lds, c->stream, ml);
@@ -531,10 +534,15 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   int k0 = 0;
   if (c->tabs.kmass[0].wfast > 0 && c->L[0] <= 4096) {
     LineFastArgs la = line_args<RT>(c, r, D == 1 ? udot : tmp, 0, false);
-    la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 2048, P);
+    constexpr int W = LineTapsV<P, RT>::W;
+    const int re = line_x_re(la.ntrans, la.L, P, W, 1, 2);
+    la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 4096, re * P);
     const size_t lds = (size_t)la.nlb * line_row_pitch<P, RT>(la.L) * sizeof(RT);
     const unsigned grid = (unsigned)((la.ntrans + la.nlb - 1) / la.nlb);
-    CEM_LAUNCH(c, 3, (k_gather_line_x<D, P, M, 1, RT>), grid, 256, lds, c->stream, a, la);
+    if (re == 2)
+      CEM_LAUNCH(c, 3, (k_gather_line_x<D, P, M, 2, RT>), grid, 256, lds, c->stream, a, la);
+    else
+      CEM_LAUNCH(c, 3, (k_gather_line_x<D, P, M, 1, RT>), grid, 256, lds, c->stream, a, la);
     HIPCHK(hipGetLastError());
     src = D == 1 ? udot : tmp;
     k0 = 1;
@@ -629,29 +637,41 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
   // one line pass of every problem (axis k), grouped by kernel variant
   auto lines = [&](std::vector<BLaunch>& out, const std::vector<cem_ctx*>& probs, bool grad, int k, auto src_of,
                    auto dst_of) -> cem_status {
-    Group gx, gy, gg;
-    gx.l.kind = B_LINE_X;
-    gy.l.kind = B_LINE_Y;
+    // runs of 2P wherever the line allows (the whole batch fills the chip,
+    // so the strided tiles are as long as 40 KB of LDS allows)
+    Group gx[2], gy[2], gg;
+    for (int v = 0; v < 2; ++v) {
+      gx[v].l.kind = B_LINE_X;
+      gy[v].l.kind = B_LINE_Y;
+      gx[v].l.re = gy[v].l.re = v + 1;
+      gx[v].l.grad = gy[v].l.grad = grad;
+    }
     gg.l.kind = B_LINE;
-    gx.l.grad = gy.l.grad = gg.l.grad = grad;
+    gg.l.grad = grad;
     for (cem_ctx* c : probs) {
       const LineKernel& K = grad ? c->tabs.kgrad[k] : c->tabs.kmass[k];
       const void* in = src_of(c);
       void* out_p = dst_of(c);
       if (K.wfast > 0) {
         LineFastArgs a = line_args<RT>(c, in, out_p, k, grad, false);
+        const int re = a.L >= 2 * P + 2 * W ? 2 : 1;
         if (k == 0) {
           if (a.L > 4096) return fail(CEM_EINVAL, "batched form: x-lines longer than 4096 nodes");
-          a.nlb = line_rows_per_block<P, RT>(a.L, a.ntrans, b->xlines_cap, P);
-          gx.lf.push_back(a);
-          gx.first.push_back(gx.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
-          gx.l.lds = std::max(gx.l.lds, (size_t)a.nlb * line_row_pitch<P, RT>(a.L) * sizeof(RT));
+          a.nlb = line_rows_per_block<P, RT>(a.L, a.ntrans, b->xlines_cap, re * P);
+          Group& G = gx[re - 1];
+          G.lf.push_back(a);
+          G.first.push_back(G.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
+          G.l.lds = std::max(G.l.lds, (size_t)a.nlb * line_row_pitch<P, RT>(a.L) * sizeof(RT));
         } else {
-          const int TY = 8 * P * a.ky;
+          a.re = re;
+          a.ky = 1;
+          while (a.ky < 4 && (8 * P * re * 2 * a.ky + S) * kTileX * (int)sizeof(RT) <= 40960) a.ky *= 2;
+          const int TY = 8 * P * re * a.ky;
           a.gx = (int)nblocks(a.ntrans, kTileX);
-          gy.lf.push_back(a);
-          gy.first.push_back(gy.first.back() + a.gx * ((a.L + TY - 1) / TY));
-          gy.l.lds = std::max(gy.l.lds, (size_t)(TY + S) * kTileX * sizeof(RT));
+          Group& G = gy[re - 1];
+          G.lf.push_back(a);
+          G.first.push_back(G.first.back() + a.gx * ((a.L + TY - 1) / TY));
+          G.l.lds = std::max(G.l.lds, (size_t)(TY + S) * kTileX * sizeof(RT));
         }
       } else {
         LineArgs a{};
@@ -672,9 +692,10 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         gg.first.push_back(gg.first.back() + (int)nblocks(a.total, 256));
       }
     }
-    (void)W;
-    close(gx, out);
-    close(gy, out);
+    for (int v = 0; v < 2; ++v) {
+      close(gx[v], out);
+      close(gy[v], out);
+    }
     close(gg, out);
     return CEM_OK;
   };
@@ -729,24 +750,30 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     }
     // assembly of r fused with the first mass pass where the x-lines allow it
     {
-      Group gf, gr;
-      gf.l.kind = B_GATHER_LX;
+      Group gf[2], gr;
+      for (int v = 0; v < 2; ++v) {
+        gf[v].l.kind = B_GATHER_LX;
+        gf[v].l.re = v + 1;
+      }
       gr.l.kind = B_GATHER_R;
       for (int q = 0; q < b->count; ++q) {
         cem_ctx* c = all[q];
         if (fused(c)) {
           LineFastArgs a = line_args<RT>(c, rbuf(c), mass_dst(c, 0), 0, false);
-          a.nlb = line_rows_per_block<P, RT>(a.L, a.ntrans, b->xlines_cap, P);
-          gf.sa.push_back(sa[q]);
-          gf.lf.push_back(a);
-          gf.first.push_back(gf.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
-          gf.l.lds = std::max(gf.l.lds, (size_t)a.nlb * line_row_pitch<P, RT>(a.L) * sizeof(RT));
+          const int re = a.L >= 2 * P + 2 * W ? 2 : 1;
+          a.nlb = line_rows_per_block<P, RT>(a.L, a.ntrans, b->xlines_cap, re * P);
+          Group& G = gf[re - 1];
+          G.sa.push_back(sa[q]);
+          G.lf.push_back(a);
+          G.first.push_back(G.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
+          G.l.lds = std::max(G.l.lds, (size_t)a.nlb * line_row_pitch<P, RT>(a.L) * sizeof(RT));
         } else {
           gr.sa.push_back(sa[q]);
           gr.first.push_back(gr.first.back() + (int)nblocks(c->N, 256));
         }
       }
-      close(gf, L);
+      close(gf[0], L);
+      close(gf[1], L);
       close(gr, L);
     }
     // remaining mass passes (axis 0 of the unfused problems, then axes >= 1)
@@ -807,12 +834,22 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
         else hipLaunchKernelGGL((kb_line<RT, RT>), g, dim3(256), 0, stream, la, mp);
         break;
       case B_LINE_X:
-        if (l.grad) hipLaunchKernelGGL((kb_line_x<P, 1, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
-        else hipLaunchKernelGGL((kb_line_x<P, 1, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        if (l.re == 2) {
+          if (l.grad) hipLaunchKernelGGL((kb_line_x<P, 2, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          else hipLaunchKernelGGL((kb_line_x<P, 2, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        } else {
+          if (l.grad) hipLaunchKernelGGL((kb_line_x<P, 1, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          else hipLaunchKernelGGL((kb_line_x<P, 1, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        }
         break;
       case B_LINE_Y:
-        if (l.grad) hipLaunchKernelGGL((kb_line_y<P, 1, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
-        else hipLaunchKernelGGL((kb_line_y<P, 1, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        if (l.re == 2) {
+          if (l.grad) hipLaunchKernelGGL((kb_line_y<P, 2, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          else hipLaunchKernelGGL((kb_line_y<P, 2, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        } else {
+          if (l.grad) hipLaunchKernelGGL((kb_line_y<P, 1, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          else hipLaunchKernelGGL((kb_line_y<P, 1, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        }
         break;
       case B_ELEM1_TILE:
         if constexpr (D == 2) hipLaunchKernelGGL((kb_elem1_tile<P, PH, true, RT>), g, dim3(128), l.lds, stream, sa, mp);
@@ -830,8 +867,12 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
           hipLaunchKernelGGL((kb_resid_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
         break;
       case B_GATHER_LX:
-        hipLaunchKernelGGL((kb_gather_line_x<D, P, M, 1, RT>), g, dim3(256), l.lds, stream, sa,
-                           reinterpret_cast<const LineFastArgs*>(base + l.o_args2), mp);
+        if (l.re == 2)
+          hipLaunchKernelGGL((kb_gather_line_x<D, P, M, 2, RT>), g, dim3(256), l.lds, stream, sa,
+                             reinterpret_cast<const LineFastArgs*>(base + l.o_args2), mp);
+        else
+          hipLaunchKernelGGL((kb_gather_line_x<D, P, M, 1, RT>), g, dim3(256), l.lds, stream, sa,
+                             reinterpret_cast<const LineFastArgs*>(base + l.o_args2), mp);
         break;
       case B_GATHER_R:
         hipLaunchKernelGGL((kb_gather_r<D, P, M, RT>), g, dim3(256), 0, stream, sa, mp);

@@ -534,15 +534,14 @@ __host__ __device__ constexpr int line_row_pitch(int L) {
   return line_row_len<P, V>(L) + line_row_len<P, V>(L) / (P % 2 == 0 ? P : 2 * P) + 1;
 }
 
-// lines per block of the axis-0 kernels (runs of R outputs): up to cap LDS
-// slots per block; enough lines for a run per thread of a 256-thread block,
-// and more on meshes with many lines (at most 512 blocks)
+// lines per block of the axis-0 kernels (runs of R outputs): enough lines
+// for a run per thread of a 256-thread block, up to cap LDS slots per block
 template <int P, class V>
 __host__ __device__ inline int line_rows_per_block(int L, int64_t nlines, int cap, int R) {
   const int per = cap / line_row_pitch<P, V>(L);
   const int64_t runs = (L + R - 1) / R;
-  int64_t want = (nlines + 511) / 512;
-  if (want * runs < 256) want = (256 + runs - 1) / runs;
+  int64_t want = (256 + runs - 1) / runs;
+  if (want > nlines) want = nlines;
   return per < 1 ? 1 : (int)(want < per ? (want < 1 ? 1 : want) : per);
 }
 
@@ -618,6 +617,14 @@ inline int line_y_runs(int64_t ntrans, int L, int R, int S, int vbytes) {
   for (int ky = 4; ky > 1; ky /= 2)
     if (line_y_blocks(ntrans, L, R, ky) >= 2048 && (8 * R * ky + S) * kTileX * vbytes <= 40960) return ky;
   return 1;
+}
+
+// Run length re P of the axis-0 kernels: the longest (re <= rmax) that keeps
+// 2^19 threads (longer runs read fewer LDS values per output), at least rmin
+inline int line_x_re(int64_t ntrans, int L, int P, int W, int rmin, int rmax) {
+  for (int re = rmax; re > rmin; re /= 2)
+    if (L >= re * P + 2 * W && ntrans * ((L + re * P - 1) / (re * P)) >= ((int64_t)1 << 19)) return re;
+  return rmin;
 }
 
 // Run length of the strided kernel: runs of 2P outputs halve the LDS reads
