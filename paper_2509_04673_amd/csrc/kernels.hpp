@@ -1649,8 +1649,12 @@ __device__ __forceinline__ void k_elem1_tile_body(const StageArgs& a, int bx) {
   block_min_dt(a.dtpart, dt_e, bx);     // every thread of the block reaches this
 }
 
+// two waves per SIMD up to Q2 (the 512-problem Q2 Euler batch: 8.3 -> 7.8 ms
+// per launch); Q3 keeps one (at two it spills: 512^2 Euler 0.34 -> 0.67 ms)
+#define CEM_TILE_BOUNDS __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(P <= 2 ? 2 : 1)))
+
 template <int P, int PH, bool WS, class RT>
-__global__ void __launch_bounds__(128) k_elem1_tile(StageArgs a) {
+__global__ void CEM_TILE_BOUNDS k_elem1_tile(StageArgs a) {
   k_elem1_tile_body<P, PH, WS, RT>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 

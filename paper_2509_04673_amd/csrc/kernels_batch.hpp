@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(256) kb_line_y(const LineFastArgs* __restrict_
 }
 
 template <int P, int PH, bool WS, class RT>
-__global__ void __launch_bounds__(128) kb_elem1_tile(const StageArgs* __restrict__ args, BatchMap m) {
+__global__ void CEM_TILE_BOUNDS kb_elem1_tile(const StageArgs* __restrict__ args, BatchMap m) {
   int lb;
   const int pid = batch_find(m, blockIdx.x, &lb);
   k_elem1_tile_body<P, PH, WS, RT>(args[pid], lb);
