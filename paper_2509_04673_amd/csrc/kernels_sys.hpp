@@ -516,10 +516,11 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
 }
 
 // pass 2: at least two waves per SIMD in float64 (the 2D pass fits three),
-// three in the mixed form (3D: 23.6 -> 20.9 ms per six launches; float64 at
-// three spills and slows, 22.7 -> 25.4)
+// three in the 3D mixed form (23.6 -> 20.9 ms per six launches; float64 at
+// three spills and slows, 22.7 -> 25.4); the 2D mixed form as float64 (held
+// at three it spilled: Q2 batch 4.4 -> 3.9 ms per launch without)
 #define CEM_SYS2_BOUNDS __launch_bounds__((Phys<D, PH>::M * SysTile<D, P, PH>::EB)) \
-  __attribute__((amdgpu_waves_per_eu(sizeof(RT) == 4 ? 3 : 2, sizeof(RT) == 4 ? 3 : 8)))
+  __attribute__((amdgpu_waves_per_eu(sizeof(RT) == 4 && D == 3 ? 3 : 2, sizeof(RT) == 4 && D == 3 ? 3 : 8)))
 
 // both halves of pass 1 (the whole pass in one kernel needed 256 VGPRs plus
 // AGPRs, one wave per SIMD, 22.4 ms per launch on the 128^3 Q2 blast; the
