@@ -40,6 +40,10 @@ STAGE_CASES = [
     ("euler3d_q2", lambda: random_euler_workload(3, 2, (5, 6, 4))),
     ("kpp2d_q2_long", lambda: random_scalar_workload(2, 2, (64, 63), kind="kpp")),
     ("euler2d_q3_long", lambda: random_euler_workload(2, 3, (55, 54))),
+    # large enough for the strided line passes to take runs of 2P
+    ("adv2d_q1_wide", lambda: random_scalar_workload(2, 1, (1024, 1024))),
+    ("euler2d_q2_wide", lambda: random_euler_workload(2, 2, (512, 256))),
+    ("euler2d_q3_wide", lambda: random_euler_workload(2, 3, (384, 256))),
 ]
 
 
