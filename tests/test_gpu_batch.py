@@ -59,8 +59,9 @@ def test_batch_matches_single_problems_euler(precision):
         mass = _multiplicity(SIZES[k], wls[k].p)
         e1 = rel_l1(g, r, mass)
         announce(f"[batch] problem {k} n={SIZES[k]}: batch vs single rel Linf {err:.1e}, rel L1 {e1:.1e}")
-        # the same kernel bodies, compiled into the batched wrappers: agreement
-        # to rounding (an ulp here and there from different FMA contraction);
+        # the same kernel bodies, compiled into the batched wrappers (the line
+        # passes with other run lengths, so other summation orders): agreement
+        # to rounding (an ulp here and there);
         # in the mixed form float-sized differences grow through the limiters
         # at the quadrant discontinuities within three steps
         if precision == "fp64":
