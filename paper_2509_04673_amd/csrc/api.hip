@@ -33,7 +33,9 @@ constexpr bool kSys2D = false;
 // 2D element pass 1 with two threads (roles) per element: scalar problems.
 // Measured per stage: KPP 256^2 Q2 22.7 -> 17.3 us; for 512^2 Q3 Euler the
 // one-thread tile stays faster (0.46 against 0.47 ms, mixed 0.36 against
-// 0.45 ms).
+// 0.45 ms).  The mixed form takes three roles (sensor, residual, facets:
+// KPP 13.3 -> 11.9 us); in float64 three roles measured slower (13.0 ->
+// 16.2 us).
 template <int PH> constexpr bool tile2_roles() { return Phys<2, PH>::M == 1; }
 
 // Euler element pass 1: the system kernels (one thread per element and
@@ -518,7 +520,10 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
       const int nb = ((c->n[0] + TT::TEX - 1) / TT::TEX) * ((c->n[1] + TT::TEY - 1) / TT::TEY);
       a.ndtpart = nb;
       if ((size_t)nb > c->ndtp) return fail(CEM_EINVAL, "internal: more element blocks than dt_e minima slots");
-      if constexpr (tile2_roles<PH>())
+      if constexpr (tile2_roles<PH>() && MIX)
+        CEM_LAUNCH(c, 1, (k_elem1_tile3<P, PH, true, RT>), nb, 384, (TT::words + 256) * sizeof(double),
+                   c->stream, a);
+      else if constexpr (tile2_roles<PH>())
         CEM_LAUNCH(c, 1, (k_elem1_tile2<P, PH, true, RT>), nb, 256, (TT::words + 256) * sizeof(double),
                    c->stream, a);
       else

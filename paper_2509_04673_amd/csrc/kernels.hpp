@@ -1098,7 +1098,11 @@ struct LdsXchg {
 
 // RT: value type of the sensor and residual contractions (double, or float
 // in the mixed-precision form); cell averages, facet data and dt_e are
-// always float64
+// always float64.  ROLE: 0 the whole pass; two threads per element: 1 the
+// sensor, viscosity and facets, 2 the residual; three threads per element:
+// 3 the sensor and viscosity, 2 the residual, 4 the facets.  Roles 1 and 3
+// hand gamma_e and nu_e to role 2 through xc; every role passes xc's one
+// barrier once.
 template <int D, int P, int PH, bool WS, class RT, class NS, int ROLE = 0, class XC = NoXchg>
 __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, const NS& ns, const XC& xc = XC()) {
   using PHY = Phys<D, PH>;
@@ -1127,7 +1131,20 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   constexpr bool keepx = 2 * D * NL <= 64;
   double nbr_mean[2 * D][M];
   double gam = 0.0, nu = 0.0;
-  if constexpr (ROLE != 2) {
+  if constexpr (ROLE == 4) {
+    // the facets need the neighbours' cell averages (as the sensor takes them)
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+      for (int l = 0; l < 2 * D; ++l) {
+        double cn[NL], sum = 0.0;
+        ns.load_nbr(c, l, cn);
+#pragma unroll
+        for (int j = 0; j < NL; ++j) sum += cn[j];
+        nbr_mean[l][c] = sum * (1.0 / NL);
+      }
+  }
+  if constexpr (ROLE != 2 && ROLE != 4) {
   double gmin = 1.0;
   for (int c = 0; c < M; ++c) {
     RT ct[NL];
@@ -1209,10 +1226,15 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     lam = fmax(lam, PHY::node_speed(uj, a.ph));
   }
   nu = lam * h / (2.0 * P);
-  }   // ROLE != 2
-  if constexpr (ROLE == 1) {
+  }   // roles 0, 1 and 3
+  if constexpr (ROLE == 1 || ROLE == 3) {
     xc.put(gam, nu);
     xc.sync();
+  }
+  if constexpr (ROLE == 3) {
+    a.gam[e] = gam;
+    a.nu[e] = nu;
+    return 1.0e300;
   }
 
   // ---- element residual R_i = int grad phi_i . f(u_h) - s_h^e(phi_i, u_h),
@@ -1322,7 +1344,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
       for (int i = 0; i < NL; ++i) store_rc(c, i, (RT)hpow * Rc[i] - (sa * s1[i] - sg * s2[i]));
     });
   }
-  if constexpr (ROLE != 1 && !SEQ) {
+  if constexpr ((ROLE == 0 || ROLE == 2) && !SEQ) {
   RT R[M][NL];
   {
     RT uq[M][NL];
@@ -1481,7 +1503,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
 #pragma unroll
     for (int i = 0; i < NL; ++i) store_r(c, i, (RT)hpow * R[c][i] - (sa * s1[i] - sg * s2[i]));
   }
-  }   // ROLE != 1
+  }   // roles 0 and 2
   if constexpr (ROLE == 2) return 1.0e300;
 
   // ---- facets (Sec. 4, eqs. 18, 40, 42, 51): canonical orientation is from
@@ -1556,13 +1578,16 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     for (int c = 0; c < M; ++c) a.ubar[c * E + e] = ue[c] - dt_e / h * fHout[c];
   }
   a.dte[e] = dt_e;
-  a.gam[e] = gam;
-  a.nu[e] = nu;
+  if constexpr (ROLE != 4) {
+    a.gam[e] = gam;
+    a.nu[e] = nu;
+  }
 #pragma unroll
   for (int c = 0; c < M; ++c) {
     a.ue[c * E + e] = ue[c];
     a.ubarL[c * E + e] = ue[c] - dt_e / h * fLsum[c];
   }
+  if constexpr (ROLE == 4) xc.sync();
   return dt_e;
 }
 
@@ -1691,6 +1716,41 @@ __device__ __forceinline__ void k_elem1_tile2_body(const StageArgs& a, int bx) {
 template <int P, int PH, bool WS, class RT>
 __global__ void __launch_bounds__(256) k_elem1_tile2(StageArgs a) {
   k_elem1_tile2_body<P, PH, WS, RT>(a, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Three threads per element (384 threads): role 3 the sensor and the
+// viscosity, role 2 the residual, role 4 the facet data and dt_e.  Only the
+// residual waits for gamma_e and nu_e (the block's one barrier).
+template <int P, int PH, bool WS, class RT>
+__device__ __forceinline__ void k_elem1_tile3_body(const StageArgs& a, int bx) {
+  constexpr int M = Phys<2, PH>::M;
+  using TT = Tile2<P, M>;
+  using TN = TileNodes2<P, M>;
+  constexpr int NE = TT::TEX * TT::TEY;
+  const MeshArgs& ms = a.mesh;
+  const int nbx = (ms.n[0] + TT::TEX - 1) / TT::TEX;
+  const int ex0 = (bx % nbx) * TT::TEX, ey0 = (bx / nbx) * TT::TEY;
+  tile_stage<P, PH, RT>(a, ex0, ey0);
+  const int role = (int)threadIdx.x / NE, li = (int)threadIdx.x - role * NE;
+  const int tx = li % TT::TEX, ty = li / TT::TEX;
+  const int ex = ex0 + tx, ey = ey0 + ty;
+  const LdsXchg xc{cem_smem + TT::words + li, NE};
+  double dt_e = 1.0e300;
+  if (ex < ms.n[0] && ey < ms.n[1]) {
+    const int64_t e = ex + (int64_t)ms.n[0] * ey;
+    const TN ns(a, e, tx, ty);
+    if (role == 0) elem1_body<2, P, PH, WS, RT, TN, 3>(a, e, ns, xc);
+    else if (role == 1) elem1_body<2, P, PH, WS, RT, TN, 2>(a, e, ns, xc);
+    else dt_e = elem1_body<2, P, PH, WS, RT, TN, 4>(a, e, ns, xc);
+  } else {
+    xc.sync();                          // the one exchange barrier of the block
+  }
+  block_min_dt_n<3 * NE>(a.dtpart, dt_e, bx);
+}
+
+template <int P, int PH, bool WS, class RT>
+__global__ void __launch_bounds__(384) k_elem1_tile3(StageArgs a) {
+  k_elem1_tile3_body<P, PH, WS, RT>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
