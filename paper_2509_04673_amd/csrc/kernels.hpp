@@ -1758,19 +1758,14 @@ __global__ void __launch_bounds__(384) k_elem1_tile3(StageArgs a) {
 // (eq. 45), slope limiter (eqs. 54-55 / Appendix A); stores the element
 // update vector [m_i^e (ubar - u_i) + beta f_i^e] / dt_e
 // ---------------------------------------------------------------------------
+// limited flux fb of the facet between eL (lower) and eR (upper): fA its raw
+// antidiffusive flux, uLs / uRs the two low-order averages, dtL / dtR the
+// two pseudo time steps
 template <int D, int PH>
-__device__ inline void limit_facet(const StageArgs& a, int k, int64_t eL, int64_t eR, double* fb) {
+__device__ inline void limit_facet(const StageArgs& a, const double* fA, const double* uLs, const double* uRs,
+                                   double dtL, double dtR, double* fb) {
   using PHY = Phys<D, PH>;
   constexpr int M = PHY::M;
-  const int64_t E = a.mesh.E;
-  double fA[M], uLs[M], uRs[M];
-#pragma unroll
-  for (int c = 0; c < M; ++c) {
-    fA[c] = a.fahi[((int64_t)k * M + c) * E + eL];
-    uLs[c] = a.ubarL[c * E + eL];
-    uRs[c] = a.ubarL[c * E + eR];
-  }
-  const double dtL = a.dte[eL], dtR = a.dte[eR];
   const double phi = a.mesh.h / (2.0 * D);     // |K| / |dK|
   if (a.alpha_mode == 2) {
 #pragma unroll
@@ -1816,45 +1811,64 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
 #pragma unroll
   for (int k = 0; k < D; ++k) axis_offsets<P>(ei[k], k, ms, off[k]);
 
-  // ---- flux-limited intermediate average (eq. 44)
+  // ---- flux-limited intermediate average (eq. 44).  The data of all 2D
+  // facets and the element's nodes are loaded first, in straight-line code:
+  // behind the limiter's (uniform) branches each facet's loads waited for
+  // the previous facet's arithmetic.
   const double dt_e = a.dte[e];
-  double fbs[M];
-#pragma unroll
-  for (int c = 0; c < M; ++c) fbs[c] = 0.0;
+  double fAl[D][M], fAh[D][M], ubl[D][M], ubh[D][M], ubc[M], uec[M], dtl[D], dth[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    if (a.flux_mode != 0) break;
     int en[3] = {ei[0], ei[1], ei[2]};
     en[k] = ei[k] == 0 ? ms.n[k] - 1 : ei[k] - 1;
     const int64_t elo = elem_id(en, ms);
     en[k] = ei[k] + 1 == ms.n[k] ? 0 : ei[k] + 1;
     const int64_t ehi = elem_id(en, ms);
-    double fb[M];
-    limit_facet<D, PH>(a, k, elo, e, fb);
 #pragma unroll
-    for (int c = 0; c < M; ++c) fbs[c] -= fb[c];
-    limit_facet<D, PH>(a, k, e, ehi, fb);
-#pragma unroll
-    for (int c = 0; c < M; ++c) fbs[c] += fb[c];
+    for (int c = 0; c < M; ++c) {
+      fAl[k][c] = a.fahi[((int64_t)k * M + c) * E + elo];    // facet (elo, e)
+      fAh[k][c] = a.fahi[((int64_t)k * M + c) * E + e];      // facet (e, ehi)
+      ubl[k][c] = a.ubarL[c * E + elo];
+      ubh[k][c] = a.ubarL[c * E + ehi];
+    }
+    dtl[k] = a.dte[elo];
+    dth[k] = a.dte[ehi];
   }
-  double ub[M], uec[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) {
+    ubc[c] = a.ubarL[c * E + e];
     uec[c] = a.ue[c * E + e];
-    if (a.flux_mode != 0) {
-      ub[c] = a.ubar[c * E + e];               // f = f^H, written by element pass 1
-    } else {
-      ub[c] = a.ubarL[c * E + e] + dt_e / h * fbs[c];
-      a.ubar[c * E + e] = ub[c];
-    }
   }
-
   double U[M][NL];
 #pragma unroll
   for (int j = 0; j < NL; ++j) {
     const int64_t nd = local_node<D, P>(j, off);
 #pragma unroll
     for (int c = 0; c < M; ++c) U[c][j] = a.u[c * N + nd];
+  }
+  double ub[M];
+  if (a.flux_mode != 0) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) ub[c] = a.ubar[c * E + e];   // f = f^H, written by element pass 1
+  } else {
+    double fbs[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) fbs[c] = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double fb[M];
+      limit_facet<D, PH>(a, fAl[k], ubl[k], ubc, dtl[k], dt_e, fb);
+#pragma unroll
+      for (int c = 0; c < M; ++c) fbs[c] -= fb[c];
+      limit_facet<D, PH>(a, fAh[k], ubc, ubh[k], dt_e, dth[k], fb);
+#pragma unroll
+      for (int c = 0; c < M; ++c) fbs[c] += fb[c];
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      ub[c] = ubc[c] + dt_e / h * fbs[c];
+      a.ubar[c * E + e] = ub[c];
+    }
   }
 
   // ---- boundary integral B_i = int_{dK} phi_i f_h . n (so that
