@@ -1124,6 +1124,24 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     ue[c] = s * (1.0 / NL);
   }
 
+  // nodal fluxes of the facet nodes (stored by the previous update), read
+  // before the sensor's arithmetic: the facet section uses them last
+  constexpr bool kPre = PHY::kNodal && (ROLE == 0 || ROLE == 1 || ROLE == 4);
+  double fpre[kPre ? D : 1][2][kPre ? NL : 1][M];
+  if constexpr (kPre) {
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int side = 0; side < 2; ++side)
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+          if (dig(j, k, P1) != (side ? P : 0)) continue;
+          const int64_t nd = ns.own_node(j);
+#pragma unroll
+          for (int c = 0; c < M; ++c) fpre[k][side][j][c] = a.fnode[((int64_t)k * M + c) * ms.N + nd];
+        }
+  }
+
   // ---- WENO sensor (Sec. 2.2, eqs. 7-8), per component; systems take the
   // minimum.  Candidates are extended into K_e by the blossom maps; every
   // semi-norm is the same packed quadratic form on coefficients shifted by
@@ -1531,9 +1549,8 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
         if (dig(j, k, P1) != (side ? P : 0)) continue;
         double fj[M];
         if constexpr (PHY::kNodal) {
-          const int64_t nd = ns.own_node(j);
 #pragma unroll
-          for (int c = 0; c < M; ++c) fj[c] = a.fnode[((int64_t)k * M + c) * ms.N + nd];
+          for (int c = 0; c < M; ++c) fj[c] = fpre[k][side][j][c];
         } else {
           double uj[M];
 #pragma unroll
