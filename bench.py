@@ -1,24 +1,35 @@
 """Benchmark: DOF x RK-stage updates per second of the limited CG-WENO
 SSP-RK3 scheme on one MI355X.
 
-Default workload: the 2D KPP problem (flux (sin u, cos u)) on
-[-2,2]x[-2.5,1.5] with 256x256 Bernstein Q2 cells (262144 unique DOFs),
-float64, fixed dt = 5e-4, seeded disc data.  A step is one full SSP-RK3 step
-(three stages, each the whole five-step algorithm: projected gradient, WENO
-sensor and residual, consistent-mass solve, facet fluxes with the flux
-limiter, element contributions with the slope limiter, assembly and the RK
-combination).  Inputs are resident in HBM when the timed region starts.
+Default workload: the batched 2D Euler problem set, 512 independent
+four-quadrant Riemann problems on the unit square (gamma = 1.4), Bernstein
+Q2 on square meshes of n_k^2 cells, n_k = 32 + floor(225 U) drawn from a
+seeded splitmix64 (seed 0: 196.8M DOFs), float64, cfl 0.5 with each
+problem's own adaptive dt.  All problems advance together (one launch per
+kernel and stage, each step one HIP graph, autotuned plan).  A step is one
+full SSP-RK3 step (three stages, each the whole five-step algorithm:
+projected gradient, WENO sensor and residual, consistent-mass solve, facet
+fluxes with the flux limiter, element contributions with the slope limiter,
+assembly and the RK combination).  Inputs are resident in HBM when the timed
+region starts.  --workload selects the single-problem workloads (kpp2d,
+euler2d, euler3d, adv1d) and --precision mixed the mixed-precision form.
 
-Prints one JSON line with the throughput (HIP events around the
-graph-replayed timed region), a roofline record of the dominant kernel and
-the float64 oracle timed on the host on a bounded sample of the same
-workload.  The dominant kernel is the single-launch-per-stage kernel with the
-largest warm-up time; its average duration is measured in a pass of directly
+Prints one JSON line: the throughput (HIP events around the graph-replayed
+timed region), a roofline record of the dominant kernel, the float64 oracle
+timed on the host on a bounded sample of the same workload, and for the
+mixed form its error against the oracle.
+
+Roofline: the dominant kernel is the one-launch-per-stage kernel with the
+largest warm-up time; its average duration comes from a pass of directly
 launched steps right after the timed region, each launch carrying HIP events
-that take the dispatch's own timestamps.  Its achieved rate is its
-algorithmic bytes (or flops, whichever bound is higher) per launch over that
-duration; `traffic` is the HBM bytes per launch from the committed rocprofv3
-counter summary of this workload, null when the kernel sources changed since.
+that take the dispatch's own timestamps.  achieved = the algorithmic minimum
+of a stage, 64/3 B per DOF-stage (stage 0 reads and writes the float64
+state, stages 1-2 also read the step base), times the DOFs one launch
+processes, over that duration; the same record holds the flop view (the
+kernel's own flop count against the FP64 vector peak), the whole stage
+against both peaks, and the HBM bytes the counters saw (per launch and per
+DOF-stage of the whole stage) when the committed rocprofv3 summary of this
+workload was taken on the current sources.
 
 Profiling helpers: --copy-probe BYTES runs a plain device copy (calibration
 of the byte counters) and --summarize-profile DIR writes that summary from
@@ -80,47 +91,29 @@ def elem2_flops(d, p, m, kind):
             + nl * (8 if m == 1 else 40) + 4 * m * nl)
 
 
-def kernel_work(name, wl, N, E, m, mixed=False):
-    """Algorithmic (bytes, flops) of one launch of a stage kernel.
-
-    Bytes are the arrays the method must read and write in that pass, each
-    once: the line operators read and write one nodal array (16 m N); the
-    gather reads the element vectors and writes r and the first line pass;
-    the update reads the element vectors, u and u_base and writes u (and the
-    nodal fluxes of KPP).  The element passes read the nodal arrays they
-    need (u, g, nodal fluxes, udot) and write the element data of the next
-    pass.  In the mixed form g, r, udot and the residual vectors are float
-    (4 bytes).  Flops of the line operators are those of a banded solve
-    (about 8p per node, not the wider truncated-inverse apply that runs);
-    those of the element passes come from elem1_flops / elem2_flops."""
-    d, p = wl.d, wl.p
-    nl = (p + 1) ** d
-    kn = d * m * N if wl.kind == "kpp" else 0        # nodal fluxes of KPP
-    f8, fr = 8.0, (4.0 if mixed else 8.0)             # state / intermediates
-    if name == "grad_line":
-        return m * N * (f8 + fr), 8 * p * m * N
-    if name == "mass_line":
-        return 2 * m * N * fr, 8 * p * m * N
-    if name == "gather_r":
-        return (m * nl * E + 2 * m * N) * fr, m * nl * E
-    if name == "update":
-        return (m * nl * E + 3 * m * N + kn) * f8, (nl + 4) * m * N
-    if name == "elem1" and split_elem1(wl):
-        # sensor and facets: u in; averages, low-order averages, f^A, dt_e,
-        # gamma_e, nu_e out
-        return m * N * f8 + (d * m + 3 + 2 * m) * E * f8, E * elem1_flops(d, p, m, wl.kind, 1)
-    if name == "elem1r":
-        # residual: u, g, averages, gamma_e, nu_e in; element vectors out
-        rd = m * N * f8 + d * m * N * fr + (m + 2) * E * f8
-        return rd + m * nl * E * fr, E * elem1_flops(d, p, m, wl.kind, 2)
+def kernel_flops(name, wl, E):
+    """Arithmetic of one launch of an element pass over E elements (the
+    kernel's own flop count by the sum-factorised algorithm; zero for the
+    streaming kernels)."""
+    d, p, m = wl.d, wl.p, wl.m
     if name == "elem1":
-        rd = (m * N + kn) * f8 + d * m * N * fr
-        wr = m * nl * E * fr + (d * m + 3 + 2 * m) * E * f8
-        return rd + wr, E * elem1_flops(d, p, m, wl.kind)
+        return E * elem1_flops(d, p, m, wl.kind, 1 if split_elem1(wl) else 0)
+    if name == "elem1r":
+        return E * elem1_flops(d, p, m, wl.kind, 2)
     if name == "elem2":
-        rd = (m * N + kn + (d * m + 2 * m + 1) * E) * f8 + (m * N + m * nl * E) * fr
-        return rd + (m * nl + m + 1) * E * f8, E * elem2_flops(d, p, m, wl.kind)
-    return 0.0, 0.0
+        return E * elem2_flops(d, p, m, wl.kind)
+    return 0.0
+
+
+# The algorithmic minimum HBM traffic of a stage per DOF: stage 0 reads and
+# writes the float64 state (16 B), stages 1 and 2 also read the step base
+# (24 B each): 64/3 B per DOF-stage over an SSP-RK3 step.
+MIN_BYTES_PER_DOF_STAGE = 64.0 / 3.0
+# Arithmetic of a whole stage per DOF (sum-factorised estimate, FMA = 2) per
+# workload: the WENO forms, the residual contractions, the facet pass, the
+# limiters and the line operators.
+STAGE_FLOPS_PER_DOF = {"adv1d": 200.0, "kpp2d": 1250.0, "euler2d": 1180.0, "euler_batch": 1070.0,
+                       "euler3d": 3900.0}
 
 
 def source_digest():
@@ -211,27 +204,48 @@ def summarize_profile(out_dir, dest, command, copy_bytes):
     print(f"wrote {dest}", flush=True)
 
 
-def profiled_traffic(wl, kernel_names, precision="fp64"):
-    """Bytes per launch of the dominant kernel from the committed counter
-    summary, or None when it is missing or was taken on other sources."""
-    path = os.path.join(PROFILE_DIR, profile_name(wl, precision))
+def _load_profile(fname):
+    """The machine-readable blob of a committed profile summary, or None."""
+    path = os.path.join(PROFILE_DIR, fname)
     if not os.path.exists(path):
-        return None, None
+        return None
     text = open(path).read()
     try:
-        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        return json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (IndexError, ValueError):
-        return None, None
-    if blob.get("digest") != source_digest():
-        return None, blob
-    for name, rec in blob["kernels"].items():
-        if any(k in name for k in kernel_names):
-            return rec["traffic_bytes"], blob
-    return None, blob
+        return None
+
+
+def _kernel_matches(name, patterns):
+    """Device kernel name against the patterns of a timing id (batched
+    wrappers kb_* count as their single-problem kernels k_*)."""
+    base = name.replace("cem::kb_", "cem::k_")
+    return any(k in base for k in patterns)
+
+
+def profiled_traffic(fname, dominant, dofs):
+    """From the committed counter summary (None where it is missing, holds no
+    counters, or was taken on other sources): HBM bytes per launch of the
+    dominant kernel, and the whole stage's HBM bytes per DOF-stage (each
+    kernel's bytes per dispatch times its dispatches per stage, counted
+    against the update kernel's, which runs once per stage)."""
+    blob = _load_profile(fname)
+    if blob is None or blob.get("digest") != source_digest() or blob.get("fetch_factor") is None:
+        return None, None, blob
+    ks = blob["kernels"]
+    upd = [r["calls"] for n, r in ks.items() if _kernel_matches(n, DEVICE_KERNELS["update"])]
+    dom = [r["traffic_bytes"] for n, r in ks.items() if _kernel_matches(n, DEVICE_KERNELS[dominant])]
+    per_launch = sum(dom) / len(dom) if dom else None
+    stage = None
+    if upd and all(r["traffic_bytes"] is not None for r in ks.values()):
+        stage_calls = sum(upd)
+        tot = sum(r["traffic_bytes"] * r["calls"] for n, r in ks.items() if "k_inv_partial" not in n)
+        stage = tot / stage_calls / dofs
+    return per_launch, stage, blob
 
 
 # device kernel names behind each timing id
-DEVICE_KERNELS = {"grad_line": ["k_line_multi", "k_line_x", "k_line_y", "k_line_fast", "k_line("],
+DEVICE_KERNELS = {"grad_line": ["k_line_multi", "k_line_x", "k_line_y", "k_line_fast", "k_line<", "k_line("],
                   "elem1": ["k_elem1"], "gather_r": ["k_gather"], "mass_line": ["k_line_y", "k_line_fast"],
                   "elem2": ["k_elem2"], "update": ["k_update"], "elem1r": ["k_resid"],
                   "stage_dt": ["k_stage_dt"]}
@@ -257,16 +271,34 @@ def copy_probe(nbytes):
     print(json.dumps(dict(copy_probe_bytes=n * 8, copies=13, copy_gb_per_s=gbs)), flush=True)
 
 
-def cpu_baseline(wl, seconds):
-    """The float64 oracle timed on the host on whole forward-Euler stages of
-    the same workload until `seconds` have elapsed (at least one stage)."""
-    from threadpoolctl import threadpool_limits
+def host_info():
+    """CPU model and logical core count of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def _oracle_for(wl):
     from oracle import Mesh, Oracle, Params, Problem
     mesh = Mesh(wl.d, wl.p, wl.n, wl.lo, wl.hi)
     prob = Problem(mesh, wl.kind, wl.velocity, wl.gamma_gas, params=Params(w_lin=wl.w_lin, q=wl.q),
                    u_min=float(wl.u0.min()), u_max=float(wl.u0.max()))
+    return Oracle(prob)
+
+
+def _oracle_stages(wl, seconds, max_stages=None):
+    """Whole forward-Euler stages of the oracle on one workload, one thread,
+    until `seconds` have elapsed (at least one): (stages, elapsed s)."""
+    from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
-        orc = Oracle(prob)
+        orc = _oracle_for(wl)
         dt = wl.dt if wl.dt > 0 else wl.cfl * orc.max_dt(wl.u0)
         u = wl.u0.copy()
         stages = 0
@@ -275,35 +307,133 @@ def cpu_baseline(wl, seconds):
             u, _ = orc.fe_stage(u, dt)
             stages += 1
             el = time.perf_counter() - t0
-            if el >= seconds:
-                break
-    return dict(value=wl.dofs * stages / el, unit="DOF*stage/s", cores=1, kind="oracle",
-                sample=f"{stages} forward-Euler stages of the full {wl.name} workload "
-                       f"({wl.dofs} DOFs), numpy float64, 1 thread, {el:.1f} s")
+            if el >= seconds or (max_stages and stages >= max_stages):
+                return stages, el
+
+
+def _oracle_stage_job(wl):
+    """One oracle stage of one problem (a worker of the all-core run)."""
+    st, el = _oracle_stages(wl, 0.0, 1)
+    return wl.dofs * st, el
+
+
+def cpu_baseline(wls, seconds, label, all_cores=False):
+    """The float64 oracle timed on the host: one thread on whole stages of
+    the sample workloads (in turn, until `seconds` have elapsed); with
+    all_cores, also one stage of every sample problem at once in a pool of
+    single-threaded processes (one per core, at most one per problem)."""
+    model, ncpu = host_info()
+    dof_stages, el = 0, 0.0
+    per = max(seconds / len(wls), 1e-3)
+    for w in wls:
+        st, e = _oracle_stages(w, per)
+        dof_stages += w.dofs * st
+        el += e
+    out = dict(value=dof_stages / el, unit="DOF*stage/s", cores=1, kind="oracle",
+               sample=f"{label}: {dof_stages} DOF-stages of forward-Euler stages, numpy float64, "
+                      f"1 thread, {el:.1f} s", cpu_model=model, host_cores=ncpu)
+    if all_cores and len(wls) > 1:
+        import multiprocessing as mp
+        workers = max(1, min(len(wls), ncpu or 1, 16))
+        ctx = mp.get_context("fork")
+        t0 = time.perf_counter()
+        with ctx.Pool(workers) as pool:
+            res = pool.map(_oracle_stage_job, wls)
+        wall = time.perf_counter() - t0
+        out["all_cores"] = dict(value=sum(r[0] for r in res) / wall, cores=workers,
+                                sample=f"one stage of each of the {len(wls)} sample problems, "
+                                       f"{workers} single-threaded processes, {wall:.1f} s wall")
+    return out
+
+
+def mixed_error(make_gpu_run, wls, nsteps=1):
+    """Relative L1 error per component (lumped masses) of the mixed form
+    against the float64 oracle after nsteps SSP-RK3 steps, max over
+    components and sample problems; make_gpu_run(wls, nsteps) returns the
+    GPU states (one (m, N) array per workload)."""
+    import numpy as np
+    got = make_gpu_run(wls, nsteps)
+    worst = 0.0
+    for w, g in zip(wls, got):
+        orc = _oracle_for(w)
+        ref, _ = orc.run(w.u0.copy(), nsteps, dt=(w.dt if w.dt > 0 else None), cfl=w.cfl)
+        mass = orc.mesh.multiplicity() * orc.mesh.h ** orc.mesh.d / orc.mesh.nloc
+        g = np.asarray(g).reshape(ref.shape)
+        num = np.sum(mass * np.abs(g - ref), axis=1)
+        den = np.sum(mass * np.abs(ref), axis=1)
+        worst = max(worst, float(np.max(num / np.where(den > 0, den, 1.0))))
+    return worst
+
+
+def roofline_record(dominant, kt, wl, dofs, E, value, mixed, profile_file):
+    """The roofline record of the dominant kernel (see the module docstring)."""
+    kms, kcnt = kt[dominant]
+    avg_s = (kms / kcnt) * 1e-3 if kcnt else float("nan")
+    nbytes = MIN_BYTES_PER_DOF_STAGE * dofs
+    achieved = nbytes / avg_s / 1e9
+    kfl = kernel_flops(dominant, wl, E)
+    fpeak = FP32_VECTOR_TFLOPS if mixed else FP64_VECTOR_TFLOPS
+    traffic, stage_traffic, prof = profiled_traffic(profile_file, dominant, dofs)
+    prof_us = None
+    if prof is not None and traffic is not None:
+        us = [r["avg_us"] for n, r in prof["kernels"].items() if _kernel_matches(n, DEVICE_KERNELS[dominant])]
+        prof_us = sum(us) / len(us) if us else None
+    sflops = STAGE_FLOPS_PER_DOF.get(wl.name)
+    return dict(
+        bound="hbm", kernel=dominant, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+        frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+        algorithmic_bytes=nbytes, min_bytes_per_dof_stage=MIN_BYTES_PER_DOF_STAGE, dofs_per_launch=dofs,
+        avg_launch_us=avg_s * 1e6, launches=kcnt, profiled_avg_us=prof_us,
+        traffic_per_dof_stage_kernel=None if traffic is None else traffic / dofs,
+        traffic_per_dof_stage_stage=stage_traffic,
+        flop_view=dict(kernel_flops=kfl, achieved=kfl / avg_s / 1e12, peak=fpeak, unit="TFLOP/s",
+                       frac=kfl / avg_s / 1e12 / fpeak),
+        stage_view=dict(hbm_frac=MIN_BYTES_PER_DOF_STAGE * value / (HBM_PEAK_GBS * 1e9),
+                        flops_per_dof_stage=sflops,
+                        alu_frac=None if sflops is None else sflops * value / (fpeak * 1e12)))
+
+
+def _dominant(warm, nwarm):
+    """The one-launch-per-stage kernel with the largest warm-up time."""
+    single = {k: v for k, v in warm.items() if v[1] == 3 * nwarm}
+    return max(single, key=lambda k: single[k][0])
 
 
 def bench_batch(args):
     """The batched workload: count independent four-quadrant Euler problems
     (Q2, n_k^2 meshes, n_k = 32 + floor(225 U)) advanced together, one launch
     per kernel and stage, each step one HIP graph; adaptive dt per problem."""
+    import numpy as np
     import torch
     from paper_2509_04673_amd import cem, workloads
-    prec = args.precision if args.precision != "fp64" or "--precision" in sys.argv else "mixed"
+    prec = args.precision
+    mixed = prec == "mixed"
     wls = workloads.euler_batch(seed=0, count=args.count)
     dofs = sum(w.dofs for w in wls)
+    E = sum(w.n[0] * w.n[1] for w in wls)
     print(f"[bench] batched Euler: {len(wls)} problems, n in [{min(w.n[0] for w in wls)}, "
           f"{max(w.n[0] for w in wls)}], {dofs} DOFs, precision={prec}", flush=True)
     dev = torch.device("cuda:0")
     b = cem.BatchSolver([(w.d, w.p, w.n, w.lo, w.hi) for w in wls], "euler", gamma_gas=wls[0].gamma_gas,
                         w_lin=wls[0].w_lin, precision=prec)
     b.upload([w.u0 for w in wls])
+    wl0 = wls[0]
     del wls
     cfl = 0.5
-    tune = b.autotune(cfl=cfl, steps=1)
-    print(f"[bench] autotuned plan: {tune['best']}", flush=True)
-    b.step(cfl=cfl, nsteps=args.warmup)
+    tune = b.autotune(cfl=cfl, steps=1) if not args.no_autotune else dict(best=None, trials=[])
+    print(f"[bench] autotuned plan: {tune['best']} ({len(tune['trials'])} plans tried)", flush=True)
+
+    nwarm = max(1, args.warmup)
+    cem.cem_batch_set_timing(b.b, (1 << len(cem.KERNELS)) - 1)
+    b.step(cfl=cfl, nsteps=nwarm)
+    warm = cem.cem_batch_kernel_times(b.b)
+    dominant = _dominant(warm, nwarm)
+    print("[bench] warm-up kernel ms: " + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in warm.items()
+                                                   if v[1]), flush=True)
+    cem.cem_batch_set_timing(b.b, 0)
+    b.step(cfl=cfl, nsteps=1)                  # captures the graph
     cem.cem_batch_reset_counters(b.b)
-    stream = torch.cuda.current_stream(dev)
+    stream = b.stream
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize(dev)
     w0 = time.perf_counter()
@@ -314,66 +444,69 @@ def bench_batch(args):
     wall = time.perf_counter() - w0
     ms = ev0.elapsed_time(ev1)
     chk = b.check()
+
+    nroof = max(1, min(args.steps, 10))
+    cem.cem_batch_set_timing(b.b, 1 << cem.KERNELS.index(dominant))
+    b.step(cfl=cfl, nsteps=nroof)
+    kt = cem.cem_batch_kernel_times(b.b)
+    cem.cem_batch_set_timing(b.b, 0)
     b.close()
+    del b
+    torch.cuda.empty_cache()
+
     value = dofs * 3 * args.steps / (ms * 1e-3)
+    wlb = workloads.Workload("euler_batch", 2, 2, (args.count,), (0.0, 0.0), (1.0, 1.0), "euler",
+                             np.zeros((4, 1)))
+    pname = f"euler_batch_{args.count}_q2{'_mixed' if mixed else ''}_stage_kernels.md"
+    roof = roofline_record(dominant, kt, wlb, dofs, E, value, mixed, pname)
+
+    # the oracle and the mixed-form error on eight problems spanning the sizes
+    sample = workloads.euler_batch(0, count=args.count, only=workloads.euler_batch_octiles(0, args.count))
+    label = f"the 8 problems at the size octiles (n = {', '.join(str(w.n[0]) for w in sample)})"
+    cpu, err = None, None
+    if not args.no_cpu_baseline:
+        print(f"[bench] timing the oracle for ~{args.cpu_seconds:.0f} s on {label}", flush=True)
+        cpu = cpu_baseline(sample, args.cpu_seconds, label, all_cores=True)
+        cpu["extrapolated_full_batch_s_per_stage"] = dofs / cpu["value"]
+    if mixed and not args.no_error:
+        def run(ws, nsteps):
+            bb = cem.BatchSolver([(w.d, w.p, w.n, w.lo, w.hi) for w in ws], "euler",
+                                 gamma_gas=ws[0].gamma_gas, w_lin=ws[0].w_lin, precision="mixed")
+            bb.upload([w.u0 for w in ws])
+            bb.step(cfl=cfl, nsteps=nsteps)
+            out = bb.download()
+            bb.close()
+            return out
+        print("[bench] mixed-form error against the oracle (1 step, 8 problems)", flush=True)
+        err = dict(rel_l1=mixed_error(run, sample, 1), sample=f"{label}, one SSP-RK3 step, max over "
+                                                                "components and problems")
     out = dict(metric="DOF*RK-stage updates/s", value=value, unit="DOF*stage/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps,
                higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype="f64" if prec == "fp64" else "f32+f64", data="synthetic",
-               config=dict(workload="euler_batch", problems=args.count, degree=2, dofs=dofs, physics="euler",
-                           cfl=cfl, seed=0, wall_s=wall,
+               dtype="f32+f64" if mixed else "f64", data="synthetic",
+               config=dict(workload="euler_batch", problems=args.count, dim=2, degree=2, dofs=dofs,
+                           elements=E, physics="euler", cfl=cfl, seed=0, precision=prec, wall_s=wall,
                            violations=int(sum(c["violations"] for c in chk)),
                            rho_min=min(c["rho_min"] for c in chk), p_min=min(c["p_min"] for c in chk),
                            autotune=tune["best"]),
-               roofline=None, cpu_baseline=None)
+               roofline=roof, cpu_baseline=cpu)
+    if err is not None:
+        out["mixed_error"] = err
     print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="kpp2d", choices=["kpp2d", "adv1d", "euler2d", "euler3d", "euler_batch"])
-    ap.add_argument("--count", type=int, default=512, help="problems of the batched workload")
-    ap.add_argument("--n", type=int, default=None, help="cells per axis (default: workload size)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
-                    help="fp64, or mixed: float contractions with float64 state, limiters and dt")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
-                    help="only run a plain device copy of BYTES (counter calibration)")
-    ap.add_argument("--summarize-profile", metavar="DIR",
-                    help="write the rocprofv3 summary of DIR/{stats,fetch,write,copy_fetch,copy_write}")
-    ap.add_argument("--profile-command", default="", help="command text recorded in the summary")
-    args = ap.parse_args()
-    if args.copy_probe:
-        copy_probe(args.copy_probe)
-        return
-    if args.summarize_profile:
-        from paper_2509_04673_amd import workloads
-        kw = {} if args.n is None else dict(n=args.n)
-        if args.workload == "euler_batch":
-            name = f"euler_batch_{args.count}_q2_{args.precision}_stage_kernels.md"
-        else:
-            name = profile_name(workloads.make(args.workload, seed=0, **kw), args.precision)
-        summarize_profile(args.summarize_profile, os.path.join(PROFILE_DIR, name),
-                          args.profile_command, COPY_PROBE_BYTES)
-        return
+# oracle samples of the single-problem workloads: the mesh of the error and
+# baseline runs where the full mesh would take the oracle minutes per stage
+SAMPLE_N = {"euler2d": 256, "euler3d": 32}
 
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "decomposition is described, not implemented", file=sys.stderr)
-        sys.exit(2)
 
+def bench_single(args):
+    import numpy as np  # noqa: F401
     import torch
     from paper_2509_04673_amd import cem, workloads
-
-    if args.workload == "euler_batch":
-        return bench_batch(args)
-
     kw = {} if args.n is None else dict(n=args.n)
     wl = workloads.make(args.workload, seed=0, **kw)
+    mixed = args.precision == "mixed"
     print(f"[bench] workload {wl.name} d={wl.d} p={wl.p} n={wl.n} dofs={wl.dofs} "
           f"precision={args.precision}", flush=True)
     dev = torch.device("cuda:0")
@@ -383,21 +516,14 @@ def main():
         s.set_bounds()
     dt, cfl = (wl.dt, 0.0) if wl.dt > 0 else (0.0, wl.cfl)
 
-    # warm-up with every kernel timed (direct launches): the dominant kernel
-    # (at least one step, also with --warmup 0, to find that kernel)
     nwarm = max(1, args.warmup)
     cem.cem_set_timing(s.ctx, (1 << len(cem.KERNELS)) - 1)
     for _ in range(nwarm):
         s.step(dt, cfl)
     warm = cem.cem_kernel_times(s.ctx)
-    # the dominant kernel among the ids that are one device launch per stage
-    # (the line-operator ids cover one launch per axis)
-    single = {k: v for k, v in warm.items() if v[1] == 3 * nwarm}
-    dominant = max(single, key=lambda k: single[k][0])
+    dominant = _dominant(warm, nwarm)
     print("[bench] warm-up kernel ms: " + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in warm.items()
                                                    if v[1]), flush=True)
-
-    # timed region: whole steps replayed as HIP graphs, no events inside
     cem.cem_set_timing(s.ctx, 0)
     s.step(dt, cfl)                       # captures the graph
     cem.cem_reset_counters(s.ctx)
@@ -414,57 +540,98 @@ def main():
     ms = ev0.elapsed_time(ev1)
     chk = s.check()
 
-    # roofline pass right after, same steps launched directly with HIP events
-    # on the library's stream around every launch of the dominant kernel
     nroof = min(args.steps, 50)
     cem.cem_set_timing(s.ctx, 1 << cem.KERNELS.index(dominant))
     for _ in range(nroof):
         s.step(dt, cfl)
     kt = cem.cem_kernel_times(s.ctx)
     cem.cem_set_timing(s.ctx, 0)
+    E, N = s.E, s.N
     s.close()
 
-    stages = 3 * args.steps
-    value = wl.dofs * stages / (ms * 1e-3)
-    mixed = args.precision == "mixed"
-    nbytes, nflops = kernel_work(dominant, wl, s.N, s.E, s.m, mixed)
-    if dominant == "grad_line":
-        # one launch may carry the passes of several axes
-        per_stage = warm[dominant][1] / (3 * nwarm)
-        nbytes, nflops = nbytes * wl.d / per_stage, nflops * wl.d / per_stage
-    kms, kcnt = kt[dominant]
-    avg_s = (kms / kcnt) * 1e-3 if kcnt else float("nan")
-    # the bound is the larger of the two algorithmic lower bounds
-    fpeak = FP32_VECTOR_TFLOPS if mixed else FP64_VECTOR_TFLOPS
-    if nbytes / (HBM_PEAK_GBS * 1e9) >= nflops / (fpeak * 1e12):
-        bound, achieved, peak, unit = "hbm", nbytes / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
-    else:
-        bound, achieved, peak, unit = "alu", nflops / avg_s / 1e12, fpeak, "TFLOP/s"
-    traffic, prof = profiled_traffic(wl, DEVICE_KERNELS[dominant], args.precision)
-    roof = dict(bound=bound, kernel=dominant, achieved=achieved, peak=peak, unit=unit,
-                frac=achieved / peak, traffic=traffic, algorithmic_bytes=nbytes, algorithmic_flops=nflops,
-                avg_launch_us=avg_s * 1e6, launches=kcnt,
-                profiled_avg_us=None if prof is None or traffic is None else
-                next(r["avg_us"] for n, r in prof["kernels"].items()
-                     if any(k in n for k in DEVICE_KERNELS[dominant])))
+    value = wl.dofs * 3 * args.steps / (ms * 1e-3)
+    roof = roofline_record(dominant, kt, wl, wl.dofs, E, value, mixed, profile_name(wl, args.precision))
 
-    cpu = None
+    sn = SAMPLE_N.get(wl.name) if args.n is None else None
+    swl = workloads.make(args.workload, seed=0, n=sn) if sn else wl
+    label = f"the {wl.name} workload" + (f" at n = {sn}" if sn else "") + f" ({swl.dofs} DOFs)"
+    cpu, err = None, None
     if not args.no_cpu_baseline:
-        print(f"[bench] timing the oracle for ~{args.cpu_seconds:.0f} s", flush=True)
-        cpu = cpu_baseline(wl, args.cpu_seconds)
-
+        print(f"[bench] timing the oracle for ~{args.cpu_seconds:.0f} s on {label}", flush=True)
+        cpu = cpu_baseline([swl], args.cpu_seconds, label)
+    if mixed and not args.no_error:
+        def run(ws, nsteps):
+            outs = []
+            for w in ws:
+                ss = cem.Solver.from_workload(w, device="cuda:0", precision="mixed")
+                ss.upload(w.u0)
+                if w.kind != "euler":
+                    ss.set_bounds()
+                for _ in range(nsteps):
+                    ss.step(w.dt if w.dt > 0 else 0.0, 0.0 if w.dt > 0 else w.cfl)
+                outs.append(ss.download())
+                ss.close()
+            return outs
+        print(f"[bench] mixed-form error against the oracle (1 step, {label})", flush=True)
+        err = dict(rel_l1=mixed_error(run, [swl], 1), sample=f"{label}, one SSP-RK3 step, max over components")
     out = dict(metric="DOF*RK-stage updates/s", value=value, unit="DOF*stage/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps,
                higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype="f64" if args.precision == "fp64" else "f32+f64",
-               data="synthetic",
+               dtype="f32+f64" if mixed else "f64", data="synthetic",
                config=dict(workload=wl.name, dim=wl.d, degree=wl.p, cells=list(wl.n),
-                           dofs=wl.dofs, physics=wl.kind, dt=wl.dt if wl.dt > 0 else None,
-                           cfl=None if wl.dt > 0 else wl.cfl, seed=0,
-                           wall_s=wall, violations=chk["violations"],
-                           clamped=chk["clamped"]),
+                           dofs=wl.dofs, elements=E, physics=wl.kind, dt=wl.dt if wl.dt > 0 else None,
+                           cfl=None if wl.dt > 0 else wl.cfl, seed=0, precision=args.precision,
+                           wall_s=wall, violations=chk["violations"], clamped=chk["clamped"]),
                roofline=roof, cpu_baseline=cpu)
+    if err is not None:
+        out["mixed_error"] = err
     print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="euler_batch",
+                    choices=["euler_batch", "kpp2d", "adv1d", "euler2d", "euler3d"])
+    ap.add_argument("--count", type=int, default=512, help="problems of the batched workload")
+    ap.add_argument("--n", type=int, default=None, help="cells per axis (default: workload size)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="fp64, or mixed: float contractions with float64 state, limiters and dt")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error", action="store_true", help="skip the mixed-form error run")
+    ap.add_argument("--no-autotune", action="store_true", help="batched workload: default plan")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="write the rocprofv3 summary of DIR/{stats,fetch,write,copy_fetch,copy_write}")
+    ap.add_argument("--profile-command", default="", help="command text recorded in the summary")
+    args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    if args.summarize_profile:
+        from paper_2509_04673_amd import workloads
+        kw = {} if args.n is None else dict(n=args.n)
+        if args.workload == "euler_batch":
+            name = f"euler_batch_{args.count}_q2{'_mixed' if args.precision == 'mixed' else ''}_stage_kernels.md"
+        else:
+            name = profile_name(workloads.make(args.workload, seed=0, **kw), args.precision)
+        summarize_profile(args.summarize_profile, os.path.join(PROFILE_DIR, name),
+                          args.profile_command, COPY_PROBE_BYTES)
+        return
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build measures "
+              "the path on a single MI355X; the multi-GPU decomposition is described, not "
+              "implemented", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "euler_batch":
+        bench_batch(args)
+    else:
+        bench_single(args)
 
 
 if __name__ == "__main__":

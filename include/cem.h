@@ -112,17 +112,29 @@ typedef struct {
 
 typedef struct cem_ctx cem_ctx;
 
-/* Pseudo time step statistics and invariant report. */
+/* Pseudo time step statistics and invariant report.  The invariant domain
+ * G is the one Theorem 1 (Sec. 3.3) preserves: u_min <= u <= u_max for
+ * scalar problems (global bounds, Sec. 4.1-4.2), rho > 0 and p > 0 for the
+ * Euler equations (Sec. 5.2, Appendix A).  Every test is written so that a
+ * NaN fails it; extrema propagate NaN. */
 typedef struct {
-  double dt;             /* global time step of the current/last step */
-  double min_dt_e;       /* min over elements and stages of dt_e (eq. 40) */
-  int cfl_violated;      /* 1 if dt > min_e dt_e at some stage */
-  long long clamped;     /* scalar values clamped by <= clamp width (round-off) */
-  long long violations;  /* values outside the admissible set beyond round-off */
+  double dt;             /* global time step of the current/last step (eq. 23) */
+  double min_dt_e;       /* min over elements and stages of dt_e (eq. 40 / 37) */
+  int cfl_violated;      /* 1 if dt > min_e dt_e at some stage (eq. 23) */
+  long long clamped;     /* stage results clamped by <= clamp width (round-off) */
+  long long violations;  /* stage results outside G beyond round-off, summed
+                            over the stages since the last reset: scalar
+                            values outside [u_min - tol, u_max + tol] or NaN;
+                            Euler nodes with !(rho > 0), plus nodes with
+                            !(p > 0) (each failed condition counts once) */
   int m;                 /* number of components */
   double u_min[5], u_max[5];   /* per-component extrema of the state */
   double mass[5];        /* per-component sum_i m_i u_i (lumped masses) */
   double rho_min, p_min; /* Euler: smallest density and pressure */
+  long long nonfinite;   /* state values that are NaN or infinite */
+  long long state_violations; /* failed conditions of G in the current state,
+                            counted as for violations (at the time of the
+                            check, also without any stage run) */
 } cem_invariants;
 
 /* Fills p with the defaults: q = 1, r = 2, eps = 1e-12, w_lin = 1e-3,
@@ -185,8 +197,11 @@ cem_status cem_set_graphs(cem_ctx* ctx, int enable);
 cem_status cem_state_modified(cem_ctx* ctx);
 
 /* Synchronous: reads the step size, CFL flag and clamp/violation counters
- * accumulated since the last cem_reset_counters, and the state invariants.
- * Returns CEM_ECFL or CEM_EIDP when the corresponding check failed. */
+ * accumulated since the last cem_reset_counters, and the state invariants
+ * (Theorem 1: the stage results stay in G when dt <= min_e dt_e, eq. 23).
+ * Returns CEM_EIDP when violations, state_violations or nonfinite is
+ * nonzero, else CEM_ECFL when the CFL flag is set, else CEM_OK; *out is
+ * filled in every case. */
 cem_status cem_check_invariants(cem_ctx* ctx, cem_invariants* out);
 cem_status cem_reset_counters(cem_ctx* ctx);
 
@@ -222,6 +237,7 @@ cem_status cem_kernel_times(cem_ctx* ctx, double* total_ms, long long* launches,
 void cem_destroy(cem_ctx* ctx);
 const char* cem_last_error(void);
 
+
 /* ---- Batched form --------------------------------------------------------
  * count independent problems (uneven mesh sizes; the same dimension, degree,
  * physics, parameters and precision) advance together: every kernel of a
@@ -254,7 +270,15 @@ cem_status cem_batch_set_bounds(cem_batch* b, int from_state, double u_min, doub
 cem_status cem_batch_step(cem_batch* b, double dt, double cfl, int nsteps);
 cem_status cem_batch_set_graphs(cem_batch* b, int enable);
 cem_status cem_batch_reset_counters(cem_batch* b);
-/* one record per problem (n == count); returns the worst status. */
+/* Per-kernel timing of the batched launches, as cem_set_timing /
+ * cem_kernel_times (the same kernel ids; each batched launch is one record,
+ * covering every problem it serves).  While a mask is set, cem_batch_step
+ * launches directly instead of replaying its graph.  cem_batch_kernel_times
+ * is synchronous. */
+cem_status cem_batch_set_timing(cem_batch* b, unsigned mask);
+cem_status cem_batch_kernel_times(cem_batch* b, double* total_ms, long long* launches, int n);
+/* one record per problem (n == count); returns EIDP if any problem failed an
+ * invariant-domain check, else ECFL if any set its CFL flag. */
 cem_status cem_batch_check_invariants(cem_batch* b, cem_invariants* out, int n);
 /* Autotuner of the batched launches: times `steps` steps of every candidate
  * plan (lines per block of the x-line kernels: 512 .. 4096 staged values;

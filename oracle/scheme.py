@@ -483,13 +483,16 @@ class Oracle:
         ulps of rounding are clamped and counted; larger excursions are
         reported as violations.  Euler: count nonpositive rho or p."""
         prob = self.prob
+        # G of Theorem 1 holds rho > 0, p > 0 (Euler) or u in [u_min, u_max];
+        # the tests are written so that a NaN is counted as outside G
         if prob.kind == "euler":
-            bad = int(np.sum(u[0] <= 0) + np.sum(prob.phys.pressure(u) <= 0))
+            with np.errstate(invalid="ignore", divide="ignore"):
+                bad = int(np.sum(~(u[0] > 0)) + np.sum(~(prob.phys.pressure(u) > 0)))
             return u, 0, bad
         tol = prob.params.clamp_ulps * np.finfo(float).eps * max(abs(prob.u_min), abs(prob.u_max))
         hi = (u > prob.u_max) & (u <= prob.u_max + tol)
         lo = (u < prob.u_min) & (u >= prob.u_min - tol)
-        bad = int(np.sum(u > prob.u_max + tol) + np.sum(u < prob.u_min - tol))
+        bad = int(np.sum(~((u >= prob.u_min - tol) & (u <= prob.u_max + tol))))
         u = np.where(hi, prob.u_max, np.where(lo, prob.u_min, u))
         return u, int(np.sum(hi) + np.sum(lo)), bad
 

@@ -56,7 +56,8 @@ class Invariants(ctypes.Structure):
                 ("violations", ctypes.c_longlong), ("m", ctypes.c_int),
                 ("u_min", ctypes.c_double * 5), ("u_max", ctypes.c_double * 5),
                 ("mass", ctypes.c_double * 5), ("rho_min", ctypes.c_double),
-                ("p_min", ctypes.c_double)]
+                ("p_min", ctypes.c_double), ("nonfinite", ctypes.c_longlong),
+                ("state_violations", ctypes.c_longlong)]
 
 
 # (name, restype, argtypes) of every exported symbol
@@ -97,6 +98,9 @@ _SIGS = [
     ("cem_batch_set_graphs", ctypes.c_int, [_P, ctypes.c_int]),
     ("cem_batch_reset_counters", ctypes.c_int, [_P]),
     ("cem_batch_check_invariants", ctypes.c_int, [_P, ctypes.POINTER(Invariants), ctypes.c_int]),
+    ("cem_batch_set_timing", ctypes.c_int, [_P, ctypes.c_uint]),
+    ("cem_batch_kernel_times", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
     ("cem_batch_autotune", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _P,
                                           ctypes.c_size_t, ctypes.c_char_p, ctypes.c_size_t]),
     ("cem_batch_destroy", None, [_P]),
@@ -296,13 +300,20 @@ class Solver:
     def step(self, dt=0.0, cfl=0.0):
         cem_step(self.ctx, dt, cfl)
 
+    def set_graphs(self, enable):
+        cem_set_graphs(self.ctx, enable)
+
+    def reset_counters(self):
+        cem_reset_counters(self.ctx)
+
     def check(self, raise_on_failure=False):
         inv, st = cem_check_invariants(self.ctx, raise_on_failure)
         m = inv.m
         return dict(status=st, dt=inv.dt, min_dt_e=inv.min_dt_e, cfl_violated=inv.cfl_violated,
                     clamped=inv.clamped, violations=inv.violations,
                     u_min=list(inv.u_min)[:m], u_max=list(inv.u_max)[:m],
-                    mass=list(inv.mass)[:m], rho_min=inv.rho_min, p_min=inv.p_min)
+                    mass=list(inv.mass)[:m], rho_min=inv.rho_min, p_min=inv.p_min,
+                    nonfinite=inv.nonfinite, state_violations=inv.state_violations)
 
     def tap(self, name):
         tid = TAPS[name]
@@ -382,6 +393,18 @@ def cem_batch_check_invariants(b, count):
     return list(inv), st
 
 
+def cem_batch_set_timing(b, mask):
+    _check(lib().cem_batch_set_timing(b, int(mask)))
+
+
+def cem_batch_kernel_times(b):
+    n = len(KERNELS)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_longlong * n)()
+    _check(lib().cem_batch_kernel_times(b, ms, cnt, n))
+    return {KERNELS[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
 def cem_batch_autotune(b, dt, cfl, steps, scratch_ptr, scratch_bytes):
     buf = ctypes.create_string_buffer(8192)
     _check(lib().cem_batch_autotune(b, float(dt), float(cfl), int(steps), _P(scratch_ptr), int(scratch_bytes),
@@ -456,7 +479,8 @@ class BatchSolver:
         inv, st = cem_batch_check_invariants(self.b, self.count)
         return [dict(status=st, dt=r.dt, min_dt_e=r.min_dt_e, cfl_violated=r.cfl_violated,
                      clamped=r.clamped, violations=r.violations, rho_min=r.rho_min, p_min=r.p_min,
-                     mass=list(r.mass)[:r.m]) for r in inv]
+                     mass=list(r.mass)[:r.m], nonfinite=r.nonfinite,
+                     state_violations=r.state_violations) for r in inv]
 
     def close(self):
         if self.b:

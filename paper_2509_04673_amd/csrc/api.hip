@@ -827,7 +827,11 @@ template <int D, int P, int PH, class RT>
 cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
   constexpr int M = Phys<D, PH>::M;
   const char* base = b->ws + b->o_plan;
+  // per-kernel timing (cem_batch_set_timing) goes through the first
+  // problem's context: one record per batched launch
+  cem_ctx* c0 = b->pr[0];
   for (const BLaunch& l : b->launches[st]) {
+    const int LID = l.grad ? 0 : 4;     // line kernels: gradient or mass pass
     const BatchMap mp{reinterpret_cast<const int*>(base + l.o_first), l.nprob};
     const StageArgs* sa = reinterpret_cast<const StageArgs*>(base + l.o_args);
     const LineFastArgs* lf = reinterpret_cast<const LineFastArgs*>(base + l.o_args);
@@ -835,63 +839,63 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
     const dim3 g(l.blocks);
     switch (l.kind) {
       case B_LINE:
-        if (l.grad) hipLaunchKernelGGL((kb_line<double, RT>), g, dim3(256), 0, stream, la, mp);
-        else hipLaunchKernelGGL((kb_line<RT, RT>), g, dim3(256), 0, stream, la, mp);
+        if (l.grad) CEM_LAUNCH(c0, LID, (kb_line<double, RT>), g, dim3(256), 0, stream, la, mp);
+        else CEM_LAUNCH(c0, LID, (kb_line<RT, RT>), g, dim3(256), 0, stream, la, mp);
         break;
       case B_LINE_X:
         if (l.re == 2) {
-          if (l.grad) hipLaunchKernelGGL((kb_line_x<P, 2, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
-          else hipLaunchKernelGGL((kb_line_x<P, 2, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          if (l.grad) CEM_LAUNCH(c0, LID, (kb_line_x<P, 2, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          else CEM_LAUNCH(c0, LID, (kb_line_x<P, 2, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
         } else {
-          if (l.grad) hipLaunchKernelGGL((kb_line_x<P, 1, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
-          else hipLaunchKernelGGL((kb_line_x<P, 1, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          if (l.grad) CEM_LAUNCH(c0, LID, (kb_line_x<P, 1, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          else CEM_LAUNCH(c0, LID, (kb_line_x<P, 1, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
         }
         break;
       case B_LINE_Y:
         if (l.re == 2) {
-          if (l.grad) hipLaunchKernelGGL((kb_line_y<P, 2, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
-          else hipLaunchKernelGGL((kb_line_y<P, 2, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          if (l.grad) CEM_LAUNCH(c0, LID, (kb_line_y<P, 2, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          else CEM_LAUNCH(c0, LID, (kb_line_y<P, 2, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
         } else {
-          if (l.grad) hipLaunchKernelGGL((kb_line_y<P, 1, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
-          else hipLaunchKernelGGL((kb_line_y<P, 1, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          if (l.grad) CEM_LAUNCH(c0, LID, (kb_line_y<P, 1, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+          else CEM_LAUNCH(c0, LID, (kb_line_y<P, 1, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
         }
         break;
       case B_ELEM1_TILE:
-        if constexpr (D == 2) hipLaunchKernelGGL((kb_elem1_tile<P, PH, true, RT>), g, dim3(128), l.lds, stream, sa, mp);
+        if constexpr (D == 2) CEM_LAUNCH(c0, 1, (kb_elem1_tile<P, PH, true, RT>), g, dim3(128), l.lds, stream, sa, mp);
         break;
       case B_ELEM1_TILE2:
         if constexpr (D == 2 && tile2_roles<PH>())
-          hipLaunchKernelGGL((kb_elem1_tile2<P, PH, true, RT>), g, dim3(256), l.lds, stream, sa, mp);
+          CEM_LAUNCH(c0, 1, (kb_elem1_tile2<P, PH, true, RT>), g, dim3(256), l.lds, stream, sa, mp);
         break;
       case B_ELEM1_SYS:
         if constexpr (sys_pass1<D, P, PH, RT>())
-          hipLaunchKernelGGL((kb_elem1_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
+          CEM_LAUNCH(c0, 1, (kb_elem1_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
         break;
       case B_RESID_SYS:
         if constexpr (sys_pass1<D, P, PH, RT>())
-          hipLaunchKernelGGL((kb_resid_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
+          CEM_LAUNCH(c0, 7, (kb_resid_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
         break;
       case B_GATHER_LX:
         if (l.re == 2)
-          hipLaunchKernelGGL((kb_gather_line_x<D, P, M, 2, RT>), g, dim3(256), l.lds, stream, sa,
+          CEM_LAUNCH(c0, 3, (kb_gather_line_x<D, P, M, 2, RT>), g, dim3(256), l.lds, stream, sa,
                              reinterpret_cast<const LineFastArgs*>(base + l.o_args2), mp);
         else
-          hipLaunchKernelGGL((kb_gather_line_x<D, P, M, 1, RT>), g, dim3(256), l.lds, stream, sa,
+          CEM_LAUNCH(c0, 3, (kb_gather_line_x<D, P, M, 1, RT>), g, dim3(256), l.lds, stream, sa,
                              reinterpret_cast<const LineFastArgs*>(base + l.o_args2), mp);
         break;
       case B_GATHER_R:
-        hipLaunchKernelGGL((kb_gather_r<D, P, M, RT>), g, dim3(256), 0, stream, sa, mp);
+        CEM_LAUNCH(c0, 3, (kb_gather_r<D, P, M, RT>), g, dim3(256), 0, stream, sa, mp);
         break;
       case B_ELEM2:
         if constexpr (!(PH == EUL && D >= 2))
-          hipLaunchKernelGGL((kb_elem2<D, P, PH, RT>), g, dim3(128), 0, stream, sa, mp);
+          CEM_LAUNCH(c0, 5, (kb_elem2<D, P, PH, RT>), g, dim3(128), 0, stream, sa, mp);
         break;
       case B_ELEM2_SYS:
         if constexpr (PH == EUL && D >= 2)
-          hipLaunchKernelGGL((kb_elem2_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
+          CEM_LAUNCH(c0, 5, (kb_elem2_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
         break;
       case B_UPDATE:
-        hipLaunchKernelGGL((kb_update<D, P, PH>), g, dim3(256), 0, stream, sa, mp);
+        CEM_LAUNCH(c0, 6, (kb_update<D, P, PH>), g, dim3(256), 0, stream, sa, mp);
         break;
       default:
         return fail(CEM_EINVAL, "batched form: unknown launch");
@@ -1058,7 +1062,7 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->upd_blocks = (int)nblocks(c->N, 256);
   c->o_counts = take((size_t)c->upd_blocks * 2 * sizeof(int));
   c->inv_blocks = 256;
-  c->o_inv = take((size_t)c->inv_blocks * (c->m * 3 + 2) * 8);
+  c->o_inv = take((size_t)c->inv_blocks * inv_nvals(c->m) * 8);
   if (c->mixed) {
     const size_t mN4 = (size_t)c->m * c->N * 4;
     c->o_g32 = take((size_t)d * mN4);
@@ -1137,10 +1141,14 @@ cem_status cem_set_bounds(cem_ctx* c, int from_state, double u_min, double u_max
   if (c->kind == CEM_EULER) return CEM_OK;
   if (from_state) {
     cem_invariants inv;
+    const double keep_min = c->prm.u_min, keep_max = c->prm.u_max;
     c->prm.u_min = -INFINITY;
     c->prm.u_max = INFINITY;
     cem_status s = cem_check_invariants(c, &inv);
+    c->prm.u_min = keep_min;          // restored on every path out
+    c->prm.u_max = keep_max;
     if (s != CEM_OK && s != CEM_EIDP && s != CEM_ECFL) return s;
+    if (inv.nonfinite) return fail(CEM_EINVAL, "state holds non-finite values");
     u_min = inv.u_min[0];
     u_max = inv.u_max[0];
   }
@@ -1234,10 +1242,13 @@ cem_status cem_check_invariants(cem_ctx* c, cem_invariants* out) {
   ia.P = c->p;
   ia.Lx = c->L[0];
   ia.Ly = c->L[1];
+  ia.umin = c->prm.u_min;
+  ia.umax = c->prm.u_max;
+  ia.tol = c->prm.clamp_ulps * DBL_EPSILON * std::fmax(std::fabs(c->prm.u_min), std::fabs(c->prm.u_max));
   ia.part = c->W<double>(c->o_inv);
   hipLaunchKernelGGL(k_inv_partial, dim3(c->inv_blocks), dim3(256), 0, c->stream, ia);
   HIPCHK(hipGetLastError());
-  const int nv = c->m * 3 + 2;
+  const int nv = inv_nvals(c->m);
   std::vector<double> part((size_t)c->inv_blocks * nv);
   std::vector<int> cnt((size_t)c->upd_blocks * 2);
   double dtb[8];
@@ -1254,17 +1265,24 @@ cem_status cem_check_invariants(cem_ctx* c, cem_invariants* out) {
   }
   out->rho_min = INFINITY;
   out->p_min = INFINITY;
+  // NaN-propagating extrema (std::fmin / fmax would drop a NaN)
+  auto nmin = [](double x, double y) { return (x < y || x != x) ? x : y; };
+  auto nmax = [](double x, double y) { return (x > y || x != x) ? x : y; };
+  double nonfin = 0.0, sviol = 0.0;
   for (int b = 0; b < c->inv_blocks; ++b)
     for (int v = 0; v < nv; ++v) {
       const double x = part[(size_t)b * nv + v];
       if (v >= c->m * 3) {
-        if (!ia.euler) continue;
-        if (v == c->m * 3) out->rho_min = std::fmin(out->rho_min, x);
-        else out->p_min = std::fmin(out->p_min, x);
+        const int kind = v - c->m * 3;    // 0 rho_min, 1 p_min, 2 non-finite, 3 violations
+        if (kind == 2) nonfin += x;
+        else if (kind == 3) sviol += x;
+        else if (!ia.euler) continue;
+        else if (kind == 0) out->rho_min = nmin(out->rho_min, x);
+        else out->p_min = nmin(out->p_min, x);
       } else if (v % 3 == 0) {
-        out->u_min[v / 3] = std::fmin(out->u_min[v / 3], x);
+        out->u_min[v / 3] = nmin(out->u_min[v / 3], x);
       } else if (v % 3 == 1) {
-        out->u_max[v / 3] = std::fmax(out->u_max[v / 3], x);
+        out->u_max[v / 3] = nmax(out->u_max[v / 3], x);
       } else {
         out->mass[v / 3] += x;
       }
@@ -1273,12 +1291,16 @@ cem_status cem_check_invariants(cem_ctx* c, cem_invariants* out) {
     out->clamped += cnt[2 * (size_t)b];
     out->violations += cnt[2 * (size_t)b + 1];
   }
+  out->nonfinite = (long long)nonfin;
+  out->state_violations = (long long)sviol;
   out->dt = dtb[0];
   out->min_dt_e = dtb[1];
   out->cfl_violated = dtb[2] != 0.0;
-  if (ia.euler && !(out->rho_min > 0.0 && out->p_min > 0.0)) out->violations += 1;
+  // an invariant-domain failure is reported ahead of a CFL violation (the
+  // latter is what made the former possible)
+  if (out->violations || out->state_violations || out->nonfinite)
+    return fail(CEM_EIDP, "invariant domain violated");
   if (out->cfl_violated) return fail(CEM_ECFL, "dt exceeded min_e dt_e");
-  if (out->violations) return fail(CEM_EIDP, "invariant domain violated");
   return CEM_OK;
 }
 
@@ -1500,7 +1522,7 @@ cem_status cem_batch_step(cem_batch* b, double dt, double cfl, int nsteps) {
     cem_status st = fn.plan(b, dt, cfl);
     if (st != CEM_OK) return st;
   }
-  if (!b->use_graphs) {
+  if (!b->use_graphs || b->pr[0]->timing_mask) {
     for (int n = 0; n < nsteps; ++n)
       for (int s = 0; s < 3; ++s) {
         cem_status st = fn.stage(b, s, b->stream);
@@ -1538,6 +1560,17 @@ cem_status cem_batch_reset_counters(cem_batch* b) {
     if (st != CEM_OK) return st;
   }
   return CEM_OK;
+}
+
+cem_status cem_batch_set_timing(cem_batch* b, unsigned mask) {
+  if (!b || b->pr.empty()) return fail(CEM_EINVAL, "null batch");
+  return cem_set_timing(b->pr[0], mask);
+}
+
+cem_status cem_batch_kernel_times(cem_batch* b, double* total_ms, long long* launches, int n) {
+  if (!b || b->pr.empty()) return fail(CEM_EINVAL, "null batch");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return cem_kernel_times(b->pr[0], total_ms, launches, n);
 }
 
 cem_status cem_batch_check_invariants(cem_batch* b, cem_invariants* out, int n) {

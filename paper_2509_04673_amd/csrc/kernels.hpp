@@ -1718,15 +1718,17 @@ __device__ __forceinline__ void k_elem1_tile2_body(const StageArgs& a, int bx) {
   const int tx = li % TT::TEX, ty = li / TT::TEX;
   const int ex = ex0 + tx, ey = ey0 + ty;
   const LdsXchg xc{cem_smem + TT::words + li, NE};
+  // Lanes past the mesh edge run the body of the last element of their row
+  // or column (which lies in this tile): every lane of the block then
+  // reaches the exchange barrier inside the body once, in uniform control
+  // flow.  Their stores repeat the owner's bitwise-equal values; their dt_e
+  // repeats a value of the block.
+  const int tx1 = min(ex, ms.n[0] - 1) - ex0, ty1 = min(ey, ms.n[1] - 1) - ey0;
+  const int64_t e = (ex0 + tx1) + (int64_t)ms.n[0] * (ey0 + ty1);
+  const TN ns(a, e, tx1, ty1);
   double dt_e = 1.0e300;
-  if (ex < ms.n[0] && ey < ms.n[1]) {
-    const int64_t e = ex + (int64_t)ms.n[0] * ey;
-    const TN ns(a, e, tx, ty);
-    if (role2) elem1_body<2, P, PH, WS, RT, TN, 2>(a, e, ns, xc);
-    else dt_e = elem1_body<2, P, PH, WS, RT, TN, 1>(a, e, ns, xc);
-  } else {
-    xc.sync();                          // the one exchange barrier of the block
-  }
+  if (role2) elem1_body<2, P, PH, WS, RT, TN, 2>(a, e, ns, xc);
+  else dt_e = elem1_body<2, P, PH, WS, RT, TN, 1>(a, e, ns, xc);
   block_min_dt_n<2 * NE>(a.dtpart, dt_e, bx);
 }
 
@@ -1752,16 +1754,16 @@ __device__ __forceinline__ void k_elem1_tile3_body(const StageArgs& a, int bx) {
   const int tx = li % TT::TEX, ty = li / TT::TEX;
   const int ex = ex0 + tx, ey = ey0 + ty;
   const LdsXchg xc{cem_smem + TT::words + li, NE};
+  // lanes past the mesh edge repeat the last element of their row or column
+  // (see k_elem1_tile2_body): the exchange barrier stays in uniform control
+  // flow
+  const int tx1 = min(ex, ms.n[0] - 1) - ex0, ty1 = min(ey, ms.n[1] - 1) - ey0;
+  const int64_t e = (ex0 + tx1) + (int64_t)ms.n[0] * (ey0 + ty1);
+  const TN ns(a, e, tx1, ty1);
   double dt_e = 1.0e300;
-  if (ex < ms.n[0] && ey < ms.n[1]) {
-    const int64_t e = ex + (int64_t)ms.n[0] * ey;
-    const TN ns(a, e, tx, ty);
-    if (role == 0) elem1_body<2, P, PH, WS, RT, TN, 3>(a, e, ns, xc);
-    else if (role == 1) elem1_body<2, P, PH, WS, RT, TN, 2>(a, e, ns, xc);
-    else dt_e = elem1_body<2, P, PH, WS, RT, TN, 4>(a, e, ns, xc);
-  } else {
-    xc.sync();                          // the one exchange barrier of the block
-  }
+  if (role == 0) elem1_body<2, P, PH, WS, RT, TN, 3>(a, e, ns, xc);
+  else if (role == 1) elem1_body<2, P, PH, WS, RT, TN, 2>(a, e, ns, xc);
+  else dt_e = elem1_body<2, P, PH, WS, RT, TN, 4>(a, e, ns, xc);
   block_min_dt_n<3 * NE>(a.dtpart, dt_e, bx);
 }
 
@@ -2183,15 +2185,23 @@ __device__ __forceinline__ void k_update_body(const StageArgs& a, int bx) {
       double v = (a.rk_a == 0.0) ? ufe : a.rk_a * ubase[c] + a.rk_b * ufe;
       if (SCALAR) {
         // round-off excess is clamped and counted; larger excursions (only
-        // possible with a limiter switched off) are kept and counted
-        if (v > a.umax) {
-          if (v - a.umax <= a.clamp_tol) { ++nclamp; v = a.umax; } else { ++nbad; }
-        } else if (v < a.umin) {
-          if (a.umin - v <= a.clamp_tol) { ++nclamp; v = a.umin; } else { ++nbad; }
+        // possible with a limiter switched off) and non-finite values are
+        // kept and counted (the test is written so that NaN fails it)
+        if (!(v >= a.umin && v <= a.umax)) {
+          if (v > a.umax && v - a.umax <= a.clamp_tol) { ++nclamp; v = a.umax; }
+          else if (v < a.umin && a.umin - v <= a.clamp_tol) { ++nclamp; v = a.umin; }
+          else ++nbad;
         }
       }
       a.uout[c * N + i] = v;
       vout[c] = v;
+    }
+    if constexpr (!SCALAR) {
+      // invariant domain of the Euler equations: rho > 0 and p > 0 at every
+      // node (Theorem 1); each failed condition counts once, NaN included
+      const double pr = Phys<D, PH>::pressure(vout, a.ph);
+      nbad += !(vout[0] > 0.0);
+      nbad += !(pr > 0.0);
     }
     if constexpr (Phys<D, PH>::kNodal) {
       // nodal fluxes of the new state, read by the next stage's element passes
@@ -2321,8 +2331,14 @@ struct InvArgs {
   double gam, mnode;      // lumped-mass unit h^D / NL
   int P;
   int Lx, Ly;
-  double* part;           // [blocks][M*3 + 2]
+  double umin, umax, tol; // scalar bounds and round-off clamp width
+  double* part;           // [blocks][M*3 + 4]
 };
+
+// number of partial values per block: per component min, max, mass; then
+// rho_min, p_min (Euler), the count of non-finite values and the count of
+// failed invariant-domain conditions of the state
+__host__ __device__ inline int inv_nvals(int M) { return M * 3 + 4; }
 
 __device__ inline int node_mult(int64_t i, int D, int P, int Lx, int Ly) {
   int ik[3] = {(int)(i % Lx), 0, 0};
@@ -2334,29 +2350,42 @@ __device__ inline int node_mult(int64_t i, int D, int P, int Lx, int Ly) {
   return m;
 }
 
+// min / max that return NaN when either argument is NaN (fmin / fmax drop
+// it, which would hide a diverged state from the checks)
+__device__ __forceinline__ double nan_min(double x, double y) { return (x < y || x != x) ? x : y; }
+__device__ __forceinline__ double nan_max(double x, double y) { return (x > y || x != x) ? x : y; }
+
 __global__ void __launch_bounds__(256) k_inv_partial(InvArgs a) {
   __shared__ double red[256];
-  const int nv = a.M * 3 + 2;
+  const int nv = inv_nvals(a.M);
   const int64_t per = (a.N + gridDim.x - 1) / gridDim.x;
   const int64_t lo = blockIdx.x * per, hi = min(a.N, lo + per);
   for (int v = 0; v < nv; ++v) {
-    const int c = v / 3, kind = v % 3;
-    double acc = (v >= a.M * 3) ? 1.0e300 : (kind == 0 ? 1.0e300 : (kind == 1 ? -1.0e300 : 0.0));
+    const int c = v / 3, kind = v < a.M * 3 ? v % 3 : 3 + (v - a.M * 3);
+    // kinds: 0 min, 1 max, 2 mass, 3 rho_min, 4 p_min, 5 non-finite, 6 violations
+    const bool is_min = kind == 0 || kind == 3 || kind == 4, is_sum = kind == 2 || kind >= 5;
+    double acc = is_min ? 1.0e300 : (kind == 1 ? -1.0e300 : 0.0);
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-      if (v < a.M * 3) {
+      if (kind <= 2) {
         const double x = a.u[c * a.N + i];
-        if (kind == 0) acc = fmin(acc, x);
-        else if (kind == 1) acc = fmax(acc, x);
+        if (kind == 0) acc = nan_min(acc, x);
+        else if (kind == 1) acc = nan_max(acc, x);
         else acc += a.mnode * node_mult(i, a.D, a.P, a.Lx, a.Ly) * x;
+      } else if (kind == 5) {
+        for (int q = 0; q < a.M; ++q) acc += !isfinite(a.u[q * a.N + i]);
       } else if (a.euler) {
         const double rho = a.u[i];
-        if (v == a.M * 3) {
-          acc = fmin(acc, rho);
-        } else {
-          double m2 = 0.0;
-          for (int k = 0; k < a.D; ++k) m2 += a.u[(1 + k) * a.N + i] * a.u[(1 + k) * a.N + i];
-          acc = fmin(acc, (a.gam - 1.0) * (a.u[(a.D + 1) * a.N + i] - 0.5 * m2 / rho));
-        }
+        double m2 = 0.0;
+        for (int k = 0; k < a.D; ++k) m2 += a.u[(1 + k) * a.N + i] * a.u[(1 + k) * a.N + i];
+        const double pr = (a.gam - 1.0) * (a.u[(a.D + 1) * a.N + i] - 0.5 * m2 / rho);
+        if (kind == 3) acc = nan_min(acc, rho);
+        else if (kind == 4) acc = nan_min(acc, pr);
+        else acc += (double)(!(rho > 0.0)) + (double)(!(pr > 0.0));
+      } else if (kind == 6) {
+        // a scalar value outside the bounds by more than the clamp width,
+        // or not a number
+        const double x = a.u[i];
+        acc += !(x >= a.umin - a.tol && x <= a.umax + a.tol);
       }
     }
     red[threadIdx.x] = acc;
@@ -2364,7 +2393,7 @@ __global__ void __launch_bounds__(256) k_inv_partial(InvArgs a) {
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
       if ((int)threadIdx.x < s) {
         const double x = red[threadIdx.x], y = red[threadIdx.x + s];
-        red[threadIdx.x] = (v >= a.M * 3 || kind == 0) ? fmin(x, y) : (kind == 1 ? fmax(x, y) : x + y);
+        red[threadIdx.x] = is_sum ? x + y : (is_min ? nan_min(x, y) : nan_max(x, y));
       }
       __syncthreads();
     }

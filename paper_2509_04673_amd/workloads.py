@@ -160,17 +160,29 @@ def euler_batch_sizes(seed=0, count=512):
     return [32 + int(225 * rng.uniform()) for _ in range(count)]
 
 
-def euler_batch(seed=0, count=512, p=2, gamma=1.4, sizes=None):
+def euler_batch_octiles(seed=0, count=512):
+    """Indices of eight problems of the batched workload that span its size
+    range: the smallest, the largest and the six octiles between them (by
+    mesh size, first index among equal sizes)."""
+    sizes = euler_batch_sizes(seed, count)
+    order = sorted(range(count), key=lambda k: (sizes[k], k))
+    return [order[round(q * (count - 1) / 7)] for q in range(8)]
+
+
+def euler_batch(seed=0, count=512, p=2, gamma=1.4, sizes=None, only=None):
     """The batched Euler workload: count independent four-quadrant problems
     on the unit square, Q2, square n_k^2 meshes with n_k = 32 + floor(225 U)
     (drawn first), then each problem's quadrant states (NE, NW, SW, SE; rho,
-    vx, vy, p per quadrant) from the same generator."""
+    vx, vy, p per quadrant) from the same generator.  only: indices of the
+    problems to build (the draws of all problems still happen in order)."""
     rng = SplitMix64(seed)
     if sizes is None:
         sizes = [32 + int(225 * rng.uniform()) for _ in range(count)]
     out = []
     for k, n in enumerate(sizes):
         st = _quadrant_states(rng)
+        if only is not None and k not in only:
+            continue
         xy = node_coords(2, p, (n, n), (0.0, 0.0), (1.0, 1.0))
         east = xy[:, 0] >= 0.5
         north = xy[:, 1] >= 0.5

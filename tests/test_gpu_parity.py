@@ -127,5 +127,9 @@ def test_adaptive_dt_and_cfl_flag():
     s.upload(wl.u0)
     s.step(dt=4.0 * orc.max_dt(wl.u0))
     chk = s.check()
-    assert chk["cfl_violated"] == 1 and chk["status"] == -4
+    # the flag is set; the status is CEM_ECFL, or CEM_EIDP (reported ahead of
+    # it) when the oversized step also left the invariant domain
+    assert chk["cfl_violated"] == 1
+    assert (chk["status"] == -4 and chk["violations"] == 0) or \
+        (chk["status"] == -5 and chk["violations"] > 0), chk
     s.close()
