@@ -237,6 +237,29 @@ cem_status cem_kernel_times(cem_ctx* ctx, double* total_ms, long long* launches,
 void cem_destroy(cem_ctx* ctx);
 const char* cem_last_error(void);
 
+/* ---- No-allocation entry point -------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * cem_step_static runs nsteps SSP-RK3 steps exactly as cem_step does (the
+ * same kernels, direct launches, the same results) on the caller's device
+ * arrays u (the state, m*N float64, updated in place) and u_base (m*N
+ * float64, distinct from u), with the workspace taken from a static device
+ * array of CEM_STATIC_WORKSPACE_BYTES inside the library instead of a bound
+ * workspace.  ctx needs cem_create only; a binding made with cem_bind, if
+ * any, is set aside during the call and left as it was.  The call allocates
+ * and frees no memory.  Scalar problems need finite bounds (cem_params
+ * u_min/u_max, or an earlier cem_set_bounds).
+ * Errors: CEM_ENOMEM when cem_workspace_bytes(ctx) exceeds the static size
+ * (nothing is launched); CEM_EINVAL for bad arguments; CEM_EHIP.
+ * Every GPU the library runs on holds one copy of the array until the
+ * process ends, and every call on that GPU uses it and leaves it holding the
+ * last call's data (the call itself sets the tables and zeroes its counters
+ * first): calls that overlap on one GPU (other threads, other streams) race
+ * and must be serialised by the caller.  The call's counters, dt and CFL
+ * flag stay in the array and are not reported.  Asynchronous on the
+ * context's stream (the table upload reads host memory before returning). */
+#define CEM_STATIC_WORKSPACE_BYTES (64ll << 20)
+cem_status cem_step_static(cem_ctx* ctx, double* u, double* u_base, double dt, double cfl, int nsteps);
 
 /* ---- Batched form --------------------------------------------------------
  * count independent problems (uneven mesh sizes; the same dimension, degree,

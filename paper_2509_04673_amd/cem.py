@@ -84,6 +84,7 @@ _SIGS = [
     ("cem_set_timing", ctypes.c_int, [_P, ctypes.c_uint]),
     ("cem_kernel_times", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
+    ("cem_step_static", ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
     ("cem_destroy", None, [_P]),
     ("cem_last_error", ctypes.c_char_p, []),
     ("cem_batch_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(MeshDesc), ctypes.POINTER(PhysicsDesc),
@@ -239,6 +240,13 @@ def cem_kernel_times(ctx):
     cnt = (ctypes.c_longlong * n)()
     _check(lib().cem_kernel_times(ctx, ms, cnt, n))
     return {KERNELS[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
+def cem_step_static(ctx, u_ptr, u_base_ptr, dt=0.0, cfl=0.0, nsteps=1):
+    _check(lib().cem_step_static(ctx, _P(u_ptr), _P(u_base_ptr), float(dt), float(cfl), int(nsteps)))
+
+
+STATIC_WORKSPACE_BYTES = 64 << 20     # CEM_STATIC_WORKSPACE_BYTES of include/cem.h
 
 
 def cem_destroy(ctx):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1660,6 +1661,116 @@ cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, vo
     std::snprintf(report, report_cap, "%s", r.c_str());
   }
   return CEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// No-allocation variant of cem_step: the workspace is a static device array
+// (one copy per GPU, held until the process ends) instead of the bound one.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+__device__ __align__(256) char scratch[CEM_STATIC_WORKSPACE_BYTES];
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the static array on the current device: looked up once
+// per device (the host-side name of the array is not a device address).
+cem_status static_workspace(char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CEM_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(CEM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return CEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cem_status cem_step_static(cem_ctx* c, double* u, double* u_base, double dt, double cfl, int nsteps) {
+  if (!c || !u || !u_base) return fail(CEM_EINVAL, "null argument");
+  if (u == u_base) return fail(CEM_EINVAL, "u and u_base must differ");
+  if (nsteps < 0) return fail(CEM_EINVAL, "nsteps < 0");
+  if (!(dt > 0.0) && !(cfl > 0.0)) return fail(CEM_EINVAL, "need dt > 0 or cfl > 0");
+  if (c->kind != CEM_EULER && !c->bounds_set && !(std::isfinite(c->prm.u_min) && std::isfinite(c->prm.u_max)))
+    return fail(CEM_EINVAL, "scalar bounds not set (cem_params u_min/u_max or cem_set_bounds)");
+  if (c->ws_need > (size_t)CEM_STATIC_WORKSPACE_BYTES)
+    return fail(CEM_ENOMEM, "problem needs " + std::to_string(c->ws_need) + " workspace bytes; the static "
+                "workspace holds " + std::to_string((size_t)CEM_STATIC_WORKSPACE_BYTES));
+  char* ws = nullptr;
+  cem_status st = static_workspace(&ws);
+  if (st != CEM_OK) return st;
+  // the context's own binding is set aside for the call and restored after
+  struct Saved {
+    double *u, *u0;
+    char* ws;
+    bool bound, bounds_set, fnode_valid;
+    int lds_max;
+  } sv{c->u, c->u0, c->ws, c->bound, c->bounds_set, c->fnode_valid, c->lds_max};
+  auto restore = [&]() {
+    c->u = sv.u;
+    c->u0 = sv.u0;
+    c->ws = sv.ws;
+    c->bound = sv.bound;
+    c->bounds_set = sv.bounds_set;
+    c->fnode_valid = sv.fnode_valid;
+    c->lds_max = sv.lds_max;
+  };
+  c->u = u;
+  c->u0 = u_base;
+  c->ws = ws;
+  c->bound = true;
+  c->bounds_set = true;
+  {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+      restore();
+      return fail(CEM_EHIP, "device query failed");
+    }
+    c->lds_max = v;
+  }
+  // tables into the array; counters and the dt / CFL words start at zero
+  // (fill kernels, not memset nodes, so that a caller may capture the call)
+  hipError_t e = hipMemcpyAsync(c->ws + c->o_tab, c->tabblob.data(), c->tabblob.size() * 8,
+                                hipMemcpyHostToDevice, c->stream);
+  const int64_t ncnt = (int64_t)c->upd_blocks * 2;
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_zero_words, dim3(nblocks(ncnt, 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<unsigned*>(c->ws + c->o_counts), ncnt);
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, c->stream, reinterpret_cast<unsigned*>(c->ws + c->o_dtbuf),
+                       (int64_t)16);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    restore();
+    return fail(CEM_EHIP, std::string("static workspace set-up: ") + hipGetErrorString(e));
+  }
+  if (c->kind == CEM_KPP) {
+    // nodal fluxes of the given state
+    StageArgs a = make_args(c);
+    hipLaunchKernelGGL((k_nodal_flux<2, KPP>), dim3(nblocks(c->N, 256)), dim3(256), 0, c->stream, a);
+    if ((e = hipGetLastError()) != hipSuccess) {
+      restore();
+      return fail(CEM_EHIP, std::string("k_nodal_flux: ") + hipGetErrorString(e));
+    }
+  }
+  c->fnode_valid = true;
+  for (int n = 0; n < nsteps && st == CEM_OK; ++n) st = step_direct(c, dt, cfl);
+  restore();
+  return st;
 }
 
 }  // extern "C"

@@ -2315,6 +2315,13 @@ __global__ void __launch_bounds__(256) k_gather_line_x(StageArgs sa, LineFastArg
   k_gather_line_x_body<D, P, M, RE, RT>(sa, a, xcd_block(blockIdx.x, gridDim.x));
 }
 
+// zero fill of n 32-bit words (counters and flags that must start at zero,
+// in code a caller may capture into a graph: a kernel, not a memset node)
+__global__ void __launch_bounds__(256) k_zero_words(unsigned* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 // float -> double copy (debug taps of the mixed-precision intermediates)
 __global__ void __launch_bounds__(256) k_widen(const float* in, double* out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
