@@ -151,52 +151,124 @@ def _one(folder, suffix):
 
 
 def _counter_means(folder):
-    """Mean counter value (KiB) per kernel name over its dispatches."""
+    """Mean counter value per kernel name and counter over the dispatches:
+    {kernel: {counter: mean}}."""
     agg = {}
     for r in _read_csv(_one(folder, "counter_collection.csv")):
-        agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-    return {k: sum(v) / len(v) for k, v in agg.items()}
+        agg.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in agg.items()}
+
+
+# request-size resolved HBM counters (one pass each): bytes read are the 32,
+# 64 and 128 byte read requests of the L2 to memory; bytes written the 32
+# and 64 byte write requests (the WRITE_SIZE definition)
+RD_COUNTERS = "TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_sum"
+WR_COUNTERS = "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum"
+
+
+def _read_bytes(c):
+    return 32.0 * c["TCC_EA0_RDREQ_32B_sum"] + 64.0 * c["TCC_EA0_RDREQ_64B_sum"] + 128.0 * c["TCC_EA0_RDREQ_128B_sum"]
+
+
+def _write_bytes(c):
+    return 32.0 * (c["TCC_EA0_WRREQ_sum"] - c["TCC_EA0_WRREQ_64B_sum"]) + 64.0 * c["TCC_EA0_WRREQ_64B_sum"]
 
 
 def summarize_profile(out_dir, dest, command, copy_bytes):
     """Write the rocprofv3 summary of one bench workload: kernel-trace stats
-    and FETCH_SIZE / WRITE_SIZE per dispatch, the counters scaled by the
-    factor that makes a plain copy of copy_bytes read what it moved."""
+    and the HBM bytes per dispatch.  With the request-size passes (rd, wr)
+    the bytes are 32/64/128 B read requests and 32/64 B write requests of
+    the L2 to memory, checked on a plain device copy of copy_bytes; without
+    them, FETCH_SIZE / WRITE_SIZE scaled by the factor that makes the copy
+    read what it moved (the older calibration; FETCH_SIZE undercounts 128 B
+    requests on gfx950, which is what that factor made up for the copy)."""
     stats = _read_csv(_one(os.path.join(out_dir, "stats"), "kernel_stats.csv"))
-    counters = os.path.isdir(os.path.join(out_dir, "fetch"))   # else a kernel trace only
-    fetch = _counter_means(os.path.join(out_dir, "fetch")) if counters else {}
-    write = _counter_means(os.path.join(out_dir, "write")) if counters else {}
-    if counters:
+    resolved = os.path.isdir(os.path.join(out_dir, "rd"))
+    counters = resolved or os.path.isdir(os.path.join(out_dir, "fetch"))
+    per = {}            # kernel -> (read bytes, written bytes, FETCH_SIZE KiB, WRITE_SIZE KiB)
+    ffac = wfac = None
+    ck = None
+    if resolved:
+        rd, wr = _counter_means(os.path.join(out_dir, "rd")), _counter_means(os.path.join(out_dir, "wr"))
+        for k in rd:
+            if k in wr:
+                per[k] = (_read_bytes(rd[k]), _write_bytes(wr[k]), None, None)
+        crd, cwr = _counter_means(os.path.join(out_dir, "copy_rd")), _counter_means(os.path.join(out_dir, "copy_wr"))
+        ck = max(crd, key=lambda k: _read_bytes(crd[k]))
+        cr, cw = _read_bytes(crd[ck]), _write_bytes(cwr[ck])
+        calib = (f"HBM bytes from the request-size counters ({RD_COUNTERS}; {WR_COUNTERS}): read = "
+                 f"32 n32 + 64 n64 + 128 n128, written = 32 (n - n64) + 64 n64 per dispatch.  Check on a "
+                 f"plain device copy of {copy_bytes} bytes (`{ck}`): read {cr:.0f} B ({cr / copy_bytes:.3f} "
+                 f"of the copy), written {cw:.0f} B ({cw / copy_bytes:.3f}).")
+    elif counters:
+        fetch = _counter_means(os.path.join(out_dir, "fetch"))
+        write = _counter_means(os.path.join(out_dir, "write"))
         cf = _counter_means(os.path.join(out_dir, "copy_fetch"))
-        cw = _counter_means(os.path.join(out_dir, "copy_write"))
-        ck = max(cf, key=cf.get)
+        cwm = _counter_means(os.path.join(out_dir, "copy_write"))
+        ck = max(cf, key=lambda k: cf[k]["FETCH_SIZE"])
         kib = copy_bytes / 1024.0
-        ffac, wfac = kib / cf[ck], kib / cw[ck]
+        ffac, wfac = kib / cf[ck]["FETCH_SIZE"], kib / cwm[ck]["WRITE_SIZE"]
+        for k in fetch:
+            if k in write:
+                f, w = fetch[k]["FETCH_SIZE"], write[k]["WRITE_SIZE"]
+                per[k] = (f * ffac * 1024.0, w * wfac * 1024.0, f, w)
+        calib = (f"Counter calibration: a plain device copy of {copy_bytes} bytes (`{ck}`) reads "
+                 f"FETCH_SIZE {cf[ck]['FETCH_SIZE']:.0f} KiB and WRITE_SIZE {cwm[ck]['WRITE_SIZE']:.0f} KiB "
+                 f"per dispatch, so traffic = {ffac:.3f} x FETCH_SIZE + {wfac:.3f} x WRITE_SIZE.")
     else:
-        ck, ffac, wfac = None, None, None
+        calib = "Kernel trace only (no counter passes for this workload)."
     rows, data = [], {}
     for r in stats:
         name = r["Name"]
         if "cem::" not in name:
             continue
         avg_us = float(r["AverageNs"]) / 1e3
-        f = fetch.get(name)
-        w = write.get(name)
-        tr = None if f is None or w is None else (f * ffac + w * wfac) * 1024.0
-        data[name] = dict(calls=int(r["Calls"]), avg_us=avg_us, fetch_kib=f, write_kib=w, traffic_bytes=tr)
+        rb, wb, f, w = per.get(name, (None, None, None, None))
+        tr = None if rb is None else rb + wb
+        data[name] = dict(calls=int(r["Calls"]), avg_us=avg_us, read_bytes=rb, write_bytes=wb,
+                          fetch_kib=f, write_kib=w, traffic_bytes=tr)
         rows.append(f"| `{name}` | {r['Calls']} | {avg_us:.2f} | {float(r['Percentage']):.1f} | "
-                    + (f"{f:.0f} | {w:.0f} | {tr / 1e6:.2f} |" if tr is not None else "- | - | - |"))
-    blob = dict(digest=source_digest(), fetch_factor=ffac, write_factor=wfac, copy_kernel=ck,
-                copy_bytes=copy_bytes, kernels=data)
-    calib = (f"Counter calibration: a plain device copy of {copy_bytes} bytes (`{ck}`) reads "
-             f"FETCH_SIZE {cf[ck]:.0f} KiB and WRITE_SIZE {cw[ck]:.0f} KiB per dispatch, so traffic = "
-             f"{ffac:.3f} x FETCH_SIZE + {wfac:.3f} x WRITE_SIZE." if counters
-             else "Kernel trace only (no counter passes for this workload).")
+                    + (f"{rb / 1e6:.1f} | {wb / 1e6:.1f} | {tr / 1e6:.1f} | {tr / (avg_us * 1e-6) / 1e9:.0f} |"
+                       if tr is not None else "- | - | - | - |"))
+    sq_rows = []
+    if os.path.isdir(os.path.join(out_dir, "sq")):
+        # wave-level counters: VALU busy (% of the kernel's GPU time with a
+        # VALU instruction in flight, per CU), occupancy (% of the 32 wave
+        # slots of a CU, as rocprofv3's OccupancyPercent), waiting (% of wave
+        # cycles a wave waited to issue), FP64 flops the VALU executed
+        sq = _counter_means(os.path.join(out_dir, "sq"))
+        cu, xcc = 256.0, 8.0
+        for name, c in sq.items():
+            if "cem::" not in name or name not in data:
+                continue
+            # GRBM_GUI_ACTIVE is reported summed over the 8 XCDs, each busy
+            # for the whole dispatch: per-XCD active cycles = sum / 8
+            g = c.get("GRBM_GUI_ACTIVE", 0.0) / xcc
+            if g <= 0:
+                continue
+            valu = 100.0 * c["SQ_ACTIVE_INST_VALU"] / cu / g
+            occ = 400.0 * c["SQ_WAVE_CYCLES"] / g / cu / 32.0
+            wait = 100.0 * c["SQ_WAIT_INST_ANY"] / max(c["SQ_WAVE_CYCLES"], 1.0)
+            data[name].update(valu_busy_pct=valu, occupancy_pct=occ, wait_pct=wait,
+                              valu_insts=c["SQ_INSTS_VALU"], lds_insts=c["SQ_INSTS_LDS"], waves=c["SQ_WAVES"],
+                              fp64_flops_counter=c["SQ_INSTS_VALU_FLOPS_FP64"])
+            sq_rows.append(f"| `{name}` | {valu:.1f} | {occ:.1f} | {wait:.1f} | {c['SQ_WAVES']:.0f} | "
+                           f"{c['SQ_INSTS_VALU'] / 1e6:.1f} | {c['SQ_INSTS_LDS'] / 1e6:.2f} |")
+    blob = dict(digest=source_digest(), resolved=resolved, fetch_factor=ffac, write_factor=wfac,
+                copy_kernel=ck, copy_bytes=copy_bytes, kernels=data)
+    sq_text = ([
+        "Wave counters per dispatch (SQ_ACTIVE_INST_VALU, SQ_WAVE_CYCLES, SQ_WAIT_INST_ANY, SQ_WAVES, "
+        "SQ_INSTS_VALU, SQ_INSTS_LDS, GRBM_GUI_ACTIVE; 256 CUs in 8 XCDs, GRBM_GUI_ACTIVE summed over the "
+        "XCDs): VALU busy = 100 ACTIVE_INST_VALU / 256 / (GUI_ACTIVE / 8) (rocprofv3's VALUBusy), "
+        "occupancy = 400 WAVE_CYCLES / (GUI_ACTIVE / 8) / 256 / 32 (OccupancyPercent: % of the 32 wave "
+        "slots of a CU), waiting = 100 WAIT_INST_ANY / WAVE_CYCLES (% of wave time waiting to issue).", "",
+        "| kernel | VALU busy % | occupancy % | waiting % | waves | VALU Minsts | LDS Minsts |",
+        "|---|---|---|---|---|---|---|", *sq_rows, ""] if sq_rows else [])
     text = ["# Stage kernels: rocprofv3 kernel trace" + (" and HBM counters" if counters else ""), "",
             "Command (from the repository root, R = its absolute path):", "", "```", command.strip(), "```", "",
             calib, "",
-            "| kernel | calls | avg us | % time | FETCH_SIZE KiB | WRITE_SIZE KiB | traffic MB |",
-            "|---|---|---|---|---|---|---|", *rows, "",
+            "| kernel | calls | avg us | % time | read MB | written MB | traffic MB | GB/s |",
+            "|---|---|---|---|---|---|---|---|", *rows, "", *sq_text,
             "Machine-readable copy (read by bench.py for the roofline traffic):", "",
             "```json", json.dumps(blob), "```", ""]
     with open(dest, "w") as fh:
@@ -230,7 +302,8 @@ def profiled_traffic(fname, dominant, dofs):
     kernel's bytes per dispatch times its dispatches per stage, counted
     against the update kernel's, which runs once per stage)."""
     blob = _load_profile(fname)
-    if blob is None or blob.get("digest") != source_digest() or blob.get("fetch_factor") is None:
+    if blob is None or blob.get("digest") != source_digest() or not any(
+            r.get("traffic_bytes") is not None for r in blob.get("kernels", {}).values()):
         return None, None, blob
     ks = blob["kernels"]
     upd = [r["calls"] for n, r in ks.items() if _kernel_matches(n, DEVICE_KERNELS["update"])]
@@ -420,7 +493,14 @@ def bench_batch(args):
     wl0 = wls[0]
     del wls
     cfl = 0.5
-    tune = b.autotune(cfl=cfl, steps=1) if not args.no_autotune else dict(best=None, trials=[])
+    if args.plan:
+        o, xc, yc, e1 = (int(v) for v in args.plan.split(","))
+        cem.cem_batch_set_plan(b.b, o, xc, yc, e1)
+        tune = dict(best=dict(order=o, xlines_cap=xc, ytile_lds_bytes=yc, elem1=e1, source="--plan"), trials=[])
+    elif args.no_autotune:
+        tune = dict(best=None, trials=[])
+    else:
+        tune = b.autotune(cfl=cfl, steps=1)
     print(f"[bench] autotuned plan: {tune['best']} ({len(tune['trials'])} plans tried)", flush=True)
 
     nwarm = max(1, args.warmup)
@@ -428,6 +508,7 @@ def bench_batch(args):
     b.step(cfl=cfl, nsteps=nwarm)
     warm = cem.cem_batch_kernel_times(b.b)
     dominant = _dominant(warm, nwarm)
+    kernel_ms_per_step = sum(v[0] for v in warm.values()) / nwarm
     print("[bench] warm-up kernel ms: " + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in warm.items()
                                                    if v[1]), flush=True)
     cem.cem_batch_set_timing(b.b, 0)
@@ -488,7 +569,12 @@ def bench_batch(args):
                            elements=E, physics="euler", cfl=cfl, seed=0, precision=prec, wall_s=wall,
                            violations=int(sum(c["violations"] for c in chk)),
                            rho_min=min(c["rho_min"] for c in chk), p_min=min(c["p_min"] for c in chk),
-                           autotune=tune["best"]),
+                           autotune=tune["best"], autotune_trials=len(tune["trials"]),
+                           # what one launch per kernel costs: the graph's time per step against
+                           # the sum of the kernels' own durations (dispatch timestamps)
+                           launch_gap=dict(kernel_ms_per_step=kernel_ms_per_step,
+                                           graph_ms_per_step=ms / args.steps,
+                                           gap_frac=(ms / args.steps - kernel_ms_per_step) / (ms / args.steps))),
                roofline=roof, cpu_baseline=cpu)
     if err is not None:
         out["mixed_error"] = err
@@ -603,6 +689,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true", help="skip the mixed-form error run")
     ap.add_argument("--no-autotune", action="store_true", help="batched workload: default plan")
+    ap.add_argument("--plan", default="", metavar="ORDER,XCAP,YTILE,ELEM1",
+                    help="batched workload: this plan instead of the autotuner (cem_batch_set_plan)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--summarize-profile", metavar="DIR",

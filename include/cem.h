@@ -144,7 +144,8 @@ cem_status cem_params_default(cem_params* p);
 
 /* Creates a context: validates the configuration and builds the element
  * tables on the host (Sec. 2.1: Bernstein basis; Sec. 2.2: semi-norm (8)).
- * Size limit: m * N < 2^31 (device index arithmetic is 32-bit below it).
+ * Size limits: m * N < 2^31 and m (p+1)^d E < 2^31 (device index arithmetic
+ * of the nodal arrays and of the element vectors is 32-bit below them).
  * stream: hipStream_t for all later work.  *out receives the context.
  * No GPU memory is touched until cem_bind. */
 cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys,
@@ -293,6 +294,13 @@ cem_status cem_batch_set_bounds(cem_batch* b, int from_state, double u_min, doub
 cem_status cem_batch_step(cem_batch* b, double dt, double cfl, int nsteps);
 cem_status cem_batch_set_graphs(cem_batch* b, int enable);
 cem_status cem_batch_reset_counters(cem_batch* b);
+/* Sets the plan's knobs directly (those the autotuner searches): order 0
+ * input / 1 largest first; xlines_cap values staged per block of the
+ * x-line kernels (256 .. 65536); ytile_lds_bytes LDS bytes of a strided
+ * line tile (8192 .. 65536); elem1_kernel 0 the 2D element LDS tile, 1 the
+ * system kernels (Euler only; 3D Euler always takes them).  The next step
+ * rebuilds the plan. */
+cem_status cem_batch_set_plan(cem_batch* b, int order, int xlines_cap, int ytile_lds_bytes, int elem1_kernel);
 /* Per-kernel timing of the batched launches, as cem_set_timing /
  * cem_kernel_times (the same kernel ids; each batched launch is one record,
  * covering every problem it serves).  While a mask is set, cem_batch_step
@@ -303,12 +311,18 @@ cem_status cem_batch_kernel_times(cem_batch* b, double* total_ms, long long* lau
 /* one record per problem (n == count); returns EIDP if any problem failed an
  * invariant-domain check, else ECFL if any set its CFL flag. */
 cem_status cem_batch_check_invariants(cem_batch* b, cem_invariants* out, int n);
-/* Autotuner of the batched launches: times `steps` steps of every candidate
- * plan (lines per block of the x-line kernels: 512 .. 4096 staged values;
- * problem order: input or largest first) from the current state, keeps the
- * fastest, and restores the state.  scratch: caller-owned device memory of
- * at least offsets[count] doubles (the saved state).  report (optional):
- * a JSON record of the trials and the choice, NUL-terminated, truncated to
+/* Autotuner of the batched launches: a coordinate search over the plan's
+ * knobs from the current plan, each knob in turn over its values with the
+ * others at their best so far, timing `steps` steps of each candidate from
+ * the current state.  Knobs: problem order (input, largest first); values
+ * staged per block of the x-line kernels (512 .. 4096, lines per block);
+ * LDS bytes of a strided line tile (20, 40, 56 KiB: one, two or four runs
+ * per thread along the line); for 2D Euler the element pass-1 kernel (the
+ * 16 x 8 element LDS tile with one thread per element, or element blocks
+ * with one thread per element and component).  Keeps the fastest plan and
+ * restores the state.  scratch: caller-owned device memory of at least
+ * offsets[count] doubles (the saved state).  report (optional): a JSON
+ * record of every trial and the choice, NUL-terminated, truncated to
  * report_cap bytes.  Synchronous; resets the counters. */
 cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, void* scratch,
                               size_t scratch_bytes, char* report, size_t report_cap);

@@ -99,6 +99,7 @@ _SIGS = [
     ("cem_batch_set_graphs", ctypes.c_int, [_P, ctypes.c_int]),
     ("cem_batch_reset_counters", ctypes.c_int, [_P]),
     ("cem_batch_check_invariants", ctypes.c_int, [_P, ctypes.POINTER(Invariants), ctypes.c_int]),
+    ("cem_batch_set_plan", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("cem_batch_set_timing", ctypes.c_int, [_P, ctypes.c_uint]),
     ("cem_batch_kernel_times", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
@@ -399,6 +400,10 @@ def cem_batch_check_invariants(b, count):
     inv = (Invariants * count)()
     st = lib().cem_batch_check_invariants(b, inv, count)
     return list(inv), st
+
+
+def cem_batch_set_plan(b, order=0, xlines_cap=2048, ytile_lds_bytes=40960, elem1_kernel=0):
+    _check(lib().cem_batch_set_plan(b, int(order), int(xlines_cap), int(ytile_lds_bytes), int(elem1_kernel)))
 
 
 def cem_batch_set_timing(b, mask):

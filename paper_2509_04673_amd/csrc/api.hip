@@ -40,12 +40,10 @@ constexpr bool kSys2D = false;
 template <int PH> constexpr bool tile2_roles() { return Phys<2, PH>::M == 1; }
 
 // Euler element pass 1: the system kernels (one thread per element and
-// component, two launches) rather than the one-thread LDS tile
-template <int D, int P, int PH, class RT> constexpr bool sys_pass1() {
-  if constexpr (PH != EUL || D == 1) return false;
-  else if constexpr (D == 3) return true;
-  else return kSys2D;
-}
+// component, two launches) rather than the one-thread LDS tile.  3D Euler
+// always takes them; 2D Euler can take either (cem_ctx::elem1_sys, a knob of
+// the batch autotuner; kSys2D is the default), so both are compiled for it.
+template <int D, int PH> constexpr bool sys_capable() { return PH == EUL && D >= 2; }
 
 thread_local std::string g_err;
 
@@ -93,6 +91,7 @@ struct cem_ctx {
   int lds_max = 65536;        // LDS bytes one block may use on the bound device
   int upd_blocks = 0, inv_blocks = 0;
   size_t ndtp = 0;                 // capacity of the per-block dt_e minima
+  int elem1_sys = kSys2D ? 1 : 0;  // 2D Euler: element pass 1 on the system kernels
   bool bound = false, bounds_set = false;
   // whole-step HIP graph (captured on a private stream, launched on stream)
   bool use_graphs = true;
@@ -142,6 +141,8 @@ struct cem_batch {
   // tuning knobs of the plan (cem_batch_autotune)
   int xlines_cap = 2048;           // axis-0 line kernels: cap on values staged per block
   int order = 0;                   // 0: problems in input order, 1: largest first
+  int ytile_cap = 40960;           // strided line kernels: LDS bytes of a tile (sets the runs per thread)
+  int elem1_sys = kSys2D ? 1 : 0;  // 2D Euler: element pass 1 on the system kernels (else the LDS tile)
 };
 
 namespace {
@@ -513,9 +514,16 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     // (sensor and facets; residual).  2D: the LDS element tile with one
     // thread per element measured faster for both physics (512^2 Q3 Euler:
     // 0.46 ms per stage against 0.52 for the two system launches)
-    if constexpr (sys_pass1<D, P, PH, RT>()) {
-      cem_status st = launch_sys<D, P, PH, RT>(c, a, true);
-      if (st != CEM_OK) return st;
+    bool sys_done = false;
+    if constexpr (sys_capable<D, PH>()) {
+      if (D == 3 || c->elem1_sys) {
+        cem_status st = launch_sys<D, P, PH, RT>(c, a, true);
+        if (st != CEM_OK) return st;
+        sys_done = true;
+      }
+    }
+    if (sys_done) {
+    } else if constexpr (sys_capable<D, PH>() && D == 3) {
     } else if constexpr (D == 2) {
       using TT = Tile2<P, M>;
       const int nb = ((c->n[0] + TT::TEX - 1) / TT::TEX) * ((c->n[1] + TT::TEY - 1) / TT::TEY);
@@ -543,7 +551,8 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     constexpr int W = LineTapsV<P, RT>::W;
     const int re = line_x_re(la.ntrans, la.L, P, W, 1, 2);
     la.nlb = line_rows_per_block<P, RT>(la.L, la.ntrans, 4096, re * P);
-    const size_t lds = (size_t)la.nlb * line_row_pitch<P, RT>(la.L) * sizeof(RT);
+    const size_t lds = (size_t)la.nlb * line_row_pitch<P, RT>(la.L) * sizeof(RT) +
+                       (size_t)la.nlb * kGatherLineInts * sizeof(int);
     const unsigned grid = (unsigned)((la.ntrans + la.nlb - 1) / la.nlb);
     if (re == 2)
       CEM_LAUNCH(c, 3, (k_gather_line_x<D, P, M, 2, RT>), grid, 256, lds, c->stream, a, la);
@@ -595,8 +604,10 @@ StageArgs batch_stage_args(cem_ctx* c, int stage, double dt, double cfl) {
   a.dt_fixed = dt;
   a.cfl = cfl;
   constexpr int M = Phys<D, PH>::M;
-  if constexpr (sys_pass1<D, P, PH, RT>()) {
-    a.ndtpart = (int)SysTile<D, P, PH>::blocks(c->n);
+  bool sys = false;
+  if constexpr (sys_capable<D, PH>()) sys = D == 3 || c->elem1_sys;
+  if (sys) {
+    if constexpr (sys_capable<D, PH>()) a.ndtpart = (int)SysTile<D, P, PH>::blocks(c->n);
   } else if constexpr (D == 2) {
     using TT = Tile2<P, M>;
     a.ndtpart = ((c->n[0] + TT::TEX - 1) / TT::TEX) * ((c->n[1] + TT::TEY - 1) / TT::TEY);
@@ -612,6 +623,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
   // problems in launch order (largest first puts the long-running blocks at
   // the front of every grid)
   std::vector<cem_ctx*> all = b->pr;
+  for (cem_ctx* c : all) c->elem1_sys = b->elem1_sys;
   if (b->order == 1)
     std::stable_sort(all.begin(), all.end(), [](const cem_ctx* x, const cem_ctx* y) { return x->N > y->N; });
   constexpr bool MIX = sizeof(RT) == 4;
@@ -671,7 +683,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         } else {
           a.re = re;
           a.ky = 1;
-          while (a.ky < 4 && (8 * P * re * 2 * a.ky + S) * kTileX * (int)sizeof(RT) <= 40960) a.ky *= 2;
+          while (a.ky < 4 && (8 * P * re * 2 * a.ky + S) * kTileX * (int)sizeof(RT) <= b->ytile_cap) a.ky *= 2;
           const int TY = 8 * P * re * a.ky;
           a.gx = (int)nblocks(a.ntrans, kTileX);
           Group& G = gy[re - 1];
@@ -729,10 +741,15 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     // element pass 1
     {
       Group g;
-      constexpr bool sys = sys_pass1<D, P, PH, RT>();
-      if constexpr (sys) {
-        g.l.kind = B_ELEM1_SYS;
-        g.l.lds = SysTile<D, P, PH>::LY::bytes;
+      bool sys = false;
+      if constexpr (sys_capable<D, PH>()) {
+        sys = D == 3 || b->elem1_sys;
+        if (sys) {
+          g.l.kind = B_ELEM1_SYS;
+          g.l.lds = SysTile<D, P, PH>::LY::bytes;
+        }
+      }
+      if (sys) {
       } else if constexpr (D == 2) {
         using TT = Tile2<P, M>;
         g.l.kind = tile2_roles<PH>() ? B_ELEM1_TILE2 : B_ELEM1_TILE;
@@ -744,7 +761,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         g.sa.push_back(sa[q]);
         g.first.push_back(g.first.back() + sa[q].ndtpart);
       }
-      if constexpr (sys) {
+      if (sys) {
         // the residual half of the system pass: the same blocks
         Group gr = g;
         gr.l.kind = B_RESID_SYS;
@@ -772,7 +789,8 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
           G.sa.push_back(sa[q]);
           G.lf.push_back(a);
           G.first.push_back(G.first.back() + (int)((a.ntrans + a.nlb - 1) / a.nlb));
-          G.l.lds = std::max(G.l.lds, (size_t)a.nlb * line_row_pitch<P, RT>(a.L) * sizeof(RT));
+          G.l.lds = std::max(G.l.lds, (size_t)a.nlb * line_row_pitch<P, RT>(a.L) * sizeof(RT) +
+                                          (size_t)a.nlb * kGatherLineInts * sizeof(int));
         } else {
           gr.sa.push_back(sa[q]);
           gr.first.push_back(gr.first.back() + (int)nblocks(c->N, 256));
@@ -869,11 +887,11 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
           CEM_LAUNCH(c0, 1, (kb_elem1_tile2<P, PH, true, RT>), g, dim3(256), l.lds, stream, sa, mp);
         break;
       case B_ELEM1_SYS:
-        if constexpr (sys_pass1<D, P, PH, RT>())
+        if constexpr (sys_capable<D, PH>())
           CEM_LAUNCH(c0, 1, (kb_elem1_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
         break;
       case B_RESID_SYS:
-        if constexpr (sys_pass1<D, P, PH, RT>())
+        if constexpr (sys_capable<D, PH>())
           CEM_LAUNCH(c0, 7, (kb_resid_sys<D, P, PH, RT>), g, dim3(M * SysTile<D, P, PH>::EB), l.lds, stream, sa, mp);
         break;
       case B_GATHER_LX:
@@ -1019,6 +1037,10 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   }
   c->nl = 1;
   for (int k = 0; k < d; ++k) c->nl *= (p + 1);
+  if ((int64_t)c->m * c->nl * c->E >= (int64_t(1) << 31)) {
+    delete c;
+    return fail(CEM_EINVAL, "mesh too large: the element vectors, m (p+1)^d E values, must stay below 2^31");
+  }
   c->prm = *prm;
   c->mixed = prm->precision == CEM_FP32_MIXED;
   for (int k = 0; k < 3; ++k) c->ph.vel[k] = k < d ? phys->velocity[k] : 0.0;
@@ -1563,6 +1585,23 @@ cem_status cem_batch_reset_counters(cem_batch* b) {
   return CEM_OK;
 }
 
+cem_status cem_batch_set_plan(cem_batch* b, int order, int xlines_cap, int ytile_lds_bytes, int elem1_kernel) {
+  if (!b) return fail(CEM_EINVAL, "null batch");
+  if (order < 0 || order > 1) return fail(CEM_EINVAL, "order must be 0 (input) or 1 (largest first)");
+  if (xlines_cap < 256 || xlines_cap > 65536) return fail(CEM_EINVAL, "xlines_cap out of [256, 65536]");
+  if (ytile_lds_bytes < 8192 || ytile_lds_bytes > 65536) return fail(CEM_EINVAL, "ytile_lds_bytes out of [8192, 65536]");
+  if (elem1_kernel < 0 || elem1_kernel > 1) return fail(CEM_EINVAL, "elem1_kernel must be 0 (tile) or 1 (system)");
+  if (elem1_kernel == 1 && !(b->kind == CEM_EULER && b->d >= 2))
+    return fail(CEM_EINVAL, "the system element kernels serve the Euler equations in 2D and 3D");
+  b->order = order;
+  b->xlines_cap = xlines_cap;
+  b->ytile_cap = ytile_lds_bytes;
+  b->elem1_sys = elem1_kernel;
+  batch_drop_graph(b);
+  b->plan_dt = b->plan_cfl = -1.0;     // the next step rebuilds the plan
+  return CEM_OK;
+}
+
 cem_status cem_batch_set_timing(cem_batch* b, unsigned mask) {
   if (!b || b->pr.empty()) return fail(CEM_EINVAL, "null batch");
   return cem_set_timing(b->pr[0], mask);
@@ -1600,46 +1639,80 @@ cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, vo
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  const int caps[4] = {512, 1024, 2048, 4096};
-  struct Trial { int cap, order; float ms; };
+  // the knobs of a plan and the values tried: problem order, values staged
+  // per block of the x-line kernels, LDS bytes of a strided line tile (runs
+  // per thread ky = 1, 2, 4), and for 2D Euler the element pass-1 kernel
+  // (16 x 8 element LDS tile with one thread per element, or blocks of 32/64
+  // elements with one thread per element and component)
+  struct Knobs { int order, xcap, ycap, sys; };
+  struct Trial { Knobs k; float ms; };
+  const bool sys_choice = b->d == 2 && b->kind == CEM_EULER;
+  const std::vector<int> orders = {0, 1}, xcaps = {512, 1024, 2048, 4096}, ycaps = {20480, 40960, 57344};
+  const std::vector<int> syss = sys_choice ? std::vector<int>{0, 1} : std::vector<int>{b->elem1_sys};
   std::vector<Trial> trials;
   cem_status st = CEM_OK;
-  for (int order = 0; order < 2 && st == CEM_OK; ++order)
-    for (int ci = 0; ci < 4 && st == CEM_OK; ++ci) {
-      b->xlines_cap = caps[ci];
-      b->order = order;
-      batch_drop_graph(b);
-      b->plan_dt = b->plan_cfl = -1.0;
-      if ((st = restore()) != CEM_OK) break;
-      if ((st = cem_batch_step(b, dt, cfl, 1)) != CEM_OK) break;      // plan, capture, warm
-      if ((st = restore()) != CEM_OK) break;
-      if ((st = cem_batch_step(b, dt, cfl, 1)) != CEM_OK) break;      // nodal fluxes outside the timing
-      if ((st = restore()) != CEM_OK) break;
-      for (cem_ctx* c : b->pr) c->fnode_valid = c->kind != CEM_KPP;
-      if (b->kind == CEM_KPP) {
-        // KPP: the restored state needs its nodal fluxes before timing
-        for (cem_ctx* c : b->pr) {
-          StageArgs a = make_args(c);
-          hipLaunchKernelGGL((k_nodal_flux<2, KPP>), dim3(nblocks(c->N, 256)), dim3(256), 0, c->stream, a);
-          c->fnode_valid = true;
-        }
+  auto run_trial = [&](const Knobs& k, float* ms_out) -> cem_status {
+    b->order = k.order;
+    b->xlines_cap = k.xcap;
+    b->ytile_cap = k.ycap;
+    b->elem1_sys = k.sys;
+    batch_drop_graph(b);
+    b->plan_dt = b->plan_cfl = -1.0;
+    cem_status s2;
+    if ((s2 = restore()) != CEM_OK) return s2;
+    if ((s2 = cem_batch_step(b, dt, cfl, 1)) != CEM_OK) return s2;      // plan, capture, warm
+    if ((s2 = restore()) != CEM_OK) return s2;
+    if ((s2 = cem_batch_step(b, dt, cfl, 1)) != CEM_OK) return s2;      // nodal fluxes outside the timing
+    if ((s2 = restore()) != CEM_OK) return s2;
+    for (cem_ctx* c : b->pr) c->fnode_valid = c->kind != CEM_KPP;
+    if (b->kind == CEM_KPP) {
+      // KPP: the restored state needs its nodal fluxes before timing
+      for (cem_ctx* c : b->pr) {
+        StageArgs a = make_args(c);
+        hipLaunchKernelGGL((k_nodal_flux<2, KPP>), dim3(nblocks(c->N, 256)), dim3(256), 0, c->stream, a);
+        c->fnode_valid = true;
       }
-      HIPCHK(hipEventRecord(e0, b->stream));
-      if ((st = cem_batch_step(b, dt, cfl, steps)) != CEM_OK) break;
-      HIPCHK(hipEventRecord(e1, b->stream));
-      HIPCHK(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      trials.push_back({caps[ci], order, ms / steps});
     }
+    HIPCHK(hipEventRecord(e0, b->stream));
+    if ((s2 = cem_batch_step(b, dt, cfl, steps)) != CEM_OK) return s2;
+    HIPCHK(hipEventRecord(e1, b->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    *ms_out = ms / steps;
+    return CEM_OK;
+  };
+  // coordinate search from the current plan: each knob in turn over its
+  // values, the others at their best so far
+  Knobs best_k{b->order, b->xlines_cap, b->ytile_cap, b->elem1_sys};
+  float best_ms = 0.0f;
+  if ((st = run_trial(best_k, &best_ms)) == CEM_OK) trials.push_back({best_k, best_ms});
+  for (int knob = 0; knob < 4 && st == CEM_OK; ++knob) {
+    const std::vector<int>& vals = knob == 0 ? orders : knob == 1 ? xcaps : knob == 2 ? ycaps : syss;
+    for (int v : vals) {
+      Knobs k = best_k;
+      int* slot = knob == 0 ? &k.order : knob == 1 ? &k.xcap : knob == 2 ? &k.ycap : &k.sys;
+      *slot = v;
+      bool seen = false;       // each plan is timed once
+      for (const Trial& t : trials)
+        seen = seen || (t.k.order == k.order && t.k.xcap == k.xcap && t.k.ycap == k.ycap && t.k.sys == k.sys);
+      if (seen) continue;
+      float ms = 0.0f;
+      if ((st = run_trial(k, &ms)) != CEM_OK) break;
+      trials.push_back({k, ms});
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_k = k;
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != CEM_OK) return st;
-  const Trial* best = &trials[0];
-  for (const Trial& t : trials)
-    if (t.ms < best->ms) best = &t;
-  b->xlines_cap = best->cap;
-  b->order = best->order;
+  b->order = best_k.order;
+  b->xlines_cap = best_k.xcap;
+  b->ytile_cap = best_k.ycap;
+  b->elem1_sys = best_k.sys;
   batch_drop_graph(b);
   b->plan_dt = b->plan_cfl = -1.0;
   st = restore();
@@ -1648,16 +1721,17 @@ cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, vo
   st = cem_batch_reset_counters(b);
   if (st != CEM_OK) return st;
   if (report && report_cap) {
+    auto rec = [&](const Knobs& k, float ms) {
+      char buf[256];
+      std::snprintf(buf, sizeof(buf),
+                    "{\"order\": \"%s\", \"xlines_cap\": %d, \"ytile_lds_bytes\": %d, \"elem1\": \"%s\", "
+                    "\"ms_per_step\": %.4f}",
+                    k.order ? "largest_first" : "input", k.xcap, k.ycap, k.sys ? "system" : "tile", ms);
+      return std::string(buf);
+    };
     std::string r = "{\"trials\": [";
-    char buf[160];
-    for (size_t k = 0; k < trials.size(); ++k) {
-      std::snprintf(buf, sizeof(buf), "%s{\"xlines_cap\": %d, \"order\": \"%s\", \"ms_per_step\": %.4f}",
-                    k ? ", " : "", trials[k].cap, trials[k].order ? "largest_first" : "input", trials[k].ms);
-      r += buf;
-    }
-    std::snprintf(buf, sizeof(buf), "], \"best\": {\"xlines_cap\": %d, \"order\": \"%s\", \"ms_per_step\": %.4f}}",
-                  best->cap, best->order ? "largest_first" : "input", best->ms);
-    r += buf;
+    for (size_t k = 0; k < trials.size(); ++k) r += (k ? ", " : "") + rec(trials[k].k, trials[k].ms);
+    r += "], \"best\": " + rec(best_k, best_ms) + "}";
     std::snprintf(report, report_cap, "%s", r.c_str());
   }
   return CEM_OK;

@@ -553,6 +553,17 @@ __device__ __forceinline__ int line_wrap(int k, int W, int L) {
   return x;
 }
 
+// Integer division by a block-uniform divisor d >= 1 without a division
+// per use: q = floor(n / d) = umulhi(n, ceil(2^32 / d)) for d >= 2, exact
+// whenever n d < 2^32 (the error of the rounded reciprocal, below n / 2^32,
+// stays under 1 / d).  The staging and run loops of the line kernels index
+// a block's lines with n < 2^17 and d < 2^13.
+struct DivMagic {
+  unsigned d, m;
+  __device__ __forceinline__ explicit DivMagic(unsigned d_) : d(d_), m(d_ > 1u ? 0xFFFFFFFFu / d_ + 1u : 0u) {}
+  __device__ __forceinline__ unsigned div(unsigned n) const { return d > 1u ? __umulhi(n, m) : n; }
+};
+
 // Axis 0 (contiguous lines): a block stages nlb whole lines in LDS (one
 // coalesced copy, periodic wrap inside LDS) and each thread computes runs of
 // R outputs.  Consecutive lanes take consecutive runs.
@@ -567,24 +578,28 @@ __device__ __forceinline__ void k_line_x_body(const LineFastArgs& a, int bx) {
   const TI* src = static_cast<const TI*>(a.in) + t0 * L;   // lines of axis 0 are contiguous
   const int LS = line_row_len<P, TO>(L), LP = line_row_pitch<P, TO>(L);
   // four values per thread and pass: the loads are issued before the stores
+  // (block indices by magic-number division: an integer division per value
+  // made the staging cost as much as the taps of the short lines)
   const int nv = nl * LS, nt = (int)blockDim.x;
+  const DivMagic dls((unsigned)LS);
   for (int i0 = threadIdx.x; i0 < nv; i0 += 4 * nt) {
     TO v[4];
+    int slot[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int i = i0 + k * nt, line = i / LS;
-      v[k] = i < nv ? (TO)src[line * L + line_wrap(i - line * LS, W, L)] : (TO)0;
+      const int i = i0 + k * nt, line = (int)dls.div((unsigned)i), pos = i - line * LS;
+      slot[k] = line * LP + lds_slot<R>(pos);
+      v[k] = i < nv ? (TO)src[line * L + line_wrap(pos, W, L)] : (TO)0;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int i = i0 + k * nt, line = i / LS;
-      if (i < nv) sm[line * LP + lds_slot<R>(i - line * LS)] = v[k];
-    }
+    for (int k = 0; k < 4; ++k)
+      if (i0 + k * nt < nv) sm[slot[k]] = v[k];
   }
   __syncthreads();
   const int runs = (L + R - 1) / R;
+  const DivMagic drun((unsigned)runs);
   for (int g = threadIdx.x; g < nl * runs; g += blockDim.x) {
-    const int line = g / runs, s = (g - line * runs) * R;
+    const int line = (int)drun.div((unsigned)g), s = (g - line * runs) * R;
     const TO* row = sm + line * LP + lds_slot<R>(s);
     auto ld = [&](int j) { return row[lds_slot<R>(j)]; };
     TO acc[R];
@@ -642,21 +657,22 @@ __device__ __forceinline__ void k_line_y_body(const LineFastArgs& a, int bx, int
   const int L = a.L;
   TO* sm = reinterpret_cast<TO*>(cem_smem);
   const TI* in = static_cast<const TI*>(a.in);
-  const int64_t t0 = (int64_t)bx * kTileX;
+  const int t0 = bx * kTileX;
   const int s0 = by * TY;
   const int tx = threadIdx.x % kTileX, rg = threadIdx.x / kTileX;   // rg = 0..7
-  // base of transverse line t and the stride along the line
-  auto base_of = [&](int64_t t) -> int64_t {
-    const int64_t comp = t / a.NT, rr = t - comp * a.NT;
+  // base of transverse line t and the stride along the line; 32-bit: every
+  // offset is below m N < 2^31 (checked at create)
+  auto base_of = [&](int t) -> int {
+    const int NT = (int)a.NT, comp = t / NT, rr = t - comp * NT;
     if (a.axis == 1) {
-      const int64_t x = rr % a.L0, z = rr / a.L0;
-      return comp * a.N + x + z * (int64_t)a.L0 * a.L1;
+      const int x = rr % a.L0, z = rr / a.L0;
+      return comp * (int)a.N + x + z * a.L0 * a.L1;
     }
-    return comp * a.N + rr;
+    return comp * (int)a.N + rr;
   };
-  const int64_t sl = (a.axis == 1) ? (int64_t)a.L0 : (int64_t)a.L0 * a.L1;
+  const int sl = (a.axis == 1) ? a.L0 : a.L0 * a.L1;
   const bool have = t0 + tx < a.ntrans;
-  const int64_t b = have ? base_of(t0 + tx) : 0;
+  const int b = have ? base_of(t0 + tx) : 0;
   int p = s0 - W;
   if (p < 0) p += L;
   p += rg;
@@ -667,7 +683,7 @@ __device__ __forceinline__ void k_line_y_body(const LineFastArgs& a, int bx, int
     TO v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      v[k] = have ? (TO)in[b + (int64_t)p * sl] : (TO)0;
+      v[k] = have ? (TO)in[b + p * sl] : (TO)0;
       p += 8;
       if (p >= L) p -= L;
       if (p >= L) p -= L;
@@ -676,7 +692,7 @@ __device__ __forceinline__ void k_line_y_body(const LineFastArgs& a, int bx, int
     for (int k = 0; k < 8; ++k) sm[(row + 8 * k) * kTileX + tx] = v[k];
   }
   for (; row < ROWS; row += 8) {
-    sm[row * kTileX + tx] = have ? (TO)in[b + (int64_t)p * sl] : (TO)0;
+    sm[row * kTileX + tx] = have ? (TO)in[b + p * sl] : (TO)0;
     p += 8;
     if (p >= L) p -= L;
     if (p >= L) p -= L;
@@ -694,7 +710,7 @@ __device__ __forceinline__ void k_line_y_body(const LineFastArgs& a, int bx, int
     line_run<P, RE>(static_cast<const TO*>(a.w), ld, acc);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (s + r < L) out[b + (int64_t)(s + r) * sl] = acc[r];
+      if (s + r < L) out[b + (s + r) * sl] = acc[r];
   }
 }
 
@@ -923,6 +939,17 @@ template <int D, int P, int M> struct GlobalNodes {
     asm volatile("" : "+v"(nd));
     return a->u[c * a->mesh.N + nd];
   }
+  // direction k of the projected gradient of component c
+  template <class V>
+  __device__ __forceinline__ void load_grad_k(int c, int k, V* gk) const {
+    constexpr int NL = ipow(P + 1, D);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int64_t q = ((int64_t)k * M + c) * a->mesh.N + local_node<D, P>(j, off);
+      if constexpr (sizeof(V) == 4) gk[j] = a->g32[q];
+      else gk[j] = a->g[q];
+    }
+  }
   // projected gradient: g (float64) or g32 (mixed precision)
   template <class V>
   __device__ __forceinline__ void load_grad(int c, V (*gk)[ipow(P + 1, D)]) const {
@@ -977,6 +1004,17 @@ template <int P, int M> struct TileNodes2 {
     const int b = base + s * P * (k == 0 ? 1 : TT::NX);
 #pragma unroll
     for (int j = 0; j < NL; ++j) cn[j] = cem_smem[c * TT::NXY + b + (j / (P + 1)) * TT::NX + j % (P + 1)];
+  }
+  template <class V>
+  __device__ __forceinline__ void load_grad_k(int c, int k, V* gk) const {
+    if constexpr (TT::stage_g) {
+      const double* gs = cem_smem + M * TT::NXY;
+#pragma unroll
+      for (int j = 0; j < NL; ++j)
+        gk[j] = (V)gs[(k * M + c) * TT::GXY + gbase + (j / (P + 1)) * TT::GX + j % (P + 1)];
+    } else {
+      gl.load_grad_k(c, k, gk);
+    }
   }
   template <class V>
   __device__ __forceinline__ void load_grad(int c, V (*gk)[NL]) const {
@@ -1113,14 +1151,24 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   const MeshArgs& ms = a.mesh;
   const int64_t E = ms.E;
   const double h = ms.h;
-  double U[M][NL];
-  ns.load_own(U);
+  // systems keep no register copy of the element's coefficients: they are
+  // read from the tile (or memory) where they are needed (with the one
+  // thread per element of the 2D Euler tile, the copy, the candidate
+  // extensions and the facet section's temporaries took more than 256
+  // registers and spilled)
+  constexpr bool KEEPU = M == 1;
+  double U[KEEPU ? M : 1][KEEPU ? NL : 1];
+  if constexpr (KEEPU) ns.load_own(U);
+  auto Uc = [&](int c, int j) -> double {
+    if constexpr (KEEPU) return U[c][j];
+    else return ns.own(c, j);
+  };
   double ue[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) {
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < NL; ++j) s += U[c][j];
+    for (int j = 0; j < NL; ++j) s += Uc(c, j);
     ue[c] = s * (1.0 / NL);
   }
 
@@ -1146,7 +1194,9 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   // minimum.  Candidates are extended into K_e by the blossom maps; every
   // semi-norm is the same packed quadratic form on coefficients shifted by
   // their first entry (exactly zero for constant polynomials).
-  constexpr bool keepx = 2 * D * NL <= 64;
+  // scalar problems keep the extended candidates for the second sweep;
+  // systems recompute them (register pressure)
+  constexpr bool keepx = M == 1 && 2 * D * NL <= 64;
   double nbr_mean[2 * D][M];
   double gam = 0.0, nu = 0.0;
   if constexpr (ROLE == 4) {
@@ -1168,9 +1218,9 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     RT ct[NL];
     // systems: the component is a runtime value here, so the coefficients
     // are re-read (U[c][j] would index a register array dynamically)
-    const double u00 = M > 1 ? ns.own(c, 0) : U[0][0];
+    const double u00 = M > 1 ? ns.own(c, 0) : Uc(0, 0);
 #pragma unroll
-    for (int j = 0; j < NL; ++j) ct[j] = (RT)((M > 1 ? ns.own(c, j) : U[0][j]) - u00);
+    for (int j = 0; j < NL; ++j) ct[j] = (RT)((M > 1 ? ns.own(c, j) : Uc(0, j)) - u00);
     RT beta[1 + 2 * D];
     beta[0] = qsym<NL>(T, SF::qp, ct);
     RT X[keepx ? 2 * D : 1][NL];
@@ -1179,9 +1229,14 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
       double cn[NL], sum = 0.0;
       RT cr[NL], xe[NL];
       ns.load_nbr(c, l, cn);
+      if constexpr (M == 1) {
+        // systems recompute the neighbour means in the facet section (a
+        // register array indexed by the runtime component would sit in
+        // scratch, and these values would stay live through the residual)
 #pragma unroll
-      for (int j = 0; j < NL; ++j) sum += cn[j];
-      nbr_mean[l][c] = sum * (1.0 / NL);
+        for (int j = 0; j < NL; ++j) sum += cn[j];
+        nbr_mean[l][c] = sum * (1.0 / NL);
+      }
 #pragma unroll
       for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
       ax<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cr, xe);
@@ -1240,7 +1295,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   for (int j = 0; j < NL; ++j) {
     double uj[M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) uj[c] = U[c][j];
+    for (int c = 0; c < M; ++c) uj[c] = Uc(c, j);
     lam = fmax(lam, PHY::node_speed(uj, a.ph));
   }
   nu = lam * h / (2.0 * P);
@@ -1293,7 +1348,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
       for (int c = 0; c < M; ++c) {
         RT uc[NL];
 #pragma unroll
-        for (int j = 0; j < NL; ++j) uc[j] = MIX ? (RT)(U[c][j] - ue[c]) : (RT)U[c][j];
+        for (int j = 0; j < NL; ++j) uc[j] = MIX ? (RT)(Uc(c, j) - ue[c]) : (RT)Uc(c, j);
         tensor_apply<D, P>(T, mv, false, uc, uq[c]);
       }
     }
@@ -1309,6 +1364,32 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     static_for<M>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
       const TabRef<RT>& Tc = T;
+      // the stabilisation first, one gradient direction at a time (fewer
+      // live registers than both directions of g with the flux sums)
+      RT st[NL];
+      {
+        RT s1[NL], s2[NL];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) s1[i] = s2[i] = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          int ms1[3] = {SF::g, SF::g, SF::g}, ms2[3] = {SF::g, SF::g, SF::g};
+          ms1[k] = SF::k1;
+          ms2[k] = SF::ct;
+          RT t[NL], v[NL];
+#pragma unroll
+          for (int i = 0; i < NL; ++i) v[i] = MIX ? (RT)(ns.own(c, i) - ue[c]) : (RT)ns.own(c, i);
+          tensor_apply<D, P>(Tc, ms1, false, v, t);
+#pragma unroll
+          for (int i = 0; i < NL; ++i) s1[i] += t[i];
+          ns.load_grad_k(c, k, v);
+          tensor_apply<D, P>(Tc, ms2, false, v, t);
+#pragma unroll
+          for (int i = 0; i < NL; ++i) s2[i] += t[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NL; ++i) st[i] = sa * s1[i] - sg * s2[i];
+      }
       RT Rc[NL];
 #pragma unroll
       for (int i = 0; i < NL; ++i) Rc[i] = 0;
@@ -1338,28 +1419,8 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
 #pragma unroll
         for (int i = 0; i < NL; ++i) Rc[i] += t[i];
       }
-      RT gk[D][NL], s1[NL], s2[NL], uc[NL];
-      ns.load_grad(c, gk);
 #pragma unroll
-      for (int i = 0; i < NL; ++i) {
-        s1[i] = s2[i] = 0;
-        uc[i] = MIX ? (RT)(ns.own(c, i) - ue[c]) : (RT)ns.own(c, i);
-      }
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        int ms1[3] = {SF::g, SF::g, SF::g}, ms2[3] = {SF::g, SF::g, SF::g};
-        ms1[k] = SF::k1;
-        ms2[k] = SF::ct;
-        RT t[NL];
-        tensor_apply<D, P>(Tc, ms1, false, uc, t);
-#pragma unroll
-        for (int i = 0; i < NL; ++i) s1[i] += t[i];
-        tensor_apply<D, P>(Tc, ms2, false, gk[k], t);
-#pragma unroll
-        for (int i = 0; i < NL; ++i) s2[i] += t[i];
-      }
-#pragma unroll
-      for (int i = 0; i < NL; ++i) store_rc(c, i, (RT)hpow * Rc[i] - (sa * s1[i] - sg * s2[i]));
+      for (int i = 0; i < NL; ++i) store_rc(c, i, (RT)hpow * Rc[i] - st[i]);
     });
   }
   if constexpr ((ROLE == 0 || ROLE == 2) && !SEQ) {
@@ -1371,7 +1432,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     for (int c = 0; c < M; ++c) {
       RT uc[NL];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) uc[j] = MIX ? (RT)(U[c][j] - ue[c]) : (RT)U[c][j];
+      for (int j = 0; j < NL; ++j) uc[j] = MIX ? (RT)(Uc(c, j) - ue[c]) : (RT)Uc(c, j);
       tensor_apply<D, P>(T, mv, false, uc, uq[c]);
     }
     RT wq[NL];
@@ -1470,7 +1531,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
 #pragma unroll
       for (int i = 0; i < NL; ++i) {
         s1[c][i] = s2[c][i] = 0;
-        uc[i] = MIX ? (RT)(U[c][i] - ue[c]) : (RT)U[c][i];
+        uc[i] = MIX ? (RT)(Uc(c, i) - ue[c]) : (RT)Uc(c, i);
       }
 #pragma unroll
       for (int k = 0; k < D; ++k) {
@@ -1503,7 +1564,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
       s1[i] = s2[i] = 0;
-      uc[i] = MIX ? (RT)(U[c][i] - ue[c]) : (RT)U[c][i];   // the stiffness annihilates constants
+      uc[i] = MIX ? (RT)(Uc(c, i) - ue[c]) : (RT)Uc(c, i);   // the stiffness annihilates constants
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -1529,12 +1590,30 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   double lamsum = 0.0, fLsum[M], fHout[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) fLsum[c] = fHout[c] = 0.0;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
+  // one facet at a time: the axis a compile-time constant (the facet-node
+  // indices stay constants), and for systems the two sides a rolled loop,
+  // so that the Riemann speeds (three pow each) and facet sums of all facets
+  // are not in flight at once (in the one-thread 2D Euler tile that alone
+  // took more than 256 registers)
+  static_for<D>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
     const double* fo = foa + k * M;
+    auto facet = [&](int side) {
+      double unb[M];
+      if constexpr (M > 1 && ROLE != 4) {
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const double* un = nbr_mean[2 * k + side];
+        for (int c = 0; c < M; ++c) {
+          double cn[NL], sum = 0.0;
+          ns.load_nbr(c, 2 * k + side, cn);
+#pragma unroll
+          for (int j = 0; j < NL; ++j) sum += cn[j];
+          unb[c] = sum * (1.0 / NL);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) unb[c] = nbr_mean[2 * k + side][c];
+      }
+      const double* un = unb;
       double fn[M];
       PHY::flux(k, un, fn, a.ph);
       const double* uL = side ? ue : un;
@@ -1554,7 +1633,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
         } else {
           double uj[M];
 #pragma unroll
-          for (int c = 0; c < M; ++c) uj[c] = SEQ ? ns.own(c, j) : U[c][j];
+          for (int c = 0; c < M; ++c) uj[c] = SEQ ? ns.own(c, j) : Uc(c, j);
           PHY::flux(k, uj, fj, a.ph);
         }
 #pragma unroll
@@ -1569,8 +1648,15 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
         fHout[c] += side ? fH[c] * (1.0 / NF) : -(fH[c] * (1.0 / NF));
         if (side) a.fahi[((int64_t)k * M + c) * E + e] = fLc - fH[c] * (1.0 / NF);
       }
+    };
+    if constexpr (M == 1) {
+      facet(0);
+      facet(1);
+    } else {
+#pragma unroll 1
+      for (int side = 0; side < 2; ++side) facet(side);
     }
-  }
+  });
   double dt_e = h / lamsum;                                   // eq. (40)
   if (a.flux_mode != 0) {
     // flux limiter off (Sec. 4.3, steps 3-4): f_ee' = f^H and ubar^e =
@@ -1580,7 +1666,7 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
       if constexpr (SEQ)
         dt_e = subcell_dt<D, P, PHY>([&](int c, int j) { return ns.own(c, j); }, ue, h, a.ph);
       else
-        dt_e = subcell_dt<D, P, PHY>([&](int c, int j) { return U[c][j]; }, ue, h, a.ph);
+        dt_e = subcell_dt<D, P, PHY>([&](int c, int j) { return Uc(c, j); }, ue, h, a.ph);
     } else if constexpr (PH == EUL) {
       double dl[M];
 #pragma unroll
@@ -2257,6 +2343,9 @@ __global__ void __launch_bounds__(1024) k_stage_dt(StageArgs a) {
   if (threadIdx.x == 0) stage_dt_record(a, mn);
 }
 
+// LDS words of the fused gather's per-line slot table (ints per line)
+constexpr int kGatherLineInts = 10;
+
 // Residual assembly fused with the first mass-solve pass (axis 0): a block
 // gathers r = sum_e (element residual vectors) for nlb whole x-lines into LDS
 // (fixed element order per node, as k_gather_r), stores r, then applies the
@@ -2273,32 +2362,85 @@ __device__ __forceinline__ void k_gather_line_x_body(const StageArgs& sa, const 
   const int lpc = (int)(N / L);                  // lines per component
   const int LS = line_row_len<P, RT>(L), LP = line_row_pitch<P, RT>(L);
   static_assert(R % 2 == 1 || R >= (P % 2 == 0 ? P : 2 * P), "row pitch too short for this run length");
-  for (int q = threadIdx.x; q < nl * L; q += blockDim.x) {
-    const int ql = q / L, x = q - ql * L;
+  // Per line of the block: its component and the transverse element slots
+  // of its nodes (one or two per axis > 0, lower element first), so that a
+  // node's elements follow from its x position alone.  32-bit offsets: the
+  // element vectors hold m (p+1)^d E < 2^31 values (checked at create).
+  // ln[ql]: [0] component, [1] slots, [2..5] element offset n0 (ey + n1 ez),
+  // [6..9] local offset (p+1) (ay + (p+1) az), in the order of k_gather_r
+  int* ln = reinterpret_cast<int*>(sm + (size_t)a.nlb * LP);
+  for (int ql = threadIdx.x; ql < nl; ql += blockDim.x) {
     const int line = (int)t0 + ql, c = line / lpc;
-    const int64_t i = (int64_t)(line - c * lpc) * L + x;
-    const int64_t g = c * N + i;                   // component-major flat index
-    int64_t eids[8];
-    int locs[8];
-    const int nrec = node_elements<D, P>(i, sa.mesh, eids, locs);
+    unsigned r = (unsigned)(line - c * lpc);
+    int ik[3] = {0, 0, 0};
+    if (D > 1) {
+      ik[1] = (int)(r % (unsigned)sa.mesh.L[1]);
+      r /= (unsigned)sa.mesh.L[1];
+    }
+    if (D > 2) ik[2] = (int)r;
+    int cnt[3] = {1, 1, 1}, ek[3][2] = {{0, 0}, {0, 0}, {0, 0}}, ak[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+      const int e0 = ik[k] / P, a0 = ik[k] % P;
+      if (a0 == 0) {
+        cnt[k] = 2;
+        ek[k][0] = e0 == 0 ? sa.mesh.n[k] - 1 : e0 - 1;
+        ak[k][0] = P;
+        ek[k][1] = e0;
+      } else {
+        ek[k][0] = e0;
+        ak[k][0] = a0;
+      }
+    }
+    int ns = 0;
+    for (int z = 0; z < cnt[2]; ++z)
+      for (int y = 0; y < cnt[1]; ++y) {
+        ln[ql * kGatherLineInts + 2 + ns] = sa.mesh.n[0] * (ek[1][y] + sa.mesh.n[1] * ek[2][z]);
+        ln[ql * kGatherLineInts + 6 + ns] = (P + 1) * (ak[1][y] + (P + 1) * ak[2][z]);
+        ++ns;
+      }
+    ln[ql * kGatherLineInts] = c;
+    ln[ql * kGatherLineInts + 1] = ns;
+  }
+  __syncthreads();
+  const DivMagic dl((unsigned)L);
+  const int Ei = (int)E;
+  for (int q = threadIdx.x; q < nl * L; q += blockDim.x) {
+    const int ql = (int)dl.div((unsigned)q), x = q - ql * L;
+    const int* li = ln + ql * kGatherLineInts;
+    const int c = li[0], nyz = li[1];
+    // x slots: the lower element (local a = P) first where x is a vertex
+    const int e0 = x / P, a0 = x - e0 * P;
+    const int nx = a0 == 0 ? 2 : 1;
+    const int ex0 = a0 == 0 ? (e0 == 0 ? sa.mesh.n[0] - 1 : e0 - 1) : e0;
+    const int ax0 = a0 == 0 ? P : a0;
+    const int cb = c * NL;
     double s = 0.0;
-    #pragma unroll
-    for (int t = 0; t < (1 << D); ++t)    // constant indices into eids / locs
-      if (t < nrec) s += sa.relem[(c * NL + locs[t]) * E + eids[t]];
+#pragma unroll
+    for (int yz = 0; yz < (D == 3 ? 4 : (D == 2 ? 2 : 1)); ++yz) {
+      if (yz < nyz) {
+        const int eb = li[2 + yz], lb = cb + li[6 + yz];
+        s += sa.relem[(int64_t)((lb + ax0) * Ei + eb + ex0)];
+        if (nx == 2) s += sa.relem[(int64_t)(lb * Ei + eb + e0)];
+      }
+    }
     sm[ql * LP + lds_slot<R>(W + x)] = (RT)s;
-    rr[g] = (RT)s;
+    rr[(t0 + ql) * L + x] = (RT)s;         // component-major: line (t0 + ql) starts at its c N + ...
   }
   __syncthreads();
   // periodic padding of the rows from their interiors
-  for (int q = threadIdx.x; q < nl * (LS - L); q += blockDim.x) {
-    const int ql = q / (LS - L), h = q - ql * (LS - L);
+  const int pad = LS - L;
+  const DivMagic dpad((unsigned)pad);
+  for (int q = threadIdx.x; q < nl * pad; q += blockDim.x) {
+    const int ql = (int)dpad.div((unsigned)q), h = q - ql * pad;
     const int k = h < W ? h : L + h;
     sm[ql * LP + lds_slot<R>(k)] = sm[ql * LP + lds_slot<R>(W + line_wrap(k, W, L))];
   }
   __syncthreads();
   const int runs = (L + R - 1) / R;
+  const DivMagic drun((unsigned)runs);
   for (int g = threadIdx.x; g < nl * runs; g += blockDim.x) {
-    const int line = g / runs, s = (g - line * runs) * R;
+    const int line = (int)drun.div((unsigned)g), s = (g - line * runs) * R;
     const RT* row = sm + line * LP + lds_slot<R>(s);
     auto ld = [&](int j) { return row[lds_slot<R>(j)]; };
     RT acc[R];

@@ -89,9 +89,13 @@ def test_batch_matches_single_problems_kpp():
         assert rel_linf(_cm(g, 1), _cm(r, 1)) <= 1e-12, k
 
 
-def test_batch_small_problems_match_oracle():
+@pytest.mark.parametrize("elem1", [0, 1], ids=["tile", "system"])
+def test_batch_small_problems_match_oracle(elem1):
+    # both element pass-1 kernels of 2D Euler (the autotuner's choice)
+    from paper_2509_04673_amd import cem
     wls = W.euler_batch(seed=5, sizes=[8, 11, 6])
     b = _batch_for(wls)
+    cem.cem_batch_set_plan(b.b, elem1_kernel=elem1)
     b.step(cfl=0.5, nsteps=2)
     got = b.download()
     b.close()
@@ -147,18 +151,34 @@ def test_batch_autotune_keeps_state_and_results():
     b = _batch_for(wls)
     before = b.download(split=False)
     rep = b.autotune(cfl=0.5, steps=1)
-    announce(f"[batch] autotune: {rep['best']}")
-    assert len(rep["trials"]) == 8 and rep["best"]["ms_per_step"] > 0
+    announce(f"[batch] autotune: {rep['best']} from {len(rep['trials'])} trials")
+    # a coordinate search: every value of every knob is tried, each plan
+    # once (order 2, x-line caps 4, strided tile sizes 3, pass-1 kernel 2)
+    trials = rep["trials"]
+    keys = [(t["order"], t["xlines_cap"], t["ytile_lds_bytes"], t["elem1"]) for t in trials]
+    assert len(set(keys)) == len(keys) and 8 <= len(trials) <= 11, keys
+    assert rep["best"]["ms_per_step"] > 0
+    assert rep["best"]["ms_per_step"] == min(t["ms_per_step"] for t in trials)
+    assert {t["order"] for t in trials} == {"input", "largest_first"}
+    assert {t["xlines_cap"] for t in trials} == {512, 1024, 2048, 4096}
+    assert {t["ytile_lds_bytes"] for t in trials} == {20480, 40960, 57344}
+    assert {t["elem1"] for t in trials} == {"tile", "system"}
     assert np.array_equal(b.download(split=False), before)     # state restored
     b.step(cfl=0.5, nsteps=2)
     tuned = b.download(split=False)
     b.close()
+    # the same plan set explicitly gives bitwise the same states (the plan
+    # is the whole of what the autotuner changes); every pass-1 kernel the
+    # plans can pick is compared with the oracle on its own
+    from paper_2509_04673_amd import cem
+    best = rep["best"]
     ref = _batch_for(wls)
+    cem.cem_batch_set_plan(ref.b, 1 if best["order"] == "largest_first" else 0, best["xlines_cap"],
+                           best["ytile_lds_bytes"], 1 if best["elem1"] == "system" else 0)
     ref.step(cfl=0.5, nsteps=2)
     plain = ref.download(split=False)
     ref.close()
-    # the plan choices change launch shapes and order, not the arithmetic
-    assert np.max(np.abs(tuned - plain)) <= 1e-12 * np.max(np.abs(plain))
+    assert np.array_equal(tuned, plain)
 
 
 def test_batch_matches_single_problems_euler3d():
