@@ -53,6 +53,12 @@ class Params:
     # with dt_e of eq. (37); "shrink" = no flux limiter, dt_e of eq. (40)
     # reduced until ubar^e is admissible (the Remark after eq. (40))
     flux_mode: str = "limit"
+    # bounds of the scalar limiters [KHV Sec. 4.1, 4.2, "local or global
+    # bounds"]: "global" = [u_min, u_max]; "local" = per element, the range
+    # of the old cell averages of the element and its facet neighbours,
+    # imposed on ubar^e (flux limiter) and on the limited states of the
+    # element's nodes (slope limiter)
+    bounds: str = "global"
 
 
 @dataclass
@@ -393,6 +399,19 @@ class Oracle:
         fL_sum = sum(outward(fL_c, k, s) for k in range(d) for s in (-1, 1))
         ubarL = ue - dt_e / vol * area * fL_sum                # [KHV eq. (51)]
 
+        # bounds of the scalar limiters per element (Sec. 4.1, 4.2): global,
+        # or the range of the cell averages of K_e and its facet neighbours
+        # (the low-order average ubar^{e,L} lies in it: it is a convex
+        # combination of u^e and the bar states of its facets)
+        if prob.kind != "euler" and prm.bounds == "local":
+            b_lo, b_hi = ue[0].copy(), ue[0].copy()
+            for k in range(d):
+                for s_ in (-1, 1):
+                    b_lo = np.minimum(b_lo, ue[0][self.nbr[(k, s_)]])
+                    b_hi = np.maximum(b_hi, ue[0][self.nbr[(k, s_)]])
+        else:
+            b_lo, b_hi = np.full(E, prob.u_min), np.full(E, prob.u_max)
+
         fA_c = [fL_c[k] - fH_c[k] for k in range(d)]           # f^A = f^L - f^H
         phi_e = vol / (2 * d * area)                           # |K_e| / |dK_e|
         fAbar_c = []
@@ -412,11 +431,12 @@ class Oracle:
                 a2 = self._euler_alpha(ubarL[:, hi], dh, 1.0)
                 fAbar_c.append(np.minimum(a1, a2)[None] * fA)
             else:
-                # [KHV eq. (53)] with global bounds
-                fmax = np.minimum(phi_e * (prob.u_max - ubarL) / dt_e,
-                                  phi_e * (ubarL[:, hi] - prob.u_min) / dt_e[hi])
-                fmin = np.maximum(phi_e * (prob.u_min - ubarL) / dt_e,
-                                  phi_e * (ubarL[:, hi] - prob.u_max) / dt_e[hi])
+                # [KHV eq. (53)]: e keeps ubar^e <= its upper bound, e' keeps
+                # ubar^{e'} >= its lower bound (and the mirror for f^min)
+                fmax = np.minimum(phi_e * (b_hi - ubarL) / dt_e,
+                                  phi_e * (ubarL[:, hi] - b_lo[hi]) / dt_e[hi])
+                fmin = np.maximum(phi_e * (b_lo - ubarL) / dt_e,
+                                  phi_e * (ubarL[:, hi] - b_hi[hi]) / dt_e[hi])
                 fAbar_c.append(np.where(fA >= 0.0, np.minimum(fA, fmax),
                                         np.maximum(fA, fmin)))
 
@@ -454,10 +474,10 @@ class Oracle:
             ub = ubar[0][:, None]
             f0 = fe[0]
             with np.errstate(divide="ignore", invalid="ignore"):
-                # ubar lies in [u_min, u_max] up to rounding; a ratio made
-                # negative by a rounding excess is taken as 0
-                bpos = np.clip(mloc * (prob.u_max - ub) / np.where(f0 > 0, f0, 1.0), 0.0, 1.0)
-                bneg = np.clip(mloc * (prob.u_min - ub) / np.where(f0 < 0, f0, 1.0), 0.0, 1.0)
+                # ubar lies in the element's bounds up to rounding; a ratio
+                # made negative by a rounding excess is taken as 0
+                bpos = np.clip(mloc * (b_hi[:, None] - ub) / np.where(f0 > 0, f0, 1.0), 0.0, 1.0)
+                bneg = np.clip(mloc * (b_lo[:, None] - ub) / np.where(f0 < 0, f0, 1.0), 0.0, 1.0)
             bi = np.where(f0 > 0, bpos, np.where(f0 < 0, bneg, 1.0))
             beta = np.min(bi, axis=-1)
 
@@ -474,6 +494,7 @@ class Oracle:
         taps = dict(g=g, gamma=gamma, nu=nu, lam_e=lam_e, r=r, udot=udot, ue=ue,
                     fgrad_h=fgrad_h, fH=np.stack(fH_c), fL=np.stack(fL_c), lam_f=np.stack(lam_c),
                     dt_e=dt_e, ubarL=ubarL, fA=np.stack(fA_c), fAbar=np.stack(fAbar_c),
+                    b_lo=b_lo, b_hi=b_hi,
                     ubar=ubar, fe=fe, beta=beta, A=A, S=S, u_fe=u_fe)
         return u_fe, taps
 

@@ -97,3 +97,93 @@ def test_euler_appendix_a_alpha_is_admissible():
     assert np.mean(alpha < 1) > 0.1
     small = orc._euler_alpha(ubar, 1e-9 * f, m)
     assert np.all(small == 1.0)
+
+
+# ---- local bounds (Sec. 4.1, 4.2: "local or global bounds") ---------------
+def _kpp_local(seed=0, n=6):
+    orc, u = _kpp_case(seed, n)
+    orc.prob.params.bounds = "local"
+    return orc, u
+
+
+def test_local_bounds_contain_the_low_order_average():
+    # the range of the old cell averages of K_e and its facet neighbours
+    # holds the low-order average of eq. (51) (a convex combination of u^e
+    # and the bar states of its facets), so the flux limiter's bounds are
+    # consistent (f^max >= 0 >= f^min)
+    orc, u = _kpp_local(seed=1)
+    _, taps = orc.fe_stage(u, 1e-3)
+    lo, hi, ubL = taps["b_lo"], taps["b_hi"], taps["ubarL"][0]
+    tol = 1e-13 * np.max(np.abs(u))
+    assert np.all(ubL >= lo - tol) and np.all(ubL <= hi + tol)
+    # and they are the neighbourhood ranges, inside the global bounds
+    ue = taps["ue"][0]
+    assert np.all(lo <= ue) and np.all(hi >= ue)
+    assert np.all(lo >= orc.prob.u_min) and np.all(hi <= orc.prob.u_max)
+    assert np.any(hi < orc.prob.u_max) and np.any(lo > orc.prob.u_min)
+
+
+def test_local_flux_limiter_is_admissible_and_maximal():
+    # ubar^e of eq. (44) stays in [lo_e, hi_e]; each limited facet flux is
+    # the largest |fbar| <= |f^A| keeping both sides in their own bounds
+    orc, u = _kpp_local(seed=2)
+    _, taps = orc.fe_stage(u, 1e-3)
+    h, d = orc.mesh.h, orc.mesh.d
+    phi = h / (2 * d)
+    lo, hi = taps["b_lo"], taps["b_hi"]
+    tol = 1e-12 * np.max(np.abs(u))
+    ub = taps["ubar"][0]
+    assert np.all(ub >= lo - tol) and np.all(ub <= hi + tol)
+    limited = 0
+    for k in range(d):
+        nb = orc.nbr[(k, 1)]
+        fA, fb = taps["fA"][k, 0], taps["fAbar"][k, 0]
+        ule, ulh = taps["ubarL"][0], taps["ubarL"][0][nb]
+        dte, dth = taps["dt_e"], taps["dt_e"][nb]
+        assert np.all(np.abs(fb) <= np.abs(fA) + 1e-300) and np.all(fb * fA >= 0)
+        for i in range(fA.size):
+            if fb[i] == fA[i]:
+                continue
+            limited += 1
+            grid = np.linspace(0.0, fA[i], 20001)
+            a1 = ule[i] + dte[i] * grid / phi
+            a2 = ulh[i] - dth[i] * grid / phi
+            ok = ((a1 <= hi[i] + tol) & (a1 >= lo[i] - tol) & (a2 <= hi[nb[i]] + tol) & (a2 >= lo[nb[i]] - tol))
+            best = grid[np.nonzero(ok)[0].max()]
+            assert abs(best - fb[i]) <= abs(fA[i]) / 20000 * 1.01
+    assert limited > 0
+
+
+def test_local_slope_limiter_is_admissible_and_maximal():
+    orc, u = _kpp_local(seed=3)
+    _, taps = orc.fe_stage(u, 1e-3)
+    mloc = orc.mesh.h ** 2 / orc.mesh.nloc
+    lo, hi = taps["b_lo"], taps["b_hi"]
+    ub, fe, beta = taps["ubar"][0], taps["fe"][0], taps["beta"]
+    tol = 1e-12 * np.max(np.abs(u))
+    states = ub[:, None] + beta[:, None] * fe / mloc
+    assert np.all(states >= lo[:, None] - tol) and np.all(states <= hi[:, None] + tol)
+    grid = np.linspace(0.0, 1.0, 4001)
+    for e in np.nonzero(beta < 1.0)[0][:40]:
+        s = ub[e] + grid[:, None] * fe[e][None, :] / mloc
+        ok = np.all((s >= lo[e] - tol) & (s <= hi[e] + tol), axis=1)
+        assert abs(grid[np.nonzero(ok)[0].max()] - beta[e]) <= 1.0 / 4000 * 1.01
+
+
+def test_local_bounds_give_a_local_maximum_principle():
+    # u_i^FE is a convex combination of u_i and the limited states of the
+    # elements around node i, each in its element's bounds: per stage, the
+    # new value lies in [min(u_i, min lo_e), max(u_i, max hi_e)] over e in E_i
+    orc, u = _kpp_local(seed=4, n=8)
+    dt = 0.5 * orc.max_dt(u)
+    ufe, taps = orc.fe_stage(u, dt)
+    lo_n = np.minimum(u[0], np.full(orc.mesh.N, np.inf))
+    hi_n = np.maximum(u[0], np.full(orc.mesh.N, -np.inf))
+    np.minimum.at(lo_n, orc.conn, np.broadcast_to(taps["b_lo"][:, None], orc.conn.shape))
+    np.maximum.at(hi_n, orc.conn, np.broadcast_to(taps["b_hi"][:, None], orc.conn.shape))
+    tol = 1e-12 * np.max(np.abs(u))
+    assert np.all(ufe[0] >= lo_n - tol) and np.all(ufe[0] <= hi_n + tol)
+    # and several stages keep the global bounds (the local ones lie inside)
+    v, st = orc.run(u.copy(), 5, dt=dt)
+    assert st["violations"] == 0
+    assert v.min() >= orc.prob.u_min and v.max() <= orc.prob.u_max
