@@ -78,6 +78,19 @@ typedef enum { CEM_FP64 = 0, CEM_FP32_MIXED = 1 } cem_precision;
  *   CFL violation. */
 typedef enum { CEM_FLUX_LIMIT = 0, CEM_FLUX_SUBCELL = 1, CEM_FLUX_SHRINK = 2 } cem_flux_mode;
 
+/* Bounds of the scalar limiters (Sec. 4.1, 4.2 allow local or global ones).
+ * CEM_BOUNDS_GLOBAL: [u_min, u_max] for every element.
+ * CEM_BOUNDS_LOCAL: per element, [min, max] of the stage input's cell
+ *   averages of K_e and its 2d facet neighbours; imposed on the
+ *   flux-limited average ubar^e (eq. 53: each facet keeps both of its
+ *   elements within their own bounds) and on every slope-limited state of
+ *   the element (eq. 55, u_i^min/max taken as the element's bounds).  The
+ *   range holds the low-order average ubar^{e,L} (eq. 51), so a zero
+ *   limited flux is always admissible, and it lies inside [u_min, u_max].
+ *   The flux modes other than CEM_FLUX_LIMIT keep the global bounds for
+ *   dt_e (the Remark after eq. 40).  Ignored for Euler. */
+typedef enum { CEM_BOUNDS_GLOBAL = 0, CEM_BOUNDS_LOCAL = 1 } cem_bounds_mode;
+
 /* Uniform periodic box [lo, hi] with n[k] cube cells per axis (cell edge h
  * equal on every axis; unused axes ignored).  n[k] >= 2. */
 typedef struct {
@@ -108,6 +121,7 @@ typedef struct {
   double u_min, u_max; /* global bounds of scalar problems (Sec. 4.1, 4.2) */
   int precision;       /* cem_precision */
   int flux_mode;       /* cem_flux_mode */
+  int bounds;          /* cem_bounds_mode */
 } cem_params;
 
 typedef struct cem_ctx cem_ctx;
@@ -139,7 +153,7 @@ typedef struct {
 
 /* Fills p with the defaults: q = 1, r = 2, eps = 1e-12, w_lin = 1e-3,
  * eps_pos = 1e-10, clamp_ulps = 64, all modes 0, bounds (-inf, +inf),
- * precision CEM_FP64, flux_mode CEM_FLUX_LIMIT. */
+ * precision CEM_FP64, flux_mode CEM_FLUX_LIMIT, bounds CEM_BOUNDS_GLOBAL. */
 cem_status cem_params_default(cem_params* p);
 
 /* Creates a context: validates the configuration and builds the element
@@ -211,7 +225,9 @@ cem_status cem_reset_counters(cem_ctx* ctx);
  *   0 g [d][m][N]      1 r [m][N]        2 udot [m][N]    3 gamma [E]
  *   4 nu [E]           5 dt_e [E]        6 u^e [m][E]     7 ubar^{e,L} [m][E]
  *   8 ubar^e [m][E]    9 beta [E]       10 f^A of the +e_k facet [d][m][E]
- *  11 element update vectors [m][(p+1)^d][E] */
+ *  11 element update vectors [m][(p+1)^d][E]
+ *  12 local bounds of the scalar limiters [2][E] (lower, upper; written by
+ *     the element pass only with CEM_BOUNDS_LOCAL) */
 cem_status cem_debug_tap(cem_ctx* ctx, int tap, double* dst, size_t count);
 size_t cem_tap_size(const cem_ctx* ctx, int tap);
 

@@ -85,7 +85,7 @@ struct cem_ctx {
   size_t ws_need = 0;
   // workspace carve-up (byte offsets)
   size_t o_g, o_r, o_udot, o_tmp, o_tmp2, o_relem, o_ue, o_ubarL, o_ubar, o_fahi, o_dte, o_gam,
-      o_nu, o_beta, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart, o_fnode;
+      o_nu, o_beta, o_bnd, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart, o_fnode;
   size_t o_g32 = 0, o_r32 = 0, o_udot32 = 0, o_tmp32 = 0, o_tmp2_32 = 0;
   bool fnode_valid = false;   // nodal fluxes match the bound state
   int lds_max = 65536;        // LDS bytes one block may use on the bound device
@@ -322,6 +322,8 @@ StageArgs make_args(const cem_ctx* c) {
   a.umin = c->prm.u_min;
   a.umax = c->prm.u_max;
   a.clamp_tol = c->prm.clamp_ulps * DBL_EPSILON * std::fmax(std::fabs(c->prm.u_min), std::fabs(c->prm.u_max));
+  a.bounds_local = c->kind != CEM_EULER && c->prm.bounds == CEM_BOUNDS_LOCAL;
+  a.bnd = c->W<double>(c->o_bnd);
   a.u = c->u;
   a.u0 = c->u0;
   a.uout = c->u;
@@ -1000,6 +1002,8 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
     return fail(CEM_EINVAL, "unsupported (dim, degree, physics, precision)");
   if (prm->flux_mode < CEM_FLUX_LIMIT || prm->flux_mode > CEM_FLUX_SHRINK)
     return fail(CEM_EINVAL, "flux_mode must be CEM_FLUX_LIMIT, CEM_FLUX_SUBCELL or CEM_FLUX_SHRINK");
+  if (prm->bounds != CEM_BOUNDS_GLOBAL && prm->bounds != CEM_BOUNDS_LOCAL)
+    return fail(CEM_EINVAL, "bounds must be CEM_BOUNDS_GLOBAL or CEM_BOUNDS_LOCAL");
   double h = 0.0;
   for (int k = 0; k < d; ++k) {
     if (mesh->n[k] < 2) return fail(CEM_EINVAL, "need at least 2 cells per axis");
@@ -1075,6 +1079,7 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->o_gam = take(E8);
   c->o_nu = take(E8);
   c->o_beta = take(E8);
+  c->o_bnd = take(2 * E8);
   c->o_dtbuf = take(8 * 8);
   // per-block dt_e minima: one-thread-per-element blocks, 2D element tiles
   // or the 32- / 64-element blocks of the system passes
@@ -1337,6 +1342,7 @@ size_t cem_tap_size(const cem_ctx* c, int tap) {
     case 6: case 7: case 8: return mE;
     case 10: return (size_t)c->d * mE;
     case 11: return (size_t)c->nl * mE;
+    case 12: return 2 * E;
     default: return 0;
   }
 }
@@ -1345,8 +1351,8 @@ cem_status cem_debug_tap(cem_ctx* c, int tap, double* dst, size_t count) {
   if (!c || !c->bound || !dst) return fail(CEM_EINVAL, "context not bound / null");
   const size_t n = cem_tap_size(c, tap);
   if (n == 0 || count != n) return fail(CEM_EINVAL, "bad tap id or count");
-  const size_t offs[12] = {c->o_g, c->o_r, c->o_udot, c->o_gam, c->o_nu, c->o_dte,
-                           c->o_ue, c->o_ubarL, c->o_ubar, c->o_beta, c->o_fahi, c->o_relem};
+  const size_t offs[13] = {c->o_g, c->o_r, c->o_udot, c->o_gam, c->o_nu, c->o_dte, c->o_ue,
+                           c->o_ubarL, c->o_ubar, c->o_beta, c->o_fahi, c->o_relem, c->o_bnd};
   if (c->mixed && tap <= 2) {
     // g, r and udot are float arrays in the mixed form
     const size_t o32[3] = {c->o_g32, c->o_r32, c->o_udot32};
@@ -1447,12 +1453,15 @@ cem_status cem_batch_create(int count, const cem_mesh_desc* meshes, const cem_ph
     b->wsoff.push_back(ws);
     ws += align256(c->ws_need);
   }
-  // plan region: per stage at most 4 StageArgs arrays, 2d + 1 LineFastArgs
-  // arrays, 2d LineArgs arrays and 6d + 4 block prefixes, each padded
-  const size_t per_stage = 4 * (size_t)count * sizeof(StageArgs) +
-                           (2 * d + 1) * (size_t)count * sizeof(LineFastArgs) +
-                           2 * d * (size_t)count * sizeof(LineArgs) + (6 * d + 4) * (size_t)(count + 1) * sizeof(int) +
-                           (12 * d + 8) * 256;
+  // plan region, per stage: StageArgs entries, one per problem in element
+  // pass 1 (two with the system kernels' residual half), the assembly, pass
+  // 2 and the update; one line-argument entry per problem and line pass (d
+  // gradient, d mass); at most 10 d + 7 launch groups, each with a block
+  // prefix of at most count + 1 ints and up to three arrays padded to 256
+  const size_t ngroups = 10 * (size_t)d + 7;
+  const size_t per_stage = 5 * (size_t)count * sizeof(StageArgs) +
+                           2 * (size_t)d * count * std::max(sizeof(LineFastArgs), sizeof(LineArgs)) +
+                           ngroups * (size_t)(count + 1) * sizeof(int) + 3 * ngroups * 256;
   b->o_plan = ws;
   b->plan_cap = 3 * per_stage;
   b->ws_need = ws + align256(b->plan_cap);

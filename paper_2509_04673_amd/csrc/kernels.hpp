@@ -80,6 +80,8 @@ struct StageArgs {
   int gamma_mode, alpha_mode, beta_mode;   // 0 method, 1 force 0, 2 force 1
   int flux_mode;        // 0 flux limiter, dt_e of (40); 1 f = f^H, dt_e of (37); 2 f = f^H, reduced (40)
   double umin, umax, clamp_tol;
+  int bounds_local;     // scalar limiters: 0 the global [umin, umax], 1 per-element bounds in bnd
+  double* bnd;          // [2][E] per-element lower, upper bounds (bounds_local)
   const double* u;      // stage input u^(s)   [M][N]
   double* u0;           // step base u^n       [M][N]
   double* uout;         // stage output (may alias u: per-node read-then-write)
@@ -1690,6 +1692,23 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     a.ue[c * E + e] = ue[c];
     a.ubarL[c * E + e] = ue[c] - dt_e / h * fLsum[c];
   }
+  if constexpr (M == 1) {
+    // local bounds of the scalar limiters (Sec. 4.1, 4.2): the range of the
+    // cell averages of K_e and its 2d facet neighbours; it holds ubar^{e,L}
+    // (a convex combination of u^e and the facets' bar states).  NaN
+    // propagates, as it does through the global bounds' tests.
+    if (a.bounds_local) {
+      double lo = ue[0], hi = ue[0];
+#pragma unroll
+      for (int l = 0; l < 2 * D; ++l) {
+        const double v = nbr_mean[l][0];
+        lo = (v < lo || v != v) ? v : lo;
+        hi = (v > hi || v != v) ? v : hi;
+      }
+      a.bnd[e] = lo;
+      a.bnd[E + e] = hi;
+    }
+  }
   if constexpr (ROLE == 4) xc.sync();
   return dt_e;
 }
@@ -1866,9 +1885,10 @@ __global__ void __launch_bounds__(384) k_elem1_tile3(StageArgs a) {
 // limited flux fb of the facet between eL (lower) and eR (upper): fA its raw
 // antidiffusive flux, uLs / uRs the two low-order averages, dtL / dtR the
 // two pseudo time steps
+// and, for scalar problems, bL / bR the two elements' bounds {lower, upper}
 template <int D, int PH>
 __device__ inline void limit_facet(const StageArgs& a, const double* fA, const double* uLs, const double* uRs,
-                                   double dtL, double dtR, double* fb) {
+                                   double dtL, double dtR, const double* bL, const double* bR, double* fb) {
   using PHY = Phys<D, PH>;
   constexpr int M = PHY::M;
   const double phi = a.mesh.h / (2.0 * D);     // |K| / |dK|
@@ -1893,8 +1913,10 @@ __device__ inline void limit_facet(const StageArgs& a, const double* fA, const d
 #pragma unroll
     for (int c = 0; c < M; ++c) fb[c] = al * fA[c];
   } else {
-    const double fmx = fmin(phi * (a.umax - uLs[0]) / dtL, phi * (uRs[0] - a.umin) / dtR);
-    const double fmn = fmax(phi * (a.umin - uLs[0]) / dtL, phi * (uRs[0] - a.umax) / dtR);
+    // eL keeps ubar^{eL} within its upper bound and eR within its lower
+    // one (and the mirror for f^min)
+    const double fmx = fmin(phi * (bL[1] - uLs[0]) / dtL, phi * (uRs[0] - bR[0]) / dtR);
+    const double fmn = fmax(phi * (bL[0] - uLs[0]) / dtL, phi * (uRs[0] - bR[1]) / dtR);
     fb[0] = fA[0] >= 0.0 ? fmin(fA[0], fmx) : fmax(fA[0], fmn);
   }
 }
@@ -1921,7 +1943,7 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
   // behind the limiter's (uniform) branches each facet's loads waited for
   // the previous facet's arithmetic.
   const double dt_e = a.dte[e];
-  double fAl[D][M], fAh[D][M], ubl[D][M], ubh[D][M], ubc[M], uec[M], dtl[D], dth[D];
+  double fAl[D][M], fAh[D][M], ubl[D][M], ubh[D][M], ubc[M], uec[M], dtl[D], dth[D], bl[D][2], bh[D][2];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     int en[3] = {ei[0], ei[1], ei[2]};
@@ -1938,11 +1960,26 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
     }
     dtl[k] = a.dte[elo];
     dth[k] = a.dte[ehi];
+    if (M == 1 && a.bounds_local) {
+      bl[k][0] = a.bnd[elo];
+      bl[k][1] = a.bnd[E + elo];
+      bh[k][0] = a.bnd[ehi];
+      bh[k][1] = a.bnd[E + ehi];
+    } else {
+      bl[k][0] = bh[k][0] = a.umin;
+      bl[k][1] = bh[k][1] = a.umax;
+    }
   }
 #pragma unroll
   for (int c = 0; c < M; ++c) {
     ubc[c] = a.ubarL[c * E + e];
     uec[c] = a.ue[c * E + e];
+  }
+  // the element's own bounds (scalar limiters: flux and slope)
+  double bc[2] = {a.umin, a.umax};
+  if (M == 1 && a.bounds_local) {
+    bc[0] = a.bnd[e];
+    bc[1] = a.bnd[E + e];
   }
   double U[M][NL];
 #pragma unroll
@@ -1962,10 +1999,10 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       double fb[M];
-      limit_facet<D, PH>(a, fAl[k], ubl[k], ubc, dtl[k], dt_e, fb);
+      limit_facet<D, PH>(a, fAl[k], ubl[k], ubc, dtl[k], dt_e, bl[k], bc, fb);
 #pragma unroll
       for (int c = 0; c < M; ++c) fbs[c] -= fb[c];
-      limit_facet<D, PH>(a, fAh[k], ubc, ubh[k], dt_e, dth[k], fb);
+      limit_facet<D, PH>(a, fAh[k], ubc, ubh[k], dt_e, dth[k], bc, bh[k], fb);
 #pragma unroll
       for (int c = 0; c < M; ++c) fbs[c] += fb[c];
     }
@@ -2102,8 +2139,8 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
         double bi = 1.0;
         // ubar is in bounds up to rounding: a ratio made negative by a
         // rounding excess counts as 0
-        if (fi > 0.0) bi = fmax(0.0, fmin(1.0, mloc * (a.umax - ub[0]) / fi));
-        else if (fi < 0.0) bi = fmax(0.0, fmin(1.0, mloc * (a.umin - ub[0]) / fi));
+        if (fi > 0.0) bi = fmax(0.0, fmin(1.0, mloc * (bc[1] - ub[0]) / fi));
+        else if (fi < 0.0) bi = fmax(0.0, fmin(1.0, mloc * (bc[0] - ub[0]) / fi));
         beta = fmin(beta, bi);
       }
     }

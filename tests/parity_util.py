@@ -84,7 +84,7 @@ def gpu_for(wl, modes=None, precision="fp64"):
     from paper_2509_04673_amd.cem import Solver
     kw = {}
     for k, v in (modes or {}).items():
-        kw[k] = v if k == "flux_mode" else MODE_CODES[v]
+        kw[k] = v if k in ("flux_mode", "bounds") else MODE_CODES[v]
     s = Solver.from_workload(wl, precision=precision, **kw)
     s.upload(wl.u0)
     if wl.kind != "euler":
@@ -186,6 +186,9 @@ def compare_stage(wl, modes=None, label="", tol=1e-12, floors=None, ref=None):
         errs[name] = rel_linf(s.tap(name).reshape(np.shape(taps[name])), taps[name],
                               floors.get(name, 0.0))
     errs["u_fe"] = rel_linf(got, ufe, floors.get("u_fe", 0.0))
+    if (modes or {}).get("bounds") == "local":
+        tols["bounds"] = tol
+        errs["bounds"] = rel_linf(s.tap("bounds").reshape(2, -1), np.stack([taps["b_lo"], taps["b_hi"]]))
     s.close()
     announce(f"[parity] {label}: " + ", ".join(f"{k}={v:.1e}" for k, v in errs.items())
              + f" (udot held to {tols['udot']:.1e})")

@@ -210,3 +210,28 @@ def test_batch_flux_limiter_off_matches_single(mode):
         err = rel_linf(_cm(g, 4), _cm(r, 4))
         announce(f"[batch] {mode} problem {k}: batch vs single rel Linf {err:.1e}")
         assert err <= 1e-10, (k, err)
+
+
+@pytest.mark.parametrize("elem1", [0, 1], ids=["tile", "system"])
+def test_batch_plan_region_holds_many_small_problems(elem1):
+    # 700 small problems: every plan entry is per problem, so the plan's
+    # device region (sized at creation) is tested at its largest per-problem
+    # demand, the system pass 1 with its residual half, both fused and
+    # unfused assembly and all line-kernel variants
+    from paper_2509_04673_amd import cem
+    sizes = [6 + (k % 60) for k in range(700)]
+    wls = W.euler_batch(seed=9, sizes=sizes)
+    b = _batch_for(wls)
+    cem.cem_batch_set_plan(b.b, 1, 512, 20480, elem1)
+    b.step(cfl=0.5, nsteps=1)
+    chk = b.check()
+    got = b.download()
+    b.close()
+    announce(f"[batch] plan region: {len(wls)} problems, elem1 kernel {elem1}, one step")
+    for k in (0, 1, 2, 350, 699):
+        s = gpu_for(wls[k])
+        s.step(cfl=0.5)
+        err = rel_linf(_cm(got[k], 4), _cm(s.download(), 4))
+        s.close()
+        assert err <= 1e-10, (k, err)
+    assert all(c["violations"] == 0 and c["rho_min"] > 0 for c in chk)
