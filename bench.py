@@ -494,14 +494,20 @@ def bench_batch(args):
     del wls
     cfl = 0.5
     if args.plan:
-        o, xc, yc, e1 = (int(v) for v in args.plan.split(","))
+        vals = [int(v) for v in args.plan.split(",")]
+        o, xc, yc, e1 = vals[:4]
+        lines = vals[4] if len(vals) > 4 else 1
         cem.cem_batch_set_plan(b.b, o, xc, yc, e1)
-        tune = dict(best=dict(order=o, xlines_cap=xc, ytile_lds_bytes=yc, elem1=e1, source="--plan"), trials=[])
+        cem.cem_batch_set_line_kernels(b.b, lines)
+        tune = dict(best=dict(order=o, xlines_cap=xc, ytile_lds_bytes=yc, elem1=e1, lines=lines, source="--plan"),
+                    trials=[])
     elif args.no_autotune:
         tune = dict(best=None, trials=[])
     else:
         tune = b.autotune(cfl=cfl, steps=1)
     print(f"[bench] autotuned plan: {tune['best']} ({len(tune['trials'])} plans tried)", flush=True)
+    for t in tune["trials"]:
+        print(f"[bench]   trial {t}", flush=True)
 
     nwarm = max(1, args.warmup)
     cem.cem_batch_set_timing(b.b, (1 << len(cem.KERNELS)) - 1)
@@ -689,8 +695,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true", help="skip the mixed-form error run")
     ap.add_argument("--no-autotune", action="store_true", help="batched workload: default plan")
-    ap.add_argument("--plan", default="", metavar="ORDER,XCAP,YTILE,ELEM1",
-                    help="batched workload: this plan instead of the autotuner (cem_batch_set_plan)")
+    ap.add_argument("--plan", default="", metavar="ORDER,XCAP,YTILE,ELEM1[,LINES]",
+                    help="batched workload: this plan instead of the autotuner (cem_batch_set_plan; "
+                         "LINES 1 matrix-core line tiles (default), 0 vector, cem_batch_set_line_kernels)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--summarize-profile", metavar="DIR",

@@ -82,6 +82,7 @@ _SIGS = [
     ("cem_debug_tap", ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_size_t]),
     ("cem_tap_size", ctypes.c_size_t, [_P, ctypes.c_int]),
     ("cem_set_graphs", ctypes.c_int, [_P, ctypes.c_int]),
+    ("cem_set_line_kernels", ctypes.c_int, [_P, ctypes.c_int]),
     ("cem_state_modified", ctypes.c_int, [_P]),
     ("cem_set_timing", ctypes.c_int, [_P, ctypes.c_uint]),
     ("cem_kernel_times", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
@@ -102,6 +103,7 @@ _SIGS = [
     ("cem_batch_reset_counters", ctypes.c_int, [_P]),
     ("cem_batch_check_invariants", ctypes.c_int, [_P, ctypes.POINTER(Invariants), ctypes.c_int]),
     ("cem_batch_set_plan", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    ("cem_batch_set_line_kernels", ctypes.c_int, [_P, ctypes.c_int]),
     ("cem_batch_set_timing", ctypes.c_int, [_P, ctypes.c_uint]),
     ("cem_batch_kernel_times", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
@@ -231,6 +233,10 @@ def cem_set_graphs(ctx, enable):
     _check(lib().cem_set_graphs(ctx, int(bool(enable))))
 
 
+def cem_set_line_kernels(ctx, mode):
+    _check(lib().cem_set_line_kernels(ctx, int(mode)))
+
+
 def cem_state_modified(ctx):
     _check(lib().cem_state_modified(ctx))
 
@@ -312,6 +318,10 @@ class Solver:
 
     def step(self, dt=0.0, cfl=0.0):
         cem_step(self.ctx, dt, cfl)
+
+    def set_line_kernels(self, mode):
+        """0 vector, 1 matrix cores, 2 by size (see cem_set_line_kernels)."""
+        cem_set_line_kernels(self.ctx, mode)
 
     def set_graphs(self, enable):
         cem_set_graphs(self.ctx, enable)
@@ -408,6 +418,10 @@ def cem_batch_check_invariants(b, count):
 
 def cem_batch_set_plan(b, order=0, xlines_cap=2048, ytile_lds_bytes=40960, elem1_kernel=0):
     _check(lib().cem_batch_set_plan(b, int(order), int(xlines_cap), int(ytile_lds_bytes), int(elem1_kernel)))
+
+
+def cem_batch_set_line_kernels(b, matrix):
+    _check(lib().cem_batch_set_line_kernels(b, int(matrix)))
 
 
 def cem_batch_set_timing(b, mask):

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/cem.h"
@@ -92,6 +93,7 @@ struct cem_ctx {
   int upd_blocks = 0, inv_blocks = 0;
   size_t ndtp = 0;                 // capacity of the per-block dt_e minima
   int elem1_sys = kSys2D ? 1 : 0;  // 2D Euler: element pass 1 on the system kernels
+  int line_mfma = 2;               // float64 line passes: 0 vector, 1 matrix cores, 2 by size
   bool bound = false, bounds_set = false;
   // whole-step HIP graph (captured on a private stream, launched on stream)
   bool use_graphs = true;
@@ -109,7 +111,7 @@ struct cem_ctx {
 };
 
 // batched form: launches of one stage over all problems (see kernels_batch.hpp)
-enum BKind { B_LINE, B_LINE_X, B_LINE_Y, B_ELEM1_TILE, B_ELEM1_TILE2, B_ELEM1_SYS, B_RESID_SYS, B_GATHER_LX,
+enum BKind { B_LINE, B_LINE_X, B_LINE_Y, B_LINE_MX, B_LINE_MY, B_ELEM1_TILE, B_ELEM1_TILE2, B_ELEM1_SYS, B_RESID_SYS, B_GATHER_LX,
              B_GATHER_R, B_ELEM2, B_ELEM2_SYS, B_UPDATE };
 
 struct BLaunch {
@@ -143,6 +145,7 @@ struct cem_batch {
   int order = 0;                   // 0: problems in input order, 1: largest first
   int ytile_cap = 40960;           // strided line kernels: LDS bytes of a tile (sets the runs per thread)
   int elem1_sys = kSys2D ? 1 : 0;  // 2D Euler: element pass 1 on the system kernels (else the LDS tile)
+  int line_mfma = 1;               // float64 line passes on the matrix cores (else the vector kernels)
 };
 
 namespace {
@@ -251,9 +254,29 @@ const int kSfast[5] = {0, LineTaps<1>::S, LineTaps<2>::S, LineTaps<3>::S, 0};
 const int kWfast32[5] = {0, LineTaps32<1>::W, LineTaps32<2>::W, LineTaps32<3>::W, 0};
 const int kSfast32[5] = {0, LineTaps32<1>::S, LineTaps32<2>::S, LineTaps32<3>::S, 0};
 
+// float64 line passes on the matrix cores: always (mode 1), never (0), or
+// from 2^20 values per pass (2; smaller meshes keep the one-launch vector
+// gradient passes, whose launch count matters more there)
+inline bool use_mfma(const cem_ctx* c) {
+  return !c->mixed && (c->line_mfma == 1 || (c->line_mfma == 2 && (int64_t)c->m * c->N >= (int64_t(1) << 20)));
+}
+
 template <int P, class TI, class TO>
 void launch_line_fast(cem_ctx* c, int id, LineFastArgs la, hipStream_t st) {
   constexpr int W = LineTapsV<P, TO>::W;
+  if constexpr (std::is_same<TI, double>::value && std::is_same<TO, double>::value) {
+    if (use_mfma(c)) {
+      la.ky = line_mfma_chunks(la.ntrans, la.L, 2048);
+      const int seg = kMfmaTY * la.ky;
+      dim3 grid((unsigned)((la.ntrans + kMfmaLines - 1) / kMfmaLines), (unsigned)((la.L + seg - 1) / seg));
+      const size_t lds = line_mfma_lds<P>();
+      if (la.axis == 0)
+        CEM_LAUNCH(c, id, (k_line_mfma<P, true>), grid, 256, lds, st, la);
+      else
+        CEM_LAUNCH(c, id, (k_line_mfma<P, false>), grid, 256, lds, st, la);
+      return;
+    }
+  }
   if (la.axis == 0 && la.L <= 4096) {
     // whole lines in LDS; one line per block unless lines are short
     const int re = la.L >= 2 * P + 2 * W ? 2 : 1;
@@ -464,7 +487,7 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
   RT* tmp2 = c->W<RT>(MIX ? c->o_tmp2_32 : c->o_tmp2);
   // projected gradient g_k = M_1D^{-1} C_1D u along axis k (Sec. 2.2): the
   // passes are independent, so on fast-kernel lines they share one launch
-  bool multi = D >= 2 && c->L[0] <= 4096;
+  bool multi = D >= 2 && c->L[0] <= 4096 && !use_mfma(c);
   for (int k = 0; k < D; ++k) multi = multi && c->tabs.kgrad[k].wfast > 0;
   if (multi) {
     constexpr int W = LineTapsV<P, RT>::W, S = LineTapsV<P, RT>::S;
@@ -659,7 +682,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
                    auto dst_of) -> cem_status {
     // runs of 2P wherever the line allows (the whole batch fills the chip,
     // so the strided tiles are as long as 40 KB of LDS allows)
-    Group gx[2], gy[2], gg;
+    Group gx[2], gy[2], gg, gm;
     for (int v = 0; v < 2; ++v) {
       gx[v].l.kind = B_LINE_X;
       gy[v].l.kind = B_LINE_Y;
@@ -668,11 +691,22 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     }
     gg.l.kind = B_LINE;
     gg.l.grad = grad;
+    gm.l.kind = k == 0 ? B_LINE_MX : B_LINE_MY;
+    gm.l.grad = grad;
     for (cem_ctx* c : probs) {
       const LineKernel& K = grad ? c->tabs.kgrad[k] : c->tabs.kmass[k];
       const void* in = src_of(c);
       void* out_p = dst_of(c);
-      if (K.wfast > 0) {
+      if (K.wfast > 0 && !MIX && b->line_mfma) {
+        // matrix-core blocks of 16 whole lines (the batch fills the chip)
+        LineFastArgs a = line_args<RT>(c, in, out_p, k, grad, false);
+        a.ky = line_mfma_chunks(a.ntrans, a.L, 0);
+        a.gx = (int)((a.ntrans + kMfmaLines - 1) / kMfmaLines);
+        const int seg = kMfmaTY * a.ky;
+        gm.lf.push_back(a);
+        gm.first.push_back(gm.first.back() + a.gx * ((a.L + seg - 1) / seg));
+        gm.l.lds = line_mfma_lds<P>();
+      } else if (K.wfast > 0) {
         LineFastArgs a = line_args<RT>(c, in, out_p, k, grad, false);
         const int re = a.L >= 2 * P + 2 * W ? 2 : 1;
         if (k == 0) {
@@ -716,6 +750,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
       close(gx[v], out);
       close(gy[v], out);
     }
+    close(gm, out);
     close(gg, out);
     return CEM_OK;
   };
@@ -847,6 +882,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
 template <int D, int P, int PH, class RT>
 cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
   constexpr int M = Phys<D, PH>::M;
+  constexpr bool MIX = sizeof(RT) == 4;
   const char* base = b->ws + b->o_plan;
   // per-kernel timing (cem_batch_set_timing) goes through the first
   // problem's context: one record per batched launch
@@ -880,6 +916,12 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
           if (l.grad) CEM_LAUNCH(c0, LID, (kb_line_y<P, 1, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
           else CEM_LAUNCH(c0, LID, (kb_line_y<P, 1, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
         }
+        break;
+      case B_LINE_MX:
+        if constexpr (!MIX) CEM_LAUNCH(c0, LID, (kb_line_mfma<P, true>), g, dim3(256), l.lds, stream, lf, mp);
+        break;
+      case B_LINE_MY:
+        if constexpr (!MIX) CEM_LAUNCH(c0, LID, (kb_line_mfma<P, false>), g, dim3(256), l.lds, stream, lf, mp);
         break;
       case B_ELEM1_TILE:
         if constexpr (D == 2) CEM_LAUNCH(c0, 1, (kb_elem1_tile<P, PH, true, RT>), g, dim3(128), l.lds, stream, sa, mp);
@@ -1247,6 +1289,14 @@ cem_status cem_state_modified(cem_ctx* c) {
   return CEM_OK;
 }
 
+cem_status cem_set_line_kernels(cem_ctx* c, int mode) {
+  if (!c) return fail(CEM_EINVAL, "null context");
+  if (mode < 0 || mode > 2) return fail(CEM_EINVAL, "line kernel mode must be 0 (vector), 1 (matrix) or 2 (by size)");
+  c->line_mfma = mode;
+  drop_graph(c);
+  return CEM_OK;
+}
+
 cem_status cem_set_graphs(cem_ctx* c, int enable) {
   if (!c) return fail(CEM_EINVAL, "null context");
   c->use_graphs = enable != 0;
@@ -1611,6 +1661,15 @@ cem_status cem_batch_set_plan(cem_batch* b, int order, int xlines_cap, int ytile
   return CEM_OK;
 }
 
+cem_status cem_batch_set_line_kernels(cem_batch* b, int matrix) {
+  if (!b) return fail(CEM_EINVAL, "null batch");
+  if (matrix < 0 || matrix > 1) return fail(CEM_EINVAL, "line kernels must be 0 (vector) or 1 (matrix)");
+  b->line_mfma = matrix;
+  batch_drop_graph(b);
+  b->plan_dt = b->plan_cfl = -1.0;
+  return CEM_OK;
+}
+
 cem_status cem_batch_set_timing(cem_batch* b, unsigned mask) {
   if (!b || b->pr.empty()) return fail(CEM_EINVAL, "null batch");
   return cem_set_timing(b->pr[0], mask);
@@ -1650,14 +1709,18 @@ cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, vo
   HIPCHK(hipEventCreate(&e1));
   // the knobs of a plan and the values tried: problem order, values staged
   // per block of the x-line kernels, LDS bytes of a strided line tile (runs
-  // per thread ky = 1, 2, 4), and for 2D Euler the element pass-1 kernel
-  // (16 x 8 element LDS tile with one thread per element, or blocks of 32/64
-  // elements with one thread per element and component)
-  struct Knobs { int order, xcap, ycap, sys; };
+  // per thread ky = 1, 2, 4 of the vector kernels; row groups of the
+  // matrix-core tiles), for 2D Euler the element pass-1 kernel (16 x 8
+  // element LDS tile with one thread per element, or blocks of 32/64
+  // elements with one thread per element and component), and in float64
+  // the line kernels (matrix-core tiles or vector runs)
+  struct Knobs { int order, xcap, ycap, sys, mfma; };
   struct Trial { Knobs k; float ms; };
   const bool sys_choice = b->d == 2 && b->kind == CEM_EULER;
   const std::vector<int> orders = {0, 1}, xcaps = {512, 1024, 2048, 4096}, ycaps = {20480, 40960, 57344};
   const std::vector<int> syss = sys_choice ? std::vector<int>{0, 1} : std::vector<int>{b->elem1_sys};
+  // float64 line passes: matrix-core tiles or the vector kernels
+  const std::vector<int> mfmas = b->mixed ? std::vector<int>{b->line_mfma} : std::vector<int>{0, 1};
   std::vector<Trial> trials;
   cem_status st = CEM_OK;
   auto run_trial = [&](const Knobs& k, float* ms_out) -> cem_status {
@@ -1665,6 +1728,7 @@ cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, vo
     b->xlines_cap = k.xcap;
     b->ytile_cap = k.ycap;
     b->elem1_sys = k.sys;
+    b->line_mfma = k.mfma;
     batch_drop_graph(b);
     b->plan_dt = b->plan_cfl = -1.0;
     cem_status s2;
@@ -1693,18 +1757,20 @@ cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, vo
   };
   // coordinate search from the current plan: each knob in turn over its
   // values, the others at their best so far
-  Knobs best_k{b->order, b->xlines_cap, b->ytile_cap, b->elem1_sys};
+  Knobs best_k{b->order, b->xlines_cap, b->ytile_cap, b->elem1_sys, b->line_mfma};
   float best_ms = 0.0f;
   if ((st = run_trial(best_k, &best_ms)) == CEM_OK) trials.push_back({best_k, best_ms});
-  for (int knob = 0; knob < 4 && st == CEM_OK; ++knob) {
-    const std::vector<int>& vals = knob == 0 ? orders : knob == 1 ? xcaps : knob == 2 ? ycaps : syss;
+  for (int knob = 0; knob < 5 && st == CEM_OK; ++knob) {
+    const std::vector<int>& vals =
+        knob == 0 ? orders : knob == 1 ? xcaps : knob == 2 ? ycaps : knob == 3 ? syss : mfmas;
     for (int v : vals) {
       Knobs k = best_k;
-      int* slot = knob == 0 ? &k.order : knob == 1 ? &k.xcap : knob == 2 ? &k.ycap : &k.sys;
+      int* slot = knob == 0 ? &k.order : knob == 1 ? &k.xcap : knob == 2 ? &k.ycap : knob == 3 ? &k.sys : &k.mfma;
       *slot = v;
       bool seen = false;       // each plan is timed once
       for (const Trial& t : trials)
-        seen = seen || (t.k.order == k.order && t.k.xcap == k.xcap && t.k.ycap == k.ycap && t.k.sys == k.sys);
+        seen = seen || (t.k.order == k.order && t.k.xcap == k.xcap && t.k.ycap == k.ycap && t.k.sys == k.sys &&
+                        t.k.mfma == k.mfma);
       if (seen) continue;
       float ms = 0.0f;
       if ((st = run_trial(k, &ms)) != CEM_OK) break;
@@ -1722,6 +1788,7 @@ cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, vo
   b->xlines_cap = best_k.xcap;
   b->ytile_cap = best_k.ycap;
   b->elem1_sys = best_k.sys;
+  b->line_mfma = best_k.mfma;
   batch_drop_graph(b);
   b->plan_dt = b->plan_cfl = -1.0;
   st = restore();
@@ -1734,8 +1801,9 @@ cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, vo
       char buf[256];
       std::snprintf(buf, sizeof(buf),
                     "{\"order\": \"%s\", \"xlines_cap\": %d, \"ytile_lds_bytes\": %d, \"elem1\": \"%s\", "
-                    "\"ms_per_step\": %.4f}",
-                    k.order ? "largest_first" : "input", k.xcap, k.ycap, k.sys ? "system" : "tile", ms);
+                    "\"lines\": \"%s\", \"ms_per_step\": %.4f}",
+                    k.order ? "largest_first" : "input", k.xcap, k.ycap, k.sys ? "system" : "tile",
+                    k.mfma ? "matrix" : "vector", ms);
       return std::string(buf);
     };
     std::string r = "{\"trials\": [";

@@ -826,6 +826,214 @@ __device__ __forceinline__ V pick_m(const V* v, int c) {
 }
 
 // ---------------------------------------------------------------------------
+// Line operators on the matrix cores (float64).  16 lines x TY = 128
+// outputs of a line operator are a block-Toeplitz product out[i][j] =
+// sum_x K[i][x] in[x][j], K[i][x] = w[i mod P][x - i + W] inside the band
+// and 0 outside: eight row groups of 16 outputs, each a chain of NQ =
+// ceil((16 + 2W) / 4) V_MFMA_F64_16X16X4_F64 steps along its band.  The
+// matrix cores have the vector units' FP64 peak, but the vector kernels read
+// S + R staged inputs per R outputs from LDS and were bound by LDS bandwidth
+// on the strided axes; here one 512-byte LDS read feeds 1024 multiply-adds.
+// Lane layout of the instruction (checked with a one-wave probe on gfx950):
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
+// D[4 r + l / 16][l % 16] in result r.  The strided axes multiply K (A) by
+// the staged inputs (B), so a result row is one output position across 16
+// consecutive lines (a 128-byte store); axis 0 multiplies the transposed
+// product, inputs as A and K as B, so a result row is 16 consecutive
+// outputs of one line.
+//
+// A block walks a segment of its 16 lines in chunks of TY outputs.  The
+// staged rows live in an LDS ring of 256 rows: chunk c reads rows base ..
+// base + TY + HALO - 1 (mod 256), base = c TY; the TY new rows of chunk c+1
+// are loaded into registers before chunk c's products and stored after
+// them, over rows the next chunk no longer needs (TY + HALO <= 256), so the
+// halo is read from HBM once per segment and the loads overlap the matrix
+// work.
+// ---------------------------------------------------------------------------
+typedef double cem_v4d __attribute__((ext_vector_type(4)));
+constexpr int kMfmaLines = 16;     // lines per block
+constexpr int kMfmaTY = 128;       // outputs per chunk (8 row groups of 16)
+constexpr int kMfmaRing = 256;     // LDS ring rows
+template <int P> struct MfmaLine {
+  static constexpr int W = LineTaps<P>::W, S = LineTaps<P>::S;
+  static constexpr int NQ = (16 + 2 * W + 3) / 4;   // band steps of 4 inputs
+  static constexpr int HALO = 4 * NQ - 16;          // staged rows beyond the TY outputs
+  static_assert(kMfmaTY + HALO <= kMfmaRing, "chunk and halo must fit the ring");
+  // K's row groups are alike when P divides 16 (chunk starts are multiples
+  // of 16): the K operand of every step stays in registers; for P = 3 it is
+  // read from the weights staged in LDS
+  static constexpr bool KREG = 16 % P == 0;
+};
+
+// LDS bytes of a block
+template <int P>
+__host__ __device__ constexpr size_t line_mfma_lds() {
+  return (size_t)kMfmaRing * kMfmaLines * sizeof(double) +
+         (MfmaLine<P>::KREG ? 0 : (size_t)P * MfmaLine<P>::S * sizeof(double));
+}
+
+// block (bx, by): lines bx*16 .. +15, outputs [by a.ky TY, (by + 1) a.ky TY)
+// of them (a.ky chunks per segment)
+template <int P, bool AX0>
+__device__ __forceinline__ void k_line_mfma_body(const LineFastArgs& a, int bx, int by) {
+  using ML = MfmaLine<P>;
+  constexpr int W = ML::W, S = ML::S, NQ = ML::NQ, LW = kMfmaLines, TY = kMfmaTY, RB = kMfmaRing;
+  constexpr int ROWS = TY + ML::HALO, NV = TY / 16;
+  const int L = a.L;
+  double* sm = cem_smem;
+  double* wsm = sm + RB * LW;
+  const double* in = static_cast<const double*>(a.in);
+  double* out = static_cast<double*>(a.out);
+  const double* w = static_cast<const double*>(a.w);
+  const int t0 = bx * LW, seg0 = by * a.ky * TY;
+  const int nch = min(a.ky, (L - seg0 + TY - 1) / TY);
+  const int ntrans = (int)a.ntrans;
+  // offset of line t (32-bit: every offset is below m N < 2^31) and the
+  // stride along it; the lines of axis 0 are contiguous
+  auto base_of = [&](int t) -> int {
+    if constexpr (AX0) return t * L;
+    const int NT = (int)a.NT, comp = t / NT, rr = t - comp * NT;
+    if (a.axis == 1) {
+      const int x = rr % a.L0, z = rr / a.L0;
+      return comp * (int)a.N + x + z * a.L0 * a.L1;
+    }
+    return comp * (int)a.N + rr;
+  };
+  const int sl = AX0 ? 1 : (a.axis == 1 ? a.L0 : a.L0 * a.L1);
+  // staging: thread (j, r0) = (tid % 16, tid / 16) takes rows r0 + 16 k of
+  // line j.  A row of the strided axes is 128 contiguous bytes; on axis 0
+  // four lanes read 32 contiguous bytes of one line.
+  const int j = threadIdx.x & (LW - 1), r0 = threadIdx.x >> 4;
+  const bool have = t0 + j < ntrans;
+  const int lb = have ? base_of(t0 + j) : 0;
+  auto wrap = [&](int p) {
+    while (p < 0) p += L;
+    while (p >= L) p -= L;
+    return p;
+  };
+  // chunk 0: ring rows 0 .. ROWS-1 = positions seg0 - W + row
+  {
+    int p = wrap(seg0 - W + r0);
+    int row = r0;
+    for (; row + 112 < ROWS; row += 128) {
+      double v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        v[k] = have ? in[lb + p * sl] : 0.0;
+        p += 16;
+        if (p >= L) p -= L;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sm[(row + 16 * k) * LW + j] = v[k];
+    }
+    for (; row < ROWS; row += 16) {
+      sm[row * LW + j] = have ? in[lb + p * sl] : 0.0;
+      p += 16;
+      if (p >= L) p -= L;
+    }
+    if constexpr (!ML::KREG)
+      for (int i = threadIdx.x; i < P * S; i += blockDim.x) wsm[i] = w[i];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ii = lane & 15, kk = lane >> 4;
+  // K operand of band step q: K[ii][kk] of the step = w[class][4 q + kk - ii]
+  double kreg[ML::KREG ? NQ : 1];
+  if constexpr (ML::KREG) {
+    const int cls = ii % P;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int t = 4 * q + kk - ii;
+      kreg[q] = (t >= 0 && t < S) ? w[cls * S + t] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int oline = t0 + ii;                 // strided axes: this lane's output line
+  const int ob = oline < ntrans ? base_of(oline) : 0;
+  for (int c = 0; c < nch; ++c) {
+    const int s = seg0 + c * TY, base = (c * TY) & (RB - 1);
+    // the next chunk's new rows (positions s + TY - W + HALO + r0 + 16 k)
+    const bool more = c + 1 < nch;
+    double v[NV];
+    if (more) {
+      int p = wrap(s + TY - W + ML::HALO + r0);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        v[k] = have ? in[lb + p * sl] : 0.0;
+        p += 16;
+        if (p >= L) p -= L;
+      }
+    }
+    // wave wv: row groups wv and wv + 4, two independent chains
+    cem_v4d acc[2];
+    int cls[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      acc[h] = cem_v4d{0.0, 0.0, 0.0, 0.0};
+      cls[h] = (s + 16 * (wv + 4 * h) + ii) % P;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double kv;
+        if constexpr (ML::KREG) {
+          kv = kreg[q];
+        } else {
+          const int t = 4 * q + kk - ii;
+          kv = (t >= 0 && t < S) ? wsm[cls[h] * S + t] : 0.0;
+        }
+        const int row = (base + 16 * (wv + 4 * h) + 4 * q + kk) & (RB - 1);
+        const double xv = sm[row * LW + ii];
+        if constexpr (AX0)
+          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, kv, acc[h], 0, 0, 0);
+        else
+          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, xv, acc[h], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = wv + 4 * h;
+      if constexpr (AX0) {
+        const int pos = s + 16 * g + ii;
+        if (pos < L) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int line = t0 + 4 * r + kk;
+            if (line < ntrans) out[line * L + pos] = acc[h][r];
+          }
+        }
+      } else if (oline < ntrans) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int pos = s + 16 * g + 4 * r + kk;
+          if (pos < L) out[ob + pos * sl] = acc[h][r];
+        }
+      }
+    }
+    if (!more) break;
+    __syncthreads();     // every wave is done with chunk c's rows
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sm[((base + ROWS + r0 + 16 * k) & (RB - 1)) * LW + j] = v[k];
+    __syncthreads();
+  }
+}
+
+template <int P, bool AX0>
+__global__ void __launch_bounds__(256) k_line_mfma(LineFastArgs a) {
+  k_line_mfma_body<P, AX0>(a, blockIdx.x, blockIdx.y);
+}
+
+// chunks per segment of an MFMA line block: whole lines unless fewer than
+// min_blocks blocks would result, then segments of ceil(chunks / k) chunks
+inline int line_mfma_chunks(int64_t ntrans, int L, int64_t min_blocks) {
+  const int64_t gx = (ntrans + kMfmaLines - 1) / kMfmaLines;
+  const int chunks = (L + kMfmaTY - 1) / kMfmaTY;
+  int nseg = 1;
+  while (nseg < chunks && gx * nseg < min_blocks) ++nseg;
+  return (chunks + nseg - 1) / nseg;
+}
+
+// ---------------------------------------------------------------------------
 // sum-factorised element operators
 // ---------------------------------------------------------------------------
 // y = (A along axis K) x with the P1 x P1 table A at offset ao:

@@ -54,6 +54,15 @@ __global__ void __launch_bounds__(256) kb_line_y(const LineFastArgs* __restrict_
   k_line_y_body<P, RE, TI, TO>(args[pid], lb % gx, lb / gx);
 }
 
+// matrix-core line tiles: local block lb -> (lb % gx, lb / gx) as above
+template <int P, bool AX0>
+__global__ void __launch_bounds__(256) kb_line_mfma(const LineFastArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  const int gx = args[pid].gx;
+  k_line_mfma_body<P, AX0>(args[pid], lb % gx, lb / gx);
+}
+
 template <int P, int PH, bool WS, class RT>
 __global__ void CEM_TILE_BOUNDS kb_elem1_tile(const StageArgs* __restrict__ args, BatchMap m) {
   int lb;

@@ -65,11 +65,16 @@ def lumped_mass(orc):
     return mesh.multiplicity() * mesh.h ** mesh.d / mesh.nloc
 
 
+# switches of the HIP path alone (kernel choices with the same results)
+GPU_ONLY = ("line_kernels",)
+
+
 def oracle_for(wl, modes=None, bounds=None):
     mesh = Mesh(wl.d, wl.p, wl.n, wl.lo, wl.hi)
     prm = Params(w_lin=wl.w_lin, q=wl.q)
     for k, v in (modes or {}).items():
-        setattr(prm, k, v)
+        if k not in GPU_ONLY:
+            setattr(prm, k, v)
     if bounds is None:
         bounds = (float(wl.u0.min()), float(wl.u0.max()))
     prob = Problem(mesh, wl.kind, wl.velocity, wl.gamma_gas, params=prm,
@@ -84,8 +89,11 @@ def gpu_for(wl, modes=None, precision="fp64"):
     from paper_2509_04673_amd.cem import Solver
     kw = {}
     for k, v in (modes or {}).items():
-        kw[k] = v if k in ("flux_mode", "bounds") else MODE_CODES[v]
+        if k not in GPU_ONLY:
+            kw[k] = v if k in ("flux_mode", "bounds") else MODE_CODES[v]
     s = Solver.from_workload(wl, precision=precision, **kw)
+    if "line_kernels" in (modes or {}):
+        s.set_line_kernels(modes["line_kernels"])
     s.upload(wl.u0)
     if wl.kind != "euler":
         s.set_bounds()

@@ -53,7 +53,7 @@ def test_create_and_sizes_on_host():
 
 
 @pytest.mark.parametrize("bad", ["dim", "degree", "cells", "aspect", "gamma", "velocity", "precision",
-                                 "flux_mode", "too_large"])
+                                 "flux_mode", "bounds", "too_large"])
 def test_create_rejects_invalid_configurations(bad):
     kw = dict()
     mesh, phys = _desc()
@@ -62,6 +62,8 @@ def test_create_rejects_invalid_configurations(bad):
         prm.precision = 5
     elif bad == "flux_mode":
         prm.flux_mode = 3
+    elif bad == "bounds":
+        prm.bounds = 2
     elif bad == "too_large":
         # m N must stay below 2^31 (32-bit device index arithmetic)
         mesh.dim, mesh.degree = 3, 2
@@ -98,5 +100,18 @@ def test_calls_before_bind_are_rejected():
             cem.cem_rk_stage(ctx, 0, 1e-3)
         with pytest.raises(cem.CemError):
             cem.cem_check_invariants(ctx)
+    finally:
+        cem.cem_destroy(ctx)
+
+
+def test_line_kernel_mode_is_validated_on_the_host():
+    mesh, phys = _desc()
+    ctx = cem.cem_create(mesh, phys, cem.cem_params_default(), 0)
+    try:
+        for mode in (0, 1, 2):
+            cem.cem_set_line_kernels(ctx, mode)
+        for bad in (-1, 3):
+            with pytest.raises(cem.CemError):
+                cem.cem_set_line_kernels(ctx, bad)
     finally:
         cem.cem_destroy(ctx)

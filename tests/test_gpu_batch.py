@@ -25,6 +25,8 @@ def _batch_for(wls, precision="fp64", **modes):
 
 
 def _singles(wls, nsteps, dt, cfl, precision="fp64", **modes):
+    # the batch's float64 line passes run on the matrix cores by default
+    modes.setdefault("line_kernels", 1)
     outs = []
     for w in wls:
         s = gpu_for(w, modes, precision=precision)
@@ -153,16 +155,18 @@ def test_batch_autotune_keeps_state_and_results():
     rep = b.autotune(cfl=0.5, steps=1)
     announce(f"[batch] autotune: {rep['best']} from {len(rep['trials'])} trials")
     # a coordinate search: every value of every knob is tried, each plan
-    # once (order 2, x-line caps 4, strided tile sizes 3, pass-1 kernel 2)
+    # once (order 2, x-line caps 4, strided tile sizes 3, pass-1 kernel 2,
+    # line kernels 2)
     trials = rep["trials"]
-    keys = [(t["order"], t["xlines_cap"], t["ytile_lds_bytes"], t["elem1"]) for t in trials]
-    assert len(set(keys)) == len(keys) and 8 <= len(trials) <= 11, keys
+    keys = [(t["order"], t["xlines_cap"], t["ytile_lds_bytes"], t["elem1"], t["lines"]) for t in trials]
+    assert len(set(keys)) == len(keys) and 9 <= len(trials) <= 12, keys
     assert rep["best"]["ms_per_step"] > 0
     assert rep["best"]["ms_per_step"] == min(t["ms_per_step"] for t in trials)
     assert {t["order"] for t in trials} == {"input", "largest_first"}
     assert {t["xlines_cap"] for t in trials} == {512, 1024, 2048, 4096}
     assert {t["ytile_lds_bytes"] for t in trials} == {20480, 40960, 57344}
     assert {t["elem1"] for t in trials} == {"tile", "system"}
+    assert {t["lines"] for t in trials} == {"matrix", "vector"}
     assert np.array_equal(b.download(split=False), before)     # state restored
     b.step(cfl=0.5, nsteps=2)
     tuned = b.download(split=False)
@@ -175,6 +179,7 @@ def test_batch_autotune_keeps_state_and_results():
     ref = _batch_for(wls)
     cem.cem_batch_set_plan(ref.b, 1 if best["order"] == "largest_first" else 0, best["xlines_cap"],
                            best["ytile_lds_bytes"], 1 if best["elem1"] == "system" else 0)
+    cem.cem_batch_set_line_kernels(ref.b, 1 if best["lines"] == "matrix" else 0)
     ref.step(cfl=0.5, nsteps=2)
     plain = ref.download(split=False)
     ref.close()
@@ -235,3 +240,19 @@ def test_batch_plan_region_holds_many_small_problems(elem1):
         s.close()
         assert err <= 1e-10, (k, err)
     assert all(c["violations"] == 0 and c["rho_min"] > 0 for c in chk)
+
+
+def test_batch_vector_lines_match_single_problems():
+    # the batch with its float64 line passes on the vector kernels
+    from paper_2509_04673_amd import cem
+    wls = W.euler_batch(seed=4, sizes=[32, 55, 97, 256])
+    b = _batch_for(wls)
+    cem.cem_batch_set_line_kernels(b.b, 0)
+    b.step(cfl=0.5, nsteps=2)
+    got = b.download()
+    b.close()
+    ref = _singles(wls, 2, 0.0, 0.5, line_kernels=0)
+    for k, (g, r) in enumerate(zip(got, ref)):
+        err = rel_linf(_cm(g, 4), _cm(r, 4))
+        announce(f"[batch] vector lines problem {k} n={wls[k].n[0]}: batch vs single rel Linf {err:.1e}")
+        assert err <= 1e-10, (k, err)

@@ -6,8 +6,9 @@ or four runs per thread (ky = 1, 2, 4), along axis 1 and along axis 2.
 One stage against the oracle on meshes big enough for the launch rule to
 pick each shape (asserted per case from the rule restated in
 parity_util.line_plan): every intermediate at relative L-infinity 1e-12 per
-component in float64, and the mixed form within the stage bounds of the
-mixed-form tests.  The 3D meshes run with gamma_e forced to 1 (gamma_mode
+component in float64 on the vector line kernels, and again on the
+matrix-core line tiles (which these mesh sizes take by default), and the
+mixed form within the stage bounds of the mixed-form tests.  The 3D meshes run with gamma_e forced to 1 (gamma_mode
 "one") to keep the oracle's WENO evaluation out of the test's time; the
 sensor does not touch the line passes, and every other intermediate is
 still compared.  The full-size 2D Q3 quadrant workload (512^2 cells) is one
@@ -53,7 +54,16 @@ def test_line_tiles_fp64(label, make, modes, plan64, plan32):
     got = {ax: line_plan(wl, ax, "fp64") for ax in range(1, wl.d)}
     announce(f"[lines] {label} float64 plan {got}")
     assert got == plan64
-    compare_stage(wl, modes, label, TOL, ref=_oracle_stage(label, wl, modes))
+    vec = dict(modes or {}, line_kernels=0)
+    compare_stage(wl, vec, label + "-vector", TOL, ref=_oracle_stage(label, wl, modes))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("label,make,modes,plan64,plan32", CASES, ids=[c[0] for c in CASES])
+def test_line_tiles_fp64_matrix_cores(label, make, modes, plan64, plan32):
+    wl = make()
+    mat = dict(modes or {}, line_kernels=1)
+    compare_stage(wl, mat, label + "-matrix", TOL, ref=_oracle_stage(label, wl, modes))
 
 
 @pytest.mark.timeout(600)

@@ -8,7 +8,7 @@ import math
 
 import pytest
 
-from parity_util import compare_stage, random_euler_workload, random_scalar_workload
+from parity_util import compare_stage, oracle_stage, random_euler_workload, random_scalar_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -34,6 +34,10 @@ CASES = [
 
 @pytest.mark.parametrize("label,make", CASES, ids=[c[0] for c in CASES])
 def test_wide_strided_runs_stage_parity(label, make):
+    # the vector line kernels (these meshes take the matrix-core tiles by
+    # default), then the matrix-core tiles against the same oracle stage
     wl = make()
     assert takes_wide_runs(wl)
-    compare_stage(wl, label=label, tol=TOL)
+    ref = oracle_stage(wl)
+    compare_stage(wl, dict(line_kernels=0), label=label + "-vector", tol=TOL, ref=ref)
+    compare_stage(wl, dict(line_kernels=1), label=label + "-matrix", tol=TOL, ref=ref)
