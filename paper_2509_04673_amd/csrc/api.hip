@@ -1092,6 +1092,12 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   for (int k = 0; k < 3; ++k) c->ph.vel[k] = k < d ? phys->velocity[k] : 0.0;
   c->ph.vnorm = std::sqrt(c->ph.vel[0] * c->ph.vel[0] + c->ph.vel[1] * c->ph.vel[1] + c->ph.vel[2] * c->ph.vel[2]);
   c->ph.gam = phys->gamma_gas;
+  c->ph.rn = 0;
+  if (phys->kind == CEM_EULER) {
+    // the integer 1 / ex of the two-rarefaction bound, when there is one
+    const double r = 2.0 * phys->gamma_gas / (phys->gamma_gas - 1.0), rr = std::nearbyint(r);
+    if (rr >= 2.0 && rr <= 32.0 && std::fabs(r - rr) <= 1e-9 * rr) c->ph.rn = (int)rr;
+  }
   c->stream = (hipStream_t)stream;
   if (!build_tables(d, p, h, c->L, kWfast, kRfast, kSfast, kWfast32, kSfast32, c->tabs)) {
     delete c;

@@ -27,6 +27,7 @@ struct PhysParams {
   double vel[3];
   double vnorm;     // |v| (advection)
   double gam;       // ratio of specific heats (Euler)
+  int rn;           // 2 gamma / (gamma - 1) when an integer in [2, 32] (7 for 1.4, 5 for 5/3), else 0
 };
 
 struct DevTabs {
@@ -175,20 +176,28 @@ template <int D> struct Phys<D, KPP> {
   }
 };
 
+// pow kept out of the callers' register allocation (a rarely taken path)
+__device__ __attribute__((noinline)) double pow_out_of_line(double x, double y) { return pow(x, y); }
+
 template <int D> struct Phys<D, EUL> {
   static constexpr int M = D + 2;
   static constexpr bool kNodal = false;
+  // every quotient by the density is a product with 1 / rho, which the
+  // compiler computes once per state however many fluxes, pressures and
+  // speeds of that state are formed (one division instead of up to five)
   template <class T>
   __device__ static inline T pressure(const T* u, const PhysParams& pp) {
     T m2 = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) m2 += u[1 + k] * u[1 + k];
-    return ((T)pp.gam - (T)1) * (u[D + 1] - (T)0.5 * m2 / u[0]);
+    const T ir = (T)1 / u[0];
+    return ((T)pp.gam - (T)1) * (u[D + 1] - (T)0.5 * m2 * ir);
   }
   template <class T>
   __device__ static inline void flux(int k, const T* u, T* f, const PhysParams& pp) {
     const T p = pressure(u, pp);
-    const T vk = u[1 + k] / u[0];
+    const T ir = (T)1 / u[0];
+    const T vk = u[1 + k] * ir;
     f[0] = u[1 + k];
 #pragma unroll
     for (int j = 0; j < D; ++j) f[1 + j] = u[1 + j] * vk + (j == k ? p : (T)0);
@@ -201,13 +210,52 @@ template <int D> struct Phys<D, EUL> {
   }
   __device__ static inline double node_speed(const double* u, const PhysParams& pp) {
     double v2 = 0.0;
+    const double ir = 1.0 / u[0];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const double v = u[1 + k] / u[0];
+      const double v = u[1 + k] * ir;
       v2 += v * v;
     }
-    const double c = sqrt(fmax(0.0, pp.gam * pressure(u, pp) / u[0]));
+    const double c = sqrt(fmax(0.0, pp.gam * pressure(u, pp) * ir));
     return sqrt(v2) + c;
+  }
+  // x^n for an integer n >= 1 (repeated squaring)
+  __device__ static inline double int_pow(double x, int n) {
+    double r = 1.0, b = x;
+    for (;;) {
+      if (n & 1) r *= b;
+      n >>= 1;
+      if (!n) return r;
+      b *= b;
+    }
+  }
+  // p^(-ex), ex = (gamma - 1) / (2 gamma).  With the integer n = 1 / ex of
+  // common gases: p = m 2^e with e = n q + r, 0 <= r < n, so p^(-1/n) =
+  // 2^(-q) (m 2^r)^(-1/n); the root of p' = m 2^r in [0.5, 2^31) is Newton's
+  // method on p' y^n = 1 from a float seed (hardware log2 / exp2), y <- y
+  // (n + 1 - p' y^n) / n, whose relative error (~1e-7) squares to ~1e-12 and
+  // then to float64 rounding in the second step.  pow's special values are
+  // kept (0 -> inf, inf -> 0, negative or NaN -> NaN).  A double pow costs
+  // ~230 instructions here, this ~30; other gases call pow out of line (it
+  // would otherwise raise the register pressure of every caller).
+  __device__ static inline double p_pow_mex(double p, double ex, const PhysParams& pp) {
+    if (!pp.rn) return pow_out_of_line(p, -ex);
+    if (!(p > 0.0)) return p == 0.0 ? (double)INFINITY : (double)NAN;
+    if (p == (double)INFINITY) return 0.0;
+    const int n = pp.rn;
+    int e;
+    const double m = frexp(p, &e);
+    const int q = (int)floorf((float)e / (float)n);
+    const double pr = ldexp(m, e - q * n);
+    const double inv_n = 1.0 / n;
+    double y = (double)exp2f(-log2f((float)pr) / (float)n);
+    y *= ((double)(n + 1) - pr * int_pow(y, n)) * inv_n;
+    y *= ((double)(n + 1) - pr * int_pow(y, n)) * inv_n;
+    return ldexp(y, -q);
+  }
+  // x^(1 / ex): x^n with the integer n, else pow out of line
+  __device__ static inline double pow_inv_ex(double x, double ex, const PhysParams& pp) {
+    return pp.rn ? int_pow(x, pp.rn) : pow_out_of_line(x, 1.0 / ex);
   }
   // Guaranteed upper bound of the largest wave speed of the 1D Riemann
   // problem along +e_k: two-rarefaction estimate of the star pressure
@@ -215,14 +263,15 @@ template <int D> struct Phys<D, EUL> {
   __device__ static inline double riemann_speed(const double* uL, const double* uR, int k,
                                                 const PhysParams& pp) {
     const double g = pp.gam;
-    const double vL = uL[1 + k] / uL[0], vR = uR[1 + k] / uR[0];
+    const double irL = 1.0 / uL[0], irR = 1.0 / uR[0];
+    const double vL = uL[1 + k] * irL, vR = uR[1 + k] * irR;
     const double pL = pressure(uL, pp), pR = pressure(uR, pp);
-    const double cL = sqrt(fmax(0.0, g * pL / uL[0]));
-    const double cR = sqrt(fmax(0.0, g * pR / uR[0]));
+    const double cL = sqrt(fmax(0.0, g * pL * irL));
+    const double cR = sqrt(fmax(0.0, g * pR * irR));
     const double ex = (g - 1.0) / (2.0 * g);
     const double num = fmax(cL + cR - 0.5 * (g - 1.0) * (vR - vL), 0.0);
-    const double den = cL * pow(pL, -ex) + cR * pow(pR, -ex);
-    const double ps = pow(num / den, 1.0 / ex);
+    const double den = cL * p_pow_mex(pL, ex, pp) + cR * p_pow_mex(pR, ex, pp);
+    const double ps = pow_inv_ex(num / den, ex, pp);
     const double kap = (g + 1.0) / (2.0 * g);
     const double l1 = vL - cL * sqrt(1.0 + kap * fmax(0.0, (ps - pL) / pL));
     const double l3 = vR + cR * sqrt(1.0 + kap * fmax(0.0, (ps - pR) / pR));
@@ -238,14 +287,15 @@ template <int D> struct Phys<D, EUL> {
       mL += n[k] * uL[1 + k];
       mR += n[k] * uR[1 + k];
     }
-    const double vL = mL / uL[0], vR = mR / uR[0];
+    const double irL = 1.0 / uL[0], irR = 1.0 / uR[0];
+    const double vL = mL * irL, vR = mR * irR;
     const double pL = pressure(uL, pp), pR = pressure(uR, pp);
-    const double cL = sqrt(fmax(0.0, g * pL / uL[0]));
-    const double cR = sqrt(fmax(0.0, g * pR / uR[0]));
+    const double cL = sqrt(fmax(0.0, g * pL * irL));
+    const double cR = sqrt(fmax(0.0, g * pR * irR));
     const double ex = (g - 1.0) / (2.0 * g);
     const double num = fmax(cL + cR - 0.5 * (g - 1.0) * (vR - vL), 0.0);
-    const double den = cL * pow(pL, -ex) + cR * pow(pR, -ex);
-    const double ps = pow(num / den, 1.0 / ex);
+    const double den = cL * p_pow_mex(pL, ex, pp) + cR * p_pow_mex(pR, ex, pp);
+    const double ps = pow_inv_ex(num / den, ex, pp);
     const double kap = (g + 1.0) / (2.0 * g);
     const double l1 = vL - cL * sqrt(1.0 + kap * fmax(0.0, (ps - pL) / pL));
     const double l3 = vR + cR * sqrt(1.0 + kap * fmax(0.0, (ps - pR) / pR));

@@ -135,8 +135,9 @@ __device__ __forceinline__ V euler_flux_comp(int k, int c, const V* u, double ga
   V m2 = 0;
 #pragma unroll
   for (int j = 0; j < D; ++j) m2 += u[1 + j] * u[1 + j];
-  const V p = ((V)gam - (V)1) * (u[D + 1] - (V)0.5 * m2 / u[0]);
-  const V vk = mk / u[0];
+  const V ir = (V)1 / u[0];
+  const V p = ((V)gam - (V)1) * (u[D + 1] - (V)0.5 * m2 * ir);
+  const V vk = mk * ir;
   V r = pick_c<D + 2>(u, c) * vk + (c - 1 == k ? p : (V)0);
   if (c == 0) r = mk;
   if (c == D + 1) r = vk * (u[D + 1] + p);
