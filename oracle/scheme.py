@@ -59,6 +59,12 @@ class Params:
     # imposed on ubar^e (flux limiter) and on the limited states of the
     # element's nodes (slope limiter)
     bounds: str = "global"
+    # antidiffusive element contributions: "aec" = [KHV eq. (45)]; "q1" =
+    # the Q1 form of [KHV Sec. 5.3] (p = 1), gamma_e (m_i^e (u_i - u^e) -
+    # dt_e [int (phi_i - m_i^e/|K|) div f_h + int phi_i (udot_h^L -
+    # udot_i^L)]), with udot^L the time derivative of the low-order scheme
+    # of [KHV Sec. 3] (eq. weak:low1 with the Rusanov term, b_i = 0)
+    contrib: str = "aec"
 
 
 @dataclass
@@ -128,6 +134,8 @@ class Oracle:
         d = self.mesh.d
         self.nbr = {(k, s): self.mesh.neighbour(k, s) for k in range(d) for s in (-1, 1)}
         self.mult = self.mesh.multiplicity()
+        if prob.params.contrib == "q1" and self.mesh.p != 1:
+            raise ValueError("the Q1 element contributions are defined for p = 1")
 
     # -- global consistent mass matrix, exact solve -------------------------
     @cached_property
@@ -454,12 +462,27 @@ class Oracle:
                             for k in range(d))                 # int phi_i div f_h
         fdiv_tot = area * sum(np.einsum("j,cej->ce", el.int_dphi[k], fh_nodes[k])
                               for k in range(d))               # int div f_h
-        Ud = udot[:, conn]
-        cons = vol * np.einsum("ij,cej->cei", el.mass, Ud) - mloc * Ud
-        fe = (mloc * (U - ue[:, :, None])
-              + dt_e[None, :, None] * ((A - fgrad_h)
-                                       - (fdiv_h - (mloc / vol) * fdiv_tot[:, :, None])
-                                       - S - cons))
+        mi = self.assemble(np.broadcast_to(mloc, (1, E, nloc)).copy())[0]
+        udot_lo = None
+        if prm.contrib == "q1":
+            # low-order time derivative [KHV eq. (weak:low1)], periodic (b = 0):
+            # m_i udot_i^L = -a_i - s_i, a_i = sum_e (m_i^e/|K_e|) int div f_h,
+            # s_i^e = (m_i^e / dt_e)(u_i - u^e) [KHV eq. (rusdiss)]
+            lo = (-(mloc / vol)[None, None, :] * fdiv_tot[:, :, None]
+                  - mloc[None, None, :] / dt_e[None, :, None] * (U - ue[:, :, None]))
+            udot_lo = self.assemble(lo) / mi
+            UdL = udot_lo[:, conn]
+            consL = vol * np.einsum("ij,cej->cei", el.mass, UdL) - mloc * UdL
+            fe = gamma[None, :, None] * (
+                mloc * (U - ue[:, :, None])
+                - dt_e[None, :, None] * ((fdiv_h - (mloc / vol) * fdiv_tot[:, :, None]) + consL))
+        else:
+            Ud = udot[:, conn]
+            cons = vol * np.einsum("ij,cej->cei", el.mass, Ud) - mloc * Ud
+            fe = (mloc * (U - ue[:, :, None])
+                  + dt_e[None, :, None] * ((A - fgrad_h)
+                                           - (fdiv_h - (mloc / vol) * fdiv_tot[:, :, None])
+                                           - S - cons))
 
         # slope limiter [KHV eqs. (54), (55)] / Appendix A
         if prm.beta_mode == "one":
@@ -488,13 +511,12 @@ class Oracle:
             raise CFLViolation(float(dt), float(dt_e.min()))
         ratio = (dt / dt_e)[None, :, None]
         contrib = mloc * ((1.0 - ratio) * U + ratio * ubar_i)
-        mi = self.assemble(np.broadcast_to(mloc, (1, E, nloc)).copy())[0]
         u_fe = self.assemble(contrib) / mi
 
         taps = dict(g=g, gamma=gamma, nu=nu, lam_e=lam_e, r=r, udot=udot, ue=ue,
                     fgrad_h=fgrad_h, fH=np.stack(fH_c), fL=np.stack(fL_c), lam_f=np.stack(lam_c),
                     dt_e=dt_e, ubarL=ubarL, fA=np.stack(fA_c), fAbar=np.stack(fAbar_c),
-                    b_lo=b_lo, b_hi=b_hi,
+                    b_lo=b_lo, b_hi=b_hi, fdiv_tot=fdiv_tot, udot_lo=udot_lo,
                     ubar=ubar, fe=fe, beta=beta, A=A, S=S, u_fe=u_fe)
         return u_fe, taps
 
