@@ -91,6 +91,21 @@ typedef enum { CEM_FLUX_LIMIT = 0, CEM_FLUX_SUBCELL = 1, CEM_FLUX_SHRINK = 2 } c
  *   dt_e (the Remark after eq. 40).  Ignored for Euler. */
 typedef enum { CEM_BOUNDS_GLOBAL = 0, CEM_BOUNDS_LOCAL = 1 } cem_bounds_mode;
 
+/* Antidiffusive element contributions f_i^e.
+ * CEM_CONTRIB_AEC: eq. (45), the contributions that recover the stabilized
+ *   high-order scheme (every degree).
+ * CEM_CONTRIB_Q1: the Q1 form of Sec. 5.3, gamma_e (m_i^e (u_i - u^e) -
+ *   dt_e [int (phi_i - m_i^e/|K|) div f_h + int phi_i (udot_h^L -
+ *   udot_i^L)]), with udot^L the time derivative of the low-order scheme
+ *   of Sec. 3 (lumped mass, element-averaged flux divergence and the
+ *   Rusanov term with the element's pseudo time step; b_i = 0 on the
+ *   periodic box).  Degree 1, scalar problems, float64, single problems
+ *   only (CEM_EINVAL otherwise).  The stage still computes g, r and the
+ *   consistent-mass solve (debug taps 0, 1), and tap 2 then holds udot^L.
+ *   The entropy correction of Sec. 5.3.2 is not provided: its nodal sensors
+ *   are defined only in the cited work. */
+typedef enum { CEM_CONTRIB_AEC = 0, CEM_CONTRIB_Q1 = 1 } cem_contrib;
+
 /* Uniform periodic box [lo, hi] with n[k] cube cells per axis (cell edge h
  * equal on every axis; unused axes ignored).  n[k] >= 2. */
 typedef struct {
@@ -122,6 +137,7 @@ typedef struct {
   int precision;       /* cem_precision */
   int flux_mode;       /* cem_flux_mode */
   int bounds;          /* cem_bounds_mode */
+  int contrib;         /* cem_contrib */
 } cem_params;
 
 typedef struct cem_ctx cem_ctx;
@@ -153,7 +169,8 @@ typedef struct {
 
 /* Fills p with the defaults: q = 1, r = 2, eps = 1e-12, w_lin = 1e-3,
  * eps_pos = 1e-10, clamp_ulps = 64, all modes 0, bounds (-inf, +inf),
- * precision CEM_FP64, flux_mode CEM_FLUX_LIMIT, bounds CEM_BOUNDS_GLOBAL. */
+ * precision CEM_FP64, flux_mode CEM_FLUX_LIMIT, bounds CEM_BOUNDS_GLOBAL,
+ * contrib CEM_CONTRIB_AEC. */
 cem_status cem_params_default(cem_params* p);
 
 /* Creates a context: validates the configuration and builds the element

@@ -21,6 +21,8 @@ FLUX_LIMIT, FLUX_SUBCELL, FLUX_SHRINK = 0, 1, 2
 FLUX_MODES = {"limit": FLUX_LIMIT, "subcell": FLUX_SUBCELL, "shrink": FLUX_SHRINK}
 BOUNDS_GLOBAL, BOUNDS_LOCAL = 0, 1
 BOUNDS = {"global": BOUNDS_GLOBAL, "local": BOUNDS_LOCAL}
+CONTRIB_AEC, CONTRIB_Q1 = 0, 1
+CONTRIBS = {"aec": CONTRIB_AEC, "q1": CONTRIB_Q1}
 STATUS = {0: "CEM_OK", -1: "CEM_EINVAL", -2: "CEM_EHIP", -3: "CEM_ENOMEM",
           -4: "CEM_ECFL", -5: "CEM_EIDP"}
 TAPS = dict(g=0, r=1, udot=2, gamma=3, nu=4, dt_e=5, ue=6, ubarL=7, ubar=8, beta=9,
@@ -49,7 +51,8 @@ class Params(ctypes.Structure):
                 ("clamp_ulps", ctypes.c_double), ("gamma_mode", ctypes.c_int),
                 ("alpha_mode", ctypes.c_int), ("beta_mode", ctypes.c_int),
                 ("u_min", ctypes.c_double), ("u_max", ctypes.c_double),
-                ("precision", ctypes.c_int), ("flux_mode", ctypes.c_int), ("bounds", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("flux_mode", ctypes.c_int), ("bounds", ctypes.c_int),
+                ("contrib", ctypes.c_int)]
 
 
 class Invariants(ctypes.Structure):
@@ -146,8 +149,8 @@ def cem_params_default():
 
 def make_params(params):
     """cem_params from the defaults and keyword overrides; precision,
-    flux_mode and bounds also take their names ("fp64" / "mixed", "limit" /
-    "subcell" / "shrink", "global" / "local")."""
+    flux_mode, bounds and contrib also take their names ("fp64" / "mixed",
+    "limit" / "subcell" / "shrink", "global" / "local", "aec" / "q1")."""
     prm = cem_params_default()
     for k, v in params.items():
         if k == "precision" and isinstance(v, str):
@@ -156,6 +159,8 @@ def make_params(params):
             v = FLUX_MODES[v]
         if k == "bounds" and isinstance(v, str):
             v = BOUNDS[v]
+        if k == "contrib" and isinstance(v, str):
+            v = CONTRIBS[v]
         setattr(prm, k, v)
     return prm
 

@@ -86,7 +86,7 @@ struct cem_ctx {
   size_t ws_need = 0;
   // workspace carve-up (byte offsets)
   size_t o_g, o_r, o_udot, o_tmp, o_tmp2, o_relem, o_ue, o_ubarL, o_ubar, o_fahi, o_dte, o_gam,
-      o_nu, o_beta, o_bnd, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart, o_fnode;
+      o_nu, o_beta, o_bnd, o_fdiv, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart, o_fnode;
   size_t o_g32 = 0, o_r32 = 0, o_udot32 = 0, o_tmp32 = 0, o_tmp2_32 = 0;
   bool fnode_valid = false;   // nodal fluxes match the bound state
   int lds_max = 65536;        // LDS bytes one block may use on the bound device
@@ -347,6 +347,8 @@ StageArgs make_args(const cem_ctx* c) {
   a.clamp_tol = c->prm.clamp_ulps * DBL_EPSILON * std::fmax(std::fabs(c->prm.u_min), std::fabs(c->prm.u_max));
   a.bounds_local = c->kind != CEM_EULER && c->prm.bounds == CEM_BOUNDS_LOCAL;
   a.bnd = c->W<double>(c->o_bnd);
+  a.contrib_q1 = c->prm.contrib == CEM_CONTRIB_Q1;
+  a.fdiv = c->W<double>(c->o_fdiv);
   a.u = c->u;
   a.u0 = c->u0;
   a.uout = c->u;
@@ -595,6 +597,13 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     cem_status s = launch_line(c, src, dst, k, false);
     if (s != CEM_OK) return s;
     src = dst;
+  }
+  if constexpr (P == 1 && PH != EUL && !MIX) {
+    // Q1 contributions: udot becomes the low-order time derivative
+    if (a.contrib_q1) {
+      hipLaunchKernelGGL((k_udot_lo<D, P>), dim3(nblocks(c->N, 256)), dim3(256), 0, c->stream, a);
+      HIPCHK(hipGetLastError());
+    }
   }
   if constexpr (PH == EUL && D >= 2) {
     cem_status st = launch_sys<D, P, PH, RT>(c, a, false);
@@ -1046,6 +1055,10 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
     return fail(CEM_EINVAL, "flux_mode must be CEM_FLUX_LIMIT, CEM_FLUX_SUBCELL or CEM_FLUX_SHRINK");
   if (prm->bounds != CEM_BOUNDS_GLOBAL && prm->bounds != CEM_BOUNDS_LOCAL)
     return fail(CEM_EINVAL, "bounds must be CEM_BOUNDS_GLOBAL or CEM_BOUNDS_LOCAL");
+  if (prm->contrib != CEM_CONTRIB_AEC && prm->contrib != CEM_CONTRIB_Q1)
+    return fail(CEM_EINVAL, "contrib must be CEM_CONTRIB_AEC or CEM_CONTRIB_Q1");
+  if (prm->contrib == CEM_CONTRIB_Q1 && (p != 1 || phys->kind == CEM_EULER || prm->precision != CEM_FP64))
+    return fail(CEM_EINVAL, "the Q1 contributions need degree 1, a scalar problem and float64");
   double h = 0.0;
   for (int k = 0; k < d; ++k) {
     if (mesh->n[k] < 2) return fail(CEM_EINVAL, "need at least 2 cells per axis");
@@ -1128,6 +1141,7 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->o_nu = take(E8);
   c->o_beta = take(E8);
   c->o_bnd = take(2 * E8);
+  c->o_fdiv = take(E8);
   c->o_dtbuf = take(8 * 8);
   // per-block dt_e minima: one-thread-per-element blocks, 2D element tiles
   // or the 32- / 64-element blocks of the system passes
@@ -1483,6 +1497,8 @@ cem_status cem_batch_create(int count, const cem_mesh_desc* meshes, const cem_ph
   const bool mixed = prm->precision == CEM_FP32_MIXED;
   if (!pick_batch(d, p, phys->kind, mixed).plan)
     return fail(CEM_EINVAL, "batched form: 2D problems or 3D Euler only");
+  if (prm->contrib == CEM_CONTRIB_Q1)
+    return fail(CEM_EINVAL, "batched form: the Q1 contributions run on single problems");
   cem_batch* b = new cem_batch();
   b->count = count;
   b->d = d;

@@ -83,6 +83,8 @@ struct StageArgs {
   double umin, umax, clamp_tol;
   int bounds_local;     // scalar limiters: 0 the global [umin, umax], 1 per-element bounds in bnd
   double* bnd;          // [2][E] per-element lower, upper bounds (bounds_local)
+  int contrib_q1;       // scalar Q1: element contributions of Sec. 5.3 (low-order derivative in udot)
+  double* fdiv;         // [E] int_dK f_h . n of each element (contrib_q1)
   const double* u;      // stage input u^(s)   [M][N]
   double* u0;           // step base u^n       [M][N]
   double* uout;         // stage output (may alias u: per-node read-then-write)
@@ -1951,6 +1953,14 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     a.ubarL[c * E + e] = ue[c] - dt_e / h * fLsum[c];
   }
   if constexpr (M == 1) {
+    // Q1 contributions: int_dK f_h . n = |S| sum over facets of the outward
+    // facet means of f(u_j) . n (the low-order scheme's a_i, Sec. 3)
+    if (a.contrib_q1) {
+      double area = 1.0;
+#pragma unroll
+      for (int k = 0; k < D - 1; ++k) area *= h;
+      a.fdiv[e] = area * fHout[0];
+    }
     // local bounds of the scalar limiters (Sec. 4.1, 4.2): the range of the
     // cell averages of K_e and its 2d facet neighbours; it holds ubar^{e,L}
     // (a convex combination of u^e and the facets' bar states).  NaN
@@ -2331,6 +2341,51 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
   // is removed in float64 so that the update stays conservative to float64
   // round-off.
   double f[M][NL];
+  // Q1 form of Sec. 5.3 (scalar, p = 1, float64): gamma_e (m_i^e (u_i - u^e)
+  // - dt_e [int (phi_i - m_i^e/|K|) div f_h + int phi_i (udot_h^L -
+  // udot_i^L)]), udot holding the low-order derivative; with int phi_i div
+  // f_h = B_i - int grad phi_i . f_h, the bracket is B_i - G_i - F^e / NL +
+  // the mass term, G_i = sum_j f_k(u_j) int d_k phi_i phi_j by the 1D Q1
+  // integrals (int B_a' B_b = -1/2 or 1/2 as a = 0 or 1; int B_a B_b = 1/3,
+  // 1/6)
+  constexpr bool Q1F = P == 1 && M == 1 && !MIX;
+  const bool q1 = Q1F && a.contrib_q1;
+  double q1g[Q1F ? NL : 1];
+  if constexpr (Q1F) {
+    if (q1) {
+      double fall[D][NL];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        if constexpr (PHY::kNodal) {
+          const int64_t nd = local_node<D, P>(j, off);
+#pragma unroll
+          for (int k = 0; k < D; ++k) fall[k][j] = a.fnode[(int64_t)k * N + nd];
+        } else {
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            double fv[1];
+            PHY::flux(k, &U[0][j], fv, a.ph);
+            fall[k][j] = fv[0];
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        double gi = 0.0;
+#pragma unroll
+        for (int j = 0; j < NL; ++j)
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            double cf = dig(i, k, 2) ? 0.5 : -0.5;
+#pragma unroll
+            for (int l = 0; l < D; ++l)
+              if (l != k) cf *= dig(i, l, 2) == dig(j, l, 2) ? (1.0 / 3.0) : (1.0 / 6.0);
+            gi += cf * fall[k][j];
+          }
+        q1g[i] = hpow * gi;
+      }
+    }
+  }
 #pragma unroll
   for (int c = 0; c < M; ++c) {
     RT Fe = 0;
@@ -2363,6 +2418,9 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
 #pragma unroll
         for (int k = 0; k < D; ++k) rb += fbar[k] * ref_grad_int<D, P>(i, k);
         f[c][i] = (R - hpow * rb) + (double)(-fb[c][i] + Fe * (RT)(1.0 / NL) - Tc);
+      } else if constexpr (Q1F) {
+        f[c][i] = q1 ? (double)(q1g[i] - fb[c][i] + Fe * (RT)(1.0 / NL) - Tc)
+                     : (double)(R - fb[c][i] + Fe * (RT)(1.0 / NL) - Tc);
       } else {
         f[c][i] = (double)(R - fb[c][i] + Fe * (RT)(1.0 / NL) - Tc);
       }
@@ -2373,8 +2431,9 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
       for (int i = 0; i < NL; ++i) zs += f[c][i];
       zs *= 1.0 / NL;
     }
+    const double gsc = q1 ? a.gam[e] : 1.0;
 #pragma unroll
-    for (int i = 0; i < NL; ++i) f[c][i] = mloc * (U[c][i] - uec[c]) + dt_e * (f[c][i] - zs);
+    for (int i = 0; i < NL; ++i) f[c][i] = gsc * (mloc * (U[c][i] - uec[c]) + dt_e * (f[c][i] - zs));
   }
 
   // ---- slope limiter
@@ -2754,6 +2813,31 @@ __global__ void __launch_bounds__(256) k_gather_line_x(StageArgs sa, LineFastArg
 
 // zero fill of n 32-bit words (counters and flags that must start at zero,
 // in code a caller may capture into a graph: a kernel, not a memset node)
+// Low-order time derivative for the Q1 contributions (Sec. 3, the
+// low-order scheme with its Rusanov term; periodic, b_i = 0):
+// udot_i^L = -(1 / |E_i|) sum over the elements e around node i of
+// F^e / |K| + (u_i - u^e) / dt_e, F^e = int_dK f_h . n from element pass 1;
+// m_i^e / m_i = 1 / |E_i| for Bernstein elements.  Elements in
+// node_elements' fixed order.  Scalar problems.
+template <int D, int P>
+__global__ void __launch_bounds__(256) k_udot_lo(StageArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.mesh.N) return;
+  int64_t eids[8];
+  int locs[8];
+  const int ne = node_elements<D, P>(i, a.mesh, eids, locs);
+  double vol = 1.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) vol *= a.mesh.h;
+  const double ui = a.u[i];
+  double s = 0.0;
+  for (int r = 0; r < ne; ++r) {
+    const int64_t e = eids[r];
+    s += a.fdiv[e] / vol + (ui - a.ue[e]) / a.dte[e];
+  }
+  a.udot[i] = -s / ne;
+}
+
 __global__ void __launch_bounds__(256) k_zero_words(unsigned* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;

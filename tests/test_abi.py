@@ -53,7 +53,7 @@ def test_create_and_sizes_on_host():
 
 
 @pytest.mark.parametrize("bad", ["dim", "degree", "cells", "aspect", "gamma", "velocity", "precision",
-                                 "flux_mode", "bounds", "too_large"])
+                                 "flux_mode", "bounds", "contrib", "q1_degree", "too_large"])
 def test_create_rejects_invalid_configurations(bad):
     kw = dict()
     mesh, phys = _desc()
@@ -64,6 +64,10 @@ def test_create_rejects_invalid_configurations(bad):
         prm.flux_mode = 3
     elif bad == "bounds":
         prm.bounds = 2
+    elif bad == "contrib":
+        prm.contrib = 2
+    elif bad == "q1_degree":
+        prm.contrib = cem.CONTRIB_Q1     # the default mesh has degree 2
     elif bad == "too_large":
         # m N must stay below 2^31 (32-bit device index arithmetic)
         mesh.dim, mesh.degree = 3, 2
