@@ -251,7 +251,9 @@ cem_status cem_reset_counters(cem_ctx* ctx);
  *   0 g [d][m][N]      1 r [m][N]        2 udot [m][N]    3 gamma [E]
  *   4 nu [E]           5 dt_e [E]        6 u^e [m][E]     7 ubar^{e,L} [m][E]
  *   8 ubar^e [m][E]    9 beta [E]       10 f^A of the +e_k facet [d][m][E]
- *  11 element update vectors [m][(p+1)^d][E]
+ *  11 element update vectors [m][(p+1)^d][E]   (tap 1, r, is stored by
+ *     cem_rk_stage; cem_step skips it where the assembly is fused with the
+ *     first mass pass, as the batched form always does)
  *  12 local bounds of the scalar limiters [2][E] (lower, upper; written by
  *     the element pass only with CEM_BOUNDS_LOCAL) */
 cem_status cem_debug_tap(cem_ctx* ctx, int tap, double* dst, size_t count);

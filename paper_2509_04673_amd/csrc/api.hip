@@ -98,6 +98,7 @@ struct cem_ctx {
   // whole-step HIP graph (captured on a private stream, launched on stream)
   bool use_graphs = true;
   bool copy_base_next = false;   // the next stage 0 also writes u_base = u
+  bool in_step = false;          // stages of cem_step: the fused assembly skips storing r
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph = nullptr;
   double graph_dt = -1.0, graph_cfl = -1.0;
@@ -348,6 +349,7 @@ StageArgs make_args(const cem_ctx* c) {
   a.bounds_local = c->kind != CEM_EULER && c->prm.bounds == CEM_BOUNDS_LOCAL;
   a.bnd = c->W<double>(c->o_bnd);
   a.contrib_q1 = c->prm.contrib == CEM_CONTRIB_Q1;
+  a.store_r = c->in_step ? 0 : 1;
   a.fdiv = c->W<double>(c->o_fdiv);
   a.u = c->u;
   a.u0 = c->u0;
@@ -630,6 +632,7 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
 template <int D, int P, int PH, class RT>
 StageArgs batch_stage_args(cem_ctx* c, int stage, double dt, double cfl) {
   StageArgs a = make_args(c);
+  a.store_r = 0;
   const double rka[3] = {0.0, 0.75, 1.0 / 3.0}, rkb[3] = {1.0, 0.25, 2.0 / 3.0};
   a.rk_a = rka[stage];
   a.rk_b = rkb[stage];
@@ -1260,9 +1263,11 @@ cem_status cem_rk_stage(cem_ctx* c, int stage, double dt, double cfl) {
 
 static cem_status step_direct(cem_ctx* c, double dt, double cfl) {
   c->copy_base_next = true;     // stage 0 writes u_base = u (no separate copy)
+  c->in_step = true;
   cem_status st = CEM_OK;
   for (int s = 0; s < 3 && st == CEM_OK; ++s) st = pick(c->d, c->p, c->kind, c->mixed)(c, s, dt, cfl);
   c->copy_base_next = false;
+  c->in_step = false;
   return st;
 }
 

@@ -84,6 +84,7 @@ struct StageArgs {
   int bounds_local;     // scalar limiters: 0 the global [umin, umax], 1 per-element bounds in bnd
   double* bnd;          // [2][E] per-element lower, upper bounds (bounds_local)
   int contrib_q1;       // scalar Q1: element contributions of Sec. 5.3 (low-order derivative in udot)
+  int store_r;          // the assembly fused with the first mass pass also stores r (a debug tap only)
   double* fdiv;         // [E] int_dK f_h . n of each element (contrib_q1)
   const double* u;      // stage input u^(s)   [M][N]
   double* u0;           // step base u^n       [M][N]
@@ -2779,7 +2780,7 @@ __device__ __forceinline__ void k_gather_line_x_body(const StageArgs& sa, const 
       }
     }
     sm[ql * LP + lds_slot<R>(W + x)] = (RT)s;
-    rr[(t0 + ql) * L + x] = (RT)s;         // component-major: line (t0 + ql) starts at its c N + ...
+    if (sa.store_r) rr[(t0 + ql) * L + x] = (RT)s;   // component-major: line t0 + ql starts at c N + ...
   }
   __syncthreads();
   // periodic padding of the rows from their interiors
