@@ -222,14 +222,14 @@ cem_status cem_step(cem_ctx* ctx, double dt, double cfl);
 
 /* Enables (default) or disables graph replay in cem_step. */
 cem_status cem_set_graphs(cem_ctx* ctx, int enable);
-/* Line kernels of the float64 stage (projected gradient, Sec. 2.2; mass
- * solve, Sec. 4.3 step 2; the results agree to rounding): mode 0 the
- * vector kernels (LDS runs, all gradient axes in one launch), 1 tiles of 16
- * lines on the matrix cores (the banded line operator as chains of float64
- * 16x16x4 matrix products), 2 (default) the matrix cores when a pass
- * covers at least 2^20 values.  The assembly-fused first mass pass and
- * lines too short for the truncated operators keep their kernels; the
- * mixed form always runs the vector kernels.  Drops the captured step. */
+/* Line kernels of the stage (projected gradient, Sec. 2.2; mass solve,
+ * Sec. 4.3 step 2; the results agree to rounding): mode 0 the vector
+ * kernels (LDS runs, all gradient axes in one launch), 1 tiles of 16 lines
+ * on the matrix cores (the banded line operator as chains of 16x16x4
+ * matrix products: float64, or float with float accumulation in the mixed
+ * form), 2 (default) the matrix cores when a pass covers at least 2^20
+ * values.  The assembly-fused first mass pass and lines too short for the
+ * truncated operators keep their kernels.  Drops the captured step. */
 cem_status cem_set_line_kernels(cem_ctx* ctx, int mode);
 
 /* Call after writing the bound state u by other means than
@@ -345,11 +345,11 @@ cem_status cem_batch_reset_counters(cem_batch* b);
  * system kernels (Euler only; 3D Euler always takes them).  The next step
  * rebuilds the plan. */
 cem_status cem_batch_set_plan(cem_batch* b, int order, int xlines_cap, int ytile_lds_bytes, int elem1_kernel);
-/* Line kernels of the float64 batch (projected gradient, Sec. 2.2; mass
- * solve, Sec. 4.3 step 2): matrix != 0 runs every fast-operator line pass
- * except the assembly-fused one as matrix-core tiles (the default), 0 as
- * the vector kernels.  Ignored in the mixed form.  The next step rebuilds
- * the plan. */
+/* Line kernels of the batch (projected gradient, Sec. 2.2; mass solve,
+ * Sec. 4.3 step 2): matrix != 0 runs every fast-operator line pass except
+ * the assembly-fused one as matrix-core tiles (the default; float64, or
+ * float products with float accumulation in the mixed form), 0 as the
+ * vector kernels.  The next step rebuilds the plan. */
 cem_status cem_batch_set_line_kernels(cem_batch* b, int matrix);
 /* Per-kernel timing of the batched launches, as cem_set_timing /
  * cem_kernel_times (the same kernel ids; each batched launch is one record,
@@ -370,8 +370,8 @@ cem_status cem_batch_check_invariants(cem_batch* b, cem_invariants* out, int n);
  * per thread along the line, or the row groups of a matrix-core tile); for
  * 2D Euler the element pass-1 kernel (the 16 x 8 element LDS tile with one
  * thread per element, or element blocks with one thread per element and
- * component); in float64 the line kernels (matrix-core tiles or vector
- * runs, cem_batch_set_line_kernels).  Keeps the fastest plan and
+ * component); the line kernels (matrix-core tiles or vector runs,
+ * cem_batch_set_line_kernels).  Keeps the fastest plan and
  * restores the state.  scratch: caller-owned device memory of at least
  * offsets[count] doubles (the saved state).  report (optional): a JSON
  * record of every trial and the choice, NUL-terminated, truncated to

@@ -255,28 +255,26 @@ const int kSfast[5] = {0, LineTaps<1>::S, LineTaps<2>::S, LineTaps<3>::S, 0};
 const int kWfast32[5] = {0, LineTaps32<1>::W, LineTaps32<2>::W, LineTaps32<3>::W, 0};
 const int kSfast32[5] = {0, LineTaps32<1>::S, LineTaps32<2>::S, LineTaps32<3>::S, 0};
 
-// float64 line passes on the matrix cores: always (mode 1), never (0), or
-// from 2^20 values per pass (2; smaller meshes keep the one-launch vector
+// line passes on the matrix cores: always (mode 1), never (0), or from
+// 2^20 values per pass (2; smaller meshes keep the one-launch vector
 // gradient passes, whose launch count matters more there)
 inline bool use_mfma(const cem_ctx* c) {
-  return !c->mixed && (c->line_mfma == 1 || (c->line_mfma == 2 && (int64_t)c->m * c->N >= (int64_t(1) << 20)));
+  return c->line_mfma == 1 || (c->line_mfma == 2 && (int64_t)c->m * c->N >= (int64_t(1) << 20));
 }
 
 template <int P, class TI, class TO>
 void launch_line_fast(cem_ctx* c, int id, LineFastArgs la, hipStream_t st) {
   constexpr int W = LineTapsV<P, TO>::W;
-  if constexpr (std::is_same<TI, double>::value && std::is_same<TO, double>::value) {
-    if (use_mfma(c)) {
-      la.ky = line_mfma_chunks(la.ntrans, la.L, 2048);
-      const int seg = kMfmaTY * la.ky;
-      dim3 grid((unsigned)((la.ntrans + kMfmaLines - 1) / kMfmaLines), (unsigned)((la.L + seg - 1) / seg));
-      const size_t lds = line_mfma_lds<P>();
-      if (la.axis == 0)
-        CEM_LAUNCH(c, id, (k_line_mfma<P, true>), grid, 256, lds, st, la);
-      else
-        CEM_LAUNCH(c, id, (k_line_mfma<P, false>), grid, 256, lds, st, la);
-      return;
-    }
+  if (use_mfma(c)) {
+    la.ky = line_mfma_chunks(la.ntrans, la.L, 2048);
+    const int seg = kMfmaTY * la.ky;
+    dim3 grid((unsigned)((la.ntrans + kMfmaLines - 1) / kMfmaLines), (unsigned)((la.L + seg - 1) / seg));
+    const size_t lds = line_mfma_lds<P, TO>();
+    if (la.axis == 0)
+      CEM_LAUNCH(c, id, (k_line_mfma<P, true, TI, TO>), grid, 256, lds, st, la);
+    else
+      CEM_LAUNCH(c, id, (k_line_mfma<P, false, TI, TO>), grid, 256, lds, st, la);
+    return;
   }
   if (la.axis == 0 && la.L <= 4096) {
     // whole lines in LDS; one line per block unless lines are short
@@ -709,7 +707,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
       const LineKernel& K = grad ? c->tabs.kgrad[k] : c->tabs.kmass[k];
       const void* in = src_of(c);
       void* out_p = dst_of(c);
-      if (K.wfast > 0 && !MIX && b->line_mfma) {
+      if (K.wfast > 0 && b->line_mfma) {
         // matrix-core blocks of 16 whole lines (the batch fills the chip)
         LineFastArgs a = line_args<RT>(c, in, out_p, k, grad, false);
         a.ky = line_mfma_chunks(a.ntrans, a.L, 0);
@@ -717,7 +715,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         const int seg = kMfmaTY * a.ky;
         gm.lf.push_back(a);
         gm.first.push_back(gm.first.back() + a.gx * ((a.L + seg - 1) / seg));
-        gm.l.lds = line_mfma_lds<P>();
+        gm.l.lds = line_mfma_lds<P, RT>();
       } else if (K.wfast > 0) {
         LineFastArgs a = line_args<RT>(c, in, out_p, k, grad, false);
         const int re = a.L >= 2 * P + 2 * W ? 2 : 1;
@@ -930,10 +928,12 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
         }
         break;
       case B_LINE_MX:
-        if constexpr (!MIX) CEM_LAUNCH(c0, LID, (kb_line_mfma<P, true>), g, dim3(256), l.lds, stream, lf, mp);
+        if (l.grad) CEM_LAUNCH(c0, LID, (kb_line_mfma<P, true, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        else CEM_LAUNCH(c0, LID, (kb_line_mfma<P, true, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
         break;
       case B_LINE_MY:
-        if constexpr (!MIX) CEM_LAUNCH(c0, LID, (kb_line_mfma<P, false>), g, dim3(256), l.lds, stream, lf, mp);
+        if (l.grad) CEM_LAUNCH(c0, LID, (kb_line_mfma<P, false, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        else CEM_LAUNCH(c0, LID, (kb_line_mfma<P, false, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
         break;
       case B_ELEM1_TILE:
         if constexpr (D == 2) CEM_LAUNCH(c0, 1, (kb_elem1_tile<P, PH, true, RT>), g, dim3(128), l.lds, stream, sa, mp);
@@ -1739,15 +1739,15 @@ cem_status cem_batch_autotune(cem_batch* b, double dt, double cfl, int steps, vo
   // per thread ky = 1, 2, 4 of the vector kernels; row groups of the
   // matrix-core tiles), for 2D Euler the element pass-1 kernel (16 x 8
   // element LDS tile with one thread per element, or blocks of 32/64
-  // elements with one thread per element and component), and in float64
+  // elements with one thread per element and component), and
   // the line kernels (matrix-core tiles or vector runs)
   struct Knobs { int order, xcap, ycap, sys, mfma; };
   struct Trial { Knobs k; float ms; };
   const bool sys_choice = b->d == 2 && b->kind == CEM_EULER;
   const std::vector<int> orders = {0, 1}, xcaps = {512, 1024, 2048, 4096}, ycaps = {20480, 40960, 57344};
   const std::vector<int> syss = sys_choice ? std::vector<int>{0, 1} : std::vector<int>{b->elem1_sys};
-  // float64 line passes: matrix-core tiles or the vector kernels
-  const std::vector<int> mfmas = b->mixed ? std::vector<int>{b->line_mfma} : std::vector<int>{0, 1};
+  // line passes: matrix-core tiles or the vector kernels
+  const std::vector<int> mfmas = {0, 1};
   std::vector<Trial> trials;
   cem_status st = CEM_OK;
   auto run_trial = [&](const Knobs& k, float* ms_out) -> cem_status {

@@ -887,9 +887,10 @@ __device__ __forceinline__ V pick_m(const V* v, int c) {
 // matrix cores have the vector units' FP64 peak, but the vector kernels read
 // S + R staged inputs per R outputs from LDS and were bound by LDS bandwidth
 // on the strided axes; here one 512-byte LDS read feeds 1024 multiply-adds.
-// Lane layout of the instruction (checked with a one-wave probe on gfx950):
+// Lane layout of the instructions (checked with one-wave probes on gfx950):
 // lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
-// D[4 r + l / 16][l % 16] in result r.  The strided axes multiply K (A) by
+// D[4 r + l / 16][l % 16] in result r for float64, D[4 (l / 16) + r][l % 16]
+// for float (the mixed form's line passes, V_MFMA_F32_16X16X4_F32).  The strided axes multiply K (A) by
 // the staged inputs (B), so a result row is one output position across 16
 // consecutive lines (a 128-byte store); axis 0 multiplies the transposed
 // product, inputs as A and K as B, so a result row is 16 consecutive
@@ -904,11 +905,29 @@ __device__ __forceinline__ V pick_m(const V* v, int c) {
 // work.
 // ---------------------------------------------------------------------------
 typedef double cem_v4d __attribute__((ext_vector_type(4)));
+typedef float cem_v4f __attribute__((ext_vector_type(4)));
 constexpr int kMfmaLines = 16;     // lines per block
 constexpr int kMfmaTY = 128;       // outputs per chunk (8 row groups of 16)
 constexpr int kMfmaRing = 256;     // LDS ring rows
-template <int P> struct MfmaLine {
-  static constexpr int W = LineTaps<P>::W, S = LineTaps<P>::S;
+template <class V> struct MfmaV;
+template <> struct MfmaV<double> {
+  typedef cem_v4d acc;
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // result row of register r in lane l (kk = l / 16): 4 r + kk
+  static __device__ __forceinline__ int row(int r, int kk) { return 4 * r + kk; }
+};
+template <> struct MfmaV<float> {
+  typedef cem_v4f acc;
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // the float instruction groups its result rows by lane: 4 kk + r (probed)
+  static __device__ __forceinline__ int row(int r, int kk) { return 4 * kk + r; }
+};
+template <int P, class V = double> struct MfmaLine {
+  static constexpr int W = LineTapsV<P, V>::W, S = LineTapsV<P, V>::S;
   static constexpr int NQ = (16 + 2 * W + 3) / 4;   // band steps of 4 inputs
   static constexpr int HALO = 4 * NQ - 16;          // staged rows beyond the TY outputs
   static_assert(kMfmaTY + HALO <= kMfmaRing, "chunk and halo must fit the ring");
@@ -919,25 +938,28 @@ template <int P> struct MfmaLine {
 };
 
 // LDS bytes of a block
-template <int P>
+template <int P, class V = double>
 __host__ __device__ constexpr size_t line_mfma_lds() {
-  return (size_t)kMfmaRing * kMfmaLines * sizeof(double) +
-         (MfmaLine<P>::KREG ? 0 : (size_t)P * MfmaLine<P>::S * sizeof(double));
+  return (size_t)kMfmaRing * kMfmaLines * sizeof(V) +
+         (MfmaLine<P, V>::KREG ? 0 : (size_t)P * MfmaLine<P, V>::S * sizeof(V));
 }
 
 // block (bx, by): lines bx*16 .. +15, outputs [by a.ky TY, (by + 1) a.ky TY)
-// of them (a.ky chunks per segment)
-template <int P, bool AX0>
+// of them (a.ky chunks per segment).  TI: input values (converted to TO as
+// they are staged); TO: the operator's type (float64 or float, the mixed
+// form), with float accumulation in the float case as in the vector kernels
+template <int P, bool AX0, class TI, class TO>
 __device__ __forceinline__ void k_line_mfma_body(const LineFastArgs& a, int bx, int by) {
-  using ML = MfmaLine<P>;
+  using ML = MfmaLine<P, TO>;
+  using MV = MfmaV<TO>;
   constexpr int W = ML::W, S = ML::S, NQ = ML::NQ, LW = kMfmaLines, TY = kMfmaTY, RB = kMfmaRing;
   constexpr int ROWS = TY + ML::HALO, NV = TY / 16;
   const int L = a.L;
-  double* sm = cem_smem;
-  double* wsm = sm + RB * LW;
-  const double* in = static_cast<const double*>(a.in);
-  double* out = static_cast<double*>(a.out);
-  const double* w = static_cast<const double*>(a.w);
+  TO* sm = reinterpret_cast<TO*>(cem_smem);
+  TO* wsm = sm + RB * LW;
+  const TI* in = static_cast<const TI*>(a.in);
+  TO* out = static_cast<TO*>(a.out);
+  const TO* w = static_cast<const TO*>(a.w);
   const int t0 = bx * LW, seg0 = by * a.ky * TY;
   const int nch = min(a.ky, (L - seg0 + TY - 1) / TY);
   const int ntrans = (int)a.ntrans;
@@ -954,8 +976,8 @@ __device__ __forceinline__ void k_line_mfma_body(const LineFastArgs& a, int bx, 
   };
   const int sl = AX0 ? 1 : (a.axis == 1 ? a.L0 : a.L0 * a.L1);
   // staging: thread (j, r0) = (tid % 16, tid / 16) takes rows r0 + 16 k of
-  // line j.  A row of the strided axes is 128 contiguous bytes; on axis 0
-  // four lanes read 32 contiguous bytes of one line.
+  // line j.  A row of the strided axes is one contiguous segment of 16
+  // values; on axis 0 four lanes read four contiguous values of one line.
   const int j = threadIdx.x & (LW - 1), r0 = threadIdx.x >> 4;
   const bool have = t0 + j < ntrans;
   const int lb = have ? base_of(t0 + j) : 0;
@@ -969,10 +991,10 @@ __device__ __forceinline__ void k_line_mfma_body(const LineFastArgs& a, int bx, 
     int p = wrap(seg0 - W + r0);
     int row = r0;
     for (; row + 112 < ROWS; row += 128) {
-      double v[8];
+      TO v[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        v[k] = have ? in[lb + p * sl] : 0.0;
+        v[k] = have ? (TO)in[lb + p * sl] : (TO)0;
         p += 16;
         if (p >= L) p -= L;
       }
@@ -980,7 +1002,7 @@ __device__ __forceinline__ void k_line_mfma_body(const LineFastArgs& a, int bx, 
       for (int k = 0; k < 8; ++k) sm[(row + 16 * k) * LW + j] = v[k];
     }
     for (; row < ROWS; row += 16) {
-      sm[row * LW + j] = have ? in[lb + p * sl] : 0.0;
+      sm[row * LW + j] = have ? (TO)in[lb + p * sl] : (TO)0;
       p += 16;
       if (p >= L) p -= L;
     }
@@ -990,13 +1012,13 @@ __device__ __forceinline__ void k_line_mfma_body(const LineFastArgs& a, int bx, 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int ii = lane & 15, kk = lane >> 4;
   // K operand of band step q: K[ii][kk] of the step = w[class][4 q + kk - ii]
-  double kreg[ML::KREG ? NQ : 1];
+  TO kreg[ML::KREG ? NQ : 1];
   if constexpr (ML::KREG) {
     const int cls = ii % P;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int t = 4 * q + kk - ii;
-      kreg[q] = (t >= 0 && t < S) ? w[cls * S + t] : 0.0;
+      kreg[q] = (t >= 0 && t < S) ? w[cls * S + t] : (TO)0;
     }
   }
   __syncthreads();
@@ -1006,41 +1028,38 @@ __device__ __forceinline__ void k_line_mfma_body(const LineFastArgs& a, int bx, 
     const int s = seg0 + c * TY, base = (c * TY) & (RB - 1);
     // the next chunk's new rows (positions s + TY - W + HALO + r0 + 16 k)
     const bool more = c + 1 < nch;
-    double v[NV];
+    TO v[NV];
     if (more) {
       int p = wrap(s + TY - W + ML::HALO + r0);
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
-        v[k] = have ? in[lb + p * sl] : 0.0;
+        v[k] = have ? (TO)in[lb + p * sl] : (TO)0;
         p += 16;
         if (p >= L) p -= L;
       }
     }
     // wave wv: row groups wv and wv + 4, two independent chains
-    cem_v4d acc[2];
+    typename MV::acc acc[2];
     int cls[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      acc[h] = cem_v4d{0.0, 0.0, 0.0, 0.0};
+      acc[h] = typename MV::acc{0, 0, 0, 0};
       cls[h] = (s + 16 * (wv + 4 * h) + ii) % P;
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        double kv;
+        TO kv;
         if constexpr (ML::KREG) {
           kv = kreg[q];
         } else {
           const int t = 4 * q + kk - ii;
-          kv = (t >= 0 && t < S) ? wsm[cls[h] * S + t] : 0.0;
+          kv = (t >= 0 && t < S) ? wsm[cls[h] * S + t] : (TO)0;
         }
         const int row = (base + 16 * (wv + 4 * h) + 4 * q + kk) & (RB - 1);
-        const double xv = sm[row * LW + ii];
-        if constexpr (AX0)
-          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, kv, acc[h], 0, 0, 0);
-        else
-          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, xv, acc[h], 0, 0, 0);
+        const TO xv = sm[row * LW + ii];
+        acc[h] = AX0 ? MV::mma(xv, kv, acc[h]) : MV::mma(kv, xv, acc[h]);
       }
     }
 #pragma unroll
@@ -1051,14 +1070,14 @@ __device__ __forceinline__ void k_line_mfma_body(const LineFastArgs& a, int bx, 
         if (pos < L) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int line = t0 + 4 * r + kk;
+            const int line = t0 + MV::row(r, kk);
             if (line < ntrans) out[line * L + pos] = acc[h][r];
           }
         }
       } else if (oline < ntrans) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int pos = s + 16 * g + 4 * r + kk;
+          const int pos = s + 16 * g + MV::row(r, kk);
           if (pos < L) out[ob + pos * sl] = acc[h][r];
         }
       }
@@ -1071,9 +1090,9 @@ __device__ __forceinline__ void k_line_mfma_body(const LineFastArgs& a, int bx, 
   }
 }
 
-template <int P, bool AX0>
+template <int P, bool AX0, class TI, class TO>
 __global__ void __launch_bounds__(256) k_line_mfma(LineFastArgs a) {
-  k_line_mfma_body<P, AX0>(a, blockIdx.x, blockIdx.y);
+  k_line_mfma_body<P, AX0, TI, TO>(a, blockIdx.x, blockIdx.y);
 }
 
 // chunks per segment of an MFMA line block: whole lines unless fewer than

@@ -55,12 +55,12 @@ __global__ void __launch_bounds__(256) kb_line_y(const LineFastArgs* __restrict_
 }
 
 // matrix-core line tiles: local block lb -> (lb % gx, lb / gx) as above
-template <int P, bool AX0>
+template <int P, bool AX0, class TI, class TO>
 __global__ void __launch_bounds__(256) kb_line_mfma(const LineFastArgs* __restrict__ args, BatchMap m) {
   int lb;
   const int pid = batch_find(m, blockIdx.x, &lb);
   const int gx = args[pid].gx;
-  k_line_mfma_body<P, AX0>(args[pid], lb % gx, lb / gx);
+  k_line_mfma_body<P, AX0, TI, TO>(args[pid], lb % gx, lb / gx);
 }
 
 template <int P, int PH, bool WS, class RT>

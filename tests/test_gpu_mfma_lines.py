@@ -66,3 +66,33 @@ def test_matrix_and_vector_lines_agree_on_a_large_mesh():
         err = rel_linf(np.asarray(a).reshape(-1, m, wl.N), np.asarray(b).reshape(-1, m, wl.N))
         announce(f"[mfma] euler3d 64^3 {name}: matrix vs vector rel Linf {err:.1e}")
         assert err <= 1e-11, (name, err)
+
+
+MIXED_CASES = [
+    ("kpp2d_q2_48x47", lambda: random_scalar_workload(2, 2, (48, 47), kind="kpp")),
+    ("euler2d_q3_41x43", lambda: random_euler_workload(2, 3, (41, 43))),
+    ("adv2d_q1_64x65", lambda: random_scalar_workload(2, 1, (64, 65))),
+    ("euler3d_q2_47x3x50", lambda: random_euler_workload(3, 2, (47, 3, 50))),
+]
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("label,make", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_matrix_core_lines_mixed_stage(label, make):
+    # the mixed form's float line passes on the matrix cores (float products,
+    # float accumulation): one stage against the float64 oracle within the
+    # mixed-form stage bounds (rel L1 1e-5, rel Linf 5e-5)
+    from parity_util import lumped_mass, oracle_for, rel_l1
+    wl = make()
+    orc = oracle_for(wl)
+    dt = 0.5 * orc.max_dt(wl.u0)
+    ufe = orc.clamp(orc.fe_stage(wl.u0, dt)[0])[0]
+    s = gpu_for(wl, MAT, precision="mixed")
+    s.stage(0, dt=dt)
+    got = s.download()
+    chk = s.check()
+    s.close()
+    e1, einf = rel_l1(got, ufe, lumped_mass(orc)), rel_linf(got, ufe)
+    announce(f"[mfma] {label} mixed: rel L1 {e1:.2e}, rel Linf {einf:.2e}")
+    assert e1 <= 1e-5 and einf <= 5e-5, (e1, einf)
+    assert chk["violations"] == 0
