@@ -231,6 +231,16 @@ cem_status cem_set_graphs(cem_ctx* ctx, int enable);
  * values.  The assembly-fused first mass pass and lines too short for the
  * truncated operators keep their kernels.  Drops the captured step. */
 cem_status cem_set_line_kernels(cem_ctx* ctx, int mode);
+/* 2D Euler: with enable != 0 element pass 2 also performs the update (eq.
+ * 49, SSP-RK3 combination, invariant counts) of the nodes whose elements
+ * all lie in one of its blocks of consecutive elements, whose update
+ * vectors then meet in LDS instead of being stored and re-read; the update
+ * kernel handles the other nodes.  Node sums keep the same element order
+ * and rounding, so both settings give bitwise the same states.  Off by
+ * default: with blocks of 64 consecutive elements about half of the nodes
+ * qualify, and the extra barriers of pass 2 cost what the update saves.
+ * No effect on other problems.  Drops the captured step. */
+cem_status cem_set_fused_update(cem_ctx* ctx, int enable);
 
 /* Call after writing the bound state u by other means than
  * cem_upload_state or the stage calls (e.g. a device copy): derived per-node
@@ -351,6 +361,8 @@ cem_status cem_batch_set_plan(cem_batch* b, int order, int xlines_cap, int ytile
  * float products with float accumulation in the mixed form), 0 as the
  * vector kernels.  The next step rebuilds the plan. */
 cem_status cem_batch_set_line_kernels(cem_batch* b, int matrix);
+/* as cem_set_fused_update, for the batched 2D Euler problems. */
+cem_status cem_batch_set_fused_update(cem_batch* b, int enable);
 /* Per-kernel timing of the batched launches, as cem_set_timing /
  * cem_kernel_times (the same kernel ids; each batched launch is one record,
  * covering every problem it serves).  While a mask is set, cem_batch_step

@@ -86,6 +86,7 @@ _SIGS = [
     ("cem_tap_size", ctypes.c_size_t, [_P, ctypes.c_int]),
     ("cem_set_graphs", ctypes.c_int, [_P, ctypes.c_int]),
     ("cem_set_line_kernels", ctypes.c_int, [_P, ctypes.c_int]),
+    ("cem_set_fused_update", ctypes.c_int, [_P, ctypes.c_int]),
     ("cem_state_modified", ctypes.c_int, [_P]),
     ("cem_set_timing", ctypes.c_int, [_P, ctypes.c_uint]),
     ("cem_kernel_times", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
@@ -107,6 +108,7 @@ _SIGS = [
     ("cem_batch_check_invariants", ctypes.c_int, [_P, ctypes.POINTER(Invariants), ctypes.c_int]),
     ("cem_batch_set_plan", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("cem_batch_set_line_kernels", ctypes.c_int, [_P, ctypes.c_int]),
+    ("cem_batch_set_fused_update", ctypes.c_int, [_P, ctypes.c_int]),
     ("cem_batch_set_timing", ctypes.c_int, [_P, ctypes.c_uint]),
     ("cem_batch_kernel_times", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
@@ -242,6 +244,10 @@ def cem_set_line_kernels(ctx, mode):
     _check(lib().cem_set_line_kernels(ctx, int(mode)))
 
 
+def cem_set_fused_update(ctx, enable):
+    _check(lib().cem_set_fused_update(ctx, int(bool(enable))))
+
+
 def cem_state_modified(ctx):
     _check(lib().cem_state_modified(ctx))
 
@@ -327,6 +333,9 @@ class Solver:
     def set_line_kernels(self, mode):
         """0 vector, 1 matrix cores, 2 by size (see cem_set_line_kernels)."""
         cem_set_line_kernels(self.ctx, mode)
+
+    def set_fused_update(self, enable):
+        cem_set_fused_update(self.ctx, enable)
 
     def set_graphs(self, enable):
         cem_set_graphs(self.ctx, enable)
@@ -427,6 +436,10 @@ def cem_batch_set_plan(b, order=0, xlines_cap=2048, ytile_lds_bytes=40960, elem1
 
 def cem_batch_set_line_kernels(b, matrix):
     _check(lib().cem_batch_set_line_kernels(b, int(matrix)))
+
+
+def cem_batch_set_fused_update(b, enable):
+    _check(lib().cem_batch_set_fused_update(b, int(bool(enable))))
 
 
 def cem_batch_set_timing(b, mask):

@@ -61,6 +61,8 @@ cem_status fail(cem_status s, const std::string& msg) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+// log2 of a power of two
+constexpr int ilog2_exact(int v) { return v <= 1 ? 0 : 1 + ilog2_exact(v / 2); }
 }  // namespace
 
 struct cem_ctx {
@@ -94,6 +96,8 @@ struct cem_ctx {
   size_t ndtp = 0;                 // capacity of the per-block dt_e minima
   int elem1_sys = kSys2D ? 1 : 0;  // 2D Euler: element pass 1 on the system kernels
   int line_mfma = 2;               // float64 line passes: 0 vector, 1 matrix cores, 2 by size
+  bool fuse_update = false;        // 2D Euler: pass 2 updates the nodes inside its blocks
+  int cnt_slots = 0;               // per-block counter pairs: update blocks, then pass-2 blocks
   bool bound = false, bounds_set = false;
   // whole-step HIP graph (captured on a private stream, launched on stream)
   bool use_graphs = true;
@@ -112,7 +116,7 @@ struct cem_ctx {
 };
 
 // batched form: launches of one stage over all problems (see kernels_batch.hpp)
-enum BKind { B_LINE, B_LINE_X, B_LINE_Y, B_LINE_MX, B_LINE_MY, B_ELEM1_TILE, B_ELEM1_TILE2, B_ELEM1_SYS, B_RESID_SYS, B_GATHER_LX,
+enum BKind { B_LINE, B_LINE_X, B_LINE_Y, B_LINE_MX, B_LINE_MY, B_STAGE_DT, B_ELEM1_TILE, B_ELEM1_TILE2, B_ELEM1_SYS, B_RESID_SYS, B_GATHER_LX,
              B_GATHER_R, B_ELEM2, B_ELEM2_SYS, B_UPDATE };
 
 struct BLaunch {
@@ -147,6 +151,7 @@ struct cem_batch {
   int ytile_cap = 40960;           // strided line kernels: LDS bytes of a tile (sets the runs per thread)
   int elem1_sys = kSys2D ? 1 : 0;  // 2D Euler: element pass 1 on the system kernels (else the LDS tile)
   int line_mfma = 1;               // float64 line passes on the matrix cores (else the vector kernels)
+  int fuse_update = 0;             // 2D Euler: pass 2 updates the nodes inside its blocks
 };
 
 namespace {
@@ -605,6 +610,16 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
       HIPCHK(hipGetLastError());
     }
   }
+  bool fused = false;
+  if constexpr (PH == EUL && D == 2) fused = c->fuse_update;
+  if (fused) {
+    // pass 2 updates the nodes inside its blocks: the stage dt first
+    a.fuse_upd = ilog2_exact(SysTile<D, P, PH>::EB);
+    a.cnt_off = c->upd_blocks;
+    a.dt_ready = 1;
+    CEM_LAUNCH(c, 2, k_stage_dt, 1, 1024, 0, c->stream, a);
+    HIPCHK(hipGetLastError());
+  }
   if constexpr (PH == EUL && D >= 2) {
     cem_status st = launch_sys<D, P, PH, RT>(c, a, false);
     if (st != CEM_OK) return st;
@@ -612,7 +627,7 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     CEM_LAUNCH(c, 5, (k_elem2<D, P, PH, RT>), nblocks(c->E, 128), 128, 0, c->stream, a);
   }
   HIPCHK(hipGetLastError());
-  if (a.ndtpart > kDtFusedMax) {
+  if (!fused && a.ndtpart > kDtFusedMax) {
     // many per-block minima: one block reduces them once for the update
     a.dt_ready = 1;
     CEM_LAUNCH(c, 2, k_stage_dt, 1, 1024, 0, c->stream, a);
@@ -649,6 +664,15 @@ StageArgs batch_stage_args(cem_ctx* c, int stage, double dt, double cfl) {
   } else {
     a.ndtpart = (int)nblocks(c->E, 128);
   }
+  if constexpr (PH == EUL && D == 2) {
+    if (c->fuse_update) {
+      // pass 2 updates the nodes inside its blocks (the stage dt reduced
+      // ahead of it by kb_stage_dt)
+      a.fuse_upd = ilog2_exact(SysTile<D, P, PH>::EB);
+      a.cnt_off = c->upd_blocks;
+      a.dt_ready = 1;
+    }
+  }
   return a;
 }
 
@@ -658,7 +682,10 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
   // problems in launch order (largest first puts the long-running blocks at
   // the front of every grid)
   std::vector<cem_ctx*> all = b->pr;
-  for (cem_ctx* c : all) c->elem1_sys = b->elem1_sys;
+  for (cem_ctx* c : all) {
+    c->elem1_sys = b->elem1_sys;
+    c->fuse_update = b->fuse_update != 0;
+  }
   if (b->order == 1)
     std::stable_sort(all.begin(), all.end(), [](const cem_ctx* x, const cem_ctx* y) { return x->N > y->N; });
   constexpr bool MIX = sizeof(RT) == 4;
@@ -857,7 +884,19 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
                            [&](cem_ctx* c) -> void* { return mass_dst(c, k); });
       if (s != CEM_OK) return s;
     }
-    // element pass 2 and the update
+    // element pass 2 and the update; with the fused update, the stage dt
+    // of every problem first (one block each)
+    if constexpr (PH == EUL && D == 2) {
+      if (b->fuse_update) {
+        Group gd;
+        gd.l.kind = B_STAGE_DT;
+        for (int q = 0; q < b->count; ++q) {
+          gd.sa.push_back(sa[q]);
+          gd.first.push_back(gd.first.back() + 1);
+        }
+        close(gd, L);
+      }
+    }
     {
       Group g2, gu;
       if constexpr (PH == EUL && D >= 2) {
@@ -934,6 +973,9 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
       case B_LINE_MY:
         if (l.grad) CEM_LAUNCH(c0, LID, (kb_line_mfma<P, false, double, RT>), g, dim3(256), l.lds, stream, lf, mp);
         else CEM_LAUNCH(c0, LID, (kb_line_mfma<P, false, RT, RT>), g, dim3(256), l.lds, stream, lf, mp);
+        break;
+      case B_STAGE_DT:
+        CEM_LAUNCH(c0, 2, kb_stage_dt, g, dim3(1024), 0, stream, sa, mp);
         break;
       case B_ELEM1_TILE:
         if constexpr (D == 2) CEM_LAUNCH(c0, 1, (kb_elem1_tile<P, PH, true, RT>), g, dim3(128), l.lds, stream, sa, mp);
@@ -1153,7 +1195,10 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->ndtp = ndtp;
   c->o_dtpart = take(ndtp * 8);
   c->upd_blocks = (int)nblocks(c->N, 256);
-  c->o_counts = take((size_t)c->upd_blocks * 2 * sizeof(int));
+  // counter pairs: one per update block, then one per pass-2 block of the
+  // fused update (at most ndtp of them)
+  c->cnt_slots = c->upd_blocks + (int)ndtp;
+  c->o_counts = take((size_t)c->cnt_slots * 2 * sizeof(int));
   c->inv_blocks = 256;
   c->o_inv = take((size_t)c->inv_blocks * inv_nvals(c->m) * 8);
   if (c->mixed) {
@@ -1186,7 +1231,7 @@ cem_status cem_workspace_bytes(const cem_ctx* c, size_t* bytes) {
 
 cem_status cem_reset_counters(cem_ctx* c) {
   if (!c || !c->bound) return fail(CEM_EINVAL, "context not bound");
-  HIPCHK(hipMemsetAsync(c->ws + c->o_counts, 0, (size_t)c->upd_blocks * 2 * sizeof(int), c->stream));
+  HIPCHK(hipMemsetAsync(c->ws + c->o_counts, 0, (size_t)c->cnt_slots * 2 * sizeof(int), c->stream));
   HIPCHK(hipMemsetAsync(c->ws + c->o_dtbuf, 0, 8 * 8, c->stream));
   return CEM_OK;
 }
@@ -1322,6 +1367,13 @@ cem_status cem_set_line_kernels(cem_ctx* c, int mode) {
   return CEM_OK;
 }
 
+cem_status cem_set_fused_update(cem_ctx* c, int enable) {
+  if (!c) return fail(CEM_EINVAL, "null context");
+  c->fuse_update = enable != 0;
+  drop_graph(c);
+  return CEM_OK;
+}
+
 cem_status cem_set_graphs(cem_ctx* c, int enable) {
   if (!c) return fail(CEM_EINVAL, "null context");
   c->use_graphs = enable != 0;
@@ -1353,7 +1405,7 @@ cem_status cem_check_invariants(cem_ctx* c, cem_invariants* out) {
   HIPCHK(hipGetLastError());
   const int nv = inv_nvals(c->m);
   std::vector<double> part((size_t)c->inv_blocks * nv);
-  std::vector<int> cnt((size_t)c->upd_blocks * 2);
+  std::vector<int> cnt((size_t)c->cnt_slots * 2);
   double dtb[8];
   HIPCHK(hipMemcpyAsync(part.data(), ia.part, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipMemcpyAsync(cnt.data(), c->ws + c->o_counts, cnt.size() * sizeof(int), hipMemcpyDeviceToHost,
@@ -1390,7 +1442,7 @@ cem_status cem_check_invariants(cem_ctx* c, cem_invariants* out) {
         out->mass[v / 3] += x;
       }
     }
-  for (int b = 0; b < c->upd_blocks; ++b) {
+  for (int b = 0; b < c->cnt_slots; ++b) {
     out->clamped += cnt[2 * (size_t)b];
     out->violations += cnt[2 * (size_t)b + 1];
   }
@@ -1531,12 +1583,13 @@ cem_status cem_batch_create(int count, const cem_mesh_desc* meshes, const cem_ph
     ws += align256(c->ws_need);
   }
   // plan region, per stage: StageArgs entries, one per problem in element
-  // pass 1 (two with the system kernels' residual half), the assembly, pass
-  // 2 and the update; one line-argument entry per problem and line pass (d
-  // gradient, d mass); at most 10 d + 7 launch groups, each with a block
-  // prefix of at most count + 1 ints and up to three arrays padded to 256
-  const size_t ngroups = 10 * (size_t)d + 7;
-  const size_t per_stage = 5 * (size_t)count * sizeof(StageArgs) +
+  // pass 1 (two with the system kernels' residual half), the assembly, the
+  // stage dt of the fused update, pass 2 and the update; one line-argument
+  // entry per problem and line pass (d gradient, d mass); at most 10 d + 8
+  // launch groups, each with a block prefix of at most count + 1 ints and
+  // up to three arrays padded to 256
+  const size_t ngroups = 10 * (size_t)d + 8;
+  const size_t per_stage = 6 * (size_t)count * sizeof(StageArgs) +
                            2 * (size_t)d * count * std::max(sizeof(LineFastArgs), sizeof(LineArgs)) +
                            ngroups * (size_t)(count + 1) * sizeof(int) + 3 * ngroups * 256;
   b->o_plan = ws;
@@ -1692,6 +1745,14 @@ cem_status cem_batch_set_line_kernels(cem_batch* b, int matrix) {
   if (!b) return fail(CEM_EINVAL, "null batch");
   if (matrix < 0 || matrix > 1) return fail(CEM_EINVAL, "line kernels must be 0 (vector) or 1 (matrix)");
   b->line_mfma = matrix;
+  batch_drop_graph(b);
+  b->plan_dt = b->plan_cfl = -1.0;
+  return CEM_OK;
+}
+
+cem_status cem_batch_set_fused_update(cem_batch* b, int enable) {
+  if (!b) return fail(CEM_EINVAL, "null batch");
+  b->fuse_update = enable != 0;
   batch_drop_graph(b);
   b->plan_dt = b->plan_cfl = -1.0;
   return CEM_OK;
@@ -1924,7 +1985,7 @@ cem_status cem_step_static(cem_ctx* c, double* u, double* u_base, double dt, dou
   // (fill kernels, not memset nodes, so that a caller may capture the call)
   hipError_t e = hipMemcpyAsync(c->ws + c->o_tab, c->tabblob.data(), c->tabblob.size() * 8,
                                 hipMemcpyHostToDevice, c->stream);
-  const int64_t ncnt = (int64_t)c->upd_blocks * 2;
+  const int64_t ncnt = (int64_t)c->cnt_slots * 2;
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_zero_words, dim3(nblocks(ncnt, 256)), dim3(256), 0, c->stream,
                        reinterpret_cast<unsigned*>(c->ws + c->o_counts), ncnt);

@@ -85,6 +85,9 @@ struct StageArgs {
   double* bnd;          // [2][E] per-element lower, upper bounds (bounds_local)
   int contrib_q1;       // scalar Q1: element contributions of Sec. 5.3 (low-order derivative in udot)
   int store_r;          // the assembly fused with the first mass pass also stores r (a debug tap only)
+  int fuse_upd;         // 2D systems: 0, or log2 of pass 2's elements per block when pass 2 updates
+                        // the nodes whose elements all lie in its block
+  int cnt_off;          // first counter slot of the pass-2 blocks (fuse_upd)
   double* fdiv;         // [E] int_dK f_h . n of each element (contrib_q1)
   const double* u;      // stage input u^(s)   [M][N]
   double* u0;           // step base u^n       [M][N]
@@ -2600,6 +2603,15 @@ __device__ inline double stage_dt(const StageArgs& a, int bx) {
   return a.stage == 0 ? (a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl * mn) : a.dtbuf[0];
 }
 
+// the stage update of one nodal value: u^FE = u_i + dt / m_i sum (eq. 49),
+// then the SSP-RK combination a u^n + b u^FE.  Explicit fused multiply-adds,
+// so that every kernel that updates nodes rounds alike (contraction left to
+// the compiler may pick different products in different callers).
+__device__ __forceinline__ double stage_value(double ui, double ub, double sum, double dt_over_m, const StageArgs& a) {
+  const double ufe = fma(dt_over_m, sum, ui);
+  return (a.rk_a == 0.0) ? ufe : fma(a.rk_a, ub, a.rk_b * ufe);
+}
+
 template <int D, int P, int PH>
 __device__ __forceinline__ void k_update_body(const StageArgs& a, int bx) {
   constexpr int M = Phys<D, PH>::M;
@@ -2607,16 +2619,28 @@ __device__ __forceinline__ void k_update_body(const StageArgs& a, int bx) {
   constexpr int NL = ipow(P + 1, D);
   __shared__ int red[2][4];
   const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
-  const bool live = i < a.mesh.N;
+  bool live = i < a.mesh.N;
   const int64_t E = a.mesh.E, N = a.mesh.N;
   // the node's data is read first, so that its loads overlap the reduction
   // of the time step
   double ssum[M], uin[M], ubase[M];
   int nrec = 0;
+  int64_t eids[8];
+  int locs[8];
   if (live) {
-    int64_t eids[8];
-    int locs[8];
     nrec = node_elements<D, P>(i, a.mesh, eids, locs);
+    if constexpr (D == 2 && PH == EUL) {
+      // nodes whose elements all lie in one block of the system pass 2 were
+      // updated there (fuse_upd: the blocks hold 2^fuse_upd consecutive
+      // elements)
+      if (a.fuse_upd) {
+        bool same = true;
+        for (int t = 1; t < nrec; ++t) same = same && ((eids[t] >> a.fuse_upd) == (eids[0] >> a.fuse_upd));
+        live = !same;
+      }
+    }
+  }
+  if (live) {
 #pragma unroll
     for (int c = 0; c < M; ++c) {
       double s = 0.0;
@@ -2641,8 +2665,7 @@ __device__ __forceinline__ void k_update_body(const StageArgs& a, int bx) {
       const double s = ssum[c];
       const double ui = uin[c];
       if (a.copy_base) a.u0[c * N + i] = ui;
-      const double ufe = ui + dt / mi * s;
-      double v = (a.rk_a == 0.0) ? ufe : a.rk_a * ubase[c] + a.rk_b * ufe;
+      double v = stage_value(ui, ubase[c], s, dt / mi, a);
       if (SCALAR) {
         // round-off excess is clamped and counted; larger excursions (only
         // possible with a limiter switched off) and non-finite values are
@@ -2710,12 +2733,14 @@ __global__ void __launch_bounds__(256) k_nodal_flux(StageArgs a) {
 // The same reduction in one block of 1024 threads, ahead of the node update,
 // when there are many per-block minima (k_update then reads dtbuf[0] instead
 // of every block reducing all of them itself)
-__global__ void __launch_bounds__(1024) k_stage_dt(StageArgs a) {
+__device__ __forceinline__ void k_stage_dt_body(const StageArgs& a) {
   double m = 1.0e300;
   for (int j = threadIdx.x; j < a.ndtpart; j += 1024) m = fmin(m, a.dtpart[j]);
   const double mn = block_min<1024>(m);
   if (threadIdx.x == 0) stage_dt_record(a, mn);
 }
+
+__global__ void __launch_bounds__(1024) k_stage_dt(StageArgs a) { k_stage_dt_body(a); }
 
 // LDS words of the fused gather's per-line slot table (ints per line)
 constexpr int kGatherLineInts = 10;

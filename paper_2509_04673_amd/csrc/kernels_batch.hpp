@@ -63,6 +63,13 @@ __global__ void __launch_bounds__(256) kb_line_mfma(const LineFastArgs* __restri
   k_line_mfma_body<P, AX0, TI, TO>(args[pid], lb % gx, lb / gx);
 }
 
+// the stage dt of every problem: one block per problem
+__global__ void __launch_bounds__(1024) kb_stage_dt(const StageArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_stage_dt_body(args[pid]);
+}
+
 template <int P, int PH, bool WS, class RT>
 __global__ void CEM_TILE_BOUNDS kb_elem1_tile(const StageArgs* __restrict__ args, BatchMap m) {
   int lb;

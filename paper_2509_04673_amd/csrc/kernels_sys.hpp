@@ -731,9 +731,116 @@ __device__ __forceinline__ void k_elem2_sys_body(const StageArgs& a, int bx) {
   for (int k = 0; k < M; ++k) beta = fmin(beta, S[LY::oPart + k * EB + le]);
   if (a.beta_mode == 1) beta = 0.0;
   else if (a.beta_mode == 2) beta = 1.0;
+  const double idt = 1.0 / dt_e;
+  if constexpr (D == 2) {
+    if (a.fuse_upd) {
+      // ---- fused update (eq. 49 and the SSP-RK combination) of the nodes
+      // whose elements all lie in this block (its EB consecutive elements):
+      // their update vectors meet in LDS instead of HBM.  The other nodes'
+      // vectors are stored for k_update as before.  Each node is updated by
+      // the component threads of its first element in node_elements' order
+      // (the lower one along each axis: the element holding it at local
+      // indices >= 1), summing in that order, as k_update does; the stage
+      // dt was reduced by k_stage_dt ahead of this launch.
+      const int64_t e0 = (int64_t)bx * EB;
+      const int n0 = ms.n[0], n1 = ms.n[1], ex = ns.ei[0], ey = ns.ei[1];
+      const int exm = ex == 0 ? n0 - 1 : ex - 1, exq = ex + 1 == n0 ? 0 : ex + 1;
+      const int eym = ey == 0 ? n1 - 1 : ey - 1, eyq = ey + 1 == n1 ? 0 : ey + 1;
+      auto id_of = [&](int x, int y) { return (int64_t)x + (int64_t)y * n0; };
+      auto inb = [&](int x, int y) {
+        const int64_t q = id_of(x, y);
+        return q >= e0 && q < e0 + EB;
+      };
+      const bool bl = inb(exm, ey), br = inb(exq, ey), bd = inb(ex, eym), bu = inb(ex, eyq);
+      const bool bdl = inb(exm, eym), bdr = inb(exq, eym), bul = inb(exm, eyq), bur = inb(exq, eyq);
+      auto interior = [&](int ax, int ay) {
+        bool in = true;
+        if (ax == 0) in = in && bl;
+        if (ax == P) in = in && br;
+        if (ay == 0) in = in && bd;
+        if (ay == P) in = in && bu;
+        if (ax == 0 && ay == 0) in = in && bdl;
+        if (ax == P && ay == 0) in = in && bdr;
+        if (ax == 0 && ay == P) in = in && bul;
+        if (ax == P && ay == P) in = in && bur;
+        return in;
+      };
+      double vv[NL];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) vv[i] = (dU[i] + beta * f[i]) * idt;
+      if (live) {
+        if (c == 0) a.beta[e] = beta;
+#pragma unroll
+        for (int i = 0; i < NL; ++i)
+          if (!interior(i % P1, i / P1)) a.relem[((int64_t)c * NL + i) * E + e] = vv[i];
+      }
+      // every read of the nodal states and of f from S is behind the
+      // barrier of the slope limiter: S now takes the update vectors
+#pragma unroll
+      for (int i = 0; i < NL; ++i) Us[i * CS] = vv[i];
+      __syncthreads();
+      const double dt = a.dtbuf[0];
+      const double hd = h * h;
+      constexpr int NO = P * P;              // owned local nodes (indices >= 1)
+      double nv[NO];
+      bool own[NO];
+#pragma unroll
+      for (int ay = 1; ay <= P; ++ay)
+#pragma unroll
+        for (int ax = 1; ax <= P; ++ax) {
+          const int o = (ax - 1) + P * (ay - 1), j = ax + P1 * ay;
+          own[o] = live && interior(ax, ay);
+          nv[o] = 0.0;
+          if (own[o]) {
+            const int nx = ax == P ? 2 : 1, ny = ay == P ? 2 : 1;
+            double sum = 0.0;
+            for (int yy = 0; yy < ny; ++yy)
+              for (int xx = 0; xx < nx; ++xx) {
+                const int lane = (int)(id_of(xx ? exq : ex, yy ? eyq : ey) - e0);
+                const int jj = (xx ? 0 : ax) + P1 * (yy ? 0 : ay);
+                sum += S[(jj * M + c) * EB + lane];
+              }
+            const double mi = (nx * ny) * (hd * (1.0 / NL));
+            const int64_t nd = ns.own_node(j);
+            const double ui = a.u[c * N + nd];
+            const double ub = (a.rk_a == 0.0) ? 0.0 : a.u0[c * N + nd];
+            if (a.copy_base) a.u0[c * N + nd] = ui;
+            const double v = stage_value(ui, ub, sum, dt / mi, a);
+            a.uout[c * N + nd] = v;
+            nv[o] = v;
+          }
+        }
+      // invariant domain at the updated nodes (rho > 0, p > 0; each failed
+      // condition counts once, NaN included), counted by component 0
+      __syncthreads();                       // every read of the update vectors is done
+#pragma unroll
+      for (int o = 0; o < NO; ++o) S[(o * M + c) * EB + le] = nv[o];
+      __syncthreads();
+      int nbad = 0;
+      if (c == 0) {
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+          if (!own[o]) continue;
+          double st[M];
+          state_at<M, EB>(S, o, le, st);
+          nbad += !(st[0] > 0.0);
+          nbad += !(PHY::pressure(st, a.ph) > 0.0);
+        }
+      }
+      nbad = wave_sum(nbad);
+      __syncthreads();                       // S is rewritten below
+      if ((threadIdx.x & 63) == 0) S[threadIdx.x >> 6] = (double)nbad;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < (M * EB) / 64; ++w) tot += (int)S[w];
+        if (tot != 0) a.counts[2 * (a.cnt_off + bx) + 1] += tot;
+      }
+      return;
+    }
+  }
   if (live) {
     if (c == 0) a.beta[e] = beta;
-    const double idt = 1.0 / dt_e;
 #pragma unroll
     for (int i = 0; i < NL; ++i) a.relem[((int64_t)c * NL + i) * E + e] = (dU[i] + beta * f[i]) * idt;
   }
