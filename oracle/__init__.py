@@ -25,6 +25,11 @@ Parity status per function (pins live in tests/test_oracle_*.py):
   Appendix A limiter      pinned (admissibility on an alpha grid)
   stage / SSP-RK3         pinned (equivalence theorem, conservation,
                           constant states, IDP, design order)
+  non-periodic 1D line    pinned (Galerkin exactness on polynomials with
+  (b_i, f^partial, g_i^e) consistent inflow data, the weak form with test
+                          function 1, upwind P1 low-order step with an
+                          inflow state, equivalence theorem, walls carry
+                          no mass or energy, interior = periodic scheme)
 """
 from .mesh import Mesh, multi_indices            # noqa: F401
 from .scheme import Oracle, Params, Problem, CFLViolation   # noqa: F401

@@ -1,4 +1,4 @@
-"""Uniform periodic box meshes of Bernstein Q_p elements for the oracle.
+"""Uniform box meshes of Bernstein Q_p elements for the oracle.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
@@ -9,6 +9,11 @@ nodes per axis; node (i_1..i_d) has global index sum_k i_k S_k with x
 fastest, element (e_1..e_d) owns local nodes a in [0, p]^d at global
 positions (p e_k + a_k) mod L_k.  Local node numbering is lexicographic with
 the first axis fastest.
+
+A non-periodic mesh (``periodic=False``) is a 1D line [lo, hi] of n cells:
+L = p n + 1 nodes, element e owns nodes p e .. p e + p, and the two end
+facets are boundary facets (index e' > E_h of [KHV Table 1]): element 0 has
+no low neighbour and element n - 1 no high one (``neighbour`` returns -1).
 """
 from dataclasses import dataclass
 from itertools import product
@@ -23,14 +28,17 @@ class Mesh:
     n: tuple          # elements per axis
     lo: tuple
     hi: tuple
+    periodic: bool = True
 
     def __post_init__(self):
         self.n = tuple(int(x) for x in self.n)
         assert len(self.n) == self.d and 1 <= self.d <= 3
+        assert self.periodic or self.d == 1, "non-periodic meshes are 1D lines"
         hs = [(self.hi[k] - self.lo[k]) / self.n[k] for k in range(self.d)]
         assert max(hs) - min(hs) <= 1e-12 * max(hs), "cube cells required"
         self.h = hs[0]
-        self.L = tuple(self.p * nk for nk in self.n)
+        extra = 0 if self.periodic else 1
+        self.L = tuple(self.p * nk + extra for nk in self.n)
         self.N = int(np.prod(self.L))
         self.E = int(np.prod(self.n))
         self.nloc = (self.p + 1) ** self.d
@@ -70,8 +78,12 @@ class Mesh:
 
     def neighbour(self, axis, side):
         """Element id of the facet neighbour of every element along `axis`
-        on the low (side = -1) or high (side = +1) side, periodic."""
+        on the low (side = -1) or high (side = +1) side: periodic, or -1
+        across a boundary facet of a non-periodic line."""
         eidx = self.element_index().copy()
+        if not self.periodic:
+            nb = eidx[:, axis] + side
+            return np.where((nb >= 0) & (nb < self.n[axis]), nb, -1)
         eidx[:, axis] = (eidx[:, axis] + side) % self.n[axis]
         return eidx @ np.array(self.elem_stride)
 

@@ -7,7 +7,9 @@ built from the exact tables of ``oracle.bernstein``; global sums use
 ``np.add.at`` in element order; the consistent mass matrix is inverted with a
 dense LU factorisation per axis.  The stage follows the five-step algorithm
 of [KHV §4.3] in the paper's order and notation on a uniform periodic box
-(so the boundary terms b_i and g_i^e vanish, [KHV §3.1, §4]).
+(so the boundary terms b_i and g_i^e vanish, [KHV §3.1, §4]) or on a
+non-periodic 1D line with weakly imposed boundary data (b_i of eq. bidef,
+f^partial of Sec. 4, g_i^e of eq. aecb).
 
 Readings of points the paper leaves open:
   * g_h is the consistent L2 projection of grad u_h, solved exactly.
@@ -21,6 +23,12 @@ Readings of points the paper leaves open:
   * The element integral of grad(phi_i) . f(u_h) uses (p+1)^d Gauss points.
   * The flux limiter is on with pseudo time steps (40); Euler facet pairs use
     Appendix A with the increments the states u_ee', u_e'e actually receive.
+  * Non-periodic lines (1D): the boundary data u_hat is a prescribed state,
+    the interior state itself (outflow) or, for Euler, the mirror state with
+    reversed momentum (wall); u_hat^{e'} of the low-order boundary flux is
+    that data for the state u^e; a WENO candidate across a boundary facet is
+    absent (weight 0); the flux limiter of a boundary facet keeps only its
+    element's bounds (eq. 53, e' > E_h); local bounds include u_hat^{e'}.
   * Strict positivity margin eps_pos in the Appendix A limiters; slope
     limiter ratios of (55) are clipped to [0, 1]; a scalar stage result that
     leaves [u_min, u_max] by no more than a few ulps of rounding is clamped
@@ -76,10 +84,23 @@ class Problem:
     params: Params = field(default_factory=Params)
     u_min: float = -np.inf      # global bounds (scalar problems)
     u_max: float = np.inf
+    # boundary conditions of a non-periodic line [KHV eq. (ibvp)]: one
+    # (kind, state) pair per end (lo, hi); kind "state" (u_hat = the given
+    # conserved state), "outflow" (u_hat = u) or "wall" (Euler: u_hat = the
+    # state with reversed momentum)
+    bc: tuple = None
 
     def __post_init__(self):
         self.phys = phys.make(self.kind, self.mesh.d, self.velocity, self.gamma_gas)
         self.m = self.phys.m
+        if self.mesh.periodic:
+            assert self.bc is None, "boundary conditions need a non-periodic mesh"
+        else:
+            assert self.bc is not None and len(self.bc) == 2
+            for kind, state in self.bc:
+                assert kind in ("state", "outflow", "wall"), kind
+                assert kind != "wall" or self.kind == "euler", "walls are an Euler condition"
+                assert kind != "state" or len(state) == self.m
 
 
 # ---------------------------------------------------------------------------
@@ -136,6 +157,12 @@ class Oracle:
         self.mult = self.mesh.multiplicity()
         if prob.params.contrib == "q1" and self.mesh.p != 1:
             raise ValueError("the Q1 element contributions are defined for p = 1")
+        if not self.mesh.periodic:
+            # the subcell bound of Lemma 1 with boundary facets is left open
+            # by the paper (Sec. 3.3), and the Q1 form of Sec. 5.3 is stated
+            # for the periodic low-order scheme
+            if prob.params.flux_mode == "subcell" or prob.params.contrib == "q1":
+                raise ValueError("not defined on a non-periodic line")
 
     # -- global consistent mass matrix, exact solve -------------------------
     @cached_property
@@ -173,6 +200,49 @@ class Oracle:
         out = np.zeros((m, self.mesh.N))
         for c in range(m):
             np.add.at(out[c], self.conn, elem_vec[c])
+        return out
+
+    # -- boundary data of a non-periodic line [KHV §2.1, §3, §4] -----------
+    def ghost(self, u, side):
+        """Boundary data u_hat at the end side = -1 (lo) or +1 (hi) for the
+        interior states u (m, ...): the prescribed state, u itself
+        (outflow) or u with reversed momentum (Euler wall)."""
+        kind, state = self.prob.bc[0 if side < 0 else 1]
+        if kind == "state":
+            st = np.asarray(state, dtype=np.float64).reshape((-1,) + (1,) * (u.ndim - 1))
+            return np.broadcast_to(st, u.shape).copy()
+        out = np.array(u, dtype=np.float64, copy=True)
+        if kind == "wall":
+            out[1] = -out[1]
+        return out
+
+    def llf(self, u_in, u_out, n):
+        """Local Lax-Friedrichs flux F(u_L, u_R; n) of [KHV eq. (fluxLLF)]
+        on a 1D line: u_L = u_in the interior state, u_R = u_out the
+        exterior one, n = +-1 the outward normal, lambda_LR the guaranteed
+        speed bound of the Riemann problem along n.  Returns (F, lambda)."""
+        F = self.prob.phys
+        lam = F.riemann_speed_n(u_in, u_out, np.array([float(n)]))
+        return 0.5 * n * (F.flux(u_in)[0] + F.flux(u_out)[0]) - 0.5 * lam * (u_out - u_in), lam
+
+    def boundary_facets(self, U, ue):
+        """The two boundary facets of a non-periodic line, per side s = -1
+        (lo, element 0, local node 0) and +1 (hi, element n - 1, local node
+        p), outward: f^partial = F(u_j, u_hat_j; n) of the end node j (in 1D
+        |S| = |c_j| = 1 and phi_j is 1 at the end point), which is also the
+        boundary flux of b(phi_i, u_h, u_hat_h) [KHV eqs. (bidef), (aecb)];
+        the low-order flux f^L = F(u^e, u_hat^{e'}; n) with u_hat^{e'} the
+        boundary data of u^e and its speed lambda_ee'; f_h . n at the end."""
+        out = {}
+        for s in (-1, 1):
+            e = 0 if s < 0 else self.mesh.E - 1
+            loc = 0 if s < 0 else self.mesh.p
+            uj = U[:, e, loc]
+            fb, _ = self.llf(uj, self.ghost(uj, s), s)
+            uhe = self.ghost(ue[:, e], s)
+            fL, lam = self.llf(ue[:, e], uhe, s)
+            out[s] = dict(e=e, loc=loc, node=self.conn[e, loc], fb=fb, fL=fL, lam=float(lam),
+                          fhn=s * self.prob.phys.flux(uj)[0], uhat_e=uhe)
         return out
 
     # -- [KHV §2.2] projected gradient ------------------------------------
@@ -237,17 +307,24 @@ class Oracle:
                 cands.append((k, self.nbr[(k, s)], -float(s)))
         nl = len(cands)
         wlin = np.array([1.0 - (nl - 1) * prm.w_lin] + [prm.w_lin] * (nl - 1))
+        # a boundary facet has no neighbour: its candidate is absent
+        present = np.ones((nl, E), dtype=bool)
+        for l, (ax, nb, sh) in enumerate(cands):
+            if nb is not None:
+                present[l] = nb >= 0
         shape = (E,) + (p + 1,) * d
         out = dict(beta=[], omega=[], dev=[], nrm=[], gamma=[])
         for c in range(m):
             T = U[c].reshape(shape)
             vals = []       # vals[l][kk] : (E, q...)
             for (ax, nb, sh) in cands:
-                Tl = T if nb is None else T[nb]
+                # (an absent candidate is given the element's own polynomial:
+                # its weight is zero, so it adds nothing)
+                Tl = T if nb is None else T[np.where(nb >= 0, nb, np.arange(E))]
                 vals.append([self._deriv_at_gauss(Tl, kk, ax, sh) for kk in ks])
             beta = np.stack([sum(np.sum(W * v ** 2, axis=axes_q) for v in vl)
                              for vl in vals])                 # (nl, E)
-            wt = wlin[:, None] / (beta ** (prm.r / 2.0) + prm.eps)
+            wt = np.where(present, wlin[:, None] / (beta ** (prm.r / 2.0) + prm.eps), 0.0)
             om = wt / wt.sum(axis=0)
             dev2 = 0.0
             for kk in range(len(ks)):
@@ -373,6 +450,14 @@ class Oracle:
             - gamma[None, :, None] * area
             * sum(np.einsum("ij,cej->cei", el.cgrad[k], Gn[k]) for k in range(d)))
         r = self.assemble(A - S)      # residual of (10): M_C udot = r (periodic, b = 0)
+        bf = None
+        if not mesh.periodic:
+            # -a(phi_i, u_h) - b(phi_i, u_h, u_hat_h) [KHV eqs. (weak:stab2),
+            # (bidef)]: integrating div f(u_h) by parts leaves phi_i f(u_h) . n
+            # at the two end points, which b turns into phi_i F(u_h, u_hat_h; n)
+            bf = self.boundary_facets(U, ue)
+            for sd in (-1, 1):
+                r[:, bf[sd]["node"]] -= bf[sd]["fb"]
 
         # ---- step 2: consistent-mass solve for udot ------------------------
         udot = self.solve_consistent_mass(r)
@@ -392,19 +477,43 @@ class Oracle:
             fL = 0.5 * (F.flux(ue)[k] + F.flux(ue[:, hi])[k]) - 0.5 * lam * (ue[:, hi] - ue)
             fL_c.append(fL)                                    # [KHV eq. (18)]
             lam_c.append(lam)
+        if bf is not None:
+            # non-periodic line: the high boundary facet takes the place of
+            # the last element's canonical facet (same orientation, +x), with
+            # f^H = f^partial and f^L with the boundary data [KHV eqs.
+            # (hoflux), (fL)]; the low boundary facet is kept apart (outward)
+            eh = bf[1]["e"]
+            fH_c[0][:, eh] = bf[1]["fb"]
+            fL_c[0][:, eh] = bf[1]["fL"]
+            lam_c[0][eh] = bf[1]["lam"]
 
-        def outward(qc, k, s):
-            """facet quantity of element e on side s of axis k, outward."""
-            return qc[k] if s > 0 else -qc[k][..., self.nbr[(k, -1)]]
+        def outward(qc, k, s, low=None):
+            """facet quantity of element e on side s of axis k, outward; on a
+            non-periodic line element 0's low facet takes `low`, the boundary
+            facet's own outward value."""
+            if s > 0:
+                return qc[k]
+            v = -qc[k][..., self.nbr[(k, -1)]]
+            if bf is not None:
+                v = v.copy()
+                v[..., 0] = low
+            return v
 
-        lam_sum = sum(lam_c[k] + lam_c[k][self.nbr[(k, -1)]] for k in range(d))
+        lo_b = bf[-1] if bf is not None else dict(fb=None, fL=None, lam=None)
+        lam_sum = 0.0
+        for k in range(d):
+            lam_lo = lam_c[k][self.nbr[(k, -1)]]
+            if bf is not None:
+                lam_lo = lam_lo.copy()
+                lam_lo[0] = lo_b["lam"]
+            lam_sum = lam_sum + lam_c[k] + lam_lo
         dt_e = vol / (area * lam_sum)                          # [KHV eq. (40)]
-        fH_sum = sum(outward(fH_c, k, s) for k in range(d) for s in (-1, 1))
+        fH_sum = sum(outward(fH_c, k, s, lo_b["fb"]) for k in range(d) for s in (-1, 1))
         if prm.flux_mode == "subcell":
             dt_e = self.subcell_dt(U, ue)                      # [KHV eq. (37)]
         elif prm.flux_mode == "shrink":
             dt_e = self.shrunk_dt(ue, fH_sum, dt_e)            # Remark after (40)
-        fL_sum = sum(outward(fL_c, k, s) for k in range(d) for s in (-1, 1))
+        fL_sum = sum(outward(fL_c, k, s, lo_b["fL"]) for k in range(d) for s in (-1, 1))
         ubarL = ue - dt_e / vol * area * fL_sum                # [KHV eq. (51)]
 
         # bounds of the scalar limiters per element (Sec. 4.1, 4.2): global,
@@ -415,41 +524,66 @@ class Oracle:
             b_lo, b_hi = ue[0].copy(), ue[0].copy()
             for k in range(d):
                 for s_ in (-1, 1):
-                    b_lo = np.minimum(b_lo, ue[0][self.nbr[(k, s_)]])
-                    b_hi = np.maximum(b_hi, ue[0][self.nbr[(k, s_)]])
+                    nb = self.nbr[(k, s_)]
+                    v = ue[0][nb]
+                    if bf is not None:
+                        # across a boundary facet: the boundary data u_hat^{e'}
+                        # (the low-order average mixes it in)
+                        v = np.where(nb >= 0, v, bf[s_]["uhat_e"][0])
+                    b_lo = np.minimum(b_lo, v)
+                    b_hi = np.maximum(b_hi, v)
         else:
             b_lo, b_hi = np.full(E, prob.u_min), np.full(E, prob.u_max)
 
         fA_c = [fL_c[k] - fH_c[k] for k in range(d)]           # f^A = f^L - f^H
         phi_e = vol / (2 * d * area)                           # |K_e| / |dK_e|
         fAbar_c = []
-        for k in range(d):
-            hi = self.nbr[(k, 1)]
-            fA = fA_c[k]
+        def limit(fA, has_hi, hi, dt_hi=None):
+            """limited antidiffusive flux of canonical facets (e, hi) [KHV eq.
+            (53) / Appendix A]; where has_hi is False the facet is the
+            boundary facet of e, which keeps only e's bounds (e' > E_h)"""
             if prm.alpha_mode == "one":
-                fAbar_c.append(fA)
-            elif prm.alpha_mode == "zero":
-                fAbar_c.append(np.zeros_like(fA))
-            elif prob.kind == "euler":
+                return fA
+            if prm.alpha_mode == "zero":
+                return np.zeros_like(fA)
+            if prob.kind == "euler":
                 # Appendix A on the pair (u_ee', u_e'e); u_ee' = ubarL_e +
                 # alpha |dK_e| dt_e f^A / |K_e| and the mirror for e'
                 de = fA / phi_e * dt_e
                 dh = -fA / phi_e * dt_e[hi]
                 a1 = self._euler_alpha(ubarL, de, 1.0)
-                a2 = self._euler_alpha(ubarL[:, hi], dh, 1.0)
-                fAbar_c.append(np.minimum(a1, a2)[None] * fA)
-            else:
-                # [KHV eq. (53)]: e keeps ubar^e <= its upper bound, e' keeps
-                # ubar^{e'} >= its lower bound (and the mirror for f^min)
+                a2 = np.where(has_hi, self._euler_alpha(ubarL[:, hi], dh, 1.0), 1.0)
+                return np.minimum(a1, a2)[None] * fA
+            # [KHV eq. (53)]: e keeps ubar^e <= its upper bound, e' keeps
+            # ubar^{e'} >= its lower bound (and the mirror for f^min)
+            with np.errstate(invalid="ignore"):
                 fmax = np.minimum(phi_e * (b_hi - ubarL) / dt_e,
-                                  phi_e * (ubarL[:, hi] - b_lo[hi]) / dt_e[hi])
+                                  np.where(has_hi, phi_e * (ubarL[:, hi] - b_lo[hi]) / dt_e[hi], np.inf))
                 fmin = np.maximum(phi_e * (b_lo - ubarL) / dt_e,
-                                  phi_e * (ubarL[:, hi] - b_hi[hi]) / dt_e[hi])
-                fAbar_c.append(np.where(fA >= 0.0, np.minimum(fA, fmax),
-                                        np.maximum(fA, fmin)))
+                                  np.where(has_hi, phi_e * (ubarL[:, hi] - b_hi[hi]) / dt_e[hi], -np.inf))
+            return np.where(fA >= 0.0, np.minimum(fA, fmax), np.maximum(fA, fmin))
+
+        for k in range(d):
+            hi = self.nbr[(k, 1)]
+            fAbar_c.append(limit(fA_c[k], hi >= 0, hi))
+        fAbar_low = None
+        if bf is not None:
+            # the low boundary facet of element 0, outward: the same one-sided
+            # limiter seen from element 0 (a 1-element view of limit())
+            fA_lo = lo_b["fL"] - lo_b["fb"]
+            if prm.alpha_mode == "one":
+                fAbar_low = fA_lo
+            elif prm.alpha_mode == "zero":
+                fAbar_low = np.zeros_like(fA_lo)
+            elif prob.kind == "euler":
+                fAbar_low = self._euler_alpha(ubarL[:, 0], fA_lo / phi_e * dt_e[0], 1.0) * fA_lo
+            else:
+                fmax = phi_e * (b_hi[0] - ubarL[:, 0]) / dt_e[0]
+                fmin = phi_e * (b_lo[0] - ubarL[:, 0]) / dt_e[0]
+                fAbar_low = np.where(fA_lo >= 0.0, np.minimum(fA_lo, fmax), np.maximum(fA_lo, fmin))
 
         # ---- step 4: element loop: limited averages, contributions, beta ---
-        fAbar_sum = sum(outward(fAbar_c, k, s) for k in range(d) for s in (-1, 1))
+        fAbar_sum = sum(outward(fAbar_c, k, s, fAbar_low) for k in range(d) for s in (-1, 1))
         if prm.flux_mode == "limit":
             ubar = ubarL + dt_e / vol * area * fAbar_sum       # [KHV eq. (44)]
         else:
@@ -479,10 +613,21 @@ class Oracle:
         else:
             Ud = udot[:, conn]
             cons = vol * np.einsum("ij,cej->cei", el.mass, Ud) - mloc * Ud
+            gb = np.zeros_like(U)
+            if bf is not None:
+                # g_i^e of [KHV eq. (aecb)] on the two boundary elements: in 1D
+                # the facet integrals are point values at the end, so g_i^e =
+                # (delta_{i,end} - m_i^e/|K_e|) (F(u_end, u_hat; n) - f_h . n)
+                for sd in (-1, 1):
+                    jump = bf[sd]["fb"] - bf[sd]["fhn"]
+                    w = -mloc / vol
+                    w = w.copy()
+                    w[bf[sd]["loc"]] += 1.0
+                    gb[:, bf[sd]["e"], :] += w[None, :] * jump[:, None]
             fe = (mloc * (U - ue[:, :, None])
                   + dt_e[None, :, None] * ((A - fgrad_h)
                                            - (fdiv_h - (mloc / vol) * fdiv_tot[:, :, None])
-                                           - S - cons))
+                                           - gb - S - cons))
 
         # slope limiter [KHV eqs. (54), (55)] / Appendix A
         if prm.beta_mode == "one":
@@ -517,6 +662,8 @@ class Oracle:
                     fgrad_h=fgrad_h, fH=np.stack(fH_c), fL=np.stack(fL_c), lam_f=np.stack(lam_c),
                     dt_e=dt_e, ubarL=ubarL, fA=np.stack(fA_c), fAbar=np.stack(fAbar_c),
                     b_lo=b_lo, b_hi=b_hi, fdiv_tot=fdiv_tot, udot_lo=udot_lo,
+                    fA_low=(lo_b["fL"] - lo_b["fb"]) if bf is not None else None,
+                    fAbar_low=fAbar_low,
                     ubar=ubar, fe=fe, beta=beta, A=A, S=S, u_fe=u_fe)
         return u_fe, taps
 
@@ -542,7 +689,7 @@ class Oracle:
     def max_dt(self, u):
         """min_e dt_e(u) of [KHV eq. (40)] without running a stage (with the
         flux limiter off: of the stage's own dt_e, eq. (37) or the Remark)."""
-        if self.prob.params.flux_mode != "limit":
+        if self.prob.params.flux_mode != "limit" or not self.mesh.periodic:
             return float(np.min(self.fe_stage(u, 0.0)[1]["dt_e"]))
         mesh, F = self.mesh, self.prob.phys
         d, h = mesh.d, mesh.h
