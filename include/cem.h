@@ -11,7 +11,9 @@
  * Scope: uniform periodic boxes of cube cells in 1, 2 or 3 dimensions,
  * tensor-product Bernstein elements Q_p (p = 1..3, p = 1..2 in 3D), scalar
  * linear advection, the KPP flux (sin u, cos u) in 2D, and the compressible
- * Euler equations of an ideal gas.  Arithmetic is IEEE float64.
+ * Euler equations of an ideal gas; in 1D also non-periodic lines with
+ * weakly imposed boundary data (cem_mesh_desc.bc).  Arithmetic is IEEE
+ * float64.
  *
  * Conventions shared by every call
  *  - Every call returns a cem_status; 0 is success.  A failing call leaves a
@@ -27,7 +29,8 @@
  *  - Nodal arrays are structure-of-arrays, component-major, float64:
  *        u[c * N + node],  node = i0 + L0 * (i1 + L1 * i2),  0 <= ik < Lk,
  *    with Lk = p * n[k] unique nodes per axis of the periodic box (the node
- *    at the upper end of an axis is the node at its lower end).  Node
+ *    at the upper end of an axis is the node at its lower end), or
+ *    L0 = p * n[0] + 1 nodes on a non-periodic line.  Node
  *    (i0, i1, i2) carries the Bernstein coefficient whose nodal point is
  *    lo + h * (i0, i1, i2) / p.  Components: scalar problems m = 1; Euler
  *    m = d + 2 with (rho, rho v_1..rho v_d, rho E).
@@ -106,13 +109,38 @@ typedef enum { CEM_BOUNDS_GLOBAL = 0, CEM_BOUNDS_LOCAL = 1 } cem_bounds_mode;
  *   are defined only in the cited work. */
 typedef enum { CEM_CONTRIB_AEC = 0, CEM_CONTRIB_Q1 = 1 } cem_contrib;
 
-/* Uniform periodic box [lo, hi] with n[k] cube cells per axis (cell edge h
- * equal on every axis; unused axes ignored).  n[k] >= 2. */
+/* Boundary conditions of a non-periodic line (eq. ibvp: f(u) . n =
+ * F(u, u_hat; n) on the boundary, imposed weakly through the boundary term
+ * b of eq. bidef, the boundary facet fluxes f^partial and F(u^e, u_hat^e';
+ * n) of Sec. 4 and g_i^e of eq. aecb, with the LLF flux of eq. fluxLLF).
+ * CEM_BC_PERIODIC: no boundary (both ends must be periodic together).
+ * CEM_BC_STATE: u_hat is the conserved state given in bc_state (inflow or
+ *   far-field data; an admissible state for Euler, a value inside the
+ *   global bounds for scalar problems).
+ * CEM_BC_OUTFLOW: u_hat = u (the boundary flux is f(u) . n).
+ * CEM_BC_WALL: Euler only, u_hat = u with reversed momentum (a reflecting
+ *   wall: no mass or energy crosses it).
+ * At a boundary facet the low-order flux uses u_hat^e' = the boundary data
+ * of the element's cell average, the WENO candidate of the missing
+ * neighbour is absent, the flux limiter keeps only the element's bounds
+ * (eq. 53 for e' > E_h) and local bounds include u_hat^e'. */
+typedef enum { CEM_BC_PERIODIC = 0, CEM_BC_STATE = 1, CEM_BC_OUTFLOW = 2, CEM_BC_WALL = 3 } cem_bc_kind;
+
+/* Uniform box [lo, hi] with n[k] cube cells per axis (cell edge h equal on
+ * every axis; unused axes ignored).  n[k] >= 2.  Periodic unless bc says
+ * otherwise: bc[0], bc[1] (cem_bc_kind) are the conditions at lo[0] and
+ * hi[0] of a 1D line, both CEM_BC_PERIODIC (all zero: the periodic box) or
+ * both non-periodic.  Non-periodic lines need dim = 1, CEM_FP64,
+ * CEM_FLUX_LIMIT or CEM_FLUX_SHRINK and CEM_CONTRIB_AEC (the subcell bound
+ * with boundary facets and the periodic Q1 form are not defined), and are
+ * single problems only (cem_batch_create refuses them). */
 typedef struct {
   int dim;       /* 1, 2 or 3 */
   int degree;    /* Bernstein degree p */
   int n[3];
   double lo[3], hi[3];
+  int bc[2];               /* cem_bc_kind at lo[0] and hi[0] */
+  double bc_state[2][5];   /* CEM_BC_STATE: conserved state (m values) at each end */
 } cem_mesh_desc;
 
 typedef struct {

@@ -23,6 +23,8 @@ BOUNDS_GLOBAL, BOUNDS_LOCAL = 0, 1
 BOUNDS = {"global": BOUNDS_GLOBAL, "local": BOUNDS_LOCAL}
 CONTRIB_AEC, CONTRIB_Q1 = 0, 1
 CONTRIBS = {"aec": CONTRIB_AEC, "q1": CONTRIB_Q1}
+BC_PERIODIC, BC_STATE, BC_OUTFLOW, BC_WALL = 0, 1, 2, 3
+BCS = {"periodic": BC_PERIODIC, "state": BC_STATE, "outflow": BC_OUTFLOW, "wall": BC_WALL}
 STATUS = {0: "CEM_OK", -1: "CEM_EINVAL", -2: "CEM_EHIP", -3: "CEM_ENOMEM",
           -4: "CEM_ECFL", -5: "CEM_EIDP"}
 TAPS = dict(g=0, r=1, udot=2, gamma=3, nu=4, dt_e=5, ue=6, ubarL=7, ubar=8, beta=9,
@@ -37,7 +39,22 @@ class CemError(RuntimeError):
 
 class MeshDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("degree", ctypes.c_int), ("n", ctypes.c_int * 3),
-                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("bc", ctypes.c_int * 2), ("bc_state", (ctypes.c_double * 5) * 2)]
+
+
+def set_mesh_bc(mesh, bc):
+    """bc: None (periodic) or ((kind, state), (kind, state)) for the ends at
+    lo[0] and hi[0]; kind a key of BCS, state the conserved values of a
+    "state" end (else None)."""
+    if bc is None:
+        return
+    for s, (kind, state) in enumerate(bc):
+        mesh.bc[s] = BCS[kind] if isinstance(kind, str) else int(kind)
+        if state is not None:
+            vals = list(np.asarray(state, dtype=np.float64).ravel())
+            for q, v in enumerate(vals[:5]):
+                mesh.bc_state[s][q] = float(v)
 
 
 class PhysicsDesc(ctypes.Structure):
@@ -281,7 +298,7 @@ class Solver:
     tensors on `device`; all work goes to the current torch stream."""
 
     def __init__(self, d, p, n, lo, hi, kind, velocity=(1.0, 0.0, 0.0), gamma_gas=1.4,
-                 device="cuda:0", **params):
+                 device="cuda:0", bc=None, **params):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -289,6 +306,7 @@ class Solver:
         mesh = MeshDesc(d, p, (ctypes.c_int * 3)(*(list(n) + [1] * (3 - d))),
                         (ctypes.c_double * 3)(*(list(lo) + [0.0] * (3 - d))),
                         (ctypes.c_double * 3)(*(list(hi) + [1.0] * (3 - d))))
+        set_mesh_bc(mesh, bc)
         phys = PhysicsDesc(KINDS[kind], (ctypes.c_double * 3)(*(list(velocity) + [0.0] * 3)[:3]),
                            gamma_gas)
         prm = make_params(params)
@@ -309,7 +327,7 @@ class Solver:
         params.setdefault("w_lin", wl.w_lin)
         params.setdefault("q", wl.q)
         return cls(wl.d, wl.p, wl.n, wl.lo, wl.hi, wl.kind, wl.velocity, wl.gamma_gas,
-                   device=device, **params)
+                   device=device, bc=getattr(wl, "bc", None), **params)
 
     def upload(self, host_u):
         cem_upload_state(self.ctx, np.asarray(host_u, dtype=np.float64).reshape(self.m, self.N))

@@ -81,6 +81,11 @@ struct cem_ctx {
   size_t boff_kg32[3] = {0, 0, 0}, boff_km32[3] = {0, 0, 0}, boff_kgf32[3] = {0, 0, 0},
          boff_kmf32[3] = {0, 0, 0}, boff_sf32 = 0;
   bool mixed = false;
+  // non-periodic 1D line: boundary conditions and line-operator tables
+  bool bounded = false;
+  int bc[2] = {0, 0};
+  double bc_u[2][5] = {{0.0}};
+  size_t off_bm[3] = {0, 0, 0}, off_bg[3] = {0, 0, 0};   // wi, lo, hi (doubles)
   // bound memory
   double* u = nullptr;
   double* u0 = nullptr;
@@ -88,7 +93,7 @@ struct cem_ctx {
   size_t ws_need = 0;
   // workspace carve-up (byte offsets)
   size_t o_g, o_r, o_udot, o_tmp, o_tmp2, o_relem, o_ue, o_ubarL, o_ubar, o_fahi, o_dte, o_gam,
-      o_nu, o_beta, o_bnd, o_fdiv, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart, o_fnode;
+      o_nu, o_beta, o_bnd, o_fdiv, o_dtbuf, o_counts, o_inv, o_tab, o_dtpart, o_fnode, o_fbnd;
   size_t o_g32 = 0, o_r32 = 0, o_udot32 = 0, o_tmp32 = 0, o_tmp2_32 = 0;
   bool fnode_valid = false;   // nodal fluxes match the bound state
   int lds_max = 65536;        // LDS bytes one block may use on the bound device
@@ -183,6 +188,14 @@ void pack_tables(cem_ctx* c) {
     app(T.ext, 2 * PP);
     app(T.qp, (int)T.qp.size());
     c->off_sf = put(sf);
+  }
+  if (c->bounded) {
+    c->off_bm[0] = put(T.bmass.wi);
+    c->off_bm[1] = put(T.bmass.lo);
+    c->off_bm[2] = put(T.bmass.hi);
+    c->off_bg[0] = put(T.bgrad.wi);
+    c->off_bg[1] = put(T.bgrad.lo);
+    c->off_bg[2] = put(T.bgrad.hi);
   }
   for (int k = 0; k < D; ++k) {
     c->off_kg[k] = put(T.kgrad[k].w);
@@ -328,6 +341,12 @@ StageArgs make_args(const cem_ctx* c) {
   a.mesh.N = c->N;
   a.mesh.E = c->E;
   a.mesh.h = c->h;
+  a.mesh.bnd1d = c->bounded ? 1 : 0;
+  for (int s = 0; s < 2; ++s) {
+    a.bc_kind[s] = c->bc[s];
+    for (int q = 0; q < 5; ++q) a.bc_u[s][q] = c->bc_u[s][q];
+  }
+  a.fbnd = c->W<double>(c->o_fbnd);
   const double* tb = c->W<double>(c->o_tab);
   a.tab.sf = tb + c->off_sf;
   a.tab.sf32 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(tb) + c->boff_sf32);
@@ -440,6 +459,34 @@ cem_status launch_line(cem_ctx* c, const TI* in, TO* out, int axis, bool grad) {
   la.total = (int64_t)c->m * c->N;
   la.scale = 1.0;
   CEM_LAUNCH(c, id, (k_line<TI, TO>), nblocks(la.total, 256), 256, 0, c->stream, la);
+  HIPCHK(hipGetLastError());
+  return CEM_OK;
+}
+
+// a line operator of a non-periodic line (grad: Mb^{-1} Cb, else Mb^{-1})
+cem_status launch_line_bnd(cem_ctx* c, const double* in, double* out, bool grad) {
+  const BoundedLine& K = grad ? c->tabs.bgrad : c->tabs.bmass;
+  const size_t* off = grad ? c->off_bg : c->off_bm;
+  const double* tb = c->W<double>(c->o_tab);
+  BndLineArgs la{};
+  la.in = in;
+  la.out = out;
+  la.wi = tb + off[0];
+  la.lo = tb + off[1];
+  la.hi = tb + off[2];
+  la.N = c->N;
+  la.total = (int64_t)c->m * c->N;
+  la.P = c->p;
+  la.W = K.W;
+  la.blo = K.blo;
+  la.bhi = K.bhi;
+  la.cw = K.cw;
+  // the kernel's reads stay in the line: end blocks of at least W rows, or
+  // one exact block over the whole line
+  if (!((K.blo >= K.W && K.bhi >= K.W && 2 * (int64_t)K.W < c->N && K.cw <= c->N) ||
+        (K.blo == c->N && K.bhi == 0 && K.cw == c->N)))
+    return fail(CEM_EINVAL, "internal: line operator blocks do not cover the line");
+  CEM_LAUNCH(c, grad ? 0 : 4, k_line_bnd, nblocks(la.total, 256), 256, 0, c->stream, la);
   HIPCHK(hipGetLastError());
   return CEM_OK;
 }
@@ -634,6 +681,47 @@ cem_status stage_impl(cem_ctx* c, int stage, double dt, double cfl) {
     HIPCHK(hipGetLastError());
   }
   CEM_LAUNCH(c, 6, (k_update<D, P, PH>), c->upd_blocks, 256, 0, c->stream, a);
+  HIPCHK(hipGetLastError());
+  return CEM_OK;
+}
+
+// One stage on a non-periodic 1D line (float64): the same five steps with
+// the line operators of the bounded line, the boundary facets in the
+// element passes and the end nodes gathered from their one element.
+template <int P, int PH>
+cem_status stage_line_impl(cem_ctx* c, int stage, double dt, double cfl) {
+  constexpr int M = Phys<1, PH>::M;
+  static_assert(!Phys<1, PH>::kNodal, "no nodal-flux physics on lines");
+  StageArgs a = make_args(c);
+  const double rka[3] = {0.0, 0.75, 1.0 / 3.0}, rkb[3] = {1.0, 0.25, 2.0 / 3.0};
+  a.rk_a = rka[stage];
+  a.rk_b = rkb[stage];
+  a.stage = stage;
+  a.copy_base = (stage == 0 && c->copy_base_next) ? 1 : 0;
+  a.ndtpart = (int)nblocks(c->E, 128);
+  a.dt_fixed = dt;
+  a.cfl = cfl;
+  if ((size_t)a.ndtpart > c->ndtp) return fail(CEM_EINVAL, "internal: more element blocks than dt_e minima slots");
+  // projected gradient g = Mb^{-1} Cb u (Sec. 2.2)
+  cem_status st = launch_line_bnd(c, c->u, a.g, true);
+  if (st != CEM_OK) return st;
+  // element pass: sensor, residual with the boundary flux at the end
+  // nodes, facets (boundary facets at the ends)
+  CEM_LAUNCH(c, 1, (k_elem1<1, P, PH, true, double>), nblocks(c->E, 128), 128, 0, c->stream, a);
+  HIPCHK(hipGetLastError());
+  // r, then udot = Mb^{-1} r (Sec. 4.3, step 2)
+  CEM_LAUNCH(c, 3, (k_gather_r<1, P, M, double>), nblocks(c->N, 256), 256, 0, c->stream, a);
+  HIPCHK(hipGetLastError());
+  st = launch_line_bnd(c, a.r, a.udot, false);
+  if (st != CEM_OK) return st;
+  CEM_LAUNCH(c, 5, (k_elem2<1, P, PH, double>), nblocks(c->E, 128), 128, 0, c->stream, a);
+  HIPCHK(hipGetLastError());
+  if (a.ndtpart > kDtFusedMax) {
+    a.dt_ready = 1;
+    CEM_LAUNCH(c, 2, k_stage_dt, 1, 1024, 0, c->stream, a);
+    HIPCHK(hipGetLastError());
+  }
+  CEM_LAUNCH(c, 6, (k_update<1, P, PH>), c->upd_blocks, 256, 0, c->stream, a);
   HIPCHK(hipGetLastError());
   return CEM_OK;
 }
@@ -1049,8 +1137,17 @@ void drop_graph(cem_ctx* c) {
 }
 
 // float64 stages for every supported (d, p, physics); the mixed-precision
-// form is built for d = 2, 3
-StageFn pick(int d, int p, int kind, bool mixed = false) {
+// form is built for d = 2, 3; non-periodic lines for 1D advection and Euler
+StageFn pick(int d, int p, int kind, bool mixed = false, bool bounded = false) {
+  if (bounded) {
+    if (d != 1 || mixed) return nullptr;
+#define LCASE(P, PH) \
+    if (p == P && kind == PH) return &stage_line_impl<P, PH>;
+    LCASE(1, ADV) LCASE(2, ADV) LCASE(3, ADV)
+    LCASE(1, EUL) LCASE(2, EUL) LCASE(3, EUL)
+#undef LCASE
+    return nullptr;
+  }
 #define CASE(D, P, PH) \
   if (d == D && p == P && kind == PH && !mixed) return &stage_impl<D, P, PH, double>;
 #define CASEM(D, P, PH) \
@@ -1094,7 +1191,34 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   if (d < 1 || d > 3) return fail(CEM_EINVAL, "dim must be 1, 2 or 3");
   if (prm->precision != CEM_FP64 && prm->precision != CEM_FP32_MIXED)
     return fail(CEM_EINVAL, "precision must be CEM_FP64 or CEM_FP32_MIXED");
-  if (!pick(d, p, phys->kind, prm->precision == CEM_FP32_MIXED))
+  for (int s = 0; s < 2; ++s)
+    if (mesh->bc[s] < CEM_BC_PERIODIC || mesh->bc[s] > CEM_BC_WALL) return fail(CEM_EINVAL, "bc must be a cem_bc_kind");
+  const bool bounded = mesh->bc[0] != CEM_BC_PERIODIC || mesh->bc[1] != CEM_BC_PERIODIC;
+  if (bounded) {
+    if (mesh->bc[0] == CEM_BC_PERIODIC || mesh->bc[1] == CEM_BC_PERIODIC)
+      return fail(CEM_EINVAL, "both ends periodic, or neither");
+    if (d != 1) return fail(CEM_EINVAL, "non-periodic boundaries are provided for 1D lines");
+    if (prm->precision != CEM_FP64) return fail(CEM_EINVAL, "non-periodic lines compute in float64");
+    if (prm->flux_mode == CEM_FLUX_SUBCELL)
+      return fail(CEM_EINVAL, "the subcell bound of Lemma 1 is not defined with boundary facets");
+    if (prm->contrib == CEM_CONTRIB_Q1) return fail(CEM_EINVAL, "the Q1 contributions need a periodic mesh");
+    const int mm = phys->kind == CEM_EULER ? 3 : 1;
+    for (int s = 0; s < 2; ++s) {
+      if (mesh->bc[s] == CEM_BC_WALL && phys->kind != CEM_EULER)
+        return fail(CEM_EINVAL, "CEM_BC_WALL is an Euler condition");
+      if (mesh->bc[s] != CEM_BC_STATE) continue;
+      const double* st = mesh->bc_state[s];
+      for (int q = 0; q < mm; ++q)
+        if (!std::isfinite(st[q])) return fail(CEM_EINVAL, "boundary state not finite");
+      if (phys->kind == CEM_EULER) {
+        const double pr = (phys->gamma_gas - 1.0) * (st[2] - 0.5 * st[1] * st[1] / st[0]);
+        if (!(st[0] > 0.0) || !(pr > 0.0)) return fail(CEM_EINVAL, "boundary state outside the invariant domain");
+      } else if (!(st[0] >= prm->u_min && st[0] <= prm->u_max)) {
+        return fail(CEM_EINVAL, "boundary state outside [u_min, u_max]");
+      }
+    }
+  }
+  if (!pick(d, p, phys->kind, prm->precision == CEM_FP32_MIXED, bounded))
     return fail(CEM_EINVAL, "unsupported (dim, degree, physics, precision)");
   if (prm->flux_mode < CEM_FLUX_LIMIT || prm->flux_mode > CEM_FLUX_SHRINK)
     return fail(CEM_EINVAL, "flux_mode must be CEM_FLUX_LIMIT, CEM_FLUX_SUBCELL or CEM_FLUX_SHRINK");
@@ -1129,9 +1253,14 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->h = h;
   c->N = 1;
   c->E = 1;
+  c->bounded = bounded;
+  for (int s = 0; s < 2; ++s) {
+    c->bc[s] = mesh->bc[s];
+    for (int q = 0; q < 5; ++q) c->bc_u[s][q] = mesh->bc_state[s][q];
+  }
   for (int k = 0; k < d; ++k) {
     c->n[k] = mesh->n[k];
-    c->L[k] = p * mesh->n[k];
+    c->L[k] = p * mesh->n[k] + (bounded ? 1 : 0);
     c->N *= c->L[k];
     c->E *= c->n[k];
   }
@@ -1157,7 +1286,11 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
     if (rr >= 2.0 && rr <= 32.0 && std::fabs(r - rr) <= 1e-9 * rr) c->ph.rn = (int)rr;
   }
   c->stream = (hipStream_t)stream;
-  if (!build_tables(d, p, h, c->L, kWfast, kRfast, kSfast, kWfast32, kSfast32, c->tabs)) {
+  // (the periodic line tables of a non-periodic line are built for the
+  // periodic line of the same cells and stay unused)
+  const int Lper[3] = {p * c->n[0], c->L[1], c->L[2]};
+  if (!build_tables(d, p, h, Lper, kWfast, kRfast, kSfast, kWfast32, kSfast32, c->tabs) ||
+      (bounded && !build_bounded_line(p, c->n[0], h, c->tabs))) {
     delete c;
     return fail(CEM_EINVAL, "table construction failed");
   }
@@ -1187,6 +1320,7 @@ cem_status cem_create(const cem_mesh_desc* mesh, const cem_physics_desc* phys, c
   c->o_beta = take(E8);
   c->o_bnd = take(2 * E8);
   c->o_fdiv = take(E8);
+  c->o_fbnd = take((size_t)4 * c->m * 8);
   c->o_dtbuf = take(8 * 8);
   // per-block dt_e minima: one-thread-per-element blocks, 2D element tiles
   // or the 32- / 64-element blocks of the system passes
@@ -1289,8 +1423,17 @@ cem_status cem_set_bounds(cem_ctx* c, int from_state, double u_min, double u_max
     if (inv.nonfinite) return fail(CEM_EINVAL, "state holds non-finite values");
     u_min = inv.u_min[0];
     u_max = inv.u_max[0];
+    // the boundary data of a non-periodic line enters the scheme as well
+    for (int s = 0; s < 2; ++s)
+      if (c->bounded && c->bc[s] == CEM_BC_STATE) {
+        u_min = std::fmin(u_min, c->bc_u[s][0]);
+        u_max = std::fmax(u_max, c->bc_u[s][0]);
+      }
   }
   if (!(u_min <= u_max)) return fail(CEM_EINVAL, "u_min > u_max");
+  for (int s = 0; s < 2; ++s)
+    if (c->bounded && c->bc[s] == CEM_BC_STATE && !(c->bc_u[s][0] >= u_min && c->bc_u[s][0] <= u_max))
+      return fail(CEM_EINVAL, "boundary state outside [u_min, u_max]");
   c->prm.u_min = u_min;
   c->prm.u_max = u_max;
   c->bounds_set = true;
@@ -1303,14 +1446,14 @@ cem_status cem_rk_stage(cem_ctx* c, int stage, double dt, double cfl) {
   if (stage < 0 || stage > 2) return fail(CEM_EINVAL, "stage must be 0, 1 or 2");
   if (stage == 0 && !(dt > 0.0) && !(cfl > 0.0)) return fail(CEM_EINVAL, "need dt > 0 or cfl > 0");
   if (c->kind != CEM_EULER && !c->bounds_set) return fail(CEM_EINVAL, "scalar bounds not set");
-  return pick(c->d, c->p, c->kind, c->mixed)(c, stage, dt, cfl);
+  return pick(c->d, c->p, c->kind, c->mixed, c->bounded)(c, stage, dt, cfl);
 }
 
 static cem_status step_direct(cem_ctx* c, double dt, double cfl) {
   c->copy_base_next = true;     // stage 0 writes u_base = u (no separate copy)
   c->in_step = true;
   cem_status st = CEM_OK;
-  for (int s = 0; s < 3 && st == CEM_OK; ++s) st = pick(c->d, c->p, c->kind, c->mixed)(c, s, dt, cfl);
+  for (int s = 0; s < 3 && st == CEM_OK; ++s) st = pick(c->d, c->p, c->kind, c->mixed, c->bounded)(c, s, dt, cfl);
   c->copy_base_next = false;
   c->in_step = false;
   return st;
@@ -1566,6 +1709,10 @@ cem_status cem_batch_create(int count, const cem_mesh_desc* meshes, const cem_ph
   b->uoff.assign(1, 0);
   size_t ws = 0;
   for (int k = 0; k < count; ++k) {
+    if (meshes[k].bc[0] != CEM_BC_PERIODIC || meshes[k].bc[1] != CEM_BC_PERIODIC) {
+      cem_batch_destroy(b);
+      return fail(CEM_EINVAL, "batched form: periodic meshes only");
+    }
     if (meshes[k].dim != d || meshes[k].degree != p) {
       cem_batch_destroy(b);
       return fail(CEM_EINVAL, "batched form: every problem needs the same dimension and degree");

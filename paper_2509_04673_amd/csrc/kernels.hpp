@@ -71,7 +71,11 @@ struct MeshArgs {
   int L[3];         // nodes per axis (1 for unused axes)
   int64_t N, E;
   double h;
+  int bnd1d;        // 1: a non-periodic 1D line (L[0] = p n + 1, boundary facets at both ends)
 };
+
+// boundary conditions of a non-periodic line (the values of cem_bc_kind)
+constexpr int kBcState = 1, kBcOutflow = 2, kBcWall = 3;
 
 struct StageArgs {
   MeshArgs mesh;
@@ -89,6 +93,10 @@ struct StageArgs {
                         // the nodes whose elements all lie in its block
   int cnt_off;          // first counter slot of the pass-2 blocks (fuse_upd)
   double* fdiv;         // [E] int_dK f_h . n of each element (contrib_q1)
+  int bc_kind[2];       // non-periodic line: kBc* of the low and high end
+  double bc_u[2][5];    // kBcState: the prescribed conserved state of each end
+  double* fbnd;         // non-periodic line: [2 ends][2][M], [.][1] the boundary
+                        // facet's boundary flux F(u_end, u_hat; n) (outward)
   const double* u;      // stage input u^(s)   [M][N]
   double* u0;           // step base u^n       [M][N]
   double* uout;         // stage output (may alias u: per-node read-then-write)
@@ -329,6 +337,19 @@ __device__ inline double euler_alpha(const double* ub, const double* f, double m
   return fmin(a, 1.0);
 }
 
+// Boundary data u_hat of end `side` (0 low, 1 high) of a non-periodic line
+// for the interior state u: the prescribed state, u itself (outflow) or,
+// for Euler, u with reversed momentum (reflecting wall)
+template <int M>
+__device__ __forceinline__ void bc_ghost(const StageArgs& a, int side, const double* u, double* uh) {
+  // (selects with constant indices: the kernel argument is not indexed by a
+  // runtime value)
+  const int kind = side ? a.bc_kind[1] : a.bc_kind[0];
+#pragma unroll
+  for (int c = 0; c < M; ++c) uh[c] = kind == kBcState ? (side ? a.bc_u[1][c] : a.bc_u[0][c]) : u[c];
+  if (M > 1 && kind == kBcWall) uh[1] = -u[1];
+}
+
 // XCD-aware block order: the hardware hands workgroup b to XCD b mod 8, and
 // each XCD has its own L2.  Giving XCD x the contiguous range of logical
 // blocks [x q + min(x, r), ... + q + (x < r)), q = nb / 8, r = nb mod 8, puts
@@ -439,6 +460,42 @@ __global__ void __launch_bounds__(256) k_line(LineArgs a) {
 // accumulators and streams R + TAPS - 1 inputs once.
 // W: half-width; runs of R = P * RE outputs, RE in {1, 2, 4} chosen per
 // launch so that small meshes still fill the chip
+// Line operators of a non-periodic 1D line (Mb^{-1} or Mb^{-1} Cb), one
+// thread per output value: the first blo and last bhi rows are exact rows
+// over the first / last cw nodes, the rows between them the infinite-line
+// rows of their node class (i mod p) at offsets -W..W.  Every access stays
+// inside the line: blo, bhi >= W, or blo = N with cw = N (short lines).
+struct BndLineArgs {
+  const double* in;     // [M][N]
+  double* out;          // [M][N]
+  const double* wi;     // [P][2W + 1]
+  const double* lo;     // [blo][cw]
+  const double* hi;     // [bhi][cw]
+  int64_t N, total;     // nodes of the line, M N
+  int P, W, blo, bhi, cw;
+};
+
+__global__ void __launch_bounds__(256) k_line_bnd(BndLineArgs a) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.total) return;
+  const int64_t c = q / a.N, i = q - c * a.N;
+  const double* x = a.in + c * a.N;
+  double s = 0.0;
+  if (i < a.blo) {
+    const double* w = a.lo + i * a.cw;
+    for (int j = 0; j < a.cw; ++j) s = fma(w[j], x[j], s);
+  } else if (i >= a.N - a.bhi) {
+    const double* w = a.hi + (i - (a.N - a.bhi)) * a.cw;
+    const double* xs = x + (a.N - a.cw);
+    for (int j = 0; j < a.cw; ++j) s = fma(w[j], xs[j], s);
+  } else {
+    const double* w = a.wi + (int)(i % a.P) * (2 * a.W + 1);
+    const double* xs = x + (i - a.W);
+    for (int t = 0; t <= 2 * a.W; ++t) s = fma(w[t], xs[t], s);
+  }
+  a.out[q] = s;
+}
+
 template <int P> struct LineTaps;
 constexpr int kLineMaxRE = 4;
 // S: per-class weight stride, 2W+1 taps zero padded to a multiple of every
@@ -1538,6 +1595,11 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     for (int l = 0; l <= 2 * D; ++l) {
       const RT nr = (a.rexp == 2.0) ? beta[l] : (RT)pow((double)beta[l], 0.5 * a.rexp);
       wt[l] = (l == 0 ? wl0 : wlin) / (nr + eps);
+      if constexpr (D == 1) {
+        // a boundary facet of a non-periodic line has no neighbour: its
+        // candidate is absent
+        if (ms.bnd1d && ((l == 1 && e == 0) || (l == 2 && e == E - 1))) wt[l] = 0;
+      }
       wsum += wt[l];
     }
     const RT iws = (RT)1 / wsum;
@@ -1871,7 +1933,24 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   if constexpr (ROLE == 2) return 1.0e300;
 
   // ---- facets (Sec. 4, eqs. 18, 40, 42, 51): canonical orientation is from
-  // the lower to the upper element along +e_k; both sides evaluate it alike
+  // the lower to the upper element along +e_k; both sides evaluate it alike.
+  // The ends of a non-periodic line are boundary facets: the neighbour's
+  // average becomes the boundary data of u^e (low-order flux, local bounds)
+  // and f^H the boundary flux of the end node.
+  bool bfac[2] = {false, false};
+  if constexpr (D == 1) {
+    bfac[0] = ms.bnd1d && e == 0;
+    bfac[1] = ms.bnd1d && e == E - 1;
+    if constexpr (M == 1) {
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd)
+        if (bfac[sd]) {
+          double gh[M];
+          bc_ghost<M>(a, sd, ue, gh);
+          nbr_mean[sd][0] = gh[0];
+        }
+    }
+  }
   double lamsum = 0.0, fLsum[M], fHout[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) fLsum[c] = fHout[c] = 0.0;
@@ -1886,13 +1965,17 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     auto facet = [&](int side) {
       double unb[M];
       if constexpr (M > 1 && ROLE != 4) {
+        if (D == 1 && bfac[side]) {
+          bc_ghost<M>(a, side, ue, unb);
+        } else {
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-          double cn[NL], sum = 0.0;
-          ns.load_nbr(c, 2 * k + side, cn);
+          for (int c = 0; c < M; ++c) {
+            double cn[NL], sum = 0.0;
+            ns.load_nbr(c, 2 * k + side, cn);
 #pragma unroll
-          for (int j = 0; j < NL; ++j) sum += cn[j];
-          unb[c] = sum * (1.0 / NL);
+            for (int j = 0; j < NL; ++j) sum += cn[j];
+            unb[c] = sum * (1.0 / NL);
+          }
         }
       } else {
 #pragma unroll
@@ -1908,21 +1991,47 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
       double fH[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) fH[c] = 0.0;
+      if (D == 1 && bfac[side]) {
+        // boundary facet: f^H = f^partial = F(u_j, u_hat_j; n) of the end
+        // node j (eq. fluxLLF; |S| = |c_j| = 1 on a line), in the +x
+        // orientation of the canonical facets
+        const int j = side ? P : 0;
+        double uj[M], gj[M], fa[M], fz[M];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) {
-        if (dig(j, k, P1) != (side ? P : 0)) continue;
-        double fj[M];
-        if constexpr (PHY::kNodal) {
+        for (int c = 0; c < M; ++c) uj[c] = SEQ ? ns.own(c, j) : Uc(c, j);
+        bc_ghost<M>(a, side, uj, gj);
+        const double* pL = side ? uj : gj;
+        const double* pR = side ? gj : uj;
+        PHY::flux(k, pL, fa, a.ph);
+        PHY::flux(k, pR, fz, a.ph);
+        const double lb = PHY::riemann_speed(pL, pR, k, a.ph);
 #pragma unroll
-          for (int c = 0; c < M; ++c) fj[c] = fpre[k][side][j][c];
-        } else {
-          double uj[M];
-#pragma unroll
-          for (int c = 0; c < M; ++c) uj[c] = SEQ ? ns.own(c, j) : Uc(c, j);
-          PHY::flux(k, uj, fj, a.ph);
+        for (int c = 0; c < M; ++c) {
+          fH[c] = 0.5 * (fa[c] + fz[c]) - 0.5 * lb * (pR[c] - pL[c]);
+          // the outward boundary flux: -a(phi_j, u_h) - b(phi_j, u_h, u_hat)
+          // leaves -F(u_j, u_hat; n) at the end node (eqs. weak:stab2,
+          // bidef); pass 2 takes it for the element's boundary integral
+          const double Fb = side ? fH[c] : -fH[c];
+          a.fbnd[(side * 2 + 1) * M + c] = Fb;
+          a.relem[((int64_t)c * NL + j) * E + e] -= Fb;
         }
+      } else {
 #pragma unroll
-        for (int c = 0; c < M; ++c) fH[c] += fj[c];
+        for (int j = 0; j < NL; ++j) {
+          if (dig(j, k, P1) != (side ? P : 0)) continue;
+          double fj[M];
+          if constexpr (PHY::kNodal) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) fj[c] = fpre[k][side][j][c];
+          } else {
+            double uj[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) uj[c] = SEQ ? ns.own(c, j) : Uc(c, j);
+            PHY::flux(k, uj, fj, a.ph);
+          }
+#pragma unroll
+          for (int c = 0; c < M; ++c) fH[c] += fj[c];
+        }
       }
       const double lm = PHY::riemann_speed(uL, uR, k, a.ph);
       lamsum += lm;
@@ -2176,10 +2285,13 @@ __global__ void __launch_bounds__(384) k_elem1_tile3(StageArgs a) {
 // limited flux fb of the facet between eL (lower) and eR (upper): fA its raw
 // antidiffusive flux, uLs / uRs the two low-order averages, dtL / dtR the
 // two pseudo time steps
-// and, for scalar problems, bL / bR the two elements' bounds {lower, upper}
+// and, for scalar problems, bL / bR the two elements' bounds {lower, upper};
+// ghost 1 or 2: the lower or upper side is a boundary facet's exterior,
+// whose (absent) element imposes nothing (eq. 53, e' > E_h)
 template <int D, int PH>
 __device__ inline void limit_facet(const StageArgs& a, const double* fA, const double* uLs, const double* uRs,
-                                   double dtL, double dtR, const double* bL, const double* bR, double* fb) {
+                                   double dtL, double dtR, const double* bL, const double* bR, double* fb,
+                                   int ghost = 0) {
   using PHY = Phys<D, PH>;
   constexpr int M = PHY::M;
   const double phi = a.mesh.h / (2.0 * D);     // |K| / |dK|
@@ -2200,14 +2312,18 @@ __device__ inline void limit_facet(const StageArgs& a, const double* fA, const d
       dL[c] = fA[c] / phi * dtL;
       dR[c] = -fA[c] / phi * dtR;
     }
-    const double al = fmin(euler_alpha<D>(uLs, dL, 1.0, a.eps_pos), euler_alpha<D>(uRs, dR, 1.0, a.eps_pos));
+    const double al = fmin(ghost == 1 ? 1.0 : euler_alpha<D>(uLs, dL, 1.0, a.eps_pos),
+                           ghost == 2 ? 1.0 : euler_alpha<D>(uRs, dR, 1.0, a.eps_pos));
 #pragma unroll
     for (int c = 0; c < M; ++c) fb[c] = al * fA[c];
   } else {
     // eL keeps ubar^{eL} within its upper bound and eR within its lower
     // one (and the mirror for f^min)
-    const double fmx = fmin(phi * (bL[1] - uLs[0]) / dtL, phi * (uRs[0] - bR[0]) / dtR);
-    const double fmn = fmax(phi * (bL[0] - uLs[0]) / dtL, phi * (uRs[0] - bR[1]) / dtR);
+    const double inf = (double)INFINITY;
+    const double fmx = fmin(ghost == 1 ? inf : phi * (bL[1] - uLs[0]) / dtL,
+                            ghost == 2 ? inf : phi * (uRs[0] - bR[0]) / dtR);
+    const double fmn = fmax(ghost == 1 ? -inf : phi * (bL[0] - uLs[0]) / dtL,
+                            ghost == 2 ? -inf : phi * (uRs[0] - bR[1]) / dtR);
     fb[0] = fA[0] >= 0.0 ? fmin(fA[0], fmx) : fmax(fA[0], fmn);
   }
 }
@@ -2266,6 +2382,27 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
     ubc[c] = a.ubarL[c * E + e];
     uec[c] = a.ue[c * E + e];
   }
+  // the ends of a non-periodic line: element 0's low facet and the last
+  // element's high facet are boundary facets.  The high one's raw flux is in
+  // fahi like any +x facet; the low one's is formed here as pass 1 formed
+  // it, f^L = F(u_hat^e', u^e) along +x minus f^H = -F(u_end, u_hat; -1)
+  bool glo = false, ghi = false;
+  if constexpr (D == 1) {
+    glo = ms.bnd1d && e == 0;
+    ghi = ms.bnd1d && e == E - 1;
+    if (glo) {
+      double gh[M], fa[M], fz[M];
+      bc_ghost<M>(a, 0, uec, gh);
+      PHY::flux(0, gh, fa, a.ph);
+      PHY::flux(0, uec, fz, a.ph);
+      const double lm = PHY::riemann_speed(gh, uec, 0, a.ph);
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const double fLc = 0.5 * (fa[c] + fz[c]) - 0.5 * lm * (uec[c] - gh[c]);
+        fAl[0][c] = fLc + a.fbnd[M + c];
+      }
+    }
+  }
   // the element's own bounds (scalar limiters: flux and slope)
   double bc[2] = {a.umin, a.umax};
   if (M == 1 && a.bounds_local) {
@@ -2290,10 +2427,10 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       double fb[M];
-      limit_facet<D, PH>(a, fAl[k], ubl[k], ubc, dtl[k], dt_e, bl[k], bc, fb);
+      limit_facet<D, PH>(a, fAl[k], ubl[k], ubc, dtl[k], dt_e, bl[k], bc, fb, glo ? 1 : 0);
 #pragma unroll
       for (int c = 0; c < M; ++c) fbs[c] -= fb[c];
-      limit_facet<D, PH>(a, fAh[k], ubc, ubh[k], dt_e, dth[k], bc, bh[k], fb);
+      limit_facet<D, PH>(a, fAh[k], ubc, ubh[k], dt_e, dth[k], bc, bh[k], fb, ghi ? 2 : 0);
 #pragma unroll
       for (int c = 0; c < M; ++c) fbs[c] += fb[c];
     }
@@ -2311,15 +2448,29 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
   double hpow = 1.0;
 #pragma unroll
   for (int k = 0; k < D - 1; ++k) hpow *= h;
+  // On a boundary facet of a non-periodic line f_h . n is replaced by the
+  // boundary flux F(u_end, u_hat; n) of pass 1, whose phi_i-part element
+  // pass 1 already put into the residual vector: with g_i^e of eq. (aecb),
+  // int grad phi_i . (f(u_h) - f_h) - int (phi_i - m_i/|K|) div f_h - g_i^e
+  // = R_i - B_i + F^e / NL with B_i without that facet's term and F^e
+  // taking F(u_end, u_hat; n) for it (a point value in 1D)
   RT fb[M][NL];
+  double feb[M];
 #pragma unroll
-  for (int c = 0; c < M; ++c)
+  for (int c = 0; c < M; ++c) {
+    feb[c] = 0.0;
 #pragma unroll
     for (int i = 0; i < NL; ++i) fb[c][i] = 0;
+  }
 #pragma unroll
   for (int k = 0; k < D; ++k) {
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
+      if (D == 1 && (side ? ghi : glo)) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) feb[c] += a.fbnd[(side * 2 + 1) * M + c];
+        continue;
+      }
       const int av = side ? P : 0;
       const RT sg = (RT)(side ? hpow : -hpow);
       double fbar[M];                  // mixed form: flux of the cell average
@@ -2411,7 +2562,7 @@ __device__ __forceinline__ void k_elem2_body(const StageArgs& a, int bx) {
   }
 #pragma unroll
   for (int c = 0; c < M; ++c) {
-    RT Fe = 0;
+    RT Fe = (RT)feb[c];
 #pragma unroll
     for (int i = 0; i < NL; ++i) Fe += fb[c][i];
     RT ud[NL], mu[NL];
@@ -2504,6 +2655,14 @@ __global__ void __launch_bounds__(128) k_elem2(StageArgs a) {
 // ---------------------------------------------------------------------------
 template <int D, int P>
 __device__ inline int node_elements(int64_t i, const MeshArgs& m, int64_t* eids, int* locs) {
+  if constexpr (D == 1) {
+    // the two end nodes of a non-periodic line belong to one element each
+    if (m.bnd1d && (i == 0 || i == m.L[0] - 1)) {
+      eids[0] = i == 0 ? 0 : m.n[0] - 1;
+      locs[0] = i == 0 ? 0 : P;
+      return 1;
+    }
+  }
   int ik[3] = {0, 0, 0};
   unsigned r = (unsigned)i;                 // node ids are below 2^31
   ik[0] = (int)(r % (unsigned)m.L[0]);

@@ -222,7 +222,149 @@ void line_kernels(int p, int L, LD h, int wfast, int rfast, int sfast, int wfast
   }
 }
 
+// Rows of Mb^{-1} and Mb^{-1} Cb of a non-periodic line of nb = p ne + 1
+// nodes for the requested row indices (dense storage, band-limited LU
+// without pivoting: Mb is symmetric positive definite with half-bandwidth p).
+void bounded_line_rows(int p, int ne, LD h, const std::vector<int>& rows, std::vector<LD>& out_m,
+                       std::vector<LD>& out_g) {
+  const int nb = p * ne + 1;
+  std::vector<LD> M((size_t)nb * nb, 0.0L), C((size_t)nb * nb, 0.0L);
+  for (int e = 0; e < ne; ++e)
+    for (int a = 0; a <= p; ++a)
+      for (int b = 0; b <= p; ++b) {
+        const int i = p * e + a, j = p * e + b;
+        M[(size_t)i * nb + j] += h * gram(p, a, p, b);
+        C[(size_t)i * nb + j] += gram_deriv(p, a, 0, b, 1);   // int psi_i psi_j'
+      }
+  // LU in place (L unit lower, U upper), both within the band
+  for (int k = 0; k < nb; ++k)
+    for (int i = k + 1; i <= std::min(nb - 1, k + p); ++i) {
+      const LD f = M[(size_t)i * nb + k] / M[(size_t)k * nb + k];
+      M[(size_t)i * nb + k] = f;
+      for (int j = k + 1; j <= std::min(nb - 1, k + p); ++j) M[(size_t)i * nb + j] -= f * M[(size_t)k * nb + j];
+    }
+  const size_t nr = rows.size();
+  out_m.assign(nr * nb, 0.0L);
+  out_g.assign(nr * nb, 0.0L);
+  std::vector<LD> z(nb);
+  for (size_t r = 0; r < nr; ++r) {
+    // row i of the symmetric Mb^{-1} is the solution of Mb z = e_i
+    std::fill(z.begin(), z.end(), 0.0L);
+    z[rows[r]] = 1.0L;
+    for (int i = 1; i < nb; ++i)
+      for (int k = std::max(0, i - p); k < i; ++k) z[i] -= M[(size_t)i * nb + k] * z[k];
+    for (int i = nb - 1; i >= 0; --i) {
+      for (int k = i + 1; k <= std::min(nb - 1, i + p); ++k) z[i] -= M[(size_t)i * nb + k] * z[k];
+      z[i] /= M[(size_t)i * nb + i];
+    }
+    for (int j = 0; j < nb; ++j) {
+      out_m[r * nb + j] = z[j];
+      LD s = 0.0L;
+      for (int k = std::max(0, j - p); k <= std::min(nb - 1, j + p); ++k) s += z[k] * C[(size_t)k * nb + j];
+      out_g[r * nb + j] = s;
+    }
+  }
+}
+
 }  // namespace
+
+bool build_bounded_line(int p, int n, double h, HostTables& T) {
+  if (p < 1 || p > 4 || n < 2) return false;
+  const LD hl = (LD)h;
+  const int nb = p * n + 1;
+  // infinite-line rows: a periodic auxiliary line long enough for the
+  // periodic images to vanish, cut where both operators fall below 1e-17
+  // of their peak
+  const int Laux = ((4 * 64 + 64 + p - 1) / p) * p;
+  std::vector<LD> am, ag;
+  periodic_line_rows(p, Laux, hl, am, ag);
+  const int W = std::max(decay_width(p, Laux, am), decay_width(p, Laux, ag));
+  LD pk_m = 0.0L, pk_g = 0.0L;
+  for (LD v : am) pk_m = std::max(pk_m, std::fabs(v));
+  for (LD v : ag) pk_g = std::max(pk_g, std::fabs(v));
+  auto inf_row = [&](const std::vector<LD>& rows, int cls, int off) -> LD {
+    if (off < -W || off > W) return 0.0L;
+    return rows[(size_t)cls * Laux + ((cls + off) % Laux + Laux) % Laux];
+  };
+  // exact rows near the low end on a line of at most nx cells (the far
+  // end's influence on them is then far below rounding); the high end
+  // mirrors it but is computed directly on the same line
+  const int nx = std::min(n, (8 * W + 64) / p + 2);
+  const int nbx = p * nx + 1;
+  const int want = std::min(nbx, 3 * W + 2 * p);
+  std::vector<int> rws;
+  for (int i = 0; i < want; ++i) rws.push_back(i);
+  for (int i = 0; i < want; ++i) rws.push_back(nbx - want + i);
+  std::vector<LD> rm, rg;
+  bounded_line_rows(p, nx, hl, rws, rm, rg);
+  BoundedLine* outs[2] = {&T.bmass, &T.bgrad};
+  // the first row index from which the exact rows match the infinite ones
+  // (checked for all classes, both ends, both operators)
+  const LD tol = 4e-17L;
+  int B = W;
+  auto dev = [&](int i, bool hi_end, bool grad) {
+    const std::vector<LD>& R = grad ? rg : rm;
+    const std::vector<LD>& I = grad ? ag : am;
+    const LD pk = grad ? pk_g : pk_m;
+    const int r = hi_end ? 2 * want - 1 - i : i;    // row index in rws
+    const int row = rws[r];
+    LD mx = 0.0L;
+    for (int j = 0; j < nbx; ++j) mx = std::max(mx, std::fabs(R[(size_t)r * nbx + j] - inf_row(I, row % p, j - row)));
+    return mx / pk;
+  };
+  const bool short_line = nb <= 2 * want;
+  if (!short_line) {
+    for (; B + p <= want; ++B) {
+      bool ok = true;
+      for (int i = B; i < B + p && ok; ++i)
+        for (int e = 0; e < 2 && ok; ++e)
+          for (int g = 0; g < 2 && ok; ++g) ok = dev(i, e == 1, g == 1) <= tol;
+      if (ok) break;
+    }
+    if (B + p > want) return false;
+  }
+  for (int g = 0; g < 2; ++g) {
+    BoundedLine& K = *outs[g];
+    const std::vector<LD>& I = g ? ag : am;
+    K.W = W;
+    K.wi.assign((size_t)p * (2 * W + 1), 0.0);
+    for (int cls = 0; cls < p; ++cls)
+      for (int t = 0; t <= 2 * W; ++t) K.wi[(size_t)cls * (2 * W + 1) + t] = (double)inf_row(I, cls, t - W);
+    if (short_line) {
+      // every row exact, on the line itself
+      std::vector<int> all(nb);
+      for (int i = 0; i < nb; ++i) all[i] = i;
+      std::vector<LD> em, eg;
+      bounded_line_rows(p, n, hl, all, em, eg);
+      const std::vector<LD>& R = g ? eg : em;
+      K.blo = nb;
+      K.bhi = 0;
+      K.cw = nb;
+      K.lo.assign((size_t)nb * nb, 0.0);
+      for (size_t q = 0; q < (size_t)nb * nb; ++q) K.lo[q] = (double)R[q];
+      K.hi.clear();
+      continue;
+    }
+    const std::vector<LD>& R = g ? rg : rm;
+    const LD pk = g ? pk_g : pk_m;
+    K.blo = K.bhi = B;
+    K.cw = B + W + 1;
+    // the dropped entries of the end rows must be negligible too
+    for (int i = 0; i < B; ++i)
+      for (int j = K.cw; j < nbx; ++j)
+        if (std::fabs(R[(size_t)i * nbx + j]) > tol * pk) return false;
+    K.lo.assign((size_t)B * K.cw, 0.0);
+    K.hi.assign((size_t)B * K.cw, 0.0);
+    for (int i = 0; i < B; ++i)
+      for (int j = 0; j < K.cw; ++j) {
+        K.lo[(size_t)i * K.cw + j] = (double)R[(size_t)i * nbx + j];
+        // high block row i is line row nb - B + i; its columns nb - cw + j
+        const int r = 2 * want - B + i;          // rws[r] = nbx - B + i
+        K.hi[(size_t)i * K.cw + j] = (double)R[(size_t)r * nbx + (nbx - K.cw + j)];
+      }
+  }
+  return true;
+}
 
 bool build_tables(int d, int p, double h, const int L[3], const int wfast[5], const int rfast[5],
                   const int sfast[5], const int wfast32[5], const int sfast32[5], HostTables& T) {

@@ -31,6 +31,20 @@ struct LineKernel {
   std::vector<double> wf32;  // [P][sfast32]
 };
 
+// Line operators Mb^{-1} and Mb^{-1} Cb of a non-periodic line of
+// Nb = p n + 1 nodes (consistent 1D mass matrix and int psi_i psi_j').
+// Rows blo <= i < Nb - bhi are the infinite-line rows of node class i mod p
+// at offsets -W..W: the ends change them by less than 1e-17 of the peak.
+// The first blo rows span columns [0, cw) and the last bhi rows columns
+// [Nb - cw, Nb), exact to long-double rounding (entries dropped beyond cw
+// are below 1e-17 of the peak).  A short line keeps every row exact:
+// blo = Nb, bhi = 0, cw = Nb.
+struct BoundedLine {
+  int W = 0, blo = 0, bhi = 0, cw = 0;
+  std::vector<double> wi;       // [p][2W + 1]
+  std::vector<double> lo, hi;   // [blo][cw], [bhi][cw]
+};
+
 struct HostTables {
   int d = 0, p = 0, nl = 0, nlf = 0;
   std::vector<double> vq, dq, wq;   // [P1][P1] B_a(t_q), B_a'(t_q); [P1] weights
@@ -39,6 +53,7 @@ struct HostTables {
   std::vector<double> qp;           // packed upper triangle of the semi-norm form,
                                     // row i: Q_ii, 2 Q_i,i+1, ..., 2 Q_i,NL-1
   LineKernel kgrad[3], kmass[3];    // per axis line operators (physical h)
+  BoundedLine bgrad, bmass;         // axis 0 of a non-periodic line (1D)
 };
 
 // Build all tables for dimension d, degree p, cell size h and L_k nodes per
@@ -50,5 +65,9 @@ struct HostTables {
 // below 1e-9 of their peak)
 bool build_tables(int d, int p, double h, const int L[3], const int wfast[5], const int rfast[5],
                   const int sfast[5], const int wfast32[5], const int sfast32[5], HostTables& out);
+
+// The line operators of a non-periodic line of n cells (into T.bgrad,
+// T.bmass).  Returns false on an unsupported degree.
+bool build_bounded_line(int p, int n, double h, HostTables& T);
 
 }  // namespace cem

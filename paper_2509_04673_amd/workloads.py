@@ -16,6 +16,18 @@ Workloads (shapes of the paper's test problems):
              seeded rho, p in [0.1, 2] and velocities in [-1, 1]
   euler3d    3D Euler, unit cube, Q2: rho = 1, v = 0, p = 1e-2, p = 10
              inside a radius-0.1 ball at a seeded centre
+
+Non-periodic 1D lines (the paper's 1D boundary tests, Sec. 5.1-5.2):
+  inflow1d   linear advection on [0,1], v = 1: the step-and-bump profile of
+             the 1D advection test, inflow state 0 at x = 0, outflow at 1
+  sod1d      modified Sod shock tube on [0,1]: (1, 0.75, 1) left of the
+             interface (0.25 + seeded shift below h/4), (0.125, 0, 0.1)
+             right of it; the initial states as boundary data at both ends
+  blast1d    Woodward-Colella blast wave on [0,1]: rho = 1, v = 0, p = 1000
+             / 0.01 / 100 split at 0.1 and 0.9, reflecting walls
+  shuosher1d Shu-Osher on [-5,5]: (3.857143, 2.629369, 10.33333) left of
+             x = -4, (1 + 0.2 sin(5x), 0, 1) right of it, u_hat = u at both
+             ends
 """
 from dataclasses import dataclass, field
 import math
@@ -60,6 +72,8 @@ class Workload:
     cfl: float = 0.5
     nsteps: int = 1
     meta: dict = field(default_factory=dict)
+    # None: periodic; else ((kind, state), (kind, state)) of a 1D line's ends
+    bc: tuple = None
 
     @property
     def m(self):
@@ -74,10 +88,11 @@ class Workload:
         return self.u0.size
 
 
-def node_coords(d, p, n, lo, hi):
-    """(N, d) nodal points x_j = lo + h i / p on the periodic node lattice,
-    x fastest (node index sum_k i_k prod_{j<k} L_j)."""
-    L = [p * nk for nk in n]
+def node_coords(d, p, n, lo, hi, periodic=True):
+    """(N, d) nodal points x_j = lo + h i / p on the periodic node lattice
+    (or the p n + 1 points of a non-periodic line), x fastest (node index
+    sum_k i_k prod_{j<k} L_j)."""
+    L = [p * nk + (0 if periodic else 1) for nk in n]
     h = [(hi[k] - lo[k]) / n[k] for k in range(d)]
     axes = [lo[k] + h[k] * np.arange(L[k]) / p for k in range(d)]
     grids = np.meshgrid(*reversed(axes), indexing="ij")    # slowest first
@@ -200,3 +215,66 @@ MAKERS = dict(adv1d=adv1d, kpp2d=kpp2d, euler2d=euler2d, euler3d=euler3d)
 
 def make(name, seed=0, **kw):
     return MAKERS[name](seed=seed, **kw)
+
+
+# ---------------------------------------------------------------------------
+# non-periodic 1D lines
+# ---------------------------------------------------------------------------
+def _line_x(p, n, lo, hi):
+    return node_coords(1, p, (n,), (lo,), (hi,), periodic=False)[:, 0]
+
+
+def inflow1d(seed=0, n=128, p=1):
+    rng = SplitMix64(seed)
+    shift = 0.01 * (rng.uniform() - 0.5)
+    x = _line_x(p, n, 0.0, 1.0) - shift
+    bump = np.zeros_like(x)
+    inside = (x > 0.5) & (x < 0.9)
+    xi = x[inside]
+    bump[inside] = np.exp(10.0 + 1.0 / (0.5 - xi) + 1.0 / (xi - 0.9))
+    u = np.where((x >= 0.2) & (x <= 0.4), 1.0, bump)
+    return Workload("inflow1d", 1, p, (n,), (0.0,), (1.0,), "advection", u[None, :],
+                    velocity=(1.0, 0.0, 0.0), dt=0.0, cfl=0.5, nsteps=100,
+                    meta=dict(shift=shift, seed=seed), bc=(("state", [0.0]), ("outflow", None)))
+
+
+def _line_euler(name, p, n, lo, hi, prim, gamma, nsteps, bc_kind, meta):
+    u = _conserved(prim[0], [prim[1]], prim[2], gamma)
+    if bc_kind == "state":
+        bc = (("state", u[:, 0].copy()), ("state", u[:, -1].copy()))
+    else:
+        bc = ((bc_kind, None), (bc_kind, None))
+    return Workload(name, 1, p, (n,), (lo,), (hi,), "euler", u, gamma_gas=gamma, w_lin=1e-3,
+                    dt=0.0, cfl=0.5, nsteps=nsteps, meta=meta, bc=bc)
+
+
+def sod1d(seed=0, n=128, p=1, gamma=1.4):
+    rng = SplitMix64(seed)
+    h = 1.0 / n
+    xs = 0.25 + 0.25 * h * (rng.uniform() - 0.5)
+    x = _line_x(p, n, 0.0, 1.0)
+    left = x < xs
+    prim = (np.where(left, 1.0, 0.125), np.where(left, 0.75, 0.0), np.where(left, 1.0, 0.1))
+    return _line_euler("sod1d", p, n, 0.0, 1.0, prim, gamma, 100, "state", dict(split=xs, seed=seed))
+
+
+def blast1d(seed=0, n=1000, p=1, gamma=1.4):
+    rng = SplitMix64(seed)
+    h = 1.0 / n
+    a = 0.1 + 0.25 * h * (rng.uniform() - 0.5)
+    b = 0.9 + 0.25 * h * (rng.uniform() - 0.5)
+    x = _line_x(p, n, 0.0, 1.0)
+    pr = np.where(x < a, 1000.0, np.where(x > b, 100.0, 0.01))
+    prim = (np.ones_like(x), np.zeros_like(x), pr)
+    return _line_euler("blast1d", p, n, 0.0, 1.0, prim, gamma, 100, "wall", dict(splits=(a, b), seed=seed))
+
+
+def shuosher1d(seed=0, n=500, p=1, gamma=1.4):
+    rng = SplitMix64(seed)
+    h = 10.0 / n
+    xs = -4.0 + 0.25 * h * (rng.uniform() - 0.5)
+    x = _line_x(p, n, -5.0, 5.0)
+    left = x < xs
+    prim = (np.where(left, 3.857143, 1.0 + 0.2 * np.sin(5.0 * x)), np.where(left, 2.629369, 0.0),
+            np.where(left, 10.33333, 1.0))
+    return _line_euler("shuosher1d", p, n, -5.0, 5.0, prim, gamma, 100, "outflow", dict(split=xs, seed=seed))

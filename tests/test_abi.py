@@ -119,3 +119,65 @@ def test_line_kernel_mode_is_validated_on_the_host():
                 cem.cem_set_line_kernels(ctx, bad)
     finally:
         cem.cem_destroy(ctx)
+
+
+def _line_desc(p=2, n=10, kind=cem.EULER, bc=("state", "outflow"), state=(1.0, 0.2, 2.5)):
+    mesh, phys = _desc(d=1, p=p, n=(n,), kind=kind)
+    for s, k in enumerate(bc):
+        mesh.bc[s] = cem.BCS[k]
+        for q, v in enumerate(state):
+            mesh.bc_state[s][q] = v
+    return mesh, phys
+
+
+def test_line_create_and_sizes_on_host():
+    # a non-periodic line holds p n + 1 nodes
+    for p, n in ((1, 7), (2, 10), (3, 200)):
+        mesh, phys = _line_desc(p, n)
+        ctx = cem.cem_create(mesh, phys, cem.cem_params_default(), 0)
+        try:
+            assert cem.cem_sizes(ctx) == (p * n + 1, n, 3)
+        finally:
+            cem.cem_destroy(ctx)
+
+
+@pytest.mark.parametrize("bad", ["one_periodic", "two_d", "mixed", "subcell", "q1", "wall_scalar",
+                                 "state_pressure", "state_nan", "scalar_outside", "kind"])
+def test_line_create_rejects_invalid_boundaries(bad):
+    mesh, phys = _line_desc()
+    prm = cem.cem_params_default()
+    if bad == "one_periodic":
+        mesh.bc[1] = cem.BC_PERIODIC
+    elif bad == "two_d":
+        mesh.dim, mesh.n[1], mesh.hi[1] = 2, 10, 1.0
+    elif bad == "mixed":
+        prm.precision = cem.FP32_MIXED
+    elif bad == "subcell":
+        prm.flux_mode = cem.FLUX_SUBCELL
+    elif bad == "q1":
+        mesh, phys = _line_desc(p=1, kind=cem.ADVECTION, bc=("outflow", "outflow"))
+        prm.contrib = cem.CONTRIB_Q1
+    elif bad == "wall_scalar":
+        mesh, phys = _line_desc(kind=cem.ADVECTION, bc=("wall", "outflow"))
+    elif bad == "state_pressure":
+        mesh.bc_state[0][2] = 0.01          # E below the kinetic energy
+    elif bad == "state_nan":
+        mesh.bc_state[0][0] = float("nan")
+    elif bad == "scalar_outside":
+        mesh, phys = _line_desc(kind=cem.ADVECTION, bc=("state", "outflow"), state=(3.0,))
+        prm.u_min, prm.u_max = 0.0, 1.0
+    elif bad == "kind":
+        mesh.bc[0] = 7
+    with pytest.raises(cem.CemError) as ei:
+        cem.cem_create(mesh, phys, prm, 0)
+    assert ei.value.status == -1
+
+
+def test_batch_refuses_boundaries():
+    # (a 2D Euler batch, which the batched form supports, with boundary
+    # conditions set on its mesh)
+    mesh, phys = _desc(kind=cem.EULER)
+    mesh.bc[0] = mesh.bc[1] = cem.BC_OUTFLOW
+    with pytest.raises(cem.CemError) as ei:
+        cem.cem_batch_create([mesh], phys, cem.cem_params_default(), 0)
+    assert "periodic" in str(ei.value)

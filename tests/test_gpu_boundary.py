@@ -1,0 +1,151 @@
+"""Non-periodic 1D lines on the GPU against the oracle: the boundary term
+b_i of eq. (bidef), the boundary facet fluxes f^partial and f^L of Sec. 4,
+g_i^e of eq. (aecb), one-sided flux limiting at boundary facets (eq. 53,
+e' > E_h), absent WENO candidates and the line operators of the bounded
+mass matrix.
+
+Tolerances: one stage, relative L-infinity 1e-12 per intermediate and for
+the stage result (udot to 4 kappa(M) eps, as on periodic meshes); runs
+within the oracle's own 1-ulp sensitivity floor.  Cases span short lines
+(every line-operator row exact) and long ones (exact end blocks, infinite-
+line rows inside), every boundary kind, both physics and p = 1..3."""
+import numpy as np
+import pytest
+
+from paper_2509_04673_amd import workloads as W
+from parity_util import (announce, compare_stage, gpu_for, lumped_mass, oracle_for, rel_linf, run_both,
+                         run_tol)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def line_workload(kind, p, n, bc, seed=0, velocity=1.0):
+    """Rough data on [0, 1] (plateaus, noise, a smooth part) with the given
+    boundary kinds; prescribed states are drawn near the interior data."""
+    rng = np.random.default_rng(seed)
+    x = W.node_coords(1, p, (n,), (0.0,), (1.0,), periodic=False)[:, 0]
+    if kind == "advection":
+        u = np.sin(2 * np.pi * x) + 0.3 * rng.standard_normal(x.size) * (x > 0.5)
+        u = np.where(np.abs(x - 0.3) < 0.1, 1.5, u)
+        u = u[None]
+        st = lambda: [float(rng.uniform(-1.0, 1.8))]
+    else:
+        rho = 1.0 + 0.5 * np.exp(-30 * (x - 0.4) ** 2) + 0.4 * (x > 0.7)
+        v = 0.4 * np.sin(3 * np.pi * x) + 0.05 * rng.standard_normal(x.size)
+        pr = 1.0 + 3.0 * (x < 0.2) + 0.05 * rng.random(x.size)
+        u = W._conserved(rho, [v], pr, 1.4)
+        st = lambda: list(W._conserved(np.array([rng.uniform(0.5, 2.0)]), [np.array([rng.uniform(-0.5, 0.5)])],
+                                       np.array([rng.uniform(0.5, 3.0)]), 1.4)[:, 0])
+    bcs = tuple((k, st() if k == "state" else None) for k in bc)
+    return W.Workload(f"line_{kind}", 1, p, (n,), (0.0,), (1.0,), kind, u, velocity=(velocity, 0.0, 0.0),
+                      w_lin=1e-3, bc=bcs)
+
+
+CASES = [
+    ("adv_p1_in_out", lambda: line_workload("advection", 1, 41, ("state", "outflow"))),
+    ("adv_p2_out_in", lambda: line_workload("advection", 2, 23, ("outflow", "state"), velocity=-0.7)),
+    ("adv_p3_state_state", lambda: line_workload("advection", 3, 17, ("state", "state"), seed=2)),
+    ("adv_p1_long", lambda: line_workload("advection", 1, 400, ("state", "outflow"), seed=3)),
+    ("adv_p2_long", lambda: line_workload("advection", 2, 200, ("state", "outflow"), seed=4)),
+    ("adv_p3_long", lambda: line_workload("advection", 3, 150, ("outflow", "state"), seed=5, velocity=-1.0)),
+    ("eul_p1_state_wall", lambda: line_workload("euler", 1, 40, ("state", "wall"))),
+    ("eul_p2_wall_out", lambda: line_workload("euler", 2, 24, ("wall", "outflow"), seed=6)),
+    ("eul_p3_out_state", lambda: line_workload("euler", 3, 15, ("outflow", "state"), seed=7)),
+    ("eul_p2_long", lambda: line_workload("euler", 2, 300, ("state", "wall"), seed=8)),
+    ("eul_p2_two_cells", lambda: line_workload("euler", 2, 2, ("wall", "wall"), seed=9)),
+    ("sod_p1", lambda: W.sod1d(seed=1, n=64, p=1)),
+    ("sod_p2", lambda: W.sod1d(seed=1, n=32, p=2)),
+    ("blast_p1", lambda: W.blast1d(seed=1, n=100, p=1)),
+    ("blast_p2", lambda: W.blast1d(seed=1, n=50, p=2)),
+    ("shuosher_p2", lambda: W.shuosher1d(seed=1, n=60, p=2)),
+    ("inflow_p3", lambda: W.inflow1d(seed=1, n=30, p=3)),
+]
+
+MODES = [
+    ("method", {}),
+    ("target", dict(alpha_mode="one", beta_mode="one")),
+    ("low_order", dict(gamma_mode="zero", alpha_mode="zero", beta_mode="zero")),
+    ("shrink", dict(flux_mode="shrink")),
+]
+
+
+@pytest.mark.parametrize("mlabel,modes", MODES, ids=[m[0] for m in MODES])
+@pytest.mark.parametrize("label,make", CASES, ids=[c[0] for c in CASES])
+def test_line_stage_parity(label, make, mlabel, modes):
+    wl = make()
+    floors = None
+    if label.startswith("blast"):
+        # the blast wave starts with constant density and zero momentum: g,
+        # r and udot of those components are rounding noise on both sides
+        # (row sums of the line operators), measured against the largest
+        # component (energy)
+        floors = {"g": "whole", "r": "whole", "udot": "whole"}
+    compare_stage(wl, modes, f"{label}-{mlabel}", TOL, floors=floors)
+
+
+@pytest.mark.parametrize("label,make", [c for c in CASES if c[0].startswith(("adv", "inflow"))],
+                         ids=[c[0] for c in CASES if c[0].startswith(("adv", "inflow"))])
+def test_line_stage_parity_local_bounds(label, make):
+    wl = make()
+    errs, taps = compare_stage(wl, dict(bounds="local"), f"{label}-local", TOL)
+    # the inflow element's bounds reach its boundary data
+    assert np.all(taps["ubar"][0] >= taps["b_lo"] - 1e-12) and np.all(taps["ubar"][0] <= taps["b_hi"] + 1e-12)
+
+
+def test_line_stage_parity_at_two_thousand_nodes():
+    compare_stage(line_workload("euler", 2, 1000, ("state", "outflow"), seed=11), {}, "eul_p2_1000", TOL)
+
+
+RUNS = [
+    ("sod_p2", lambda: W.sod1d(seed=2, n=64, p=2), 30),
+    ("sod_p1", lambda: W.sod1d(seed=2, n=128, p=1), 30),
+    ("blast_p1", lambda: W.blast1d(seed=2, n=200, p=1), 30),
+    ("shuosher_p2", lambda: W.shuosher1d(seed=2, n=100, p=2), 30),
+    ("inflow_p2", lambda: W.inflow1d(seed=2, n=64, p=2), 40),
+]
+
+
+@pytest.mark.parametrize("label,make,nsteps", RUNS, ids=[r[0] for r in RUNS])
+def test_line_run_parity(label, make, nsteps):
+    wl = make()
+    err, floor, st, chk = run_both(wl, nsteps, cfl=0.5)
+    assert err <= run_tol(floor), (err, floor)
+    assert chk["violations"] == 0 == st["violations"]
+    assert not chk["cfl_violated"]
+
+
+def test_walls_conserve_mass_and_energy_on_the_gpu():
+    wl = W.blast1d(seed=3, n=400, p=2)
+    s = gpu_for(wl)
+    m = lumped_mass(oracle_for(wl))
+    before = m @ wl.u0[0], m @ wl.u0[2]
+    for _ in range(20):
+        s.step(cfl=0.5)
+    u = s.download()
+    chk = s.check()
+    s.close()
+    dm = abs(m @ u[0] - before[0]) / before[0]
+    de = abs(m @ u[2] - before[1]) / before[1]
+    announce(f"[boundary] blast p2 400 cells, 20 steps: mass drift {dm:.1e}, energy drift {de:.1e}")
+    assert dm <= 1e-13 and de <= 1e-13
+    assert chk["violations"] == 0
+
+
+def test_inflow_state_enters_the_bounds():
+    from paper_2509_04673_amd.cem import CemError
+    wl = W.inflow1d(seed=0, n=40, p=2)
+    wl.bc = (("state", [1.7]), ("outflow", None))
+    s = gpu_for(wl)                 # bounds from the state: [0, 1.7]
+    with pytest.raises(CemError):
+        s.set_bounds(0.0, 1.0)      # the inflow state would lie outside
+    s.set_bounds(0.0, 1.7)
+    for _ in range(30):
+        s.step(cfl=0.5)
+    u = s.download()
+    chk = s.check()
+    s.close()
+    assert chk["violations"] == 0 and u.max() <= 1.7 + 1e-12 and u.min() >= -1e-12
+    # the inflow state reaches the first node
+    assert abs(u[0, 0] - 1.7) < 0.2
