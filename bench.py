@@ -12,7 +12,9 @@ projected gradient, WENO sensor and residual, consistent-mass solve, facet
 fluxes with the flux limiter, element contributions with the slope limiter,
 assembly and the RK combination).  Inputs are resident in HBM when the timed
 region starts.  --workload selects the single-problem workloads (kpp2d,
-euler2d, euler3d, adv1d) and --precision mixed the mixed-precision form.
+euler2d, euler3d, adv1d; the non-periodic 1D lines sod1d, blast1d,
+shuosher1d, inflow1d, by default Q2 on 2^20 cells) and --precision mixed the
+mixed-precision form.
 
 Prints one JSON line: the throughput (HIP events around the graph-replayed
 timed region), a roofline record of the dominant kernel, the float64 oracle
@@ -318,8 +320,10 @@ def profiled_traffic(fname, dominant, dofs):
 
 
 # device kernel names behind each timing id
-DEVICE_KERNELS = {"grad_line": ["k_line_multi", "k_line_x", "k_line_y", "k_line_fast", "k_line<", "k_line("],
-                  "elem1": ["k_elem1"], "gather_r": ["k_gather"], "mass_line": ["k_line_y", "k_line_fast"],
+DEVICE_KERNELS = {"grad_line": ["k_line_multi", "k_line_x", "k_line_y", "k_line_fast", "k_line<", "k_line(",
+                                "k_line_bnd"],
+                  "elem1": ["k_elem1"], "gather_r": ["k_gather"],
+                  "mass_line": ["k_line_y", "k_line_fast", "k_line_bnd"],
                   "elem2": ["k_elem2"], "update": ["k_update"], "elem1r": ["k_resid"],
                   "stage_dt": ["k_stage_dt"]}
 
@@ -360,9 +364,14 @@ def host_info():
 
 def _oracle_for(wl):
     from oracle import Mesh, Oracle, Params, Problem
-    mesh = Mesh(wl.d, wl.p, wl.n, wl.lo, wl.hi)
+    bc = getattr(wl, "bc", None)
+    mesh = Mesh(wl.d, wl.p, wl.n, wl.lo, wl.hi, periodic=bc is None)
+    lo, hi = float(wl.u0.min()), float(wl.u0.max())
+    for kind, state in (bc or ()):
+        if kind == "state" and wl.kind != "euler":
+            lo, hi = min(lo, float(state[0])), max(hi, float(state[0]))
     prob = Problem(mesh, wl.kind, wl.velocity, wl.gamma_gas, params=Params(w_lin=wl.w_lin, q=wl.q),
-                   u_min=float(wl.u0.min()), u_max=float(wl.u0.max()))
+                   u_min=lo, u_max=hi, bc=bc)
     return Oracle(prob)
 
 
@@ -370,6 +379,7 @@ def _oracle_stages(wl, seconds, max_stages=None):
     """Whole forward-Euler stages of the oracle on one workload, one thread,
     until `seconds` have elapsed (at least one): (stages, elapsed s)."""
     from threadpoolctl import threadpool_limits
+    from oracle import CFLViolation
     with threadpool_limits(limits=1):
         orc = _oracle_for(wl)
         dt = wl.dt if wl.dt > 0 else wl.cfl * orc.max_dt(wl.u0)
@@ -377,7 +387,15 @@ def _oracle_stages(wl, seconds, max_stages=None):
         stages = 0
         t0 = time.perf_counter()
         while True:
-            u, _ = orc.fe_stage(u, dt)
+            try:
+                u, _ = orc.fe_stage(u, dt)
+            except CFLViolation:
+                # the waves sped up: a new step size from the current state
+                # (its evaluation is not counted as oracle work)
+                t1 = time.perf_counter()
+                dt = wl.cfl * orc.max_dt(u)
+                t0 += time.perf_counter() - t1
+                continue
             stages += 1
             el = time.perf_counter() - t0
             if el >= seconds or (max_stages and stages >= max_stages):
@@ -590,13 +608,21 @@ def bench_batch(args):
 # oracle samples of the single-problem workloads: the mesh of the error and
 # baseline runs where the full mesh would take the oracle minutes per stage
 SAMPLE_N = {"euler2d": 256, "euler3d": 32}
+# non-periodic lines: the timed size (Q2, 2^20 cells) and the oracle's sample
+# (Q2, 1000 cells: its dense line solves grow with the square of the nodes)
+LINE_WORKLOADS = ("sod1d", "blast1d", "shuosher1d", "inflow1d")
+LINE_BENCH = dict(n=1 << 20, p=2)
+LINE_SAMPLE = dict(n=1000, p=2)
 
 
 def bench_single(args):
     import numpy as np  # noqa: F401
     import torch
     from paper_2509_04673_amd import cem, workloads
+    line = args.workload in LINE_WORKLOADS
     kw = {} if args.n is None else dict(n=args.n)
+    if line:
+        kw = dict(LINE_BENCH, **kw)
     wl = workloads.make(args.workload, seed=0, **kw)
     mixed = args.precision == "mixed"
     print(f"[bench] workload {wl.name} d={wl.d} p={wl.p} n={wl.n} dofs={wl.dofs} "
@@ -646,6 +672,9 @@ def bench_single(args):
 
     sn = SAMPLE_N.get(wl.name) if args.n is None else None
     swl = workloads.make(args.workload, seed=0, n=sn) if sn else wl
+    if line:
+        sn = LINE_SAMPLE["n"]
+        swl = workloads.make(args.workload, seed=0, **LINE_SAMPLE)
     label = f"the {wl.name} workload" + (f" at n = {sn}" if sn else "") + f" ({swl.dofs} DOFs)"
     cpu, err = None, None
     if not args.no_cpu_baseline:
@@ -671,6 +700,7 @@ def bench_single(args):
                higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="f32+f64" if mixed else "f64", data="synthetic",
                config=dict(workload=wl.name, dim=wl.d, degree=wl.p, cells=list(wl.n),
+                           boundary=None if wl.bc is None else [b[0] for b in wl.bc],
                            dofs=wl.dofs, elements=E, physics=wl.kind, dt=wl.dt if wl.dt > 0 else None,
                            cfl=None if wl.dt > 0 else wl.cfl, seed=0, precision=args.precision,
                            wall_s=wall, violations=chk["violations"], clamped=chk["clamped"]),
@@ -686,7 +716,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="euler_batch",
-                    choices=["euler_batch", "kpp2d", "adv1d", "euler2d", "euler3d"])
+                    choices=["euler_batch", "kpp2d", "adv1d", "euler2d", "euler3d", "sod1d", "blast1d",
+                             "shuosher1d", "inflow1d"])
     ap.add_argument("--count", type=int, default=512, help="problems of the batched workload")
     ap.add_argument("--n", type=int, default=None, help="cells per axis (default: workload size)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
@@ -713,6 +744,8 @@ def main():
         if args.workload == "euler_batch":
             name = f"euler_batch_{args.count}_q2{'_mixed' if args.precision == 'mixed' else ''}_stage_kernels.md"
         else:
+            if args.workload in LINE_WORKLOADS:
+                kw = dict(LINE_BENCH, **kw)
             name = profile_name(workloads.make(args.workload, seed=0, **kw), args.precision)
         summarize_profile(args.summarize_profile, os.path.join(PROFILE_DIR, name),
                           args.profile_command, COPY_PROBE_BYTES)

@@ -486,7 +486,25 @@ cem_status launch_line_bnd(cem_ctx* c, const double* in, double* out, bool grad)
   if (!((K.blo >= K.W && K.bhi >= K.W && 2 * (int64_t)K.W < c->N && K.cw <= c->N) ||
         (K.blo == c->N && K.bhi == 0 && K.cw == c->N)))
     return fail(CEM_EINVAL, "internal: line operator blocks do not cover the line");
-  CEM_LAUNCH(c, grad ? 0 : 4, k_line_bnd, nblocks(la.total, 256), 256, 0, c->stream, la);
+  const int id = grad ? 0 : 4;
+  // long lines: LDS tiles with register-blocked runs of 2P outputs, on the
+  // padded interior rows of the periodic fast tables (the same infinite-line
+  // rows, built for the periodic line of the same cells)
+  const LineKernel& F = grad ? c->tabs.kgrad[0] : c->tabs.kmass[0];
+  if (K.blo < c->N && F.wfast == K.W && kWfast[c->p] == K.W) {
+    la.wf = tb + (grad ? c->off_kgf[0] : c->off_kmf[0]);
+    const int R = 2 * c->p, LW = 256 * R + kSfast[c->p];
+    const size_t lds = (size_t)(LW + (R % 2 == 0 ? (LW - 1) / R : 0)) * sizeof(double);
+    dim3 grid(nblocks(c->N, 256 * R), (unsigned)c->m);
+    switch (c->p) {
+      case 1: CEM_LAUNCH(c, id, (k_line_bnd_runs<1, 2>), grid, 256, lds, c->stream, la); break;
+      case 2: CEM_LAUNCH(c, id, (k_line_bnd_runs<2, 2>), grid, 256, lds, c->stream, la); break;
+      case 3: CEM_LAUNCH(c, id, (k_line_bnd_runs<3, 2>), grid, 256, lds, c->stream, la); break;
+      default: return fail(CEM_EINVAL, "no line kernel for this degree");
+    }
+  } else {
+    CEM_LAUNCH(c, id, k_line_bnd, nblocks(la.total, 256), 256, 0, c->stream, la);
+  }
   HIPCHK(hipGetLastError());
   return CEM_OK;
 }

@@ -460,42 +460,6 @@ __global__ void __launch_bounds__(256) k_line(LineArgs a) {
 // accumulators and streams R + TAPS - 1 inputs once.
 // W: half-width; runs of R = P * RE outputs, RE in {1, 2, 4} chosen per
 // launch so that small meshes still fill the chip
-// Line operators of a non-periodic 1D line (Mb^{-1} or Mb^{-1} Cb), one
-// thread per output value: the first blo and last bhi rows are exact rows
-// over the first / last cw nodes, the rows between them the infinite-line
-// rows of their node class (i mod p) at offsets -W..W.  Every access stays
-// inside the line: blo, bhi >= W, or blo = N with cw = N (short lines).
-struct BndLineArgs {
-  const double* in;     // [M][N]
-  double* out;          // [M][N]
-  const double* wi;     // [P][2W + 1]
-  const double* lo;     // [blo][cw]
-  const double* hi;     // [bhi][cw]
-  int64_t N, total;     // nodes of the line, M N
-  int P, W, blo, bhi, cw;
-};
-
-__global__ void __launch_bounds__(256) k_line_bnd(BndLineArgs a) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= a.total) return;
-  const int64_t c = q / a.N, i = q - c * a.N;
-  const double* x = a.in + c * a.N;
-  double s = 0.0;
-  if (i < a.blo) {
-    const double* w = a.lo + i * a.cw;
-    for (int j = 0; j < a.cw; ++j) s = fma(w[j], x[j], s);
-  } else if (i >= a.N - a.bhi) {
-    const double* w = a.hi + (i - (a.N - a.bhi)) * a.cw;
-    const double* xs = x + (a.N - a.cw);
-    for (int j = 0; j < a.cw; ++j) s = fma(w[j], xs[j], s);
-  } else {
-    const double* w = a.wi + (int)(i % a.P) * (2 * a.W + 1);
-    const double* xs = x + (i - a.W);
-    for (int t = 0; t <= 2 * a.W; ++t) s = fma(w[t], xs[t], s);
-  }
-  a.out[q] = s;
-}
-
 template <int P> struct LineTaps;
 constexpr int kLineMaxRE = 4;
 // S: per-class weight stride, 2W+1 taps zero padded to a multiple of every
@@ -658,6 +622,87 @@ __host__ __device__ inline int line_rows_per_block(int L, int64_t nlines, int ca
   int64_t want = (256 + runs - 1) / runs;
   if (want > nlines) want = nlines;
   return per < 1 ? 1 : (int)(want < per ? (want < 1 ? 1 : want) : per);
+}
+
+// Line operators of a non-periodic 1D line (Mb^{-1} or Mb^{-1} Cb), one
+// thread per output value: the first blo and last bhi rows are exact rows
+// over the first / last cw nodes, the rows between them the infinite-line
+// rows of their node class (i mod p) at offsets -W..W.  Every access stays
+// inside the line: blo, bhi >= W, or blo = N with cw = N (short lines).
+struct BndLineArgs {
+  const double* in;     // [M][N]
+  double* out;          // [M][N]
+  const double* wf;     // [P][S] the interior rows zero padded to the stride of the
+                        // register-blocked runs (k_line_bnd_runs), offsets -W..
+  const double* wi;     // [P][2W + 1]
+  const double* lo;     // [blo][cw]
+  const double* hi;     // [bhi][cw]
+  int64_t N, total;     // nodes of the line, M N
+  int P, W, blo, bhi, cw;
+};
+
+// output i of component c by its row (end block or interior row)
+__device__ __forceinline__ double line_bnd_row(const BndLineArgs& a, const double* x, int64_t i) {
+  double s = 0.0;
+  if (i < a.blo) {
+    const double* w = a.lo + i * a.cw;
+    for (int j = 0; j < a.cw; ++j) s = fma(w[j], x[j], s);
+  } else if (i >= a.N - a.bhi) {
+    const double* w = a.hi + (i - (a.N - a.bhi)) * a.cw;
+    const double* xs = x + (a.N - a.cw);
+    for (int j = 0; j < a.cw; ++j) s = fma(w[j], xs[j], s);
+  } else {
+    const double* w = a.wi + (int)(i % a.P) * (2 * a.W + 1);
+    const double* xs = x + (i - a.W);
+    for (int t = 0; t <= 2 * a.W; ++t) s = fma(w[t], xs[t], s);
+  }
+  return s;
+}
+
+__global__ void __launch_bounds__(256) k_line_bnd(BndLineArgs a) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.total) return;
+  const int64_t c = q / a.N, i = q - c * a.N;
+  a.out[q] = line_bnd_row(a, a.in + c * a.N, i);
+}
+
+// Long lines: a block stages 256 R + S inputs of component blockIdx.y in LDS
+// (zero outside the line) and each thread computes a run of R = P RE
+// outputs starting at a multiple of R (so output r has class r mod P).  Runs
+// that lie inside the interior rows take the register-blocked taps
+// (line_run, weights wf); runs that touch an end block compute their rows
+// one by one from global memory.  Every LDS slot read lies in the staged
+// window, every global read inside the line.
+template <int P, int RE>
+__global__ void __launch_bounds__(256) k_line_bnd_runs(BndLineArgs a) {
+  constexpr int W = LineTaps<P>::W, R = P * RE, S = LineTaps<P>::S;
+  constexpr int LW = 256 * R + S;                  // staged window
+  double* sm = reinterpret_cast<double*>(cem_smem);
+  const int64_t N = a.N;
+  const int64_t c = blockIdx.y;
+  const int64_t s0 = (int64_t)blockIdx.x * (256 * R);
+  const double* x = a.in + c * N;
+  const int64_t ws = s0 - W;                      // input of window slot 0
+  for (int k = threadIdx.x; k < LW; k += 256) {
+    const int64_t g = ws + k;
+    sm[lds_slot<R>(k)] = (g >= 0 && g < N) ? x[g] : 0.0;
+  }
+  __syncthreads();
+  const int64_t s = s0 + (int64_t)threadIdx.x * R;
+  if (s >= N) return;
+  double* y = a.out + c * N;
+  if (s >= a.blo && s + R <= N - a.bhi) {
+    // interior: x(s - W + j) = window slot threadIdx.x R + j
+    const int off = threadIdx.x * R;
+    auto ld = [&](int j) { return sm[lds_slot<R>(off + j)]; };
+    double acc[R];
+    line_run<P, RE>(a.wf, ld, acc);
+#pragma unroll
+    for (int r = 0; r < R; ++r) y[s + r] = acc[r];
+  } else {
+    for (int r = 0; r < R; ++r)
+      if (s + r < N) y[s + r] = line_bnd_row(a, x, s + r);
+  }
 }
 
 // x((k - W) mod L) of the padded row position k

@@ -278,3 +278,6 @@ def shuosher1d(seed=0, n=500, p=1, gamma=1.4):
     prim = (np.where(left, 3.857143, 1.0 + 0.2 * np.sin(5.0 * x)), np.where(left, 2.629369, 0.0),
             np.where(left, 10.33333, 1.0))
     return _line_euler("shuosher1d", p, n, -5.0, 5.0, prim, gamma, 100, "outflow", dict(split=xs, seed=seed))
+
+
+MAKERS.update(inflow1d=inflow1d, sod1d=sod1d, blast1d=blast1d, shuosher1d=shuosher1d)
