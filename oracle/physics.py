@@ -7,6 +7,8 @@ States are arrays u[c, ...] with the conserved component first.
   * KPP        f(u) = (sin u, cos u)       [KHV §5.3.2]
   * Euler      u = (rho, rho v, rho E), p = (gamma-1)(rho E - |rho v|^2/(2 rho))
                                            [KHV §5.2]
+  * nonconvex  1D, f(u) = u (1 - u) / 4 for u <= 1/2, u (u - 1) / 2 + 3/16
+               otherwise                   [KHV §5.1.2, eq. (1dkpp-flux)]
 """
 import numpy as np
 
@@ -131,6 +133,35 @@ class Euler:
         return np.maximum(np.maximum(-lam1, 0.0), np.maximum(lam3, 0.0))
 
 
+class NonConvex:
+    """The C^1 nonconvex flux of [KHV eq. (1dkpp-flux)] on a line: concave
+    below u = 1/2, convex above, f'(u) = 1/4 - u/2 and u - 1/2 on the two
+    branches."""
+
+    def __init__(self, d):
+        assert d == 1
+        self.d = d
+        self.m = 1
+
+    def flux(self, u):
+        return np.stack([np.where(u <= 0.5, 0.25 * u * (1.0 - u), 0.5 * u * (u - 1.0) + 3.0 / 16.0)])
+
+    def dflux(self, u):
+        return np.where(u <= 0.5, 0.25 - 0.5 * u, u - 0.5)
+
+    def node_speed(self, u):
+        return np.abs(self.dflux(u[0]))
+
+    def riemann_speed(self, uL, uR, axis):
+        """Largest |f'| over the states between u_L and u_R: |f'| is
+        piecewise linear with its only minimum (0) at u = 1/2, so the
+        largest value is at an end point."""
+        return np.maximum(np.abs(self.dflux(uL[0])), np.abs(self.dflux(uR[0])))
+
+    def riemann_speed_n(self, uL, uR, n):
+        return self.riemann_speed(uL, uR, 0)
+
+
 def make(kind, d, velocity=(1.0, 0.0, 0.0), gamma=1.4):
     if kind == "advection":
         return Advection(d, velocity)
@@ -138,4 +169,6 @@ def make(kind, d, velocity=(1.0, 0.0, 0.0), gamma=1.4):
         return KPP(d)
     if kind == "euler":
         return Euler(d, gamma)
+    if kind == "nonconvex":
+        return NonConvex(d)
     raise ValueError(kind)

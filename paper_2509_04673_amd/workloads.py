@@ -28,6 +28,9 @@ Non-periodic 1D lines (the paper's 1D boundary tests, Sec. 5.1-5.2):
   shuosher1d Shu-Osher on [-5,5]: (3.857143, 2.629369, 10.33333) left of
              x = -4, (1 + 0.2 sin(5x), 0, 1) right of it, u_hat = u at both
              ends
+  nonconvex1d the nonconvex flux of Sec. 5.1.2 on [0,1]: u_0 = 1 from
+             x = 1/4 (+ a seeded shift below h/4), inflow state 0 at x = 0,
+             outflow at x = 1
 """
 from dataclasses import dataclass, field
 import math
@@ -62,7 +65,7 @@ class Workload:
     n: tuple
     lo: tuple
     hi: tuple
-    kind: str                       # "advection" | "kpp" | "euler"
+    kind: str                       # "advection" | "kpp" | "euler" | "nonconvex"
     u0: np.ndarray                  # (m, N) float64, component-major, x fastest
     velocity: tuple = (1.0, 0.0, 0.0)
     gamma_gas: float = 1.4
@@ -280,4 +283,14 @@ def shuosher1d(seed=0, n=500, p=1, gamma=1.4):
     return _line_euler("shuosher1d", p, n, -5.0, 5.0, prim, gamma, 100, "outflow", dict(split=xs, seed=seed))
 
 
-MAKERS.update(inflow1d=inflow1d, sod1d=sod1d, blast1d=blast1d, shuosher1d=shuosher1d)
+def nonconvex1d(seed=0, n=128, p=1):
+    rng = SplitMix64(seed)
+    h = 1.0 / n
+    xs = 0.25 + 0.25 * h * (rng.uniform() - 0.5)
+    x = _line_x(p, n, 0.0, 1.0)
+    u = (x >= xs).astype(np.float64)
+    return Workload("nonconvex1d", 1, p, (n,), (0.0,), (1.0,), "nonconvex", u[None, :], dt=0.0, cfl=0.5,
+                    nsteps=100, meta=dict(split=xs, seed=seed), bc=(("state", [0.0]), ("outflow", None)))
+
+
+MAKERS.update(inflow1d=inflow1d, sod1d=sod1d, blast1d=blast1d, shuosher1d=shuosher1d, nonconvex1d=nonconvex1d)
