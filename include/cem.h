@@ -10,9 +10,10 @@
  *
  * Scope: uniform periodic boxes of cube cells in 1, 2 or 3 dimensions,
  * tensor-product Bernstein elements Q_p (p = 1..3, p = 1..2 in 3D), scalar
- * linear advection, the KPP flux (sin u, cos u) in 2D, and the compressible
- * Euler equations of an ideal gas; in 1D also non-periodic lines with
- * weakly imposed boundary data (cem_mesh_desc.bc).  Arithmetic is IEEE
+ * linear advection, the KPP flux (sin u, cos u) in 2D, the nonconvex flux of
+ * Sec. 5.1.2 in 1D, and the compressible Euler equations of an ideal gas; in
+ * 1D also non-periodic lines with weakly imposed boundary data
+ * (cem_mesh_desc.bc).  Arithmetic is IEEE
  * float64.
  *
  * Conventions shared by every call
@@ -53,7 +54,10 @@ typedef enum {
   CEM_EIDP = -5    /* an invariant-domain check failed beyond round-off */
 } cem_status;
 
-typedef enum { CEM_ADVECTION = 0, CEM_KPP = 1, CEM_EULER = 2 } cem_physics_kind;
+/* CEM_NONCONVEX: the 1D nonconvex flux of Sec. 5.1.2 (eq. 1dkpp-flux),
+ * f(u) = u (1 - u) / 4 for u <= 1/2, u (u - 1) / 2 + 3/16 otherwise; dim 1
+ * only (periodic or non-periodic lines). */
+typedef enum { CEM_ADVECTION = 0, CEM_KPP = 1, CEM_EULER = 2, CEM_NONCONVEX = 3 } cem_physics_kind;
 
 /* Arithmetic of a stage.  CEM_FP32_MIXED (d = 2, 3): the projected
  * gradient and mass-solve line operators, the WENO sensor (eqs. 7-8) and the

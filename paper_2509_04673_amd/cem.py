@@ -13,8 +13,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libcem.so")
 
-ADVECTION, KPP, EULER = 0, 1, 2
-KINDS = {"advection": ADVECTION, "kpp": KPP, "euler": EULER}
+ADVECTION, KPP, EULER, NONCONVEX = 0, 1, 2, 3
+KINDS = {"advection": ADVECTION, "kpp": KPP, "euler": EULER, "nonconvex": NONCONVEX}
 FP64, FP32_MIXED = 0, 1
 PRECISIONS = {"fp64": FP64, "mixed": FP32_MIXED}
 FLUX_LIMIT, FLUX_SUBCELL, FLUX_SHRINK = 0, 1, 2

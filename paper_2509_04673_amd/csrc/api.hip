@@ -1155,7 +1155,8 @@ void drop_graph(cem_ctx* c) {
 }
 
 // float64 stages for every supported (d, p, physics); the mixed-precision
-// form is built for d = 2, 3; non-periodic lines for 1D advection and Euler
+// form is built for d = 2, 3; non-periodic lines for 1D advection, Euler
+// and the nonconvex flux
 StageFn pick(int d, int p, int kind, bool mixed = false, bool bounded = false) {
   if (bounded) {
     if (d != 1 || mixed) return nullptr;
@@ -1163,6 +1164,7 @@ StageFn pick(int d, int p, int kind, bool mixed = false, bool bounded = false) {
     if (p == P && kind == PH) return &stage_line_impl<P, PH>;
     LCASE(1, ADV) LCASE(2, ADV) LCASE(3, ADV)
     LCASE(1, EUL) LCASE(2, EUL) LCASE(3, EUL)
+    LCASE(1, NCV) LCASE(2, NCV) LCASE(3, NCV)
 #undef LCASE
     return nullptr;
   }
@@ -1172,6 +1174,7 @@ StageFn pick(int d, int p, int kind, bool mixed = false, bool bounded = false) {
   if (d == D && p == P && kind == PH) return mixed ? &stage_impl<D, P, PH, float> : &stage_impl<D, P, PH, double>;
   CASE(1, 1, ADV) CASE(1, 2, ADV) CASE(1, 3, ADV)
   CASE(1, 1, EUL) CASE(1, 2, EUL) CASE(1, 3, EUL)
+  CASE(1, 1, NCV) CASE(1, 2, NCV) CASE(1, 3, NCV)
   CASEM(2, 1, ADV) CASEM(2, 2, ADV) CASEM(2, 3, ADV)
   CASEM(2, 1, KPP) CASEM(2, 2, KPP) CASEM(2, 3, KPP)
   CASEM(2, 1, EUL) CASEM(2, 2, EUL) CASEM(2, 3, EUL)

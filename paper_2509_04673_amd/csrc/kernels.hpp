@@ -15,7 +15,7 @@
 
 namespace cem {
 
-constexpr int ADV = 0, KPP = 1, EUL = 2;
+constexpr int ADV = 0, KPP = 1, EUL = 2, NCV = 3;
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 // k-th base-(p+1) digit of a local id (axis 0 fastest)
@@ -187,6 +187,33 @@ template <int D> struct Phys<D, KPP> {
   }
   __device__ static inline double riemann_speed_n(const double*, const double*, const double*, const PhysParams&) {
     return 1.0;
+  }
+};
+
+// The nonconvex flux of Sec. 5.1.2 on a line: u (1 - u) / 4 for u <= 1/2
+// (concave), u (u - 1) / 2 + 3/16 above (convex), C^1 at 1/2.  |f'| is
+// piecewise linear with its only minimum (0) at 1/2, so the largest |f'|
+// between two states is at one of them.
+template <int D> struct Phys<D, NCV> {
+  static_assert(D == 1, "the nonconvex flux is one-dimensional");
+  static constexpr int M = 1;
+  static constexpr bool kNodal = false;
+  template <class T>
+  __device__ static inline T f1(T u) {
+    return u <= (T)0.5 ? (T)0.25 * u * ((T)1 - u) : (T)0.5 * u * (u - (T)1) + (T)0.1875;
+  }
+  __device__ static inline double df(double u) { return u <= 0.5 ? 0.25 - 0.5 * u : u - 0.5; }
+  template <class T>
+  __device__ static inline void flux_all(const T* u, T* f, const PhysParams&) { f[0] = f1(u[0]); }
+  template <class T>
+  __device__ static inline void flux(int, const T* u, T* f, const PhysParams&) { f[0] = f1(u[0]); }
+  __device__ static inline double node_speed(const double* u, const PhysParams&) { return fabs(df(u[0])); }
+  __device__ static inline double riemann_speed(const double* uL, const double* uR, int, const PhysParams&) {
+    return fmax(fabs(df(uL[0])), fabs(df(uR[0])));
+  }
+  __device__ static inline double riemann_speed_n(const double* uL, const double* uR, const double*,
+                                                  const PhysParams&) {
+    return fmax(fabs(df(uL[0])), fabs(df(uR[0])));
   }
 };
 

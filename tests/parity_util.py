@@ -189,8 +189,9 @@ def compare_stage(wl, modes=None, label="", tol=1e-12, floors=None, ref=None):
     kappa(M_C) eps of its size (the perturbation bound of a linear solve;
     kappa ~ 14^d for p = 2, ~ 51^d for p = 3), whichever solver computes it:
     that tap is held to max(tol, 4 kappa eps).  beta is compared on the
-    elements whose contributions exceed 1e-12 of the largest (elsewhere they
-    are rounding noise and beta, a ratio of them, is arbitrary and inert)."""
+    elements where float64 fixes it to the tolerance: contributions above
+    1e-12 of the largest and a rounding sensitivity 4 eps |u| m / |f| below
+    the tolerance (elsewhere beta is arbitrary and inert)."""
     announce(f"[parity] stage {label} d={wl.d} p={wl.p} n={wl.n} kind={wl.kind} modes={modes}")
     orc, dt, ufe, taps = ref if ref is not None else oracle_stage(wl, modes)
     tols = {name: tol for name in STAGE_TAPS + ["u_fe"]}
@@ -210,11 +211,22 @@ def compare_stage(wl, modes=None, label="", tol=1e-12, floors=None, ref=None):
         got_t = s.tap(name).reshape(np.shape(taps[ref_name]))
         ref_t = taps[ref_name]
         if name == "beta":
-            # beta_e is a ratio of the element's contributions to its bound
-            # gaps: where the contributions are rounding noise (a constant
-            # state at a bound) any value is valid and none has an effect
+            # beta_e is a ratio of the element's bound gaps to its
+            # contributions (eq. 55, Appendix A): the gap subtracts two
+            # rounded values, so a rounding change of ubar^e moves beta by up
+            # to about 4 eps |u| m_i / |f_i^e|.  Where that exceeds
+            # the tolerance (contributions that are rounding noise, or an
+            # average at its bound to the last ulp) float64 does not fix
+            # beta, and beta f_i^e / m_i changes the state only at rounding
+            # level (u_fe is compared everywhere)
             fmax = np.max(np.abs(taps["fe"]), axis=(0, 2))
-            live = fmax > 1e-12 * max(float(np.max(fmax)), 1e-300)
+            mloc = orc.mesh.h ** orc.mesh.d / orc.mesh.nloc
+            size = np.max(np.abs(taps["ubar"]), axis=0)
+            if wl.kind != "euler":
+                size = np.maximum(size, np.maximum(np.abs(taps["b_lo"]), np.abs(taps["b_hi"])))
+            with np.errstate(divide="ignore"):
+                sens = 4.0 * np.finfo(float).eps * size * mloc / fmax
+            live = (fmax > 1e-12 * max(float(np.max(fmax)), 1e-300)) & (sens <= tols["beta"])
             got_t, ref_t = got_t[live], ref_t[live]
         errs[name] = rel_linf(got_t, ref_t, floors.get(name, 0.0))
     errs["u_fe"] = rel_linf(got, ufe, floors.get("u_fe", 0.0))

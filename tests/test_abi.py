@@ -181,3 +181,15 @@ def test_batch_refuses_boundaries():
     with pytest.raises(cem.CemError) as ei:
         cem.cem_batch_create([mesh], phys, cem.cem_params_default(), 0)
     assert "periodic" in str(ei.value)
+
+
+def test_nonconvex_flux_is_one_dimensional():
+    mesh, phys = _desc(d=1, p=2, n=(12,), kind=cem.NONCONVEX)
+    ctx = cem.cem_create(mesh, phys, cem.cem_params_default(), 0)
+    cem.cem_destroy(ctx)
+    mesh, phys = _line_desc(kind=cem.NONCONVEX, bc=("state", "outflow"), state=(0.0,))
+    ctx = cem.cem_create(mesh, phys, cem.cem_params_default(), 0)
+    cem.cem_destroy(ctx)
+    mesh, phys = _desc(d=2, kind=cem.NONCONVEX)
+    with pytest.raises(cem.CemError):
+        cem.cem_create(mesh, phys, cem.cem_params_default(), 0)

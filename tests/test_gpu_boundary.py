@@ -26,7 +26,7 @@ def line_workload(kind, p, n, bc, seed=0, velocity=1.0):
     boundary kinds; prescribed states are drawn near the interior data."""
     rng = np.random.default_rng(seed)
     x = W.node_coords(1, p, (n,), (0.0,), (1.0,), periodic=False)[:, 0]
-    if kind == "advection":
+    if kind != "euler":
         u = np.sin(2 * np.pi * x) + 0.3 * rng.standard_normal(x.size) * (x > 0.5)
         u = np.where(np.abs(x - 0.3) < 0.1, 1.5, u)
         u = u[None]
@@ -61,6 +61,9 @@ CASES = [
     ("blast_p2", lambda: W.blast1d(seed=1, n=50, p=2)),
     ("shuosher_p2", lambda: W.shuosher1d(seed=1, n=60, p=2)),
     ("inflow_p3", lambda: W.inflow1d(seed=1, n=30, p=3)),
+    ("ncv_p1", lambda: W.nonconvex1d(seed=1, n=64, p=1)),
+    ("ncv_p2_long", lambda: W.nonconvex1d(seed=1, n=200, p=2)),
+    ("ncv_p3_rough", lambda: line_workload("nonconvex", 3, 20, ("state", "outflow"), seed=12)),
 ]
 
 MODES = [
@@ -85,8 +88,8 @@ def test_line_stage_parity(label, make, mlabel, modes):
     compare_stage(wl, modes, f"{label}-{mlabel}", TOL, floors=floors)
 
 
-@pytest.mark.parametrize("label,make", [c for c in CASES if c[0].startswith(("adv", "inflow"))],
-                         ids=[c[0] for c in CASES if c[0].startswith(("adv", "inflow"))])
+@pytest.mark.parametrize("label,make", [c for c in CASES if c[0].startswith(("adv", "inflow", "ncv"))],
+                         ids=[c[0] for c in CASES if c[0].startswith(("adv", "inflow", "ncv"))])
 def test_line_stage_parity_local_bounds(label, make):
     wl = make()
     errs, taps = compare_stage(wl, dict(bounds="local"), f"{label}-local", TOL)
@@ -104,6 +107,7 @@ RUNS = [
     ("blast_p1", lambda: W.blast1d(seed=2, n=200, p=1), 30),
     ("shuosher_p2", lambda: W.shuosher1d(seed=2, n=100, p=2), 30),
     ("inflow_p2", lambda: W.inflow1d(seed=2, n=64, p=2), 40),
+    ("nonconvex_p1", lambda: W.nonconvex1d(seed=2, n=128, p=1), 40),
 ]
 
 
@@ -149,3 +153,31 @@ def test_inflow_state_enters_the_bounds():
     assert chk["violations"] == 0 and u.max() <= 1.7 + 1e-12 and u.min() >= -1e-12
     # the inflow state reaches the first node
     assert abs(u[0, 0] - 1.7) < 0.2
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_nonconvex_riemann_problem_reaches_the_entropy_solution(p):
+    # Sec. 5.1.2 with N_h = 129 to t = 1: the GPU run matches the oracle's
+    # within its 1-ulp floor, and its L1 distance to the exact entropy
+    # solution (shock from 0 to sqrt(3/8), then the rarefaction) is that of
+    # the oracle's run
+    from test_oracle_nonconvex import exact
+    wl = W.nonconvex1d(seed=0, n=128 // p, p=p)
+    orc = oracle_for(wl)
+    dt0 = 0.5 * orc.max_dt(wl.u0)
+    nsteps = int(np.ceil(1.0 / dt0))
+    err, floor, st, chk = run_both(wl, nsteps, dt=1.0 / nsteps)
+    assert err <= run_tol(floor), (err, floor)
+    assert chk["violations"] == 0
+    s = gpu_for(wl)
+    for _ in range(nsteps):
+        s.step(dt=1.0 / nsteps)
+    u = s.download()[0]
+    s.close()
+    conn = np.arange(wl.n[0])[:, None] * p + np.arange(p + 1)[None, :]
+    h = 1.0 / wl.n[0]
+    tq, wq = np.polynomial.legendre.leggauss(8)
+    ex = np.array([np.sum(wq * exact(e * h + h * (tq + 1) / 2, 1.0)) / 2 for e in range(wl.n[0])])
+    l1 = h * np.sum(np.abs(u[conn].mean(axis=1) - ex))
+    announce(f"[boundary] nonconvex Riemann problem p={p}, t = 1: L1 distance to the entropy solution {l1:.2e}")
+    assert l1 < 1.5e-2
