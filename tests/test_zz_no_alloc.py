@@ -11,7 +11,7 @@ import torch
 
 from paper_2509_04673_amd import cem
 from paper_2509_04673_amd import workloads as W
-from parity_util import announce, gpu_for, random_euler_workload, rel_linf
+from parity_util import announce, gpu_for, random_euler_workload, rel_linf, state_bounds
 
 pytestmark = pytest.mark.gpu
 
@@ -23,6 +23,7 @@ def _raw_ctx(wl, **params):
     mesh = cem.MeshDesc(d, wl.p, (ctypes.c_int * 3)(*(list(wl.n) + [1] * (3 - d))),
                         (ctypes.c_double * 3)(*(list(wl.lo) + [0.0] * (3 - d))),
                         (ctypes.c_double * 3)(*(list(wl.hi) + [1.0] * (3 - d))))
+    cem.set_mesh_bc(mesh, getattr(wl, "bc", None))
     phys = cem.PhysicsDesc(cem.KINDS[wl.kind], (ctypes.c_double * 3)(*(list(wl.velocity) + [0.0] * 3)[:3]),
                            wl.gamma_gas)
     params.setdefault("w_lin", wl.w_lin)
@@ -68,6 +69,30 @@ def test_static_step_matches_bound_step_two_calls():
             params = dict(u_min=float(wl.u0.min()), u_max=float(wl.u0.max()))
         got, need = _static_run(wl, nsteps, dt, cfl, **params)
         ref = _bound_run(wl, nsteps, dt, cfl)
+        err = rel_linf(got, ref)
+        announce(f"[no-alloc] {label}: workspace {need} B, rel Linf vs bound path {err:.1e}, "
+                 f"bitwise {np.array_equal(got, ref)}")
+        sizes.append(need)
+        assert err <= 1e-12
+        assert np.array_equal(got, ref)
+    assert sizes[1] < sizes[0]
+
+
+def test_static_step_on_non_periodic_lines():
+    # the same two-call check on lines with boundary data (the exact line
+    # operator tables travel in the static array too)
+    cases = [
+        ("sod_q2_300", W.sod1d(seed=4, n=300, p=2), 5),
+        ("inflow_q3_40", W.inflow1d(seed=4, n=40, p=3), 5),
+    ]
+    sizes = []
+    for label, wl, nsteps in cases:
+        params = {}
+        if wl.kind != "euler":
+            lo, hi = state_bounds(wl)
+            params = dict(u_min=lo, u_max=hi)
+        got, need = _static_run(wl, nsteps, 0.0, 0.5, **params)
+        ref = _bound_run(wl, nsteps, 0.0, 0.5)
         err = rel_linf(got, ref)
         announce(f"[no-alloc] {label}: workspace {need} B, rel Linf vs bound path {err:.1e}, "
                  f"bitwise {np.array_equal(got, ref)}")
