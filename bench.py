@@ -362,7 +362,7 @@ def host_info():
     return model, os.cpu_count()
 
 
-def _oracle_for(wl):
+def _oracle_for(wl, method=None):
     from oracle import Mesh, Oracle, Params, Problem
     bc = getattr(wl, "bc", None)
     mesh = Mesh(wl.d, wl.p, wl.n, wl.lo, wl.hi, periodic=bc is None)
@@ -370,18 +370,18 @@ def _oracle_for(wl):
     for kind, state in (bc or ()):
         if kind == "state" and wl.kind != "euler":
             lo, hi = min(lo, float(state[0])), max(hi, float(state[0]))
-    prob = Problem(mesh, wl.kind, wl.velocity, wl.gamma_gas, params=Params(w_lin=wl.w_lin, q=wl.q),
+    prob = Problem(mesh, wl.kind, wl.velocity, wl.gamma_gas, params=Params(w_lin=wl.w_lin, q=wl.q, **(method or {})),
                    u_min=lo, u_max=hi, bc=bc)
     return Oracle(prob)
 
 
-def _oracle_stages(wl, seconds, max_stages=None):
+def _oracle_stages(wl, seconds, max_stages=None, method=None):
     """Whole forward-Euler stages of the oracle on one workload, one thread,
     until `seconds` have elapsed (at least one): (stages, elapsed s)."""
     from threadpoolctl import threadpool_limits
     from oracle import CFLViolation
     with threadpool_limits(limits=1):
-        orc = _oracle_for(wl)
+        orc = _oracle_for(wl, method)
         dt = wl.dt if wl.dt > 0 else wl.cfl * orc.max_dt(wl.u0)
         u = wl.u0.copy()
         stages = 0
@@ -408,7 +408,7 @@ def _oracle_stage_job(wl):
     return wl.dofs * st, el
 
 
-def cpu_baseline(wls, seconds, label, all_cores=False):
+def cpu_baseline(wls, seconds, label, all_cores=False, method=None):
     """The float64 oracle timed on the host: one thread on whole stages of
     the sample workloads (in turn, until `seconds` have elapsed); with
     all_cores, also one stage of every sample problem at once in a pool of
@@ -417,7 +417,7 @@ def cpu_baseline(wls, seconds, label, all_cores=False):
     dof_stages, el = 0, 0.0
     per = max(seconds / len(wls), 1e-3)
     for w in wls:
-        st, e = _oracle_stages(w, per)
+        st, e = _oracle_stages(w, per, method=method)
         dof_stages += w.dofs * st
         el += e
     out = dict(value=dof_stages / el, unit="DOF*stage/s", cores=1, kind="oracle",
@@ -437,7 +437,7 @@ def cpu_baseline(wls, seconds, label, all_cores=False):
     return out
 
 
-def mixed_error(make_gpu_run, wls, nsteps=1):
+def mixed_error(make_gpu_run, wls, nsteps=1, method=None):
     """Relative L1 error per component (lumped masses) of the mixed form
     against the float64 oracle after nsteps SSP-RK3 steps, max over
     components and sample problems; make_gpu_run(wls, nsteps) returns the
@@ -446,7 +446,7 @@ def mixed_error(make_gpu_run, wls, nsteps=1):
     got = make_gpu_run(wls, nsteps)
     worst = 0.0
     for w, g in zip(wls, got):
-        orc = _oracle_for(w)
+        orc = _oracle_for(w, method)
         ref, _ = orc.run(w.u0.copy(), nsteps, dt=(w.dt if w.dt > 0 else None), cfl=w.cfl)
         mass = orc.mesh.multiplicity() * orc.mesh.h ** orc.mesh.d / orc.mesh.nloc
         g = np.asarray(g).reshape(ref.shape)
@@ -610,7 +610,7 @@ def bench_batch(args):
 SAMPLE_N = {"euler2d": 256, "euler3d": 32}
 # non-periodic lines: the timed size (Q2, 2^20 cells) and the oracle's sample
 # (Q2, 1000 cells: its dense line solves grow with the square of the nodes)
-LINE_WORKLOADS = ("sod1d", "blast1d", "shuosher1d", "inflow1d")
+LINE_WORKLOADS = ("sod1d", "blast1d", "shuosher1d", "inflow1d", "nonconvex1d")
 LINE_BENCH = dict(n=1 << 20, p=2)
 LINE_SAMPLE = dict(n=1000, p=2)
 
@@ -621,6 +621,8 @@ def bench_single(args):
     from paper_2509_04673_amd import cem, workloads
     line = args.workload in LINE_WORKLOADS
     kw = {} if args.n is None else dict(n=args.n)
+    if args.degree is not None:
+        kw["p"] = args.degree
     if line:
         kw = dict(LINE_BENCH, **kw)
     wl = workloads.make(args.workload, seed=0, **kw)
@@ -628,7 +630,8 @@ def bench_single(args):
     print(f"[bench] workload {wl.name} d={wl.d} p={wl.p} n={wl.n} dofs={wl.dofs} "
           f"precision={args.precision}", flush=True)
     dev = torch.device("cuda:0")
-    s = cem.Solver.from_workload(wl, device="cuda:0", precision=args.precision)
+    method = dict(bounds=args.bounds, contrib=args.contrib)
+    s = cem.Solver.from_workload(wl, device="cuda:0", precision=args.precision, **method)
     s.upload(wl.u0)
     if wl.kind != "euler":
         s.set_bounds()
@@ -679,12 +682,12 @@ def bench_single(args):
     cpu, err = None, None
     if not args.no_cpu_baseline:
         print(f"[bench] timing the oracle for ~{args.cpu_seconds:.0f} s on {label}", flush=True)
-        cpu = cpu_baseline([swl], args.cpu_seconds, label)
+        cpu = cpu_baseline([swl], args.cpu_seconds, label, method=method)
     if mixed and not args.no_error:
         def run(ws, nsteps):
             outs = []
             for w in ws:
-                ss = cem.Solver.from_workload(w, device="cuda:0", precision="mixed")
+                ss = cem.Solver.from_workload(w, device="cuda:0", precision="mixed", **method)
                 ss.upload(w.u0)
                 if w.kind != "euler":
                     ss.set_bounds()
@@ -694,7 +697,7 @@ def bench_single(args):
                 ss.close()
             return outs
         print(f"[bench] mixed-form error against the oracle (1 step, {label})", flush=True)
-        err = dict(rel_l1=mixed_error(run, [swl], 1), sample=f"{label}, one SSP-RK3 step, max over components")
+        err = dict(rel_l1=mixed_error(run, [swl], 1, method=method), sample=f"{label}, one SSP-RK3 step, max over components")
     out = dict(metric="DOF*RK-stage updates/s", value=value, unit="DOF*stage/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps,
                higher_is_better=True, scaling="weak", vs_baseline=None,
@@ -703,6 +706,7 @@ def bench_single(args):
                            boundary=None if wl.bc is None else [b[0] for b in wl.bc],
                            dofs=wl.dofs, elements=E, physics=wl.kind, dt=wl.dt if wl.dt > 0 else None,
                            cfl=None if wl.dt > 0 else wl.cfl, seed=0, precision=args.precision,
+                           bounds=args.bounds, contrib=args.contrib,
                            wall_s=wall, violations=chk["violations"], clamped=chk["clamped"]),
                roofline=roof, cpu_baseline=cpu)
     if err is not None:
@@ -717,9 +721,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="euler_batch",
                     choices=["euler_batch", "kpp2d", "adv1d", "euler2d", "euler3d", "sod1d", "blast1d",
-                             "shuosher1d", "inflow1d"])
+                             "shuosher1d", "inflow1d", "nonconvex1d"])
+    ap.add_argument("--bounds", default="global", choices=["global", "local"],
+                    help="single workloads: global or local bounds of the scalar limiters")
+    ap.add_argument("--contrib", default="aec", choices=["aec", "q1"],
+                    help="single workloads: element contributions of eq. (45) or their Q1 form (p = 1)")
     ap.add_argument("--count", type=int, default=512, help="problems of the batched workload")
     ap.add_argument("--n", type=int, default=None, help="cells per axis (default: workload size)")
+    ap.add_argument("--degree", type=int, default=None, help="single workloads: Bernstein degree p")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="fp64, or mixed: float contractions with float64 state, limiters and dt")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
