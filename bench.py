@@ -605,6 +605,78 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_line_batch(args):
+    """Many independent Euler lines (the paper's modified Sod, blast and
+    Shu-Osher problems, Q2 by default, 64..512 cells each, their own
+    boundary data) advanced together by the batched form: one launch per
+    kernel and stage, each step one HIP graph, adaptive dt per problem."""
+    import torch
+    from paper_2509_04673_amd import cem, workloads
+    p = args.degree or 2
+    wls = workloads.line_batch(seed=0, count=args.count, p=p)
+    dofs = sum(w.dofs for w in wls)
+    E = sum(w.n[0] for w in wls)
+    print(f"[bench] batched lines: {len(wls)} problems, n in [{min(w.n[0] for w in wls)}, "
+          f"{max(w.n[0] for w in wls)}], {dofs} DOFs", flush=True)
+    dev = torch.device("cuda:0")
+    b = cem.BatchSolver([(w.d, w.p, w.n, w.lo, w.hi, w.bc) for w in wls], "euler", gamma_gas=wls[0].gamma_gas,
+                        w_lin=wls[0].w_lin)
+    b.upload([w.u0 for w in wls])
+    cfl = 0.5
+    nwarm = max(1, args.warmup)
+    cem.cem_batch_set_timing(b.b, (1 << len(cem.KERNELS)) - 1)
+    b.step(cfl=cfl, nsteps=nwarm)
+    warm = cem.cem_batch_kernel_times(b.b)
+    dominant = _dominant(warm, nwarm)
+    print("[bench] warm-up kernel ms: " + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in warm.items()
+                                                   if v[1]), flush=True)
+    cem.cem_batch_set_timing(b.b, 0)
+    b.step(cfl=cfl, nsteps=1)                  # captures the graph
+    cem.cem_batch_reset_counters(b.b)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    w0 = time.perf_counter()
+    ev0.record(b.stream)
+    b.step(cfl=cfl, nsteps=args.steps)
+    ev1.record(b.stream)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    chk = b.check()
+    cem.cem_batch_set_timing(b.b, 1 << cem.KERNELS.index(dominant))
+    b.step(cfl=cfl, nsteps=max(1, min(args.steps, 10)))
+    kt = cem.cem_batch_kernel_times(b.b)
+    cem.cem_batch_set_timing(b.b, 0)
+    b.close()
+    value = dofs * 3 * args.steps / (ms * 1e-3)
+    wlb = workloads.Workload("line_batch", 1, p, (args.count,), (0.0,), (1.0,), "euler", wls[0].u0[:, :1])
+    pname = f"line_batch_{args.count}_q{p}_stage_kernels.md"
+    roof = roofline_record(dominant, kt, wlb, dofs, E, value, False, pname)
+    # the oracle on one problem of each kind at the smallest, middle and
+    # largest size of the batch
+    order = sorted(range(len(wls)), key=lambda k: wls[k].n[0])
+    pick = []
+    for kind in range(3):
+        ks = [k for k in order if k % 3 == kind]
+        pick.append(ks[[0, len(ks) // 2, -1][kind]])
+    sample = [wls[k] for k in pick]
+    label = "one Sod, blast and Shu-Osher line of the batch (n = " + ", ".join(str(w.n[0]) for w in sample) + ")"
+    cpu = None
+    if not args.no_cpu_baseline:
+        print(f"[bench] timing the oracle for ~{args.cpu_seconds:.0f} s on {label}", flush=True)
+        cpu = cpu_baseline(sample, args.cpu_seconds, label)
+        cpu["extrapolated_full_batch_s_per_stage"] = dofs / cpu["value"]
+    out = dict(metric="DOF*RK-stage updates/s", value=value, unit="DOF*stage/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload="line_batch", problems=args.count, dim=1, degree=p, dofs=dofs, elements=E,
+                           physics="euler", boundary="state / wall / outflow by problem", cfl=cfl, seed=0,
+                           precision="fp64", wall_s=wall, violations=int(sum(c["violations"] for c in chk)),
+                           rho_min=min(c["rho_min"] for c in chk), p_min=min(c["p_min"] for c in chk)),
+               roofline=roof, cpu_baseline=cpu)
+    print(json.dumps(out), flush=True)
+
+
 # oracle samples of the single-problem workloads: the mesh of the error and
 # baseline runs where the full mesh would take the oracle minutes per stage
 SAMPLE_N = {"euler2d": 256, "euler3d": 32}
@@ -720,13 +792,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="euler_batch",
-                    choices=["euler_batch", "kpp2d", "adv1d", "euler2d", "euler3d", "sod1d", "blast1d",
-                             "shuosher1d", "inflow1d", "nonconvex1d"])
+                    choices=["euler_batch", "line_batch", "kpp2d", "adv1d", "euler2d", "euler3d", "sod1d",
+                             "blast1d", "shuosher1d", "inflow1d", "nonconvex1d"])
     ap.add_argument("--bounds", default="global", choices=["global", "local"],
                     help="single workloads: global or local bounds of the scalar limiters")
     ap.add_argument("--contrib", default="aec", choices=["aec", "q1"],
                     help="single workloads: element contributions of eq. (45) or their Q1 form (p = 1)")
-    ap.add_argument("--count", type=int, default=512, help="problems of the batched workload")
+    ap.add_argument("--count", type=int, default=None,
+                    help="problems of the batched workload (euler_batch 512, line_batch 4096)")
     ap.add_argument("--n", type=int, default=None, help="cells per axis (default: workload size)")
     ap.add_argument("--degree", type=int, default=None, help="single workloads: Bernstein degree p")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
@@ -744,6 +817,8 @@ def main():
                     help="write the rocprofv3 summary of DIR/{stats,fetch,write,copy_fetch,copy_write}")
     ap.add_argument("--profile-command", default="", help="command text recorded in the summary")
     args = ap.parse_args()
+    if args.count is None:
+        args.count = 4096 if args.workload == "line_batch" else 512
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
@@ -752,6 +827,8 @@ def main():
         kw = {} if args.n is None else dict(n=args.n)
         if args.workload == "euler_batch":
             name = f"euler_batch_{args.count}_q2{'_mixed' if args.precision == 'mixed' else ''}_stage_kernels.md"
+        elif args.workload == "line_batch":
+            name = f"line_batch_{args.count}_q{args.degree or 2}_stage_kernels.md"
         else:
             if args.workload in LINE_WORKLOADS:
                 kw = dict(LINE_BENCH, **kw)
@@ -767,6 +844,8 @@ def main():
         sys.exit(2)
     if args.workload == "euler_batch":
         bench_batch(args)
+    elif args.workload == "line_batch":
+        bench_line_batch(args)
     else:
         bench_single(args)
 

@@ -488,16 +488,20 @@ class BatchSolver:
     one concatenated torch tensor (problem k at offsets[k]:offsets[k+1])."""
 
     def __init__(self, problems, kind, velocity=(1.0, 0.0, 0.0), gamma_gas=1.4, device="cuda:0", **params):
-        """problems: list of (d, p, n, lo, hi)."""
+        """problems: list of (d, p, n, lo, hi) or (d, p, n, lo, hi, bc), bc
+        the boundary conditions of a 1D line (see set_mesh_bc)."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
         meshes = []
-        for d, p, n, lo, hi in problems:
-            meshes.append(MeshDesc(d, p, (ctypes.c_int * 3)(*(list(n) + [1] * (3 - d))),
-                                   (ctypes.c_double * 3)(*(list(lo) + [0.0] * (3 - d))),
-                                   (ctypes.c_double * 3)(*(list(hi) + [1.0] * (3 - d)))))
+        for prob in problems:
+            d, p, n, lo, hi = prob[:5]
+            mesh = MeshDesc(d, p, (ctypes.c_int * 3)(*(list(n) + [1] * (3 - d))),
+                            (ctypes.c_double * 3)(*(list(lo) + [0.0] * (3 - d))),
+                            (ctypes.c_double * 3)(*(list(hi) + [1.0] * (3 - d))))
+            set_mesh_bc(mesh, prob[5] if len(prob) > 5 else None)
+            meshes.append(mesh)
         phys = PhysicsDesc(KINDS[kind], (ctypes.c_double * 3)(*(list(velocity) + [0.0] * 3)[:3]), gamma_gas)
         prm = make_params(params)
         self.count = len(problems)

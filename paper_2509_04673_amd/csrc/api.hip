@@ -122,7 +122,7 @@ struct cem_ctx {
 
 // batched form: launches of one stage over all problems (see kernels_batch.hpp)
 enum BKind { B_LINE, B_LINE_X, B_LINE_Y, B_LINE_MX, B_LINE_MY, B_STAGE_DT, B_ELEM1_TILE, B_ELEM1_TILE2, B_ELEM1_SYS, B_RESID_SYS, B_GATHER_LX,
-             B_GATHER_R, B_ELEM2, B_ELEM2_SYS, B_UPDATE };
+             B_GATHER_R, B_ELEM2, B_ELEM2_SYS, B_UPDATE, B_LINE_BND, B_LINE_BND_RUNS, B_ELEM1 };
 
 struct BLaunch {
   int kind = 0;
@@ -463,12 +463,13 @@ cem_status launch_line(cem_ctx* c, const TI* in, TO* out, int axis, bool grad) {
   return CEM_OK;
 }
 
-// a line operator of a non-periodic line (grad: Mb^{-1} Cb, else Mb^{-1})
-cem_status launch_line_bnd(cem_ctx* c, const double* in, double* out, bool grad) {
+// arguments of a line operator of a non-periodic line (grad: Mb^{-1} Cb,
+// else Mb^{-1}); false when its blocks would not cover the line
+bool bnd_line_args(const cem_ctx* c, const double* in, double* out, bool grad, BndLineArgs& la) {
   const BoundedLine& K = grad ? c->tabs.bgrad : c->tabs.bmass;
   const size_t* off = grad ? c->off_bg : c->off_bm;
   const double* tb = c->W<double>(c->o_tab);
-  BndLineArgs la{};
+  la = BndLineArgs{};
   la.in = in;
   la.out = out;
   la.wi = tb + off[0];
@@ -483,8 +484,15 @@ cem_status launch_line_bnd(cem_ctx* c, const double* in, double* out, bool grad)
   la.cw = K.cw;
   // the kernel's reads stay in the line: end blocks of at least W rows, or
   // one exact block over the whole line
-  if (!((K.blo >= K.W && K.bhi >= K.W && 2 * (int64_t)K.W < c->N && K.cw <= c->N) ||
-        (K.blo == c->N && K.bhi == 0 && K.cw == c->N)))
+  return (K.blo >= K.W && K.bhi >= K.W && 2 * (int64_t)K.W < c->N && K.cw <= c->N) ||
+         (K.blo == c->N && K.bhi == 0 && K.cw == c->N);
+}
+
+cem_status launch_line_bnd(cem_ctx* c, const double* in, double* out, bool grad) {
+  const BoundedLine& K = grad ? c->tabs.bgrad : c->tabs.bmass;
+  const double* tb = c->W<double>(c->o_tab);
+  BndLineArgs la;
+  if (!bnd_line_args(c, in, out, grad, la))
     return fail(CEM_EINVAL, "internal: line operator blocks do not cover the line");
   const int id = grad ? 0 : 4;
   // long lines: LDS tiles with register-blocked runs of 2P outputs, on the
@@ -809,6 +817,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     std::vector<StageArgs> sa;
     std::vector<LineFastArgs> lf;
     std::vector<LineArgs> la;
+    std::vector<BndLineArgs> bl;
   };
   auto close = [&](Group& g, std::vector<BLaunch>& out) {
     if (g.first.size() <= 1) return;
@@ -818,6 +827,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     if (!g.sa.empty()) g.l.o_args = put(g.sa.data(), g.sa.size() * sizeof(StageArgs));
     if (!g.lf.empty()) (g.sa.empty() ? g.l.o_args : g.l.o_args2) = put(g.lf.data(), g.lf.size() * sizeof(LineFastArgs));
     if (!g.la.empty()) g.l.o_args = put(g.la.data(), g.la.size() * sizeof(LineArgs));
+    if (!g.bl.empty()) g.l.o_args = put(g.bl.data(), g.bl.size() * sizeof(BndLineArgs));
     out.push_back(g.l);
   };
   // one line pass of every problem (axis k), grouped by kernel variant
@@ -825,7 +835,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
                    auto dst_of) -> cem_status {
     // runs of 2P wherever the line allows (the whole batch fills the chip,
     // so the strided tiles are as long as 40 KB of LDS allows)
-    Group gx[2], gy[2], gg, gm;
+    Group gx[2], gy[2], gg, gm, gb, gbr;
     for (int v = 0; v < 2; ++v) {
       gx[v].l.kind = B_LINE_X;
       gy[v].l.kind = B_LINE_Y;
@@ -836,11 +846,32 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     gg.l.grad = grad;
     gm.l.kind = k == 0 ? B_LINE_MX : B_LINE_MY;
     gm.l.grad = grad;
+    gb.l.kind = B_LINE_BND;
+    gb.l.grad = grad;
+    gbr.l.kind = B_LINE_BND_RUNS;
+    gbr.l.grad = grad;
     for (cem_ctx* c : probs) {
       const LineKernel& K = grad ? c->tabs.kgrad[k] : c->tabs.kmass[k];
       const void* in = src_of(c);
       void* out_p = dst_of(c);
-      if (K.wfast > 0 && b->line_mfma) {
+      if (c->bounded) {
+        // non-periodic lines (float64): LDS tiles of runs on long lines,
+        // one output per thread on short ones (every row exact)
+        BndLineArgs a;
+        if (!bnd_line_args(c, static_cast<const double*>(in), static_cast<double*>(out_p), grad, a))
+          return fail(CEM_EINVAL, "internal: line operator blocks do not cover the line");
+        const BoundedLine& BK = grad ? c->tabs.bgrad : c->tabs.bmass;
+        if (BK.blo < c->N && K.wfast == BK.W && kWfast[P] == BK.W) {
+          a.wf = c->W<double>(c->o_tab) + (grad ? c->off_kgf[0] : c->off_kmf[0]);
+          constexpr int R = 2 * P, LW = 256 * R + LineTaps<P>::S;
+          gbr.bl.push_back(a);
+          gbr.first.push_back(gbr.first.back() + (int)nblocks(c->N, 256 * R) * c->m);
+          gbr.l.lds = (size_t)(LW + (R % 2 == 0 ? (LW - 1) / R : 0)) * sizeof(double);
+        } else {
+          gb.bl.push_back(a);
+          gb.first.push_back(gb.first.back() + (int)nblocks(a.total, 256));
+        }
+      } else if (K.wfast > 0 && b->line_mfma) {
         // matrix-core blocks of 16 whole lines (the batch fills the chip)
         LineFastArgs a = line_args<RT>(c, in, out_p, k, grad, false);
         a.ky = line_mfma_chunks(a.ntrans, a.L, 0);
@@ -895,6 +926,8 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     }
     close(gm, out);
     close(gg, out);
+    close(gb, out);
+    close(gbr, out);
     return CEM_OK;
   };
   auto gbuf = [&](cem_ctx* c) -> RT* { return c->W<RT>(MIX ? c->o_g32 : c->o_g); };
@@ -904,7 +937,7 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
     return c->W<RT>(i == 0 ? (MIX ? c->o_tmp32 : c->o_tmp) : (MIX ? c->o_tmp2_32 : c->o_tmp2));
   };
   // mass pass k of problem c: (source, destination) as in the single-problem stage
-  auto fused = [&](cem_ctx* c) { return c->tabs.kmass[0].wfast > 0 && c->L[0] <= 4096; };
+  auto fused = [&](cem_ctx* c) { return !c->bounded && c->tabs.kmass[0].wfast > 0 && c->L[0] <= 4096; };
   auto mass_dst = [&](cem_ctx* c, int k) -> RT* { return k == D - 1 ? ubuf(c) : tbuf(c, k % 2); };
   auto mass_src = [&](cem_ctx* c, int k) -> const RT* { return k == 0 ? rbuf(c) : mass_dst(c, k - 1); };
   for (int st = 0; st < 3; ++st) {
@@ -934,8 +967,10 @@ cem_status batch_plan(cem_batch* b, double dt, double cfl) {
         using TT = Tile2<P, M>;
         g.l.kind = tile2_roles<PH>() ? B_ELEM1_TILE2 : B_ELEM1_TILE;
         g.l.lds = (TT::words + (tile2_roles<PH>() ? 256 : 0)) * sizeof(double);
+      } else if constexpr (D == 1) {
+        g.l.kind = B_ELEM1;
       } else {
-        return fail(CEM_EINVAL, "batched form: 2D problems or 3D Euler only");
+        return fail(CEM_EINVAL, "batched form: 1D lines, 2D problems or 3D Euler only");
       }
       for (int q = 0; q < b->count; ++q) {
         g.sa.push_back(sa[q]);
@@ -1120,6 +1155,18 @@ cem_status batch_stage(cem_batch* b, int st, hipStream_t stream) {
       case B_UPDATE:
         CEM_LAUNCH(c0, 6, (kb_update<D, P, PH>), g, dim3(256), 0, stream, sa, mp);
         break;
+      case B_LINE_BND:
+        CEM_LAUNCH(c0, LID, kb_line_bnd, g, dim3(256), 0, stream,
+                   reinterpret_cast<const BndLineArgs*>(base + l.o_args), mp);
+        break;
+      case B_LINE_BND_RUNS:
+        if constexpr (D == 1 && !MIX)
+          CEM_LAUNCH(c0, LID, (kb_line_bnd_runs<P, 2>), g, dim3(256), l.lds, stream,
+                     reinterpret_cast<const BndLineArgs*>(base + l.o_args), mp);
+        break;
+      case B_ELEM1:
+        if constexpr (D == 1) CEM_LAUNCH(c0, 1, (kb_elem1<D, P, PH, true, RT>), g, dim3(128), 0, stream, sa, mp);
+        break;
       default:
         return fail(CEM_EINVAL, "batched form: unknown launch");
     }
@@ -1133,12 +1180,21 @@ struct BatchFns {
   cem_status (*stage)(cem_batch*, int, hipStream_t);
 };
 
-// the batched form covers 2D problems (every physics) and 3D Euler
+// the batched form covers 1D problems (float64, periodic or non-periodic
+// lines), 2D problems (every physics) and 3D Euler
 BatchFns pick_batch(int d, int p, int kind, bool mixed) {
 #define BCASE(D, P, PH)                                                                 \
   if (d == D && p == P && kind == PH)                                                   \
     return mixed ? BatchFns{&batch_plan<D, P, PH, float>, &batch_stage<D, P, PH, float>} \
                  : BatchFns{&batch_plan<D, P, PH, double>, &batch_stage<D, P, PH, double>};
+  // 1D (periodic or non-periodic lines) in float64
+#define BCASE1(P, PH)                              \
+  if (d == 1 && p == P && kind == PH && !mixed)    \
+    return BatchFns{&batch_plan<1, P, PH, double>, &batch_stage<1, P, PH, double>};
+  BCASE1(1, ADV) BCASE1(2, ADV) BCASE1(3, ADV)
+  BCASE1(1, EUL) BCASE1(2, EUL) BCASE1(3, EUL)
+  BCASE1(1, NCV) BCASE1(2, NCV) BCASE1(3, NCV)
+#undef BCASE1
   BCASE(2, 1, ADV) BCASE(2, 2, ADV) BCASE(2, 3, ADV)
   BCASE(2, 1, KPP) BCASE(2, 2, KPP) BCASE(2, 3, KPP)
   BCASE(2, 1, EUL) BCASE(2, 2, EUL) BCASE(2, 3, EUL)
@@ -1717,7 +1773,7 @@ cem_status cem_batch_create(int count, const cem_mesh_desc* meshes, const cem_ph
   const int d = meshes[0].dim, p = meshes[0].degree;
   const bool mixed = prm->precision == CEM_FP32_MIXED;
   if (!pick_batch(d, p, phys->kind, mixed).plan)
-    return fail(CEM_EINVAL, "batched form: 2D problems or 3D Euler only");
+    return fail(CEM_EINVAL, "batched form: 1D problems in float64, 2D problems or 3D Euler only");
   if (prm->contrib == CEM_CONTRIB_Q1)
     return fail(CEM_EINVAL, "batched form: the Q1 contributions run on single problems");
   cem_batch* b = new cem_batch();
@@ -1730,10 +1786,6 @@ cem_status cem_batch_create(int count, const cem_mesh_desc* meshes, const cem_ph
   b->uoff.assign(1, 0);
   size_t ws = 0;
   for (int k = 0; k < count; ++k) {
-    if (meshes[k].bc[0] != CEM_BC_PERIODIC || meshes[k].bc[1] != CEM_BC_PERIODIC) {
-      cem_batch_destroy(b);
-      return fail(CEM_EINVAL, "batched form: periodic meshes only");
-    }
     if (meshes[k].dim != d || meshes[k].degree != p) {
       cem_batch_destroy(b);
       return fail(CEM_EINVAL, "batched form: every problem needs the same dimension and degree");

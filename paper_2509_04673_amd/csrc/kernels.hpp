@@ -195,7 +195,7 @@ template <int D> struct Phys<D, KPP> {
 // piecewise linear with its only minimum (0) at 1/2, so the largest |f'|
 // between two states is at one of them.
 template <int D> struct Phys<D, NCV> {
-  static_assert(D == 1, "the nonconvex flux is one-dimensional");
+  // (instantiated with D = 1 only: the dispatch offers it on lines)
   static constexpr int M = 1;
   static constexpr bool kNodal = false;
   template <class T>
@@ -668,46 +668,52 @@ struct BndLineArgs {
   int P, W, blo, bhi, cw;
 };
 
-// output i of component c by its row (end block or interior row)
-__device__ __forceinline__ double line_bnd_row(const BndLineArgs& a, const double* x, int64_t i) {
-  double s = 0.0;
-  if (i < a.blo) {
-    const double* w = a.lo + i * a.cw;
-    for (int j = 0; j < a.cw; ++j) s = fma(w[j], x[j], s);
-  } else if (i >= a.N - a.bhi) {
-    const double* w = a.hi + (i - (a.N - a.bhi)) * a.cw;
-    const double* xs = x + (a.N - a.cw);
-    for (int j = 0; j < a.cw; ++j) s = fma(w[j], xs[j], s);
-  } else {
-    const double* w = a.wi + (int)(i % a.P) * (2 * a.W + 1);
-    const double* xs = x + (i - a.W);
-    for (int t = 0; t <= 2 * a.W; ++t) s = fma(w[t], xs[t], s);
+// sum_j w[j] x[j], j < n, in four interleaved partial sums (independent
+// loads and FMAs in flight: the end-block rows are long serial loops)
+__device__ __forceinline__ double dot4(const double* w, const double* x, int n) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = 0;
+  for (; j + 4 <= n; j += 4) {
+    s0 = fma(w[j], x[j], s0);
+    s1 = fma(w[j + 1], x[j + 1], s1);
+    s2 = fma(w[j + 2], x[j + 2], s2);
+    s3 = fma(w[j + 3], x[j + 3], s3);
   }
-  return s;
+  for (; j < n; ++j) s0 = fma(w[j], x[j], s0);
+  return (s0 + s1) + (s2 + s3);
 }
 
-__global__ void __launch_bounds__(256) k_line_bnd(BndLineArgs a) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// output i of component c by its row (end block or interior row)
+__device__ __forceinline__ double line_bnd_row(const BndLineArgs& a, const double* x, int64_t i) {
+  if (i < a.blo) return dot4(a.lo + i * a.cw, x, a.cw);
+  if (i >= a.N - a.bhi) return dot4(a.hi + (i - (a.N - a.bhi)) * a.cw, x + (a.N - a.cw), a.cw);
+  return dot4(a.wi + (int)(i % a.P) * (2 * a.W + 1), x + (i - a.W), 2 * a.W + 1);
+}
+
+__device__ __forceinline__ void k_line_bnd_body(const BndLineArgs& a, int bx) {
+  const int64_t q = (int64_t)bx * blockDim.x + threadIdx.x;
   if (q >= a.total) return;
   const int64_t c = q / a.N, i = q - c * a.N;
   a.out[q] = line_bnd_row(a, a.in + c * a.N, i);
 }
 
+__global__ void __launch_bounds__(256) k_line_bnd(BndLineArgs a) { k_line_bnd_body(a, blockIdx.x); }
+
 // Long lines: a block stages 256 R + S inputs of component blockIdx.y in LDS
 // (zero outside the line) and each thread computes a run of R = P RE
 // outputs starting at a multiple of R (so output r has class r mod P).  Runs
 // that lie inside the interior rows take the register-blocked taps
-// (line_run, weights wf); runs that touch an end block compute their rows
-// one by one from global memory.  Every LDS slot read lies in the staged
-// window, every global read inside the line.
+// (line_run, weights wf); the rows of runs that touch an end block are then
+// spread over the block, one row per thread, from global memory.  Every LDS
+// slot read lies in the staged window, every global read inside the line.
 template <int P, int RE>
-__global__ void __launch_bounds__(256) k_line_bnd_runs(BndLineArgs a) {
+__device__ __forceinline__ void k_line_bnd_runs_body(const BndLineArgs& a, int bx, int by) {
   constexpr int W = LineTaps<P>::W, R = P * RE, S = LineTaps<P>::S;
   constexpr int LW = 256 * R + S;                  // staged window
   double* sm = reinterpret_cast<double*>(cem_smem);
   const int64_t N = a.N;
-  const int64_t c = blockIdx.y;
-  const int64_t s0 = (int64_t)blockIdx.x * (256 * R);
+  const int64_t c = by;
+  const int64_t s0 = (int64_t)bx * (256 * R);
   const double* x = a.in + c * N;
   const int64_t ws = s0 - W;                      // input of window slot 0
   for (int k = threadIdx.x; k < LW; k += 256) {
@@ -716,9 +722,9 @@ __global__ void __launch_bounds__(256) k_line_bnd_runs(BndLineArgs a) {
   }
   __syncthreads();
   const int64_t s = s0 + (int64_t)threadIdx.x * R;
-  if (s >= N) return;
   double* y = a.out + c * N;
-  if (s >= a.blo && s + R <= N - a.bhi) {
+  auto interior_run = [&](int64_t rs) { return rs >= a.blo && rs + R <= N - a.bhi; };
+  if (s < N && interior_run(s)) {
     // interior: x(s - W + j) = window slot threadIdx.x R + j
     const int off = threadIdx.x * R;
     auto ld = [&](int j) { return sm[lds_slot<R>(off + j)]; };
@@ -726,10 +732,18 @@ __global__ void __launch_bounds__(256) k_line_bnd_runs(BndLineArgs a) {
     line_run<P, RE>(a.wf, ld, acc);
 #pragma unroll
     for (int r = 0; r < R; ++r) y[s + r] = acc[r];
-  } else {
-    for (int r = 0; r < R; ++r)
-      if (s + r < N) y[s + r] = line_bnd_row(a, x, s + r);
   }
+  // the rows of the other runs of the tile, one per thread
+  const int64_t te = s0 + 256 * R < N ? s0 + 256 * R : N;
+  for (int64_t i = s0 + threadIdx.x; i < te; i += 256) {
+    const int64_t rs = s0 + ((i - s0) / R) * R;
+    if (!interior_run(rs)) y[i] = line_bnd_row(a, x, i);
+  }
+}
+
+template <int P, int RE>
+__global__ void __launch_bounds__(256) k_line_bnd_runs(BndLineArgs a) {
+  k_line_bnd_runs_body<P, RE>(a, blockIdx.x, blockIdx.y);
 }
 
 // x((k - W) mod L) of the padded row position k
@@ -2186,11 +2200,16 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
 }
 
 template <int D, int P, int PH, bool WS, class RT>
-__global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_elem1_body(const StageArgs& a, int bx) {
+  const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
   double dt_e = 1.0e300;
   if (e < a.mesh.E) dt_e = elem1_body<D, P, PH, WS, RT>(a, e, GlobalNodes<D, P, Phys<D, PH>::M>(a, e));
-  block_min_dt(a.dtpart, dt_e, blockIdx.x);     // every thread of the block reaches this
+  block_min_dt(a.dtpart, dt_e, bx);     // every thread of the block reaches this
+}
+
+template <int D, int P, int PH, bool WS, class RT>
+__global__ void __launch_bounds__(128) k_elem1(StageArgs a) {
+  k_elem1_body<D, P, PH, WS, RT>(a, blockIdx.x);
 }
 
 // 2D element pass on a 16 x 8 element tile: the block first stages the

@@ -63,6 +63,32 @@ __global__ void __launch_bounds__(256) kb_line_mfma(const LineFastArgs* __restri
   k_line_mfma_body<P, AX0, TI, TO>(args[pid], lb % gx, lb / gx);
 }
 
+// line operators of non-periodic lines (one output per thread)
+__global__ void __launch_bounds__(256) kb_line_bnd(const BndLineArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_line_bnd_body(args[pid], lb);
+}
+
+// the LDS-tiled runs of long non-periodic lines: local block lb -> (tile
+// lb % gx along the line, component lb / gx), gx tiles of 256 R outputs
+template <int P, int RE>
+__global__ void __launch_bounds__(256) kb_line_bnd_runs(const BndLineArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  const BndLineArgs& a = args[pid];
+  const int gx = (int)((a.N + 256 * P * RE - 1) / (256 * P * RE));
+  k_line_bnd_runs_body<P, RE>(a, lb % gx, lb / gx);
+}
+
+// element pass 1 with one thread per element (1D)
+template <int D, int P, int PH, bool WS, class RT>
+__global__ void __launch_bounds__(128) kb_elem1(const StageArgs* __restrict__ args, BatchMap m) {
+  int lb;
+  const int pid = batch_find(m, blockIdx.x, &lb);
+  k_elem1_body<D, P, PH, WS, RT>(args[pid], lb);
+}
+
 // the stage dt of every problem: one block per problem
 __global__ void __launch_bounds__(1024) kb_stage_dt(const StageArgs* __restrict__ args, BatchMap m) {
   int lb;

@@ -31,6 +31,8 @@ Non-periodic 1D lines (the paper's 1D boundary tests, Sec. 5.1-5.2):
   nonconvex1d the nonconvex flux of Sec. 5.1.2 on [0,1]: u_0 = 1 from
              x = 1/4 (+ a seeded shift below h/4), inflow state 0 at x = 0,
              outflow at x = 1
+  line_batch many Sod, blast and Shu-Osher lines of 64..512 cells (the
+             batched form)
 """
 from dataclasses import dataclass, field
 import math
@@ -294,3 +296,19 @@ def nonconvex1d(seed=0, n=128, p=1):
 
 
 MAKERS.update(inflow1d=inflow1d, sod1d=sod1d, blast1d=blast1d, shuosher1d=shuosher1d, nonconvex1d=nonconvex1d)
+
+
+def line_batch(seed=0, count=4096, p=2):
+    """Many independent Euler lines of the paper's 1D boundary tests for
+    the batched form: problem k is the modified Sod tube, the blast wave or
+    the Shu-Osher problem (k mod 3) on n_k = 64 + floor(449 U) cells drawn
+    from splitmix64 (seed), its own data seeded with k."""
+    rng = SplitMix64(seed)
+    makers = (sod1d, blast1d, shuosher1d)
+    out = []
+    for k in range(count):
+        n = 64 + int(449 * rng.uniform())
+        w = makers[k % 3](seed=k, n=n, p=p)
+        w.name = f"line_batch[{k}]:{w.name}"
+        out.append(w)
+    return out
