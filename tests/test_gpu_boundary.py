@@ -13,8 +13,8 @@ import numpy as np
 import pytest
 
 from paper_2509_04673_amd import workloads as W
-from parity_util import (announce, compare_stage, gpu_for, lumped_mass, oracle_for, rel_linf, run_both,
-                         run_tol)
+from parity_util import (announce, compare_stage, gpu_for, lumped_mass, oracle_for, random_euler_workload,
+                         random_scalar_workload, rel_linf, run_both, run_tol)
 
 pytestmark = pytest.mark.gpu
 
@@ -208,6 +208,9 @@ BATCHES = [
                           line_workload("euler", 2, 24, ("state", "wall"), seed=13)]),
     ("euler_p1", lambda: [W.blast1d(seed=3, n=2, p=1), W.sod1d(seed=3, n=129, p=1), W.shuosher1d(seed=3, n=400, p=1)]),
     ("nonconvex_p3", lambda: [W.nonconvex1d(seed=4, n=n, p=3) for n in (5, 33, 120)]),
+    # periodic lines through the same batched launches
+    ("periodic_euler_p2", lambda: [random_euler_workload(1, 2, (n,), seed=n) for n in (3, 40, 700)]),
+    ("periodic_adv_p3", lambda: [random_scalar_workload(1, 3, (n,), seed=n) for n in (4, 50, 300)]),
 ]
 
 
