@@ -136,8 +136,8 @@ typedef enum { CEM_BC_PERIODIC = 0, CEM_BC_STATE = 1, CEM_BC_OUTFLOW = 2, CEM_BC
  * hi[0] of a 1D line, both CEM_BC_PERIODIC (all zero: the periodic box) or
  * both non-periodic.  Non-periodic lines need dim = 1, CEM_FP64,
  * CEM_FLUX_LIMIT or CEM_FLUX_SHRINK and CEM_CONTRIB_AEC (the subcell bound
- * with boundary facets and the periodic Q1 form are not defined), and are
- * single problems only (cem_batch_create refuses them). */
+ * with boundary facets and the periodic Q1 form are not defined); the
+ * batched form takes them with any boundary kinds per problem. */
 typedef struct {
   int dim;       /* 1, 2 or 3 */
   int degree;    /* Bernstein degree p */
@@ -355,7 +355,9 @@ cem_status cem_step_static(cem_ctx* ctx, double* u, double* u_base, double dt, d
  * prefix table), and a whole SSP-RK3 step is captured as one HIP graph and
  * replayed.  Each problem keeps its own time step (fixed dt, or cfl times
  * its own min_e dt_e, eq. 40) and its own counters.  Supported: d = 2 (all
- * physics), 3D Euler; both precisions.
+ * physics), 3D Euler, both precisions; d = 1 in float64 (advection, Euler,
+ * the nonconvex flux; periodic lines or lines with their own boundary
+ * conditions, cem_mesh_desc.bc).
  *
  * State layout: problem k occupies [offsets[k], offsets[k+1]) of the
  * concatenated state arrays (its own component-major SoA block).
