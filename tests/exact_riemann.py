@@ -1,32 +1,59 @@
 """Exact solution of the Riemann problem of the 1D Euler equations of an
 ideal gas (test helper, no GPU): the star pressure from the sum of the two
 wave functions (shock: Rankine-Hugoniot; rarefaction: isentropic
-characteristic relation), then the self-similar solution sampled at
-x / t (the textbook construction, written here from those relations)."""
+characteristic relation), root by bracketing, then the extreme wave speeds
+and the self-similar solution sampled at x / t (the textbook construction,
+written here from those relations)."""
+import math
+
 import numpy as np
 from scipy.optimize import brentq
 
 
-def _wave(p, rho, pk, c, g):
-    """velocity change across the left / right wave for star pressure p"""
+def wave_fn(p, rho, pk, c, g):
+    """Velocity jump across the left / right wave as a function of the star
+    pressure p (shock for p > pk, rarefaction otherwise)."""
     if p > pk:
         a = 2.0 / ((g + 1.0) * rho)
         b = (g - 1.0) / (g + 1.0) * pk
-        return (p - pk) * np.sqrt(a / (p + b))
+        return (p - pk) * math.sqrt(a / (p + b))
     return 2.0 * c / (g - 1.0) * ((p / pk) ** ((g - 1.0) / (2.0 * g)) - 1.0)
 
 
+def _pstar(rhoL, vL, pL, rhoR, vR, pR, g):
+    """Star pressure; 0 when the two rarefactions open a vacuum."""
+    cL, cR = math.sqrt(g * pL / rhoL), math.sqrt(g * pR / rhoR)
+    f = lambda p: wave_fn(p, rhoL, pL, cL, g) + wave_fn(p, rhoR, pR, cR, g) + (vR - vL)
+    if f(0.0) >= 0.0:
+        return 0.0
+    hi = max(pL, pR)
+    while f(hi) < 0.0:
+        hi *= 2.0
+    return brentq(f, 0.0, hi, xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500)
+
+
+def extreme_speeds(rhoL, vL, pL, rhoR, vR, pR, g):
+    """Star pressure and the two extreme wave speeds (S_left, S_right)."""
+    cL, cR = math.sqrt(g * pL / rhoL), math.sqrt(g * pR / rhoR)
+    ps = _pstar(rhoL, vL, pL, rhoR, vR, pR, g)
+    if ps == 0.0:
+        return 0.0, vL - cL, vR + cR
+    kap = (g + 1.0) / (2.0 * g)
+    sL = vL - cL * (math.sqrt(1.0 + kap * (ps / pL - 1.0)) if ps > pL else 1.0)
+    sR = vR + cR * (math.sqrt(1.0 + kap * (ps / pR - 1.0)) if ps > pR else 1.0)
+    return ps, sL, sR
+
+
 def star_state(left, right, g=1.4):
-    """(p*, u*) of the primitive states left = (rho, u, p), right = (...)."""
+    """(p*, u*) of the primitive states left = (rho, u, p), right = (...)
+    (no vacuum)."""
     rl, ul, pl = left
     rr, ur, pr = right
-    cl, cr = np.sqrt(g * pl / rl), np.sqrt(g * pr / rr)
-    f = lambda p: _wave(p, rl, pl, cl, g) + _wave(p, rr, pr, cr, g) + (ur - ul)
-    lo, hi = 1e-12, 10.0 * max(pl, pr)
-    while f(hi) < 0:
-        hi *= 10.0
-    ps = brentq(f, lo, hi, xtol=1e-15, rtol=1e-15, maxiter=500)
-    us = 0.5 * (ul + ur) + 0.5 * (_wave(ps, rr, pr, cr, g) - _wave(ps, rl, pl, cl, g))
+    cl, cr = math.sqrt(g * pl / rl), math.sqrt(g * pr / rr)
+    ps = _pstar(rl, ul, pl, rr, ur, pr, g)
+    if ps == 0.0:
+        raise ValueError("the rarefactions open a vacuum")
+    us = 0.5 * (ul + ur) + 0.5 * (wave_fn(ps, rr, pr, cr, g) - wave_fn(ps, rl, pl, cl, g))
     return ps, us
 
 

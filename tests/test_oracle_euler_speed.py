@@ -1,5 +1,5 @@
 """Pins of the oracle's Euler wave speeds against an exact Riemann solver
-written here from the textbook pressure function (no GPU).
+written from the textbook pressure function (`exact_riemann.py`, no GPU).
 
 The facet speed lambda_ee' of the LLF flux (eq. (18)) and the subcell speeds
 lambda_0i of Lemma 1 must bound the largest wave speed of the 1D Riemann
@@ -18,40 +18,9 @@ pressure function of the left and right waves, root by bracketing) and check
 import math
 
 import numpy as np
-from scipy.optimize import brentq
 
+from exact_riemann import extreme_speeds as exact_riemann
 from oracle import physics as phys
-
-
-def _wave_fn(p, rho, pk, c, g):
-    """Velocity jump across the left/right wave as a function of the star
-    pressure p (shock for p > pk, rarefaction otherwise)."""
-    if p > pk:
-        a = 2.0 / ((g + 1.0) * rho)
-        b = (g - 1.0) / (g + 1.0) * pk
-        return (p - pk) * math.sqrt(a / (p + b))
-    return 2.0 * c / (g - 1.0) * ((p / pk) ** ((g - 1.0) / (2.0 * g)) - 1.0)
-
-
-def exact_riemann(rhoL, vL, pL, rhoR, vR, pR, g):
-    """Star pressure and the two extreme wave speeds (S_left, S_right) of
-    the exact solution of the 1D Riemann problem of an ideal gas."""
-    cL, cR = math.sqrt(g * pL / rhoL), math.sqrt(g * pR / rhoR)
-    dv = vR - vL
-
-    def f(p):
-        return _wave_fn(p, rhoL, pL, cL, g) + _wave_fn(p, rhoR, pR, cR, g) + dv
-
-    if f(0.0) >= 0.0:                      # the rarefactions open a vacuum
-        return 0.0, vL - cL, vR + cR
-    hi = max(pL, pR)
-    while f(hi) < 0.0:
-        hi *= 2.0
-    pstar = brentq(f, 0.0, hi, xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500)
-    kap = (g + 1.0) / (2.0 * g)
-    sL = vL - cL * (math.sqrt(1.0 + kap * (pstar / pL - 1.0)) if pstar > pL else 1.0)
-    sR = vR + cR * (math.sqrt(1.0 + kap * (pstar / pR - 1.0)) if pstar > pR else 1.0)
-    return pstar, sL, sR
 
 
 def _cons(rho, v, p, g):
