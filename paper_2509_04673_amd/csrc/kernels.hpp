@@ -1621,10 +1621,10 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   // ---- WENO sensor (Sec. 2.2, eqs. 7-8), per component; systems take the
   // minimum.  Candidates are extended into K_e by the blossom maps; every
   // semi-norm is the same packed quadratic form on coefficients shifted by
-  // their first entry (exactly zero for constant polynomials).
-  // scalar problems keep the extended candidates for the second sweep;
-  // systems recompute them (register pressure)
-  constexpr bool keepx = M == 1 && 2 * D * NL <= 64;
+  // their first entry (exactly zero for constant polynomials).  The
+  // nonlinear weights share one denominator, so sum_l w_l (u - u_l) builds
+  // up with unnormalised weights as each candidate is formed and is scaled
+  // once at the end: every candidate is extended once.
   double nbr_mean[2 * D][M];
   double gam = 0.0, nu = 0.0;
   if constexpr (ROLE == 4) {
@@ -1642,6 +1642,9 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
   }
   if constexpr (ROLE != 2 && ROLE != 4) {
   double gmin = 1.0;
+  const bool sense = a.gamma_mode == 0;
+  const RT wl0 = (RT)(1.0 - 2 * D * a.w_lin), wlin = (RT)a.w_lin, eps = (RT)a.eps;
+  auto nrm = [&](RT b) { return (a.rexp == 2.0) ? b : (RT)pow((double)b, 0.5 * a.rexp); };
   for (int c = 0; c < M; ++c) {
     RT ct[NL];
     // systems: the component is a runtime value here, so the coefficients
@@ -1649,9 +1652,11 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
     const double u00 = M > 1 ? ns.own(c, 0) : Uc(0, 0);
 #pragma unroll
     for (int j = 0; j < NL; ++j) ct[j] = (RT)((M > 1 ? ns.own(c, j) : Uc(0, j)) - u00);
-    RT beta[1 + 2 * D];
-    beta[0] = qsym<NL>(T, SF::qp, ct);
-    RT X[keepx ? 2 * D : 1][NL];
+    const RT beta0 = qsym<NL>(T, SF::qp, ct);
+    RT wsum = wl0 / (nrm(beta0) + eps);
+    RT w[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) w[j] = 0;
 #pragma unroll
     for (int l = 0; l < 2 * D; ++l) {
       double cn[NL], sum = 0.0;
@@ -1665,56 +1670,29 @@ __device__ __forceinline__ double elem1_body(const StageArgs& a, int64_t e, cons
         for (int j = 0; j < NL; ++j) sum += cn[j];
         nbr_mean[l][c] = sum * (1.0 / NL);
       }
+      if (!sense) continue;
 #pragma unroll
       for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
       ax<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cr, xe);
-      beta[1 + l] = qsym<NL>(T, SF::qp, xe);
-      if constexpr (keepx) {
-#pragma unroll
-        for (int j = 0; j < NL; ++j) X[l][j] = xe[j];
-      }
-    }
-    if (a.gamma_mode != 0) continue;
-    const RT wl0 = (RT)(1.0 - 2 * D * a.w_lin), wlin = (RT)a.w_lin, eps = (RT)a.eps;
-    RT wt[1 + 2 * D], wsum = 0;
-#pragma unroll
-    for (int l = 0; l <= 2 * D; ++l) {
-      const RT nr = (a.rexp == 2.0) ? beta[l] : (RT)pow((double)beta[l], 0.5 * a.rexp);
-      wt[l] = (l == 0 ? wl0 : wlin) / (nr + eps);
+      RT wt = wlin / (nrm(qsym<NL>(T, SF::qp, xe)) + eps);
       if constexpr (D == 1) {
         // a boundary facet of a non-periodic line has no neighbour: its
         // candidate is absent
-        if (ms.bnd1d && ((l == 1 && e == 0) || (l == 2 && e == E - 1))) wt[l] = 0;
+        if (ms.bnd1d && ((l == 0 && e == 0) || (l == 1 && e == E - 1))) wt = 0;
       }
-      wsum += wt[l];
+      wsum += wt;
+#pragma unroll
+      for (int i = 0; i < NL; ++i) w[i] += wt * (ct[i] - xe[i]);
     }
+    if (!sense) continue;
     const RT iws = (RT)1 / wsum;
-    RT w[NL];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) w[j] = 0;
-#pragma unroll
-    for (int l = 0; l < 2 * D; ++l) {
-      const RT om = wt[1 + l] * iws;
-      RT xe[NL];
-      if constexpr (keepx) {
-#pragma unroll
-        for (int j = 0; j < NL; ++j) xe[j] = X[l][j];
-      } else {
-        double cn[NL];
-        RT cr[NL];
-        ns.load_nbr(c, l, cn);
-#pragma unroll
-        for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
-        ax<D, P>(l / 2, T, SF::ext + (l % 2) * P1 * P1, false, cr, xe);
-      }
-#pragma unroll
-      for (int i = 0; i < NL; ++i) w[i] += om * (ct[i] - xe[i]);
-    }
+    for (int i = 0; i < NL; ++i) w[i] *= iws;
     // the ratio of eq. (7) is 0/0 on constant elements; it is regularised
     // with the weights' epsilon: ||u - u*|| / (||u||^2 + eps)^(1/2)
     const RT q2 = qsym<NL>(T, SF::qp, w);
     const RT dev = sqrt(q2 > (RT)0 ? q2 : (RT)0);
-    const RT b0 = beta[0] > (RT)0 ? beta[0] : (RT)0;
+    const RT b0 = beta0 > (RT)0 ? beta0 : (RT)0;
     RT ratio = dev / sqrt(b0 + eps);
     ratio = ratio < (RT)1 ? ratio : (RT)1;
     const double gc = 1.0 - (a.q == 1.0 ? (double)ratio : pow((double)ratio, a.q));

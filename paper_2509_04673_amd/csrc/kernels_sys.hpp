@@ -212,16 +212,26 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
   // entry.  The neighbour averages go to S for the facet fluxes.  The
   // neighbour loops are not unrolled: unrolled, the compiler issues all 2d
   // candidates' loads together and runs out of registers.
+  // The nonlinear weights share one denominator: sum_l w_l (u - u_l)
+  // builds up with unnormalised weights as each candidate is formed and is
+  // scaled once at the end, so every candidate is extended once.
   double gc = 1.0;
   {
-    RT beta0, betan[2 * D];
+    const bool sense = a.gamma_mode == 0;
+    auto nrm = [&](RT b) { return (a.rexp == 2.0) ? b : (RT)pow((double)b, 0.5 * a.rexp); };
+    const RT eps = (RT)a.eps, wlin = (RT)a.w_lin;
+    const double u0 = Us[0];
+    RT beta0;
     {
       RT x[NL];
-      const double u0 = Us[0];
 #pragma unroll
       for (int j = 0; j < NL; ++j) x[j] = (RT)(Us[j * CS] - u0);
       beta0 = qsym<NL>(T, SF::qp, x);
     }
+    RT wsum = (RT)(1.0 - 2 * D * a.w_lin) / (nrm(beta0) + eps);
+    RT w[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) w[j] = 0;
     // the axis is a compile-time constant in the body, so the candidate
     // arrays stay in registers; the two sides of an axis form a rolled loop
     static_for<D>([&](auto kc) {
@@ -234,44 +244,21 @@ __device__ __forceinline__ void k_elem1_sys_body(const StageArgs& a, int bx) {
 #pragma unroll
         for (int j = 0; j < NL; ++j) sum += cn[j];
         S[LY::oNm + (l * M + c) * EB + le] = sum * (1.0 / NL);
+        if (!sense) continue;
         RT cr[NL];
 #pragma unroll
         for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
         ax_ip1<D, P, k>(T, SF::ext + side * P1 * P1, false, cr);
-        set_sel<2 * D>(betan, l, qsym<NL>(T, SF::qp, cr));
+        const RT wt = wlin / (nrm(qsym<NL>(T, SF::qp, cr)) + eps);
+        wsum += wt;
+#pragma unroll
+        for (int i = 0; i < NL; ++i) w[i] += wt * ((RT)(Us[i * CS] - u0) - cr[i]);
       }
     });
-    if (a.gamma_mode == 0) {
-      auto nrm = [&](RT b) { return (a.rexp == 2.0) ? b : (RT)pow((double)b, 0.5 * a.rexp); };
-      const RT eps = (RT)a.eps, wlin = (RT)a.w_lin;
-      RT wt[2 * D];
-      RT wsum = (RT)(1.0 - 2 * D * a.w_lin) / (nrm(beta0) + eps);
-#pragma unroll
-      for (int l = 0; l < 2 * D; ++l) {
-        wt[l] = wlin / (nrm(betan[l]) + eps);
-        wsum += wt[l];
-      }
+    if (sense) {
       const RT iws = (RT)1 / wsum;
-      RT w[NL];
 #pragma unroll
-      for (int j = 0; j < NL; ++j) w[j] = 0;
-      const double u0 = Us[0];
-      static_for<D>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-#pragma unroll 1
-        for (int side = 0; side < 2; ++side) {
-          const int l = 2 * k + side;
-          const RT om = get_sel<2 * D>(wt, l) * iws;
-          double cn[NL];
-          ns.load_nbr(c, l, cn);
-          RT cr[NL];
-#pragma unroll
-          for (int j = 0; j < NL; ++j) cr[j] = (RT)(cn[j] - cn[0]);
-          ax_ip1<D, P, k>(T, SF::ext + side * P1 * P1, false, cr);
-#pragma unroll
-          for (int i = 0; i < NL; ++i) w[i] += om * ((RT)(Us[i * CS] - u0) - cr[i]);
-        }
-      });
+      for (int i = 0; i < NL; ++i) w[i] *= iws;
       // 0/0 on constant elements, regularised with the weights' epsilon
       const RT q2 = qsym<NL>(T, SF::qp, w);
       const RT dev = sqrt(q2 > (RT)0 ? q2 : (RT)0);
