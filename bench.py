@@ -53,7 +53,8 @@ FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak (the element passes of 
 COPY_PROBE_BYTES = 1 << 28     # plain copy used to calibrate the byte counters
 
 
-FLUX_FLOPS = {"advection": 1, "kpp": 40, "euler": 30}   # per state and direction
+# per state and direction (the nonconvex flux: one branch-selected quadratic)
+FLUX_FLOPS = {"advection": 1, "kpp": 40, "euler": 30, "nonconvex": 4}
 
 
 def elem1_flops(d, p, m, kind, part=0):
