@@ -662,32 +662,34 @@ struct BndLineArgs {
   const double* wf;     // [P][S] the interior rows zero padded to the stride of the
                         // register-blocked runs (k_line_bnd_runs), offsets -W..
   const double* wi;     // [P][2W + 1]
-  const double* lo;     // [blo][cw]
-  const double* hi;     // [bhi][cw]
+  const double* lo;     // [cw][blo] (by column: consecutive rows, consecutive weights)
+  const double* hi;     // [cw][bhi]
   int64_t N, total;     // nodes of the line, M N
   int P, W, blo, bhi, cw;
 };
 
-// sum_j w[j] x[j], j < n, in four interleaved partial sums (independent
+// sum_j w[j ld] x[j], j < n, in four interleaved partial sums (independent
 // loads and FMAs in flight: the end-block rows are long serial loops)
-__device__ __forceinline__ double dot4(const double* w, const double* x, int n) {
+__device__ __forceinline__ double dot4(const double* w, int64_t ld, const double* x, int n) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int j = 0;
   for (; j + 4 <= n; j += 4) {
-    s0 = fma(w[j], x[j], s0);
-    s1 = fma(w[j + 1], x[j + 1], s1);
-    s2 = fma(w[j + 2], x[j + 2], s2);
-    s3 = fma(w[j + 3], x[j + 3], s3);
+    s0 = fma(w[j * ld], x[j], s0);
+    s1 = fma(w[(j + 1) * ld], x[j + 1], s1);
+    s2 = fma(w[(j + 2) * ld], x[j + 2], s2);
+    s3 = fma(w[(j + 3) * ld], x[j + 3], s3);
   }
-  for (; j < n; ++j) s0 = fma(w[j], x[j], s0);
+  for (; j < n; ++j) s0 = fma(w[j * ld], x[j], s0);
   return (s0 + s1) + (s2 + s3);
 }
 
-// output i of component c by its row (end block or interior row)
+// output i of component c by its row (end block or interior row); the end
+// blocks are stored by column, so the rows of consecutive threads read
+// consecutive weights while x[j] is the same address for all of them
 __device__ __forceinline__ double line_bnd_row(const BndLineArgs& a, const double* x, int64_t i) {
-  if (i < a.blo) return dot4(a.lo + i * a.cw, x, a.cw);
-  if (i >= a.N - a.bhi) return dot4(a.hi + (i - (a.N - a.bhi)) * a.cw, x + (a.N - a.cw), a.cw);
-  return dot4(a.wi + (int)(i % a.P) * (2 * a.W + 1), x + (i - a.W), 2 * a.W + 1);
+  if (i < a.blo) return dot4(a.lo + i, a.blo, x, a.cw);
+  if (i >= a.N - a.bhi) return dot4(a.hi + (i - (a.N - a.bhi)), a.bhi, x + (a.N - a.cw), a.cw);
+  return dot4(a.wi + (int)(i % a.P) * (2 * a.W + 1), 1, x + (i - a.W), 2 * a.W + 1);
 }
 
 __device__ __forceinline__ void k_line_bnd_body(const BndLineArgs& a, int bx) {

@@ -312,8 +312,15 @@ bool build_bounded_line(int p, int n, double h, HostTables& T) {
     for (int j = 0; j < nbx; ++j) mx = std::max(mx, std::fabs(R[(size_t)r * nbx + j] - inf_row(I, row % p, j - row)));
     return mx / pk;
   };
-  const bool short_line = nb <= 2 * want;
-  if (!short_line) {
+  // The banded layout (exact end blocks of B rows, the infinite-line rows
+  // between them) wherever both end blocks fit on the line and their rows
+  // meet the infinite ones: on lines shorter than the auxiliary line the
+  // exact rows are those of the line itself (nx = n), so the checks below
+  // see both ends.  Otherwise every row is exact (a dense operator over the
+  // whole line).  Long lines must take the banded layout.
+  const bool must_band = nb > 2 * want;
+  bool banded = nb >= 2 * W + 2 * p + 1;
+  if (banded) {
     for (; B + p <= want; ++B) {
       bool ok = true;
       for (int i = B; i < B + p && ok; ++i)
@@ -321,8 +328,21 @@ bool build_bounded_line(int p, int n, double h, HostTables& T) {
           for (int g = 0; g < 2 && ok; ++g) ok = dev(i, e == 1, g == 1) <= tol;
       if (ok) break;
     }
-    if (B + p > want) return false;
+    banded = B + p <= want && 2 * B <= nb && B + W + 1 <= nb;
+    // the dropped entries of the end rows must be negligible too
+    for (int g = 0; g < 2 && banded; ++g) {
+      const std::vector<LD>& R = g ? rg : rm;
+      const LD pk = g ? pk_g : pk_m;
+      for (int i = 0; i < B && banded; ++i)
+        for (int j = B + W + 1; j < nbx; ++j)
+          if (std::fabs(R[(size_t)i * nbx + j]) > tol * pk) {
+            banded = false;
+            break;
+          }
+    }
   }
+  if (must_band && !banded) return false;
+  const bool short_line = !banded;
   for (int g = 0; g < 2; ++g) {
     BoundedLine& K = *outs[g];
     const std::vector<LD>& I = g ? ag : am;
@@ -341,26 +361,22 @@ bool build_bounded_line(int p, int n, double h, HostTables& T) {
       K.bhi = 0;
       K.cw = nb;
       K.lo.assign((size_t)nb * nb, 0.0);
-      for (size_t q = 0; q < (size_t)nb * nb; ++q) K.lo[q] = (double)R[q];
+      for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < nb; ++j) K.lo[(size_t)j * nb + i] = (double)R[(size_t)i * nb + j];
       K.hi.clear();
       continue;
     }
     const std::vector<LD>& R = g ? rg : rm;
-    const LD pk = g ? pk_g : pk_m;
     K.blo = K.bhi = B;
     K.cw = B + W + 1;
-    // the dropped entries of the end rows must be negligible too
-    for (int i = 0; i < B; ++i)
-      for (int j = K.cw; j < nbx; ++j)
-        if (std::fabs(R[(size_t)i * nbx + j]) > tol * pk) return false;
     K.lo.assign((size_t)B * K.cw, 0.0);
     K.hi.assign((size_t)B * K.cw, 0.0);
     for (int i = 0; i < B; ++i)
       for (int j = 0; j < K.cw; ++j) {
-        K.lo[(size_t)i * K.cw + j] = (double)R[(size_t)i * nbx + j];
+        K.lo[(size_t)j * B + i] = (double)R[(size_t)i * nbx + j];
         // high block row i is line row nb - B + i; its columns nb - cw + j
         const int r = 2 * want - B + i;          // rws[r] = nbx - B + i
-        K.hi[(size_t)i * K.cw + j] = (double)R[(size_t)r * nbx + (nbx - K.cw + j)];
+        K.hi[(size_t)j * B + i] = (double)R[(size_t)r * nbx + (nbx - K.cw + j)];
       }
   }
   return true;

@@ -38,11 +38,12 @@ struct LineKernel {
 // The first blo rows span columns [0, cw) and the last bhi rows columns
 // [Nb - cw, Nb), exact to long-double rounding (entries dropped beyond cw
 // are below 1e-17 of the peak).  A short line keeps every row exact:
-// blo = Nb, bhi = 0, cw = Nb.
+// blo = Nb, bhi = 0, cw = Nb.  The end blocks are stored by column, so that
+// threads computing consecutive rows read consecutive weights.
 struct BoundedLine {
   int W = 0, blo = 0, bhi = 0, cw = 0;
   std::vector<double> wi;       // [p][2W + 1]
-  std::vector<double> lo, hi;   // [blo][cw], [bhi][cw]
+  std::vector<double> lo, hi;   // [cw][blo], [cw][bhi]
 };
 
 struct HostTables {
