@@ -735,11 +735,39 @@ __device__ __forceinline__ void k_line_bnd_runs_body(const BndLineArgs& a, int b
 #pragma unroll
     for (int r = 0; r < R; ++r) y[s + r] = acc[r];
   }
-  // the rows of the other runs of the tile, one per thread
+  // the rows of the other runs of the tile: those of the runs starting
+  // below blo, [s0, e1), and of the runs reaching past N - bhi, [s2, te),
+  // two lanes per row (each half of the taps, summed by a lane shuffle: the
+  // end rows are the block's longest serial chains).  The trip count is the
+  // same for the whole block, so every lane reaches the shuffle.
   const int64_t te = s0 + 256 * R < N ? s0 + 256 * R : N;
-  for (int64_t i = s0 + threadIdx.x; i < te; i += 256) {
-    const int64_t rs = s0 + ((i - s0) / R) * R;
-    if (!interior_run(rs)) y[i] = line_bnd_row(a, x, i);
+  auto run_up = [&](int64_t v) { return v <= s0 ? s0 : s0 + (v - s0 + R - 1) / R * R; };
+  const int64_t e1 = min(run_up(a.blo), te);
+  const int64_t s2 = min(max(run_up(N - a.bhi - R + 1), e1), te);
+  const int n1 = (int)(e1 - s0), nend = n1 + (int)(te - s2);
+  const int half = threadIdx.x & 1;
+  for (int base = 0; base < nend; base += 128) {
+    const int r = base + (int)(threadIdx.x >> 1);
+    double part = 0.0;
+    int64_t i = 0;
+    if (r < nend) {
+      i = r < n1 ? s0 + r : s2 + (r - n1);
+      const double* w;
+      const double* xs;
+      int64_t ld;
+      int n;
+      if (i < a.blo) {
+        w = a.lo + i, ld = a.blo, xs = x, n = a.cw;
+      } else if (i >= N - a.bhi) {
+        w = a.hi + (i - (N - a.bhi)), ld = a.bhi, xs = x + (N - a.cw), n = a.cw;
+      } else {
+        w = a.wi + (int)(i % a.P) * (2 * a.W + 1), ld = 1, xs = x + (i - a.W), n = 2 * a.W + 1;
+      }
+      const int h0 = n / 2;
+      part = half ? dot4(w + h0 * ld, ld, xs + h0, n - h0) : dot4(w, ld, xs, h0);
+    }
+    const double sum = part + __shfl_xor(part, 1);
+    if (r < nend && half == 0) y[i] = sum;
   }
 }
 
