@@ -71,11 +71,14 @@ __global__ void __launch_bounds__(256) kb_line_bnd(const BndLineArgs* __restrict
 }
 
 // the LDS-tiled runs of long non-periodic lines: local block lb -> (tile
-// lb % gx along the line, component lb / gx), gx tiles of 256 R outputs
+// lb % gx along the line, component lb / gx), gx tiles of 256 R outputs.
+// Each problem has its own end-block weights, read by the blocks of all its
+// components: consecutive blocks on one XCD, so that they share its L2
+// (in launch order, consecutive blocks go to different XCDs)
 template <int P, int RE>
 __global__ void __launch_bounds__(256) kb_line_bnd_runs(const BndLineArgs* __restrict__ args, BatchMap m) {
   int lb;
-  const int pid = batch_find(m, blockIdx.x, &lb);
+  const int pid = batch_find(m, xcd_block(blockIdx.x, gridDim.x), &lb);
   const BndLineArgs& a = args[pid];
   const int gx = (int)((a.N + 256 * P * RE - 1) / (256 * P * RE));
   k_line_bnd_runs_body<P, RE>(a, lb % gx, lb / gx);
