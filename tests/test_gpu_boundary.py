@@ -64,6 +64,13 @@ CASES = [
     ("ncv_p1", lambda: W.nonconvex1d(seed=1, n=64, p=1)),
     ("ncv_p2_long", lambda: W.nonconvex1d(seed=1, n=200, p=2)),
     ("ncv_p3_rough", lambda: line_workload("nonconvex", 3, 20, ("state", "outflow"), seed=12)),
+    # either side of the shortest line that takes the banded layout (end
+    # blocks + infinite rows): 62 / 46 / 40 cells for p = 1 / 2 / 3
+    ("adv_p1_62_first_banded", lambda: line_workload("advection", 1, 62, ("outflow", "state"), seed=14,
+                                                      velocity=-1.0)),
+    ("eul_p2_46_first_banded", lambda: line_workload("euler", 2, 46, ("state", "wall"), seed=13)),
+    ("eul_p2_45_last_dense", lambda: line_workload("euler", 2, 45, ("wall", "state"), seed=15)),
+    ("ncv_p3_40_first_banded", lambda: line_workload("nonconvex", 3, 40, ("state", "outflow"), seed=16)),
 ]
 
 MODES = [
